@@ -1,0 +1,249 @@
+/*
+ * nysadmm.h - C ABI of the NysADMM x-subproblem hot path for AMD MI355X (gfx950).
+ *
+ * Method: Zhao, Frangella, Udell, "NysADMM: faster composite convex
+ * optimization via low-rank approximation" (ICML 2022).  The library solves
+ * the ADMM x-subproblem, eq. (ADMMSubProb),
+ *
+ *     (A^T diag(D) A + (c + rho) I) x = rhs,
+ *
+ * by Nystrom-preconditioned CG (Algorithm Nystrom PCG) with the randomized
+ * Nystrom factor of Algorithm RandNysAppx / AdaptiveRandNysAppx, and runs the
+ * surrounding ADMM loop (Algorithm NysADMM) for the composite problem eq. (1),
+ * min l(Ax; b) + c/2 ||x||^2 + gamma ||x||_1, with l the least-squares loss
+ * (lasso, eq. 2; elastic net, eq. 6) or the logistic loss (eq. 9).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named A.data, D, b, omega, w, y, rhs, x, z, u and U are DEVICE
+ *    pointers; pointers to option/info structs and *_host arrays are host
+ *    pointers.  The caller owns every buffer it passes; the library owns only
+ *    the opaque nys_ctx / nys_factor objects and the device workspace they
+ *    hold (allocated with hipMalloc on first need, grown on demand, freed by
+ *    nys_ctx_destroy / nys_factor_destroy).
+ *  - A is dense row-major n x d with leading dimension ld >= d (elements), in
+ *    FP32 or FP64.  Rows whose byte offset is a multiple of 16 take the vector
+ *    load path; any ld is accepted.
+ *  - Every vector (D, b, rhs, x, z, u, w, y) is FP64 and contiguous.  D is an
+ *    n-vector of non-negative Hessian weights (H^l of the loss, Section 2.1);
+ *    D == NULL means the identity (least squares).
+ *  - The Gaussian test-matrix entries `omega` are drawn by the caller (the
+ *    library draws no random numbers): FP64, column-major d x r (column k at
+ *    omega + k*d).  The library orthonormalises them (thin QR, as in
+ *    Algorithm RandNysAppx).
+ *  - All work is ordered on the HIP stream given to nys_ctx_create.  Calls
+ *    that return scalars (info structs, factor info) synchronise that stream.
+ *    A context is not thread-safe; use one per stream.
+ *  - Errors are returned as nys_status; nothing aborts or throws across the
+ *    ABI.  nys_status_string() gives a static message.  On NYS_ERR_MAXITER,
+ *    NYS_ERR_BREAKDOWN and NYS_ERR_NOT_SPD the outputs hold the last iterate
+ *    and the info struct is filled.
+ */
+#ifndef NYSADMM_H
+#define NYSADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NYS_OK = 0,
+  NYS_ERR_INVALID = 1,       /* bad argument (NULL, size, rho <= 0, r out of range, ...) */
+  NYS_ERR_HIP = 2,           /* a HIP runtime call failed */
+  NYS_ERR_NOT_SPD = 3,       /* Cholesky of Omega^T Y_nu failed after 3 shift retries */
+  NYS_ERR_BREAKDOWN = 4,     /* PCG met p^T (H + rho I) p <= 0 */
+  NYS_ERR_MAXITER = 5,       /* PCG stopped at max_iter above its tolerance */
+  NYS_ERR_NONFINITE = 6,     /* NaN or Inf in a residual or eigenvalue */
+  NYS_ERR_NOMEM = 7,         /* device allocation failed */
+  NYS_ERR_NOT_CONVERGED = 8  /* the FP64 eigensolver of the factor core did not converge */
+} nys_status;
+
+typedef enum { NYS_F32 = 0, NYS_F64 = 1, NYS_BF16 = 2 } nys_dtype;
+typedef enum { NYS_LOSS_LS = 0, NYS_LOSS_LOGISTIC = 1 } nys_loss;
+
+typedef struct nys_ctx_s* nys_ctx;
+typedef struct nys_factor_s* nys_factor;
+
+/* Dense row-major matrix: element (i, j) at data + i*ld + j. */
+typedef struct {
+  int64_t n, d, ld;
+  nys_dtype dtype;   /* NYS_F32 or NYS_F64 */
+  const void* data;  /* device */
+} nys_dense;
+
+/* ----------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL means the null stream).  *out receives the handle. */
+nys_status nys_ctx_create(int device, void* hip_stream, nys_ctx* out);
+nys_status nys_ctx_destroy(nys_ctx ctx);
+/* Rebind the context to another stream of the same device. */
+nys_status nys_ctx_set_stream(nys_ctx ctx, void* hip_stream);
+const char* nys_status_string(nys_status s);
+/* Bytes of device workspace currently held by the context. */
+size_t nys_ctx_workspace_bytes(nys_ctx ctx);
+
+/* ------------------------------------------------------------------ sketch */
+
+/* Randomized Nystrom approximation of H = A^T diag(D) A + c I
+ * (Algorithm RandNysAppx; eq. NysAppx; Section 2.2):
+ *   Omega = qr(omega) (thin, FP64), Y = H Omega, nu = sqrt(d) eps(||Y||_2),
+ *   Y_nu = Y + nu Omega, C = chol(Omega^T Y_nu) (upper), B = Y_nu C^-1,
+ *   [U, Sigma] = svd(B), Lambda = max(0, Sigma^2 - nu).
+ * eps(x) is the FP64 spacing of x (2^(floor(log2 x) - 52)) when
+ * sketch_prec == NYS_F64 and the FP32 spacing (exponent - 23) otherwise.
+ * If the Cholesky fails, nu is multiplied by 10 and the step repeated, at most
+ * 3 times, then NYS_ERR_NOT_SPD.
+ *
+ *  omega       device, FP64, column-major d x r, Gaussian entries.
+ *  r           columns to sketch, 1 <= r, total rank < d, total rank <= 1024.
+ *  sketch_prec precision of Y = A^T (D (A Omega)): NYS_F64 (FP64 arithmetic,
+ *              any A dtype), NYS_F32 (A FP32, FP32 MFMA, FP32 accumulate) or
+ *              NYS_BF16 (A FP32 rounded to BF16 on load, BF16 MFMA, FP32
+ *              accumulate).  The core (shift, Cholesky, SVD) is always FP64.
+ *  F           in/out.  *F == NULL creates a factor of rank r.  *F != NULL
+ *              appends r new columns to the existing sketch (the block step of
+ *              Algorithm AdaptiveRandNysAppx: only the new block is
+ *              orthonormalised and sketched) and recomputes the core, giving
+ *              rank r_old + r.  A, D, c must be those of the earlier call. */
+nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                      const double* omega, int r, nys_dtype sketch_prec, nys_factor* F);
+
+/* Algorithm AdaptiveRandNysAppx: starting at rank s0, double the rank (the
+ * last step cut to s_max) until (lambda_s + rho)/rho <= tol (eq. empCondNum,
+ * tol = 1 + epsilon).  omega holds d x s_max Gaussian entries; block k uses the
+ * next columns in order.  *F must be NULL on entry. */
+nys_status nys_sketch_adaptive(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                               const double* omega, int s0, int s_max, double rho, double tol,
+                               nys_dtype sketch_prec, nys_factor* F);
+
+/* Factor from a given eigendecomposition (U device FP64 column-major d x r,
+ * lambda_host descending, r entries).  Used to run PCG with an externally
+ * built preconditioner. */
+nys_status nys_factor_import(nys_ctx ctx, int64_t d, int r, const double* U,
+                             const double* lambda_host, double nu, nys_factor* F);
+
+/* rank, shift nu, lambda_s (smallest retained eigenvalue) and, if
+ * lambda_host != NULL, all r eigenvalues in descending order. */
+nys_status nys_factor_info(nys_factor F, int* rank, double* nu, double* lambda_s,
+                           double* lambda_host);
+/* Copy U (FP64, column-major d x rank) to the device buffer U_out. */
+nys_status nys_factor_get_U(nys_ctx ctx, nys_factor F, double* U_out);
+nys_status nys_factor_destroy(nys_factor F);
+
+/* ------------------------------------------------------------ matvec pair */
+
+/* v = (A^T diag(D) A + (c + rho) I) p : the Hessian-vector product of the
+ * subproblem eq. (ADMMSubProb) (the T_mv of Table t-ComplexityComparison), in
+ * one streaming pass over A with FP64 products and sums.  If pv_host != NULL
+ * it receives p^T v = sum_i D_i (A p)_i^2 + (c + rho) ||p||^2 (synchronises).
+ * p, v: device FP64 d-vectors, not overlapping.  rho + c >= 0. */
+nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                             double rho, const double* p, double* v, double* pv_host);
+
+/* --------------------------------------------------------- preconditioner */
+
+/* y = P^-1 w with, eq. (Nyspreconditioner),
+ *   P^-1 = (lambda_s + rho) U (Lambda + rho I)^-1 U^T + (I - U U^T),
+ * applied in O(d r) as y = w + U (s o (U^T w)), s_i = (lambda_s + rho)/(lambda_i + rho) - 1.
+ * rho > 0.  w and y are device FP64 d-vectors and must not overlap. */
+nys_status nys_precond_apply(nys_ctx ctx, nys_factor F, double rho, const double* w, double* y);
+
+/* --------------------------------------------------------------------- PCG */
+
+typedef struct {
+  double tol;        /* stop when ||w||_2 <= tol ||rhs||_2 (tol_abs: ||w||_2 <= tol) */
+  int tol_abs;
+  int max_iter;      /* PCG iterations; 0 means 1000 */
+  int check_every;   /* host convergence check cadence; 0 means 8 */
+  int true_residual; /* 1: recompute rhs - H_rho x at the end and restart if above tol */
+  int max_restarts;  /* restarts allowed by the true-residual check; 0 means 2 */
+} nys_pcg_opts;
+
+typedef struct {
+  int iters;            /* PCG iterations over all restarts */
+  int restarts;
+  double rhs_norm;      /* ||rhs||_2 */
+  double res_norm;      /* recursive ||w||_2 at exit */
+  double true_res_norm; /* ||rhs - H_rho x||_2 with FP64 accumulation (if requested, else -1) */
+  nys_status status;
+} nys_pcg_info;
+
+/* Algorithm Nystrom PCG on (A^T diag(D) A + (c + rho) I) x = rhs (eq.
+ * ADMMSubProb).  x holds the initial guess on entry and the solution on exit.
+ * F == NULL runs plain CG.  rhs = 0 returns x = 0 after 0 iterations.
+ * The matrix-vector products multiply the stored A exactly in FP64 (products
+ * and sums) whatever its storage type. */
+nys_status pcg_solve(nys_ctx ctx, const nys_dense* A, const double* D, double c, double rho,
+                     nys_factor F, const double* rhs, double* x, const nys_pcg_opts* opts,
+                     nys_pcg_info* info);
+
+/* -------------------------------------------------------------------- ADMM */
+
+typedef struct {
+  nys_loss loss;     /* NYS_LOSS_LS: 1/2||Ax - b||^2; NYS_LOSS_LOGISTIC: -sum(b t - log(1+e^t)), t = Ax */
+  nys_dense A;
+  const double* b;   /* device FP64 n-vector; labels in {0,1} for the logistic loss */
+  double gamma;      /* l1 weight, >= 0 */
+  double c;          /* smooth ridge part c/2 ||x||^2, >= 0 (elastic net: c = 1 - gamma) */
+} nys_problem;
+
+typedef struct {
+  double rho;            /* ADMM step size, > 0 */
+  int rank;              /* fixed rank, or the initial rank s0 of the adaptive sketch */
+  int rank_max;          /* adaptive: s_max; <= rank means fixed rank */
+  double ada_tol;        /* adaptive: Tol = 1 + epsilon of eq. (empCondNum) */
+  int resketch_every;    /* logistic: rebuild the factor every k iterations (0: never) */
+  nys_dtype sketch_prec; /* NYS_F64, NYS_F32 or NYS_BF16 */
+  const double* omega;   /* device FP64 column-major d x max(rank, rank_max) Gaussian entries */
+  nys_pcg_opts pcg;      /* subproblem tolerance and limits */
+  int tol_schedule;      /* 1: eps^{k+1} = sqrt(||r_p|| ||r_d||) absolute (Section 5 setup) */
+  int max_iter;          /* ADMM iterations (admm_solve) */
+  double eps_abs, eps_rel; /* Section 2.1 residual stop; eps_rel <= 0 disables */
+  double rel_change_tol; /* ||z_k - z_{k+1}||_inf / ||z_k||_inf < tol stop; <= 0 disables */
+  double kkt_tol;        /* stop when the relative KKT residual (eq. 31) <= kkt_tol; <= 0 disables */
+  int kkt_every;         /* KKT check cadence (one extra matvec pair each); 0 means 10 */
+} nys_admm_opts;
+
+/* Caller-owned device FP64 d-vectors; x = z = u = 0 for a cold start.  k counts
+ * completed iterations (resume = pass the saved state back). */
+typedef struct {
+  double* x;
+  double* z;
+  double* u;
+  int k;
+} nys_admm_state;
+
+typedef struct {
+  int iters;           /* ADMM iterations done by this call */
+  long pcg_iters;      /* PCG iterations summed over those */
+  int pcg_max;         /* largest PCG count of one subproblem */
+  double r_p, r_d;     /* last primal / dual residual norms */
+  double eta;          /* last relative KKT residual (eq. 31 or its logistic form), -1 if not computed */
+  double obj;          /* objective at z, -1 if not computed */
+  int rank;            /* Nystrom rank in use */
+  int converged;       /* a stopping rule fired */
+  nys_status status;
+} nys_admm_info;
+
+/* One iteration of Algorithm NysADMM: right-hand side (lasso: rho(z-u) + A^T b;
+ * logistic: t = A x, w = sigma(t)(1-sigma(t)), rhs = rho(z-u) + A^T(w t + b - sigma(t))),
+ * PCG warm-started at x, z = S_{gamma/rho}(x + u), u += x - z, residuals.
+ * *F is the factor to precondition with; for the logistic loss it is rebuilt
+ * in place when state->k is a multiple of opts->resketch_every (and created
+ * if NULL). */
+nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, nys_factor* F,
+                     nys_admm_state* S, nys_admm_info* I);
+
+/* Algorithm NysADMM / AdaNysADMM: build the factor (fixed or adaptive rank),
+ * then iterate admm_step until max_iter or a stopping rule.  count problems
+ * are solved one after another (arrays of length count). */
+nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_admm_opts* O,
+                      nys_admm_state* S, nys_admm_info* I);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NYSADMM_H */

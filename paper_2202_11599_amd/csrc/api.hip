@@ -1,0 +1,385 @@
+// C ABI: contexts, factors, preconditioner apply and the PCG driver.
+// The sketch entry points live in sketch.hip, the ADMM drivers in admm.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "internal.h"
+
+namespace nys {
+
+static thread_local char g_last_err[256] = {0};
+
+void set_last_hip_error(hipError_t e, const char* what, const char* file, int line) {
+  snprintf(g_last_err, sizeof(g_last_err), "%s failed (%s) at %s:%d", what,
+           hipGetErrorString(e), file, line);
+}
+
+nys_status DevBuf::reserve(size_t want) {
+  if (want <= bytes && ptr != nullptr) return NYS_OK;
+  if (ptr != nullptr) {
+    (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  if (want == 0) want = 256;
+  want = (want + 4095) / 4096 * 4096;
+  if (hipMalloc(&ptr, want) != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    return NYS_ERR_NOMEM;
+  }
+  bytes = want;
+  return NYS_OK;
+}
+
+void DevBuf::release() {
+  if (ptr != nullptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+nys_status validate_dense(const nys_dense* A) {
+  if (A == nullptr || A->data == nullptr) return NYS_ERR_INVALID;
+  if (A->n < 0 || A->d < 1 || A->ld < A->d) return NYS_ERR_INVALID;
+  if (A->dtype != NYS_F32 && A->dtype != NYS_F64) return NYS_ERR_INVALID;
+  return NYS_OK;
+}
+
+// Carves the PCG workspace out of the context buffers.
+nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws) {
+  const size_t ypb = align_up(sizeof(double) * ((size_t)pl.grid * pl.ldy)) +
+                     align_up(sizeof(double) * (size_t)std::max(pl.grid, 1));
+  NYS_TRY(ctx->ypart.reserve(ypb));
+  ws->ypart = ctx->ypart.as<double>();
+  ws->qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ypart.ptr) +
+                                        align_up(sizeof(double) * ((size_t)pl.grid * pl.ldy)));
+  const size_t nv = align_up(sizeof(double) * d);
+  const size_t vb = 2 * nv + align_up(sizeof(double) * 1024) +
+                    align_up(sizeof(double) * (size_t)(max_iter + 2));
+  NYS_TRY(ctx->vecs.reserve(vb));
+  char* v = static_cast<char*>(ctx->vecs.ptr);
+  ws->w = reinterpret_cast<double*>(v);
+  ws->p = reinterpret_cast<double*>(v + nv);
+  ws->cvec = reinterpret_cast<double*>(v + 2 * nv);
+  ws->wy = reinterpret_cast<double*>(v + 2 * nv + align_up(sizeof(double) * 1024));
+  ws->nred = nblk(d, kRedBlock);
+  ws->nvec = nblk(d, kVecBlock);
+  const size_t sb = align_up(sizeof(PcgDev)) + 2 * align_up(sizeof(double) * ws->nred) +
+                    align_up(sizeof(double) * ws->nvec);
+  NYS_TRY(ctx->small.reserve(sb));
+  char* s = static_cast<char*>(ctx->small.ptr);
+  ws->st = reinterpret_cast<PcgDev*>(s);
+  s += align_up(sizeof(PcgDev));
+  ws->wwpart = reinterpret_cast<double*>(s);
+  s += align_up(sizeof(double) * ws->nred);
+  ws->rrpart = reinterpret_cast<double*>(s);
+  s += align_up(sizeof(double) * ws->nred);
+  ws->pppart = reinterpret_cast<double*>(s);
+  return NYS_OK;
+}
+
+nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out) {
+  NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, ws.st, sizeof(PcgDev), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  std::memcpy(out, ctx->host_pinned, sizeof(PcgDev));
+  return NYS_OK;
+}
+
+// Algorithm Nystrom PCG (see pcg_solve in nysadmm.h).
+nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
+                   nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
+                   nys_pcg_info* info) {
+  const int64_t d = A.d;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
+  const int check = o.check_every > 0 ? o.check_every : 8;
+  const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 2;
+  const GramPlan pl = make_gram_plan(A, ctx->num_cu);
+  PcgWs ws;
+  NYS_TRY(pcg_workspace(ctx, pl, d, max_iter, &ws));
+  const double rho_eff = rho + c;
+  hipStream_t st = ctx->stream;
+
+  const int r = F ? F->r : 0;
+  const void* U = F ? (F->use_u32 ? F->U32.ptr : F->U.ptr) : nullptr;
+  const bool u32 = F ? F->use_u32 : false;
+  const double* lam = F ? F->lam.as<double>() : nullptr;
+  const double lam_s = (F && r > 0) ? F->lam_host[r - 1] : 0.0;
+
+  int total_iters = 0, restarts = 0;
+  PcgDev h{};
+  nys_status status = NYS_OK;
+  double true_rr = -1.0;
+  for (;;) {
+    NYS_TRY_HIP(hipMemsetAsync(ws.st, 0, sizeof(PcgDev), st));
+    // w0 = rhs - H_rho x0 ; y0 = P^-1 w0 ; p0 = y0
+    NYS_TRY(launch_gram(A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr, st));
+    NYS_TRY(launch_reduce_update(1, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x, nullptr,
+                                 ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, ws.rrpart, ws.st, st));
+    NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred,
+                               ws.rrpart, -1, 1, o.tol, o.tol_abs, st));
+    NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, 0,
+                                  ws.wwpart, ws.nred, ws.pppart, ws.st, 1, st));
+    int it = 0;
+    for (;;) {
+      NYS_TRY(read_pcg_state(ctx, ws, &h));
+      if (h.done || it >= max_iter - total_iters) break;
+      const int chunk = std::min(check, max_iter - total_iters - it);
+      for (int kk = 0; kk < chunk; ++kk) {
+        const int k = it + kk;
+        NYS_TRY(launch_gram(A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done,
+                            st));
+        NYS_TRY(launch_reduce_update(0, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
+                                     ws.w, nullptr, ws.wy, k, ws.pppart, ws.nvec, ws.wwpart,
+                                     nullptr, ws.st, st));
+        NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred,
+                                   nullptr, k, 0, o.tol, o.tol_abs, st));
+        NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy,
+                                      k, ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st));
+      }
+      it += chunk;
+    }
+    total_iters += h.done ? h.iters : it;
+    if (h.flags & kFlagZeroRhs) {
+      NYS_TRY_HIP(hipMemsetAsync(x, 0, sizeof(double) * d, st));
+      status = NYS_OK;
+      true_rr = 0.0;
+      break;
+    }
+    if (h.flags & kFlagNonfinite) {
+      status = NYS_ERR_NONFINITE;
+      break;
+    }
+    if (h.flags & kFlagBreakdown) {
+      status = NYS_ERR_BREAKDOWN;
+      break;
+    }
+    if (!h.done) status = NYS_ERR_MAXITER;
+    if (!o.true_residual) break;
+    // true residual rhs - H_rho x with FP64 accumulation
+    NYS_TRY(launch_gram(A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr, st));
+    NYS_TRY(launch_reduce_update(2, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x, nullptr,
+                                 ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, nullptr, ws.st, st));
+    NYS_TRY(launch_precond_dot(U, u32, d, 0, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred, nullptr,
+                               0, 3, 0.0, 0, st));
+    NYS_TRY(read_pcg_state(ctx, ws, &h));
+    true_rr = h.true_rr;
+    if (!(true_rr <= h.thr2) && status == NYS_OK && restarts < max_restarts &&
+        total_iters < max_iter) {
+      ++restarts;
+      continue;
+    }
+    if (!(true_rr <= h.thr2) && status == NYS_OK) status = NYS_ERR_MAXITER;
+    break;
+  }
+  if (info) {
+    info->iters = total_iters;
+    info->restarts = restarts;
+    info->rhs_norm = std::sqrt(h.rr);
+    info->res_norm = std::sqrt(h.ww);
+    info->true_res_norm = true_rr >= 0 ? std::sqrt(true_rr) : -1.0;
+    info->status = status;
+  }
+  return status;
+}
+
+}  // namespace nys
+
+using namespace nys;
+
+extern "C" {
+
+const char* nys_status_string(nys_status s) {
+  switch (s) {
+    case NYS_OK: return "ok";
+    case NYS_ERR_INVALID: return "invalid argument";
+    case NYS_ERR_HIP: return g_last_err[0] ? g_last_err : "HIP runtime error";
+    case NYS_ERR_NOT_SPD: return "Cholesky of Omega^T Y_nu failed after shift retries";
+    case NYS_ERR_BREAKDOWN: return "PCG breakdown: p^T H p <= 0";
+    case NYS_ERR_MAXITER: return "PCG reached max_iter above tolerance";
+    case NYS_ERR_NONFINITE: return "non-finite value";
+    case NYS_ERR_NOMEM: return "device allocation failed";
+    case NYS_ERR_NOT_CONVERGED: return "eigensolver did not converge";
+  }
+  return "unknown status";
+}
+
+nys_status nys_ctx_create(int device, void* hip_stream, nys_ctx* out) {
+  if (out == nullptr) return NYS_ERR_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  NYS_TRY_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(device));
+  nys_ctx c = new (std::nothrow) nys_ctx_s();
+  if (c == nullptr) return NYS_ERR_NOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cu = prop.multiProcessorCount;
+  if (hipHostMalloc(&c->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return NYS_ERR_NOMEM;
+  }
+  *out = c;
+  return NYS_OK;
+}
+
+nys_status nys_ctx_destroy(nys_ctx ctx) {
+  if (ctx == nullptr) return NYS_ERR_INVALID;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->ypart.release();
+  ctx->vecs.release();
+  ctx->small.release();
+  ctx->gemm_ws.release();
+  ctx->core_ws.release();
+  ctx->admm_ws.release();
+  if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  delete ctx;
+  return NYS_OK;
+}
+
+nys_status nys_ctx_set_stream(nys_ctx ctx, void* hip_stream) {
+  if (ctx == nullptr) return NYS_ERR_INVALID;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return NYS_OK;
+}
+
+size_t nys_ctx_workspace_bytes(nys_ctx ctx) {
+  if (ctx == nullptr) return 0;
+  return ctx->ypart.bytes + ctx->vecs.bytes + ctx->small.bytes + ctx->gemm_ws.bytes +
+         ctx->core_ws.bytes + ctx->admm_ws.bytes;
+}
+
+nys_status nys_factor_import(nys_ctx ctx, int64_t d, int r, const double* U,
+                             const double* lambda_host, double nu, nys_factor* F) {
+  if (ctx == nullptr || F == nullptr || U == nullptr || lambda_host == nullptr)
+    return NYS_ERR_INVALID;
+  if (d < 2 || r < 1 || r >= d || r > 1024) return NYS_ERR_INVALID;
+  for (int i = 0; i < r; ++i) {
+    if (!(lambda_host[i] >= 0.0) || !std::isfinite(lambda_host[i])) return NYS_ERR_INVALID;
+    if (i > 0 && lambda_host[i] > lambda_host[i - 1]) return NYS_ERR_INVALID;
+  }
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys_factor f = new (std::nothrow) nys_factor_s();
+  if (f == nullptr) return NYS_ERR_NOMEM;
+  f->d = d;
+  f->r = r;
+  f->cap = r;
+  f->nu = nu;
+  f->device = ctx->device;
+  f->prec = NYS_F64;
+  f->use_u32 = false;
+  nys_status s = f->U.reserve(sizeof(double) * d * r);
+  if (s == NYS_OK) s = f->lam.reserve(sizeof(double) * r);
+  if (s != NYS_OK) {
+    nys_factor_destroy(f);
+    return s;
+  }
+  f->lam_host.assign(lambda_host, lambda_host + r);
+  if (hipMemcpyAsync(f->U.ptr, U, sizeof(double) * d * r, hipMemcpyDeviceToDevice,
+                     ctx->stream) != hipSuccess ||
+      hipMemcpyAsync(f->lam.ptr, f->lam_host.data(), sizeof(double) * r, hipMemcpyHostToDevice,
+                     ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    nys_factor_destroy(f);
+    return NYS_ERR_HIP;
+  }
+  *F = f;
+  return NYS_OK;
+}
+
+nys_status nys_factor_info(nys_factor F, int* rank, double* nu, double* lambda_s,
+                           double* lambda_host) {
+  if (F == nullptr) return NYS_ERR_INVALID;
+  if (rank) *rank = F->r;
+  if (nu) *nu = F->nu;
+  if (lambda_s) *lambda_s = F->r > 0 ? F->lam_host[F->r - 1] : 0.0;
+  if (lambda_host && F->r > 0) std::memcpy(lambda_host, F->lam_host.data(), sizeof(double) * F->r);
+  return NYS_OK;
+}
+
+nys_status nys_factor_get_U(nys_ctx ctx, nys_factor F, double* U_out) {
+  if (ctx == nullptr || F == nullptr || U_out == nullptr) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipMemcpyAsync(U_out, F->U.ptr, sizeof(double) * F->d * F->r,
+                             hipMemcpyDeviceToDevice, ctx->stream));
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  return NYS_OK;
+}
+
+nys_status nys_factor_destroy(nys_factor F) {
+  if (F == nullptr) return NYS_ERR_INVALID;
+  (void)hipSetDevice(F->device);
+  (void)hipDeviceSynchronize();
+  F->U.release();
+  F->U32.release();
+  F->lam.release();
+  F->Omega.release();
+  F->Y.release();
+  delete F;
+  return NYS_OK;
+}
+
+nys_status nys_precond_apply(nys_ctx ctx, nys_factor F, double rho, const double* w, double* y) {
+  if (ctx == nullptr || F == nullptr || w == nullptr || y == nullptr) return NYS_ERR_INVALID;
+  if (!(rho > 0.0) || F->r < 1) return NYS_ERR_INVALID;
+  if (w == y) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  PcgWs ws;
+  GramPlan pl;
+  pl.grid = 0;
+  pl.ldy = 64;
+  NYS_TRY(pcg_workspace(ctx, pl, F->d, 1, &ws));
+  const void* U = F->use_u32 ? F->U32.ptr : F->U.ptr;
+  NYS_TRY(launch_precond_dot(U, F->use_u32, F->d, F->r, w, ws.cvec, ws.st, nullptr, 0, nullptr, 0,
+                             2, 0.0, 0, ctx->stream));
+  NYS_TRY(launch_precond_update(U, F->use_u32, F->d, F->r, F->lam.as<double>(),
+                                F->lam_host[F->r - 1], rho, ws.cvec, w, y, nullptr, 0, nullptr, 0,
+                                nullptr, ws.st, 2, ctx->stream));
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  return NYS_OK;
+}
+
+nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                             double rho, const double* p, double* v, double* pv_host) {
+  if (ctx == nullptr || p == nullptr || v == nullptr || p == v) return NYS_ERR_INVALID;
+  NYS_TRY(validate_dense(A));
+  if (!(rho + c >= 0.0)) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  const GramPlan pl = make_gram_plan(*A, ctx->num_cu);
+  PcgWs ws;
+  NYS_TRY(pcg_workspace(ctx, pl, A->d, 1, &ws));
+  NYS_TRY(launch_gram(*A, pl, kModeHess, p, D, nullptr, ws.ypart, ws.qpart, nullptr, ctx->stream));
+  NYS_TRY(launch_reduce_update(3, ws.ypart, pl.grid, pl.ldy, ws.qpart, A->d, rho + c, p, nullptr,
+                               v, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, ws.st,
+                               ctx->stream));
+  if (pv_host != nullptr) {
+    NYS_TRY(launch_dot(v, p, A->d, &ws.st->true_rr, ctx->stream));
+    PcgDev h;
+    NYS_TRY(read_pcg_state(ctx, ws, &h));
+    *pv_host = h.true_rr;
+  }
+  return NYS_OK;
+}
+
+nys_status pcg_solve(nys_ctx ctx, const nys_dense* A, const double* D, double c, double rho,
+                     nys_factor F, const double* rhs, double* x, const nys_pcg_opts* opts,
+                     nys_pcg_info* info) {
+  if (ctx == nullptr || rhs == nullptr || x == nullptr || opts == nullptr)
+    return NYS_ERR_INVALID;
+  NYS_TRY(validate_dense(A));
+  if (!(rho > 0.0) || !(c >= 0.0) || !(opts->tol >= 0.0) || opts->max_iter < 0)
+    return NYS_ERR_INVALID;
+  if (F != nullptr && F->d != A->d) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  return pcg_run(ctx, *A, D, c, rho, F, rhs, x, *opts, info);
+}
+
+}  // extern "C"

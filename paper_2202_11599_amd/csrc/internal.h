@@ -1,0 +1,171 @@
+// Internal declarations shared by the translation units of libnysadmm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/nysadmm.h"
+
+#define NYS_TRY_HIP(expr)                                                         \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      nys::set_last_hip_error(e_, #expr, __FILE__, __LINE__);                     \
+      return NYS_ERR_HIP;                                                         \
+    }                                                                             \
+  } while (0)
+
+#define NYS_TRY(expr)                 \
+  do {                                \
+    nys_status s_ = (expr);           \
+    if (s_ != NYS_OK) return s_;      \
+  } while (0)
+
+namespace nys {
+
+void set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
+
+// Grow-only device buffer owned by a context or factor.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  nys_status reserve(size_t want);
+  void release();
+  template <typename T>
+  T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Device-side PCG bookkeeping.  Written only by kernels; read by the host at
+// convergence checks.
+struct PcgDev {
+  int done;      // 1 once converged / broken down
+  int iters;     // iterations completed when done was set
+  int flags;     // kFlag* bits
+  int pad;
+  double thr2;   // squared stopping threshold
+  double ww;     // last ||w||^2
+  double rr;     // ||rhs||^2
+  double true_rr;// last ||rhs - H_rho x||^2
+};
+constexpr int kFlagBreakdown = 1;
+constexpr int kFlagNonfinite = 2;
+constexpr int kFlagZeroRhs = 4;
+
+// Launch geometry of the fused Gram matvec for one matrix shape.
+struct GramPlan {
+  int waves = 4;     // waves per workgroup
+  int cpl = 4;       // 16-byte chunks per lane
+  int grid = 512;    // workgroups (each owns a contiguous row range)
+  int64_t rows_per_wg = 0;
+  bool aligned = true;
+  int ldy = 0;       // leading dimension of the per-workgroup partial sums
+};
+
+enum GramMode : int {
+  kModeHess = 0,     // s = D t (D NULL: s = t), q += s t
+  kModeLsGrad = 1,   // s = t - b, q += s^2
+  kModeLogit = 2,    // w = sigma(t)(1-sigma(t)) -> Dout, s = w t + b - sigma(t), q += loss
+  kModeLogGrad = 3,  // s = sigma(t) - b, q += loss
+  kModeTOnly = 4,    // s = b (no product with p), q = 0
+};
+
+
+// Pointers into the context workspace used by one PCG solve.
+struct PcgWs {
+  double* ypart = nullptr;
+  double* qpart = nullptr;
+  double* w = nullptr;
+  double* p = nullptr;
+  double* cvec = nullptr;
+  double* wy = nullptr;
+  PcgDev* st = nullptr;
+  double* wwpart = nullptr;
+  double* rrpart = nullptr;
+  double* pppart = nullptr;
+  int nred = 0;
+  int nvec = 0;
+};
+
+// ---- api.hip
+size_t align_up(size_t x);
+nys_status validate_dense(const nys_dense* A);
+nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws);
+nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out);
+nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
+                   nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
+                   nys_pcg_info* info);
+}  // namespace nys
+
+struct nys_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  nys::DevBuf ypart;     // per-workgroup partial sums of the Gram matvec
+  nys::DevBuf vecs;      // PCG / ADMM d- and n-vector temporaries
+  nys::DevBuf small;     // partial-sum arrays, scalars, PcgDev
+  nys::DevBuf gemm_ws;   // sketch temporaries (T = A Omega, ...)
+  nys::DevBuf core_ws;   // FP64 core temporaries
+  nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
+  void* host_pinned = nullptr;  // small pinned readback area
+};
+
+struct nys_factor_s {
+  int64_t d = 0;
+  int r = 0;
+  int cap = 0;               // column capacity of Omega/Y
+  double nu = 0.0;
+  int mantissa_bits = 52;
+  nys_dtype prec = NYS_F64;
+  int device = 0;
+  nys::DevBuf U;             // FP64 d x r column-major
+  nys::DevBuf U32;           // FP32 copy used by the PCG preconditioner when prec != F64
+  nys::DevBuf lam;           // FP64 r, descending
+  nys::DevBuf Omega;         // FP64 d x cap, orthonormalised blocks
+  nys::DevBuf Y;             // FP64 d x cap, sketch H Omega
+  std::vector<double> lam_host;
+  bool use_u32 = false;
+};
+
+namespace nys {
+
+// ---- gemv.hip
+GramPlan make_gram_plan(const nys_dense& A, int num_cu);
+// Launch the fused pass  t = A p;  s = mode(t);  y_g = sum_{rows of g} s_i A_i.
+nys_status launch_gram(const nys_dense& A, const GramPlan& plan, int mode, const double* p,
+                       const double* aux, double* auxout, double* ypart, double* qpart,
+                       const int* done, hipStream_t st);
+
+// ---- vec.hip
+constexpr int kVecBlock = 256;   // d-slice per workgroup of the vector kernels
+constexpr int kRedBlock = 64;    // columns per workgroup of the partial reduction
+inline int nblk(int64_t d, int b) { return (int)((d + b - 1) / b); }
+
+// v = sum_g ypart[g] + rho_eff * p ; then per `op`:
+//   op 0 (iterate): alpha = wy[k] / (sum q + rho_eff ||p||^2); x += alpha p; w -= alpha v
+//   op 1 (init):    w = rhs - v ;  ||rhs||^2 partials
+//   op 2 (true):    w = rhs - v  (true residual, FP64 accumulation)
+//   op 3 (plain):   out = v + beta * aux   (used for rhs/gradient assembly)
+nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, const double* qpart,
+                                int64_t d, double rho_eff, const double* p, double* x, double* w,
+                                const double* rhs, double* wy, int k, const double* pppart,
+                                int npp, double* wwpart, double* rrpart, PcgDev* st,
+                                hipStream_t stream);
+// *out = a^T b (one workgroup, fixed order)
+nys_status launch_dot(const double* a, const double* b, int64_t d, double* out,
+                      hipStream_t stream);
+// mode 0: PCG iteration k test + dots, 1: PCG init (threshold from ||rhs||) test + dots,
+// 2: dots only, 3: store sum(wwpart) into st->true_rr
+nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const double* w,
+                              double* cvec, PcgDev* st, const double* wwpart, int nww,
+                              const double* rrpart, int k, int mode, double tol, int tol_abs,
+                              hipStream_t stream);
+// mode 0: PCG iteration k (p = y + beta p), 1: PCG init (p = y), 2: standalone y = P^-1 w
+nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, const double* lam,
+                                 double lam_s, double rho, const double* cvec, const double* w,
+                                 double* p, double* wy, int k, const double* wwpart, int nww,
+                                 double* pppart, const PcgDev* st, int mode, hipStream_t stream);
+
+}  // namespace nys

@@ -1,0 +1,298 @@
+// d-vector kernels of the PCG loop (Algorithm Nystrom PCG) and of the
+// preconditioner apply (eq. Nyspreconditioner).  Every reduction is written
+// as per-workgroup partial sums that the next kernel adds in a fixed order, so
+// results are bitwise reproducible.  Each workgroup that needs a scalar
+// (alpha, beta, ||w||^2) recomputes it from the same partials in the same
+// order, which makes the value identical across workgroups without a grid
+// barrier.  Kernels of an iteration return at once when PcgDev::done is set,
+// so the host can enqueue several iterations between convergence checks.
+#include "internal.h"
+
+namespace nys {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of a[0..n) with a 256-thread block in a fixed order; every thread gets it.
+__device__ double block_sum_array(const double* __restrict__ a, int n, double* sh4) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += a[i];
+  s = wave_sum(s);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = s;
+  __syncthreads();
+  return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+}
+
+// Sum of one value per thread over a 256-thread block; every thread gets it.
+__device__ double block_sum_value(double v, double* sh4) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+}
+
+// 1024 threads: 64 columns x 16 slices of the workgroup partials, combined in
+// a fixed order through LDS.
+__global__ __launch_bounds__(1024) void k_reduce_update(
+    int op, const double* __restrict__ ypart, int G, int ldy, const double* __restrict__ qpart,
+    int64_t d, double rho_eff, const double* __restrict__ p, double* __restrict__ x,
+    double* __restrict__ w, const double* __restrict__ rhs, double* __restrict__ wy, int k,
+    const double* __restrict__ pppart, int npp, double* __restrict__ wwpart,
+    double* __restrict__ rrpart, PcgDev* __restrict__ st) {
+  if (op == 0 && st->done) return;
+  constexpr int S = 16;
+  __shared__ double part[S][64];
+  __shared__ double sh[S];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int grp = tid >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+
+  double acc = 0.0;
+  if (j < d)
+    for (int g = grp; g < G; g += S) acc += ypart[(int64_t)g * ldy + j];
+  part[grp][lane] = acc;
+
+  double alpha = 0.0;
+  if (op == 0) {
+    // q = sum qpart, pp = sum pppart (fixed order, identical in every workgroup)
+    double q = 0.0, pp = 0.0;
+    for (int i = tid; i < G; i += 1024) q += qpart[i];
+    for (int i = tid; i < npp; i += 1024) pp += pppart[i];
+    q = wave_sum(q);
+    pp = wave_sum(pp);
+    __syncthreads();
+    if (lane == 0) sh[grp] = q;
+    __syncthreads();
+    double qs = 0.0;
+    for (int i = 0; i < S; ++i) qs += sh[i];
+    __syncthreads();
+    if (lane == 0) sh[grp] = pp;
+    __syncthreads();
+    double ps = 0.0;
+    for (int i = 0; i < S; ++i) ps += sh[i];
+    const double pv = qs + rho_eff * ps;
+    if (!(pv > 0.0)) {
+      if (blockIdx.x == 0 && tid == 0) {
+        st->flags |= (pv != pv) ? kFlagNonfinite : kFlagBreakdown;
+        st->iters = k;
+        st->done = 1;
+      }
+      return;
+    }
+    alpha = wy[k] / pv;
+  }
+  __syncthreads();
+
+  if (grp != 0) return;
+  double ww = 0.0, rr = 0.0;
+  if (j < d) {
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) sum += part[i][lane];
+    const double pj = (p != nullptr) ? p[j] : 0.0;
+    const double v = sum + rho_eff * pj;
+    if (op == 0) {
+      x[j] += alpha * pj;
+      const double wj = w[j] - alpha * v;
+      w[j] = wj;
+      ww = wj * wj;
+    } else if (op == 1 || op == 2) {
+      const double r = rhs[j];
+      const double wj = r - v;
+      w[j] = wj;
+      ww = wj * wj;
+      rr = r * r;
+    } else {  // op 3: plain reduction
+      w[j] = v;
+    }
+  }
+  if (op == 3) return;
+  ww = wave_sum(ww);
+  rr = wave_sum(rr);
+  if (lane == 0) {
+    wwpart[blockIdx.x] = ww;
+    if (rrpart != nullptr) rrpart[blockIdx.x] = rr;
+  }
+}
+
+// mode 0: PCG iteration k (convergence test, then c = U^T w)
+// mode 1: PCG init (threshold from ||rhs||, test, then c = U^T w)
+// mode 2: standalone c = U^T w
+// mode 3: record sum(wwpart) as the true residual, no dots
+template <typename UT>
+__global__ __launch_bounds__(256) void k_precond_dot(
+    const UT* __restrict__ U, int64_t d, int r, const double* __restrict__ w,
+    double* __restrict__ cvec, PcgDev* __restrict__ st, const double* __restrict__ wwpart,
+    int nww, const double* __restrict__ rrpart, int k, int mode, double tol, int tol_abs) {
+  __shared__ double sh4[4];
+  const int tid = threadIdx.x;
+  if (mode == 0 || mode == 1) {
+    if (st->done) return;
+    const double ww = block_sum_array(wwpart, nww, sh4);
+    double thr2;
+    bool zero_rhs = false;
+    if (mode == 1) {
+      const double rr = block_sum_array(rrpart, nww, sh4);
+      thr2 = tol_abs ? tol * tol : tol * tol * rr;
+      zero_rhs = (rr == 0.0);
+      if (blockIdx.x == 0 && tid == 0) {
+        st->rr = rr;
+        st->thr2 = thr2;
+      }
+    } else {
+      thr2 = st->thr2;
+    }
+    const bool bad = !(ww == ww) || (ww > 1.7e308);
+    if (blockIdx.x == 0 && tid == 0) st->ww = ww;
+    if (zero_rhs || bad || ww <= thr2) {
+      if (blockIdx.x == 0 && tid == 0) {
+        if (bad) st->flags |= kFlagNonfinite;
+        if (zero_rhs) st->flags |= kFlagZeroRhs;
+        st->iters = (mode == 1) ? 0 : k + 1;
+        st->done = 1;
+      }
+      return;
+    }
+  } else if (mode == 3) {
+    const double ww = block_sum_array(wwpart, nww, sh4);
+    if (blockIdx.x == 0 && tid == 0) st->true_rr = ww;
+    return;
+  }
+  const int lane = tid & 63;
+  const int col = blockIdx.x * 4 + (tid >> 6);
+  if (col >= r) return;
+  const UT* u = U + (int64_t)col * d;
+  double acc = 0.0;
+  for (int64_t j = lane; j < d; j += 64) acc = fma((double)u[j], w[j], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) cvec[col] = acc;
+}
+
+// y = w + U (s o c), s_i = (lambda_s + rho)/(lambda_i + rho) - 1 ;
+// w^T y = ||w||^2 + sum s_i c_i^2.
+// mode 0: p = y + beta p (beta = (w^T y)/wy[k]), wy[k+1] = w^T y
+// mode 1: p = y, wy[0] = w^T y
+// mode 2: p (output) = y, standalone apply
+template <typename UT>
+__global__ __launch_bounds__(256) void k_precond_update(
+    const UT* __restrict__ U, int64_t d, int r, const double* __restrict__ lam, double lam_s,
+    double rho, const double* __restrict__ cvec, const double* __restrict__ w,
+    double* __restrict__ p, double* __restrict__ wy, int k, const double* __restrict__ wwpart,
+    int nww, double* __restrict__ pppart, const PcgDev* __restrict__ st, int mode) {
+  if (mode != 2 && st->done) return;
+  __shared__ double g[1024];
+  __shared__ double sh4[4];
+  const int tid = threadIdx.x;
+  double sc = 0.0;
+  for (int i = tid; i < r; i += 256) {
+    const double s = (lam_s + rho) / (lam[i] + rho) - 1.0;
+    const double ci = cvec[i];
+    g[i] = s * ci;
+    sc += s * ci * ci;
+  }
+  double wy_new = 0.0;
+  if (mode != 2) {
+    const double ww = block_sum_array(wwpart, nww, sh4);
+    wy_new = ww + block_sum_value(sc, sh4);
+  } else {
+    __syncthreads();
+  }
+  const int64_t j = (int64_t)blockIdx.x * 256 + tid;
+  double pj = 0.0;
+  if (j < d) {
+    double y = w[j];
+    const UT* u = U + j;
+    int i = 0;
+    for (; i + 4 <= r; i += 4) {
+      y = fma((double)u[(int64_t)i * d], g[i], y);
+      y = fma((double)u[(int64_t)(i + 1) * d], g[i + 1], y);
+      y = fma((double)u[(int64_t)(i + 2) * d], g[i + 2], y);
+      y = fma((double)u[(int64_t)(i + 3) * d], g[i + 3], y);
+    }
+    for (; i < r; ++i) y = fma((double)u[(int64_t)i * d], g[i], y);
+    if (mode == 0) {
+      const double beta = wy_new / wy[k];
+      pj = y + beta * p[j];
+    } else {
+      pj = y;
+    }
+    p[j] = pj;
+  }
+  if (mode == 2) return;
+  const double pp = block_sum_value(pj * pj, sh4);
+  if (tid == 0) {
+    pppart[blockIdx.x] = pp;
+    if (blockIdx.x == 0) wy[mode == 1 ? 0 : k + 1] = wy_new;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a,
+                                             const double* __restrict__ b, int64_t d,
+                                             double* __restrict__ out) {
+  __shared__ double sh4[4];
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < d; j += 256) s = fma(a[j], b[j], s);
+  s = block_sum_value(s, sh4);
+  if (threadIdx.x == 0) *out = s;
+}
+
+}  // namespace
+
+nys_status launch_dot(const double* a, const double* b, int64_t d, double* out,
+                      hipStream_t stream) {
+  hipLaunchKernelGGL(k_dot, dim3(1), dim3(256), 0, stream, a, b, d, out);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, const double* qpart,
+                                int64_t d, double rho_eff, const double* p, double* x, double* w,
+                                const double* rhs, double* wy, int k, const double* pppart,
+                                int npp, double* wwpart, double* rrpart, PcgDev* st,
+                                hipStream_t stream) {
+  hipLaunchKernelGGL(k_reduce_update, dim3(nblk(d, kRedBlock)), dim3(1024), 0, stream, op, ypart,
+                     G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp, wwpart, rrpart,
+                     st);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const double* w,
+                              double* cvec, PcgDev* st, const double* wwpart, int nww,
+                              const double* rrpart, int k, int mode, double tol, int tol_abs,
+                              hipStream_t stream) {
+  const int grid = r > 0 ? (r + 3) / 4 : 1;
+  if (u32)
+    hipLaunchKernelGGL(k_precond_dot<float>, dim3(grid), dim3(256), 0, stream,
+                       static_cast<const float*>(U), d, r, w, cvec, st, wwpart, nww, rrpart, k,
+                       mode, tol, tol_abs);
+  else
+    hipLaunchKernelGGL(k_precond_dot<double>, dim3(grid), dim3(256), 0, stream,
+                       static_cast<const double*>(U), d, r, w, cvec, st, wwpart, nww, rrpart, k,
+                       mode, tol, tol_abs);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, const double* lam,
+                                 double lam_s, double rho, const double* cvec, const double* w,
+                                 double* p, double* wy, int k, const double* wwpart, int nww,
+                                 double* pppart, const PcgDev* st, int mode, hipStream_t stream) {
+  if (r > 1024) return NYS_ERR_INVALID;
+  const int grid = nblk(d, kVecBlock);
+  if (u32)
+    hipLaunchKernelGGL(k_precond_update<float>, dim3(grid), dim3(256), 0, stream,
+                       static_cast<const float*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
+                       wwpart, nww, pppart, st, mode);
+  else
+    hipLaunchKernelGGL(k_precond_update<double>, dim3(grid), dim3(256), 0, stream,
+                       static_cast<const double*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
+                       wwpart, nww, pppart, st, mode);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+}  // namespace nys

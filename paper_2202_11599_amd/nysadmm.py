@@ -1,0 +1,359 @@
+"""ctypes binding of libnysadmm (C ABI in include/nysadmm.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every step of the computation runs in the library's HIP kernels.  The
+library is loaded on first use and a missing build raises ImportError (there is
+no fallback path).
+
+Entry points keep the C names: nys_sketch, nys_sketch_adaptive,
+nys_precond_apply, nys_hessian_apply, pcg_solve, admm_step, admm_solve, plus
+the context/factor helpers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnysadmm.so")
+_lib = None
+
+NYS_OK, NYS_ERR_INVALID, NYS_ERR_HIP, NYS_ERR_NOT_SPD, NYS_ERR_BREAKDOWN, NYS_ERR_MAXITER, \
+    NYS_ERR_NONFINITE, NYS_ERR_NOMEM, NYS_ERR_NOT_CONVERGED = range(9)
+NYS_F32, NYS_F64, NYS_BF16 = 0, 1, 2
+NYS_LOSS_LS, NYS_LOSS_LOGISTIC = 0, 1
+
+EXPORTS = [
+    "nys_status_string", "nys_ctx_create", "nys_ctx_destroy", "nys_ctx_set_stream",
+    "nys_ctx_workspace_bytes", "nys_sketch", "nys_sketch_adaptive", "nys_factor_import",
+    "nys_factor_info", "nys_factor_get_U", "nys_factor_destroy", "nys_hessian_apply",
+    "nys_precond_apply", "pcg_solve", "admm_step", "admm_solve",
+]
+
+
+class NysError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({status_string(status)})")
+
+
+class Dense(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int64), ("ld", C.c_int64),
+                ("dtype", C.c_int), ("data", C.c_void_p)]
+
+
+class PcgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("tol_abs", C.c_int), ("max_iter", C.c_int),
+                ("check_every", C.c_int), ("true_residual", C.c_int), ("max_restarts", C.c_int)]
+
+
+class PcgInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("rhs_norm", C.c_double),
+                ("res_norm", C.c_double), ("true_res_norm", C.c_double), ("status", C.c_int)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("loss", C.c_int), ("A", Dense), ("b", C.c_void_p), ("gamma", C.c_double),
+                ("c", C.c_double)]
+
+
+class AdmmOpts(C.Structure):
+    _fields_ = [("rho", C.c_double), ("rank", C.c_int), ("rank_max", C.c_int),
+                ("ada_tol", C.c_double), ("resketch_every", C.c_int), ("sketch_prec", C.c_int),
+                ("omega", C.c_void_p), ("pcg", PcgOpts), ("tol_schedule", C.c_int),
+                ("max_iter", C.c_int), ("eps_abs", C.c_double), ("eps_rel", C.c_double),
+                ("rel_change_tol", C.c_double), ("kkt_tol", C.c_double), ("kkt_every", C.c_int)]
+
+
+class AdmmState(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("z", C.c_void_p), ("u", C.c_void_p), ("k", C.c_int)]
+
+
+class AdmmInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("pcg_iters", C.c_long), ("pcg_max", C.c_int),
+                ("r_p", C.c_double), ("r_d", C.c_double), ("eta", C.c_double),
+                ("obj", C.c_double), ("rank", C.c_int), ("converged", C.c_int),
+                ("status", C.c_int)]
+
+
+def lib():
+    """Load libnysadmm.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run python -m paper_2202_11599_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "nys_status_string": (C.c_char_p, [i32]),
+        "nys_ctx_create": (i32, [i32, vp, P(vp)]),
+        "nys_ctx_destroy": (i32, [vp]),
+        "nys_ctx_set_stream": (i32, [vp, vp]),
+        "nys_ctx_workspace_bytes": (C.c_size_t, [vp]),
+        "nys_sketch": (i32, [vp, P(Dense), vp, dbl, vp, i32, i32, P(vp)]),
+        "nys_sketch_adaptive": (i32, [vp, P(Dense), vp, dbl, vp, i32, i32, dbl, dbl, i32, P(vp)]),
+        "nys_factor_import": (i32, [vp, i64, i32, vp, P(dbl), dbl, P(vp)]),
+        "nys_factor_info": (i32, [vp, P(i32), P(dbl), P(dbl), P(dbl)]),
+        "nys_factor_get_U": (i32, [vp, vp, vp]),
+        "nys_factor_destroy": (i32, [vp]),
+        "nys_hessian_apply": (i32, [vp, P(Dense), vp, dbl, dbl, vp, vp, P(dbl)]),
+        "nys_precond_apply": (i32, [vp, vp, dbl, vp, vp]),
+        "pcg_solve": (i32, [vp, P(Dense), vp, dbl, dbl, vp, vp, vp, P(PcgOpts), P(PcgInfo)]),
+        "admm_step": (i32, [vp, P(Problem), P(AdmmOpts), P(vp), P(AdmmState), P(AdmmInfo)]),
+        "admm_solve": (i32, [vp, i32, P(Problem), P(AdmmOpts), P(AdmmState), P(AdmmInfo)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    return lib().nys_status_string(int(s)).decode()
+
+
+def _check(status, where, ok=(NYS_OK,)):
+    if status not in ok:
+        raise NysError(status, where)
+    return status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _vec(t: torch.Tensor, n: int, name: str):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous CUDA float64 tensor of {n} elements")
+    return t
+
+
+def dense(A: torch.Tensor) -> Dense:
+    """Describe a row-major (n, d) tensor (contiguous rows, any row stride)."""
+    if A.dim() != 2 or not A.is_cuda or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D CUDA tensor with unit column stride")
+    dt = {torch.float32: NYS_F32, torch.float64: NYS_F64}.get(A.dtype)
+    if dt is None:
+        raise ValueError("A must be float32 or float64")
+    ld = A.stride(0) if A.shape[0] > 1 else A.shape[1]
+    return Dense(A.shape[0], A.shape[1], max(ld, A.shape[1]), dt, A.data_ptr())
+
+
+class Context:
+    """nys_ctx bound to the current torch device and stream."""
+
+    def __init__(self, device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None):
+        L = lib()
+        self.device = torch.cuda.current_device() if device is None else device
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._stream = s
+        h = C.c_void_p()
+        _check(L.nys_ctx_create(self.device, C.c_void_p(s.cuda_stream), C.byref(h)),
+               "nys_ctx_create")
+        self.h = h
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._stream = stream
+        _check(lib().nys_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)), "nys_ctx_set_stream")
+
+    def workspace_bytes(self) -> int:
+        return int(lib().nys_ctx_workspace_bytes(self.h))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            lib().nys_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Factor:
+    """Owning wrapper of a nys_factor handle."""
+
+    def __init__(self, h: C.c_void_p, d: int):
+        self.h = h
+        self.d = d
+
+    def info(self):
+        r, nu, ls = C.c_int(), C.c_double(), C.c_double()
+        _check(lib().nys_factor_info(self.h, C.byref(r), C.byref(nu), C.byref(ls), None),
+               "nys_factor_info")
+        lam = (C.c_double * r.value)()
+        lib().nys_factor_info(self.h, None, None, None, lam)
+        return {"rank": r.value, "nu": nu.value, "lambda_s": ls.value, "lam": list(lam)}
+
+    def U(self, ctx: Context) -> torch.Tensor:
+        """U as a (rank, d) FP64 tensor: row k is column k of U."""
+        r = self.info()["rank"]
+        out = torch.empty(r, self.d, dtype=torch.float64, device=f"cuda:{ctx.device}")
+        _check(lib().nys_factor_get_U(ctx.h, self.h, _ptr(out)), "nys_factor_get_U")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            lib().nys_factor_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nys_factor_import(ctx: Context, U_rows: torch.Tensor, lam: Sequence[float], nu: float = 0.0) -> Factor:
+    """Factor from U given as (r, d) FP64 rows (column-major d x r) and lambda."""
+    r, d = U_rows.shape
+    _vec(U_rows.reshape(-1), r * d, "U")
+    lam_arr = (C.c_double * r)(*[float(v) for v in lam])
+    h = C.c_void_p()
+    _check(lib().nys_factor_import(ctx.h, d, r, _ptr(U_rows), lam_arr, float(nu), C.byref(h)),
+           "nys_factor_import")
+    return Factor(h, d)
+
+
+def nys_sketch(ctx: Context, A: torch.Tensor, omega_rows: torch.Tensor, D: Optional[torch.Tensor] = None,
+               c: float = 0.0, prec: int = NYS_F64, factor: Optional[Factor] = None) -> Factor:
+    """Algorithm RandNysAppx (or one appended block if `factor` is given).
+    omega_rows: (r, d) FP64 Gaussian entries."""
+    dA = dense(A)
+    r, d = omega_rows.shape
+    _vec(omega_rows.reshape(-1), r * d, "omega")
+    if D is not None:
+        _vec(D, A.shape[0], "D")
+    h = C.c_void_p(None if factor is None else factor.h.value)
+    _check(lib().nys_sketch(ctx.h, C.byref(dA), _ptr(D), float(c), _ptr(omega_rows), int(r), int(prec),
+                            C.byref(h)), "nys_sketch")
+    if factor is not None:
+        factor.h = h
+        return factor
+    return Factor(h, d)
+
+
+def nys_sketch_adaptive(ctx: Context, A: torch.Tensor, omega_rows: torch.Tensor, s0: int, s_max: int,
+                        rho: float, tol: float, D: Optional[torch.Tensor] = None, c: float = 0.0,
+                        prec: int = NYS_F64) -> Factor:
+    dA = dense(A)
+    s, d = omega_rows.shape
+    if s < s_max:
+        raise ValueError("omega must hold s_max columns")
+    _vec(omega_rows.reshape(-1), s * d, "omega")
+    h = C.c_void_p()
+    _check(lib().nys_sketch_adaptive(ctx.h, C.byref(dA), _ptr(D), float(c), _ptr(omega_rows), int(s0),
+                                     int(s_max), float(rho), float(tol), int(prec), C.byref(h)),
+           "nys_sketch_adaptive")
+    return Factor(h, d)
+
+
+def nys_hessian_apply(ctx: Context, A: torch.Tensor, p: torch.Tensor, rho: float = 0.0,
+                      D: Optional[torch.Tensor] = None, c: float = 0.0, out: Optional[torch.Tensor] = None,
+                      want_pv: bool = False):
+    dA = dense(A)
+    _vec(p, A.shape[1], "p")
+    v = torch.empty_like(p) if out is None else out
+    pv = C.c_double()
+    _check(lib().nys_hessian_apply(ctx.h, C.byref(dA), _ptr(D), float(c), float(rho), _ptr(p), _ptr(v),
+                                   C.byref(pv) if want_pv else None), "nys_hessian_apply")
+    return (v, pv.value) if want_pv else v
+
+
+def nys_precond_apply(ctx: Context, F: Factor, rho: float, w: torch.Tensor,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _vec(w, F.d, "w")
+    y = torch.empty_like(w) if out is None else out
+    _check(lib().nys_precond_apply(ctx.h, F.h, float(rho), _ptr(w), _ptr(y)), "nys_precond_apply")
+    return y
+
+
+def pcg_opts(tol=1e-6, tol_abs=False, max_iter=1000, check_every=8, true_residual=True,
+             max_restarts=2) -> PcgOpts:
+    return PcgOpts(float(tol), int(bool(tol_abs)), int(max_iter), int(check_every),
+                   int(bool(true_residual)), int(max_restarts))
+
+
+def pcg_solve(ctx: Context, A: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor, rho: float,
+              F: Optional[Factor] = None, D: Optional[torch.Tensor] = None, c: float = 0.0,
+              opts: Optional[PcgOpts] = None, allow=(NYS_OK,)) -> PcgInfo:
+    """Solve (A^T D A + (c + rho) I) x = rhs in place (x holds x0)."""
+    dA = dense(A)
+    _vec(rhs, A.shape[1], "rhs")
+    _vec(x, A.shape[1], "x")
+    if D is not None:
+        _vec(D, A.shape[0], "D")
+    o = opts or pcg_opts()
+    info = PcgInfo()
+    st = lib().pcg_solve(ctx.h, C.byref(dA), _ptr(D), float(c), float(rho),
+                         None if F is None else F.h, _ptr(rhs), _ptr(x), C.byref(o), C.byref(info))
+    _check(st, "pcg_solve", ok=tuple(allow))
+    return info
+
+
+def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resketch_every=0,
+              sketch_prec=NYS_F64, pcg: Optional[PcgOpts] = None, tol_schedule=False, max_iter=100,
+              eps_abs=0.0, eps_rel=0.0, rel_change_tol=0.0, kkt_tol=0.0, kkt_every=10) -> AdmmOpts:
+    return AdmmOpts(float(rho), int(rank), int(rank_max), float(ada_tol), int(resketch_every),
+                    int(sketch_prec), omega_rows.data_ptr(), pcg or pcg_opts(), int(bool(tol_schedule)),
+                    int(max_iter), float(eps_abs), float(eps_rel), float(rel_change_tol),
+                    float(kkt_tol), int(kkt_every))
+
+
+def problem(A: torch.Tensor, b: torch.Tensor, gamma: float, loss=NYS_LOSS_LS, c: float = 0.0) -> Problem:
+    _vec(b, A.shape[0], "b")
+    return Problem(int(loss), dense(A), b.data_ptr(), float(gamma), float(c))
+
+
+class State:
+    """Caller-owned ADMM state (x, z, u) on the device."""
+
+    def __init__(self, d: int, device, x=None, z=None, u=None, k: int = 0):
+        z0 = lambda: torch.zeros(d, dtype=torch.float64, device=device)
+        self.x = z0() if x is None else x
+        self.z = z0() if z is None else z
+        self.u = z0() if u is None else u
+        self.k = k
+
+    def c(self) -> AdmmState:
+        return AdmmState(self.x.data_ptr(), self.z.data_ptr(), self.u.data_ptr(), int(self.k))
+
+
+def admm_step(ctx: Context, prob: Problem, opts: AdmmOpts, F: Optional[Factor], state: State,
+              allow=(NYS_OK,)):
+    """One NysADMM iteration; returns (factor, info)."""
+    h = C.c_void_p(None if F is None else F.h.value)
+    cs = state.c()
+    info = AdmmInfo()
+    st = lib().admm_step(ctx.h, C.byref(prob), C.byref(opts), C.byref(h), C.byref(cs), C.byref(info))
+    _check(st, "admm_step", ok=tuple(allow))
+    state.k = cs.k
+    if F is None:
+        F = Factor(h, prob.A.d) if h.value else None
+    else:
+        F.h = h
+    return F, info
+
+
+def admm_solve(ctx: Context, probs: Sequence[Problem], opts: Sequence[AdmmOpts], states: Sequence[State],
+               allow=(NYS_OK,)):
+    n = len(probs)
+    P = (Problem * n)(*probs)
+    O = (AdmmOpts * n)(*opts)
+    S = (AdmmState * n)(*[s.c() for s in states])
+    I = (AdmmInfo * n)()
+    st = lib().admm_solve(ctx.h, n, P, O, S, I)
+    _check(st, "admm_solve", ok=tuple(allow))
+    for s, cs in zip(states, S):
+        s.k = cs.k
+    return list(I)
