@@ -85,6 +85,14 @@ const char* nys_status_string(nys_status s);
 /* Bytes of device workspace currently held by the context. */
 size_t nys_ctx_workspace_bytes(nys_ctx ctx);
 
+/* Kernel timing (instrumentation, not part of the method): while enabled the
+ * library brackets every launch of the fused matvec-pair kernel with HIP
+ * events on the context's stream.  nys_ctx_profile_stop synchronises the
+ * stream, writes the number of launches and their summed duration in ms, and
+ * disables the timing. */
+nys_status nys_ctx_profile_start(nys_ctx ctx);
+nys_status nys_ctx_profile_stop(nys_ctx ctx, long* launches, double* total_ms);
+
 /* ------------------------------------------------------------------ sketch */
 
 /* Randomized Nystrom approximation of H = A^T diag(D) A + c I

@@ -38,6 +38,7 @@ import dataclasses
 import math
 
 import numpy as np
+import scipy.linalg as sla
 
 from .nystrom import rand_nys_appx, hessian_apply, precond_inverse_apply
 from .pcg import nys_pcg, dense_solve
@@ -126,6 +127,9 @@ def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
     else:
         x, z, u = (np.array(v, dtype=np.float64) for v in state)
     Atb = A.T @ b
+    chol = None
+    if exact:   # the subproblem matrix is constant for least squares: factor once
+        chol = sla.cho_factor(A.T @ A + (c + rho) * np.eye(d))
     matvec = lambda p: hessian_apply(A, None, c, p) + rho * p
     precond = None if exact else (lambda w: precond_inverse_apply(factor.U, factor.lam, rho, w))
     its, rps, rds = [], [], []
@@ -134,7 +138,7 @@ def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
     for k in range(iters):
         rhs = rho * (z - u) + Atb
         if exact:
-            x = dense_solve(A, None, c, rho, rhs)
+            x = sla.cho_solve(chol, rhs)
             its.append(0)
         else:
             if tol_schedule:

@@ -20,6 +20,7 @@ void set_last_hip_error(hipError_t e, const char* what, const char* file, int li
 nys_status DevBuf::reserve(size_t want) {
   if (want <= bytes && ptr != nullptr) return NYS_OK;
   if (ptr != nullptr) {
+    (void)hipDeviceSynchronize();   // kernels in flight may still use the old buffer
     (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -83,6 +84,25 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
   return NYS_OK;
 }
 
+nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int mode,
+                    const double* p, const double* aux, double* auxout, double* ypart,
+                    double* qpart, const int* done) {
+  if (!ctx->prof_on || plan.grid == 0 || A.n == 0)
+    return launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream);
+  if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      NYS_TRY_HIP(hipEventCreate(&e));
+      ctx->prof_ev.push_back(e);
+    }
+  }
+  NYS_TRY_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used], ctx->stream));
+  NYS_TRY(launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream));
+  NYS_TRY_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used + 1], ctx->stream));
+  ctx->prof_used += 2;
+  return NYS_OK;
+}
+
 nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out) {
   NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, ws.st, sizeof(PcgDev), hipMemcpyDeviceToHost,
                              ctx->stream));
@@ -94,7 +114,9 @@ nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out) {
 // Algorithm Nystrom PCG (see pcg_solve in nysadmm.h).
 nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
                    nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
-                   nys_pcg_info* info) {
+                   nys_pcg_info* info, double abs_tol) {
+  const double tol_rel = o.tol_abs ? 0.0 : o.tol;
+  const double tol_abs = o.tol_abs ? o.tol : abs_tol;
   const int64_t d = A.d;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
   const int check = o.check_every > 0 ? o.check_every : 8;
@@ -112,33 +134,46 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
   const double lam_s = (F && r > 0) ? F->lam_host[r - 1] : 0.0;
 
   int total_iters = 0, restarts = 0;
+  int chunk_prev = 1;
   PcgDev h{};
   nys_status status = NYS_OK;
   double true_rr = -1.0;
   for (;;) {
     NYS_TRY_HIP(hipMemsetAsync(ws.st, 0, sizeof(PcgDev), st));
     // w0 = rhs - H_rho x0 ; y0 = P^-1 w0 ; p0 = y0
-    NYS_TRY(launch_gram(A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr, st));
+    NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr));
     NYS_TRY(launch_reduce_update(1, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x, nullptr,
                                  ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, ws.rrpart, ws.st, st));
     NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred,
-                               ws.rrpart, -1, 1, o.tol, o.tol_abs, st));
+                               ws.rrpart, -1, 1, tol_rel, tol_abs, st));
     NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, 0,
                                   ws.wwpart, ws.nred, ws.pppart, ws.st, 1, st));
     int it = 0;
+    double ww_prev = -1.0;
     for (;;) {
       NYS_TRY(read_pcg_state(ctx, ws, &h));
       if (h.done || it >= max_iter - total_iters) break;
-      const int chunk = std::min(check, max_iter - total_iters - it);
+      // Enqueue as many iterations as the observed residual decay says are
+      // still needed, minus one, so launches after convergence (which return
+      // at once) stay rare; near the threshold this is one iteration per check.
+      int chunk = 1;
+      if (ww_prev > 0.0 && h.ww > 0.0 && h.ww < ww_prev && h.thr2 > 0.0) {
+        const double rate = std::pow(std::sqrt(h.ww / ww_prev), 1.0 / std::max(1, chunk_prev));
+        const double need = std::log(std::sqrt(h.thr2 / h.ww)) / std::log(std::max(rate, 1e-6));
+        chunk = (int)std::floor(need) - 1;
+      }
+      chunk = std::max(1, std::min(chunk, check));
+      chunk = std::min(chunk, max_iter - total_iters - it);
+      ww_prev = h.ww;
+      chunk_prev = chunk;
       for (int kk = 0; kk < chunk; ++kk) {
         const int k = it + kk;
-        NYS_TRY(launch_gram(A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done,
-                            st));
+        NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done));
         NYS_TRY(launch_reduce_update(0, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
                                      ws.w, nullptr, ws.wy, k, ws.pppart, ws.nvec, ws.wwpart,
                                      nullptr, ws.st, st));
         NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred,
-                                   nullptr, k, 0, o.tol, o.tol_abs, st));
+                                   nullptr, k, 0, tol_rel, tol_abs, st));
         NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy,
                                       k, ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st));
       }
@@ -162,7 +197,7 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
     if (!h.done) status = NYS_ERR_MAXITER;
     if (!o.true_residual) break;
     // true residual rhs - H_rho x with FP64 accumulation
-    NYS_TRY(launch_gram(A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr, st));
+    NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr));
     NYS_TRY(launch_reduce_update(2, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x, nullptr,
                                  ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, nullptr, ws.st, st));
     NYS_TRY(launch_precond_dot(U, u32, d, 0, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred, nullptr,
@@ -242,7 +277,31 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   ctx->core_ws.release();
   ctx->admm_ws.release();
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
   delete ctx;
+  return NYS_OK;
+}
+
+nys_status nys_ctx_profile_start(nys_ctx ctx) {
+  if (ctx == nullptr) return NYS_ERR_INVALID;
+  ctx->prof_on = true;
+  ctx->prof_used = 0;
+  return NYS_OK;
+}
+
+nys_status nys_ctx_profile_stop(nys_ctx ctx, long* launches, double* total_ms) {
+  if (ctx == nullptr) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < ctx->prof_used; i += 2) {
+    float ms = 0.f;
+    NYS_TRY_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[i], ctx->prof_ev[i + 1]));
+    tot += ms;
+  }
+  if (launches) *launches = (long)(ctx->prof_used / 2);
+  if (total_ms) *total_ms = tot;
+  ctx->prof_on = false;
+  ctx->prof_used = 0;
   return NYS_OK;
 }
 
@@ -323,6 +382,8 @@ nys_status nys_factor_destroy(nys_factor F) {
   F->lam.release();
   F->Omega.release();
   F->Y.release();
+  F->T.release();
+  F->Mbase.release();
   delete F;
   return NYS_OK;
 }
@@ -356,7 +417,7 @@ nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, d
   const GramPlan pl = make_gram_plan(*A, ctx->num_cu);
   PcgWs ws;
   NYS_TRY(pcg_workspace(ctx, pl, A->d, 1, &ws));
-  NYS_TRY(launch_gram(*A, pl, kModeHess, p, D, nullptr, ws.ypart, ws.qpart, nullptr, ctx->stream));
+  NYS_TRY(ctx_gram(ctx, *A, pl, kModeHess, p, D, nullptr, ws.ypart, ws.qpart, nullptr));
   NYS_TRY(launch_reduce_update(3, ws.ypart, pl.grid, pl.ldy, ws.qpart, A->d, rho + c, p, nullptr,
                                v, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, ws.st,
                                ctx->stream));

@@ -1,0 +1,570 @@
+// FP64 kernels of the Nystrom core (Algorithm RandNysAppx after the sketch):
+// tiled FP64 GEMM, in-place upper Cholesky, upper triangular inverse, power
+// iteration for ||Y||_2, two-sided block Jacobi eigensolver, eigenpair sort.
+// All of them are small (r <= 1024) and latency bound; they run once per
+// sketch, never inside the PCG loop.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace nys {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ------------------------------------------------------------ FP64 GEMM
+// C(m,n) = alpha sum_k A(m,k) B(k,n) + beta C(m,n), A(m,k) = A[m*sam + k*sak],
+// B(k,n) = B[k*sbk + n*sbn], C(m,n) = C[m*scm + n*scn].  64x64 tiles, 4x4 per
+// thread.  With gridDim.z > 1 each z handles a K chunk and writes the raw sum
+// to C + z*split_stride (layout m*N + n); k_split_reduce finishes.
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, int kchunk,
+                                               const TA* __restrict__ A, int64_t sam, int64_t sak,
+                                               const TB* __restrict__ B, int64_t sbk, int64_t sbn,
+                                               double* __restrict__ C, int64_t scm, int64_t scn,
+                                               int64_t split_stride, double alpha, double beta,
+                                               const double* __restrict__ wk) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      const int mm = idx & 63, kk = idx >> 6;
+      const int gk = k0 + kk;
+      As[kk][mm] = (m0 + mm < M && gk < ke) ? (double)A[(int64_t)(m0 + mm) * sam + (int64_t)gk * sak] : 0.0;
+      Bs[kk][mm] = (n0 + mm < N && gk < ke)
+                       ? (double)B[(int64_t)gk * sbk + (int64_t)(n0 + mm) * sbn] * (wk ? wk[gk] : 1.0)
+                       : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gm = m0 + ty + 16 * i, gn = n0 + tx + 16 * j;
+      if (gm < M && gn < N) {
+        if (gridDim.z > 1) {
+          C[blockIdx.z * split_stride + (int64_t)gm * N + gn] = acc[i][j];
+        } else {
+          double* c = C + (int64_t)gm * scm + (int64_t)gn * scn;
+          *c = (beta == 0.0) ? alpha * acc[i][j] : fma(alpha, acc[i][j], beta * *c);
+        }
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_split_reduce(int M, int N, int S,
+                                                      const double* __restrict__ ws,
+                                                      double* __restrict__ C, int64_t scm,
+                                                      int64_t scn, double alpha, double beta) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)M * N) return;
+  const int m = (int)(idx / N), n = (int)(idx % N);
+  double s = 0.0;
+  for (int z = 0; z < S; ++z) s += ws[(int64_t)z * M * N + idx];
+  double* c = C + (int64_t)m * scm + (int64_t)n * scn;
+  *c = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * *c);
+}
+
+// ------------------------------------------------------------ Cholesky
+// In-place upper Cholesky of the symmetric r x r matrix M (row-major, ld):
+// on exit M = C with C^T C = M_in, strictly lower part zeroed.  One workgroup
+// of 1024 threads, thread k owns column k; row j of C is formed at step j from
+// the rows above it.  *fail = 1 on a non-positive or non-finite pivot.
+__global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int r, int ld,
+                                                     int* __restrict__ fail) {
+  __shared__ double piv;
+  __shared__ int bad;
+  const int k = threadIdx.x;
+  if (k == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    double dot = 0.0;
+    const bool mine = (k >= j && k < r);
+    if (mine) {
+      for (int i = 0; i < j; ++i) dot = fma(M[(int64_t)i * ld + j], M[(int64_t)i * ld + k], dot);
+    }
+    if (k == j) {
+      const double s = M[(int64_t)j * ld + j] - dot;
+      if (!(s > 0.0) || !isfinite(s)) {
+        bad = 1;
+        piv = 1.0;
+      } else {
+        piv = sqrt(s);
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    if (mine) {
+      if (k == j)
+        M[(int64_t)j * ld + j] = piv;
+      else
+        M[(int64_t)j * ld + k] = (M[(int64_t)j * ld + k] - dot) / piv;
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (k == 0) *fail = 1;
+    return;
+  }
+  for (int i = k + 1; i < r; ++i) M[(int64_t)i * ld + k] = 0.0;  // column k below the diagonal
+}
+
+// Z = C^-1 for upper triangular C (r x r, row-major, ld); one wavefront per
+// column k, back substitution Z(i,k) = -(sum_{l=i+1..k} C(i,l) Z(l,k)) / C(i,i).
+__global__ __launch_bounds__(256) void k_trinv_upper(const double* __restrict__ Cm, int r, int ld,
+                                                     double* __restrict__ Z, int ldz) {
+  __shared__ double zc[4][1024];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 4 + wv;
+  if (k >= r) return;
+  double* z = zc[wv];
+  const double zkk = 1.0 / Cm[(int64_t)k * ld + k];
+  z[k] = zkk;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = 0.0;
+    for (int l = i + 1 + lane; l <= k; l += 64) s = fma(Cm[(int64_t)i * ld + l], z[l], s);
+    s = wave_sum(s);
+    const double zi = -s / Cm[(int64_t)i * ld + i];
+    z[i] = zi;  // every lane writes the same value, so each lane reads its own write
+  }
+  for (int i = lane; i < r; i += 64) Z[(int64_t)i * ldz + k] = (i <= k) ? z[i] : 0.0;
+}
+
+// Largest eigenvalue of the symmetric psd r x r matrix G by power iteration
+// (x <- G x / ||G x||), Rayleigh quotient written to *out.
+__global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ G, int r, int ld,
+                                                     int iters, double* __restrict__ out) {
+  __shared__ double x[1024];
+  __shared__ double red[16];
+  const int i = threadIdx.x, lane = i & 63, wv = i >> 6;
+  if (i < r) x[i] = 1.0 / sqrt((double)r) * (1.0 + 1e-3 * (double)(i % 7));
+  __syncthreads();
+  double lam = 0.0;
+  for (int it = 0; it <= iters; ++it) {
+    double y = 0.0;
+    if (i < r)
+      for (int k = 0; k < r; ++k) y = fma(G[(int64_t)k * ld + i], x[k], y);
+    // Rayleigh quotient x^T G x (x normalised) and ||y||^2
+    double xy = (i < r) ? x[i] * y : 0.0, yy = y * y;
+    xy = wave_sum(xy);
+    yy = wave_sum(yy);
+    __syncthreads();
+    if (lane == 0) {
+      red[wv] = xy;
+    }
+    __syncthreads();
+    double sxy = 0.0;
+    for (int w = 0; w < 16; ++w) sxy += red[w];
+    __syncthreads();
+    if (lane == 0) red[wv] = yy;
+    __syncthreads();
+    double syy = 0.0;
+    for (int w = 0; w < 16; ++w) syy += red[w];
+    lam = sxy;
+    __syncthreads();
+    if (syy <= 0.0 || !isfinite(syy)) {
+      lam = 0.0;
+      break;
+    }
+    if (i < r) x[i] = y / sqrt(syy);
+    __syncthreads();
+  }
+  if (i == 0) *out = lam;
+}
+
+// ------------------------------------------------------------ Jacobi
+// Two-sided block Jacobi on the symmetric R x R matrix G (R a multiple of 64,
+// row-major), blocks of 32 indices, block pairs chosen round-robin.  Each
+// workgroup diagonalises one 64 x 64 pair block in LDS by cyclic Jacobi with
+// parallel rotation ordering and writes its rotation Q; then every tile of G
+// becomes Q_P^T G_PQ Q_Q and V becomes V Q.
+constexpr int kJB = 32;        // block size
+constexpr int kJP = 2 * kJB;   // pair block size
+constexpr double kJacTol = 1e-15;
+
+// Round-robin pairing of nb blocks (nb even): round t, pair k -> (a, b).
+__device__ __forceinline__ void rr_pair(int nb, int t, int k, int* a, int* b) {
+  auto pos = [&](int p) { return p == 0 ? 0 : ((p - 1 + t) % (nb - 1)) + 1; };
+  *a = pos(k);
+  *b = pos(nb - 1 - k);
+}
+
+// index of the i-th member (0..63) of pair block (a, b)
+__device__ __forceinline__ int pair_index(int a, int b, int i) {
+  return i < kJB ? a * kJB + i : b * kJB + (i - kJB);
+}
+
+// A rotation is applied when |a_pq| > max(tol sqrt(|a_pp a_qq|), tol * trace(G)):
+// the relative test gives small eigenvalues their accuracy, the absolute floor
+// stops rotations that only chase the rounding of the tile updates.
+__global__ __launch_bounds__(256) void k_jacobi_solve(const double* __restrict__ G, int R,
+                                                      int round, double* __restrict__ Qbuf,
+                                                      int* __restrict__ counters, int sweep,
+                                                      const double* __restrict__ gnorm) {
+  if (sweep > 0 && counters[sweep - 1] == 0) return;  // converged at an earlier sweep
+  const double floor_abs = kJacTol * (*gnorm);
+  __shared__ double S[kJP][kJP + 1];
+  __shared__ double Q[kJP][kJP + 1];
+  __shared__ double cs[kJB][2];
+  __shared__ int any_rot;
+  const int tid = threadIdx.x;
+  const int nb = R / kJB;
+  int a, b;
+  rr_pair(nb, round, blockIdx.x, &a, &b);
+  for (int e = tid; e < kJP * kJP; e += 256) {
+    const int i = e / kJP, j = e % kJP;
+    S[i][j] = G[(int64_t)pair_index(a, b, i) * R + pair_index(a, b, j)];
+    Q[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  if (tid == 0) any_rot = 0;
+  __syncthreads();
+  int significant = 0;
+  for (int isweep = 0; isweep < 30; ++isweep) {
+    __shared__ int rot_this_sweep;
+    if (tid == 0) rot_this_sweep = 0;
+    __syncthreads();
+    for (int step = 0; step < kJP - 1; ++step) {
+      if (tid < kJB) {
+        // inner round-robin over 64 indices
+        auto pos = [&](int p) { return p == 0 ? 0 : ((p - 1 + step) % (kJP - 1)) + 1; };
+        int p = pos(tid), q = pos(kJP - 1 - tid);
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs) && apq != 0.0) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                        : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          rot_this_sweep = 1;
+        }
+        cs[tid][0] = c;
+        cs[tid][1] = s;
+      }
+      __syncthreads();
+      // rows: S <- J^T S
+      for (int e = tid; e < kJB * kJP; e += 256) {
+        const int k = e / kJP, j = e % kJP;
+        auto pos = [&](int pp) { return pp == 0 ? 0 : ((pp - 1 + step) % (kJP - 1)) + 1; };
+        int p = pos(k), q = pos(kJP - 1 - k);
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double c = cs[k][0], s = cs[k][1];
+        if (s != 0.0) {
+          const double sp = S[p][j], sq = S[q][j];
+          S[p][j] = c * sp - s * sq;
+          S[q][j] = s * sp + c * sq;
+        }
+      }
+      __syncthreads();
+      // columns: S <- S J, Q <- Q J
+      for (int e = tid; e < kJB * kJP; e += 256) {
+        const int k = e / kJP, i = e % kJP;
+        auto pos = [&](int pp) { return pp == 0 ? 0 : ((pp - 1 + step) % (kJP - 1)) + 1; };
+        int p = pos(k), q = pos(kJP - 1 - k);
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double c = cs[k][0], s = cs[k][1];
+        if (s != 0.0) {
+          const double sp = S[i][p], sq = S[i][q];
+          S[i][p] = c * sp - s * sq;
+          S[i][q] = s * sp + c * sq;
+          const double qp = Q[i][p], qq = Q[i][q];
+          Q[i][p] = c * qp - s * qq;
+          Q[i][q] = s * qp + c * qq;
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = rot_this_sweep;
+    __syncthreads();
+    if (!rot) break;
+    significant = 1;
+  }
+  double* Qo = Qbuf + (int64_t)blockIdx.x * kJP * kJP;
+  for (int e = tid; e < kJP * kJP; e += 256) Qo[e] = Q[e / kJP][e % kJP];
+  if (tid == 0 && significant) atomicAdd(&counters[sweep], 1);
+}
+
+// G_out tile (P, Q) = Q_P^T G_in[P, Q] Q_Q for pair blocks P, Q of the round,
+// and V[rows, P] <- V[rows, P] Q_P (extra workgroups).
+__global__ __launch_bounds__(256) void k_jacobi_apply(const double* __restrict__ Gin,
+                                                      double* __restrict__ Gout,
+                                                      double* __restrict__ V, int R, int round,
+                                                      const double* __restrict__ Qbuf,
+                                                      const int* __restrict__ counters,
+                                                      int sweep) {
+  if (sweep > 0 && counters[sweep - 1] == 0) return;
+  __shared__ double T[kJP][kJP + 1];
+  __shared__ double W[kJP][kJP + 1];
+  const int tid = threadIdx.x;
+  const int nb = R / kJB;
+  const int np = nb / 2;
+  const int bid = blockIdx.x;
+  if (bid < np * np) {
+    const int P = bid / np, Qi = bid % np;
+    int pa, pb, qa, qb;
+    rr_pair(nb, round, P, &pa, &pb);
+    rr_pair(nb, round, Qi, &qa, &qb);
+    const double* QP = Qbuf + (int64_t)P * kJP * kJP;
+    const double* QQ = Qbuf + (int64_t)Qi * kJP * kJP;
+    for (int e = tid; e < kJP * kJP; e += 256) {
+      const int i = e / kJP, j = e % kJP;
+      T[i][j] = Gin[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)];
+      W[i][j] = QQ[e];
+    }
+    __syncthreads();
+    // X = T * Q_Q
+    double x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = tid + t * 256;
+      const int i = e / kJP, j = e % kJP;
+      double s = 0.0;
+      for (int l = 0; l < kJP; ++l) s = fma(T[i][l], W[l][j], s);
+      x[t] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = tid + t * 256;
+      T[e / kJP][e % kJP] = x[t];
+      W[e / kJP][e % kJP] = QP[e];
+    }
+    __syncthreads();
+    // out = Q_P^T * X
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = tid + t * 256;
+      const int i = e / kJP, j = e % kJP;
+      double s = 0.0;
+      for (int l = 0; l < kJP; ++l) s = fma(W[l][i], T[l][j], s);
+      Gout[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)] = s;
+    }
+  } else {
+    const int v = bid - np * np;
+    const int P = v % np, rc = v / np;
+    int pa, pb;
+    rr_pair(nb, round, P, &pa, &pb);
+    const double* QP = Qbuf + (int64_t)P * kJP * kJP;
+    for (int e = tid; e < kJP * kJP; e += 256) {
+      const int i = e / kJP, j = e % kJP;
+      T[i][j] = V[(int64_t)(rc * kJP + i) * R + pair_index(pa, pb, j)];
+      W[i][j] = QP[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = tid + t * 256;
+      const int i = e / kJP, j = e % kJP;
+      double s = 0.0;
+      for (int l = 0; l < kJP; ++l) s = fma(T[i][l], W[l][j], s);
+      V[(int64_t)(rc * kJP + i) * R + pair_index(pa, pb, j)] = s;
+    }
+  }
+}
+
+// *out = trace of the R x R matrix (one workgroup)
+__global__ __launch_bounds__(256) void k_trace(const double* __restrict__ G, int R,
+                                               double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < R; i += 256) s += fabs(G[(int64_t)i * R + i]);
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ void k_eye(double* __restrict__ V, int R) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < (int64_t)R * R) V[e] = (e / R == e % R) ? 1.0 : 0.0;
+}
+
+// Pad the r x r matrix (ld) into an R x R zero-padded matrix.
+__global__ void k_pad(const double* __restrict__ A, int r, int ld, double* __restrict__ P, int R) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)R * R) return;
+  const int i = (int)(e / R), j = (int)(e % R);
+  P[e] = (i < r && j < r) ? A[(int64_t)i * ld + j] : 0.0;
+}
+
+// Descending order of diag(G) (R entries); perm[k] = index of the k-th largest,
+// sig2[k] its value.  Ties keep index order.
+__global__ __launch_bounds__(1024) void k_eig_sort(const double* __restrict__ G, int R,
+                                                   int* __restrict__ perm,
+                                                   double* __restrict__ sig2) {
+  const int i = threadIdx.x;
+  if (i >= R) return;
+  const double v = G[(int64_t)i * R + i];
+  int rank = 0;
+  for (int j = 0; j < R; ++j) {
+    const double w = G[(int64_t)j * R + j];
+    rank += (w > v) || (w == v && j < i);
+  }
+  perm[rank] = i;
+  sig2[rank] = v;
+}
+
+// W(k, c) = V(k, perm[c]) / sqrt(sig2[c]) for k < r, c < r  (row-major r x r, ldw)
+__global__ void k_eig_vectors(const double* __restrict__ V, int R, const int* __restrict__ perm,
+                              const double* __restrict__ sig2, int r, double* __restrict__ W,
+                              int ldw) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int k = (int)(e / r), c = (int)(e % r);
+  W[(int64_t)k * ldw + c] = V[(int64_t)k * R + perm[c]] / sqrt(sig2[c]);
+}
+
+}  // namespace
+
+nys_status gemm64(hipStream_t st, int M, int N, int K, const void* A, bool a_f32, int64_t sam,
+                  int64_t sak, const void* B, bool b_f32, int64_t sbk, int64_t sbn, double* C,
+                  int64_t scm, int64_t scn, double alpha, double beta, double* split_ws,
+                  size_t split_ws_elems, const double* wk) {
+  if (M <= 0 || N <= 0) return NYS_OK;
+  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  int S = 1;
+  if (K > 2048 && split_ws != nullptr) {
+    S = std::min((K + 1023) / 1024, std::max(1, 512 / (tm * tn)));
+    while (S > 1 && (size_t)S * M * N > split_ws_elems) --S;
+  }
+  int kchunk = (K + S - 1) / S;
+  kchunk = (kchunk + 15) / 16 * 16;
+  S = std::max(1, (K + kchunk - 1) / kchunk);
+  dim3 grid(tn, tm, S);
+  double* out = S > 1 ? split_ws : C;
+  const int64_t sstride = (int64_t)M * N;
+#define NYS_GEMM(TA, TB)                                                                     \
+  hipLaunchKernelGGL((k_gemm64<TA, TB>), grid, dim3(256), 0, st, M, N, K, kchunk,            \
+                     static_cast<const TA*>(A), sam, sak, static_cast<const TB*>(B), sbk, sbn, \
+                     out, scm, scn, sstride, alpha, beta, wk)
+  if (a_f32 && b_f32) NYS_GEMM(float, float);
+  else if (a_f32) NYS_GEMM(float, double);
+  else if (b_f32) NYS_GEMM(double, float);
+  else NYS_GEMM(double, double);
+#undef NYS_GEMM
+  if (hipGetLastError() != hipSuccess) return NYS_ERR_HIP;
+  if (S > 1) {
+    const int64_t tot = (int64_t)M * N;
+    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
+                       S, split_ws, C, scm, scn, alpha, beta);
+    if (hipGetLastError() != hipSuccess) return NYS_ERR_HIP;
+  }
+  return NYS_OK;
+}
+
+nys_status chol_upper(hipStream_t st, double* M, int r, int ld, int* fail) {
+  if (r > 1024) return NYS_ERR_INVALID;
+  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, st, M, r, ld, fail);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status trinv_upper(hipStream_t st, const double* Cm, int r, int ld, double* Z, int ldz) {
+  if (r > 1024) return NYS_ERR_INVALID;
+  hipLaunchKernelGGL(k_trinv_upper, dim3((r + 3) / 4), dim3(256), 0, st, Cm, r, ld, Z, ldz);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status power_iter(hipStream_t st, const double* G, int r, int ld, int iters, double* out) {
+  if (r > 1024) return NYS_ERR_INVALID;
+  hipLaunchKernelGGL(k_power_iter, dim3(1), dim3(1024), 0, st, G, r, ld, iters, out);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+int jacobi_pad(int r) { return std::max(64, (r + 63) / 64 * 64); }
+
+size_t jacobi_ws_doubles(int r) {
+  const int R = jacobi_pad(r);
+  const int np = R / kJP;
+  return 2 * (size_t)R * R + (size_t)R * R + (size_t)np * kJP * kJP + 2 * (size_t)R + 128;
+}
+
+// Eigendecomposition of the symmetric r x r matrix G (row-major, ld) by block
+// Jacobi.  Outputs: sig2 (r, descending) and W (r x r row-major, ldw) with
+// W(:, c) = v_c / sqrt(sig2_c).  ws must hold jacobi_ws_doubles(r) doubles;
+// counters (>= max_sweeps ints) and host_flag are scratch.  Returns
+// NYS_ERR_NOT_CONVERGED if a sweep still rotated after max_sweeps.
+nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws, int* counters,
+                      int max_sweeps, void* host_pinned, double* sig2, double* W, int ldw,
+                      int* sweeps_out) {
+  const int R = jacobi_pad(r);
+  const int nb = R / kJB;
+  const int np = nb / 2;
+  double* G0 = ws;
+  double* G1 = G0 + (size_t)R * R;
+  double* V = G1 + (size_t)R * R;
+  double* Qb = V + (size_t)R * R;
+  double* s2 = Qb + (size_t)np * kJP * kJP;
+  int* perm = reinterpret_cast<int*>(s2 + R);
+  double* gnorm = s2 + 2 * R;   // perm occupies R ints = R/2 doubles
+  const int64_t RR = (int64_t)R * R;
+  hipLaunchKernelGGL(k_pad, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, G, r, ld, G0, R);
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, G0, R, gnorm);
+  hipLaunchKernelGGL(k_eye, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, V, R);
+  if (hipMemsetAsync(counters, 0, sizeof(int) * (max_sweeps + 1), st) != hipSuccess)
+    return NYS_ERR_HIP;
+  int sweeps = 0;
+  bool converged = false;
+  for (int s = 0; s < max_sweeps; ++s) {
+    for (int t = 0; t < nb - 1; ++t) {
+      hipLaunchKernelGGL(k_jacobi_solve, dim3(np), dim3(256), 0, st, G0, R, t, Qb, counters, s,
+                         gnorm);
+      hipLaunchKernelGGL(k_jacobi_apply, dim3(np * np + np * (R / kJP)), dim3(256), 0, st, G0, G1,
+                         V, R, t, Qb, counters, s);
+      std::swap(G0, G1);
+    }
+    ++sweeps;
+    // a sweep without any significant rotation means G0 is diagonal to the
+    // tolerance; checking after every sweep means no launch is ever skipped
+    // on the device, so the host-side buffer swap stays in step
+    if (hipMemcpyAsync(host_pinned, counters + s, sizeof(int), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return NYS_ERR_HIP;
+    if (*static_cast<int*>(host_pinned) == 0) {
+      converged = true;
+      break;
+    }
+  }
+  if (!converged) return NYS_ERR_NOT_CONVERGED;
+  hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, G0, R, perm, s2);
+  if (hipMemcpyAsync(sig2, s2, sizeof(double) * r, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return NYS_ERR_HIP;
+  const int64_t rr = (int64_t)r * r;
+  hipLaunchKernelGGL(k_eig_vectors, dim3((unsigned)((rr + 255) / 256)), dim3(256), 0, st, V, R,
+                     perm, s2, r, W, ldw);
+  if (sweeps_out) *sweeps_out = sweeps;
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+}  // namespace nys

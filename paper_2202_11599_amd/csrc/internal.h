@@ -91,13 +91,45 @@ struct PcgWs {
 
 // ---- api.hip
 size_t align_up(size_t x);
+// launch_gram on the context's stream, timed when profiling is on
+nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int mode,
+                    const double* p, const double* aux, double* auxout, double* ypart,
+                    double* qpart, const int* done);
 nys_status validate_dense(const nys_dense* A);
 nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws);
 nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out);
+
+// ---- core.hip
+// C(m,n) = alpha sum_k A(m,k) w_k B(k,n) + beta C(m,n) in FP64 (w NULL: 1),
+// A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn], C(m,n) = C[m*scm + n*scn].
+nys_status gemm64(hipStream_t st, int M, int N, int K, const void* A, bool a_f32, int64_t sam,
+                  int64_t sak, const void* B, bool b_f32, int64_t sbk, int64_t sbn, double* C,
+                  int64_t scm, int64_t scn, double alpha, double beta, double* split_ws,
+                  size_t split_ws_elems, const double* wk = nullptr);
+nys_status chol_upper(hipStream_t st, double* M, int r, int ld, int* fail);
+nys_status trinv_upper(hipStream_t st, const double* Cm, int r, int ld, double* Z, int ldz);
+nys_status power_iter(hipStream_t st, const double* G, int r, int ld, int iters, double* out);
+int jacobi_pad(int r);
+size_t jacobi_ws_doubles(int r);
+nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws, int* counters,
+                      int max_sweeps, void* host_pinned, double* sig2, double* W, int ldw,
+                      int* sweeps_out);
+// Stop when ||w|| <= max(abs_tol, tol ||rhs||) (o.tol_abs: ||w|| <= o.tol).
 nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
                    nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
-                   nys_pcg_info* info);
+                   nys_pcg_info* info, double abs_tol = 0.0);
 }  // namespace nys
+
+// Key of the cached A^T b of the lasso right-hand side.
+struct AtbKey {
+  const void* A = nullptr;
+  const double* b = nullptr;
+  int64_t n = -1, d = -1, ld = -1;
+  const void* buf = nullptr;
+  bool operator==(const AtbKey& o) const {
+    return A == o.A && b == o.b && n == o.n && d == o.d && ld == o.ld && buf == o.buf;
+  }
+};
 
 struct nys_ctx_s {
   int device = 0;
@@ -110,6 +142,10 @@ struct nys_ctx_s {
   nys::DevBuf core_ws;   // FP64 core temporaries
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
   void* host_pinned = nullptr;  // small pinned readback area
+  AtbKey atb_key;                // which (A, b) the cached A^T b in admm_ws belongs to
+  bool prof_on = false;          // time matvec-pair launches with events
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
 };
 
 struct nys_factor_s {
@@ -125,6 +161,8 @@ struct nys_factor_s {
   nys::DevBuf lam;           // FP64 r, descending
   nys::DevBuf Omega;         // FP64 d x cap, orthonormalised blocks
   nys::DevBuf Y;             // FP64 d x cap, sketch H Omega
+  nys::DevBuf T;             // FP32 n x cap column-major, A Omega (FP32/BF16 sketches)
+  nys::DevBuf Mbase;         // FP64 cap x cap, Omega^T H Omega from T (FP32/BF16 sketches)
   std::vector<double> lam_host;
   bool use_u32 = false;
 };
@@ -160,8 +198,8 @@ nys_status launch_dot(const double* a, const double* b, int64_t d, double* out,
 // 2: dots only, 3: store sum(wwpart) into st->true_rr
 nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const double* w,
                               double* cvec, PcgDev* st, const double* wwpart, int nww,
-                              const double* rrpart, int k, int mode, double tol, int tol_abs,
-                              hipStream_t stream);
+                              const double* rrpart, int k, int mode, double tol_rel,
+                              double tol_abs, hipStream_t stream);
 // mode 0: PCG iteration k (p = y + beta p), 1: PCG init (p = y), 2: standalone y = P^-1 w
 nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, const double* lam,
                                  double lam_s, double rho, const double* cvec, const double* w,

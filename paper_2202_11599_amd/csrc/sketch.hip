@@ -1,16 +1,710 @@
-// Randomized Nystrom sketch and its FP64 core (Algorithm RandNysAppx).
+// Randomized Nystrom sketch (Algorithm RandNysAppx, block step of Algorithm
+// AdaptiveRandNysAppx) and its FP64 core.
+//
+//   omega (Gaussian, d x m)  --CholeskyQR2 (FP64)-->  Omega block
+//   T = A Omega               (n x m, MFMA for FP32/BF16, FP64 tiles otherwise)
+//   Y = A^T (D o T) + c Omega (d x m, split-K MFMA + FP64 reduction)
+//   core (FP64): nu from ||Y||_2, Cholesky of Omega^T Y_nu, B = Y_nu C^-1,
+//   G = B^T B = V Sigma^2 V^T (block Jacobi), U = B V Sigma^-1,
+//   Lambda = max(0, Sigma^2 - nu).
+//
+// In the FP32/BF16 forms the GEMMs use Omega rounded to that precision, and the
+// core uses that rounded Omega (upcast) as the test matrix, so Y is a sketch of
+// exactly the matrix the GEMMs multiplied.  Their core matrix Omega^T H Omega
+// is formed as T^T D T + c Omega^T Omega in FP64 from the FP32 T, which equals
+// Omega^T Y in exact arithmetic and stays positive definite whatever rounding
+// the A^T pass carried.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
 #include "internal.h"
+
+namespace nys {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBK = 32;     // K step of the MFMA kernels
+constexpr int kOPad = 40;   // LDS row pitch (elements) of the Omega / A^T tiles
+
+__device__ __forceinline__ bf16x8 to_bf16(const f8& x) {
+  bf16x8 r;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) r[v] = (__bf16)x[v];
+  return r;
+}
+
+// Load 8 consecutive floats p[0..7] (elements at or past `valid` are 0).
+__device__ __forceinline__ f8 load8(const float* p, int valid, bool vec) {
+  f8 r;
+  if (vec && valid >= 8) {
+    const f4 a = *reinterpret_cast<const f4*>(p);
+    const f4 b = *reinterpret_cast<const f4*>(p + 4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      r[v] = a[v];
+      r[v + 4] = b[v];
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) r[v] = v < valid ? p[v] : 0.0f;
+  }
+  return r;
+}
+
+// T(:, col0 + c) = A Omega_lp(:, c), c < ncols.  Workgroup: 128 rows x 16*NB
+// columns; wavefront w owns rows [32w, 32w + 32) (two 16-row MFMA blocks) and
+// every column block.  Omega_lp is (rows = columns of Omega) x ldo with zero
+// padding up to ldo (a multiple of 32) and up to 16*NB rows.
+template <bool BF, int NB>
+__global__ __launch_bounds__(256) void k_sk1(const float* __restrict__ A, int64_t n, int d,
+                                             int64_t ld, int vec, const void* __restrict__ Olp,
+                                             int ldo, float* __restrict__ T, int64_t ldt,
+                                             int col0, int ncols) {
+  constexpr int NP = 16 * NB;
+  __shared__ __attribute__((aligned(32))) char smem[NP * kOPad * (BF ? 2 : 4)];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int q = lane >> 4, m = lane & 15;
+  const int64_t m0 = (int64_t)blockIdx.x * 128 + 32 * wv;
+  const int n0 = blockIdx.y * NP;
+  f4 acc[2][NB];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = (f4)0.0f;
+
+  for (int k0 = 0; k0 < d; k0 += kBK) {
+    // stage the Omega tile (NP columns x 32 k) in LDS
+    if (BF) {
+      const __bf16* O = static_cast<const __bf16*>(Olp);
+      __bf16* Os = reinterpret_cast<__bf16*>(smem);
+      for (int e = tid; e < NP * 4; e += 256) {   // 16-byte chunks
+        const int nn = e >> 2, kk = (e & 3) * 8;
+        const uint4 v = *reinterpret_cast<const uint4*>(O + (int64_t)(n0 + nn) * ldo + k0 + kk);
+        *reinterpret_cast<uint4*>(Os + nn * kOPad + kk) = v;
+      }
+    } else {
+      const float* O = static_cast<const float*>(Olp);
+      float* Os = reinterpret_cast<float*>(smem);
+      for (int e = tid; e < NP * 8; e += 256) {
+        const int nn = e >> 3, kk = (e & 7) * 4;
+        const f4 v = *reinterpret_cast<const f4*>(O + (int64_t)(n0 + nn) * ldo + k0 + kk);
+        *reinterpret_cast<f4*>(Os + nn * kOPad + kk) = v;
+      }
+    }
+    __syncthreads();
+    f8 af[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const int64_t row = m0 + 16 * mb + m;
+      const int kk = k0 + 8 * q;
+      af[mb] = (row < n) ? load8(A + row * ld + kk, d - kk, vec) : (f8)0.0f;
+    }
+    if (BF) {
+      const bf16x8 a0 = to_bf16(af[0]), a1 = to_bf16(af[1]);
+      const __bf16* Os = reinterpret_cast<const __bf16*>(smem);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Os + (nb * 16 + m) * kOPad + 8 * q);
+        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[0][nb], 0, 0, 0);
+        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc[1][nb], 0, 0, 0);
+      }
+    } else {
+      const float* Os = reinterpret_cast<const float*>(smem);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const f8 bv = *reinterpret_cast<const f8*>(Os + (nb * 16 + m) * kOPad + 8 * q);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0][s], bv[s], acc[0][nb], 0, 0, 0);
+          acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1][s], bv[s], acc[1][nb], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = n0 + nb * 16 + m;
+      if (c >= ncols) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + 16 * mb + 4 * q + v;
+        if (row < n) T[(int64_t)(col0 + c) * ldt + row] = acc[mb][nb][v];
+      }
+    }
+}
+
+// Ypart[s][c][j] = sum_{i in slice s} A[i][j] D[i] T[i][c]  (j < d, c < ncols).
+// Workgroup: 128 columns j of A x all 16*NB sketch columns; the A^T tile goes
+// through LDS (transposed), wavefront w owns column blocks w, w+4, ...  BF16
+// form: T o D is split into bf16 hi + lo parts (two MFMAs), so only A is
+// rounded to BF16.
+template <bool BF, int NB>
+__global__ __launch_bounds__(256) void k_sk2(const float* __restrict__ A, int64_t n, int d,
+                                             int64_t ld, int vec, const double* __restrict__ D,
+                                             const float* __restrict__ T, int64_t ldt, int col0,
+                                             int ncols, int64_t slice, float* __restrict__ Yp,
+                                             int ldy) {
+  constexpr int NBW = NB / 4;
+  __shared__ __attribute__((aligned(32))) char smem[128 * kOPad * (BF ? 2 : 4)];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int q = lane >> 4, m = lane & 15;
+  const int j0 = blockIdx.x * 128;
+  const int64_t i_beg = (int64_t)blockIdx.y * slice;
+  const int64_t i_end = (i_beg + slice < n) ? i_beg + slice : n;
+  f4 acc[8][NBW];
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+    for (int t = 0; t < NBW; ++t) acc[mb][t] = (f4)0.0f;
+
+  for (int64_t i0 = i_beg; i0 < i_end; i0 += kBK) {
+    // A tile rows i0..i0+31, columns j0..j0+127 -> LDS as [j][i]
+    {
+      const int kk = tid >> 3;            // row within the tile
+      const int jc = (tid & 7) * 16;      // 16 columns
+      const int64_t i = i0 + kk;
+      float vals[16];
+      if (i < i_end) {
+        const float* src = A + i * ld + j0 + jc;
+        const int valid = d - (j0 + jc);
+        const f8 x0 = load8(src, valid, vec);
+        const f8 x1 = load8(src + 8, valid - 8, vec);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          vals[v] = x0[v];
+          vals[v + 8] = x1[v];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) vals[v] = 0.0f;
+      }
+      if (BF) {
+        __bf16* As = reinterpret_cast<__bf16*>(smem);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) As[(jc + v) * kOPad + kk] = (__bf16)vals[v];
+      } else {
+        float* As = reinterpret_cast<float*>(smem);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) As[(jc + v) * kOPad + kk] = vals[v];
+      }
+    }
+    __syncthreads();
+    // B fragments: (D o T)[i0 + 8q .. +7][c], c = 16 nb + m
+    f8 bfr[NBW];
+    {
+      const int64_t ib = i0 + 8 * q;
+      const int valid = (int)((i_end - ib) < 8 ? (i_end - ib) : 8);
+      f8 dv;
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        dv[v] = (D != nullptr && v < valid) ? (float)D[ib + v] : 1.0f;
+#pragma unroll
+      for (int t = 0; t < NBW; ++t) {
+        const int c = (wv + 4 * t) * 16 + m;
+        f8 x = (c < ncols && valid > 0) ? load8(T + (int64_t)(col0 + c) * ldt + ib, valid, true)
+                                        : (f8)0.0f;
+        if (D != nullptr) x = x * dv;
+        bfr[t] = x;
+      }
+    }
+    if (BF) {
+      const __bf16* As = reinterpret_cast<const __bf16*>(smem);
+      bf16x8 bh[NBW], bl[NBW];
+#pragma unroll
+      for (int t = 0; t < NBW; ++t) {
+        bh[t] = to_bf16(bfr[t]);
+        f8 rest;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) rest[v] = bfr[t][v] - (float)bh[t][v];
+        bl[t] = to_bf16(rest);
+      }
+#pragma unroll
+      for (int mb = 0; mb < 8; ++mb) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + (mb * 16 + m) * kOPad + 8 * q);
+#pragma unroll
+        for (int t = 0; t < NBW; ++t) {
+          acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh[t], acc[mb][t], 0, 0, 0);
+          acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[t], acc[mb][t], 0, 0, 0);
+        }
+      }
+    } else {
+      const float* As = reinterpret_cast<const float*>(smem);
+#pragma unroll
+      for (int mb = 0; mb < 8; ++mb) {
+        const f8 av = *reinterpret_cast<const f8*>(As + (mb * 16 + m) * kOPad + 8 * q);
+#pragma unroll
+        for (int t = 0; t < NBW; ++t)
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bfr[t][s], acc[mb][t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  float* Ys = Yp + (int64_t)blockIdx.y * ncols * ldy;
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+    for (int t = 0; t < NBW; ++t) {
+      const int c = (wv + 4 * t) * 16 + m;
+      if (c >= ncols) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = j0 + mb * 16 + 4 * q + v;
+        if (j < d) Ys[(int64_t)c * ldy + j] = acc[mb][t][v];
+      }
+    }
+}
+
+// Y(:, col0 + c) = sum_s Ypart[s][c] + coef * Omega(:, col0 + c)   (FP64)
+__global__ void k_sk2_reduce(const float* __restrict__ Yp, int S, int ncols, int ldy, int d,
+                             const double* __restrict__ Om, double coef, double* __restrict__ Y,
+                             int col0) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)ncols * d) return;
+  const int c = (int)(e / d), j = (int)(e % d);
+  double s = 0.0;
+  for (int z = 0; z < S; ++z) s += (double)Yp[((int64_t)z * ncols + c) * ldy + j];
+  const int64_t o = (int64_t)(col0 + c) * d + j;
+  Y[o] = s + coef * Om[o];
+}
+
+// Round the FP64 Omega block to the sketch precision: the low-precision copy
+// (rows = columns, pitch ldo, zero padded to nrows_pad x ldo) and the FP64
+// value of the rounded entries written back into Omega.
+template <bool BF>
+__global__ void k_round_omega(double* __restrict__ Om, int d, int m, void* __restrict__ lp,
+                              int ldo, int nrows_pad) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nrows_pad * ldo) return;
+  const int c = (int)(e / ldo), j = (int)(e % ldo);
+  double v = 0.0;
+  if (c < m && j < d) v = Om[(int64_t)c * d + j];
+  if (BF) {
+    const __bf16 b = (__bf16)(float)v;
+    static_cast<__bf16*>(lp)[e] = b;
+    if (c < m && j < d) Om[(int64_t)c * d + j] = (double)(float)b;
+  } else {
+    const float f = (float)v;
+    static_cast<float*>(lp)[e] = f;
+    if (c < m && j < d) Om[(int64_t)c * d + j] = (double)f;
+  }
+}
+
+// y = x + a * z elementwise (n entries)
+__global__ void k_axpy(int64_t n, const double* __restrict__ x, double a,
+                       const double* __restrict__ z, double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) y[e] = x[e] + a * z[e];
+}
+
+// M = 0.5 (X + X^T) + nu * Gam  (r x r, row-major)
+__global__ void k_shift_sym(const double* __restrict__ X, const double* __restrict__ Gam,
+                            double nu, int r, double* __restrict__ M) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e / r), j = (int)(e % r);
+  M[e] = 0.5 * (X[(int64_t)i * r + j] + X[(int64_t)j * r + i]) + nu * Gam[e];
+}
+
+// mirror the upper-left block's new columns: M[c][i] = M[i][c] for c >= c0
+__global__ void k_mirror_cols(double* __restrict__ M, int ld, int c0, int r) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * (r - c0)) return;
+  const int i = (int)(e / (r - c0)), c = c0 + (int)(e % (r - c0));
+  if (i < c0) M[(int64_t)c * ld + i] = M[(int64_t)i * ld + c];
+}
+
+__global__ void k_lambda(const double* __restrict__ sig2, double nu, int r,
+                         double* __restrict__ lam) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < r) lam[i] = fmax(0.0, sig2[i] - nu);
+}
+
+__global__ void k_to_f32(const double* __restrict__ x, int64_t n, float* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) y[e] = (float)x[e];
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+struct CoreWs {
+  double *GY, *GO, *M, *Cinv, *Bm, *G, *W, *sig2, *jac, *split, *scal;
+  int* ints;
+  size_t split_elems;
+};
+
+nys_status core_workspace(nys_ctx ctx, int64_t d, int r, CoreWs* w) {
+  const size_t rr = align_up(sizeof(double) * (size_t)r * r);
+  const size_t dr = align_up(sizeof(double) * (size_t)d * r);
+  const size_t jac = align_up(sizeof(double) * jacobi_ws_doubles(r));
+  w->split_elems = std::max<size_t>((size_t)16 * r * r, (size_t)4 * d * std::min(r, 64));
+  const size_t split = align_up(sizeof(double) * w->split_elems);
+  const size_t total = 6 * rr + dr + jac + split + align_up(sizeof(double) * 1024) + 4096 + 4096;
+  NYS_TRY(ctx->core_ws.reserve(total));
+  char* p = static_cast<char*>(ctx->core_ws.ptr);
+  auto take = [&](size_t b) { char* q = p; p += b; return reinterpret_cast<double*>(q); };
+  w->GY = take(rr);
+  w->GO = take(rr);
+  w->M = take(rr);
+  w->Cinv = take(rr);
+  w->G = take(rr);
+  w->W = take(rr);
+  w->Bm = take(dr);
+  w->jac = take(jac);
+  w->split = take(split);
+  w->sig2 = take(align_up(sizeof(double) * 1024));
+  w->scal = take(4096);
+  w->ints = reinterpret_cast<int*>(take(4096));
+  return NYS_OK;
+}
+
+nys_status read_back(nys_ctx ctx, const void* dev, size_t bytes, void* host) {
+  NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  std::memcpy(host, ctx->host_pinned, bytes);
+  return NYS_OK;
+}
+
+double eps_of(double x, int mbits) {
+  int e = 0;
+  (void)std::frexp(x, &e);   // x = f 2^e, f in [0.5, 1)
+  return std::ldexp(1.0, e - 1 - mbits);
+}
+
+// Thin QR of the Gaussian block by CholeskyQR2 (two passes of Gram ->
+// Cholesky -> Q = X R^-1), in place on Om (d x m, column-major).
+nys_status orthonormalize(nys_ctx ctx, double* Om, int64_t d, int m, const CoreWs& w) {
+  hipStream_t st = ctx->stream;
+  for (int pass = 0; pass < 2; ++pass) {
+    NYS_TRY(gemm64(st, m, m, (int)d, Om, false, d, 1, Om, false, 1, d, w.M, m, 1, 1.0, 0.0,
+                   w.split, w.split_elems));
+    NYS_TRY_HIP(hipMemsetAsync(w.ints, 0, sizeof(int), st));
+    NYS_TRY(chol_upper(st, w.M, m, m, w.ints));
+    int fail = 0;
+    NYS_TRY(read_back(ctx, w.ints, sizeof(int), &fail));
+    if (fail) return NYS_ERR_NOT_SPD;   // Gaussian block without full column rank
+    NYS_TRY(trinv_upper(st, w.M, m, m, w.Cinv, m));
+    // Bm = Om Rinv  (d x m col-major), then copy back
+    NYS_TRY(gemm64(st, (int)d, m, m, Om, false, 1, d, w.Cinv, false, m, 1, w.Bm, 1, d, 1.0, 0.0,
+                   w.split, w.split_elems));
+    NYS_TRY_HIP(hipMemcpyAsync(Om, w.Bm, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
+  }
+  return NYS_OK;
+}
+
+// The FP64 core of Algorithm RandNysAppx on the factor's current sketch.
+nys_status nys_core(nys_ctx ctx, nys_factor F) {
+  hipStream_t st = ctx->stream;
+  const int64_t d = F->d;
+  const int r = F->r;
+  CoreWs w;
+  NYS_TRY(core_workspace(ctx, d, r, &w));
+  const double* Y = F->Y.as<double>();
+  const double* Om = F->Omega.as<double>();
+  // ||Y||_2 = sqrt(lambda_max(Y^T Y))
+  NYS_TRY(gemm64(st, r, r, (int)d, Y, false, d, 1, Y, false, 1, d, w.GY, r, 1, 1.0, 0.0, w.split,
+                 w.split_elems));
+  NYS_TRY(power_iter(st, w.GY, r, r, 300, w.scal));
+  // Omega^T Omega
+  NYS_TRY(gemm64(st, r, r, (int)d, Om, false, d, 1, Om, false, 1, d, w.GO, r, 1, 1.0, 0.0,
+                 w.split, w.split_elems));
+  // base core matrix Omega^T Y (FP64 form) or the stored T^T D T + c Omega^T Omega
+  const double* base;
+  if (F->prec == NYS_F64) {
+    NYS_TRY(gemm64(st, r, r, (int)d, Om, false, d, 1, Y, false, 1, d, w.G, r, 1, 1.0, 0.0,
+                   w.split, w.split_elems));
+    base = w.G;
+  } else {
+    base = F->Mbase.as<double>();
+  }
+  double lmax = 0.0;
+  NYS_TRY(read_back(ctx, w.scal, sizeof(double), &lmax));
+  if (!(lmax > 0.0) || !std::isfinite(lmax)) return NYS_ERR_NONFINITE;
+  double nu = std::sqrt((double)d) * eps_of(std::sqrt(lmax), F->mantissa_bits);
+  int attempt = 0;
+  for (;; ++attempt) {
+    hipLaunchKernelGGL(k_shift_sym, dim3(blocks((int64_t)r * r)), dim3(256), 0, st, base, w.GO,
+                       nu, r, w.M);
+    NYS_TRY_HIP(hipMemsetAsync(w.ints, 0, sizeof(int), st));
+    NYS_TRY(chol_upper(st, w.M, r, r, w.ints));
+    int fail = 0;
+    NYS_TRY(read_back(ctx, w.ints, sizeof(int), &fail));
+    if (!fail) break;
+    if (attempt == 3) return NYS_ERR_NOT_SPD;
+    nu *= 10.0;
+  }
+  NYS_TRY(trinv_upper(st, w.M, r, r, w.Cinv, r));
+  // B = (Y + nu Omega) C^-1 : two GEMMs into Bm (d x r col-major)
+  NYS_TRY(gemm64(st, (int)d, r, r, Y, false, 1, d, w.Cinv, false, r, 1, w.Bm, 1, d, 1.0, 0.0,
+                 w.split, w.split_elems));
+  NYS_TRY(gemm64(st, (int)d, r, r, Om, false, 1, d, w.Cinv, false, r, 1, w.Bm, 1, d, nu, 1.0,
+                 w.split, w.split_elems));
+  // G = B^T B, eigendecomposition G = V Sigma^2 V^T
+  NYS_TRY(gemm64(st, r, r, (int)d, w.Bm, false, d, 1, w.Bm, false, 1, d, w.G, r, 1, 1.0, 0.0,
+                 w.split, w.split_elems));
+  int sweeps = 0;
+  NYS_TRY(jacobi_eig(st, w.G, r, r, w.jac, w.ints + 16, 40, ctx->host_pinned, w.sig2, w.W, r,
+                     &sweeps));
+  // U = B V Sigma^-1
+  NYS_TRY(F->U.reserve(sizeof(double) * d * r));
+  NYS_TRY(gemm64(st, (int)d, r, r, w.Bm, false, 1, d, w.W, false, r, 1, F->U.as<double>(), 1, d,
+                 1.0, 0.0, w.split, w.split_elems));
+  NYS_TRY(F->lam.reserve(sizeof(double) * r));
+  hipLaunchKernelGGL(k_lambda, dim3(blocks(r)), dim3(256), 0, st, w.sig2, nu, r,
+                     F->lam.as<double>());
+  F->lam_host.resize(r);
+  NYS_TRY(read_back(ctx, F->lam.ptr, sizeof(double) * r, F->lam_host.data()));
+  for (double v : F->lam_host)
+    if (!std::isfinite(v)) return NYS_ERR_NONFINITE;
+  F->nu = nu;
+  F->use_u32 = (F->prec != NYS_F64);
+  if (F->use_u32) {
+    NYS_TRY(F->U32.reserve(sizeof(float) * d * r));
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks(d * r)), dim3(256), 0, st, F->U.as<double>(), d * r,
+                       F->U32.as<float>());
+  }
+  NYS_TRY_HIP(hipGetLastError());
+  return NYS_OK;
+}
+
+nys_status grow(nys::DevBuf& b, size_t old_bytes, size_t new_bytes, hipStream_t st) {
+  if (b.bytes >= new_bytes && b.ptr != nullptr) return NYS_OK;
+  nys::DevBuf nb;
+  NYS_TRY(nb.reserve(new_bytes));
+  if (old_bytes > 0 && b.ptr != nullptr)
+    NYS_TRY_HIP(hipMemcpyAsync(nb.ptr, b.ptr, old_bytes, hipMemcpyDeviceToDevice, st));
+  NYS_TRY_HIP(hipStreamSynchronize(st));
+  b.release();
+  b = nb;
+  return NYS_OK;
+}
+
+template <bool BF>
+nys_status launch_sk1(int NB, const nys_dense& A, int vec, const void* Olp, int ldo, float* T,
+                      int64_t ldt, int col0, int ncols, int npass, hipStream_t st) {
+  dim3 grid((unsigned)((A.n + 127) / 128), npass);
+  const float* a = static_cast<const float*>(A.data);
+#define NYS_SK1(N)                                                                            \
+  hipLaunchKernelGGL((k_sk1<BF, N>), grid, dim3(256), 0, st, a, A.n, (int)A.d, A.ld, vec, Olp, \
+                     ldo, T, ldt, col0, ncols)
+  if (NB == 4) NYS_SK1(4);
+  else if (NB == 8) NYS_SK1(8);
+  else NYS_SK1(16);
+#undef NYS_SK1
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+template <bool BF>
+nys_status launch_sk2(int NB, const nys_dense& A, int vec, const double* D, const float* T,
+                      int64_t ldt, int col0, int ncols, int64_t slice, int S, float* Yp, int ldy,
+                      hipStream_t st) {
+  dim3 grid((unsigned)((A.d + 127) / 128), S);
+  const float* a = static_cast<const float*>(A.data);
+#define NYS_SK2(N)                                                                            \
+  hipLaunchKernelGGL((k_sk2<BF, N>), grid, dim3(256), 0, st, a, A.n, (int)A.d, A.ld, vec, D, T, \
+                     ldt, col0, ncols, slice, Yp, ldy)
+  if (NB == 4) NYS_SK2(4);
+  else if (NB == 8) NYS_SK2(8);
+  else NYS_SK2(16);
+#undef NYS_SK2
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+// Sketch one block of m new columns into F (columns r_old .. r_old+m-1).
+nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double c,
+                        const double* omega, int m, nys_factor F) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = A.n, d = A.d;
+  const int r0 = F->r, r1 = F->r + m;
+  // capacity
+  if (r1 > F->cap) {
+    const int cap = std::min<int64_t>(std::max(r1, 2 * F->cap), d - 1);
+    NYS_TRY(grow(F->Omega, sizeof(double) * d * r0, sizeof(double) * d * cap, st));
+    NYS_TRY(grow(F->Y, sizeof(double) * d * r0, sizeof(double) * d * cap, st));
+    if (F->prec != NYS_F64) {
+      const int64_t ldt = (n + 7) / 8 * 8;
+      NYS_TRY(grow(F->T, sizeof(float) * ldt * r0, sizeof(float) * ldt * cap, st));
+      // Mbase is cap x cap, row-major with ld = cap: re-pitch on growth
+      nys::DevBuf nb;
+      NYS_TRY(nb.reserve(sizeof(double) * (size_t)cap * cap));
+      if (r0 > 0)
+        NYS_TRY_HIP(hipMemcpy2DAsync(nb.ptr, sizeof(double) * cap, F->Mbase.ptr,
+                                     sizeof(double) * F->cap, sizeof(double) * r0, r0,
+                                     hipMemcpyDeviceToDevice, st));
+      NYS_TRY_HIP(hipStreamSynchronize(st));
+      F->Mbase.release();
+      F->Mbase = nb;
+    }
+    F->cap = cap;
+  }
+  double* Om = F->Omega.as<double>() + d * r0;
+  NYS_TRY_HIP(hipMemcpyAsync(Om, omega, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
+  CoreWs w;
+  NYS_TRY(core_workspace(ctx, d, std::max(r1, m), &w));
+  NYS_TRY(orthonormalize(ctx, Om, d, m, w));
+  double* Y = F->Y.as<double>();
+  const bool a32 = (A.dtype == NYS_F32);
+  if (F->prec == NYS_F64) {
+    // T = A Omega (n x m, column-major) in FP64 tiles, Y = A^T (D o T) + c Omega
+    NYS_TRY(ctx->gemm_ws.reserve(sizeof(double) * n * m + 256));
+    double* T = ctx->gemm_ws.as<double>();
+    NYS_TRY(gemm64(st, (int)n, m, (int)d, A.data, a32, A.ld, 1, Om, false, 1, d, T, 1, n, 1.0, 0.0,
+                   w.split, w.split_elems));
+    NYS_TRY_HIP(hipMemcpyAsync(Y + d * r0, Om, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
+    NYS_TRY(gemm64(st, (int)d, m, (int)n, A.data, a32, 1, A.ld, T, false, 1, n, Y + d * r0, 1, d,
+                   1.0, c, w.split, w.split_elems, D));
+  } else {
+    if (!a32) return NYS_ERR_INVALID;
+    const bool bf = (F->prec == NYS_BF16);
+    const int ldo = (int)((d + 31) / 32 * 32);
+    const int NB = m <= 64 ? 4 : (m <= 128 ? 8 : 16);
+    const int NP = 16 * NB;
+    const int npass = (m + NP - 1) / NP;
+    const int nrows_pad = npass * NP;
+    const int64_t ldt = (n + 7) / 8 * 8;
+    const int ldy = (int)((d + 3) / 4 * 4);
+    // split-K over rows of A: about 4 workgroups per CU
+    const int jt = (int)((d + 127) / 128);
+    int S = std::max(1, std::min<int>((int)((n + 255) / 256), (4 * ctx->num_cu) / jt));
+    int64_t slice = (n + S - 1) / S;
+    slice = (slice + kBK - 1) / kBK * kBK;
+    S = (int)((n + slice - 1) / slice);
+    const size_t olp_b = align_up((size_t)nrows_pad * ldo * (bf ? 2 : 4));
+    const size_t yp_b = align_up(sizeof(float) * (size_t)S * m * ldy);
+    NYS_TRY(ctx->gemm_ws.reserve(olp_b + yp_b));
+    void* Olp = ctx->gemm_ws.ptr;
+    float* Yp = reinterpret_cast<float*>(static_cast<char*>(ctx->gemm_ws.ptr) + olp_b);
+    if (bf)
+      hipLaunchKernelGGL(k_round_omega<true>, dim3(blocks((int64_t)nrows_pad * ldo)), dim3(256), 0,
+                         st, Om, (int)d, m, Olp, ldo, nrows_pad);
+    else
+      hipLaunchKernelGGL(k_round_omega<false>, dim3(blocks((int64_t)nrows_pad * ldo)), dim3(256),
+                         0, st, Om, (int)d, m, Olp, ldo, nrows_pad);
+    const int vec = (((uintptr_t)A.data % 16) == 0 && (A.ld % 4) == 0) ? 1 : 0;
+    float* T = F->T.as<float>();
+    if (bf)
+      NYS_TRY(launch_sk1<true>(NB, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+    else
+      NYS_TRY(launch_sk1<false>(NB, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+    for (int p = 0; p < npass; ++p) {
+      const int cols = std::min(NP, m - p * NP);
+      if (bf)
+        NYS_TRY(launch_sk2<true>(NB, A, vec, D, T, ldt, r0 + p * NP, cols, slice, S, Yp, ldy, st));
+      else
+        NYS_TRY(launch_sk2<false>(NB, A, vec, D, T, ldt, r0 + p * NP, cols, slice, S, Yp, ldy, st));
+      hipLaunchKernelGGL(k_sk2_reduce, dim3(blocks((int64_t)cols * d)), dim3(256), 0, st, Yp, S,
+                         cols, ldy, (int)d, F->Omega.as<double>(), c, Y, r0 + p * NP);
+    }
+    // new columns of the core matrix: Mbase[:, r0:r1] = T^T D T[:, r0:r1] + c Omega^T Omega_new
+    double* Mb = F->Mbase.as<double>();
+    const int ldm = F->cap;
+    NYS_TRY(gemm64(st, r1, m, (int)n, T, true, ldt, 1, T + ldt * r0, true, 1, ldt, Mb + r0, ldm, 1,
+                   1.0, 0.0, w.split, w.split_elems, D));
+    if (c != 0.0)
+      NYS_TRY(gemm64(st, r1, m, (int)d, F->Omega.ptr, false, d, 1, Om, false, 1, d, Mb + r0, ldm,
+                     1, c, 1.0, w.split, w.split_elems));
+    hipLaunchKernelGGL(k_mirror_cols, dim3(blocks((int64_t)r1 * m)), dim3(256), 0, st, Mb, ldm, r0,
+                       r1);
+  }
+  NYS_TRY_HIP(hipGetLastError());
+  F->r = r1;
+  return NYS_OK;
+}
+
+}  // namespace
+
+// Mbase with ld = cap is repacked to ld = r for the core.
+nys_status sketch_and_core(nys_ctx ctx, const nys_dense& A, const double* D, double c,
+                           const double* omega, int m, nys_factor F) {
+  NYS_TRY(sketch_block(ctx, A, D, c, omega, m, F));
+  if (F->prec != NYS_F64 && F->cap != F->r) {
+    // compact Mbase (cap pitch) into core order (r pitch) in gemm_ws
+    nys::DevBuf& Mb = F->Mbase;
+    nys::DevBuf tmp;
+    NYS_TRY(tmp.reserve(sizeof(double) * (size_t)F->r * F->r));
+    NYS_TRY_HIP(hipMemcpy2DAsync(tmp.ptr, sizeof(double) * F->r, Mb.ptr, sizeof(double) * F->cap,
+                                 sizeof(double) * F->r, F->r, hipMemcpyDeviceToDevice, ctx->stream));
+    nys::DevBuf saved = Mb;
+    Mb = tmp;
+    nys_status s = nys_core(ctx, F);
+    NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    Mb.release();
+    Mb = saved;
+    return s;
+  }
+  return nys_core(ctx, F);
+}
+
+}  // namespace nys
+
+using namespace nys;
 
 extern "C" {
 
-nys_status nys_sketch(nys_ctx, const nys_dense*, const double*, double, const double*, int,
-                      nys_dtype, nys_factor*) {
-  return NYS_ERR_INVALID;
+nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                      const double* omega, int r, nys_dtype prec, nys_factor* F) {
+  if (ctx == nullptr || F == nullptr || omega == nullptr) return NYS_ERR_INVALID;
+  NYS_TRY(validate_dense(A));
+  if (!(c >= 0.0) || r < 1) return NYS_ERR_INVALID;
+  if (prec != NYS_F64 && prec != NYS_F32 && prec != NYS_BF16) return NYS_ERR_INVALID;
+  if (prec != NYS_F64 && A->dtype != NYS_F32) return NYS_ERR_INVALID;
+  if (A->d > (int64_t)1 << 30 || A->n > ((int64_t)1 << 31) - 1) return NYS_ERR_INVALID;
+  const int r_old = (*F != nullptr) ? (*F)->r : 0;
+  if (r_old + r >= A->d || r_old + r > 1024) return NYS_ERR_INVALID;
+  if (*F != nullptr && ((*F)->d != A->d || (*F)->prec != prec)) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys_factor f = *F;
+  bool created = false;
+  if (f == nullptr) {
+    f = new (std::nothrow) nys_factor_s();
+    if (f == nullptr) return NYS_ERR_NOMEM;
+    f->d = A->d;
+    f->device = ctx->device;
+    f->prec = prec;
+    f->mantissa_bits = (prec == NYS_F64) ? 52 : 23;
+    created = true;
+  }
+  nys_status s = sketch_and_core(ctx, *A, D, c, omega, r, f);
+  if (s != NYS_OK) {
+    if (created) nys_factor_destroy(f);
+    return s;
+  }
+  *F = f;
+  return NYS_OK;
 }
 
-nys_status nys_sketch_adaptive(nys_ctx, const nys_dense*, const double*, double, const double*,
-                               int, int, double, double, nys_dtype, nys_factor*) {
-  return NYS_ERR_INVALID;
+nys_status nys_sketch_adaptive(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                               const double* omega, int s0, int s_max, double rho, double tol,
+                               nys_dtype prec, nys_factor* F) {
+  if (ctx == nullptr || F == nullptr || *F != nullptr || omega == nullptr) return NYS_ERR_INVALID;
+  NYS_TRY(validate_dense(A));
+  if (s0 < 1 || s_max < s0 || s_max >= A->d || s_max > 1024 || !(rho > 0.0) || !(tol >= 1.0))
+    return NYS_ERR_INVALID;
+  int s = 0, m = s0;
+  nys_factor f = nullptr;
+  for (;;) {
+    nys_status st = nys_sketch(ctx, A, D, c, omega + (int64_t)s * A->d, m, prec, &f);
+    if (st != NYS_OK) {
+      if (f) nys_factor_destroy(f);
+      return st;
+    }
+    s += m;
+    const double kappa = (f->lam_host[s - 1] + rho) / rho;
+    if (kappa <= tol || s >= s_max) break;
+    m = std::min(s, s_max - s);
+  }
+  *F = f;
+  return NYS_OK;
 }
 
 }  // extern "C"

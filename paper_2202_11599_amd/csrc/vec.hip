@@ -130,7 +130,7 @@ template <typename UT>
 __global__ __launch_bounds__(256) void k_precond_dot(
     const UT* __restrict__ U, int64_t d, int r, const double* __restrict__ w,
     double* __restrict__ cvec, PcgDev* __restrict__ st, const double* __restrict__ wwpart,
-    int nww, const double* __restrict__ rrpart, int k, int mode, double tol, int tol_abs) {
+    int nww, const double* __restrict__ rrpart, int k, int mode, double tol_rel, double tol_abs) {
   __shared__ double sh4[4];
   const int tid = threadIdx.x;
   if (mode == 0 || mode == 1) {
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_precond_dot(
     bool zero_rhs = false;
     if (mode == 1) {
       const double rr = block_sum_array(rrpart, nww, sh4);
-      thr2 = tol_abs ? tol * tol : tol * tol * rr;
+      thr2 = fmax(tol_abs * tol_abs, tol_rel * tol_rel * rr);
       zero_rhs = (rr == 0.0);
       if (blockIdx.x == 0 && tid == 0) {
         st->rr = rr;
@@ -264,17 +264,17 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
 
 nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const double* w,
                               double* cvec, PcgDev* st, const double* wwpart, int nww,
-                              const double* rrpart, int k, int mode, double tol, int tol_abs,
-                              hipStream_t stream) {
+                              const double* rrpart, int k, int mode, double tol_rel,
+                              double tol_abs, hipStream_t stream) {
   const int grid = r > 0 ? (r + 3) / 4 : 1;
   if (u32)
     hipLaunchKernelGGL(k_precond_dot<float>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const float*>(U), d, r, w, cvec, st, wwpart, nww, rrpart, k,
-                       mode, tol, tol_abs);
+                       mode, tol_rel, tol_abs);
   else
     hipLaunchKernelGGL(k_precond_dot<double>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const double*>(U), d, r, w, cvec, st, wwpart, nww, rrpart, k,
-                       mode, tol, tol_abs);
+                       mode, tol_rel, tol_abs);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 

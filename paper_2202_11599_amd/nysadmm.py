@@ -28,7 +28,7 @@ NYS_LOSS_LS, NYS_LOSS_LOGISTIC = 0, 1
 
 EXPORTS = [
     "nys_status_string", "nys_ctx_create", "nys_ctx_destroy", "nys_ctx_set_stream",
-    "nys_ctx_workspace_bytes", "nys_sketch", "nys_sketch_adaptive", "nys_factor_import",
+    "nys_ctx_workspace_bytes", "nys_ctx_profile_start", "nys_ctx_profile_stop", "nys_sketch", "nys_sketch_adaptive", "nys_factor_import",
     "nys_factor_info", "nys_factor_get_U", "nys_factor_destroy", "nys_hessian_apply",
     "nys_precond_apply", "pcg_solve", "admm_step", "admm_solve",
 ]
@@ -95,6 +95,8 @@ def lib():
         "nys_ctx_destroy": (i32, [vp]),
         "nys_ctx_set_stream": (i32, [vp, vp]),
         "nys_ctx_workspace_bytes": (C.c_size_t, [vp]),
+        "nys_ctx_profile_start": (i32, [vp]),
+        "nys_ctx_profile_stop": (i32, [vp, P(C.c_long), P(dbl)]),
         "nys_sketch": (i32, [vp, P(Dense), vp, dbl, vp, i32, i32, P(vp)]),
         "nys_sketch_adaptive": (i32, [vp, P(Dense), vp, dbl, vp, i32, i32, dbl, dbl, i32, P(vp)]),
         "nys_factor_import": (i32, [vp, i64, i32, vp, P(dbl), dbl, P(vp)]),
@@ -164,6 +166,16 @@ class Context:
     def set_stream(self, stream: torch.cuda.Stream):
         self._stream = stream
         _check(lib().nys_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)), "nys_ctx_set_stream")
+
+    def profile_start(self):
+        """Time every matvec-pair launch with HIP events from now on."""
+        _check(lib().nys_ctx_profile_start(self.h), "nys_ctx_profile_start")
+
+    def profile_stop(self):
+        """(launches, total_ms) of the matvec-pair kernel since profile_start."""
+        n, ms = C.c_long(), C.c_double()
+        _check(lib().nys_ctx_profile_stop(self.h, C.byref(n), C.byref(ms)), "nys_ctx_profile_stop")
+        return n.value, ms.value
 
     def workspace_bytes(self) -> int:
         return int(lib().nys_ctx_workspace_bytes(self.h))

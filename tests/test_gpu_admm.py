@@ -1,0 +1,204 @@
+"""GPU parity of admm_step / admm_solve (Algorithm NysADMM; linearised form
+for l1 logistic regression) against the FP64 oracle, through the C ABI.
+
+Parity contract:
+  * 2000 x 500 lasso (FP64, rank 50, rho 1, PCG tol 1e-8): exactly 300
+    iterations, iterates compared with the oracle's after the same 300.
+  * optimum parity on problems ADMM converges on: |f(z) - f*|/|f*| <= 1e-6 and
+    ||z - x*||/||x*|| <= 1e-5, f and x* evaluated by the oracle in FP64 (x* from
+    exact-solve ADMM run to eta <= 1e-12).
+  * eta reported by the library equals the oracle's eta of the same z.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import admm as ad
+from paper_2202_11599_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2202_11599_amd import nysadmm
+    return nysadmm
+
+
+@pytest.fixture(scope="module")
+def ctx(N):
+    c = N.Context()
+    yield c
+    c.close()
+
+
+def run_solve(N, ctx, p, A_dev, b_dev, rank, **kw):
+    d = p.d
+    st = N.State(d, DEV)
+    pcg = N.pcg_opts(tol=kw.pop("pcg_tol", p.pcg_tol), max_iter=kw.pop("pcg_max_iter", 1000))
+    o = N.admm_opts(kw.pop("rho", p.rho), rank, p.omega.to(DEV), pcg=pcg, **kw)
+    loss = N.NYS_LOSS_LOGISTIC if p.kind == "logistic" else N.NYS_LOSS_LS
+    prob = N.problem(A_dev, b_dev, p.gamma, loss=loss, c=p.c)
+    info = N.admm_solve(ctx, [prob], [o], [st])[0]
+    return st, info
+
+
+def test_lasso_c1_300_iterations_iterate_parity(N, ctx):
+    p = synth.lasso_c1()
+    A = p.A.numpy()
+    b = p.b.numpy()
+    print("[admm c1] 300 iterations fp64", flush=True)
+    st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 50, max_iter=300)
+    ora = ad.admm_lasso(A, b, p.gamma, 1.0, omega_raw=p.omega.numpy().T, iters=300, pcg_tol=1e-8)
+    z = st.z.cpu().numpy()
+    x = st.x.cpu().numpy()
+    ez = np.linalg.norm(z - ora.z) / np.linalg.norm(ora.z)
+    ex = np.linalg.norm(x - ora.x) / np.linalg.norm(ora.x)
+    print(f"[admm c1] iters={info.iters} pcg={info.pcg_iters} vs oracle {sum(ora.pcg_iters)} "
+          f"rel z diff {ez:.2e} x diff {ex:.2e} eta {info.eta:.3e}", flush=True)
+    assert info.iters == 300
+    assert ez < 1e-6 and ex < 1e-6
+    assert abs(info.pcg_iters - sum(ora.pcg_iters)) <= 0.05 * sum(ora.pcg_iters)
+    assert abs(info.eta - ad.kkt_eta_lasso(A, b, p.gamma, z)) <= 1e-9 * ad.kkt_eta_lasso(A, b, p.gamma, z)
+    assert abs(info.obj - ad.lasso_objective(A, b, p.gamma, z)) <= 1e-10 * ad.lasso_objective(A, b, p.gamma, z)
+
+
+def test_lasso_c1_fp32_storage(N, ctx):
+    # the same workload with A stored in FP32 and an FP32 sketch: iterate parity
+    # against the oracle run on the upcast FP32 matrix with the FP32 shift rule
+    p = synth.lasso_c1(dtype=torch.float32)
+    A = p.A.double().numpy()
+    b = p.b.numpy()
+    st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 50, max_iter=100,
+                         sketch_prec=N.NYS_F32)
+    ora = ad.admm_lasso(A, b, p.gamma, 1.0, omega_raw=p.omega.numpy().T, iters=100, pcg_tol=1e-8,
+                        mantissa_bits=23)
+    ez = np.linalg.norm(st.z.cpu().numpy() - ora.z) / np.linalg.norm(ora.z)
+    print(f"[admm c1 fp32] rel z diff {ez:.2e}", flush=True)
+    assert ez < 1e-6
+
+
+def small_lasso(seed=3, n=3000, d=300, alpha=0.5, rho=0.3):
+    p = synth.lasso_decay(n, d, alpha, seed=seed, dtype=torch.float64, frac=0.05, rho=rho,
+                          rank=40, s_max=40, pcg_tol=1e-10)
+    return p
+
+
+def test_lasso_optimum_parity(N, ctx):
+    p = small_lasso()
+    A, b = p.A.numpy(), p.b.numpy()
+    ex = ad.admm_lasso(A, b, p.gamma, p.rho, exact=True, iters=200000, eps_abs=1e-15, eps_rel=1e-15)
+    assert ad.kkt_eta_lasso(A, b, p.gamma, ex.z) < 1e-12
+    st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 40, max_iter=20000,
+                         kkt_tol=1e-11, kkt_every=25)
+    z = st.z.cpu().numpy()
+    fs = ad.lasso_objective(A, b, p.gamma, ex.z)
+    f = ad.lasso_objective(A, b, p.gamma, z)
+    print(f"[admm opt] iters={info.iters} eta={info.eta:.2e} rel obj {abs(f - fs) / fs:.2e} "
+          f"rel z {np.linalg.norm(z - ex.z) / np.linalg.norm(ex.z):.2e}", flush=True)
+    assert info.converged == 1
+    assert abs(f - fs) / abs(fs) <= 1e-6
+    assert np.linalg.norm(z - ex.z) <= 1e-5 * np.linalg.norm(ex.z)
+    # eta ~ 1e-11 here: its numerator is a difference of O(1) quantities, so
+    # the two FP64 evaluations agree to ~1e-16 absolute, not relative
+    assert abs(info.eta - ad.kkt_eta_lasso(A, b, p.gamma, z)) <= 1e-4 * info.eta + 1e-15
+
+
+def test_admm_step_matches_oracle_steps(N, ctx):
+    p = small_lasso(seed=5)
+    A, b = p.A.numpy(), p.b.numpy()
+    ora = ad.admm_lasso(A, b, p.gamma, p.rho, omega_raw=p.omega.numpy().T, iters=5, pcg_tol=1e-10)
+    st = N.State(p.d, DEV)
+    o = N.admm_opts(p.rho, 40, p.omega.to(DEV), pcg=N.pcg_opts(tol=1e-10))
+    prob = N.problem(p.A.to(DEV), p.b.to(DEV), p.gamma)
+    F = None
+    rps = []
+    for k in range(5):
+        F, info = N.admm_step(ctx, prob, o, F, st)
+        rps.append(info.r_p)
+    assert st.k == 5
+    z = st.z.cpu().numpy()
+    assert np.linalg.norm(z - ora.z) <= 1e-8 * np.linalg.norm(ora.z)
+    assert np.allclose(rps, ora.r_p, rtol=1e-6)
+    F.close()
+
+
+def test_elastic_net_and_residual_stop(N, ctx):
+    p = small_lasso(seed=7)
+    p.c = 0.2
+    A, b = p.A.numpy(), p.b.numpy()
+    st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 40, max_iter=5000,
+                         eps_abs=1e-12, eps_rel=1e-10)
+    ora = ad.admm_lasso(A, b, p.gamma, p.rho, omega_raw=p.omega.numpy().T, c=0.2, iters=5000,
+                        pcg_tol=1e-10, eps_abs=1e-12, eps_rel=1e-10)
+    z = st.z.cpu().numpy()
+    print(f"[enet] gpu iters {info.iters} oracle {ora.iters}", flush=True)
+    assert info.converged == 1
+    assert abs(info.iters - ora.iters) <= 2
+    assert np.linalg.norm(z - ora.z) <= 1e-7 * np.linalg.norm(ora.z)
+
+
+def test_tolerance_schedule(N, ctx):
+    p = small_lasso(seed=9)
+    A, b = p.A.numpy(), p.b.numpy()
+    st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 40, max_iter=60, tol_schedule=True,
+                         pcg_tol=1e-10)
+    ora = ad.admm_lasso(A, b, p.gamma, p.rho, omega_raw=p.omega.numpy().T, iters=60,
+                        pcg_tol=1e-10, tol_schedule=True)
+    z = st.z.cpu().numpy()
+    print(f"[schedule] gpu pcg {info.pcg_iters} oracle {sum(ora.pcg_iters)}", flush=True)
+    assert np.linalg.norm(z - ora.z) <= 1e-5 * np.linalg.norm(ora.z)
+    assert abs(info.pcg_iters - sum(ora.pcg_iters)) <= 0.1 * sum(ora.pcg_iters) + 3
+
+
+def test_logistic_parity(N, ctx):
+    p = synth.logistic_decay(6000, 200, seed=4, dtype=torch.float64, rho=5.0, rank=30,
+                             gamma_per_row=2e-3, pcg_tol=1e-10)
+    A, b = p.A.numpy(), p.b.numpy()
+    its = 60
+    ora = ad.admm_logistic(A, b, p.gamma, p.rho, omega_raw=p.omega.numpy().T, iters=its,
+                           pcg_tol=1e-10, resketch_every=10)
+    st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 30, max_iter=its, resketch_every=10)
+    z = st.z.cpu().numpy()
+    ez = np.linalg.norm(z - ora.z) / np.linalg.norm(ora.z)
+    eta_o = ad.kkt_eta_logistic(A, b, p.gamma, z)
+    print(f"[logistic] rel z diff {ez:.2e} eta {info.eta:.3e}/{eta_o:.3e} nnz {(z != 0).sum()}",
+          flush=True)
+    assert ez < 1e-7
+    assert abs(info.eta - eta_o) <= 1e-8 * eta_o
+    assert abs(info.obj - ad.logistic_objective(A, b, p.gamma, z)) <= 1e-10 * abs(info.obj)
+
+
+def test_logistic_optimum_and_rel_change_stop(N, ctx):
+    p = synth.logistic_decay(4000, 100, seed=6, dtype=torch.float64, rho=2.0, rank=20,
+                             gamma_per_row=3e-3, pcg_tol=1e-10)
+    A, b = p.A.numpy(), p.b.numpy()
+    ex = ad.admm_logistic(A, b, p.gamma, p.rho, iters=3000, exact=True)
+    st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 20, max_iter=3000,
+                         resketch_every=10, kkt_tol=1e-11, kkt_every=20)
+    z = st.z.cpu().numpy()
+    fs = ad.logistic_objective(A, b, p.gamma, ex.z)
+    f = ad.logistic_objective(A, b, p.gamma, z)
+    print(f"[logistic opt] iters {info.iters} eta {info.eta:.2e} rel obj {abs(f - fs) / abs(fs):.2e}",
+          flush=True)
+    assert abs(f - fs) <= 1e-6 * abs(fs)
+    assert np.linalg.norm(z - ex.z) <= 1e-5 * np.linalg.norm(ex.z)
+    # the relative-change stop of the logistic experiments fires and agrees with the oracle
+    st2, info2 = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 20, max_iter=3000,
+                           resketch_every=10, rel_change_tol=1e-3)
+    ora = ad.admm_logistic(A, b, p.gamma, p.rho, omega_raw=p.omega.numpy().T, iters=3000,
+                           pcg_tol=1e-10, resketch_every=10, rel_change_tol=1e-3)
+    assert info2.converged == 1 and abs(info2.iters - ora.iters) <= 1
+
+
+def test_admm_invalid_arguments(N, ctx):
+    p = small_lasso(seed=11)
+    st = N.State(p.d, DEV)
+    o = N.admm_opts(-1.0, 40, p.omega.to(DEV))
+    prob = N.problem(p.A.to(DEV), p.b.to(DEV), p.gamma)
+    with pytest.raises(N.NysError):
+        N.admm_solve(ctx, [prob], [o], [st])
+    o = N.admm_opts(0.3, 400, p.omega.to(DEV))   # rank >= d
+    with pytest.raises(N.NysError):
+        N.admm_solve(ctx, [prob], [o], [st])

@@ -1,0 +1,207 @@
+"""GPU parity of the randomized Nystrom sketch and its FP64 core against the
+oracle (Algorithm RandNysAppx / AdaptiveRandNysAppx), through the C ABI.
+
+U is not unique (signs, rotations inside clusters), so the comparisons use
+H_hat = U Lambda U^T, Lambda and the shift nu.  Bars:
+  FP64 sketch  ||H_hat - H_hat_oracle|| <= 1e-10 ||H_hat_oracle||
+  FP32 sketch  <= 1e-5 (FP32 MFMA, FP64 core)
+  BF16 sketch  error reported against the FP64 oracle, sanity bound only.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nystrom as ny
+from oracle import pcg as pc
+from paper_2202_11599_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2202_11599_amd import nysadmm
+    return nysadmm
+
+
+@pytest.fixture(scope="module")
+def ctx(N):
+    c = N.Context()
+    yield c
+    c.close()
+
+
+def hhat(F, ctx):
+    inf = F.info()
+    U = F.U(ctx).cpu().numpy().T          # d x r
+    lam = np.array(inf["lam"])
+    return (U * lam) @ U.T, U, lam, inf
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_sketch_fp64_c1_parity(N, ctx):
+    p = synth.lasso_c1()
+    A = p.A.numpy()
+    om = p.omega                                  # (50, 500) rows = columns
+    F = N.nys_sketch(ctx, p.A.to(DEV), om.to(DEV), prec=N.NYS_F64)
+    H, U, lam, inf = hhat(F, ctx)
+    f = ny.rand_nys_appx(A, None, 0.0, om.numpy().T)
+    print(f"[sketch fp64 c1] rel(Hhat)={rel(H, f.dense()):.3e} nu={inf['nu']:.3e}/{f.nu:.3e}", flush=True)
+    assert rel(H, f.dense()) < 1e-10
+    assert np.allclose(lam, f.lam, rtol=1e-10, atol=1e-12 * f.lam[0])
+    assert inf["nu"] == f.nu
+    assert np.linalg.norm(U.T @ U - np.eye(50)) < 1e-10
+    assert inf["rank"] == 50 and inf["lambda_s"] == lam[-1]
+    F.close()
+
+
+def test_sketch_fp64_weights_and_shift(N, ctx):
+    # H = A^T diag(D) A + c I (logistic weights, elastic-net shift)
+    A64 = synth.decay_matrix(3000, 300, 0.5, seed=21)
+    D = torch.rand(3000, dtype=torch.float64, generator=torch.Generator().manual_seed(4)) * 0.25
+    om = synth.omega_raw(300, 40, seed=21)
+    F = N.nys_sketch(ctx, A64.to(DEV), om.to(DEV), D=D.to(DEV), c=0.3, prec=N.NYS_F64)
+    H, U, lam, inf = hhat(F, ctx)
+    f = ny.rand_nys_appx(A64.numpy(), D.numpy(), 0.3, om.numpy().T)
+    assert rel(H, f.dense()) < 1e-10
+    assert inf["nu"] == f.nu
+    F.close()
+
+
+def test_sketch_fp64_rank_deficient_exact(N, ctx):
+    # rank(H) = 7 <= r = 12: the approximation is exact (Lemma NysPropLemma)
+    g = torch.Generator().manual_seed(5)
+    A64 = torch.randn(200, 7, generator=g, dtype=torch.float64) @ torch.randn(7, 60, generator=g, dtype=torch.float64)
+    om = synth.omega_raw(60, 12, seed=5)
+    F = N.nys_sketch(ctx, A64.to(DEV), om.to(DEV), prec=N.NYS_F64)
+    H, U, lam, inf = hhat(F, ctx)
+    Ht = A64.numpy().T @ A64.numpy()
+    assert rel(H, Ht) < 1e-10
+    assert np.all(lam[7:] <= 1e-10 * lam[0])
+    F.close()
+
+
+@pytest.mark.parametrize("n,d,r", [(20000, 1000, 100), (5003, 517, 37), (30000, 2000, 200)])
+def test_sketch_fp32_parity(N, ctx, n, d, r):
+    print(f"[sketch fp32] n={n} d={d} r={r}", flush=True)
+    A64 = synth.decay_matrix(n, d, 0.8, seed=n % 97)
+    A32 = A64.to(torch.float32)
+    om = synth.omega_raw(d, r, seed=3)
+    F = N.nys_sketch(ctx, A32.to(DEV), om.to(DEV), prec=N.NYS_F32)
+    H, U, lam, inf = hhat(F, ctx)
+    f = ny.rand_nys_appx(A32.double().numpy(), None, 0.0, om.numpy().T, mantissa_bits=23)
+    e = rel(H, f.dense())
+    print(f"[sketch fp32] rel(Hhat)={e:.3e} nu={inf['nu']:.3e}/{f.nu:.3e}", flush=True)
+    assert e < 1e-5
+    assert inf["nu"] == f.nu
+    assert np.linalg.norm(U.T @ U - np.eye(r)) < 1e-8
+    F.close()
+
+
+def test_sketch_bf16_reported(N, ctx):
+    n, d, r = 20000, 1000, 100
+    A32 = synth.decay_matrix(n, d, 0.8, seed=9).to(torch.float32)
+    om = synth.omega_raw(d, r, seed=9)
+    F = N.nys_sketch(ctx, A32.to(DEV), om.to(DEV), prec=N.NYS_BF16)
+    H, U, lam, inf = hhat(F, ctx)
+    f = ny.rand_nys_appx(A32.double().numpy(), None, 0.0, om.numpy().T, mantissa_bits=23)
+    e = rel(H, f.dense())
+    el = float(np.max(np.abs(lam[:10] - f.lam[:10]) / f.lam[:10]))
+    print(f"[sketch bf16] FP64-oracle error: rel(Hhat)={e:.3e}, top-10 eigenvalue rel err={el:.3e}", flush=True)
+    assert e < 3e-2
+    assert np.all(np.diff(lam) <= 0) and np.all(lam >= 0)
+    F.close()
+
+
+def test_sketch_append_and_adaptive(N, ctx):
+    # Algorithm AdaptiveRandNysAppx: blocks of consecutive omega columns, rank
+    # 5, 10, 20, 40 ... until (lambda_s + rho)/rho <= Tol.
+    d = 240
+    A64 = synth.decay_matrix(2000, d, 1.0, seed=31)
+    om = synth.omega_raw(d, 160, seed=31)
+    rho, tol = 1e-3, 2.0
+    F = N.nys_sketch_adaptive(ctx, A64.to(DEV), om.to(DEV), 5, 160, rho, tol, prec=N.NYS_F64)
+    H, U, lam, inf = hhat(F, ctx)
+    f, hist = ny.adaptive_rand_nys_appx(A64.numpy(), None, 0.0, om.numpy().T, rho, 5, 160, tol)
+    print(f"[adaptive] gpu rank {inf['rank']} oracle ranks {hist}", flush=True)
+    assert inf["rank"] == hist[-1][0]
+    assert rel(H, f.dense()) < 1e-9
+    # explicit append equals the adaptive blocks
+    F2 = N.nys_sketch(ctx, A64.to(DEV), om[:5].contiguous().to(DEV), prec=N.NYS_F64)
+    F2 = N.nys_sketch(ctx, A64.to(DEV), om[5:10].contiguous().to(DEV), prec=N.NYS_F64, factor=F2)
+    H2, _, _, inf2 = hhat(F2, ctx)
+    Href = ny.nystrom_definition(A64.numpy().T @ A64.numpy(),
+                                 np.concatenate([ny.orthonormalize(om[:5].numpy().T),
+                                                 ny.orthonormalize(om[5:10].numpy().T)], axis=1))
+    assert inf2["rank"] == 10
+    assert rel(H2, Href) < 1e-8
+    F.close()
+    F2.close()
+
+
+def test_pcg_with_gpu_factor_matches_oracle_iterations(N, ctx):
+    p = synth.lasso_c1()
+    A = p.A.numpy()
+    F = N.nys_sketch(ctx, p.A.to(DEV), p.omega.to(DEV), prec=N.NYS_F64)
+    f = ny.rand_nys_appx(A, None, 0.0, p.omega.numpy().T)
+    rhs = A.T @ p.b.numpy()
+    ora = pc.nys_pcg(pc.subproblem_matvec(A, None, 0.0, 1.0), rhs, np.zeros(500),
+                     pc.nystrom_precond(f, 1.0), 1e-10)
+    x = torch.zeros(500, dtype=torch.float64, device=DEV)
+    info = N.pcg_solve(ctx, p.A.to(DEV), torch.from_numpy(rhs).to(DEV), x, 1.0, F,
+                       opts=N.pcg_opts(tol=1e-10))
+    assert abs(info.iters - ora.iters) <= 1
+    xs = pc.dense_solve(A, None, 0.0, 1.0, rhs)
+    assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-6 * np.linalg.norm(xs)
+    F.close()
+
+
+def test_sketch_invalid_and_not_spd(N, ctx):
+    A = synth.decay_matrix(100, 20, 0.5, seed=1).to(DEV)
+    with pytest.raises(N.NysError) as e:
+        N.nys_sketch(ctx, A, synth.omega_raw(20, 20, seed=1).to(DEV))     # r >= d
+    assert e.value.status == N.NYS_ERR_INVALID
+    om = synth.omega_raw(20, 5, seed=1)
+    om[2] = 0.0                                                           # zero Gaussian column
+    with pytest.raises(N.NysError) as e:
+        N.nys_sketch(ctx, A, om.to(DEV))
+    assert e.value.status == N.NYS_ERR_NOT_SPD
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_sketch_full_size_properties(N, ctx, prec):
+    # 100000 x 4000 FP32 with sigma_j = j^-0.8 at rank 200 in the launch
+    # configuration of the bench: properties that hold at any size --
+    # Lambda descending and >= 0, U orthonormal, x^T H_hat x <= x^T H x
+    # (Lemma NysPropLemma, up to the sketch rounding), and the leading Ritz
+    # values close to sigma_j^2.
+    n, d, r = 100000, 4000, 200
+    print(f"[sketch full] {prec} n={n} d={d} r={r}", flush=True)
+    A = synth.decay_matrix(n, d, 0.8, seed=0, device=DEV).to(torch.float32)
+    om = synth.omega_raw(d, r, seed=0, device=DEV)
+    F = N.nys_sketch(ctx, A, om, prec=N.NYS_F32 if prec == "f32" else N.NYS_BF16)
+    inf = F.info()
+    lam = np.array(inf["lam"])
+    U = F.U(ctx)
+    assert np.all(np.diff(lam) <= 0) and lam[-1] >= 0
+    orth = torch.linalg.norm(U @ U.T - torch.eye(r, dtype=torch.float64, device=DEV)).item()
+    assert orth < 1e-6
+    g = torch.Generator(device=DEV).manual_seed(2)
+    tol = 1e-5 if prec == "f32" else 2e-2
+    for _ in range(4):
+        x = torch.randn(d, generator=g, device=DEV, dtype=torch.float64)
+        xHx = N.nys_hessian_apply(ctx, A, x, want_pv=True)[1]
+        c = U @ x
+        xHhx = float((c * c * torch.tensor(lam, device=DEV)).sum())
+        assert xHhx <= xHx * (1 + tol)
+    # interlacing lambda_j(H_hat) <= lambda_j(H) = j^-1.6, and a rank-200
+    # sketch of this spectrum captures the leading eigenvalues to ~1e-3
+    sig2 = np.arange(1, 6) ** -1.6
+    print(f"[sketch full] {prec} top eigs {lam[:5]} vs {sig2}", flush=True)
+    assert np.all(lam[:5] <= sig2 * (1 + tol))
+    assert np.all(lam[:5] >= sig2 * (1 - 1e-2))
+    F.close()
