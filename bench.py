@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Throughput of the NysADMM hot path on one MI355X.
+
+Workload: lasso, A 100000 x 4000 FP32 with singular values j^-0.8 (random
+orthogonal factors), x* 2% sparse, b = A x* + 0.01 noise,
+gamma = 0.1 ||A^T b||_inf, rho = 1e-4, adaptive Nystrom rank 50 -> 800 with
+Tol = 2, subproblem tolerance 1e-6 (relative residual, FP64-accumulated true
+residual checked), PCG warm-started at the previous x.
+
+One step = one pass of the whole hot path: the adaptive sketch and its FP64
+core (Algorithm AdaptiveRandNysAppx) followed by --admm-iters iterations of
+Algorithm NysADMM (right-hand side, Nystrom PCG subproblem solve, soft
+threshold, dual update).  value = subproblem solves per second over the timed
+steps, the sketch cost included (amortised over the step's solves).
+
+Also reported: the same steps with the BF16-MFMA sketch ("mixed"), the
+matvec-pair kernel's achieved HBM bandwidth measured with HIP events around
+every launch in the timed region, and the FP64 CPU oracle timed on a bounded
+sample on this host (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "ADMM subproblem solves/s at 1e-6 rel. residual; GEMV HBM GB/s; vs plain FP32"
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--admm-iters", type=int, default=30)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--d", type=int, default=4000)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="also run one 1.6 GB device copy (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def traffic_record(n, d):
+    """HBM bytes per matvec-pair launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "gram_traffic.json")
+    src = os.path.join(ROOT, "paper_2202_11599_amd", "csrc", "gemv.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if rec.get("gemv_sha256") != sha or rec.get("n") != n or rec.get("d") != d:
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, profile=False):
+    import torch
+    infos = []
+    ranks = []
+    sketch_s = 0.0
+    bad = 0
+    if profile:
+        ctx.profile_start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        F = N.nys_sketch_adaptive(ctx, A, omega, 50, 800, p.rho, 2.0, prec=prec)
+        torch.cuda.synchronize()
+        sketch_s += time.perf_counter() - ts
+        ranks.append(F.info()["rank"])
+        opts = N.admm_opts(p.rho, ranks[-1], omega, sketch_prec=prec,
+                           pcg=N.pcg_opts(tol=p.pcg_tol, max_iter=1000))
+        st = N.State(p.d, "cuda")
+        for _k in range(admm_iters):
+            F, info = N.admm_step(ctx, prob, opts, F, st)
+            infos.append((info.pcg_iters, info.status))
+            bad += info.status != N.NYS_OK
+        F.close()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ctx.profile_stop() if profile else None
+    its = [i for i, _ in infos]
+    return dict(wall=wall, sketch_s=sketch_s, ranks=ranks, pcg_mean=sum(its) / len(its),
+                pcg_max=max(its), solves=len(infos), unconverged=bad, prof=prof)
+
+
+def cpu_baseline(A, b, omega, p, admm_iters, cpu_iters):
+    """The FP64 oracle as it stands, on this host: its adaptive sketch once and
+    `cpu_iters` NysADMM iterations; scaled to the step definition."""
+    import numpy as np
+    from oracle import nystrom as ny
+    from oracle import admm as ad
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    A64 = A.double().cpu().numpy()
+    b64 = b.cpu().numpy()
+    om = omega.cpu().numpy().T
+    t0 = time.perf_counter()
+    f, hist = ny.adaptive_rand_nys_appx(A64, None, 0.0, om, p.rho, 50, 800, 2.0)
+    t_sketch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = ad.admm_lasso(A64, b64, p.gamma, p.rho, factor=f, iters=cpu_iters, pcg_tol=p.pcg_tol)
+    t_iter = (time.perf_counter() - t0) / cpu_iters
+    step = t_sketch + admm_iters * t_iter
+    return {
+        "value": admm_iters / step, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle on this host: adaptive sketch (rank {f.rank}, "
+                   f"{t_sketch:.1f} s) and {cpu_iters} NysADMM iterations "
+                   f"({t_iter:.2f} s each, {np.mean(r.pcg_iters):.1f} PCG iterations) on the same "
+                   f"A upcast to FP64; value = {admm_iters} solves / (sketch + {admm_iters} x "
+                   f"mean iteration), the GPU step definition"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    sys.path.insert(0, ROOT)
+    import torch
+    from paper_2202_11599_amd import nysadmm as N
+    from paper_2202_11599_amd import synth
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    p = synth.lasso_decay(args.n, args.d, 0.8, seed=0, device="cuda", dtype=torch.float32,
+                          frac=0.02, noise=0.01, gamma_frac=0.1, rho=1e-4, rank=50, s_max=800,
+                          pcg_tol=1e-6)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] generated {args.n}x{args.d} in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    A, b, omega = p.A, p.b.contiguous(), p.omega.contiguous()
+    ctx = N.Context()
+    prob = N.problem(A, b, p.gamma)
+    if args.copy_reference:
+        xs = torch.empty(400_000_000, dtype=torch.float32, device="cuda")
+        ys = torch.empty_like(xs)
+        ys.copy_(xs)
+        torch.cuda.synchronize()
+        del xs, ys
+
+    run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.warmup, args.admm_iters)
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    plain = run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.steps, args.admm_iters,
+                      profile=True)
+    print(f"[bench] plain fp32: {plain['solves'] / plain['wall']:.1f} solves/s", file=sys.stderr,
+          flush=True)
+    mixed = None
+    if not args.no_mixed:
+        run_steps(N, ctx, A, prob, omega, p, N.NYS_BF16, 1, args.admm_iters)
+        mixed = run_steps(N, ctx, A, prob, omega, p, N.NYS_BF16, args.steps, args.admm_iters)
+        print(f"[bench] mixed bf16: {mixed['solves'] / mixed['wall']:.1f} solves/s",
+              file=sys.stderr, flush=True)
+
+    launches, kms = plain["prof"]
+    avg_s = kms / 1e3 / max(launches, 1)
+    alg_bytes = float(args.n) * args.d * 4
+    achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic = traffic_record(args.n, args.d)
+    value = plain["solves"] / plain["wall"]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * plain["wall"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"lasso-{args.n}x{args.d}-fp32-sigma_j=j^-0.8-adaptive-rank-50..800",
+            "n": args.n, "d": args.d, "rho": p.rho, "gamma": p.gamma, "pcg_tol": p.pcg_tol,
+            "admm_iters_per_step": args.admm_iters, "ada_tol": 2.0,
+            "rank_final": plain["ranks"][-1],
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_gram (fused A^T D A p, FP32 A, FP64 products and sums)",
+            "alg_bytes_per_launch": alg_bytes, "launches": launches,
+            "avg_launch_us": round(avg_s * 1e6, 2),
+        },
+        "plain_fp32": {
+            "solves_per_s": round(value, 3),
+            "solves_per_s_excl_sketch": round(plain["solves"] / (plain["wall"] - plain["sketch_s"]), 3),
+            "sketch_ms": round(1e3 * plain["sketch_s"] / args.steps, 2),
+            "pcg_iters_mean": round(plain["pcg_mean"], 3), "pcg_iters_max": plain["pcg_max"],
+            "unconverged_solves": plain["unconverged"],
+        },
+        "gemv_hbm_gbs": round(achieved, 1),
+    }
+    if mixed is not None:
+        out["mixed_bf16_sketch"] = {
+            "solves_per_s": round(mixed["solves"] / mixed["wall"], 3),
+            "solves_per_s_excl_sketch": round(mixed["solves"] / (mixed["wall"] - mixed["sketch_s"]), 3),
+            "sketch_ms": round(1e3 * mixed["sketch_s"] / args.steps, 2),
+            "pcg_iters_mean": round(mixed["pcg_mean"], 3), "rank_final": mixed["ranks"][-1],
+            "unconverged_solves": mixed["unconverged"],
+            "vs_plain_fp32": round((mixed["solves"] / mixed["wall"]) / value, 4),
+        }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(A, b, omega, p, args.admm_iters, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -213,6 +213,9 @@ typedef struct {
   double rel_change_tol; /* ||z_k - z_{k+1}||_inf / ||z_k||_inf < tol stop; <= 0 disables */
   double kkt_tol;        /* stop when the relative KKT residual (eq. 31) <= kkt_tol; <= 0 disables */
   int kkt_every;         /* KKT check cadence (one extra matvec pair each); 0 means 10 */
+  nys_factor factor;     /* optional prebuilt factor of A^T A + c I for this problem (lasso):
+                            used instead of sketching and not destroyed (regularisation paths
+                            reuse it across gamma); NULL: admm_solve builds and frees one */
 } nys_admm_opts;
 
 /* Caller-owned device FP64 d-vectors; x = z = u = 0 for a cold start.  k counts
@@ -245,9 +248,14 @@ typedef struct {
 nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, nys_factor* F,
                      nys_admm_state* S, nys_admm_info* I);
 
-/* Algorithm NysADMM / AdaNysADMM: build the factor (fixed or adaptive rank),
- * then iterate admm_step until max_iter or a stopping rule.  count problems
- * are solved one after another (arrays of length count). */
+/* Algorithm NysADMM / AdaNysADMM: build the factor (fixed or adaptive rank,
+ * or take opts->factor), then iterate until max_iter or a stopping rule.
+ * count > 1 with every problem least squares: the problems are solved
+ * together in lockstep (batched path): one persistent matvec launch per row-
+ * width bucket covers all of them, the PCG iterations run as a captured
+ * hipGraph, converged instances drop out (per-instance masks).  KKT checks
+ * are made at the end only in that mode.  Otherwise the problems are solved
+ * one after another.  Arrays have length count. */
 nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_admm_opts* O,
                       nys_admm_state* S, nys_admm_info* I);
 

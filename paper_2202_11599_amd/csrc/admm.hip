@@ -158,7 +158,8 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 // of the per-row terms q when q_out != NULL (synchronises).
 nys_status gram_pass(nys_ctx ctx, const nys_dense& A, int mode, const double* p, const double* aux,
                      double* auxout, double* out, const AdmmWs& w, bool want_q) {
-  const GramPlan pl = make_gram_plan(A, ctx->num_cu);
+  GramPlan pl;
+  NYS_TRY(ctx_gram_plan(ctx, A, &pl));
   PcgWs ws;
   NYS_TRY(pcg_workspace(ctx, pl, A.d, 1, &ws));
   NYS_TRY(ctx_gram(ctx, A, pl, mode, p, aux, auxout, ws.ypart, ws.qpart, nullptr));
@@ -285,6 +286,12 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
   return ps == NYS_ERR_MAXITER ? NYS_OK : ps;
 }
 
+nys_status admm_kkt(nys_ctx ctx, const nys_problem& P, const double* z, double* eta, double* obj) {
+  AdmmWs w;
+  NYS_TRY(admm_workspace(ctx, P.A.n, P.A.d, &w));
+  return kkt_and_objective(ctx, P, z, w, eta, obj);
+}
+
 nys_status validate_problem(const nys_problem* P, const nys_admm_opts* O) {
   if (P == nullptr || O == nullptr) return NYS_ERR_INVALID;
   NYS_TRY(validate_dense(&P->A));
@@ -328,15 +335,22 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
   }
   NYS_TRY_HIP(hipSetDevice(ctx->device));
   ctx->atb_key = AtbKey{};   // b may have changed in place since an earlier call
+  bool batched = count > 1;
+  for (int q = 0; q < count; ++q) {
+    if (P[q].loss != NYS_LOSS_LS || O[q].tol_schedule || O[q].kkt_tol > 0.0) batched = false;
+    if (O[q].factor != nullptr && O[q].factor->d != P[q].A.d) return NYS_ERR_INVALID;
+  }
+  if (batched) return admm_solve_batched(ctx, count, P, O, S, I);
   nys_status worst = NYS_OK;
   for (int q = 0; q < count; ++q) {
     const nys_problem& p = P[q];
     const nys_admm_opts& o = O[q];
     nys_admm_info info{};
     info.eta = info.obj = -1.0;
-    nys_factor F = nullptr;
+    nys_factor F = o.factor;
+    const bool own = (F == nullptr);
     nys_status s = NYS_OK;
-    if (p.loss == NYS_LOSS_LS) {
+    if (p.loss == NYS_LOSS_LS && F == nullptr) {
       if (o.rank_max > o.rank && o.ada_tol >= 1.0)
         s = nys_sketch_adaptive(ctx, &p.A, nullptr, p.c, o.omega, o.rank, o.rank_max, o.rho,
                                 o.ada_tol, o.sketch_prec, &F);
@@ -381,7 +395,7 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
     if (s == NYS_OK && info.eta < 0.0)
       s = kkt_and_objective(ctx, p, S[q].z, w, &info.eta, &info.obj);
     if (s != NYS_OK) info.status = s;
-    if (F) nys_factor_destroy(F);
+    if (F && own) nys_factor_destroy(F);
     if (I) I[q] = info;
     if (s != NYS_OK && worst == NYS_OK) worst = s;
   }

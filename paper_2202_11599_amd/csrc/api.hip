@@ -103,6 +103,71 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
   return NYS_OK;
 }
 
+nys_status ctx_gram_plan(nys_ctx ctx, const nys_dense& A, GramPlan* out) {
+  const char* forced = getenv("NYSADMM_GRAM_PLAN");
+  const char* tune = getenv("NYSADMM_TUNE");
+  if (forced != nullptr || (tune != nullptr && tune[0] == '0') || A.n < 4096) {
+    *out = make_gram_plan(A, ctx->num_cu);
+    return NYS_OK;
+  }
+  const int esize = A.dtype == NYS_F64 ? 8 : 4;
+  const bool aligned = ((uintptr_t)A.data % 16 == 0) && ((A.ld * esize) % 16 == 0);
+  char key[160];
+  snprintf(key, sizeof(key), "%d|%lld|%lld|%lld|%d", (int)A.dtype, (long long)A.n,
+           (long long)A.d, (long long)A.ld, (int)aligned);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    GramPlan pl = it->second;
+    pl.aligned = aligned;
+    // the grid depends only on n and the shape; recompute for this pointer
+    *out = pl;
+    return NYS_OK;
+  }
+  std::vector<GramPlan> cands = gram_candidates(A, ctx->num_cu);
+  if (cands.empty()) {
+    *out = make_gram_plan(A, ctx->num_cu);
+    return NYS_OK;
+  }
+  int gmax = 0;
+  for (auto& c : cands) gmax = std::max(gmax, c.grid);
+  const int ldy = cands[0].ldy;
+  // scratch: partial sums of the widest candidate, and an input vector of zeros
+  DevBuf scratch;
+  const size_t yb = align_up(sizeof(double) * (size_t)gmax * ldy);
+  NYS_TRY(scratch.reserve(yb + align_up(sizeof(double) * gmax) + align_up(sizeof(double) * A.d)));
+  double* yp = scratch.as<double>();
+  double* qp = reinterpret_cast<double*>(static_cast<char*>(scratch.ptr) + yb);
+  double* pv = reinterpret_cast<double*>(static_cast<char*>(scratch.ptr) + yb +
+                                         align_up(sizeof(double) * gmax));
+  NYS_TRY_HIP(hipMemsetAsync(pv, 0, sizeof(double) * A.d, ctx->stream));
+  hipEvent_t e0, e1;
+  NYS_TRY_HIP(hipEventCreate(&e0));
+  NYS_TRY_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  GramPlan bestp = cands[0];
+  for (const GramPlan& c : cands) {
+    if (launch_gram(A, c, kModeHess, pv, nullptr, nullptr, yp, qp, nullptr, ctx->stream) != NYS_OK)
+      continue;
+    (void)hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < 3; ++r)
+      (void)launch_gram(A, c, kModeHess, pv, nullptr, nullptr, yp, qp, nullptr, ctx->stream);
+    (void)hipEventRecord(e1, ctx->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms > 0.f && ms < best) {
+      best = ms;
+      bestp = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  scratch.release();
+  ctx->plans[key] = bestp;
+  *out = bestp;
+  return NYS_OK;
+}
+
 nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out) {
   NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, ws.st, sizeof(PcgDev), hipMemcpyDeviceToHost,
                              ctx->stream));
@@ -121,7 +186,8 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
   const int check = o.check_every > 0 ? o.check_every : 8;
   const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 2;
-  const GramPlan pl = make_gram_plan(A, ctx->num_cu);
+  GramPlan pl;
+  NYS_TRY(ctx_gram_plan(ctx, A, &pl));
   PcgWs ws;
   NYS_TRY(pcg_workspace(ctx, pl, d, max_iter, &ws));
   const double rho_eff = rho + c;
@@ -278,6 +344,7 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   ctx->admm_ws.release();
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return NYS_OK;
 }
@@ -414,7 +481,8 @@ nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, d
   NYS_TRY(validate_dense(A));
   if (!(rho + c >= 0.0)) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
-  const GramPlan pl = make_gram_plan(*A, ctx->num_cu);
+  GramPlan pl;
+  NYS_TRY(ctx_gram_plan(ctx, *A, &pl));
   PcgWs ws;
   NYS_TRY(pcg_workspace(ctx, pl, A->d, 1, &ws));
   NYS_TRY(ctx_gram(ctx, *A, pl, kModeHess, p, D, nullptr, ws.ypart, ws.qpart, nullptr));

@@ -170,6 +170,7 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
   if (i < r) x[i] = 1.0 / sqrt((double)r) * (1.0 + 1e-3 * (double)(i % 7));
   __syncthreads();
   double lam = 0.0;
+  int stable = 0;
   for (int it = 0; it <= iters; ++it) {
     double y = 0.0;
     if (i < r)
@@ -190,12 +191,17 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
     __syncthreads();
     double syy = 0.0;
     for (int w = 0; w < 16; ++w) syy += red[w];
+    const double lam_prev = lam;
     lam = sxy;
     __syncthreads();
     if (syy <= 0.0 || !isfinite(syy)) {
       lam = 0.0;
       break;
     }
+    // only the binade of ||Y||_2 enters the shift: stop once the Rayleigh
+    // quotient has settled to 1e-13 for 4 consecutive iterations
+    stable = (it > 0 && fabs(lam - lam_prev) <= 1e-13 * lam) ? stable + 1 : 0;
+    if (stable >= 4) break;
     if (i < r) x[i] = y / sqrt(syy);
     __syncthreads();
   }
@@ -211,6 +217,7 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
 constexpr int kJB = 32;        // block size
 constexpr int kJP = 2 * kJB;   // pair block size
 constexpr double kJacTol = 1e-15;
+constexpr int kInnerSweeps = 1;
 
 // Round-robin pairing of nb blocks (nb even): round t, pair k -> (a, b).
 __device__ __forceinline__ void rr_pair(int nb, int t, int k, int* a, int* b) {
@@ -249,7 +256,9 @@ __global__ __launch_bounds__(256) void k_jacobi_solve(const double* __restrict__
   if (tid == 0) any_rot = 0;
   __syncthreads();
   int significant = 0;
-  for (int isweep = 0; isweep < 30; ++isweep) {
+  // one cyclic sweep of the pair block per visit (block Jacobi); the outer
+  // sweeps repeat until no block pair rotates
+  for (int isweep = 0; isweep < kInnerSweeps; ++isweep) {
     __shared__ int rot_this_sweep;
     if (tid == 0) rot_this_sweep = 0;
     __syncthreads();

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
+#include <string>
 #include <vector>
 
 #include "../../include/nysadmm.h"
@@ -44,7 +46,7 @@ struct PcgDev {
   int done;      // 1 once converged / broken down
   int iters;     // iterations completed when done was set
   int flags;     // kFlag* bits
-  int pad;
+  int k;         // iteration index (batched path; the single path passes it as an argument)
   double thr2;   // squared stopping threshold
   double ww;     // last ||w||^2
   double rr;     // ||rhs||^2
@@ -58,6 +60,8 @@ constexpr int kFlagZeroRhs = 4;
 struct GramPlan {
   int waves = 4;     // waves per workgroup
   int cpl = 4;       // 16-byte chunks per lane
+  int rows = 4;      // rows per pipelined group
+  int per_cu = 2;    // resident workgroups per CU the grid was sized for
   int grid = 512;    // workgroups (each owns a contiguous row range)
   int64_t rows_per_wg = 0;
   bool aligned = true;
@@ -91,6 +95,10 @@ struct PcgWs {
 
 // ---- api.hip
 size_t align_up(size_t x);
+// Launch shape for A: the fastest of gram_candidates() timed on A itself the
+// first time this (dtype, n, d, ld, alignment) is seen, cached in the context.
+// NYSADMM_GRAM_PLAN forces a shape, NYSADMM_TUNE=0 uses the heuristic.
+nys_status ctx_gram_plan(nys_ctx ctx, const nys_dense& A, GramPlan* out);
 // launch_gram on the context's stream, timed when profiling is on
 nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int mode,
                     const double* p, const double* aux, double* auxout, double* ypart,
@@ -98,6 +106,12 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
 nys_status validate_dense(const nys_dense* A);
 nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws);
 nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out);
+
+// ---- admm.hip / batched.hip
+// relative KKT residual (eq. 31 or its logistic form) and objective at z
+nys_status admm_kkt(nys_ctx ctx, const nys_problem& P, const double* z, double* eta, double* obj);
+nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
+                              const nys_admm_opts* O, nys_admm_state* S, nys_admm_info* I);
 
 // ---- core.hip
 // C(m,n) = alpha sum_k A(m,k) w_k B(k,n) + beta C(m,n) in FP64 (w NULL: 1),
@@ -143,6 +157,9 @@ struct nys_ctx_s {
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
   void* host_pinned = nullptr;  // small pinned readback area
   AtbKey atb_key;                // which (A, b) the cached A^T b in admm_ws belongs to
+  std::map<std::string, nys::GramPlan> plans;   // autotuned launch shapes per matrix shape
+  std::map<std::string, std::vector<int>> bplans;  // autotuned batched shapes per batch
+  hipStream_t cap_stream = nullptr;              // graph-capture stream (batched path)
   bool prof_on = false;          // time matvec-pair launches with events
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used = 0;
@@ -171,6 +188,7 @@ namespace nys {
 
 // ---- gemv.hip
 GramPlan make_gram_plan(const nys_dense& A, int num_cu);
+std::vector<GramPlan> gram_candidates(const nys_dense& A, int num_cu);
 // Launch the fused pass  t = A p;  s = mode(t);  y_g = sum_{rows of g} s_i A_i.
 nys_status launch_gram(const nys_dense& A, const GramPlan& plan, int mode, const double* p,
                        const double* aux, double* auxout, double* ypart, double* qpart,

@@ -65,7 +65,8 @@ class AdmmOpts(C.Structure):
                 ("ada_tol", C.c_double), ("resketch_every", C.c_int), ("sketch_prec", C.c_int),
                 ("omega", C.c_void_p), ("pcg", PcgOpts), ("tol_schedule", C.c_int),
                 ("max_iter", C.c_int), ("eps_abs", C.c_double), ("eps_rel", C.c_double),
-                ("rel_change_tol", C.c_double), ("kkt_tol", C.c_double), ("kkt_every", C.c_int)]
+                ("rel_change_tol", C.c_double), ("kkt_tol", C.c_double), ("kkt_every", C.c_int),
+                ("factor", C.c_void_p)]
 
 
 class AdmmState(C.Structure):
@@ -315,11 +316,12 @@ def pcg_solve(ctx: Context, A: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor,
 
 def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resketch_every=0,
               sketch_prec=NYS_F64, pcg: Optional[PcgOpts] = None, tol_schedule=False, max_iter=100,
-              eps_abs=0.0, eps_rel=0.0, rel_change_tol=0.0, kkt_tol=0.0, kkt_every=10) -> AdmmOpts:
+              eps_abs=0.0, eps_rel=0.0, rel_change_tol=0.0, kkt_tol=0.0, kkt_every=10,
+              factor: Optional["Factor"] = None) -> AdmmOpts:
     return AdmmOpts(float(rho), int(rank), int(rank_max), float(ada_tol), int(resketch_every),
                     int(sketch_prec), omega_rows.data_ptr(), pcg or pcg_opts(), int(bool(tol_schedule)),
                     int(max_iter), float(eps_abs), float(eps_rel), float(rel_change_tol),
-                    float(kkt_tol), int(kkt_every))
+                    float(kkt_tol), int(kkt_every), None if factor is None else factor.h.value)
 
 
 def problem(A: torch.Tensor, b: torch.Tensor, gamma: float, loss=NYS_LOSS_LS, c: float = 0.0) -> Problem:
