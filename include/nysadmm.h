@@ -65,6 +65,7 @@ typedef enum { NYS_LOSS_LS = 0, NYS_LOSS_LOGISTIC = 1 } nys_loss;
 
 typedef struct nys_ctx_s* nys_ctx;
 typedef struct nys_factor_s* nys_factor;
+typedef struct nys_ws_model_s* nys_ws_model;
 
 /* Dense row-major matrix: element (i, j) at data + i*ld + j. */
 typedef struct {
@@ -88,8 +89,9 @@ size_t nys_ctx_workspace_bytes(nys_ctx ctx);
 /* Kernel timing (instrumentation, not part of the method): while enabled the
  * library brackets every launch of the fused matvec-pair kernel with HIP
  * events on the context's stream.  nys_ctx_profile_stop synchronises the
- * stream, writes the number of launches and their summed duration in ms, and
- * disables the timing. */
+ * stream, writes the number of launches that did a full pass (launches queued
+ * past PCG convergence return at once and are not counted) and the summed
+ * duration in ms of all timed launches, and disables the timing. */
 nys_status nys_ctx_profile_start(nys_ctx ctx);
 nys_status nys_ctx_profile_stop(nys_ctx ctx, long* launches, double* total_ms);
 
@@ -216,6 +218,13 @@ typedef struct {
   nys_factor factor;     /* optional prebuilt factor of A^T A + c I for this problem (lasso):
                             used instead of sketching and not destroyed (regularisation paths
                             reuse it across gamma); NULL: admm_solve builds and frees one */
+  nys_ws_model warm_start; /* optional warm-start network: each subproblem also gets the
+                            candidate start x0 = U c, c = net([U^T rhs, log gamma, log rho]);
+                            PCG starts from whichever of x0 and the previous x has the smaller
+                            residual (one extra pass over A); NULL: previous x only */
+  int ws_analytic;       /* 1: the candidate is x0 = U (Lambda + rho I)^-1 U^T rhs instead */
+  double* ws_features;   /* optional device (rank + 2): features of the step's subproblem */
+  double* ws_target;     /* optional device (rank): U^T x of the step's solution */
 } nys_admm_opts;
 
 /* Caller-owned device FP64 d-vectors; x = z = u = 0 for a cold start.  k counts
@@ -237,6 +246,7 @@ typedef struct {
   int rank;            /* Nystrom rank in use */
   int converged;       /* a stopping rule fired */
   nys_status status;
+  int ws_used;         /* subproblems that started from the warm-start candidate */
 } nys_admm_info;
 
 /* One iteration of Algorithm NysADMM: right-hand side (lasso: rho(z-u) + A^T b;
@@ -258,6 +268,36 @@ nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, 
  * one after another.  Arrays have length count. */
 nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_admm_opts* O,
                       nys_admm_state* S, nys_admm_info* I);
+
+/* --------------------------------------------------- warm-start network */
+
+/* A small network proposing the PCG start of the ADMM subproblem in the
+ * Nystrom basis (not part of the paper's method; the previous iterate stays
+ * the fallback and the judge, the tolerance is never relaxed):
+ *   f  = [U^T rhs, log gamma, log rho]            (n_in = rank + 2)
+ *   f' = (f - in_mean) / in_std
+ *   h1 = gelu(f' W1 + b1), h2 = gelu(h1 W2 + b2), o = h2 W3 + b3   (n_out = rank)
+ *   c  = o * out_scale,  x0 = U c,  gelu(a) = a/2 (1 + erf(a / sqrt 2)).
+ * params_host: W1 (n_in x hidden), b1, W2 (hidden x hidden), b2,
+ * W3 (hidden x n_out), b3, row-major, FP64, nys_ws_param_count() values.
+ * in_mean/in_std/out_scale may be NULL (0, 1, 1).  All arithmetic is FP64 on
+ * the device.  Training data: the loss is (1/B) sum_ik W_ik (o_ik - T_ik)^2
+ * with T the targets already divided by out_scale; X rows are raw features. */
+size_t nys_ws_param_count(int n_in, int hidden, int n_out);
+nys_status nys_ws_create(nys_ctx ctx, int n_in, int hidden, int n_out, const double* params_host,
+                         const double* in_mean, const double* in_std, const double* out_scale,
+                         nys_ws_model* out);
+nys_status nys_ws_get_params(nys_ctx ctx, nys_ws_model m, double* params_host);
+/* out (device, batch x n_out) = o for the batch x n_in device rows X */
+nys_status nys_ws_forward(nys_ctx ctx, nys_ws_model m, const double* X, int batch, double* out);
+/* loss and, if grad_out != NULL, the gradient (device, nys_ws_param_count values,
+ * same layout as params) for device X, T, W (W NULL: weights 1) */
+nys_status nys_ws_loss_grad(nys_ctx ctx, nys_ws_model m, const double* X, const double* T,
+                            const double* W, int batch, double* loss_host, double* grad_out);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) at rate lr */
+nys_status nys_ws_train_step(nys_ctx ctx, nys_ws_model m, const double* X, const double* T,
+                             const double* W, int batch, double lr, double* loss_host);
+nys_status nys_ws_destroy(nys_ws_model m);
 
 #ifdef __cplusplus
 }

@@ -132,16 +132,19 @@ __global__ __launch_bounds__(256) void k_reduce_scalars(const double* __restrict
 }
 
 struct AdmmWs {
-  double *atb, *rhs, *g, *Dw, *part, *scal;
+  double *atb, *rhs, *g, *Dw, *part, *scal, *xalt, *wss;
   int nb;
 };
+
+constexpr int kWsScratch = 4 * 1024 + 8;   // warm-start scratch (rank <= 1024)
 
 nys_status admm_workspace(nys_ctx ctx, int64_t n, int64_t d, AdmmWs* w) {
   w->nb = nblk(d, 256);
   const size_t vd = align_up(sizeof(double) * d);
   const size_t vn = align_up(sizeof(double) * std::max<int64_t>(n, 1));
   const size_t pb = align_up(sizeof(double) * kNS * w->nb);
-  NYS_TRY(ctx->admm_ws.reserve(3 * vd + vn + pb + 256));
+  const size_t sc = align_up(sizeof(double) * (kNS + 1));
+  NYS_TRY(ctx->admm_ws.reserve(4 * vd + vn + pb + sc + sizeof(double) * kWsScratch));
   char* p = static_cast<char*>(ctx->admm_ws.ptr);
   w->atb = reinterpret_cast<double*>(p);
   w->rhs = reinterpret_cast<double*>(p + vd);
@@ -149,6 +152,8 @@ nys_status admm_workspace(nys_ctx ctx, int64_t n, int64_t d, AdmmWs* w) {
   w->Dw = reinterpret_cast<double*>(p + 3 * vd);
   w->part = reinterpret_cast<double*>(p + 3 * vd + vn);
   w->scal = reinterpret_cast<double*>(p + 3 * vd + vn + pb);
+  w->xalt = reinterpret_cast<double*>(p + 3 * vd + vn + pb + sc);
+  w->wss = reinterpret_cast<double*>(p + 4 * vd + vn + pb + sc);
   return NYS_OK;
 }
 
@@ -252,8 +257,25 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
     po.tol_abs = 0;
     abs_tol = pcg_abs;
   }
+  // warm-start candidate (network or analytic) next to the previous iterate
+  const double* x_alt = nullptr;
+  if (*F != nullptr && (O.warm_start != nullptr || O.ws_analytic)) {
+    if (O.warm_start != nullptr)
+      NYS_TRY(ws_propose(ctx, O.warm_start, *F, w.rhs, P.gamma, O.rho, w.xalt, w.wss,
+                         O.ws_features));
+    else
+      NYS_TRY(ws_analytic(ctx, *F, w.rhs, O.rho, w.xalt, w.wss));
+    x_alt = w.xalt;
+  }
+  if (*F != nullptr && O.ws_features != nullptr && O.warm_start == nullptr)
+    NYS_TRY(ws_record(ctx, *F, w.rhs, P.gamma, O.rho, nullptr, O.ws_features, nullptr, w.wss));
   nys_pcg_info pinfo{};
-  nys_status ps = pcg_run(ctx, A, D, P.c, O.rho, *F, w.rhs, S->x, po, &pinfo, abs_tol);
+  int used_alt = 0;
+  // lasso: x is only changed by PCG, so H_rho x carries over between solves
+  nys_status ps = pcg_run(ctx, A, D, P.c, O.rho, *F, w.rhs, S->x, po, &pinfo, abs_tol,
+                          P.loss == NYS_LOSS_LS, x_alt, &used_alt);
+  if (*F != nullptr && O.ws_target != nullptr && (ps == NYS_OK || ps == NYS_ERR_MAXITER))
+    NYS_TRY(ws_record(ctx, *F, nullptr, P.gamma, O.rho, S->x, nullptr, O.ws_target, w.wss));
   if (ps != NYS_OK && ps != NYS_ERR_MAXITER) {
     if (I) I->status = ps;
     return ps;
@@ -272,6 +294,7 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
     I->r_d = O.rho * std::sqrt(s[1]);
     I->rank = (*F) ? (*F)->r : 0;
     I->status = ps;
+    I->ws_used = used_alt;
     // Section 2.1 residual stop
     bool stop = false;
     if (O.eps_rel > 0.0) {
@@ -299,6 +322,7 @@ nys_status validate_problem(const nys_problem* P, const nys_admm_opts* O) {
   if (P->loss != NYS_LOSS_LS && P->loss != NYS_LOSS_LOGISTIC) return NYS_ERR_INVALID;
   if (!(O->rho > 0.0) || O->rank < 1 || O->rank >= P->A.d || O->omega == nullptr)
     return NYS_ERR_INVALID;
+  if (O->warm_start != nullptr && !(P->gamma > 0.0)) return NYS_ERR_INVALID;
   if (O->rank_max > O->rank && (O->rank_max >= P->A.d || O->rank_max > 1024))
     return NYS_ERR_INVALID;
   return NYS_OK;
@@ -335,9 +359,13 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
   }
   NYS_TRY_HIP(hipSetDevice(ctx->device));
   ctx->atb_key = AtbKey{};   // b may have changed in place since an earlier call
+  ctx->hx_key = AtbKey{};    // and x since an earlier solve
   bool batched = count > 1;
   for (int q = 0; q < count; ++q) {
     if (P[q].loss != NYS_LOSS_LS || O[q].tol_schedule || O[q].kkt_tol > 0.0) batched = false;
+    if (O[q].warm_start != nullptr || O[q].ws_analytic || O[q].ws_features != nullptr ||
+        O[q].ws_target != nullptr)
+      batched = false;
     if (O[q].factor != nullptr && O[q].factor->d != P[q].A.d) return NYS_ERR_INVALID;
   }
   if (batched) return admm_solve_batched(ctx, count, P, O, S, I);
@@ -379,6 +407,7 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
       info.r_d = step.r_d;
       info.rank = step.rank;
       info.status = step.status;
+      info.ws_used += step.ws_used;
       if (o.tol_schedule) eps_next = std::sqrt(step.r_p * step.r_d);
       bool stop = step.converged != 0;
       if (o.kkt_tol > 0.0 && ((it + 1) % kkt_every == 0 || stop)) {

@@ -785,6 +785,11 @@ nys_status batch_tune(nys_ctx ctx, Batch* B) {
     NYS_TRY(upload_tiles(ctx, &bestb, B->h, ctx->num_cu));
     bk = bestb;
     ctx->bplans[key] = {bk.waves, bk.cpl, bk.rows, bk.per_cu, (int)bk.tile_rows};
+    if (getenv("NYSADMM_VERBOSE"))
+      fprintf(stderr, "nysadmm: batched bucket (%zu instances, d <= %d): waves %d, chunks %d, "
+              "rows %d, %d wg/CU, tile %lld rows, %d tiles (%.1f us)\n", bk.insts.size(), d_max,
+              bk.waves, bk.cpl, bk.rows, bk.per_cu, (long long)bk.tile_rows, bk.ntiles,
+              cands.size() > 1 ? 1e3 * best / 2 : -1.0);
     // the partial-sum count of each instance follows the chosen tiling
     for (int q : bk.insts) B->h[q].G = (int)((B->h[q].n + bk.tile_rows - 1) / bk.tile_rows);
   }

@@ -89,6 +89,9 @@ struct PcgWs {
   double* wwpart = nullptr;
   double* rrpart = nullptr;
   double* pppart = nullptr;
+  double* w2 = nullptr;          // residual of a candidate start (judge)
+  double* wwpart2 = nullptr;
+  double* rrpart2 = nullptr;
   int nred = 0;
   int nvec = 0;
 };
@@ -129,9 +132,23 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
                       int max_sweeps, void* host_pinned, double* sig2, double* W, int ldw,
                       int* sweeps_out);
 // Stop when ||w|| <= max(abs_tol, tol ||rhs||) (o.tol_abs: ||w|| <= o.tol).
+// reuse_hx: the caller guarantees x is unchanged since the previous pcg_run on
+// the same (A, D, c, rho); H_rho x saved by that run's true-residual pass then
+// gives w0 without a pass over A, and this run saves its own for the next.
+// x_alt: a candidate start; PCG starts from whichever of x and x_alt has the
+// smaller residual (x is overwritten by x_alt if it wins, *used_alt = 1).
 nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
                    nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
-                   nys_pcg_info* info, double abs_tol = 0.0);
+                   nys_pcg_info* info, double abs_tol = 0.0, bool reuse_hx = false,
+                   const double* x_alt = nullptr, int* used_alt = nullptr);
+
+// ---- mlp.hip
+nys_status ws_propose(nys_ctx ctx, nys_ws_model m, nys_factor F, const double* rhs, double gamma,
+                      double rho, double* x0, double* scratch, double* feat_out);
+nys_status ws_record(nys_ctx ctx, nys_factor F, const double* rhs, double gamma, double rho,
+                     const double* x, double* feat_out, double* target_out, double* scratch);
+nys_status ws_analytic(nys_ctx ctx, nys_factor F, const double* rhs, double rho, double* x0,
+                       double* scratch);
 }  // namespace nys
 
 // Key of the cached A^T b of the lasso right-hand side.
@@ -157,12 +174,16 @@ struct nys_ctx_s {
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
   void* host_pinned = nullptr;  // small pinned readback area
   AtbKey atb_key;                // which (A, b) the cached A^T b in admm_ws belongs to
+  nys::DevBuf hx;                // H_rho x of the last solve (lasso ADMM sequence)
+  AtbKey hx_key;                 // (A, x) it belongs to; buf = x pointer
+  double hx_rho = -1.0, hx_c = -1.0;
   std::map<std::string, nys::GramPlan> plans;   // autotuned launch shapes per matrix shape
   std::map<std::string, std::vector<int>> bplans;  // autotuned batched shapes per batch
   hipStream_t cap_stream = nullptr;              // graph-capture stream (batched path)
   bool prof_on = false;          // time matvec-pair launches with events
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used = 0;
+  long prof_skipped = 0;         // timed launches that returned at once (PCG already done)
 };
 
 struct nys_factor_s {
@@ -202,7 +223,7 @@ inline int nblk(int64_t d, int b) { return (int)((d + b - 1) / b); }
 // v = sum_g ypart[g] + rho_eff * p ; then per `op`:
 //   op 0 (iterate): alpha = wy[k] / (sum q + rho_eff ||p||^2); x += alpha p; w -= alpha v
 //   op 1 (init):    w = rhs - v ;  ||rhs||^2 partials
-//   op 2 (true):    w = rhs - v  (true residual, FP64 accumulation)
+//   op 2 (true):    w = rhs - v  (true residual, FP64 accumulation); v -> x if x != NULL
 //   op 3 (plain):   out = v + beta * aux   (used for rhs/gradient assembly)
 nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, const double* qpart,
                                 int64_t d, double rho_eff, const double* p, double* x, double* w,

@@ -1,0 +1,444 @@
+// Warm-start network for the PCG start of the ADMM x-subproblem (not part of
+// the paper's method; the previous iterate stays the fallback):
+//   f  = [U^T rhs, log gamma, log rho]           (features, n_in = r + 2)
+//   f' = (f - mu) / sigma                          (standardisation, stored in the model)
+//   h1 = gelu(f' W1 + b1), h2 = gelu(h1 W2 + b2), o = h2 W3 + b3
+//   c  = o * s_out,  x0 = U c                      (Nystrom basis)
+// gelu(a) = a/2 (1 + erf(a/sqrt 2)).  Training minimises the weighted squared
+// error (1/B) sum w_ik (o_ik - t_ik)^2 on standardised targets t = c* / s_out
+// with Adam (bias-corrected).  Everything is FP64 on the GPU: the matrix
+// products use the library's tiled FP64 GEMM, the rest small elementwise and
+// reduction kernels here.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace nys {
+namespace {
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+__device__ __forceinline__ double gelu_d(double a) {
+  return 0.5 * a * (1.0 + erf(a * 0.70710678118654752440));
+}
+__device__ __forceinline__ double gelu_grad_d(double a) {
+  return 0.5 * (1.0 + erf(a * 0.70710678118654752440)) +
+         a * exp(-0.5 * a * a) * 0.39894228040143267794;
+}
+
+// A (M x N) += bias; H = gelu(A)
+__global__ void k_bias_gelu(double* __restrict__ A, const double* __restrict__ bias, int64_t M,
+                            int N, double* __restrict__ H) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * N) return;
+  const double a = A[e] + bias[e % N];
+  A[e] = a;
+  H[e] = gelu_d(a);
+}
+
+__global__ void k_bias(double* __restrict__ A, const double* __restrict__ bias, int64_t M, int N) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < M * N) A[e] += bias[e % N];
+}
+
+// Xn = (X - mu) / sigma   (M x N)
+__global__ void k_standardise(const double* __restrict__ X, const double* __restrict__ mu,
+                              const double* __restrict__ sig, int64_t M, int N,
+                              double* __restrict__ Xn) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < M * N) Xn[e] = (X[e] - mu[e % N]) / sig[e % N];
+}
+
+// g = 2 w (o - t) / B, loss partials per block
+__global__ __launch_bounds__(256) void k_loss_grad(const double* __restrict__ O,
+                                                   const double* __restrict__ Tg,
+                                                   const double* __restrict__ W, int64_t MN,
+                                                   int B, double* __restrict__ G,
+                                                   double* __restrict__ part) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (e < MN) {
+    const double r = O[e] - Tg[e];
+    const double w = W ? W[e] : 1.0;
+    l = w * r * r / B;
+    G[e] = 2.0 * w * r / B;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// column sums of G (M x N) into out (N), one thread per column, fixed order
+__global__ void k_colsum(const double* __restrict__ G, int64_t M, int N, double* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  double s = 0.0;
+  for (int64_t i = 0; i < M; ++i) s += G[i * N + c];
+  out[c] = s;
+}
+
+// gA = gH o gelu'(A)
+__global__ void k_gelu_back(const double* __restrict__ gH, const double* __restrict__ A, int64_t n,
+                            double* __restrict__ gA) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) gA[e] = gH[e] * gelu_grad_d(A[e]);
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int n, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  *out = s;
+}
+
+__global__ void k_adam(double* __restrict__ p, const double* __restrict__ g, double* __restrict__ m,
+                       double* __restrict__ v, int64_t n, double lr, double b1, double b2,
+                       double eps, double c1, double c2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const double ge = g[e];
+  const double me = b1 * m[e] + (1.0 - b1) * ge;
+  const double ve = b2 * v[e] + (1.0 - b2) * ge * ge;
+  m[e] = me;
+  v[e] = ve;
+  p[e] -= lr * (me / c1) / (sqrt(ve / c2) + eps);
+}
+
+// features [U^T rhs, log gamma, log rho] from the precomputed U^T rhs
+__global__ void k_features(const double* __restrict__ c, int r, double lg, double lr,
+                           double* __restrict__ f) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < r) f[i] = c[i];
+  if (i == r) f[r] = lg;
+  if (i == r + 1) f[r + 1] = lr;
+}
+
+// c = u / (lambda + rho)
+__global__ void k_shift_div(const double* __restrict__ u, const double* __restrict__ lam, int r,
+                            double rho, double* __restrict__ c) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < r) c[i] = u[i] / (lam[i] + rho);
+}
+
+// c = o * s_out
+__global__ void k_scale(const double* __restrict__ o, const double* __restrict__ s, int n,
+                        double* __restrict__ c) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) c[i] = o[i] * s[i];
+}
+
+}  // namespace
+}  // namespace nys
+
+struct nys_ws_model_s {
+  int n_in = 0, hidden = 0, n_out = 0;
+  int device = 0;
+  long t = 0;                 // Adam step count
+  nys::DevBuf params;         // W1 b1 W2 b2 W3 b3 (row-major), then mu, sigma, s_out
+  nys::DevBuf adam;           // m, v
+  nys::DevBuf grads;
+  nys::DevBuf act;            // activations workspace
+  int64_t act_batch = 0;
+};
+
+namespace nys {
+
+size_t ws_count(int ni, int h, int no) {
+  return (size_t)ni * h + h + (size_t)h * h + h + (size_t)h * no + no;
+}
+
+struct WsPtrs {
+  double *W1, *b1, *W2, *b2, *W3, *b3, *mu, *sig, *sout;
+};
+
+WsPtrs ws_ptrs(nys_ws_model m, double* base) {
+  WsPtrs p;
+  const int ni = m->n_in, h = m->hidden, no = m->n_out;
+  p.W1 = base;
+  p.b1 = p.W1 + (size_t)ni * h;
+  p.W2 = p.b1 + h;
+  p.b2 = p.W2 + (size_t)h * h;
+  p.W3 = p.b2 + h;
+  p.b3 = p.W3 + (size_t)h * no;
+  p.mu = p.b3 + no;
+  p.sig = p.mu + ni;
+  p.sout = p.sig + ni;
+  return p;
+}
+
+struct Act {
+  double *Xn, *A1, *H1, *A2, *H2, *O, *G, *gH, *gA, *part;
+};
+
+nys_status ws_act(nys_ws_model m, int64_t B, Act* a) {
+  const int ni = m->n_in, h = m->hidden, no = m->n_out;
+  const size_t need = (size_t)B * (ni + 4 * h + 2 * no + h + h) + blocks(B * std::max(no, h)) + 64;
+  NYS_TRY(m->act.reserve(sizeof(double) * need));
+  double* p = m->act.as<double>();
+  a->Xn = p;
+  p += B * ni;
+  a->A1 = p;
+  p += B * h;
+  a->H1 = p;
+  p += B * h;
+  a->A2 = p;
+  p += B * h;
+  a->H2 = p;
+  p += B * h;
+  a->O = p;
+  p += B * no;
+  a->G = p;
+  p += B * no;
+  a->gH = p;
+  p += B * h;
+  a->gA = p;
+  p += B * h;
+  a->part = p;
+  return NYS_OK;
+}
+
+// forward of B standardised rows into a.O (and the activations for backward)
+nys_status ws_forward(nys_ctx ctx, nys_ws_model m, const double* X, int64_t B, Act* a) {
+  hipStream_t st = ctx->stream;
+  const int ni = m->n_in, h = m->hidden, no = m->n_out;
+  WsPtrs p = ws_ptrs(m, m->params.as<double>());
+  hipLaunchKernelGGL(k_standardise, dim3(blocks(B * ni)), dim3(256), 0, st, X, p.mu, p.sig, B, ni,
+                     a->Xn);
+  NYS_TRY(gemm64(st, (int)B, h, ni, a->Xn, false, ni, 1, p.W1, false, h, 1, a->A1, h, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(B * h)), dim3(256), 0, st, a->A1, p.b1, B, h, a->H1);
+  NYS_TRY(gemm64(st, (int)B, h, h, a->H1, false, h, 1, p.W2, false, h, 1, a->A2, h, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(B * h)), dim3(256), 0, st, a->A2, p.b2, B, h, a->H2);
+  NYS_TRY(gemm64(st, (int)B, no, h, a->H2, false, h, 1, p.W3, false, no, 1, a->O, no, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_bias, dim3(blocks(B * no)), dim3(256), 0, st, a->O, p.b3, B, no);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+// loss (device scalar at *loss_dev) and gradients into m->grads
+nys_status ws_backward(nys_ctx ctx, nys_ws_model m, const double* Tg, const double* Wt, int64_t B,
+                       Act* a, double* loss_dev) {
+  hipStream_t st = ctx->stream;
+  const int ni = m->n_in, h = m->hidden, no = m->n_out;
+  WsPtrs p = ws_ptrs(m, m->params.as<double>());
+  WsPtrs g = ws_ptrs(m, m->grads.as<double>());
+  const unsigned nb = blocks(B * no);
+  hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(256), 0, st, a->O, Tg, Wt, B * no, (int)B, a->G,
+                     a->part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, a->part, (int)nb, loss_dev);
+  // layer 3
+  NYS_TRY(gemm64(st, h, no, (int)B, a->H2, false, 1, h, a->G, false, no, 1, g.W3, no, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(no)), dim3(256), 0, st, a->G, B, no, g.b3);
+  NYS_TRY(gemm64(st, (int)B, h, no, a->G, false, no, 1, p.W3, false, 1, no, a->gH, h, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_gelu_back, dim3(blocks(B * h)), dim3(256), 0, st, a->gH, a->A2, B * h, a->gA);
+  // layer 2
+  NYS_TRY(gemm64(st, h, h, (int)B, a->H1, false, 1, h, a->gA, false, h, 1, g.W2, h, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(h)), dim3(256), 0, st, a->gA, B, h, g.b2);
+  NYS_TRY(gemm64(st, (int)B, h, h, a->gA, false, h, 1, p.W2, false, 1, h, a->gH, h, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_gelu_back, dim3(blocks(B * h)), dim3(256), 0, st, a->gH, a->A1, B * h, a->gA);
+  // layer 1
+  NYS_TRY(gemm64(st, ni, h, (int)B, a->Xn, false, 1, ni, a->gA, false, h, 1, g.W1, h, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(h)), dim3(256), 0, st, a->gA, B, h, g.b1);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+// x0 = U c with c = s_out * MLP((f - mu)/sigma), f = [U^T rhs, log gamma, log rho].
+// scratch: >= 2 r + 2 + n_out doubles (device).
+nys_status ws_propose(nys_ctx ctx, nys_ws_model m, nys_factor F, const double* rhs, double gamma,
+                      double rho, double* x0, double* scratch, double* feat_out) {
+  hipStream_t st = ctx->stream;
+  const int r = F->r;
+  if (m->n_in != r + 2 || m->n_out != r) return NYS_ERR_INVALID;
+  double* cU = scratch;                  // U^T rhs (r)
+  double* f = scratch + r;               // features (r + 2)
+  double* c = f + r + 2;                 // coefficients (r)
+  const double* U = F->U.as<double>();
+  // U^T rhs (FP64 U; r x d GEMV through the tiled GEMM)
+  NYS_TRY(gemm64(st, r, 1, (int)F->d, U, false, F->d, 1, rhs, false, 1, 1, cU, 1, 1, 1.0, 0.0,
+                 nullptr, 0));
+  hipLaunchKernelGGL(k_features, dim3(blocks(r + 2)), dim3(256), 0, st, cU, r, std::log(gamma),
+                     std::log(rho), f);
+  if (feat_out != nullptr)
+    NYS_TRY_HIP(hipMemcpyAsync(feat_out, f, sizeof(double) * (r + 2), hipMemcpyDeviceToDevice, st));
+  Act a;
+  NYS_TRY(ws_act(m, 1, &a));
+  NYS_TRY(ws_forward(ctx, m, f, 1, &a));
+  WsPtrs p = ws_ptrs(m, m->params.as<double>());
+  hipLaunchKernelGGL(k_scale, dim3(blocks(r)), dim3(256), 0, st, a.O, p.sout, r, c);
+  NYS_TRY(gemm64(st, (int)F->d, 1, r, U, false, 1, F->d, c, false, 1, 1, x0, 1, 1, 1.0, 0.0,
+                 nullptr, 0));
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+// x0 = U (Lambda + rho I)^-1 U^T rhs: the exact solve restricted to the span of
+// U (with exact eigenvectors, the coefficient map the network is asked to learn).
+// scratch: >= 2 r doubles (device).
+nys_status ws_analytic(nys_ctx ctx, nys_factor F, const double* rhs, double rho, double* x0,
+                       double* scratch) {
+  hipStream_t st = ctx->stream;
+  const int r = F->r;
+  const double* U = F->U.as<double>();
+  NYS_TRY(gemm64(st, r, 1, (int)F->d, U, false, F->d, 1, rhs, false, 1, 1, scratch, 1, 1, 1.0,
+                 0.0, nullptr, 0));
+  hipLaunchKernelGGL(k_shift_div, dim3(blocks(r)), dim3(256), 0, st, scratch, F->lam.as<double>(),
+                     r, rho, scratch + r);
+  NYS_TRY(gemm64(st, (int)F->d, 1, r, U, false, 1, F->d, scratch + r, false, 1, 1, x0, 1, 1, 1.0,
+                 0.0, nullptr, 0));
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+// features only (for recording training data) and the target U^T x
+nys_status ws_record(nys_ctx ctx, nys_factor F, const double* rhs, double gamma, double rho,
+                     const double* x, double* feat_out, double* target_out, double* scratch) {
+  hipStream_t st = ctx->stream;
+  const int r = F->r;
+  const double* U = F->U.as<double>();
+  if (feat_out != nullptr) {
+    NYS_TRY(gemm64(st, r, 1, (int)F->d, U, false, F->d, 1, rhs, false, 1, 1, scratch, 1, 1, 1.0,
+                   0.0, nullptr, 0));
+    hipLaunchKernelGGL(k_features, dim3(blocks(r + 2)), dim3(256), 0, st, scratch, r,
+                       std::log(gamma), std::log(rho), feat_out);
+  }
+  if (target_out != nullptr)
+    NYS_TRY(gemm64(st, r, 1, (int)F->d, U, false, F->d, 1, x, false, 1, 1, target_out, 1, 1, 1.0,
+                   0.0, nullptr, 0));
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+}  // namespace nys
+
+using namespace nys;
+
+extern "C" {
+
+size_t nys_ws_param_count(int n_in, int hidden, int n_out) {
+  if (n_in < 1 || hidden < 1 || n_out < 1) return 0;
+  return ws_count(n_in, hidden, n_out);
+}
+
+nys_status nys_ws_create(nys_ctx ctx, int n_in, int hidden, int n_out, const double* params_host,
+                         const double* in_mean, const double* in_std, const double* out_scale,
+                         nys_ws_model* out) {
+  if (ctx == nullptr || out == nullptr || params_host == nullptr) return NYS_ERR_INVALID;
+  if (n_in < 1 || hidden < 1 || n_out < 1 || hidden > 4096) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys_ws_model m = new (std::nothrow) nys_ws_model_s();
+  if (m == nullptr) return NYS_ERR_NOMEM;
+  m->n_in = n_in;
+  m->hidden = hidden;
+  m->n_out = n_out;
+  m->device = ctx->device;
+  const size_t np = ws_count(n_in, hidden, n_out);
+  const size_t tot = np + 2 * (size_t)n_in + n_out;
+  std::vector<double> h(tot);
+  std::memcpy(h.data(), params_host, sizeof(double) * np);
+  for (int i = 0; i < n_in; ++i) {
+    h[np + i] = in_mean ? in_mean[i] : 0.0;
+    h[np + n_in + i] = in_std ? in_std[i] : 1.0;
+    if (!(h[np + n_in + i] > 0.0)) {
+      delete m;
+      return NYS_ERR_INVALID;
+    }
+  }
+  for (int i = 0; i < n_out; ++i) h[np + 2 * n_in + i] = out_scale ? out_scale[i] : 1.0;
+  nys_status s = m->params.reserve(sizeof(double) * tot);
+  if (s == NYS_OK) s = m->grads.reserve(sizeof(double) * tot);
+  if (s == NYS_OK) s = m->adam.reserve(sizeof(double) * 2 * np);
+  if (s != NYS_OK) {
+    nys_ws_destroy(m);
+    return s;
+  }
+  if (hipMemcpyAsync(m->params.ptr, h.data(), sizeof(double) * tot, hipMemcpyHostToDevice,
+                     ctx->stream) != hipSuccess ||
+      hipMemsetAsync(m->adam.ptr, 0, sizeof(double) * 2 * np, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    nys_ws_destroy(m);
+    return NYS_ERR_HIP;
+  }
+  *out = m;
+  return NYS_OK;
+}
+
+nys_status nys_ws_get_params(nys_ctx ctx, nys_ws_model m, double* params_host) {
+  if (ctx == nullptr || m == nullptr || params_host == nullptr) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipMemcpyAsync(params_host, m->params.ptr,
+                             sizeof(double) * ws_count(m->n_in, m->hidden, m->n_out),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  return NYS_OK;
+}
+
+nys_status nys_ws_forward(nys_ctx ctx, nys_ws_model m, const double* X, int batch, double* out) {
+  if (ctx == nullptr || m == nullptr || X == nullptr || out == nullptr || batch < 1)
+    return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  Act a;
+  NYS_TRY(ws_act(m, batch, &a));
+  NYS_TRY(ws_forward(ctx, m, X, batch, &a));
+  NYS_TRY_HIP(hipMemcpyAsync(out, a.O, sizeof(double) * batch * m->n_out, hipMemcpyDeviceToDevice,
+                             ctx->stream));
+  return NYS_OK;
+}
+
+nys_status nys_ws_loss_grad(nys_ctx ctx, nys_ws_model m, const double* X, const double* T,
+                            const double* W, int batch, double* loss_host, double* grad_out) {
+  if (ctx == nullptr || m == nullptr || X == nullptr || T == nullptr || batch < 1)
+    return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  Act a;
+  NYS_TRY(ws_act(m, batch, &a));
+  NYS_TRY(ws_forward(ctx, m, X, batch, &a));
+  double* loss_dev = a.part + blocks((int64_t)batch * std::max(m->n_out, m->hidden)) + 1;
+  NYS_TRY(ws_backward(ctx, m, T, W, batch, &a, loss_dev));
+  if (grad_out != nullptr)
+    NYS_TRY_HIP(hipMemcpyAsync(grad_out, m->grads.ptr,
+                               sizeof(double) * ws_count(m->n_in, m->hidden, m->n_out),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+  if (loss_host != nullptr) {
+    NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, loss_dev, sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    std::memcpy(loss_host, ctx->host_pinned, sizeof(double));
+  }
+  return NYS_OK;
+}
+
+nys_status nys_ws_train_step(nys_ctx ctx, nys_ws_model m, const double* X, const double* T,
+                             const double* W, int batch, double lr, double* loss_host) {
+  if (!(lr > 0.0)) return NYS_ERR_INVALID;
+  NYS_TRY(nys_ws_loss_grad(ctx, m, X, T, W, batch, loss_host, nullptr));
+  const int64_t np = (int64_t)ws_count(m->n_in, m->hidden, m->n_out);
+  m->t += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const double c1 = 1.0 - std::pow(b1, (double)m->t), c2 = 1.0 - std::pow(b2, (double)m->t);
+  double* mm = m->adam.as<double>();
+  hipLaunchKernelGGL(k_adam, dim3(blocks(np)), dim3(256), 0, ctx->stream, m->params.as<double>(),
+                     m->grads.as<double>(), mm, mm + np, np, lr, b1, b2, 1e-8, c1, c2);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status nys_ws_destroy(nys_ws_model m) {
+  if (m == nullptr) return NYS_ERR_INVALID;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  m->params.release();
+  m->adam.release();
+  m->grads.release();
+  m->act.release();
+  delete m;
+  return NYS_OK;
+}
+
+}  // extern "C"

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(1024) void k_reduce_update(
       w[j] = wj;
       ww = wj * wj;
       rr = r * r;
+      if (op == 2 && x != nullptr) x[j] = v;   // keep H_rho x for the next solve's w0
     } else {  // op 3: plain reduction
       w[j] = v;
     }

@@ -30,7 +30,9 @@ EXPORTS = [
     "nys_status_string", "nys_ctx_create", "nys_ctx_destroy", "nys_ctx_set_stream",
     "nys_ctx_workspace_bytes", "nys_ctx_profile_start", "nys_ctx_profile_stop", "nys_sketch", "nys_sketch_adaptive", "nys_factor_import",
     "nys_factor_info", "nys_factor_get_U", "nys_factor_destroy", "nys_hessian_apply",
-    "nys_precond_apply", "pcg_solve", "admm_step", "admm_solve",
+    "nys_precond_apply", "pcg_solve", "admm_step", "admm_solve", "nys_ws_param_count",
+    "nys_ws_create", "nys_ws_get_params", "nys_ws_forward", "nys_ws_loss_grad",
+    "nys_ws_train_step", "nys_ws_destroy",
 ]
 
 
@@ -66,7 +68,8 @@ class AdmmOpts(C.Structure):
                 ("omega", C.c_void_p), ("pcg", PcgOpts), ("tol_schedule", C.c_int),
                 ("max_iter", C.c_int), ("eps_abs", C.c_double), ("eps_rel", C.c_double),
                 ("rel_change_tol", C.c_double), ("kkt_tol", C.c_double), ("kkt_every", C.c_int),
-                ("factor", C.c_void_p)]
+                ("factor", C.c_void_p), ("warm_start", C.c_void_p), ("ws_analytic", C.c_int),
+                ("ws_features", C.c_void_p), ("ws_target", C.c_void_p)]
 
 
 class AdmmState(C.Structure):
@@ -77,7 +80,7 @@ class AdmmInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("pcg_iters", C.c_long), ("pcg_max", C.c_int),
                 ("r_p", C.c_double), ("r_d", C.c_double), ("eta", C.c_double),
                 ("obj", C.c_double), ("rank", C.c_int), ("converged", C.c_int),
-                ("status", C.c_int)]
+                ("status", C.c_int), ("ws_used", C.c_int)]
 
 
 def lib():
@@ -109,6 +112,13 @@ def lib():
         "pcg_solve": (i32, [vp, P(Dense), vp, dbl, dbl, vp, vp, vp, P(PcgOpts), P(PcgInfo)]),
         "admm_step": (i32, [vp, P(Problem), P(AdmmOpts), P(vp), P(AdmmState), P(AdmmInfo)]),
         "admm_solve": (i32, [vp, i32, P(Problem), P(AdmmOpts), P(AdmmState), P(AdmmInfo)]),
+        "nys_ws_param_count": (C.c_size_t, [i32, i32, i32]),
+        "nys_ws_create": (i32, [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl), P(dbl), P(vp)]),
+        "nys_ws_get_params": (i32, [vp, vp, P(dbl)]),
+        "nys_ws_forward": (i32, [vp, vp, vp, i32, vp]),
+        "nys_ws_loss_grad": (i32, [vp, vp, vp, vp, vp, i32, P(dbl), vp]),
+        "nys_ws_train_step": (i32, [vp, vp, vp, vp, vp, i32, dbl, P(dbl)]),
+        "nys_ws_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -180,6 +190,9 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return int(lib().nys_ctx_workspace_bytes(self.h))
+
+    def synchronize(self):
+        self._stream.synchronize()
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value is not None:
@@ -317,11 +330,19 @@ def pcg_solve(ctx: Context, A: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor,
 def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resketch_every=0,
               sketch_prec=NYS_F64, pcg: Optional[PcgOpts] = None, tol_schedule=False, max_iter=100,
               eps_abs=0.0, eps_rel=0.0, rel_change_tol=0.0, kkt_tol=0.0, kkt_every=10,
-              factor: Optional["Factor"] = None) -> AdmmOpts:
+              factor: Optional["Factor"] = None, warm_start: Optional["WarmStart"] = None,
+              ws_analytic=False, ws_features: Optional[torch.Tensor] = None,
+              ws_target: Optional[torch.Tensor] = None) -> AdmmOpts:
+    for t, name in ((ws_features, "ws_features"), (ws_target, "ws_target")):
+        if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous CUDA float64 tensor")
     return AdmmOpts(float(rho), int(rank), int(rank_max), float(ada_tol), int(resketch_every),
                     int(sketch_prec), omega_rows.data_ptr(), pcg or pcg_opts(), int(bool(tol_schedule)),
                     int(max_iter), float(eps_abs), float(eps_rel), float(rel_change_tol),
-                    float(kkt_tol), int(kkt_every), None if factor is None else factor.h.value)
+                    float(kkt_tol), int(kkt_every), None if factor is None else factor.h.value,
+                    None if warm_start is None else warm_start.h.value, int(bool(ws_analytic)),
+                    None if ws_features is None else ws_features.data_ptr(),
+                    None if ws_target is None else ws_target.data_ptr())
 
 
 def problem(A: torch.Tensor, b: torch.Tensor, gamma: float, loss=NYS_LOSS_LS, c: float = 0.0) -> Problem:
@@ -371,3 +392,83 @@ def admm_solve(ctx: Context, probs: Sequence[Problem], opts: Sequence[AdmmOpts],
     for s, cs in zip(states, S):
         s.k = cs.k
     return list(I)
+
+
+def nys_ws_param_count(n_in: int, hidden: int, n_out: int) -> int:
+    return int(lib().nys_ws_param_count(int(n_in), int(hidden), int(n_out)))
+
+
+def _host_f64(a, n, name):
+    if a is None:
+        return None
+    t = torch.as_tensor(a, dtype=torch.float64).contiguous().cpu()
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} values")
+    return t
+
+
+class WarmStart:
+    """Warm-start network on the device (nys_ws_*): n_in -> hidden -> hidden ->
+    n_out with GELU, FP64 parameters W1 b1 W2 b2 W3 b3 (row-major, flat)."""
+
+    def __init__(self, ctx: "Context", n_in: int, hidden: int, n_out: int, params,
+                 in_mean=None, in_std=None, out_scale=None):
+        self.ctx = ctx
+        self.n_in, self.hidden, self.n_out = int(n_in), int(hidden), int(n_out)
+        self.count = nys_ws_param_count(n_in, hidden, n_out)
+        P = _host_f64(params, self.count, "params")
+        mu = _host_f64(in_mean, n_in, "in_mean")
+        sd = _host_f64(in_std, n_in, "in_std")
+        so = _host_f64(out_scale, n_out, "out_scale")
+        dp = lambda t: None if t is None else C.cast(t.data_ptr(), C.POINTER(C.c_double))
+        self.h = C.c_void_p()
+        _check(lib().nys_ws_create(ctx.h, self.n_in, self.hidden, self.n_out, dp(P), dp(mu),
+                                   dp(sd), dp(so), C.byref(self.h)), "nys_ws_create")
+
+    def _rows(self, X, n, name):
+        if X.dtype != torch.float64 or not X.is_cuda or not X.is_contiguous() or X.dim() != 2 \
+                or X.shape[1] != n:
+            raise ValueError(f"{name} must be a contiguous CUDA float64 (batch, {n}) tensor")
+        return X
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(self.count, dtype=torch.float64)
+        _check(lib().nys_ws_get_params(self.ctx.h, self.h,
+                                       C.cast(out.data_ptr(), C.POINTER(C.c_double))),
+               "nys_ws_get_params")
+        return out
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        self._rows(X, self.n_in, "X")
+        out = torch.empty(X.shape[0], self.n_out, dtype=torch.float64, device=X.device)
+        _check(lib().nys_ws_forward(self.ctx.h, self.h, _ptr(X), X.shape[0], _ptr(out)),
+               "nys_ws_forward")
+        self.ctx.synchronize()
+        return out
+
+    def loss_grad(self, X, T, W=None, want_grad=True):
+        self._rows(X, self.n_in, "X")
+        self._rows(T, self.n_out, "T")
+        if W is not None:
+            self._rows(W, self.n_out, "W")
+        loss = C.c_double()
+        g = torch.empty(self.count, dtype=torch.float64, device=X.device) if want_grad else None
+        _check(lib().nys_ws_loss_grad(self.ctx.h, self.h, _ptr(X), _ptr(T), _ptr(W), X.shape[0],
+                                      C.byref(loss), _ptr(g)), "nys_ws_loss_grad")
+        self.ctx.synchronize()
+        return loss.value, g
+
+    def train_step(self, X, T, W=None, lr=1e-3) -> float:
+        self._rows(X, self.n_in, "X")
+        self._rows(T, self.n_out, "T")
+        if W is not None:
+            self._rows(W, self.n_out, "W")
+        loss = C.c_double()
+        _check(lib().nys_ws_train_step(self.ctx.h, self.h, _ptr(X), _ptr(T), _ptr(W), X.shape[0],
+                                       float(lr), C.byref(loss)), "nys_ws_train_step")
+        return loss.value
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            lib().nys_ws_destroy(self.h)
+            self.h = C.c_void_p()

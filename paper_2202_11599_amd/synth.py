@@ -194,3 +194,27 @@ def batched_instances(count: int = 64, seed: int = 0, device="cpu", dtype=torch.
         p.gamma = p.meta["gammas"][0]
         probs.append(p)
     return probs
+
+
+def warmstart_draws(a: torch.Tensor, draws: int, per_draw: int, seed: int,
+                    rho_range=(1e-5, 1e-3), gamma_range=(1e-3, 1e-1), frac=0.02, noise=0.01):
+    """Training/test subproblem families for the learned warm start on one fixed
+    A: `draws` right-hand sides b = A x + noise e (x sparse, each draw its own
+    seed), each paired with `per_draw` (gamma, rho) with gamma log-uniform in
+    gamma_range * ||A^T b||_inf and rho log-uniform in rho_range.
+    Returns a list of (b, gamma, rho); b is FP64 on a's device."""
+    n, d = a.shape
+    dev = a.device
+    a_up = a.to(torch.float64)
+    out = []
+    for k in range(draws):
+        s = seed * 1009 + k
+        x = sparse_truth(d, frac, s, dev)
+        b = a_up @ x + noise * gaussian((n,), s, "noise", dev)
+        gmax = float((a_up.T @ b).abs().max())
+        u = torch.rand(2 * per_draw, generator=_gen(s, "misc", "cpu"), dtype=torch.float64)
+        for j in range(per_draw):
+            lg = math.log(gamma_range[0]) + float(u[2 * j]) * math.log(gamma_range[1] / gamma_range[0])
+            lr = math.log(rho_range[0]) + float(u[2 * j + 1]) * math.log(rho_range[1] / rho_range[0])
+            out.append((b, gmax * math.exp(lg), math.exp(lr)))
+    return out

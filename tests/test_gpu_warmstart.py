@@ -1,0 +1,237 @@
+"""Learned warm start: the device network (nys_ws_*) against the FP64 oracle
+network at equal weights, the candidate/judge inside admm_step, and a small
+end-to-end training run that must lower the PCG work against the previous
+iterate alone.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import admm as ad
+from oracle import mlp as om
+from paper_2202_11599_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2202_11599_amd import nysadmm
+    return nysadmm
+
+
+@pytest.fixture(scope="module")
+def ctx(N):
+    c = N.Context()
+    yield c
+    c.close()
+
+
+def oracle_net(n_in, hidden, n_out, seed):
+    m = om.init_mlp(n_in, hidden, n_out, seed=seed)
+    r = np.random.default_rng(seed + 100)
+    for b in (m.b1, m.b2, m.b3):
+        b[:] = 0.1 * r.standard_normal(b.shape)
+    return m
+
+
+def flat(m):
+    return np.concatenate([p.reshape(-1) for p in m.params()])
+
+
+def make_data(n_in, n_out, batch, seed):
+    r = np.random.default_rng(seed)
+    X = 3.0 + 2.0 * r.standard_normal((batch, n_in))
+    T = r.standard_normal((batch, n_out))
+    W = r.uniform(0.5, 4.0, (batch, n_out))
+    mu = X.mean(0)
+    sd = X.std(0) + 0.1
+    return X, T, W, mu, sd
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+# (n_in, hidden, n_out, batch): a ragged small case and the 130-256-256-128
+# network over a batch that spans several 64-row tiles with a tail
+SHAPES = [(18, 32, 16, 37), (130, 256, 128, 300)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_matches_oracle(N, ctx, shape):
+    ni, h, no, B = shape
+    m = oracle_net(ni, h, no, seed=1)
+    X, T, W, mu, sd = make_data(ni, no, B, seed=2)
+    net = N.WarmStart(ctx, ni, h, no, flat(m), mu, sd)
+    out = net.forward(dev(X)).cpu().numpy()
+    ref, _ = om.forward(m, (X - mu) / sd)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"[ws forward] {shape}: max rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+    net.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_loss_and_gradients_match_oracle(N, ctx, shape):
+    ni, h, no, B = shape
+    m = oracle_net(ni, h, no, seed=3)
+    X, T, W, mu, sd = make_data(ni, no, B, seed=4)
+    net = N.WarmStart(ctx, ni, h, no, flat(m), mu, sd)
+    loss, g = net.loss_grad(dev(X), dev(T), dev(W))
+    L, grads = om.loss_and_grads(m, (X - mu) / sd, T, W)
+    gref = np.concatenate([q.reshape(-1) for q in grads])
+    g = g.cpu().numpy()
+    print(f"[ws grad] {shape}: loss {loss:.6e} vs {L:.6e}, max grad err "
+          f"{np.abs(g - gref).max():.2e} (scale {np.abs(gref).max():.2e})", flush=True)
+    assert abs(loss - L) <= 1e-12 * abs(L)
+    # each parameter block against its own scale
+    off = 0
+    for q in grads:
+        n = q.size
+        blk, ref = g[off:off + n], q.reshape(-1)
+        assert np.abs(blk - ref).max() <= 1e-11 * max(np.abs(ref).max(), 1e-300)
+        off += n
+    # unit weights when W is omitted
+    loss1, _ = net.loss_grad(dev(X), dev(T), None, want_grad=False)
+    assert abs(loss1 - om.loss(m, (X - mu) / sd, T, np.ones_like(T))) <= 1e-12 * loss1
+    net.close()
+
+
+def test_adam_steps_match_oracle(N, ctx):
+    ni, h, no, B = 18, 32, 16, 37
+    m = oracle_net(ni, h, no, seed=5)
+    X, T, W, mu, sd = make_data(ni, no, B, seed=6)
+    net = N.WarmStart(ctx, ni, h, no, flat(m), mu, sd)
+    opt = om.Adam(lr=1e-2)
+    Xn = (X - mu) / sd
+    for _ in range(3):
+        lg = net.train_step(dev(X), dev(T), dev(W), lr=1e-2)
+        L, grads = om.loss_and_grads(m, Xn, T, W)
+        assert abs(lg - L) <= 1e-11 * abs(L)
+        opt.step(m.params(), grads)
+    p = net.params().numpy()
+    assert np.abs(p - flat(m)).max() <= 1e-10
+    net.close()
+
+
+def test_bad_arguments_raise(N, ctx):
+    with pytest.raises(N.NysError):
+        N.WarmStart(ctx, 4, 8, 2, np.zeros(N.nys_ws_param_count(4, 8, 2)), in_std=np.zeros(4))
+    assert N.nys_ws_param_count(0, 8, 2) == 0
+    assert N.nys_ws_param_count(130, 256, 128) == 130 * 256 + 256 + 256 * 256 + 256 + 256 * 128 + 128
+
+
+# ------------------------------------------------------------ inside ADMM
+
+def small_lasso(rank=16, rho=1e-2):
+    p = synth.lasso_decay(4000, 300, 0.8, seed=11, dtype=torch.float32, rho=rho, rank=rank,
+                          s_max=rank, pcg_tol=1e-10)
+    return p
+
+
+def test_analytic_candidate_is_judged_and_solution_unchanged(N, ctx):
+    p = small_lasso()
+    A, b, om_ = p.A.to(DEV), p.b.to(DEV), p.omega.to(DEV)
+    F = N.nys_sketch(ctx, A, om_, prec=N.NYS_F32)
+    its = 12
+    prob = N.problem(A, b, p.gamma)
+    st = N.State(p.d, DEV)
+    used = []
+    for k in range(its):
+        o = N.admm_opts(p.rho, p.rank, om_, pcg=N.pcg_opts(tol=1e-12), ws_analytic=True,
+                        sketch_prec=N.NYS_F32)
+        F, info = N.admm_step(ctx, prob, o, F, st)
+        used.append(info.ws_used)
+    # from x = 0 the analytic start has the smaller residual
+    assert used[0] == 1
+    ora = ad.admm_lasso(p.A.double().numpy(), p.b.numpy(), p.gamma, p.rho,
+                        omega_raw=p.omega.numpy().T, iters=its, pcg_tol=1e-12, mantissa_bits=23)
+    z = st.z.cpu().numpy()
+    print(f"[ws analytic] used {used}, rel z err "
+          f"{np.linalg.norm(z - ora.z) / np.linalg.norm(ora.z):.2e}", flush=True)
+    assert np.linalg.norm(z - ora.z) <= 1e-8 * np.linalg.norm(ora.z)
+    F.close()
+
+
+def test_judge_rejects_a_bad_network_bit_for_bit(N, ctx):
+    p = small_lasso()
+    A, b, om_ = p.A.to(DEV), p.b.to(DEV), p.omega.to(DEV)
+    F = N.nys_sketch(ctx, A, om_, prec=N.NYS_F32)
+    r = F.info()["rank"]
+    cnt = N.nys_ws_param_count(r + 2, 8, r)
+    params = np.zeros(cnt)
+    params[-r:] = 1e6                    # b3: a proposal far from any solution
+    bad = N.WarmStart(ctx, r + 2, 8, r, params)
+    prob = N.problem(A, b, p.gamma)
+    runs = []
+    for model in (None, bad):
+        st = N.State(p.d, DEV)
+        tot_used = 0
+        for k in range(6):
+            o = N.admm_opts(p.rho, p.rank, om_, pcg=N.pcg_opts(tol=1e-6), warm_start=model)
+            _, info = N.admm_step(ctx, prob, o, F, st)
+            tot_used += info.ws_used
+        runs.append((st.z.clone(), st.x.clone(), tot_used))
+    assert runs[1][2] == 0
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    bad.close()
+    F.close()
+
+
+def test_features_and_targets_recorded(N, ctx):
+    p = small_lasso()
+    A, b, om_ = p.A.to(DEV), p.b.to(DEV), p.omega.to(DEV)
+    F = N.nys_sketch(ctx, A, om_, prec=N.NYS_F32)
+    r = F.info()["rank"]
+    U = F.U(ctx).cpu().numpy().T            # d x r
+    f = torch.empty(r + 2, dtype=torch.float64, device=DEV)
+    t = torch.empty(r, dtype=torch.float64, device=DEV)
+    st = N.State(p.d, DEV)
+    prob = N.problem(A, b, p.gamma)
+    for k in range(3):
+        z0, u0 = st.z.cpu().numpy(), st.u.cpu().numpy()
+        o = N.admm_opts(p.rho, p.rank, om_, pcg=N.pcg_opts(tol=1e-8), ws_features=f, ws_target=t)
+        N.admm_step(ctx, prob, o, F, st)
+    Ad = p.A.double().numpy()
+    rhs = p.rho * (z0 - u0) + Ad.T @ p.b.numpy()
+    fe = om.features(U, rhs, p.gamma, p.rho)
+    fg = f.cpu().numpy()
+    assert np.abs(fg - fe).max() <= 1e-9 * np.abs(fe).max()
+    tg = t.cpu().numpy()
+    te = U.T @ st.x.cpu().numpy()
+    assert np.abs(tg - te).max() <= 1e-12 * max(np.abs(te).max(), 1e-300)
+    F.close()
+
+
+def test_training_lowers_pcg_work(N, ctx):
+    # one fixed A; train on recorded solves, test on held-out right-hand sides
+    from paper_2202_11599_amd import warmstart as W
+    p = synth.lasso_decay(6000, 400, 0.8, seed=21, dtype=torch.float32, rank=24, s_max=24)
+    A, om_ = p.A.to(DEV), p.omega.to(DEV)
+    F = N.nys_sketch(ctx, A, om_, prec=N.NYS_F32)
+    lam = F.info()["lam"]
+    train = synth.warmstart_draws(A, 6, 4, seed=1, rho_range=(1e-4, 1e-2))
+    test = synth.warmstart_draws(A, 2, 4, seed=2, rho_range=(1e-4, 1e-2))
+    its = 20
+    X, T = W.record(ctx, A, F, om_, train, its)
+    model, hist = W.fit(ctx, X, T, lam, hidden=64, steps=600, batch=128, lr=2e-3, seed=3,
+                        log_every=100)
+    arms = {a: W.run_arm(ctx, A, F, om_, test, its, a, model=model) for a in
+            ("prev", "mlp", "analytic")}
+    for a, (tot, _) in arms.items():
+        print(f"[ws train] {a}: {tot}", flush=True)
+    print(f"[ws train] loss {hist[0][1]:.3e} -> {hist[-1][1]:.3e}", flush=True)
+    assert hist[-1][1] < 0.2 * hist[0][1]
+    prev, mlp = arms["prev"][0], arms["mlp"][0]
+    assert mlp["ws_used"] >= len(test)            # at least every x = 0 start
+    assert mlp["first_iters"] < prev["first_iters"]
+    assert mlp["pcg_iters"] < prev["pcg_iters"]
+    # same fixed point: the start never changes what PCG converges to
+    for za, zb in zip(arms["prev"][1], arms["mlp"][1]):
+        assert torch.linalg.norm(za - zb) <= 1e-3 * torch.linalg.norm(za)
+    model.close()
+    F.close()
