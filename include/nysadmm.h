@@ -254,7 +254,10 @@ typedef struct {
  * PCG warm-started at x, z = S_{gamma/rho}(x + u), u += x - z, residuals.
  * *F is the factor to precondition with; for the logistic loss it is rebuilt
  * in place when state->k is a multiple of opts->resketch_every (and created
- * if NULL). */
+ * if NULL).  Lasso runs keep A^T b and H_rho x of the last solve on the context
+ * and reuse them in the next step when it has the same data pointers and
+ * state->k advanced by one; a caller that edits A, b or x in place between
+ * steps must start a new run (state->k = 0). */
 nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, nys_factor* F,
                      nys_admm_state* S, nys_admm_info* I);
 
@@ -277,16 +280,18 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
  *   f  = [U^T rhs, log gamma, log rho]            (n_in = rank + 2)
  *   f' = (f - in_mean) / in_std
  *   h1 = gelu(f' W1 + b1), h2 = gelu(h1 W2 + b2), o = h2 W3 + b3   (n_out = rank)
- *   c  = o * out_scale,  x0 = U c,  gelu(a) = a/2 (1 + erf(a / sqrt 2)).
+ *   c  = o * out_scale [+ (Lambda + rho I)^-1 U^T rhs if analytic_skip],
+ *   x0 = U c,  gelu(a) = a/2 (1 + erf(a / sqrt 2)).
  * params_host: W1 (n_in x hidden), b1, W2 (hidden x hidden), b2,
  * W3 (hidden x n_out), b3, row-major, FP64, nys_ws_param_count() values.
- * in_mean/in_std/out_scale may be NULL (0, 1, 1).  All arithmetic is FP64 on
+ * in_mean/in_std/out_scale may be NULL (0, 1, 1); analytic_skip needs
+ * n_in = n_out + 2.  All arithmetic is FP64 on
  * the device.  Training data: the loss is (1/B) sum_ik W_ik (o_ik - T_ik)^2
  * with T the targets already divided by out_scale; X rows are raw features. */
 size_t nys_ws_param_count(int n_in, int hidden, int n_out);
 nys_status nys_ws_create(nys_ctx ctx, int n_in, int hidden, int n_out, const double* params_host,
                          const double* in_mean, const double* in_std, const double* out_scale,
-                         nys_ws_model* out);
+                         int analytic_skip, nys_ws_model* out);
 nys_status nys_ws_get_params(nys_ctx ctx, nys_ws_model m, double* params_host);
 /* out (device, batch x n_out) = o for the batch x n_in device rows X */
 nys_status nys_ws_forward(nys_ctx ctx, nys_ws_model m, const double* X, int batch, double* out);

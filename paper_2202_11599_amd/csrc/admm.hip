@@ -230,11 +230,14 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
   hipStream_t st = ctx->stream;
   const double* D = nullptr;
   if (P.loss == NYS_LOSS_LS) {
+    // A^T b is recomputed at the first step of a run (k = 0) and whenever the
+    // previous step was on other data, so b may change between runs
     AtbKey key{A.data, P.b, A.n, d, A.ld, ctx->admm_ws.ptr};
-    if (!(ctx->atb_key == key)) {
+    if (!(S->k > 0 && ctx->atb_key == key && ctx->atb_next_k == S->k)) {
       NYS_TRY(gram_pass(ctx, A, kModeTOnly, nullptr, P.b, nullptr, w.atb, w, false));
       ctx->atb_key = key;
     }
+    ctx->atb_next_k = (int64_t)S->k + 1;
     hipLaunchKernelGGL(k_rhs, dim3(blocks(d)), dim3(256), 0, st, d, O.rho, S->z, S->u, w.atb,
                        w.rhs);
   } else {
@@ -271,9 +274,10 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
     NYS_TRY(ws_record(ctx, *F, w.rhs, P.gamma, O.rho, nullptr, O.ws_features, nullptr, w.wss));
   nys_pcg_info pinfo{};
   int used_alt = 0;
-  // lasso: x is only changed by PCG, so H_rho x carries over between solves
+  // lasso: within a run x is only changed by PCG, so H_rho x carries over
+  // from one step's solve to the next (tagged with the step counter)
   nys_status ps = pcg_run(ctx, A, D, P.c, O.rho, *F, w.rhs, S->x, po, &pinfo, abs_tol,
-                          P.loss == NYS_LOSS_LS, x_alt, &used_alt);
+                          P.loss == NYS_LOSS_LS ? (int64_t)S->k : -1, x_alt, &used_alt);
   if (*F != nullptr && O.ws_target != nullptr && (ps == NYS_OK || ps == NYS_ERR_MAXITER))
     NYS_TRY(ws_record(ctx, *F, nullptr, P.gamma, O.rho, S->x, nullptr, O.ws_target, w.wss));
   if (ps != NYS_OK && ps != NYS_ERR_MAXITER) {

@@ -189,7 +189,7 @@ nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out) {
 // Algorithm Nystrom PCG (see pcg_solve in nysadmm.h).
 nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
                    nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
-                   nys_pcg_info* info, double abs_tol, bool reuse_hx, const double* x_alt,
+                   nys_pcg_info* info, double abs_tol, int64_t hx_tag, const double* x_alt,
                    int* used_alt) {
   if (used_alt) *used_alt = 0;
   const double tol_rel = o.tol_abs ? 0.0 : o.tol;
@@ -220,7 +220,8 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
     NYS_TRY_HIP(hipMemsetAsync(ws.st, 0, sizeof(PcgDev), st));
     // w0 = rhs - H_rho x0 ; y0 = P^-1 w0 ; p0 = y0
     const AtbKey key{A.data, D, A.n, d, A.ld, x};
-    if (reuse_hx && restarts == 0 && ctx->hx_key == key && ctx->hx_rho == rho && ctx->hx_c == c) {
+    if (hx_tag >= 0 && restarts == 0 && ctx->hx_tag == hx_tag && ctx->hx_key == key &&
+        ctx->hx_rho == rho && ctx->hx_c == c) {
       // H_rho x0 from the previous solve's true-residual pass (x0 unchanged)
       NYS_TRY(launch_reduce_update(1, ws.ypart, 0, pl.ldy, ws.qpart, d, 1.0, ctx->hx.as<double>(),
                                    nullptr, ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, ws.rrpart,
@@ -312,17 +313,18 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
     if (!o.true_residual) break;
     // true residual rhs - H_rho x with FP64 accumulation (H_rho x kept when asked)
     double* hx_out = nullptr;
-    if (reuse_hx) {
+    if (hx_tag >= 0) {
       NYS_TRY(ctx->hx.reserve(sizeof(double) * d));
       hx_out = ctx->hx.as<double>();
     }
     NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr));
     NYS_TRY(launch_reduce_update(2, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x, hx_out,
                                  ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, nullptr, ws.st, st));
-    if (reuse_hx) {
+    if (hx_tag >= 0) {
       ctx->hx_key = key;
       ctx->hx_rho = rho;
       ctx->hx_c = c;
+      ctx->hx_tag = hx_tag + 1;
     }
     NYS_TRY(launch_precond_dot(U, u32, d, 0, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred, nullptr,
                                0, 3, 0.0, 0, st));

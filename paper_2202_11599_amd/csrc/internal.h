@@ -132,14 +132,15 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
                       int max_sweeps, void* host_pinned, double* sig2, double* W, int ldw,
                       int* sweeps_out);
 // Stop when ||w|| <= max(abs_tol, tol ||rhs||) (o.tol_abs: ||w|| <= o.tol).
-// reuse_hx: the caller guarantees x is unchanged since the previous pcg_run on
-// the same (A, D, c, rho); H_rho x saved by that run's true-residual pass then
-// gives w0 without a pass over A, and this run saves its own for the next.
+// hx_tag >= 0: H_rho x saved by the previous run's true-residual pass gives w0
+// without a pass over A when that run had the same (A, D, x pointer, c, rho)
+// and was called with hx_tag - 1 (the ADMM iteration counter of one state, so
+// a new or rewound state never matches); this run saves its own with hx_tag.
 // x_alt: a candidate start; PCG starts from whichever of x and x_alt has the
 // smaller residual (x is overwritten by x_alt if it wins, *used_alt = 1).
 nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
                    nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
-                   nys_pcg_info* info, double abs_tol = 0.0, bool reuse_hx = false,
+                   nys_pcg_info* info, double abs_tol = 0.0, int64_t hx_tag = -1,
                    const double* x_alt = nullptr, int* used_alt = nullptr);
 
 // ---- mlp.hip
@@ -174,9 +175,11 @@ struct nys_ctx_s {
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
   void* host_pinned = nullptr;  // small pinned readback area
   AtbKey atb_key;                // which (A, b) the cached A^T b in admm_ws belongs to
+  int64_t atb_next_k = -1;       // ... valid for the ADMM step with this counter
   nys::DevBuf hx;                // H_rho x of the last solve (lasso ADMM sequence)
   AtbKey hx_key;                 // (A, x) it belongs to; buf = x pointer
   double hx_rho = -1.0, hx_c = -1.0;
+  int64_t hx_tag = -1;           // tag of the pcg_run that may use it
   std::map<std::string, nys::GramPlan> plans;   // autotuned launch shapes per matrix shape
   std::map<std::string, std::vector<int>> bplans;  // autotuned batched shapes per batch
   hipStream_t cap_stream = nullptr;              // graph-capture stream (batched path)

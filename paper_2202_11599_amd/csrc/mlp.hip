@@ -3,7 +3,9 @@
 //   f  = [U^T rhs, log gamma, log rho]           (features, n_in = r + 2)
 //   f' = (f - mu) / sigma                          (standardisation, stored in the model)
 //   h1 = gelu(f' W1 + b1), h2 = gelu(h1 W2 + b2), o = h2 W3 + b3
-//   c  = o * s_out,  x0 = U c                      (Nystrom basis)
+//   c  = o * s_out [+ (Lambda + rho I)^-1 U^T rhs], x0 = U c   (Nystrom basis)
+// With the optional analytic skip the network learns the correction to the
+// start that is exact on span(U) for exact eigenvectors.
 // gelu(a) = a/2 (1 + erf(a/sqrt 2)).  Training minimises the weighted squared
 // error (1/B) sum w_ik (o_ik - t_ik)^2 on standardised targets t = c* / s_out
 // with Adam (bias-corrected).  Everything is FP64 on the GPU: the matrix
@@ -126,11 +128,15 @@ __global__ void k_shift_div(const double* __restrict__ u, const double* __restri
   if (i < r) c[i] = u[i] / (lam[i] + rho);
 }
 
-// c = o * s_out
+// c = o * s_out (+ u / (lambda + rho) when the analytic skip is on)
 __global__ void k_scale(const double* __restrict__ o, const double* __restrict__ s, int n,
+                        const double* __restrict__ u, const double* __restrict__ lam, double rho,
                         double* __restrict__ c) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) c[i] = o[i] * s[i];
+  if (i >= n) return;
+  double v = o[i] * s[i];
+  if (u != nullptr) v += u[i] / (lam[i] + rho);
+  c[i] = v;
 }
 
 }  // namespace
@@ -139,6 +145,7 @@ __global__ void k_scale(const double* __restrict__ o, const double* __restrict__
 struct nys_ws_model_s {
   int n_in = 0, hidden = 0, n_out = 0;
   int device = 0;
+  int skip = 0;               // c = analytic coefficients + network output
   long t = 0;                 // Adam step count
   nys::DevBuf params;         // W1 b1 W2 b2 W3 b3 (row-major), then mu, sigma, s_out
   nys::DevBuf adam;           // m, v
@@ -254,7 +261,8 @@ nys_status ws_backward(nys_ctx ctx, nys_ws_model m, const double* Tg, const doub
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
-// x0 = U c with c = s_out * MLP((f - mu)/sigma), f = [U^T rhs, log gamma, log rho].
+// x0 = U c with c = s_out * MLP((f - mu)/sigma) [+ (Lambda + rho I)^-1 U^T rhs],
+// f = [U^T rhs, log gamma, log rho].
 // scratch: >= 2 r + 2 + n_out doubles (device).
 nys_status ws_propose(nys_ctx ctx, nys_ws_model m, nys_factor F, const double* rhs, double gamma,
                       double rho, double* x0, double* scratch, double* feat_out) {
@@ -276,7 +284,8 @@ nys_status ws_propose(nys_ctx ctx, nys_ws_model m, nys_factor F, const double* r
   NYS_TRY(ws_act(m, 1, &a));
   NYS_TRY(ws_forward(ctx, m, f, 1, &a));
   WsPtrs p = ws_ptrs(m, m->params.as<double>());
-  hipLaunchKernelGGL(k_scale, dim3(blocks(r)), dim3(256), 0, st, a.O, p.sout, r, c);
+  hipLaunchKernelGGL(k_scale, dim3(blocks(r)), dim3(256), 0, st, a.O, p.sout, r,
+                     m->skip ? cU : nullptr, F->lam.as<double>(), rho, c);
   NYS_TRY(gemm64(st, (int)F->d, 1, r, U, false, 1, F->d, c, false, 1, 1, x0, 1, 1, 1.0, 0.0,
                  nullptr, 0));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
@@ -330,9 +339,10 @@ size_t nys_ws_param_count(int n_in, int hidden, int n_out) {
 
 nys_status nys_ws_create(nys_ctx ctx, int n_in, int hidden, int n_out, const double* params_host,
                          const double* in_mean, const double* in_std, const double* out_scale,
-                         nys_ws_model* out) {
+                         int analytic_skip, nys_ws_model* out) {
   if (ctx == nullptr || out == nullptr || params_host == nullptr) return NYS_ERR_INVALID;
   if (n_in < 1 || hidden < 1 || n_out < 1 || hidden > 4096) return NYS_ERR_INVALID;
+  if (analytic_skip != 0 && n_in != n_out + 2) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
   nys_ws_model m = new (std::nothrow) nys_ws_model_s();
   if (m == nullptr) return NYS_ERR_NOMEM;
@@ -340,6 +350,7 @@ nys_status nys_ws_create(nys_ctx ctx, int n_in, int hidden, int n_out, const dou
   m->hidden = hidden;
   m->n_out = n_out;
   m->device = ctx->device;
+  m->skip = analytic_skip != 0;
   const size_t np = ws_count(n_in, hidden, n_out);
   const size_t tot = np + 2 * (size_t)n_in + n_out;
   std::vector<double> h(tot);

@@ -113,7 +113,7 @@ def lib():
         "admm_step": (i32, [vp, P(Problem), P(AdmmOpts), P(vp), P(AdmmState), P(AdmmInfo)]),
         "admm_solve": (i32, [vp, i32, P(Problem), P(AdmmOpts), P(AdmmState), P(AdmmInfo)]),
         "nys_ws_param_count": (C.c_size_t, [i32, i32, i32]),
-        "nys_ws_create": (i32, [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl), P(dbl), P(vp)]),
+        "nys_ws_create": (i32, [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl), P(dbl), i32, P(vp)]),
         "nys_ws_get_params": (i32, [vp, vp, P(dbl)]),
         "nys_ws_forward": (i32, [vp, vp, vp, i32, vp]),
         "nys_ws_loss_grad": (i32, [vp, vp, vp, vp, vp, i32, P(dbl), vp]),
@@ -409,21 +409,25 @@ def _host_f64(a, n, name):
 
 class WarmStart:
     """Warm-start network on the device (nys_ws_*): n_in -> hidden -> hidden ->
-    n_out with GELU, FP64 parameters W1 b1 W2 b2 W3 b3 (row-major, flat)."""
+    n_out with GELU, FP64 parameters W1 b1 W2 b2 W3 b3 (row-major, flat).
+    analytic_skip: the proposal is the analytic coefficients plus the output."""
 
     def __init__(self, ctx: "Context", n_in: int, hidden: int, n_out: int, params,
-                 in_mean=None, in_std=None, out_scale=None):
+                 in_mean=None, in_std=None, out_scale=None, analytic_skip=False):
         self.ctx = ctx
         self.n_in, self.hidden, self.n_out = int(n_in), int(hidden), int(n_out)
         self.count = nys_ws_param_count(n_in, hidden, n_out)
+        self.analytic_skip = bool(analytic_skip)
         P = _host_f64(params, self.count, "params")
         mu = _host_f64(in_mean, n_in, "in_mean")
         sd = _host_f64(in_std, n_in, "in_std")
         so = _host_f64(out_scale, n_out, "out_scale")
+        self.out_scale = so if so is not None else torch.ones(n_out, dtype=torch.float64)
         dp = lambda t: None if t is None else C.cast(t.data_ptr(), C.POINTER(C.c_double))
         self.h = C.c_void_p()
         _check(lib().nys_ws_create(ctx.h, self.n_in, self.hidden, self.n_out, dp(P), dp(mu),
-                                   dp(sd), dp(so), C.byref(self.h)), "nys_ws_create")
+                                   dp(sd), dp(so), int(bool(analytic_skip)), C.byref(self.h)),
+               "nys_ws_create")
 
     def _rows(self, X, n, name):
         if X.dtype != torch.float64 or not X.is_cuda or not X.is_contiguous() or X.dim() != 2 \

@@ -62,19 +62,27 @@ def init_params(n_in: int, hidden: int, n_out: int, seed: int) -> torch.Tensor:
 
 def fit(ctx: N.Context, X: torch.Tensor, T: torch.Tensor, lam: Sequence[float],
         hidden: int = 256, steps: int = 2000, batch: int = 256, lr: float = 1e-3,
-        seed: int = 0, log_every: int = 0):
-    """Train a warm-start network on (X, T); returns (model, loss history)."""
+        seed: int = 0, log_every: int = 0, analytic_skip: bool = True):
+    """Train a warm-start network on (X, T); returns (model, loss history).
+    analytic_skip: the network learns c* - (Lambda + rho I)^-1 U^T rhs."""
     n_in, n_out = X.shape[1], T.shape[1]
+    lam_t = torch.as_tensor(list(lam), dtype=torch.float64, device=X.device)
+    rho = torch.exp(X[:, -1])
+    if analytic_skip:
+        T = T - X[:, :n_out] / (lam_t[None, :] + rho[:, None])
     mu = X.mean(0)
     sd = X.std(0).clamp_min(1e-12)
     s_out = T.std(0).clamp_min(1e-30)
     Tn = (T / s_out).contiguous()
-    lam_t = torch.as_tensor(list(lam), dtype=torch.float64, device=X.device)
-    rho = torch.exp(X[:, -1])
     W = (lam_t[None, :] + rho[:, None]) / rho[:, None] * (s_out[None, :] ** 2)
     W = (W / W.mean()).contiguous()
-    model = N.WarmStart(ctx, n_in, hidden, n_out, init_params(n_in, hidden, n_out, seed),
-                        mu.cpu(), sd.cpu(), s_out.cpu())
+    params = init_params(n_in, hidden, n_out, seed)
+    if analytic_skip:
+        # start close to the analytic proposal: small last layer
+        w3 = n_in * hidden + hidden + hidden * hidden + hidden
+        params[w3:w3 + hidden * n_out] *= 0.01
+    model = N.WarmStart(ctx, n_in, hidden, n_out, params, mu.cpu(), sd.cpu(), s_out.cpu(),
+                        analytic_skip=analytic_skip)
     g = torch.Generator().manual_seed(seed + 1)
     m = X.shape[0]
     hist = []
@@ -91,6 +99,33 @@ def fit(ctx: N.Context, X: torch.Tensor, T: torch.Tensor, lam: Sequence[float],
         if log_every and (k % log_every == 0 or k == steps - 1):
             hist.append((k, loss))
     return model, hist
+
+
+def proposals(model, X: torch.Tensor, lam: Sequence[float]) -> torch.Tensor:
+    """Coefficients c the model proposes for feature rows X (as in admm_step)."""
+    r = model.n_out
+    o = model.forward(X.contiguous()) * model.out_scale.to(X.device)
+    if model.analytic_skip:
+        lam_t = torch.as_tensor(list(lam), dtype=torch.float64, device=X.device)
+        o = o + X[:, :r] / (lam_t[None, :] + torch.exp(X[:, -1])[:, None])
+    return o
+
+
+def analytic(X: torch.Tensor, lam: Sequence[float]) -> torch.Tensor:
+    """(Lambda + rho I)^-1 U^T rhs for feature rows X."""
+    r = X.shape[1] - 2
+    lam_t = torch.as_tensor(list(lam), dtype=torch.float64, device=X.device)
+    return X[:, :r] / (lam_t[None, :] + torch.exp(X[:, -1])[:, None])
+
+
+def energy_error(C: torch.Tensor, X: torch.Tensor, T: torch.Tensor, lam: Sequence[float]) -> float:
+    """Mean over rows of sum_k (lambda_k + rho)(c_k - c*_k)^2 / sum_k (lambda_k + rho) c*_k^2:
+    the relative error of x0 = U c in the norm of H + rho I restricted to span(U)."""
+    lam_t = torch.as_tensor(list(lam), dtype=torch.float64, device=X.device)
+    w = lam_t[None, :] + torch.exp(X[:, -1])[:, None]
+    num = (w * (C - T) ** 2).sum(1)
+    den = (w * T ** 2).sum(1).clamp_min(1e-300)
+    return float((num / den).mean())
 
 
 def run_arm(ctx: N.Context, A: torch.Tensor, F: N.Factor, omega: torch.Tensor,

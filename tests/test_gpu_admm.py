@@ -202,3 +202,32 @@ def test_admm_invalid_arguments(N, ctx):
     o = N.admm_opts(0.3, 400, p.omega.to(DEV))   # rank >= d
     with pytest.raises(N.NysError):
         N.admm_solve(ctx, [prob], [o], [st])
+
+
+def test_step_caches_do_not_leak_between_runs(N, ctx):
+    # A^T b and H_rho x are kept on the context between admm_step calls of one
+    # run.  A new run (k = 0) on a b edited in place, and on a state whose
+    # buffers may reuse the previous run's addresses, must give exactly what a
+    # fresh context gives.
+    p = small_lasso(seed=5)
+    A = p.A.to(DEV)
+    b = p.b.to(DEV).clone()
+    om_ = p.omega.to(DEV)
+    F = N.nys_sketch(ctx, A, om_, prec=N.NYS_F64)
+    o = N.admm_opts(p.rho, p.rank, om_, pcg=N.pcg_opts(tol=1e-8))
+
+    def run(c, bvec, steps=5):
+        st = N.State(p.d, DEV)
+        prob = N.problem(A, bvec, p.gamma)
+        for _ in range(steps):
+            N.admm_step(c, prob, o, F, st)
+        return st.z.clone(), st.x.clone()
+
+    run(ctx, b)
+    b.mul_(0.5)                            # same pointer, new data
+    z1, x1 = run(ctx, b)
+    fresh = N.Context()
+    z2, x2 = run(fresh, b)
+    fresh.close()
+    assert torch.equal(z1, z2) and torch.equal(x1, x2)
+    F.close()
