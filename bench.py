@@ -46,9 +46,12 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
-    ap.add_argument("--workload", choices=["lasso", "logistic", "path"], default="lasso",
+    ap.add_argument("--workload", choices=["lasso", "logistic", "path", "learned"],
+                    default="lasso",
                     help="lasso: 100000x4000 adaptive rank (default line); logistic: 200000x2000 "
-                         "l1-logistic; path: 64 uneven lasso instances x 16 gammas, batched")
+                         "l1-logistic; path: 64 uneven lasso instances x 16 gammas, batched; "
+                         "learned: warm-start network trained on 20000 recorded solves, "
+                         "100000x4000 at rank 128, arms compared on held-out right-hand sides")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--gammas", type=int, default=16)
     ap.add_argument("--copy-reference", action="store_true",
@@ -252,6 +255,77 @@ def bench_path(args, N, synth, torch):
     return out
 
 
+def bench_learned(args, N, synth, torch):
+    """Learned warm start on the 100000 x 4000 generator at rank 128: record
+    20000 subproblem solves (200 right-hand sides x 4 (gamma, rho) pairs x 25
+    ADMM steps), train the 130-256-256-128 network on the GPU, then solve
+    held-out right-hand sides (20 x 2 pairs) with each start rule at
+    tolerance 1e-6."""
+    from paper_2202_11599_amd import warmstart as W
+    n, d, r, its = 100000, 4000, 128, 25
+    t0 = time.perf_counter()
+    p = synth.lasso_decay(n, d, 0.8, seed=0, device="cuda", dtype=torch.float32, rank=r, s_max=r)
+    A, omega = p.A, p.omega.contiguous()
+    ctx = N.Context()
+    F = N.nys_sketch(ctx, A, omega, prec=N.NYS_F32)
+    lam = F.info()["lam"]
+    train = synth.warmstart_draws(A, 200, 4, seed=1)
+    test = synth.warmstart_draws(A, 20, 2, seed=2)
+    torch.cuda.synchronize()
+    print(f"[bench] learned: data in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    parts = []
+    for k in range(0, len(train), 100):
+        parts.append(W.record(ctx, A, F, omega, train[k:k + 100], its))
+        print(f"[bench] learned: recorded {(k + 100) * its} solves, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    X = torch.cat([q[0] for q in parts])
+    T = torch.cat([q[1] for q in parts])
+    del parts
+    rec_s = time.perf_counter() - t0
+    Xt, Tt = W.record(ctx, A, F, omega, test, its)
+    print(f"[bench] learned: recorded {X.shape[0]} solves in {rec_s:.1f} s", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    model, hist = W.fit(ctx, X, T, lam, hidden=256, steps=3000, batch=256, lr=1e-3, seed=3,
+                        log_every=500)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    print(f"[bench] learned: trained in {train_s:.1f} s, loss {hist[0][1]:.3e} -> "
+          f"{hist[-1][1]:.3e}", file=sys.stderr, flush=True)
+    errs = {"analytic": W.energy_error(W.analytic(Xt, lam), Xt, Tt, lam),
+            "network": W.energy_error(W.proposals(model, Xt, lam), Xt, Tt, lam),
+            "network_train": W.energy_error(W.proposals(model, X, lam), X, T, lam)}
+    idx0 = torch.arange(0, Xt.shape[0], its, device=Xt.device)   # first step of each run
+    X0, T0 = Xt[idx0].contiguous(), Tt[idx0].contiguous()
+    errs["network_cold"] = W.energy_error(W.proposals(model, X0, lam), X0, T0, lam)
+    errs["analytic_cold"] = W.energy_error(W.analytic(X0, lam), X0, T0, lam)
+    W.run_arm(ctx, A, F, omega, test[:2], its, "mlp", model=model)   # warm the paths
+    arms = {}
+    for arm in ("prev", "mlp", "analytic", "mlp_every_step"):
+        tot, _ = W.run_arm(ctx, A, F, omega, test, its, arm.replace("_every_step", ""),
+                           model=model, every_step=arm.endswith("every_step"))
+        arms[arm] = {"solves_per_s": round(tot["solves"] / tot["seconds"], 3),
+                     "pcg_iters_mean": round(tot["pcg_iters"] / tot["solves"], 3),
+                     "cold_start_pcg_iters_mean": round(tot["first_iters"] / len(test), 3),
+                     "candidate_used": tot["ws_used"], "solves": tot["solves"]}
+        print(f"[bench] learned arm {arm}: {arms[arm]}", file=sys.stderr, flush=True)
+    wall = sum(a["solves"] / a["solves_per_s"] for a in arms.values() if a["solves_per_s"] > 0)
+    out = base_record(arms["mlp"]["solves_per_s"], 1, 1, wall, "f32", {
+        "workload": "lasso-100000x4000-fp32-sigma_j=j^-0.8-rank128-learned-warm-start",
+        "n": n, "d": d, "rank": r, "pcg_tol": 1e-6, "train_solves": int(X.shape[0]),
+        "test_solves_per_arm": len(test) * its, "network": "130-256-256-128 GELU, analytic skip"})
+    out["arms"] = arms
+    out["mlp_vs_prev"] = round(arms["mlp"]["solves_per_s"] / arms["prev"]["solves_per_s"], 4)
+    out["heldout_energy_error"] = {k: float(f"{v:.4e}") for k, v in errs.items()}
+    out["record_s"] = round(rec_s, 2)
+    out["train_s"] = round(train_s, 2)
+    out["loss_first_last"] = [hist[0][1], hist[-1][1]]
+    model.close()
+    F.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -264,7 +338,8 @@ def main():
         from paper_2202_11599_amd import nysadmm as N
         from paper_2202_11599_amd import synth
         torch.cuda.set_device(0)
-        fn = bench_logistic if args.workload == "logistic" else bench_path
+        fn = {"logistic": bench_logistic, "path": bench_path,
+              "learned": bench_learned}[args.workload]
         print(json.dumps(fn(args, N, synth, torch)), flush=True)
         return
     from paper_2202_11599_amd import nysadmm as N

@@ -221,8 +221,11 @@ typedef struct {
   nys_ws_model warm_start; /* optional warm-start network: each subproblem also gets the
                             candidate start x0 = U c, c = net([U^T rhs, log gamma, log rho]);
                             PCG starts from whichever of x0 and the previous x has the smaller
-                            residual (one extra pass over A); NULL: previous x only */
+                            residual (one extra pass over A, decided on the device);
+                            NULL: previous x only */
   int ws_analytic;       /* 1: the candidate is x0 = U (Lambda + rho I)^-1 U^T rhs instead */
+  int ws_every_step;     /* 0: propose only at the first step of a run (state k = 0, where
+                            the previous iterate is the cold start x); 1: at every step */
   double* ws_features;   /* optional device (rank + 2): features of the step's subproblem */
   double* ws_target;     /* optional device (rank): U^T x of the step's solution */
 } nys_admm_opts;

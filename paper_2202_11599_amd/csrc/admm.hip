@@ -262,7 +262,8 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
   }
   // warm-start candidate (network or analytic) next to the previous iterate
   const double* x_alt = nullptr;
-  if (*F != nullptr && (O.warm_start != nullptr || O.ws_analytic)) {
+  const bool propose = O.ws_every_step != 0 || S->k == 0;
+  if (*F != nullptr && (O.warm_start != nullptr || O.ws_analytic) && propose) {
     if (O.warm_start != nullptr)
       NYS_TRY(ws_propose(ctx, O.warm_start, *F, w.rhs, P.gamma, O.rho, w.xalt, w.wss,
                          O.ws_features));
@@ -270,7 +271,7 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
       NYS_TRY(ws_analytic(ctx, *F, w.rhs, O.rho, w.xalt, w.wss));
     x_alt = w.xalt;
   }
-  if (*F != nullptr && O.ws_features != nullptr && O.warm_start == nullptr)
+  if (*F != nullptr && O.ws_features != nullptr && (O.warm_start == nullptr || !propose))
     NYS_TRY(ws_record(ctx, *F, w.rhs, P.gamma, O.rho, nullptr, O.ws_features, nullptr, w.wss));
   nys_pcg_info pinfo{};
   int used_alt = 0;

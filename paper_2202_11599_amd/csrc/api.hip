@@ -234,28 +234,13 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
     }
     ctx->hx_key = AtbKey{};
     if (x_alt != nullptr && restarts == 0) {
-      // judge: residual of the candidate start next to that of x
+      // judge: residual of the candidate start next to that of x, decided on
+      // the device (the smaller ||w|| wins; ties keep x)
       NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, x_alt, D, nullptr, ws.ypart, ws.qpart, nullptr));
       NYS_TRY(launch_reduce_update(1, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x_alt,
                                    nullptr, ws.w2, rhs, ws.wy, 0, nullptr, 0, ws.wwpart2,
                                    ws.rrpart2, ws.st, st));
-      double ww_x = 0.0, ww_alt = 0.0;
-      NYS_TRY(launch_precond_dot(U, u32, d, 0, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred, nullptr,
-                                 0, 3, 0.0, 0, st));
-      NYS_TRY(read_pcg_state(ctx, ws, &h));
-      ww_x = h.true_rr;
-      NYS_TRY(launch_precond_dot(U, u32, d, 0, ws.w2, ws.cvec, ws.st, ws.wwpart2, ws.nred, nullptr,
-                                 0, 3, 0.0, 0, st));
-      NYS_TRY(read_pcg_state(ctx, ws, &h));
-      ww_alt = h.true_rr;
-      if (ww_alt < ww_x) {
-        NYS_TRY_HIP(hipMemcpyAsync(x, x_alt, sizeof(double) * d, hipMemcpyDeviceToDevice, st));
-        std::swap(ws.w, ws.w2);
-        std::swap(ws.wwpart, ws.wwpart2);
-        std::swap(ws.rrpart, ws.rrpart2);
-        if (used_alt) *used_alt = 1;
-      }
-      NYS_TRY_HIP(hipMemsetAsync(ws.st, 0, sizeof(PcgDev), st));
+      NYS_TRY(launch_judge(ws.wwpart, ws.wwpart2, ws.nred, x, x_alt, ws.w, ws.w2, d, ws.st, st));
     }
     NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred,
                                ws.rrpart, -1, 1, tol_rel, tol_abs, st));
@@ -292,6 +277,7 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
       }
       it += chunk;
     }
+    if (restarts == 0 && used_alt) *used_alt = (h.flags & kFlagAltStart) ? 1 : 0;
     total_iters += h.done ? h.iters : it;
     // launches enqueued after convergence return at once; not counted as work
     if (ctx->prof_on && h.done && it > h.iters) ctx->prof_skipped += it - h.iters;

@@ -55,6 +55,7 @@ struct PcgDev {
 constexpr int kFlagBreakdown = 1;
 constexpr int kFlagNonfinite = 2;
 constexpr int kFlagZeroRhs = 4;
+constexpr int kFlagAltStart = 8;   // the candidate start won the judge
 
 // Launch geometry of the fused Gram matvec for one matrix shape.
 struct GramPlan {
@@ -234,6 +235,17 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
                                 hipStream_t stream);
 // *out = a^T b (one workgroup, fixed order)
+// Judge of two PCG starts: ||w||^2 from wwpart and from wwpart2 (same fixed
+// summation order); if the second is smaller, x <- x_alt, w <- w2,
+// wwpart <- wwpart2 and st->flags |= kFlagAltStart.  No host synchronisation.
+nys_status launch_judge(double* wwpart, const double* wwpart2, int nred, double* x,
+                        const double* x_alt, double* w, const double* w2, int64_t d, PcgDev* st,
+                        hipStream_t stream);
+// out = U^T v (FP64 U, d x r column-major), out2 (optional) = U c for c (r)
+nys_status launch_ut_v(const double* U, int64_t d, int r, const double* v, double* out,
+                       hipStream_t stream);
+nys_status launch_u_c(const double* U, int64_t d, int r, const double* c, double* out,
+                      hipStream_t stream);
 nys_status launch_dot(const double* a, const double* b, int64_t d, double* out,
                       hipStream_t stream);
 // mode 0: PCG iteration k test + dots, 1: PCG init (threshold from ||rhs||) test + dots,

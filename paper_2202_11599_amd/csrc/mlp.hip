@@ -273,9 +273,7 @@ nys_status ws_propose(nys_ctx ctx, nys_ws_model m, nys_factor F, const double* r
   double* f = scratch + r;               // features (r + 2)
   double* c = f + r + 2;                 // coefficients (r)
   const double* U = F->U.as<double>();
-  // U^T rhs (FP64 U; r x d GEMV through the tiled GEMM)
-  NYS_TRY(gemm64(st, r, 1, (int)F->d, U, false, F->d, 1, rhs, false, 1, 1, cU, 1, 1, 1.0, 0.0,
-                 nullptr, 0));
+  NYS_TRY(launch_ut_v(U, F->d, r, rhs, cU, st));
   hipLaunchKernelGGL(k_features, dim3(blocks(r + 2)), dim3(256), 0, st, cU, r, std::log(gamma),
                      std::log(rho), f);
   if (feat_out != nullptr)
@@ -286,8 +284,7 @@ nys_status ws_propose(nys_ctx ctx, nys_ws_model m, nys_factor F, const double* r
   WsPtrs p = ws_ptrs(m, m->params.as<double>());
   hipLaunchKernelGGL(k_scale, dim3(blocks(r)), dim3(256), 0, st, a.O, p.sout, r,
                      m->skip ? cU : nullptr, F->lam.as<double>(), rho, c);
-  NYS_TRY(gemm64(st, (int)F->d, 1, r, U, false, 1, F->d, c, false, 1, 1, x0, 1, 1, 1.0, 0.0,
-                 nullptr, 0));
+  NYS_TRY(launch_u_c(U, F->d, r, c, x0, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
@@ -299,12 +296,10 @@ nys_status ws_analytic(nys_ctx ctx, nys_factor F, const double* rhs, double rho,
   hipStream_t st = ctx->stream;
   const int r = F->r;
   const double* U = F->U.as<double>();
-  NYS_TRY(gemm64(st, r, 1, (int)F->d, U, false, F->d, 1, rhs, false, 1, 1, scratch, 1, 1, 1.0,
-                 0.0, nullptr, 0));
+  NYS_TRY(launch_ut_v(U, F->d, r, rhs, scratch, st));
   hipLaunchKernelGGL(k_shift_div, dim3(blocks(r)), dim3(256), 0, st, scratch, F->lam.as<double>(),
                      r, rho, scratch + r);
-  NYS_TRY(gemm64(st, (int)F->d, 1, r, U, false, 1, F->d, scratch + r, false, 1, 1, x0, 1, 1, 1.0,
-                 0.0, nullptr, 0));
+  NYS_TRY(launch_u_c(U, F->d, r, scratch + r, x0, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
@@ -315,14 +310,11 @@ nys_status ws_record(nys_ctx ctx, nys_factor F, const double* rhs, double gamma,
   const int r = F->r;
   const double* U = F->U.as<double>();
   if (feat_out != nullptr) {
-    NYS_TRY(gemm64(st, r, 1, (int)F->d, U, false, F->d, 1, rhs, false, 1, 1, scratch, 1, 1, 1.0,
-                   0.0, nullptr, 0));
+    NYS_TRY(launch_ut_v(U, F->d, r, rhs, scratch, st));
     hipLaunchKernelGGL(k_features, dim3(blocks(r + 2)), dim3(256), 0, st, scratch, r,
                        std::log(gamma), std::log(rho), feat_out);
   }
-  if (target_out != nullptr)
-    NYS_TRY(gemm64(st, r, 1, (int)F->d, U, false, F->d, 1, x, false, 1, 1, target_out, 1, 1, 1.0,
-                   0.0, nullptr, 0));
+  if (target_out != nullptr) NYS_TRY(launch_ut_v(U, F->d, r, x, target_out, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 

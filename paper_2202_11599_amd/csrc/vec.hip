@@ -244,6 +244,58 @@ __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a,
   if (threadIdx.x == 0) *out = s;
 }
 
+// Decide between two starts; one block so the partials can be rewritten safely.
+__global__ __launch_bounds__(256) void k_judge_decide(double* __restrict__ wwpart,
+                                                      const double* __restrict__ wwpart2, int n,
+                                                      PcgDev* __restrict__ st) {
+  __shared__ double sh4[4];
+  const double a = block_sum_array(wwpart, n, sh4);
+  __syncthreads();
+  const double b = block_sum_array(wwpart2, n, sh4);
+  if (!(b < a)) return;
+  for (int i = threadIdx.x; i < n; i += 256) wwpart[i] = wwpart2[i];
+  if (threadIdx.x == 0) st->flags |= kFlagAltStart;
+}
+
+__global__ void k_judge_apply(double* __restrict__ x, const double* __restrict__ x_alt,
+                              double* __restrict__ w, const double* __restrict__ w2, int64_t d,
+                              const PcgDev* __restrict__ st) {
+  if (!(st->flags & kFlagAltStart)) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < d) {
+    x[j] = x_alt[j];
+    w[j] = w2[j];
+  }
+}
+
+// out_i = sum_j U[j, i] v_j: one wave per column, fixed order
+__global__ __launch_bounds__(256) void k_ut_v(const double* __restrict__ U, int64_t d, int r,
+                                              const double* __restrict__ v,
+                                              double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= r) return;
+  const double* u = U + (int64_t)col * d;
+  double acc = 0.0;
+  for (int64_t j = lane; j < d; j += 64) acc = fma(u[j], v[j], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) out[col] = acc;
+}
+
+// out_j = sum_i U[j, i] c_i: one thread per row, columns read coalesced
+__global__ __launch_bounds__(256) void k_u_c(const double* __restrict__ U, int64_t d, int r,
+                                             const double* __restrict__ c,
+                                             double* __restrict__ out) {
+  __shared__ double cs[1024];
+  for (int i = threadIdx.x; i < r; i += 256) cs[i] = c[i];
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= d) return;
+  double acc = 0.0;
+  for (int i = 0; i < r; ++i) acc = fma(U[(int64_t)i * d + j], cs[i], acc);
+  out[j] = acc;
+}
+
 }  // namespace
 
 nys_status launch_dot(const double* a, const double* b, int64_t d, double* out,
@@ -293,6 +345,34 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
     hipLaunchKernelGGL(k_precond_update<double>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const double*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
                        wwpart, nww, pppart, st, mode);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+}  // namespace nys
+
+namespace nys {
+
+nys_status launch_judge(double* wwpart, const double* wwpart2, int nred, double* x,
+                        const double* x_alt, double* w, const double* w2, int64_t d, PcgDev* st,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(k_judge_decide, dim3(1), dim3(256), 0, stream, wwpart, wwpart2, nred, st);
+  hipLaunchKernelGGL(k_judge_apply, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, stream, x,
+                     x_alt, w, w2, d, st);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status launch_ut_v(const double* U, int64_t d, int r, const double* v, double* out,
+                       hipStream_t stream) {
+  if (r < 1 || r > 1024) return NYS_ERR_INVALID;
+  hipLaunchKernelGGL(k_ut_v, dim3((unsigned)((r + 3) / 4)), dim3(256), 0, stream, U, d, r, v, out);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status launch_u_c(const double* U, int64_t d, int r, const double* c, double* out,
+                      hipStream_t stream) {
+  if (r < 1 || r > 1024) return NYS_ERR_INVALID;
+  hipLaunchKernelGGL(k_u_c, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, stream, U, d, r, c,
+                     out);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 

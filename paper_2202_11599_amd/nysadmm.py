@@ -69,7 +69,8 @@ class AdmmOpts(C.Structure):
                 ("max_iter", C.c_int), ("eps_abs", C.c_double), ("eps_rel", C.c_double),
                 ("rel_change_tol", C.c_double), ("kkt_tol", C.c_double), ("kkt_every", C.c_int),
                 ("factor", C.c_void_p), ("warm_start", C.c_void_p), ("ws_analytic", C.c_int),
-                ("ws_features", C.c_void_p), ("ws_target", C.c_void_p)]
+                ("ws_every_step", C.c_int), ("ws_features", C.c_void_p),
+                ("ws_target", C.c_void_p)]
 
 
 class AdmmState(C.Structure):
@@ -331,7 +332,7 @@ def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resk
               sketch_prec=NYS_F64, pcg: Optional[PcgOpts] = None, tol_schedule=False, max_iter=100,
               eps_abs=0.0, eps_rel=0.0, rel_change_tol=0.0, kkt_tol=0.0, kkt_every=10,
               factor: Optional["Factor"] = None, warm_start: Optional["WarmStart"] = None,
-              ws_analytic=False, ws_features: Optional[torch.Tensor] = None,
+              ws_analytic=False, ws_every_step=False, ws_features: Optional[torch.Tensor] = None,
               ws_target: Optional[torch.Tensor] = None) -> AdmmOpts:
     for t, name in ((ws_features, "ws_features"), (ws_target, "ws_target")):
         if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
@@ -341,6 +342,7 @@ def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resk
                     int(max_iter), float(eps_abs), float(eps_rel), float(rel_change_tol),
                     float(kkt_tol), int(kkt_every), None if factor is None else factor.h.value,
                     None if warm_start is None else warm_start.h.value, int(bool(ws_analytic)),
+                    int(bool(ws_every_step)),
                     None if ws_features is None else ws_features.data_ptr(),
                     None if ws_target is None else ws_target.data_ptr())
 

@@ -129,9 +129,11 @@ def energy_error(C: torch.Tensor, X: torch.Tensor, T: torch.Tensor, lam: Sequenc
 
 
 def run_arm(ctx: N.Context, A: torch.Tensor, F: N.Factor, omega: torch.Tensor,
-            families: Sequence[Family], iters: int, arm: str, model=None, pcg=None):
+            families: Sequence[Family], iters: int, arm: str, model=None, pcg=None,
+            every_step: bool = False):
     """Solve every family for `iters` ADMM steps with one start rule
-    ("prev", "mlp" or "analytic"); returns totals and the final z of each."""
+    ("prev", "mlp" or "analytic"; the candidate is judged at the first step of
+    each run, or at every step); returns totals and the final z of each."""
     r = F.info()["rank"]
     d = A.shape[1]
     tot = {"arm": arm, "solves": 0, "pcg_iters": 0, "ws_used": 0, "first_iters": 0}
@@ -144,7 +146,7 @@ def run_arm(ctx: N.Context, A: torch.Tensor, F: N.Factor, omega: torch.Tensor,
         for k in range(iters):
             o = N.admm_opts(rho, r, omega, pcg=pcg or N.pcg_opts(tol=1e-6), factor=F,
                             warm_start=model if arm == "mlp" else None,
-                            ws_analytic=(arm == "analytic"))
+                            ws_analytic=(arm == "analytic"), ws_every_step=every_step)
             _, info = N.admm_step(ctx, prob, o, F, st)
             tot["solves"] += 1
             tot["pcg_iters"] += info.pcg_iters

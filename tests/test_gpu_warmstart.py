@@ -143,7 +143,7 @@ def test_analytic_candidate_is_judged_and_solution_unchanged(N, ctx):
     used = []
     for k in range(its):
         o = N.admm_opts(p.rho, p.rank, om_, pcg=N.pcg_opts(tol=1e-12), ws_analytic=True,
-                        sketch_prec=N.NYS_F32)
+                        ws_every_step=True, sketch_prec=N.NYS_F32)
         F, info = N.admm_step(ctx, prob, o, F, st)
         used.append(info.ws_used)
     # from x = 0 the analytic start has the smaller residual
@@ -172,7 +172,8 @@ def test_judge_rejects_a_bad_network_bit_for_bit(N, ctx):
         st = N.State(p.d, DEV)
         tot_used = 0
         for k in range(6):
-            o = N.admm_opts(p.rho, p.rank, om_, pcg=N.pcg_opts(tol=1e-6), warm_start=model)
+            o = N.admm_opts(p.rho, p.rank, om_, pcg=N.pcg_opts(tol=1e-6), warm_start=model,
+                            ws_every_step=True)
             _, info = N.admm_step(ctx, prob, o, F, st)
             tot_used += info.ws_used
         runs.append((st.z.clone(), st.x.clone(), tot_used))
@@ -193,7 +194,8 @@ def test_zero_network_with_skip_equals_analytic_start(N, ctx):
                        analytic_skip=True)
     prob = N.problem(A, b, p.gamma)
     runs = []
-    for kw in (dict(ws_analytic=True), dict(warm_start=zero)):
+    for kw in (dict(ws_analytic=True, ws_every_step=True),
+               dict(warm_start=zero, ws_every_step=True)):
         st = N.State(p.d, DEV)
         used = 0
         for k in range(5):
@@ -258,13 +260,16 @@ def test_training_lowers_pcg_work(N, ctx):
           flush=True)
     arms = {a: W.run_arm(ctx, A, F, om_, test, its, a, model=model) for a in
             ("prev", "mlp", "analytic")}
+    arms["mlp_every_step"] = W.run_arm(ctx, A, F, om_, test, its, "mlp", model=model,
+                                       every_step=True)
     for a, (tot, _) in arms.items():
         print(f"[ws train] {a}: {tot}", flush=True)
     assert hist[-1][1] < hist[0][1]
     prev, mlp = arms["prev"][0], arms["mlp"][0]
     assert mlp["ws_used"] >= len(test)            # at least every x = 0 start
     assert mlp["first_iters"] < prev["first_iters"]
-    assert mlp["pcg_iters"] <= prev["pcg_iters"] + len(test)
+    assert mlp["pcg_iters"] <= prev["pcg_iters"]          # later steps are unchanged
+    assert arms["mlp_every_step"][0]["pcg_iters"] <= prev["pcg_iters"] + len(test)
     # same fixed point: the start never changes what PCG converges to
     for za, zb in zip(arms["prev"][1], arms["mlp"][1]):
         assert torch.linalg.norm(za - zb) <= 1e-3 * torch.linalg.norm(za)
