@@ -95,48 +95,66 @@ __global__ __launch_bounds__(256) void k_split_reduce(int M, int N, int S,
   *c = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * *c);
 }
 
-// ------------------------------------------------------------ Cholesky
-// In-place upper Cholesky of the symmetric r x r matrix M (row-major, ld):
-// on exit M = C with C^T C = M_in, strictly lower part zeroed.  One workgroup
-// of 1024 threads, thread k owns column k; row j of C is formed at step j from
-// the rows above it.  *fail = 1 on a non-positive or non-finite pivot.
+// Upper Cholesky factor C (C^T C = M) in place, row-major with leading
+// dimension ld, lower triangle set to zero.  One workgroup of 1024 threads:
+// at step j, row j of C is formed from the rows above it,
+//   C(j,k) = (M(j,k) - sum_{i<j} C(i,j) C(i,k)) / C(j,j),   k >= j,
+// with g = 1024 / (r rounded up to a power of two) threads per column k, each
+// summing every g-th i, the g partial sums added in a fixed order.
+// *fail = 1 on a non-positive or non-finite pivot.
 __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int r, int ld,
-                                                     int* __restrict__ fail) {
+                                                     int g, int* __restrict__ fail) {
+  __shared__ double part[1024];
   __shared__ double piv;
   __shared__ int bad;
-  const int k = threadIdx.x;
-  if (k == 0) bad = 0;
+  const int tid = threadIdx.x;
+  const int cols = 1024 / g;          // columns covered per pass
+  const int sub = tid / cols;         // which i-slice this thread sums
+  const int kc = tid % cols;
+  if (tid == 0) bad = 0;
   __syncthreads();
   for (int j = 0; j < r; ++j) {
-    double dot = 0.0;
-    const bool mine = (k >= j && k < r);
-    if (mine) {
-      for (int i = 0; i < j; ++i) dot = fma(M[(int64_t)i * ld + j], M[(int64_t)i * ld + k], dot);
-    }
-    if (k == j) {
-      const double s = M[(int64_t)j * ld + j] - dot;
-      if (!(s > 0.0) || !isfinite(s)) {
-        bad = 1;
-        piv = 1.0;
-      } else {
-        piv = sqrt(s);
+    // columns k = j .. r-1 in passes of `cols`
+    for (int k0 = j; k0 < r; k0 += cols) {
+      const int k = k0 + kc;
+      double dot = 0.0;
+      if (k < r) {
+        for (int i = sub; i < j; i += g) dot = fma(M[(int64_t)i * ld + j], M[(int64_t)i * ld + k], dot);
       }
+      part[tid] = dot;
+      __syncthreads();
+      if (sub == 0 && k < r) {
+        double t = 0.0;
+        for (int h = 0; h < g; ++h) t += part[h * cols + kc];
+        if (k == j) {
+          const double sj = M[(int64_t)j * ld + j] - t;
+          if (!(sj > 0.0) || !isfinite(sj)) {
+            bad = 1;
+            piv = 1.0;
+          } else {
+            piv = sqrt(sj);
+          }
+        }
+        part[kc] = t;     // the reduced dot of column k (slot sub 0)
+      }
+      __syncthreads();
+      if (bad) break;
+      if (sub == 0 && k < r) {
+        if (k == j)
+          M[(int64_t)j * ld + j] = piv;
+        else
+          M[(int64_t)j * ld + k] = (M[(int64_t)j * ld + k] - part[kc]) / piv;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (bad) break;
-    if (mine) {
-      if (k == j)
-        M[(int64_t)j * ld + j] = piv;
-      else
-        M[(int64_t)j * ld + k] = (M[(int64_t)j * ld + k] - dot) / piv;
-    }
-    __syncthreads();
   }
   if (bad) {
-    if (k == 0) *fail = 1;
+    if (tid == 0) *fail = 1;
     return;
   }
-  for (int i = k + 1; i < r; ++i) M[(int64_t)i * ld + k] = 0.0;  // column k below the diagonal
+  for (int k = tid; k < r; k += 1024)
+    for (int i = k + 1; i < r; ++i) M[(int64_t)i * ld + k] = 0.0;  // below the diagonal
 }
 
 // Z = C^-1 for upper triangular C (r x r, row-major, ld); one wavefront per
@@ -209,15 +227,17 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
 }
 
 // ------------------------------------------------------------ Jacobi
-// Two-sided block Jacobi on the symmetric R x R matrix G (R a multiple of 64,
-// row-major), blocks of 32 indices, block pairs chosen round-robin.  Each
-// workgroup diagonalises one 64 x 64 pair block in LDS by cyclic Jacobi with
-// parallel rotation ordering and writes its rotation Q; then every tile of G
-// becomes Q_P^T G_PQ Q_Q and V becomes V Q.
-constexpr int kJB = 32;        // block size
+// Two-sided block Jacobi on the symmetric R x R matrix G (R a multiple of 32,
+// row-major), blocks of 16 indices, block pairs chosen round-robin.  Each
+// workgroup diagonalises one 32 x 32 pair block in LDS by one cyclic Jacobi
+// sweep with parallel rotation ordering and writes its rotation Q; then every
+// tile of G becomes Q_P^T G_PQ Q_Q and V becomes V Q.
+constexpr int kJB = 16;        // block size
 constexpr int kJP = 2 * kJB;   // pair block size
+constexpr int kJT = 256;       // threads of the solve and apply workgroups
+constexpr int kJE = kJP * kJP / kJT;   // tile elements per thread
+constexpr int kJR = kJB * kJP / kJT;   // rotation updates per thread and phase
 constexpr double kJacTol = 1e-15;
-constexpr int kInnerSweeps = 1;
 
 // Round-robin pairing of nb blocks (nb even): round t, pair k -> (a, b).
 __device__ __forceinline__ void rr_pair(int nb, int t, int k, int* a, int* b) {
@@ -234,7 +254,7 @@ __device__ __forceinline__ int pair_index(int a, int b, int i) {
 // A rotation is applied when |a_pq| > max(tol sqrt(|a_pp a_qq|), tol * trace(G)):
 // the relative test gives small eigenvalues their accuracy, the absolute floor
 // stops rotations that only chase the rounding of the tile updates.
-__global__ __launch_bounds__(256) void k_jacobi_solve(const double* __restrict__ G, int R,
+__global__ __launch_bounds__(kJT) void k_jacobi_solve(const double* __restrict__ G, int R,
                                                       int round, double* __restrict__ Qbuf,
                                                       int* __restrict__ counters, int sweep,
                                                       const double* __restrict__ gnorm) {
@@ -243,90 +263,86 @@ __global__ __launch_bounds__(256) void k_jacobi_solve(const double* __restrict__
   __shared__ double S[kJP][kJP + 1];
   __shared__ double Q[kJP][kJP + 1];
   __shared__ double cs[kJB][2];
-  __shared__ int any_rot;
+  __shared__ int pq[kJB][2];
+  __shared__ int rot_any;
   const int tid = threadIdx.x;
   const int nb = R / kJB;
   int a, b;
   rr_pair(nb, round, blockIdx.x, &a, &b);
-  for (int e = tid; e < kJP * kJP; e += 256) {
+  for (int e = tid; e < kJP * kJP; e += kJT) {
     const int i = e / kJP, j = e % kJP;
     S[i][j] = G[(int64_t)pair_index(a, b, i) * R + pair_index(a, b, j)];
     Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  if (tid == 0) any_rot = 0;
+  if (tid == 0) rot_any = 0;
   __syncthreads();
-  int significant = 0;
   // one cyclic sweep of the pair block per visit (block Jacobi); the outer
-  // sweeps repeat until no block pair rotates
-  for (int isweep = 0; isweep < kInnerSweeps; ++isweep) {
-    __shared__ int rot_this_sweep;
-    if (tid == 0) rot_this_sweep = 0;
-    __syncthreads();
-    for (int step = 0; step < kJP - 1; ++step) {
-      if (tid < kJB) {
-        // inner round-robin over 64 indices
-        auto pos = [&](int p) { return p == 0 ? 0 : ((p - 1 + step) % (kJP - 1)) + 1; };
-        int p = pos(tid), q = pos(kJP - 1 - tid);
-        if (p > q) { const int t = p; p = q; q = t; }
-        const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs) && apq != 0.0) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                        : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          rot_this_sweep = 1;
-        }
-        cs[tid][0] = c;
-        cs[tid][1] = s;
+  // sweeps repeat until no block pair rotates.  Round-robin over the kJP
+  // indices: at step t rotation k pairs positions k and kJP-1-k of the
+  // rotated order.
+  for (int step = 0; step < kJP - 1; ++step) {
+    if (tid < kJB) {
+      auto pos = [&](int p) { return p == 0 ? 0 : ((p - 1 + step) % (kJP - 1)) + 1; };
+      int p = pos(tid), q = pos(kJP - 1 - tid);
+      if (p > q) { const int t = p; p = q; q = t; }
+      const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
+      double c = 1.0, sn = 0.0;
+      if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs) && apq != 0.0) {
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                      : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+        c = 1.0 / sqrt(1.0 + t * t);
+        sn = t * c;
+        rot_any = 1;
       }
-      __syncthreads();
-      // rows: S <- J^T S
-      for (int e = tid; e < kJB * kJP; e += 256) {
-        const int k = e / kJP, j = e % kJP;
-        auto pos = [&](int pp) { return pp == 0 ? 0 : ((pp - 1 + step) % (kJP - 1)) + 1; };
-        int p = pos(k), q = pos(kJP - 1 - k);
-        if (p > q) { const int t = p; p = q; q = t; }
-        const double c = cs[k][0], s = cs[k][1];
-        if (s != 0.0) {
-          const double sp = S[p][j], sq = S[q][j];
-          S[p][j] = c * sp - s * sq;
-          S[q][j] = s * sp + c * sq;
-        }
-      }
-      __syncthreads();
-      // columns: S <- S J, Q <- Q J
-      for (int e = tid; e < kJB * kJP; e += 256) {
-        const int k = e / kJP, i = e % kJP;
-        auto pos = [&](int pp) { return pp == 0 ? 0 : ((pp - 1 + step) % (kJP - 1)) + 1; };
-        int p = pos(k), q = pos(kJP - 1 - k);
-        if (p > q) { const int t = p; p = q; q = t; }
-        const double c = cs[k][0], s = cs[k][1];
-        if (s != 0.0) {
-          const double sp = S[i][p], sq = S[i][q];
-          S[i][p] = c * sp - s * sq;
-          S[i][q] = s * sp + c * sq;
-          const double qp = Q[i][p], qq = Q[i][q];
-          Q[i][p] = c * qp - s * qq;
-          Q[i][q] = s * qp + c * qq;
-        }
-      }
-      __syncthreads();
+      cs[tid][0] = c;
+      cs[tid][1] = sn;
+      pq[tid][0] = p;
+      pq[tid][1] = q;
     }
-    const int rot = rot_this_sweep;
     __syncthreads();
-    if (!rot) break;
-    significant = 1;
+    // rows: S <- J^T S
+#pragma unroll
+    for (int h = 0; h < kJR; ++h) {
+      const int e = tid + h * kJT;
+      const int k = e / kJP, j = e % kJP;
+      const double sn = cs[k][1];
+      if (sn != 0.0) {
+        const double c = cs[k][0];
+        const int p = pq[k][0], q = pq[k][1];
+        const double sp = S[p][j], sq = S[q][j];
+        S[p][j] = c * sp - sn * sq;
+        S[q][j] = sn * sp + c * sq;
+      }
+    }
+    __syncthreads();
+    // columns: S <- S J, Q <- Q J
+#pragma unroll
+    for (int h = 0; h < kJR; ++h) {
+      const int e = tid + h * kJT;
+      const int k = e / kJP, i = e % kJP;
+      const double sn = cs[k][1];
+      if (sn != 0.0) {
+        const double c = cs[k][0];
+        const int p = pq[k][0], q = pq[k][1];
+        const double sp = S[i][p], sq = S[i][q];
+        S[i][p] = c * sp - sn * sq;
+        S[i][q] = sn * sp + c * sq;
+        const double qp = Q[i][p], qq = Q[i][q];
+        Q[i][p] = c * qp - sn * qq;
+        Q[i][q] = sn * qp + c * qq;
+      }
+    }
+    __syncthreads();
   }
   double* Qo = Qbuf + (int64_t)blockIdx.x * kJP * kJP;
-  for (int e = tid; e < kJP * kJP; e += 256) Qo[e] = Q[e / kJP][e % kJP];
-  if (tid == 0 && significant) atomicAdd(&counters[sweep], 1);
+  for (int e = tid; e < kJP * kJP; e += kJT) Qo[e] = Q[e / kJP][e % kJP];
+  if (tid == 0 && rot_any) atomicAdd(&counters[sweep], 1);
 }
 
 // G_out tile (P, Q) = Q_P^T G_in[P, Q] Q_Q for pair blocks P, Q of the round,
 // and V[rows, P] <- V[rows, P] Q_P (extra workgroups).
-__global__ __launch_bounds__(256) void k_jacobi_apply(const double* __restrict__ Gin,
+__global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__ Gin,
                                                       double* __restrict__ Gout,
                                                       double* __restrict__ V, int R, int round,
                                                       const double* __restrict__ Qbuf,
@@ -346,38 +362,38 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const double* __restrict__
     rr_pair(nb, round, Qi, &qa, &qb);
     const double* QP = Qbuf + (int64_t)P * kJP * kJP;
     const double* QQ = Qbuf + (int64_t)Qi * kJP * kJP;
-    for (int e = tid; e < kJP * kJP; e += 256) {
+    for (int e = tid; e < kJP * kJP; e += kJT) {
       const int i = e / kJP, j = e % kJP;
       T[i][j] = Gin[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)];
       W[i][j] = QQ[e];
     }
     __syncthreads();
     // X = T * Q_Q
-    double x[16];
+    double x[kJE];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int e = tid + t * 256;
+    for (int t = 0; t < kJE; ++t) {
+      const int e = tid + t * kJT;
       const int i = e / kJP, j = e % kJP;
-      double s = 0.0;
-      for (int l = 0; l < kJP; ++l) s = fma(T[i][l], W[l][j], s);
-      x[t] = s;
+      double sacc = 0.0;
+      for (int l = 0; l < kJP; ++l) sacc = fma(T[i][l], W[l][j], sacc);
+      x[t] = sacc;
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int e = tid + t * 256;
+    for (int t = 0; t < kJE; ++t) {
+      const int e = tid + t * kJT;
       T[e / kJP][e % kJP] = x[t];
       W[e / kJP][e % kJP] = QP[e];
     }
     __syncthreads();
     // out = Q_P^T * X
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int e = tid + t * 256;
+    for (int t = 0; t < kJE; ++t) {
+      const int e = tid + t * kJT;
       const int i = e / kJP, j = e % kJP;
-      double s = 0.0;
-      for (int l = 0; l < kJP; ++l) s = fma(W[l][i], T[l][j], s);
-      Gout[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)] = s;
+      double sacc = 0.0;
+      for (int l = 0; l < kJP; ++l) sacc = fma(W[l][i], T[l][j], sacc);
+      Gout[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)] = sacc;
     }
   } else {
     const int v = bid - np * np;
@@ -385,19 +401,19 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(const double* __restrict__
     int pa, pb;
     rr_pair(nb, round, P, &pa, &pb);
     const double* QP = Qbuf + (int64_t)P * kJP * kJP;
-    for (int e = tid; e < kJP * kJP; e += 256) {
+    for (int e = tid; e < kJP * kJP; e += kJT) {
       const int i = e / kJP, j = e % kJP;
       T[i][j] = V[(int64_t)(rc * kJP + i) * R + pair_index(pa, pb, j)];
       W[i][j] = QP[e];
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int e = tid + t * 256;
+    for (int t = 0; t < kJE; ++t) {
+      const int e = tid + t * kJT;
       const int i = e / kJP, j = e % kJP;
-      double s = 0.0;
-      for (int l = 0; l < kJP; ++l) s = fma(T[i][l], W[l][j], s);
-      V[(int64_t)(rc * kJP + i) * R + pair_index(pa, pb, j)] = s;
+      double sacc = 0.0;
+      for (int l = 0; l < kJP; ++l) sacc = fma(T[i][l], W[l][j], sacc);
+      V[(int64_t)(rc * kJP + i) * R + pair_index(pa, pb, j)] = sacc;
     }
   }
 }
@@ -494,7 +510,10 @@ nys_status gemm64(hipStream_t st, int M, int N, int K, const void* A, bool a_f32
 
 nys_status chol_upper(hipStream_t st, double* M, int r, int ld, int* fail) {
   if (r > 1024) return NYS_ERR_INVALID;
-  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, st, M, r, ld, fail);
+  int p2 = 1;
+  while (p2 < r) p2 *= 2;
+  const int g = std::max(1, 1024 / p2);
+  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, st, M, r, ld, g, fail);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
@@ -510,7 +529,7 @@ nys_status power_iter(hipStream_t st, const double* G, int r, int ld, int iters,
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
-int jacobi_pad(int r) { return std::max(64, (r + 63) / 64 * 64); }
+int jacobi_pad(int r) { return std::max(kJP, (r + kJP - 1) / kJP * kJP); }
 
 size_t jacobi_ws_doubles(int r) {
   const int R = jacobi_pad(r);
@@ -546,10 +565,10 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
   bool converged = false;
   for (int s = 0; s < max_sweeps; ++s) {
     for (int t = 0; t < nb - 1; ++t) {
-      hipLaunchKernelGGL(k_jacobi_solve, dim3(np), dim3(256), 0, st, G0, R, t, Qb, counters, s,
+      hipLaunchKernelGGL(k_jacobi_solve, dim3(np), dim3(kJT), 0, st, G0, R, t, Qb, counters, s,
                          gnorm);
-      hipLaunchKernelGGL(k_jacobi_apply, dim3(np * np + np * (R / kJP)), dim3(256), 0, st, G0, G1,
-                         V, R, t, Qb, counters, s);
+      hipLaunchKernelGGL(k_jacobi_apply, dim3(np * np + np * (R / kJP)), dim3(kJT), 0, st, G0,
+                         G1, V, R, t, Qb, counters, s);
       std::swap(G0, G1);
     }
     ++sweeps;

@@ -316,6 +316,15 @@ __global__ void k_shift_sym(const double* __restrict__ X, const double* __restri
   M[e] = 0.5 * (X[(int64_t)i * r + j] + X[(int64_t)j * r + i]) + nu * Gam[e];
 }
 
+// M = G - mu I (r x r)
+__global__ void k_sub_diag(const double* __restrict__ G, int r, double mu,
+                           double* __restrict__ M) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e / r), j = (int)(e % r);
+  M[e] = G[e] - (i == j ? mu : 0.0);
+}
+
 // mirror the upper-left block's new columns: M[c][i] = M[i][c] for c >= c0
 __global__ void k_mirror_cols(double* __restrict__ M, int ld, int c0, int r) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -403,7 +412,13 @@ nys_status orthonormalize(nys_ctx ctx, double* Om, int64_t d, int m, const CoreW
 }
 
 // The FP64 core of Algorithm RandNysAppx on the factor's current sketch.
-nys_status nys_core(nys_ctx ctx, nys_factor F) {
+// test_mu >= 0: stop after forming G = B^T B when G - (nu + test_mu) I is
+// positive definite (its Cholesky succeeds), i.e. when every retained
+// eigenvalue max(0, sigma^2 - nu) exceeds test_mu; *above = 1 and the factor's
+// U and lambda are left unset.  Otherwise (or test_mu < 0) the
+// eigendecomposition is completed and *above = 0.
+nys_status nys_core(nys_ctx ctx, nys_factor F, double test_mu, int* above) {
+  if (above) *above = 0;
   hipStream_t st = ctx->stream;
   const int64_t d = F->d;
   const int r = F->r;
@@ -452,6 +467,20 @@ nys_status nys_core(nys_ctx ctx, nys_factor F) {
   // G = B^T B, eigendecomposition G = V Sigma^2 V^T
   NYS_TRY(gemm64(st, r, r, (int)d, w.Bm, false, d, 1, w.Bm, false, 1, d, w.G, r, 1, 1.0, 0.0,
                  w.split, w.split_elems));
+  if (test_mu >= 0.0) {
+    // inertia of G - (nu + test_mu) I through one Cholesky attempt
+    hipLaunchKernelGGL(k_sub_diag, dim3(blocks((int64_t)r * r)), dim3(256), 0, st, w.G, r,
+                       nu + test_mu, w.M);
+    NYS_TRY_HIP(hipMemsetAsync(w.ints, 0, sizeof(int), st));
+    NYS_TRY(chol_upper(st, w.M, r, r, w.ints));
+    int fail = 0;
+    NYS_TRY(read_back(ctx, w.ints, sizeof(int), &fail));
+    if (!fail) {
+      F->nu = nu;
+      if (above) *above = 1;
+      return NYS_OK;
+    }
+  }
   int sweeps = 0;
   NYS_TRY(jacobi_eig(st, w.G, r, r, w.jac, w.ints + 16, 40, ctx->host_pinned, w.sig2, w.W, r,
                      &sweeps));
@@ -625,7 +654,8 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
 
 // Mbase with ld = cap is repacked to ld = r for the core.
 nys_status sketch_and_core(nys_ctx ctx, const nys_dense& A, const double* D, double c,
-                           const double* omega, int m, nys_factor F) {
+                           const double* omega, int m, nys_factor F, double test_mu = -1.0,
+                           int* above = nullptr) {
   NYS_TRY(sketch_block(ctx, A, D, c, omega, m, F));
   if (F->prec != NYS_F64 && F->cap != F->r) {
     // compact Mbase (cap pitch) into core order (r pitch) in gemm_ws
@@ -636,23 +666,19 @@ nys_status sketch_and_core(nys_ctx ctx, const nys_dense& A, const double* D, dou
                                  sizeof(double) * F->r, F->r, hipMemcpyDeviceToDevice, ctx->stream));
     nys::DevBuf saved = Mb;
     Mb = tmp;
-    nys_status s = nys_core(ctx, F);
+    nys_status s = nys_core(ctx, F, test_mu, above);
     NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
     Mb.release();
     Mb = saved;
     return s;
   }
-  return nys_core(ctx, F);
+  return nys_core(ctx, F, test_mu, above);
 }
 
-}  // namespace nys
-
-using namespace nys;
-
-extern "C" {
-
-nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c,
-                      const double* omega, int r, nys_dtype prec, nys_factor* F) {
+// One round of the sketch: extend *F by m columns and rebuild its core.
+nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                        const double* omega, int r, nys_dtype prec, nys_factor* F,
+                        double test_mu, int* above) {
   if (ctx == nullptr || F == nullptr || omega == nullptr) return NYS_ERR_INVALID;
   NYS_TRY(validate_dense(A));
   if (!(c >= 0.0) || r < 1) return NYS_ERR_INVALID;
@@ -674,13 +700,24 @@ nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c
     f->mantissa_bits = (prec == NYS_F64) ? 52 : 23;
     created = true;
   }
-  nys_status s = sketch_and_core(ctx, *A, D, c, omega, r, f);
+  nys_status s = sketch_and_core(ctx, *A, D, c, omega, r, f, test_mu, above);
   if (s != NYS_OK) {
     if (created) nys_factor_destroy(f);
     return s;
   }
   *F = f;
   return NYS_OK;
+}
+
+}  // namespace nys
+
+using namespace nys;
+
+extern "C" {
+
+nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                      const double* omega, int r, nys_dtype prec, nys_factor* F) {
+  return sketch_round(ctx, A, D, c, omega, r, prec, F, -1.0, nullptr);
 }
 
 nys_status nys_sketch_adaptive(nys_ctx ctx, const nys_dense* A, const double* D, double c,
@@ -690,17 +727,22 @@ nys_status nys_sketch_adaptive(nys_ctx ctx, const nys_dense* A, const double* D,
   NYS_TRY(validate_dense(A));
   if (s0 < 1 || s_max < s0 || s_max >= A->d || s_max > 1024 || !(rho > 0.0) || !(tol >= 1.0))
     return NYS_ERR_INVALID;
+  // kappa = (lambda_s + rho) / rho <= tol  <=>  lambda_s <= (tol - 1) rho, so a
+  // round that does not stop is recognised by the inertia of G - (nu + (tol - 1) rho) I
+  // and the eigendecomposition is only computed in the final round.
   int s = 0, m = s0;
   nys_factor f = nullptr;
   for (;;) {
-    nys_status st = nys_sketch(ctx, A, D, c, omega + (int64_t)s * A->d, m, prec, &f);
+    const bool last = s + m >= s_max;
+    int above = 0;
+    nys_status st = sketch_round(ctx, A, D, c, omega + (int64_t)s * A->d, m, prec, &f,
+                                 last ? -1.0 : (tol - 1.0) * rho, &above);
     if (st != NYS_OK) {
       if (f) nys_factor_destroy(f);
       return st;
     }
     s += m;
-    const double kappa = (f->lam_host[s - 1] + rho) / rho;
-    if (kappa <= tol || s >= s_max) break;
+    if (!above) break;
     m = std::min(s, s_max - s);
   }
   *F = f;
