@@ -60,15 +60,15 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
   ws->qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ypart.ptr) +
                                         align_up(sizeof(double) * ((size_t)pl.grid * pl.ldy)));
   const size_t nv = align_up(sizeof(double) * d);
-  const size_t vb = 3 * nv + align_up(sizeof(double) * 1024) +
-                    align_up(sizeof(double) * (size_t)(max_iter + 2));
+  const size_t cb = align_up(sizeof(double) * 1024 * kDotSlices);
+  const size_t vb = 3 * nv + cb + align_up(sizeof(double) * (size_t)(max_iter + 2));
   NYS_TRY(ctx->vecs.reserve(vb));
   char* v = static_cast<char*>(ctx->vecs.ptr);
   ws->w = reinterpret_cast<double*>(v);
   ws->p = reinterpret_cast<double*>(v + nv);
   ws->cvec = reinterpret_cast<double*>(v + 2 * nv);
-  ws->wy = reinterpret_cast<double*>(v + 2 * nv + align_up(sizeof(double) * 1024));
-  ws->w2 = reinterpret_cast<double*>(v + 2 * nv + align_up(sizeof(double) * 1024) +
+  ws->wy = reinterpret_cast<double*>(v + 2 * nv + cb);
+  ws->w2 = reinterpret_cast<double*>(v + 2 * nv + cb +
                                      align_up(sizeof(double) * (size_t)(max_iter + 2)));
   ws->nred = nblk(d, kRedBlock);
   ws->nvec = nblk(d, kVecBlock);

@@ -220,8 +220,9 @@ nys_status launch_gram(const nys_dense& A, const GramPlan& plan, int mode, const
                        const int* done, hipStream_t st);
 
 // ---- vec.hip
-constexpr int kVecBlock = 256;   // d-slice per workgroup of the vector kernels
-constexpr int kRedBlock = 64;    // columns per workgroup of the partial reduction
+constexpr int kVecBlock = 32;    // entries of y per workgroup of the preconditioner update
+constexpr int kRedBlock = 16;    // columns per workgroup of the partial reduction
+constexpr int kDotSlices = 8;    // d-slices of the U^T w partial sums
 inline int nblk(int64_t d, int b) { return (int)((d + b - 1) / b); }
 
 // v = sum_g ypart[g] + rho_eff * p ; then per `op`:

@@ -37,22 +37,23 @@ __device__ double block_sum_value(double v, double* sh4) {
   return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
-// 1024 threads: 64 columns x 16 slices of the workgroup partials, combined in
-// a fixed order through LDS.
-__global__ __launch_bounds__(1024) void k_reduce_update(
+// 256 threads: kRedBlock columns x (256 / kRedBlock) slices of the workgroup
+// partials, combined in a fixed order through LDS.
+__global__ __launch_bounds__(256) void k_reduce_update(
     int op, const double* __restrict__ ypart, int G, int ldy, const double* __restrict__ qpart,
     int64_t d, double rho_eff, const double* __restrict__ p, double* __restrict__ x,
     double* __restrict__ w, const double* __restrict__ rhs, double* __restrict__ wy, int k,
     const double* __restrict__ pppart, int npp, double* __restrict__ wwpart,
     double* __restrict__ rrpart, PcgDev* __restrict__ st) {
   if (op == 0 && st->done) return;
-  constexpr int S = 16;
-  __shared__ double part[S][64];
-  __shared__ double sh[S];
+  constexpr int RJ = kRedBlock;
+  constexpr int S = 256 / RJ;
+  __shared__ double part[S][RJ];
+  __shared__ double sh4[4];
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int grp = tid >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int lane = tid % RJ;
+  const int grp = tid / RJ;
+  const int64_t j = (int64_t)blockIdx.x * RJ + lane;
 
   double acc = 0.0;
   if (j < d)
@@ -62,21 +63,9 @@ __global__ __launch_bounds__(1024) void k_reduce_update(
   double alpha = 0.0;
   if (op == 0) {
     // q = sum qpart, pp = sum pppart (fixed order, identical in every workgroup)
-    double q = 0.0, pp = 0.0;
-    for (int i = tid; i < G; i += 1024) q += qpart[i];
-    for (int i = tid; i < npp; i += 1024) pp += pppart[i];
-    q = wave_sum(q);
-    pp = wave_sum(pp);
+    const double qs = block_sum_array(qpart, G, sh4);
     __syncthreads();
-    if (lane == 0) sh[grp] = q;
-    __syncthreads();
-    double qs = 0.0;
-    for (int i = 0; i < S; ++i) qs += sh[i];
-    __syncthreads();
-    if (lane == 0) sh[grp] = pp;
-    __syncthreads();
-    double ps = 0.0;
-    for (int i = 0; i < S; ++i) ps += sh[i];
+    const double ps = block_sum_array(pppart, npp, sh4);
     const double pv = qs + rho_eff * ps;
     if (!(pv > 0.0)) {
       if (blockIdx.x == 0 && tid == 0) {
@@ -90,9 +79,8 @@ __global__ __launch_bounds__(1024) void k_reduce_update(
   }
   __syncthreads();
 
-  if (grp != 0) return;
   double ww = 0.0, rr = 0.0;
-  if (j < d) {
+  if (grp == 0 && j < d) {
     double sum = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) sum += part[i][lane];
@@ -115,9 +103,11 @@ __global__ __launch_bounds__(1024) void k_reduce_update(
     }
   }
   if (op == 3) return;
-  ww = wave_sum(ww);
-  rr = wave_sum(rr);
-  if (lane == 0) {
+  __syncthreads();
+  ww = block_sum_value(ww, sh4);
+  __syncthreads();
+  rr = block_sum_value(rr, sh4);
+  if (tid == 0) {
     wwpart[blockIdx.x] = ww;
     if (rrpart != nullptr) rrpart[blockIdx.x] = rr;
   }
@@ -127,6 +117,8 @@ __global__ __launch_bounds__(1024) void k_reduce_update(
 // mode 1: PCG init (threshold from ||rhs||, test, then c = U^T w)
 // mode 2: standalone c = U^T w
 // mode 3: record sum(wwpart) as the true residual, no dots
+// c is left as kDotSlices partial sums over slices of d (cvec[s * 1024 + i]),
+// added in slice order by k_precond_update.
 template <typename UT>
 __global__ __launch_bounds__(256) void k_precond_dot(
     const UT* __restrict__ U, int64_t d, int r, const double* __restrict__ w,
@@ -143,7 +135,7 @@ __global__ __launch_bounds__(256) void k_precond_dot(
       const double rr = block_sum_array(rrpart, nww, sh4);
       thr2 = fmax(tol_abs * tol_abs, tol_rel * tol_rel * rr);
       zero_rhs = (rr == 0.0);
-      if (blockIdx.x == 0 && tid == 0) {
+      if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
         st->rr = rr;
         st->thr2 = thr2;
       }
@@ -151,9 +143,10 @@ __global__ __launch_bounds__(256) void k_precond_dot(
       thr2 = st->thr2;
     }
     const bool bad = !(ww == ww) || (ww > 1.7e308);
-    if (blockIdx.x == 0 && tid == 0) st->ww = ww;
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && tid == 0;
+    if (lead) st->ww = ww;
     if (zero_rhs || bad || ww <= thr2) {
-      if (blockIdx.x == 0 && tid == 0) {
+      if (lead) {
         if (bad) st->flags |= kFlagNonfinite;
         if (zero_rhs) st->flags |= kFlagZeroRhs;
         st->iters = (mode == 1) ? 0 : k + 1;
@@ -163,17 +156,21 @@ __global__ __launch_bounds__(256) void k_precond_dot(
     }
   } else if (mode == 3) {
     const double ww = block_sum_array(wwpart, nww, sh4);
-    if (blockIdx.x == 0 && tid == 0) st->true_rr = ww;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) st->true_rr = ww;
     return;
   }
+  // partial c = U^T w over d-slice blockIdx.y: cpart[slice * 1024 + col]
   const int lane = tid & 63;
   const int col = blockIdx.x * 4 + (tid >> 6);
   if (col >= r) return;
+  const int64_t chunk = ((d + kDotSlices - 1) / kDotSlices + 63) / 64 * 64;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = j0 + chunk < d ? j0 + chunk : d;
   const UT* u = U + (int64_t)col * d;
   double acc = 0.0;
-  for (int64_t j = lane; j < d; j += 64) acc = fma((double)u[j], w[j], acc);
+  for (int64_t j = j0 + lane; j < j1; j += 64) acc = fma((double)u[j], w[j], acc);
   acc = wave_sum(acc);
-  if (lane == 0) cvec[col] = acc;
+  if (lane == 0) cvec[(int64_t)blockIdx.y * 1024 + col] = acc;
 }
 
 // y = w + U (s o c), s_i = (lambda_s + rho)/(lambda_i + rho) - 1 ;
@@ -188,36 +185,43 @@ __global__ __launch_bounds__(256) void k_precond_update(
     double* __restrict__ p, double* __restrict__ wy, int k, const double* __restrict__ wwpart,
     int nww, double* __restrict__ pppart, const PcgDev* __restrict__ st, int mode) {
   if (mode != 2 && st->done) return;
+  constexpr int VJ = kVecBlock;        // entries of y per workgroup
+  constexpr int VS = 256 / VJ;         // slices of the rank index
   __shared__ double g[1024];
+  __shared__ double ys[VS][VJ];
   __shared__ double sh4[4];
   const int tid = threadIdx.x;
   double sc = 0.0;
   for (int i = tid; i < r; i += 256) {
+    double ci = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < kDotSlices; ++sl) ci += cvec[sl * 1024 + i];
     const double s = (lam_s + rho) / (lam[i] + rho) - 1.0;
-    const double ci = cvec[i];
     g[i] = s * ci;
     sc += s * ci * ci;
   }
   double wy_new = 0.0;
   if (mode != 2) {
     const double ww = block_sum_array(wwpart, nww, sh4);
+    __syncthreads();
     wy_new = ww + block_sum_value(sc, sh4);
   } else {
     __syncthreads();
   }
-  const int64_t j = (int64_t)blockIdx.x * 256 + tid;
-  double pj = 0.0;
+  const int jl = tid % VJ, sl = tid / VJ;
+  const int64_t j = (int64_t)blockIdx.x * VJ + jl;
+  double part = 0.0;
   if (j < d) {
-    double y = w[j];
     const UT* u = U + j;
-    int i = 0;
-    for (; i + 4 <= r; i += 4) {
-      y = fma((double)u[(int64_t)i * d], g[i], y);
-      y = fma((double)u[(int64_t)(i + 1) * d], g[i + 1], y);
-      y = fma((double)u[(int64_t)(i + 2) * d], g[i + 2], y);
-      y = fma((double)u[(int64_t)(i + 3) * d], g[i + 3], y);
-    }
-    for (; i < r; ++i) y = fma((double)u[(int64_t)i * d], g[i], y);
+    for (int i = sl; i < r; i += VS) part = fma((double)u[(int64_t)i * d], g[i], part);
+  }
+  ys[sl][jl] = part;
+  __syncthreads();
+  double pj = 0.0;
+  if (sl == 0 && j < d) {
+    double y = w[j];
+#pragma unroll
+    for (int h = 0; h < VS; ++h) y += ys[h][jl];
     if (mode == 0) {
       const double beta = wy_new / wy[k];
       pj = y + beta * p[j];
@@ -227,6 +231,7 @@ __global__ __launch_bounds__(256) void k_precond_update(
     p[j] = pj;
   }
   if (mode == 2) return;
+  __syncthreads();
   const double pp = block_sum_value(pj * pj, sh4);
   if (tid == 0) {
     pppart[blockIdx.x] = pp;
@@ -309,7 +314,7 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 const double* rhs, double* wy, int k, const double* pppart,
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
                                 hipStream_t stream) {
-  hipLaunchKernelGGL(k_reduce_update, dim3(nblk(d, kRedBlock)), dim3(1024), 0, stream, op, ypart,
+  hipLaunchKernelGGL(k_reduce_update, dim3(nblk(d, kRedBlock)), dim3(256), 0, stream, op, ypart,
                      G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp, wwpart, rrpart,
                      st);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
@@ -319,13 +324,14 @@ nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const d
                               double* cvec, PcgDev* st, const double* wwpart, int nww,
                               const double* rrpart, int k, int mode, double tol_rel,
                               double tol_abs, hipStream_t stream) {
-  const int grid = r > 0 ? (r + 3) / 4 : 1;
+  const unsigned gx = r > 0 ? (unsigned)((r + 3) / 4) : 1u;
+  const dim3 grid(gx, (mode == 0 || mode == 1 || mode == 2) ? kDotSlices : 1);
   if (u32)
-    hipLaunchKernelGGL(k_precond_dot<float>, dim3(grid), dim3(256), 0, stream,
+    hipLaunchKernelGGL(k_precond_dot<float>, grid, dim3(256), 0, stream,
                        static_cast<const float*>(U), d, r, w, cvec, st, wwpart, nww, rrpart, k,
                        mode, tol_rel, tol_abs);
   else
-    hipLaunchKernelGGL(k_precond_dot<double>, dim3(grid), dim3(256), 0, stream,
+    hipLaunchKernelGGL(k_precond_dot<double>, grid, dim3(256), 0, stream,
                        static_cast<const double*>(U), d, r, w, cvec, st, wwpart, nww, rrpart, k,
                        mode, tol_rel, tol_abs);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
