@@ -167,7 +167,8 @@ typedef struct {
   double tol;        /* stop when ||w||_2 <= tol ||rhs||_2 (tol_abs: ||w||_2 <= tol) */
   int tol_abs;
   int max_iter;      /* PCG iterations; 0 means 1000 */
-  int check_every;   /* host convergence check cadence; 0 means 8 */
+  int check_every;   /* iterations queued ahead of the host's convergence check (1..4;
+                        0 means 2); those queued after convergence return at once */
   int true_residual; /* 1: recompute rhs - H_rho x at the end and restart if above tol */
   int max_restarts;  /* restarts allowed by the true-residual check; 0 means 2 */
 } nys_pcg_opts;

@@ -196,7 +196,7 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
   const double tol_abs = o.tol_abs ? o.tol : abs_tol;
   const int64_t d = A.d;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
-  const int check = o.check_every > 0 ? o.check_every : 8;
+  const int ahead = o.check_every > 0 ? std::min(o.check_every, 4) : 2;
   const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 2;
   GramPlan pl;
   NYS_TRY(ctx_gram_plan(ctx, A, &pl));
@@ -212,7 +212,6 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
   const double lam_s = (F && r > 0) ? F->lam_host[r - 1] : 0.0;
 
   int total_iters = 0, restarts = 0;
-  int chunk_prev = 1;
   PcgDev h{};
   nys_status status = NYS_OK;
   double true_rr = -1.0;
@@ -246,36 +245,41 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
                                ws.rrpart, -1, 1, tol_rel, tol_abs, st));
     NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, 0,
                                   ws.wwpart, ws.nred, ws.pppart, ws.st, 1, st));
-    int it = 0;
-    double ww_prev = -1.0;
+    // Iterations are enqueued `ahead` at a time beyond the last state the host
+    // has read: the last kernel of each iteration writes the device state into
+    // a pinned host slot, and the host waits only for the oldest iteration in
+    // flight, so the GPU never idles on a host round trip.  Iterations queued
+    // after convergence return at once (every kernel checks PcgDev::done).
+    const int limit = max_iter - total_iters;
+    char* slots = static_cast<char*>(ctx->host_pinned) + kPollOffset;
+    auto enqueue = [&](int k) -> nys_status {
+      NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done));
+      NYS_TRY(launch_reduce_update(0, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
+                                   ws.w, nullptr, ws.wy, k, ws.pppart, ws.nvec, ws.wwpart, nullptr,
+                                   ws.st, st));
+      NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred, nullptr,
+                                 k, 0, tol_rel, tol_abs, st));
+      PcgDev* slot_dev = reinterpret_cast<PcgDev*>(static_cast<char*>(ctx->host_pinned_dev) +
+                                                   kPollOffset + 64 * (k % 4));
+      NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, k,
+                                    ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st, slot_dev));
+      NYS_TRY_HIP(hipEventRecord(ctx->poll_ev[k % 4], st));
+      return NYS_OK;
+    };
+    int it = 0, consumed = 0;
     for (;;) {
-      NYS_TRY(read_pcg_state(ctx, ws, &h));
-      if (h.done || it >= max_iter - total_iters) break;
-      // Enqueue as many iterations as the observed residual decay says are
-      // still needed, minus one, so launches after convergence (which return
-      // at once) stay rare; near the threshold this is one iteration per check.
-      int chunk = 1;
-      if (ww_prev > 0.0 && h.ww > 0.0 && h.ww < ww_prev && h.thr2 > 0.0) {
-        const double rate = std::pow(std::sqrt(h.ww / ww_prev), 1.0 / std::max(1, chunk_prev));
-        const double need = std::log(std::sqrt(h.thr2 / h.ww)) / std::log(std::max(rate, 1e-6));
-        chunk = (int)std::floor(need) - 1;
+      while (it < limit && it - consumed < ahead) {
+        NYS_TRY(enqueue(it));
+        ++it;
       }
-      chunk = std::max(1, std::min(chunk, check));
-      chunk = std::min(chunk, max_iter - total_iters - it);
-      ww_prev = h.ww;
-      chunk_prev = chunk;
-      for (int kk = 0; kk < chunk; ++kk) {
-        const int k = it + kk;
-        NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done));
-        NYS_TRY(launch_reduce_update(0, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
-                                     ws.w, nullptr, ws.wy, k, ws.pppart, ws.nvec, ws.wwpart,
-                                     nullptr, ws.st, st));
-        NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred,
-                                   nullptr, k, 0, tol_rel, tol_abs, st));
-        NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy,
-                                      k, ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st));
+      if (it == consumed) {   // nothing in flight: the iteration limit is reached
+        NYS_TRY(read_pcg_state(ctx, ws, &h));
+        break;
       }
-      it += chunk;
+      NYS_TRY_HIP(hipEventSynchronize(ctx->poll_ev[consumed % 4]));
+      std::memcpy(&h, slots + 64 * (consumed % 4), sizeof(PcgDev));
+      ++consumed;
+      if (h.done) break;
     }
     if (restarts == 0 && used_alt) *used_alt = (h.flags & kFlagAltStart) ? 1 : 0;
     total_iters += h.done ? h.iters : it;
@@ -370,9 +374,19 @@ nys_status nys_ctx_create(int device, void* hip_stream, nys_ctx* out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cu = prop.multiProcessorCount;
-  if (hipHostMalloc(&c->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&c->host_pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return NYS_ERR_NOMEM;
+  }
+  if (hipHostGetDevicePointer(&c->host_pinned_dev, c->host_pinned, 0) != hipSuccess) {
+    nys_ctx_destroy(c);
+    return NYS_ERR_HIP;
+  }
+  for (hipEvent_t& e : c->poll_ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      nys_ctx_destroy(c);
+      return NYS_ERR_HIP;
+    }
   }
   *out = c;
   return NYS_OK;
@@ -391,6 +405,8 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   ctx->admm_ws.release();
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->poll_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return NYS_OK;

@@ -164,6 +164,9 @@ struct AtbKey {
   }
 };
 
+constexpr size_t kPinnedBytes = 65536;     // pinned readback area of a context
+constexpr size_t kPollOffset = 61440;      // PCG polling slots (4 x 64 bytes) in it
+
 struct nys_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -174,7 +177,9 @@ struct nys_ctx_s {
   nys::DevBuf gemm_ws;   // sketch temporaries (T = A Omega, ...)
   nys::DevBuf core_ws;   // FP64 core temporaries
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
-  void* host_pinned = nullptr;  // small pinned readback area
+  void* host_pinned = nullptr;  // pinned readback area of kPinnedBytes
+  void* host_pinned_dev = nullptr;  // the same memory as seen from the device
+  hipEvent_t poll_ev[4] = {};    // PCG state readbacks in flight (see pcg_run)
   AtbKey atb_key;                // which (A, b) the cached A^T b in admm_ws belongs to
   int64_t atb_next_k = -1;       // ... valid for the ADMM step with this counter
   nys::DevBuf hx;                // H_rho x of the last solve (lasso ADMM sequence)
@@ -259,6 +264,7 @@ nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const d
 nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, const double* lam,
                                  double lam_s, double rho, const double* cvec, const double* w,
                                  double* p, double* wy, int k, const double* wwpart, int nww,
-                                 double* pppart, const PcgDev* st, int mode, hipStream_t stream);
+                                 double* pppart, const PcgDev* st, int mode, hipStream_t stream,
+                                 PcgDev* host_slot = nullptr);
 
 }  // namespace nys

@@ -378,9 +378,18 @@ nys_status core_workspace(nys_ctx ctx, int64_t d, int r, CoreWs* w) {
 }
 
 nys_status read_back(nys_ctx ctx, const void* dev, size_t bytes, void* host) {
-  NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
-  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
-  std::memcpy(host, ctx->host_pinned, bytes);
+  // through the pinned area below the polling slots, in pieces if needed
+  const char* src = static_cast<const char*>(dev);
+  char* dst = static_cast<char*>(host);
+  while (bytes > 0) {
+    const size_t n = bytes < kPollOffset ? bytes : kPollOffset;
+    NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, src, n, hipMemcpyDeviceToHost, ctx->stream));
+    NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    std::memcpy(dst, ctx->host_pinned, n);
+    src += n;
+    dst += n;
+    bytes -= n;
+  }
   return NYS_OK;
 }
 

@@ -55,10 +55,20 @@ __global__ __launch_bounds__(256) void k_reduce_update(
   const int grp = tid / RJ;
   const int64_t j = (int64_t)blockIdx.x * RJ + lane;
 
-  double acc = 0.0;
-  if (j < d)
-    for (int g = grp; g < G; g += S) acc += ypart[(int64_t)g * ldy + j];
-  part[grp][lane] = acc;
+  // four independent running sums (rows g, g+S, g+2S, g+3S, ...) keep
+  // several loads in flight; combined in a fixed order
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (j < d) {
+    int g = grp;
+    for (; g + 3 * S < G; g += 4 * S) {
+      a0 += ypart[(int64_t)g * ldy + j];
+      a1 += ypart[(int64_t)(g + S) * ldy + j];
+      a2 += ypart[(int64_t)(g + 2 * S) * ldy + j];
+      a3 += ypart[(int64_t)(g + 3 * S) * ldy + j];
+    }
+    for (; g < G; g += S) a0 += ypart[(int64_t)g * ldy + j];
+  }
+  part[grp][lane] = (a0 + a1) + (a2 + a3);
 
   double alpha = 0.0;
   if (op == 0) {
@@ -183,8 +193,14 @@ __global__ __launch_bounds__(256) void k_precond_update(
     const UT* __restrict__ U, int64_t d, int r, const double* __restrict__ lam, double lam_s,
     double rho, const double* __restrict__ cvec, const double* __restrict__ w,
     double* __restrict__ p, double* __restrict__ wy, int k, const double* __restrict__ wwpart,
-    int nww, double* __restrict__ pppart, const PcgDev* __restrict__ st, int mode) {
-  if (mode != 2 && st->done) return;
+    int nww, double* __restrict__ pppart, const PcgDev* __restrict__ st, int mode,
+    PcgDev* __restrict__ host_slot) {
+  // host_slot (pinned host memory, may be NULL): receives the state at the end
+  // of the iteration, read by the host once the kernel has completed
+  if (mode != 2 && st->done) {
+    if (host_slot != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *host_slot = *st;
+    return;
+  }
   constexpr int VJ = kVecBlock;        // entries of y per workgroup
   constexpr int VS = 256 / VJ;         // slices of the rank index
   __shared__ double g[1024];
@@ -235,7 +251,10 @@ __global__ __launch_bounds__(256) void k_precond_update(
   const double pp = block_sum_value(pj * pj, sh4);
   if (tid == 0) {
     pppart[blockIdx.x] = pp;
-    if (blockIdx.x == 0) wy[mode == 1 ? 0 : k + 1] = wy_new;
+    if (blockIdx.x == 0) {
+      wy[mode == 1 ? 0 : k + 1] = wy_new;
+      if (host_slot != nullptr) *host_slot = *st;
+    }
   }
 }
 
@@ -340,17 +359,18 @@ nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const d
 nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, const double* lam,
                                  double lam_s, double rho, const double* cvec, const double* w,
                                  double* p, double* wy, int k, const double* wwpart, int nww,
-                                 double* pppart, const PcgDev* st, int mode, hipStream_t stream) {
+                                 double* pppart, const PcgDev* st, int mode, hipStream_t stream,
+                                 PcgDev* host_slot) {
   if (r > 1024) return NYS_ERR_INVALID;
   const int grid = nblk(d, kVecBlock);
   if (u32)
     hipLaunchKernelGGL(k_precond_update<float>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const float*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
-                       wwpart, nww, pppart, st, mode);
+                       wwpart, nww, pppart, st, mode, host_slot);
   else
     hipLaunchKernelGGL(k_precond_update<double>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const double*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
-                       wwpart, nww, pppart, st, mode);
+                       wwpart, nww, pppart, st, mode, host_slot);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 

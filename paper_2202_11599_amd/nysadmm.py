@@ -305,7 +305,7 @@ def nys_precond_apply(ctx: Context, F: Factor, rho: float, w: torch.Tensor,
     return y
 
 
-def pcg_opts(tol=1e-6, tol_abs=False, max_iter=1000, check_every=8, true_residual=True,
+def pcg_opts(tol=1e-6, tol_abs=False, max_iter=1000, check_every=0, true_residual=True,
              max_restarts=2) -> PcgOpts:
     return PcgOpts(float(tol), int(bool(tol_abs)), int(max_iter), int(check_every),
                    int(bool(true_residual)), int(max_restarts))
