@@ -93,20 +93,22 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, profile=False)
         torch.cuda.synchronize()
         sketch_s += time.perf_counter() - ts
         ranks.append(F.info()["rank"])
-        opts = N.admm_opts(p.rho, ranks[-1], omega, sketch_prec=prec,
-                           pcg=N.pcg_opts(tol=p.pcg_tol, max_iter=1000))
+        # admm_iters NysADMM iterations with the factor just built (no early stop)
+        opts = N.admm_opts(p.rho, ranks[-1], omega, sketch_prec=prec, max_iter=admm_iters,
+                           pcg=N.pcg_opts(tol=p.pcg_tol, max_iter=1000), factor=F)
         st = N.State(p.d, "cuda")
-        for _k in range(admm_iters):
-            F, info = N.admm_step(ctx, prob, opts, F, st)
-            infos.append((info.pcg_iters, info.status))
-            bad += info.status != N.NYS_OK
+        info = N.admm_solve(ctx, [prob], [opts], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
+        infos.append((info.pcg_iters, info.iters, info.pcg_max, info.eta))
+        bad += info.status != N.NYS_OK
         F.close()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = ctx.profile_stop() if profile else None
-    its = [i for i, _ in infos]
-    return dict(wall=wall, sketch_s=sketch_s, ranks=ranks, pcg_mean=sum(its) / len(its),
-                pcg_max=max(its), solves=len(infos), unconverged=bad, prof=prof)
+    solves = sum(n for _, n, _, _ in infos)
+    return dict(wall=wall, sketch_s=sketch_s, ranks=ranks,
+                pcg_mean=sum(i for i, _, _, _ in infos) / max(solves, 1),
+                pcg_max=max(m for _, _, m, _ in infos), solves=solves, unconverged=bad, prof=prof,
+                eta=infos[-1][3])
 
 
 def cpu_baseline(A, b, omega, p, admm_iters, cpu_iters):
@@ -414,7 +416,7 @@ def main():
             "solves_per_s_excl_sketch": round(plain["solves"] / (plain["wall"] - plain["sketch_s"]), 3),
             "sketch_ms": round(1e3 * plain["sketch_s"] / args.steps, 2),
             "pcg_iters_mean": round(plain["pcg_mean"], 3), "pcg_iters_max": plain["pcg_max"],
-            "unconverged_solves": plain["unconverged"],
+            "unconverged_steps": plain["unconverged"], "kkt_eta_after_step": plain["eta"],
         },
         "gemv_hbm_gbs": round(achieved, 1),
     }
@@ -424,7 +426,7 @@ def main():
             "solves_per_s_excl_sketch": round(mixed["solves"] / (mixed["wall"] - mixed["sketch_s"]), 3),
             "sketch_ms": round(1e3 * mixed["sketch_s"] / args.steps, 2),
             "pcg_iters_mean": round(mixed["pcg_mean"], 3), "rank_final": mixed["ranks"][-1],
-            "unconverged_solves": mixed["unconverged"],
+            "unconverged_steps": mixed["unconverged"], "kkt_eta_after_step": mixed["eta"],
             "vs_plain_fp32": round((mixed["solves"] / mixed["wall"]) / value, 4),
         }
     if not args.no_cpu_baseline:

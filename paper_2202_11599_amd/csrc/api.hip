@@ -1,6 +1,7 @@
 // C ABI: contexts, factors, preconditioner apply and the PCG driver.
 // The sketch entry points live in sketch.hip, the ADMM drivers in admm.hip.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -186,6 +187,31 @@ nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out) {
   return NYS_OK;
 }
 
+// Wait until the kernel of PCG iteration seq-1 has written its state into the
+// pinned slot (sequence number seq in PcgDev::k).  The wait spins on the host
+// memory; every few thousand polls the stream is queried so that a failed
+// stream returns an error, and a stream that has drained without the slot
+// being written is reported as an internal error.
+nys_status wait_slot(hipStream_t st, const char* slot, int seq, PcgDev* out) {
+  const volatile PcgDev* v = reinterpret_cast<const volatile PcgDev*>(slot);
+  for (long n = 1;; ++n) {
+    if (v->k == seq) break;
+    if (n % 4096 == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        if (v->k == seq) break;
+        return NYS_ERR_HIP;
+      }
+      if (e != hipErrorNotReady) return NYS_ERR_HIP;
+    }
+    __builtin_ia32_pause();
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  std::memcpy(out, const_cast<const PcgDev*>(reinterpret_cast<const volatile PcgDev*>(slot)),
+              sizeof(PcgDev));
+  return NYS_OK;
+}
+
 // Algorithm Nystrom PCG (see pcg_solve in nysadmm.h).
 nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
                    nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
@@ -246,12 +272,14 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
     NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, 0,
                                   ws.wwpart, ws.nred, ws.pppart, ws.st, 1, st));
     // Iterations are enqueued `ahead` at a time beyond the last state the host
-    // has read: the last kernel of each iteration writes the device state into
-    // a pinned host slot, and the host waits only for the oldest iteration in
-    // flight, so the GPU never idles on a host round trip.  Iterations queued
-    // after convergence return at once (every kernel checks PcgDev::done).
+    // has read: the last kernel of each iteration writes the device state with
+    // a sequence number into a pinned host slot, and the host waits only for
+    // the oldest iteration in flight, so the GPU never idles on a host round
+    // trip or an event marker.  Iterations queued after convergence return at
+    // once (every kernel checks PcgDev::done).
     const int limit = max_iter - total_iters;
     char* slots = static_cast<char*>(ctx->host_pinned) + kPollOffset;
+    int seqs[4] = {0, 0, 0, 0};
     auto enqueue = [&](int k) -> nys_status {
       NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done));
       NYS_TRY(launch_reduce_update(0, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
@@ -259,11 +287,14 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
                                    ws.st, st));
       NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred, nullptr,
                                  k, 0, tol_rel, tol_abs, st));
+      // sequence numbers are unique per context, so a late write from an
+      // earlier solve's queued iteration can never be taken for this one
+      const int seq = ctx->poll_seq = (ctx->poll_seq % 1000000000) + 1;
+      seqs[k % 4] = seq;
       PcgDev* slot_dev = reinterpret_cast<PcgDev*>(static_cast<char*>(ctx->host_pinned_dev) +
                                                    kPollOffset + 64 * (k % 4));
       NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, k,
-                                    ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st, slot_dev));
-      NYS_TRY_HIP(hipEventRecord(ctx->poll_ev[k % 4], st));
+                                    ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st, slot_dev, seq));
       return NYS_OK;
     };
     int it = 0, consumed = 0;
@@ -276,8 +307,7 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
         NYS_TRY(read_pcg_state(ctx, ws, &h));
         break;
       }
-      NYS_TRY_HIP(hipEventSynchronize(ctx->poll_ev[consumed % 4]));
-      std::memcpy(&h, slots + 64 * (consumed % 4), sizeof(PcgDev));
+      NYS_TRY(wait_slot(st, slots + 64 * (consumed % 4), seqs[consumed % 4], &h));
       ++consumed;
       if (h.done) break;
     }
@@ -382,12 +412,6 @@ nys_status nys_ctx_create(int device, void* hip_stream, nys_ctx* out) {
     nys_ctx_destroy(c);
     return NYS_ERR_HIP;
   }
-  for (hipEvent_t& e : c->poll_ev) {
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      nys_ctx_destroy(c);
-      return NYS_ERR_HIP;
-    }
-  }
   *out = c;
   return NYS_OK;
 }
@@ -405,8 +429,6 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   ctx->admm_ws.release();
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
-  for (hipEvent_t e : ctx->poll_ev)
-    if (e) (void)hipEventDestroy(e);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return NYS_OK;

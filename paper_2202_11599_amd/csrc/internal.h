@@ -179,7 +179,7 @@ struct nys_ctx_s {
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
   void* host_pinned = nullptr;  // pinned readback area of kPinnedBytes
   void* host_pinned_dev = nullptr;  // the same memory as seen from the device
-  hipEvent_t poll_ev[4] = {};    // PCG state readbacks in flight (see pcg_run)
+  int poll_seq = 0;              // last sequence number of a PCG state slot write
   AtbKey atb_key;                // which (A, b) the cached A^T b in admm_ws belongs to
   int64_t atb_next_k = -1;       // ... valid for the ADMM step with this counter
   nys::DevBuf hx;                // H_rho x of the last solve (lasso ADMM sequence)
@@ -265,6 +265,6 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
                                  double lam_s, double rho, const double* cvec, const double* w,
                                  double* p, double* wy, int k, const double* wwpart, int nww,
                                  double* pppart, const PcgDev* st, int mode, hipStream_t stream,
-                                 PcgDev* host_slot = nullptr);
+                                 PcgDev* host_slot = nullptr, int seq = 0);
 
 }  // namespace nys

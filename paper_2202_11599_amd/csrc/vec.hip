@@ -194,11 +194,15 @@ __global__ __launch_bounds__(256) void k_precond_update(
     double rho, const double* __restrict__ cvec, const double* __restrict__ w,
     double* __restrict__ p, double* __restrict__ wy, int k, const double* __restrict__ wwpart,
     int nww, double* __restrict__ pppart, const PcgDev* __restrict__ st, int mode,
-    PcgDev* __restrict__ host_slot) {
+    PcgDev* __restrict__ host_slot, int seq) {
   // host_slot (pinned host memory, may be NULL): receives the state at the end
   // of the iteration, read by the host once the kernel has completed
   if (mode != 2 && st->done) {
-    if (host_slot != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *host_slot = *st;
+    if (host_slot != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+      PcgDev h = *st;
+      h.k = seq;              // sequence number the host waits for
+      *host_slot = h;
+    }
     return;
   }
   constexpr int VJ = kVecBlock;        // entries of y per workgroup
@@ -253,7 +257,11 @@ __global__ __launch_bounds__(256) void k_precond_update(
     pppart[blockIdx.x] = pp;
     if (blockIdx.x == 0) {
       wy[mode == 1 ? 0 : k + 1] = wy_new;
-      if (host_slot != nullptr) *host_slot = *st;
+      if (host_slot != nullptr) {
+        PcgDev h = *st;
+        h.k = seq;            // sequence number the host waits for
+        *host_slot = h;
+      }
     }
   }
 }
@@ -360,17 +368,17 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
                                  double lam_s, double rho, const double* cvec, const double* w,
                                  double* p, double* wy, int k, const double* wwpart, int nww,
                                  double* pppart, const PcgDev* st, int mode, hipStream_t stream,
-                                 PcgDev* host_slot) {
+                                 PcgDev* host_slot, int seq) {
   if (r > 1024) return NYS_ERR_INVALID;
   const int grid = nblk(d, kVecBlock);
   if (u32)
     hipLaunchKernelGGL(k_precond_update<float>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const float*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
-                       wwpart, nww, pppart, st, mode, host_slot);
+                       wwpart, nww, pppart, st, mode, host_slot, seq);
   else
     hipLaunchKernelGGL(k_precond_update<double>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const double*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
-                       wwpart, nww, pppart, st, mode, host_slot);
+                       wwpart, nww, pppart, st, mode, host_slot, seq);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
