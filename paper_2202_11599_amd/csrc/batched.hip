@@ -88,7 +88,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_bgram(
     double pr[CPL][VN], yr[CPL][VN];
 #pragma unroll
     for (int m = 0; m < CPL; ++m) {
-      const int c0 = (tid + m * NT) * VN;
+      const int c0 = col0<T, CPL, ALIGNED, NT>(tid, m);
 #pragma unroll
       for (int v = 0; v < VN; ++v) {
         pr[m][v] = (p != nullptr && c0 + v < d) ? p[c0 + v] : 0.0;
@@ -98,19 +98,22 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_bgram(
     double q = 0.0;
     const int64_t r1 = tl.r1;
     V a0[R][CPL], a1[R][CPL];
-    load_group<T, CPL, R, ALIGNED, NT>(a0, A, tl.r0, r1, d, I.ld, tid);
+    T e0[R][Extra<T>::N], e1[R][Extra<T>::N];
+    load_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, tl.r0, r1, d, I.ld, tid);
     for (int64_t row = tl.r0; row < r1; row += 2 * R) {
-      load_group<T, CPL, R, ALIGNED, NT>(a1, A, row + R, r1, d, I.ld, tid);
+      load_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, r1, d, I.ld, tid);
+      realign_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, row, d, I.ld, tid);
       process_group<T, WAVES, CPL, R>(a0, row, r1, mode, pr, yr, q, aux, nullptr, red, buf, tid);
       if (row + R >= r1) break;
-      load_group<T, CPL, R, ALIGNED, NT>(a0, A, row + 2 * R, r1, d, I.ld, tid);
+      load_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, row + 2 * R, r1, d, I.ld, tid);
+      realign_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, d, I.ld, tid);
       process_group<T, WAVES, CPL, R>(a1, row + R, r1, mode, pr, yr, q, aux, nullptr, red, buf,
                                       tid);
     }
     double* yp = I.ypart + (int64_t)tl.slot * I.ldy;
 #pragma unroll
     for (int m = 0; m < CPL; ++m) {
-      const int c0 = (tid + m * NT) * VN;
+      const int c0 = col0<T, CPL, ALIGNED, NT>(tid, m);
 #pragma unroll
       for (int v = 0; v < VN; ++v)
         if (c0 + v < d) yp[c0 + v] = yr[m][v];
@@ -533,6 +536,7 @@ std::vector<Bucket> bucket_candidates(const Bucket& base, int d_max, int num_cu)
   for (auto& sh : shapes) {
     const int c = cover_of(sh[0], sh[1], vn);
     if (c < d_max || c > 2 * best) continue;
+    if (!base.aligned && sh[2] == 8) continue;   // realignment state would spill
     const int mx = std::max(1, 8 / sh[0]);
     for (int per_cu : {std::max(1, mx / 2), mx})
       for (int64_t tr : {256, 1024}) {

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_gram(
   double pr[CPL][VN], yr[CPL][VN];
 #pragma unroll
   for (int m = 0; m < CPL; ++m) {
-    const int c0 = (tid + m * NT) * VN;
+    const int c0 = col0<T, CPL, ALIGNED, NT>(tid, m);
 #pragma unroll
     for (int v = 0; v < VN; ++v) {
       pr[m][v] = (!tonly && c0 + v < d) ? p[c0 + v] : 0.0;
@@ -60,19 +60,22 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_gram(
   int buf = 0;
 
   V a0[R][CPL], a1[R][CPL];
-  load_group<T, CPL, R, ALIGNED, NT>(a0, A, r0, r1, d, ld, tid);
+  T e0[R][Extra<T>::N], e1[R][Extra<T>::N];
+  load_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, r0, r1, d, ld, tid);
   for (int64_t row = r0; row < r1; row += 2 * R) {
-    load_group<T, CPL, R, ALIGNED, NT>(a1, A, row + R, r1, d, ld, tid);
+    load_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, r1, d, ld, tid);
+    realign_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, row, d, ld, tid);
     process_group<T, WAVES, CPL, R>(a0, row, r1, mode, pr, yr, q, aux, auxout, red, buf, tid);
     if (row + R >= r1) break;
-    load_group<T, CPL, R, ALIGNED, NT>(a0, A, row + 2 * R, r1, d, ld, tid);
+    load_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, row + 2 * R, r1, d, ld, tid);
+    realign_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, d, ld, tid);
     process_group<T, WAVES, CPL, R>(a1, row + R, r1, mode, pr, yr, q, aux, auxout, red, buf, tid);
   }
 
   double* yp = ypart + (int64_t)blockIdx.x * ldy;
 #pragma unroll
   for (int m = 0; m < CPL; ++m) {
-    const int c0 = (tid + m * NT) * VN;
+    const int c0 = col0<T, CPL, ALIGNED, NT>(tid, m);
 #pragma unroll
     for (int v = 0; v < VN; ++v)
       if (c0 + v < d) yp[c0 + v] = yr[m][v];
@@ -144,10 +147,14 @@ std::vector<GramPlan> gram_candidates(const nys_dense& A, int num_cu) {
     const int64_t cover = (int64_t)sh[0] * 64 * sh[1] * vn;
     if (cover >= need && (best_cover < 0 || cover < best_cover)) best_cover = cover;
   }
+  // unaligned rows carry the realignment state; groups of 8 rows then spill
+  const int esize = A.dtype == NYS_F64 ? 8 : 4;
+  const bool aligned = ((uintptr_t)A.data % 16 == 0) && ((A.ld * esize) % 16 == 0);
   std::vector<GramPlan> out;
   for (auto& sh : shapes) {
     const int64_t cover = (int64_t)sh[0] * 64 * sh[1] * vn;
     if (cover < need || cover > 2 * std::max<int64_t>(best_cover, 1)) continue;
+    if (!aligned && sh[2] == 8) continue;
     const int max_per_cu = std::max(1, 8 / sh[0]);
     for (int per_cu : {max_per_cu / 2, max_per_cu}) {
       if (per_cu < 1) continue;
@@ -171,10 +178,13 @@ GramPlan make_gram_plan(const nys_dense& A, int num_cu) {
   const int vn = A.dtype == NYS_F64 ? 2 : 4;
   const int64_t d = A.d;
   static const int pref[][3] = {{1, 2, 8}, {2, 2, 8}, {2, 4, 2}, {4, 4, 2}, {8, 2, 4}, {8, 4, 2}};
+  static const int pref_u[][3] = {{1, 2, 4}, {2, 2, 4}, {2, 4, 2}, {4, 4, 2}, {8, 2, 4}, {8, 4, 2}};
+  const int esize = A.dtype == NYS_F64 ? 8 : 4;
+  const bool aligned = ((uintptr_t)A.data % 16 == 0) && ((A.ld * esize) % 16 == 0);
   pl.waves = 8;
   pl.cpl = 4;
   pl.rows = 2;
-  for (auto& c : pref) {
+  for (auto& c : (aligned ? pref : pref_u)) {
     if ((int64_t)c[0] * 64 * c[1] * vn >= d) {
       pl.waves = c[0];
       pl.cpl = c[1];

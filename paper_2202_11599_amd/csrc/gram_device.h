@@ -29,10 +29,38 @@ __device__ __forceinline__ double sigm(double t) {
 }
 
 
+// First column of chunk m of thread tid.  Rows that are 16-byte aligned are
+// read chunk-interleaved across the workgroup (consecutive threads, then the
+// next chunk); unaligned rows give each wave a contiguous block of CPL chunks,
+// so that re-aligning a chunk only needs the next lane of the same wave
+// (except at the end of the wave's block).
+template <typename T, int CPL, bool ALIGNED, int NT>
+__device__ __forceinline__ int col0(int tid, int m) {
+  constexpr int VN = Chunk<T>::N;
+  if (ALIGNED) return (tid + m * NT) * VN;
+  return (((tid >> 6) * CPL + m) * 64 + (tid & 63)) * VN;
+}
+
+// Offset (in elements) of a row start from the previous 16-byte boundary.
+template <typename T>
+__device__ __forceinline__ int row_offset(const T* arow) {
+  return (int)((reinterpret_cast<uintptr_t>(arow) / sizeof(T)) % Chunk<T>::N);
+}
+
+template <typename T>
+struct Extra {
+  static constexpr int N = Chunk<T>::N - 1;   // elements the last lane of a wave fetches
+};
+
+// Issue the loads of R rows.  Aligned rows: one 16-byte load per chunk.
+// Unaligned rows: each lane loads the 16-byte block at row_start - o + col
+// (o = row_offset), which always holds at least one element of the row, and
+// lane 63 also loads the Extra<T>::N elements after its last chunk; the blocks
+// are shifted into column order by realign_group once they have arrived.
 template <typename T, int CPL, int R, bool ALIGNED, int NT>
 __device__ __forceinline__ void load_group(
-    typename Chunk<T>::V (&a)[R][CPL], const T* __restrict__ A, int64_t row, int64_t r1, int d,
-    int64_t ld, int tid) {
+    typename Chunk<T>::V (&a)[R][CPL], T (&ex)[R][Extra<T>::N], const T* __restrict__ A,
+    int64_t row, int64_t r1, int d, int64_t ld, int tid) {
   constexpr int VN = Chunk<T>::N;
   typedef typename Chunk<T>::V V;
 #pragma unroll
@@ -40,19 +68,91 @@ __device__ __forceinline__ void load_group(
     const int64_t rr = row + i;
     const bool ok = rr < r1;
     const T* arow = A + rr * ld;
+    if (ALIGNED) {
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        const int c0 = col0<T, CPL, ALIGNED, NT>(tid, m);
+        V val = (V)(T)0;
+        if (ok && c0 < d) {
+          if (c0 + VN <= d) {
+            val = __builtin_nontemporal_load(reinterpret_cast<const V*>(arow + c0));
+          } else {
+#pragma unroll
+            for (int v = 0; v < VN; ++v) val[v] = (c0 + v < d) ? arow[c0 + v] : (T)0;
+          }
+        }
+        a[i][m] = val;
+      }
+    } else {
+      const int o = row_offset(arow);
+      const T* base = arow - o;
+#pragma unroll
+      for (int m = 0; m < CPL; ++m) {
+        const int c0 = col0<T, CPL, ALIGNED, NT>(tid, m);
+        V val = (V)(T)0;
+        // the block holds row columns c0 - o .. c0 - o + VN - 1
+        if (ok && c0 < d + o) val = __builtin_nontemporal_load(reinterpret_cast<const V*>(base + c0));
+        a[i][m] = val;
+      }
+      const int cl = col0<T, CPL, ALIGNED, NT>(tid, CPL - 1);
+#pragma unroll
+      for (int k = 0; k < Extra<T>::N; ++k) {
+        const int c = cl + 1 + k;
+        ex[i][k] = (ok && (tid & 63) == 63 && c < d) ? arow[c] : (T)0;
+      }
+    }
+  }
+}
+
+// Shift the blocks of unaligned rows into column order: column c0 + v is
+// component v + o of the lane's block, or component v + o - VN of the next
+// lane's block (the next chunk's lane 0 for lane 63, or the prefetched extra
+// elements at the end of the wave's block).  Columns >= d become 0.
+template <typename T, int CPL, int R, bool ALIGNED, int NT>
+__device__ __forceinline__ void realign_group(typename Chunk<T>::V (&a)[R][CPL],
+                                              const T (&ex)[R][Extra<T>::N],
+                                              const T* __restrict__ A, int64_t row, int d,
+                                              int64_t ld, int tid) {
+  if (ALIGNED) return;
+  constexpr int VN = Chunk<T>::N;
+  typedef typename Chunk<T>::V V;
+  const int lane = tid & 63;
+  const int src = (lane + 1) & 63;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int o = row_offset(A + (row + i) * ld);
+    if (o == 0) continue;   // uniform across the wave
 #pragma unroll
     for (int m = 0; m < CPL; ++m) {
-      const int c0 = (tid + m * NT) * VN;
-      V val = (V)(T)0;
-      if (ok && c0 < d) {
-        if (ALIGNED && c0 + VN <= d) {
-          val = __builtin_nontemporal_load(reinterpret_cast<const V*>(arow + c0));
-        } else {
+      const V cur = a[i][m];
+      // lane 0 hands its next-chunk block to lane 63; others hand their own
+      V give = cur;
+      if (m + 1 < CPL && lane == 0) give = a[i][m + 1];
+      V nb;
 #pragma unroll
-          for (int v = 0; v < VN; ++v) val[v] = (c0 + v < d) ? arow[c0 + v] : (T)0;
+      for (int v = 0; v < VN; ++v) nb[v] = __shfl(give[v], src, 64);
+      if (m == CPL - 1 && lane == 63) {
+        // next block components k < o are columns c0 + VN - o + k = cl + 1 + (VN - o + k - 1)
+#pragma unroll
+        for (int k = 0; k < VN - 1; ++k) {
+          T val = (T)0;
+#pragma unroll
+          for (int j = 0; j < Extra<T>::N; ++j)
+            if (j == VN - o + k - 1) val = ex[i][j];
+          if (k < o) nb[k] = val;
         }
       }
-      a[i][m] = val;
+      const int c0 = col0<T, CPL, ALIGNED, NT>(tid, m);
+      V out;
+#pragma unroll
+      for (int v = 0; v < VN; ++v) {
+        T val = (T)0;
+#pragma unroll
+        for (int sft = 1; sft < VN; ++sft)
+          if (sft == o) val = (v + sft < VN) ? cur[(v + sft) % VN] : nb[(v + sft) % VN];
+        out[v] = (c0 + v < d) ? val : (T)0;
+      }
+      a[i][m] = out;
     }
   }
 }

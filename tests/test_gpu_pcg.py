@@ -38,31 +38,39 @@ def ctx(N):
     c.close()
 
 
-def padded(A64: torch.Tensor, dtype, ld: int):
-    """A stored with leading dimension ld >= d (a view into an (n, ld) buffer)."""
+def padded(A64: torch.Tensor, dtype, ld: int, off: int = 0):
+    """A stored with leading dimension ld >= d + off (a view into an (n, ld)
+    buffer starting at column off, so off > 0 moves the first row off the
+    16-byte grid)."""
     n, d = A64.shape
     buf = torch.zeros(n, ld, dtype=dtype)
-    buf[:, :d] = A64.to(dtype)
-    return buf.to(DEV)[:, :d]
+    buf[:, off:off + d] = A64.to(dtype)
+    return buf.to(DEV)[:, off:off + d]
 
 
 SHAPES = [
-    # n, d, dtype, ld, with_D
-    (2000, 500, torch.float64, 500, False),
-    (1000, 37, torch.float32, 37, True),      # ragged d, rows not 16-byte aligned
-    (513, 129, torch.float32, 132, False),    # padded rows, ragged tail
-    (300, 4000, torch.float32, 4000, True),   # widest fused layout used by the workloads
-    (77, 1, torch.float64, 1, False),
-    (1500, 2001, torch.float64, 2002, True),
-    (4097, 1023, torch.float32, 1024, False),
+    # n, d, dtype, ld, with_D, column offset of the view
+    (2000, 500, torch.float64, 500, False, 0),
+    (1000, 37, torch.float32, 37, True, 0),      # ragged d, rows not 16-byte aligned
+    (513, 129, torch.float32, 132, False, 0),    # padded rows, ragged tail
+    (300, 4000, torch.float32, 4000, True, 0),   # widest fused layout used by the workloads
+    (77, 1, torch.float64, 1, False, 0),
+    (1500, 2001, torch.float64, 2002, True, 0),
+    (4097, 1023, torch.float32, 1024, False, 0),
+    # unaligned rows over several waves and chunks: every row offset occurs
+    (3001, 2999, torch.float32, 2999, True, 0),
+    (1203, 1023, torch.float64, 1023, False, 0),
+    (800, 700, torch.float32, 703, True, 1),     # first row 4 bytes off the grid
+    (640, 3333, torch.float32, 3336, False, 3),
+    (999, 255, torch.float64, 257, True, 1),
 ]
 
 
-@pytest.mark.parametrize("n,d,dtype,ld,with_D", SHAPES)
-def test_hessian_apply_parity(N, ctx, n, d, dtype, ld, with_D):
-    print(f"[hessian_apply] n={n} d={d} {dtype} ld={ld} D={with_D}", flush=True)
+@pytest.mark.parametrize("n,d,dtype,ld,with_D,off", SHAPES)
+def test_hessian_apply_parity(N, ctx, n, d, dtype, ld, with_D, off):
+    print(f"[hessian_apply] n={n} d={d} {dtype} ld={ld} off={off} D={with_D}", flush=True)
     A64 = synth.gaussian((n, d), seed=n + d)
-    A = padded(A64, dtype, ld)
+    A = padded(A64, dtype, ld, off)
     Aup = A.to(torch.float64).cpu().numpy()
     D = torch.rand(n, dtype=torch.float64, generator=torch.Generator().manual_seed(3)) if with_D else None
     p = synth.gaussian((d,), seed=7)
