@@ -96,58 +96,76 @@ __global__ __launch_bounds__(256) void k_split_reduce(int M, int N, int S,
 }
 
 // Upper Cholesky factor C (C^T C = M) in place, row-major with leading
-// dimension ld, lower triangle set to zero.  One workgroup of 1024 threads:
-// at step j, row j of C is formed from the rows above it,
-//   C(j,k) = (M(j,k) - sum_{i<j} C(i,j) C(i,k)) / C(j,j),   k >= j,
-// with g = 1024 / (r rounded up to a power of two) threads per column k, each
-// summing every g-th i, the g partial sums added in a fixed order.
-// *fail = 1 on a non-positive or non-finite pivot.
+// dimension ld, lower triangle set to zero; only the upper triangle of M is
+// read.  One workgroup of 1024 threads, right-looking by blocks of kCB rows:
+// the diagonal block is factored in LDS, the block row of C is formed by
+// forward substitution against it (one thread per column), and the trailing
+// upper triangle takes the rank-kCB update.  *fail = 1 on a non-positive or
+// non-finite pivot.
+constexpr int kCB = 32;
+
 __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int r, int ld,
-                                                     int g, int* __restrict__ fail) {
-  __shared__ double part[1024];
-  __shared__ double piv;
+                                                     int* __restrict__ fail) {
+  __shared__ double C[kCB][kCB + 1];
+  __shared__ double rowv[kCB];
   __shared__ int bad;
   const int tid = threadIdx.x;
-  const int cols = 1024 / g;          // columns covered per pass
-  const int sub = tid / cols;         // which i-slice this thread sums
-  const int kc = tid % cols;
   if (tid == 0) bad = 0;
   __syncthreads();
-  for (int j = 0; j < r; ++j) {
-    // columns k = j .. r-1 in passes of `cols`
-    for (int k0 = j; k0 < r; k0 += cols) {
-      const int k = k0 + kc;
-      double dot = 0.0;
-      if (k < r) {
-        for (int i = sub; i < j; i += g) dot = fma(M[(int64_t)i * ld + j], M[(int64_t)i * ld + k], dot);
-      }
-      part[tid] = dot;
-      __syncthreads();
-      if (sub == 0 && k < r) {
-        double t = 0.0;
-        for (int h = 0; h < g; ++h) t += part[h * cols + kc];
-        if (k == j) {
-          const double sj = M[(int64_t)j * ld + j] - t;
-          if (!(sj > 0.0) || !isfinite(sj)) {
-            bad = 1;
-            piv = 1.0;
-          } else {
-            piv = sqrt(sj);
-          }
-        }
-        part[kc] = t;     // the reduced dot of column k (slot sub 0)
+  for (int kb = 0; kb < r; kb += kCB) {
+    const int b = (r - kb < kCB) ? r - kb : kCB;
+    const int nrest = r - kb - b;
+    for (int e = tid; e < b * b; e += 1024) {
+      const int i = e / b, j = e % b;
+      C[i][j] = (j >= i) ? M[(int64_t)(kb + i) * ld + kb + j] : 0.0;
+    }
+    __syncthreads();
+    // diagonal block: row i of the factor, then the update of the block below it
+    for (int i = 0; i < b; ++i) {
+      if (tid >= i && tid < b) {
+        const double dii = C[i][i];
+        if (tid == i && (!(dii > 0.0) || !isfinite(dii))) bad = 1;
+        const double piv = sqrt(fabs(dii));
+        rowv[tid] = (tid == i) ? piv : C[i][tid] / piv;
       }
       __syncthreads();
       if (bad) break;
-      if (sub == 0 && k < r) {
-        if (k == j)
-          M[(int64_t)j * ld + j] = piv;
-        else
-          M[(int64_t)j * ld + k] = (M[(int64_t)j * ld + k] - part[kc]) / piv;
+      if (tid >= i && tid < b) C[i][tid] = rowv[tid];
+      for (int e = tid; e < b * b; e += 1024) {
+        const int p = e / b, q = e % b;
+        if (p > i && q >= p) C[p][q] -= rowv[p] * rowv[q];
       }
       __syncthreads();
     }
     if (bad) break;
+    for (int e = tid; e < b * b; e += 1024) {
+      const int i = e / b, j = e % b;
+      if (j >= i) M[(int64_t)(kb + i) * ld + kb + j] = C[i][j];
+    }
+    // block row: C_kk^T X = M[kb.., kb+b..], one column per thread
+    for (int jc = tid; jc < nrest; jc += 1024) {
+      const int64_t j = kb + b + jc;
+      double* col = M + (int64_t)kb * ld + j;   // column j of the block row, stride ld
+      for (int i = 0; i < b; ++i) {
+        double sacc = col[(int64_t)i * ld];
+        for (int l = 0; l < i; ++l) sacc = fma(-C[l][i], col[(int64_t)l * ld], sacc);
+        col[(int64_t)i * ld] = sacc / C[i][i];
+      }
+    }
+    __syncthreads();
+    // trailing upper triangle: M[p][q] -= sum_i X[i][p] X[i][q], p <= q
+    const int64_t nt = (int64_t)nrest * nrest;
+    for (int64_t e = tid; e < nt; e += 1024) {
+      const int pp = (int)(e / nrest), qq = (int)(e % nrest);
+      if (qq < pp) continue;
+      const int64_t p = kb + b + pp, q = kb + b + qq;
+      double sacc = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < b; ++i)
+        sacc = fma(M[(int64_t)(kb + i) * ld + p], M[(int64_t)(kb + i) * ld + q], sacc);
+      M[p * ld + q] -= sacc;
+    }
+    __syncthreads();
   }
   if (bad) {
     if (tid == 0) *fail = 1;
@@ -419,6 +437,24 @@ __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__
 }
 
 // *out = trace of the R x R matrix (one workgroup)
+// flag = 1 if some off-diagonal pair of G fails the rotation criterion of
+// k_jacobi_solve (a further sweep would rotate); 0 stays otherwise.  The
+// updated G is symmetric only up to the rounding of the tile products, and a
+// pair block reads whichever of G(i,j), G(j,i) its local order puts above the
+// diagonal, so the pair counts as converged when either entry passes.
+__global__ __launch_bounds__(256) void k_jacobi_check(const double* __restrict__ G, int R,
+                                                     const double* __restrict__ gnorm,
+                                                     int* __restrict__ flag) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)R * R) return;
+  const int i = (int)(e / R), j = (int)(e % R);
+  if (j <= i) return;
+  const double floor_abs = kJacTol * (*gnorm);
+  const double apq = fmin(fabs(G[e]), fabs(G[(int64_t)j * R + i]));
+  const double app = G[(int64_t)i * R + i], aqq = G[(int64_t)j * R + j];
+  if (apq > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) *flag = 1;
+}
+
 __global__ __launch_bounds__(256) void k_trace(const double* __restrict__ G, int R,
                                                double* __restrict__ out) {
   __shared__ double red[4];
@@ -478,9 +514,10 @@ nys_status gemm64(hipStream_t st, int M, int N, int K, const void* A, bool a_f32
                   size_t split_ws_elems, const double* wk) {
   if (M <= 0 || N <= 0) return NYS_OK;
   const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  // split K (chunks of >= 128) until about four workgroups per CU are busy
   int S = 1;
-  if (K > 2048 && split_ws != nullptr) {
-    S = std::min((K + 1023) / 1024, std::max(1, 512 / (tm * tn)));
+  if (K > 256 && split_ws != nullptr) {
+    S = std::min((K + 127) / 128, std::max(1, 1024 / (tm * tn)));
     while (S > 1 && (size_t)S * M * N > split_ws_elems) --S;
   }
   int kchunk = (K + S - 1) / S;
@@ -510,10 +547,7 @@ nys_status gemm64(hipStream_t st, int M, int N, int K, const void* A, bool a_f32
 
 nys_status chol_upper(hipStream_t st, double* M, int r, int ld, int* fail) {
   if (r > 1024) return NYS_ERR_INVALID;
-  int p2 = 1;
-  while (p2 < r) p2 *= 2;
-  const int g = std::max(1, 1024 / p2);
-  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, st, M, r, ld, g, fail);
+  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, st, M, r, ld, fail);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
@@ -559,8 +593,10 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
   hipLaunchKernelGGL(k_pad, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, G, r, ld, G0, R);
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, G0, R, gnorm);
   hipLaunchKernelGGL(k_eye, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, V, R);
-  if (hipMemsetAsync(counters, 0, sizeof(int) * (max_sweeps + 1), st) != hipSuccess)
-    return NYS_ERR_HIP;
+  // counters[s]: pair blocks that rotated in sweep s; counters[64 + s]: 1 if
+  // the matrix after sweep s still fails the criterion somewhere
+  if (max_sweeps > 60) return NYS_ERR_INVALID;
+  if (hipMemsetAsync(counters, 0, sizeof(int) * 128, st) != hipSuccess) return NYS_ERR_HIP;
   int sweeps = 0;
   bool converged = false;
   for (int s = 0; s < max_sweeps; ++s) {
@@ -572,10 +608,12 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
       std::swap(G0, G1);
     }
     ++sweeps;
-    // a sweep without any significant rotation means G0 is diagonal to the
-    // tolerance; checking after every sweep means no launch is ever skipped
-    // on the device, so the host-side buffer swap stays in step
-    if (hipMemcpyAsync(host_pinned, counters + s, sizeof(int), hipMemcpyDeviceToHost, st) !=
+    // converged when every off-diagonal pair passes the rotation criterion,
+    // i.e. when the next sweep would not rotate (it is not run); checking
+    // after every sweep keeps the host-side buffer swap in step
+    hipLaunchKernelGGL(k_jacobi_check, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, G0,
+                       R, gnorm, counters + 64 + s);
+    if (hipMemcpyAsync(host_pinned, counters + 64 + s, sizeof(int), hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return NYS_ERR_HIP;
