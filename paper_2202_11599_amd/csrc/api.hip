@@ -98,14 +98,15 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
     return launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream);
   if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
     for (int i = 0; i < 2; ++i) {
+      // timing-only events: no system-scope fence (cache writeback) at each
+      // record, which would lengthen the measured kernel itself
       hipEvent_t e;
-      NYS_TRY_HIP(hipEventCreate(&e));
+      NYS_TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       ctx->prof_ev.push_back(e);
     }
   }
-  NYS_TRY_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used], ctx->stream));
-  NYS_TRY(launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream));
-  NYS_TRY_HIP(hipEventRecord(ctx->prof_ev[ctx->prof_used + 1], ctx->stream));
+  NYS_TRY(launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream,
+                      ctx->prof_ev[ctx->prof_used], ctx->prof_ev[ctx->prof_used + 1]));
   ctx->prof_used += 2;
   return NYS_OK;
 }

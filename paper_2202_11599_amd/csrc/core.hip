@@ -103,10 +103,12 @@ __global__ __launch_bounds__(256) void k_split_reduce(int M, int N, int S,
 // upper triangle takes the rank-kCB update.  *fail = 1 on a non-positive or
 // non-finite pivot.
 constexpr int kCB = 32;
+constexpr int kCW = 256;   // block-row columns staged in LDS at a time
 
 __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int r, int ld,
                                                      int* __restrict__ fail) {
   __shared__ double C[kCB][kCB + 1];
+  __shared__ double P[kCB][kCW + 1];
   __shared__ double rowv[kCB];
   __shared__ int bad;
   const int tid = threadIdx.x;
@@ -142,28 +144,52 @@ __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int
       const int i = e / b, j = e % b;
       if (j >= i) M[(int64_t)(kb + i) * ld + kb + j] = C[i][j];
     }
-    // block row: C_kk^T X = M[kb.., kb+b..], one column per thread
-    for (int jc = tid; jc < nrest; jc += 1024) {
-      const int64_t j = kb + b + jc;
-      double* col = M + (int64_t)kb * ld + j;   // column j of the block row, stride ld
-      for (int i = 0; i < b; ++i) {
-        double sacc = col[(int64_t)i * ld];
-        for (int l = 0; l < i; ++l) sacc = fma(-C[l][i], col[(int64_t)l * ld], sacc);
-        col[(int64_t)i * ld] = sacc / C[i][i];
+    // block row: C_kk^T X = M[kb.., kb+b..], one column per thread, in LDS
+    // chunks of kCW columns; the trailing update reads the block row from LDS
+    // when it fits in one chunk, else from global memory
+    for (int c0 = 0; c0 < nrest; c0 += kCW) {
+      const int nc = (nrest - c0 < kCW) ? nrest - c0 : kCW;
+      for (int e = tid; e < b * nc; e += 1024) {
+        const int i = e / nc, jj = e % nc;
+        P[i][jj] = M[(int64_t)(kb + i) * ld + kb + b + c0 + jj];
       }
+      __syncthreads();
+      if (tid < nc) {
+        for (int i = 0; i < b; ++i) {
+          double sacc = P[i][tid];
+          for (int l = 0; l < i; ++l) sacc = fma(-C[l][i], P[l][tid], sacc);
+          P[i][tid] = sacc / C[i][i];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < b * nc; e += 1024) {
+        const int i = e / nc, jj = e % nc;
+        M[(int64_t)(kb + i) * ld + kb + b + c0 + jj] = P[i][jj];
+      }
+      if (nrest > kCW) __syncthreads();
     }
-    __syncthreads();
     // trailing upper triangle: M[p][q] -= sum_i X[i][p] X[i][q], p <= q
     const int64_t nt = (int64_t)nrest * nrest;
-    for (int64_t e = tid; e < nt; e += 1024) {
-      const int pp = (int)(e / nrest), qq = (int)(e % nrest);
-      if (qq < pp) continue;
-      const int64_t p = kb + b + pp, q = kb + b + qq;
-      double sacc = 0.0;
+    if (nrest <= kCW) {
+      for (int64_t e = tid; e < nt; e += 1024) {
+        const int pp = (int)(e / nrest), qq = (int)(e % nrest);
+        if (qq < pp) continue;
+        double sacc = 0.0;
+        for (int i = 0; i < b; ++i) sacc = fma(P[i][pp], P[i][qq], sacc);
+        M[(int64_t)(kb + b + pp) * ld + kb + b + qq] -= sacc;
+      }
+    } else {
+      __syncthreads();
+      for (int64_t e = tid; e < nt; e += 1024) {
+        const int pp = (int)(e / nrest), qq = (int)(e % nrest);
+        if (qq < pp) continue;
+        const int64_t p = kb + b + pp, q = kb + b + qq;
+        double sacc = 0.0;
 #pragma unroll 8
-      for (int i = 0; i < b; ++i)
-        sacc = fma(M[(int64_t)(kb + i) * ld + p], M[(int64_t)(kb + i) * ld + q], sacc);
-      M[p * ld + q] -= sacc;
+        for (int i = 0; i < b; ++i)
+          sacc = fma(M[(int64_t)(kb + i) * ld + p], M[(int64_t)(kb + i) * ld + q], sacc);
+        M[p * ld + q] -= sacc;
+      }
     }
     __syncthreads();
   }

@@ -15,6 +15,8 @@
 // wavefronts through LDS (one barrier per group, double-buffered).  The group
 // stays in registers for the A^T pass.
 #include "internal.h"
+#include <hip/hip_ext.h>
+
 #include "gram_device.h"
 
 #include <algorithm>
@@ -86,26 +88,37 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_gram(
 template <typename T, int WAVES, int CPL, int R>
 nys_status launch_r(const nys_dense& A, const GramPlan& pl, int mode, const double* p,
                     const double* aux, double* auxout, double* ypart, double* qpart,
-                    const int* done, hipStream_t st) {
+                    const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const T* a = static_cast<const T*>(A.data);
-  if (pl.aligned)
+  // with events, the dispatch itself stamps the kernel's start and end
+  if (ev0 != nullptr) {
+    if (pl.aligned)
+      hipExtLaunchKernelGGL((k_gram<T, WAVES, CPL, R, true>), dim3(pl.grid), dim3(WAVES * 64), 0,
+                            st, ev0, ev1, 0, a, A.n, (int)A.d, A.ld, pl.rows_per_wg, mode, p,
+                            aux, auxout, ypart, pl.ldy, qpart, done);
+    else
+      hipExtLaunchKernelGGL((k_gram<T, WAVES, CPL, R, false>), dim3(pl.grid), dim3(WAVES * 64),
+                            0, st, ev0, ev1, 0, a, A.n, (int)A.d, A.ld, pl.rows_per_wg, mode, p,
+                            aux, auxout, ypart, pl.ldy, qpart, done);
+  } else if (pl.aligned) {
     hipLaunchKernelGGL((k_gram<T, WAVES, CPL, R, true>), dim3(pl.grid), dim3(WAVES * 64), 0, st,
                        a, A.n, (int)A.d, A.ld, pl.rows_per_wg, mode, p, aux, auxout, ypart,
                        pl.ldy, qpart, done);
-  else
+  } else {
     hipLaunchKernelGGL((k_gram<T, WAVES, CPL, R, false>), dim3(pl.grid), dim3(WAVES * 64), 0, st,
                        a, A.n, (int)A.d, A.ld, pl.rows_per_wg, mode, p, aux, auxout, ypart,
                        pl.ldy, qpart, done);
+  }
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
 template <typename T>
 nys_status launch_dt(const nys_dense& A, const GramPlan& pl, int mode, const double* p,
                      const double* aux, double* auxout, double* ypart, double* qpart,
-                     const int* done, hipStream_t st) {
+                     const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
 #define NYS_CASE(W, C, RR)                                                                  \
   if (pl.waves == W && pl.cpl == C && pl.rows == RR)                                        \
-    return launch_r<T, W, C, RR>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st);
+    return launch_r<T, W, C, RR>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1);
   NYS_CASE(1, 2, 4) NYS_CASE(2, 2, 4) NYS_CASE(4, 2, 4) NYS_CASE(8, 2, 4)
   NYS_CASE(1, 2, 8) NYS_CASE(2, 2, 8) NYS_CASE(4, 2, 8) NYS_CASE(8, 2, 8)
   NYS_CASE(1, 4, 2) NYS_CASE(2, 4, 2) NYS_CASE(4, 4, 2) NYS_CASE(8, 4, 2)
@@ -210,14 +223,14 @@ GramPlan make_gram_plan(const nys_dense& A, int num_cu) {
 
 nys_status launch_gram(const nys_dense& A, const GramPlan& pl, int mode, const double* p,
                        const double* aux, double* auxout, double* ypart, double* qpart,
-                       const int* done, hipStream_t st) {
+                       const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const int vn = A.dtype == NYS_F64 ? 2 : 4;
   if ((int64_t)pl.waves * 64 * pl.cpl * vn < A.d) return NYS_ERR_INVALID;
   if (A.n == 0 || pl.grid == 0) return NYS_OK;
   if (A.dtype == NYS_F64)
-    return launch_dt<double>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st);
+    return launch_dt<double>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1);
   if (A.dtype == NYS_F32)
-    return launch_dt<float>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st);
+    return launch_dt<float>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1);
   return NYS_ERR_INVALID;
 }
 

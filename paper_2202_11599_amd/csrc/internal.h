@@ -222,7 +222,8 @@ std::vector<GramPlan> gram_candidates(const nys_dense& A, int num_cu);
 // Launch the fused pass  t = A p;  s = mode(t);  y_g = sum_{rows of g} s_i A_i.
 nys_status launch_gram(const nys_dense& A, const GramPlan& plan, int mode, const double* p,
                        const double* aux, double* auxout, double* ypart, double* qpart,
-                       const int* done, hipStream_t st);
+                       const int* done, hipStream_t st,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // ---- vec.hip
 constexpr int kVecBlock = 32;    // entries of y per workgroup of the preconditioner update
