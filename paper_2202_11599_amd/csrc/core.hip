@@ -280,7 +280,8 @@ constexpr int kJB = 16;        // block size
 constexpr int kJP = 2 * kJB;   // pair block size
 constexpr int kJT = 256;       // threads of the solve and apply workgroups
 constexpr int kJE = kJP * kJP / kJT;   // tile elements per thread
-constexpr int kJR = kJB * kJP / kJT;   // rotation updates per thread and phase
+constexpr int kJR = kJB * kJP / kJT;   // Q column updates per thread and step
+static_assert(kJB * kJB == kJT, "one 2x2 block of the pair block per thread");
 constexpr double kJacTol = 1e-15;
 
 // Round-robin pairing of nb blocks (nb even): round t, pair k -> (a, b).
@@ -345,36 +346,41 @@ __global__ __launch_bounds__(kJT) void k_jacobi_solve(const double* __restrict__
       pq[tid][1] = q;
     }
     __syncthreads();
-    // rows: S <- J^T S
-#pragma unroll
-    for (int h = 0; h < kJR; ++h) {
-      const int e = tid + h * kJT;
-      const int k = e / kJP, j = e % kJP;
-      const double sn = cs[k][1];
-      if (sn != 0.0) {
-        const double c = cs[k][0];
-        const int p = pq[k][0], q = pq[k][1];
-        const double sp = S[p][j], sq = S[q][j];
-        S[p][j] = c * sp - sn * sq;
-        S[q][j] = sn * sp + c * sq;
+    // S <- J^T S J as independent 2x2 blocks: thread (a, b) takes rows
+    // {p_a, q_a} x columns {p_b, q_b} (row rotation, then column rotation);
+    // Q <- Q J on columns.  Blocks are disjoint, so one barrier per step.
+    {
+      const int ka = tid / kJB, kb2 = tid % kJB;   // kJB x kJB = kJT blocks
+      const double sa = cs[ka][1], sb = cs[kb2][1];
+      if (sa != 0.0 || sb != 0.0) {
+        const int p = pq[ka][0], q = pq[ka][1], p2 = pq[kb2][0], q2 = pq[kb2][1];
+        double x00 = S[p][p2], x01 = S[p][q2], x10 = S[q][p2], x11 = S[q][q2];
+        if (sa != 0.0) {
+          const double c = cs[ka][0];
+          const double y00 = c * x00 - sa * x10, y01 = c * x01 - sa * x11;
+          const double y10 = sa * x00 + c * x10, y11 = sa * x01 + c * x11;
+          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+        }
+        if (sb != 0.0) {
+          const double c = cs[kb2][0];
+          const double y00 = c * x00 - sb * x01, y01 = sb * x00 + c * x01;
+          const double y10 = c * x10 - sb * x11, y11 = sb * x10 + c * x11;
+          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+        }
+        S[p][p2] = x00; S[p][q2] = x01; S[q][p2] = x10; S[q][q2] = x11;
       }
-    }
-    __syncthreads();
-    // columns: S <- S J, Q <- Q J
 #pragma unroll
-    for (int h = 0; h < kJR; ++h) {
-      const int e = tid + h * kJT;
-      const int k = e / kJP, i = e % kJP;
-      const double sn = cs[k][1];
-      if (sn != 0.0) {
-        const double c = cs[k][0];
-        const int p = pq[k][0], q = pq[k][1];
-        const double sp = S[i][p], sq = S[i][q];
-        S[i][p] = c * sp - sn * sq;
-        S[i][q] = sn * sp + c * sq;
-        const double qp = Q[i][p], qq = Q[i][q];
-        Q[i][p] = c * qp - sn * qq;
-        Q[i][q] = sn * qp + c * qq;
+      for (int h = 0; h < kJR; ++h) {
+        const int e = tid + h * kJT;
+        const int k = e / kJP, i = e % kJP;
+        const double sn = cs[k][1];
+        if (sn != 0.0) {
+          const double c = cs[k][0];
+          const int pp = pq[k][0], qq = pq[k][1];
+          const double qp = Q[i][pp], qv = Q[i][qq];
+          Q[i][pp] = c * qp - sn * qv;
+          Q[i][qq] = sn * qp + c * qv;
+        }
       }
     }
     __syncthreads();
