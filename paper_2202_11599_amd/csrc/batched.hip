@@ -468,12 +468,16 @@ struct Batch {
 template <typename T, int W, int C, int RR>
 nys_status launch_bg(const Bucket& b, const BInst* insts, int mode, int vecsel, int skip,
                      hipStream_t st) {
-  if (b.aligned)
+  if (b.aligned) {
     hipLaunchKernelGGL((k_bgram<T, W, C, RR, true>), dim3(b.grid), dim3(W * 64), 0, st, insts,
                        b.tiles, b.ntiles, mode, vecsel, skip);
-  else
-    hipLaunchKernelGGL((k_bgram<T, W, C, RR, false>), dim3(b.grid), dim3(W * 64), 0, st, insts,
-                       b.tiles, b.ntiles, mode, vecsel, skip);
+  } else {
+    // unaligned rows with 8-row groups would spill (never a candidate)
+    if constexpr (RR == 8) return NYS_ERR_INVALID;
+    else
+      hipLaunchKernelGGL((k_bgram<T, W, C, RR, false>), dim3(b.grid), dim3(W * 64), 0, st,
+                         insts, b.tiles, b.ntiles, mode, vecsel, skip);
+  }
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
@@ -484,7 +488,7 @@ nys_status launch_bg_t(const Bucket& b, const BInst* insts, int mode, int vecsel
   if (b.waves == W && b.cpl == C && b.rows == RR) return launch_bg<T, W, C, RR>(b, insts, mode, vecsel, skip, st);
   NYS_BC(1, 2, 4) NYS_BC(2, 2, 4) NYS_BC(4, 2, 4) NYS_BC(8, 2, 4)
   NYS_BC(1, 2, 8) NYS_BC(2, 2, 8) NYS_BC(4, 2, 8) NYS_BC(8, 2, 8)
-  NYS_BC(8, 4, 2)
+  NYS_BC(1, 4, 2) NYS_BC(2, 4, 2) NYS_BC(4, 4, 2) NYS_BC(8, 4, 2)
 #undef NYS_BC
   return NYS_ERR_INVALID;
 }
@@ -525,7 +529,8 @@ int cover_of(int waves, int cpl, int vn) { return waves * 64 * cpl * vn; }
 // candidate launch shapes for a bucket whose widest instance has d_max columns
 std::vector<Bucket> bucket_candidates(const Bucket& base, int d_max, int num_cu) {
   static const int shapes[][3] = {{1, 2, 4}, {1, 2, 8}, {2, 2, 4}, {2, 2, 8}, {4, 2, 4},
-                                  {4, 2, 8}, {8, 2, 4}, {8, 2, 8}, {8, 4, 2}};
+                                  {4, 2, 8}, {8, 2, 4}, {8, 2, 8}, {1, 4, 2}, {2, 4, 2},
+                                  {4, 4, 2}, {8, 4, 2}};
   const int vn = base.f64 ? 2 : 4;
   int best = -1;
   for (auto& sh : shapes) {
@@ -537,17 +542,15 @@ std::vector<Bucket> bucket_candidates(const Bucket& base, int d_max, int num_cu)
     const int c = cover_of(sh[0], sh[1], vn);
     if (c < d_max || c > 2 * best) continue;
     if (!base.aligned && sh[2] == 8) continue;   // realignment state would spill
-    const int mx = std::max(1, 8 / sh[0]);
-    for (int per_cu : {std::max(1, mx / 2), mx})
-      for (int64_t tr : {256, 1024}) {
-        Bucket b = base;
-        b.waves = sh[0];
-        b.cpl = sh[1];
-        b.rows = sh[2];
-        b.per_cu = per_cu;
-        b.tile_rows = tr;
-        out.push_back(b);
-      }
+    for (int64_t tr : {128, 256, 1024}) {
+      Bucket b = base;
+      b.waves = sh[0];
+      b.cpl = sh[1];
+      b.rows = sh[2];
+      b.per_cu = std::max(1, 8 / sh[0]);
+      b.tile_rows = tr;
+      out.push_back(b);
+    }
   }
   return out;
 }
@@ -581,7 +584,7 @@ nys_status batch_build(nys_ctx ctx, int count, const nys_problem* P, const nys_a
                        nys_factor* F, nys_admm_state* S, int max_iter, Batch* B) {
   B->count = count;
   B->h.assign(count, BInst{});
-  constexpr int64_t kFinest = 256;
+  constexpr int64_t kFinest = 128;   // finest tiling the tuner may choose
   size_t bytes = au(sizeof(BInst) * count);
   std::vector<size_t> off(count);
   for (int q = 0; q < count; ++q) {
@@ -727,7 +730,9 @@ nys_status upload_tiles(nys_ctx ctx, Bucket* b, const std::vector<BInst>& h, int
   std::vector<BTile> t;
   make_tiles(*b, h, &t);
   b->ntiles = (int)t.size();
-  b->grid = std::max(1, std::min(b->ntiles, b->per_cu * num_cu));
+  // one workgroup per tile: the dispatcher hands tiles to CUs as they free
+  // up, which balances tiles of uneven width and skipped (converged) ones
+  b->grid = std::max(1, b->ntiles);
   if (!t.empty())
     NYS_TRY_HIP(hipMemcpyAsync(b->tiles, t.data(), sizeof(BTile) * t.size(), hipMemcpyHostToDevice,
                                ctx->stream));
