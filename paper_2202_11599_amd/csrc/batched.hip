@@ -488,6 +488,7 @@ nys_status launch_bg_t(const Bucket& b, const BInst* insts, int mode, int vecsel
   if (b.waves == W && b.cpl == C && b.rows == RR) return launch_bg<T, W, C, RR>(b, insts, mode, vecsel, skip, st);
   NYS_BC(1, 2, 4) NYS_BC(2, 2, 4) NYS_BC(4, 2, 4) NYS_BC(8, 2, 4)
   NYS_BC(1, 2, 8) NYS_BC(2, 2, 8) NYS_BC(4, 2, 8) NYS_BC(8, 2, 8)
+  NYS_BC(1, 3, 2) NYS_BC(2, 3, 2) NYS_BC(4, 3, 2) NYS_BC(8, 3, 2)
   NYS_BC(1, 4, 2) NYS_BC(2, 4, 2) NYS_BC(4, 4, 2) NYS_BC(8, 4, 2)
 #undef NYS_BC
   return NYS_ERR_INVALID;
@@ -529,8 +530,9 @@ int cover_of(int waves, int cpl, int vn) { return waves * 64 * cpl * vn; }
 // candidate launch shapes for a bucket whose widest instance has d_max columns
 std::vector<Bucket> bucket_candidates(const Bucket& base, int d_max, int num_cu) {
   static const int shapes[][3] = {{1, 2, 4}, {1, 2, 8}, {2, 2, 4}, {2, 2, 8}, {4, 2, 4},
-                                  {4, 2, 8}, {8, 2, 4}, {8, 2, 8}, {1, 4, 2}, {2, 4, 2},
-                                  {4, 4, 2}, {8, 4, 2}};
+                                  {4, 2, 8}, {8, 2, 4}, {8, 2, 8}, {1, 3, 2}, {2, 3, 2},
+                                  {4, 3, 2}, {8, 3, 2}, {1, 4, 2}, {2, 4, 2}, {4, 4, 2},
+                                  {8, 4, 2}};
   const int vn = base.f64 ? 2 : 4;
   int best = -1;
   for (auto& sh : shapes) {

@@ -121,6 +121,7 @@ nys_status launch_dt(const nys_dense& A, const GramPlan& pl, int mode, const dou
     return launch_r<T, W, C, RR>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1);
   NYS_CASE(1, 2, 4) NYS_CASE(2, 2, 4) NYS_CASE(4, 2, 4) NYS_CASE(8, 2, 4)
   NYS_CASE(1, 2, 8) NYS_CASE(2, 2, 8) NYS_CASE(4, 2, 8) NYS_CASE(8, 2, 8)
+  NYS_CASE(1, 3, 2) NYS_CASE(2, 3, 2) NYS_CASE(4, 3, 2) NYS_CASE(8, 3, 2)
   NYS_CASE(1, 4, 2) NYS_CASE(2, 4, 2) NYS_CASE(4, 4, 2) NYS_CASE(8, 4, 2)
 #undef NYS_CASE
   return NYS_ERR_INVALID;
@@ -151,8 +152,9 @@ static void finish_plan(const nys_dense& A, int num_cu, int per_cu, GramPlan* pl
 // rounds' worth of workgroups per CU at 2 waves per SIMD.
 std::vector<GramPlan> gram_candidates(const nys_dense& A, int num_cu) {
   static const int shapes[][3] = {{1, 2, 4}, {1, 2, 8}, {2, 2, 4}, {2, 2, 8}, {4, 2, 4},
-                                  {4, 2, 8}, {8, 2, 4}, {8, 2, 8}, {1, 4, 2}, {2, 4, 2},
-                                  {4, 4, 2}, {8, 4, 2}};
+                                  {4, 2, 8}, {8, 2, 4}, {8, 2, 8}, {1, 3, 2}, {2, 3, 2},
+                                  {4, 3, 2}, {8, 3, 2}, {1, 4, 2}, {2, 4, 2}, {4, 4, 2},
+                                  {8, 4, 2}};
   const int vn = A.dtype == NYS_F64 ? 2 : 4;
   const int64_t need = std::max<int64_t>(A.d, 1);
   int64_t best_cover = -1;
@@ -210,7 +212,7 @@ GramPlan make_gram_plan(const nys_dense& A, int num_cu) {
     int w = 0, c = 0, rr = 0, g = 0;
     if (sscanf(e, "%d,%d,%d,%d", &w, &c, &rr, &g) == 4 && (int64_t)w * 64 * c * vn >= d &&
         (w == 1 || w == 2 || w == 4 || w == 8) &&
-        ((c == 2 && (rr == 4 || rr == 8)) || (c == 4 && rr == 2)) && g >= 1) {
+        ((c == 2 && (rr == 4 || rr == 8)) || ((c == 3 || c == 4) && rr == 2)) && g >= 1) {
       pl.waves = w;
       pl.cpl = c;
       pl.rows = rr;
