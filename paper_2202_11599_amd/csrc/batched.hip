@@ -99,16 +99,18 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_bgram(
     const int64_t r1 = tl.r1;
     V a0[R][CPL], a1[R][CPL];
     T e0[R][Extra<T>::N], e1[R][Extra<T>::N];
-    load_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, tl.r0, r1, d, I.ld, tid);
+    double v0[R], v1[R];
+    load_group<T, CPL, R, ALIGNED, NT>(a0, e0, v0, A, aux, tl.r0, r1, d, I.ld, tid);
     for (int64_t row = tl.r0; row < r1; row += 2 * R) {
-      load_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, r1, d, I.ld, tid);
+      load_group<T, CPL, R, ALIGNED, NT>(a1, e1, v1, A, aux, row + R, r1, d, I.ld, tid);
       realign_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, row, d, I.ld, tid);
-      process_group<T, WAVES, CPL, R>(a0, row, r1, mode, pr, yr, q, aux, nullptr, red, buf, tid);
-      if (row + R >= r1) break;
-      load_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, row + 2 * R, r1, d, I.ld, tid);
-      realign_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, d, I.ld, tid);
-      process_group<T, WAVES, CPL, R>(a1, row + R, r1, mode, pr, yr, q, aux, nullptr, red, buf,
+      process_group<T, WAVES, CPL, R>(a0, v0, row, r1, mode, pr, yr, q, aux, nullptr, red, buf,
                                       tid);
+      if (row + R >= r1) break;
+      load_group<T, CPL, R, ALIGNED, NT>(a0, e0, v0, A, aux, row + 2 * R, r1, d, I.ld, tid);
+      realign_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, d, I.ld, tid);
+      process_group<T, WAVES, CPL, R>(a1, v1, row + R, r1, mode, pr, yr, q, aux, nullptr, red,
+                                      buf, tid);
     }
     double* yp = I.ypart + (int64_t)tl.slot * I.ldy;
 #pragma unroll

@@ -63,15 +63,18 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_gram(
 
   V a0[R][CPL], a1[R][CPL];
   T e0[R][Extra<T>::N], e1[R][Extra<T>::N];
-  load_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, r0, r1, d, ld, tid);
+  double v0[R], v1[R];
+  load_group<T, CPL, R, ALIGNED, NT>(a0, e0, v0, A, aux, r0, r1, d, ld, tid);
   for (int64_t row = r0; row < r1; row += 2 * R) {
-    load_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, r1, d, ld, tid);
+    load_group<T, CPL, R, ALIGNED, NT>(a1, e1, v1, A, aux, row + R, r1, d, ld, tid);
     realign_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, row, d, ld, tid);
-    process_group<T, WAVES, CPL, R>(a0, row, r1, mode, pr, yr, q, aux, auxout, red, buf, tid);
+    process_group<T, WAVES, CPL, R>(a0, v0, row, r1, mode, pr, yr, q, aux, auxout, red, buf,
+                                    tid);
     if (row + R >= r1) break;
-    load_group<T, CPL, R, ALIGNED, NT>(a0, e0, A, row + 2 * R, r1, d, ld, tid);
+    load_group<T, CPL, R, ALIGNED, NT>(a0, e0, v0, A, aux, row + 2 * R, r1, d, ld, tid);
     realign_group<T, CPL, R, ALIGNED, NT>(a1, e1, A, row + R, d, ld, tid);
-    process_group<T, WAVES, CPL, R>(a1, row + R, r1, mode, pr, yr, q, aux, auxout, red, buf, tid);
+    process_group<T, WAVES, CPL, R>(a1, v1, row + R, r1, mode, pr, yr, q, aux, auxout, red, buf,
+                                    tid);
   }
 
   double* yp = ypart + (int64_t)blockIdx.x * ldy;

@@ -52,15 +52,17 @@ struct Extra {
   static constexpr int N = Chunk<T>::N - 1;   // elements the last lane of a wave fetches
 };
 
-// Issue the loads of R rows.  Aligned rows: one 16-byte load per chunk.
+// Issue the loads of R rows (and of their epilogue inputs aux[row]).
+// Aligned rows: one 16-byte load per chunk.
 // Unaligned rows: each lane loads the 16-byte block at row_start - o + col
 // (o = row_offset), which always holds at least one element of the row, and
 // lane 63 also loads the Extra<T>::N elements after its last chunk; the blocks
 // are shifted into column order by realign_group once they have arrived.
 template <typename T, int CPL, int R, bool ALIGNED, int NT>
 __device__ __forceinline__ void load_group(
-    typename Chunk<T>::V (&a)[R][CPL], T (&ex)[R][Extra<T>::N], const T* __restrict__ A,
-    int64_t row, int64_t r1, int d, int64_t ld, int tid) {
+    typename Chunk<T>::V (&a)[R][CPL], T (&ex)[R][Extra<T>::N], double (&av)[R],
+    const T* __restrict__ A, const double* __restrict__ aux, int64_t row, int64_t r1, int d,
+    int64_t ld, int tid) {
   constexpr int VN = Chunk<T>::N;
   typedef typename Chunk<T>::V V;
 #pragma unroll
@@ -68,6 +70,8 @@ __device__ __forceinline__ void load_group(
     const int64_t rr = row + i;
     const bool ok = rr < r1;
     const T* arow = A + rr * ld;
+    // the per-row input of the epilogue (D, or b) travels with the row
+    av[i] = (aux != nullptr && ok) ? aux[rr] : 0.0;
     if (ALIGNED) {
 #pragma unroll
       for (int m = 0; m < CPL; ++m) {
@@ -160,7 +164,7 @@ __device__ __forceinline__ void realign_group(typename Chunk<T>::V (&a)[R][CPL],
 // Row dots of one group, cross-wave reduction, epilogue, and the A^T update.
 template <typename T, int WAVES, int CPL, int R>
 __device__ __forceinline__ void process_group(
-    typename Chunk<T>::V (&a)[R][CPL], int64_t row, int64_t r1, int mode,
+    typename Chunk<T>::V (&a)[R][CPL], const double (&av)[R], int64_t row, int64_t r1, int mode,
     const double (&pr)[CPL][Chunk<T>::N], double (&yr)[CPL][Chunk<T>::N], double& q,
     const double* __restrict__ aux, double* __restrict__ auxout, double (*red)[R][WAVES],
     int& buf, int tid) {
@@ -194,53 +198,69 @@ __device__ __forceinline__ void process_group(
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        double s = 0.0;
+        double sacc = 0.0;
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) s += red[buf][i][w];
-        t[i] = s;
+        for (int w = 0; w < WAVES; ++w) sacc += red[buf][i][w];
+        t[i] = sacc;
       }
       buf ^= 1;
     }
   }
+  double sv[R];
+  if (mode == kModeLogit || mode == kModeLogGrad) {
+    // transcendental epilogue: lane i evaluates row i, the results are
+    // broadcast (one evaluation per wave instead of R in sequence)
+    double ti = 0.0, bi = 0.0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int64_t rr = row + i;
-    double s = 0.0;
-    if (rr < r1) {
-      const double ti = tonly ? 0.0 : t[i];
-      switch (mode) {
-        case kModeHess: {
-          const double dv = aux ? aux[rr] : 1.0;
-          s = dv * ti;
-          q = fma(s, ti, q);
-        } break;
-        case kModeLsGrad: {
-          s = ti - aux[rr];
-          q = fma(s, s, q);
-        } break;
-        case kModeLogit: {
-          const double sg = sigm(ti);
-          const double w = sg * sigm(-ti);
-          const double bi = aux[rr];
-          s = w * ti + bi - sg;
-          if (auxout != nullptr && tid == 0) auxout[rr] = w;
-          q += log1p(exp(-fabs(ti))) + fmax(ti, 0.0) - bi * ti;
-        } break;
-        case kModeLogGrad: {
-          const double bi = aux[rr];
-          s = sigm(ti) - bi;
-          q += log1p(exp(-fabs(ti))) + fmax(ti, 0.0) - bi * ti;
-        } break;
-        default:  // kModeTOnly
-          s = aux[rr];
-          break;
+    for (int i = 0; i < R; ++i)
+      if (lane == i) {
+        ti = t[i];
+        bi = av[i];
       }
+    const bool mine = lane < R && row + lane < r1;
+    double sl = 0.0, ql = 0.0;
+    if (mine) {
+      const double sg = sigm(ti);
+      const double lossl = log1p(exp(-fabs(ti))) + fmax(ti, 0.0) - bi * ti;
+      if (mode == kModeLogit) {
+        const double w = sg * sigm(-ti);
+        sl = w * ti + bi - sg;
+        if (auxout != nullptr && wv == 0) auxout[row + lane] = w;
+      } else {
+        sl = sg - bi;
+      }
+      ql = lossl;
     }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      sv[i] = __shfl(sl, i, 64);
+      q += __shfl(ql, i, 64);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double sacc = 0.0;
+      if (row + i < r1) {
+        const double ti = tonly ? 0.0 : t[i];
+        if (mode == kModeHess) {
+          sacc = (aux != nullptr ? av[i] : 1.0) * ti;
+          q = fma(sacc, ti, q);
+        } else if (mode == kModeLsGrad) {
+          sacc = ti - av[i];
+          q = fma(sacc, sacc, q);
+        } else {  // kModeTOnly
+          sacc = av[i];
+        }
+      }
+      sv[i] = sacc;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i)
 #pragma unroll
     for (int m = 0; m < CPL; ++m)
 #pragma unroll
-      for (int v = 0; v < VN; ++v) yr[m][v] = fma(s, (double)a[i][m][v], yr[m][v]);
-  }
+      for (int v = 0; v < VN; ++v) yr[m][v] = fma(sv[i], (double)a[i][m][v], yr[m][v]);
 }
 
 }  // namespace gram
