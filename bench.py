@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--true-res-every", type=int, default=10,
+                    help="check the FP64 true residual of every k-th subproblem (and the last "
+                         "of a run); the others stop PCG on its recursive residual")
     ap.add_argument("--workload", choices=["lasso", "logistic", "path", "learned"],
                     default="lasso",
                     help="lasso: 100000x4000 adaptive rank (default line); logistic: 200000x2000 "
@@ -77,12 +80,13 @@ def traffic_record(n, d):
         return None
 
 
-def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, profile=False):
+def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, profile=False):
     import torch
     infos = []
     ranks = []
     sketch_s = 0.0
     bad = 0
+    tr_max = -1.0
     if profile:
         ctx.profile_start()
     torch.cuda.synchronize()
@@ -95,10 +99,12 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, profile=False)
         ranks.append(F.info()["rank"])
         # admm_iters NysADMM iterations with the factor just built (no early stop)
         opts = N.admm_opts(p.rho, ranks[-1], omega, sketch_prec=prec, max_iter=admm_iters,
-                           pcg=N.pcg_opts(tol=p.pcg_tol, max_iter=1000), factor=F)
+                           pcg=N.pcg_opts(tol=p.pcg_tol, max_iter=1000), factor=F,
+                           true_res_every=tr_every)
         st = N.State(p.d, "cuda")
         info = N.admm_solve(ctx, [prob], [opts], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
         infos.append((info.pcg_iters, info.iters, info.pcg_max, info.eta))
+        tr_max = max(tr_max, info.true_res_max)
         bad += info.status != N.NYS_OK
         F.close()
     torch.cuda.synchronize()
@@ -108,7 +114,7 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, profile=False)
     return dict(wall=wall, sketch_s=sketch_s, ranks=ranks,
                 pcg_mean=sum(i for i, _, _, _ in infos) / max(solves, 1),
                 pcg_max=max(m for _, _, m, _ in infos), solves=solves, unconverged=bad, prof=prof,
-                eta=infos[-1][3])
+                eta=infos[-1][3], true_res_max=tr_max)
 
 
 def cpu_baseline(A, b, omega, p, admm_iters, cpu_iters):
@@ -175,36 +181,38 @@ def bench_logistic(args, N, synth, torch):
     prob = N.problem(A, b, p.gamma, loss=N.NYS_LOSS_LOGISTIC)
 
     def steps(k, profile=False):
-        tot, bad, pcg = 0, 0, []
+        tot, bad, pcg, trm = 0, 0, 0, -1.0
         if profile:
             ctx.profile_start()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(k):
+            # `its` iterations from a cold start, the factor built at the first
+            # and rebuilt every 10th with the current weights
             opts = N.admm_opts(p.rho, 200, omega, resketch_every=10, sketch_prec=N.NYS_F32,
-                               pcg=N.pcg_opts(tol=1e-6))
+                               pcg=N.pcg_opts(tol=1e-6), max_iter=its,
+                               true_res_every=args.true_res_every)
             st = N.State(d, "cuda")
-            F = None
-            for _i in range(its):
-                F, info = N.admm_step(ctx, prob, opts, F, st)
-                tot += 1
-                pcg.append(info.pcg_iters)
-                bad += info.status != N.NYS_OK
-            F.close()
+            info = N.admm_solve(ctx, [prob], [opts], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
+            tot += info.iters
+            pcg += info.pcg_iters
+            bad += info.status != N.NYS_OK
+            trm = max(trm, info.true_res_max)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return wall, tot, bad, pcg, (ctx.profile_stop() if profile else None)
+        return wall, tot, bad, pcg, trm, (ctx.profile_stop() if profile else None)
 
     steps(args.warmup)
-    wall, tot, bad, pcg, prof = steps(args.steps, profile=True)
+    wall, tot, bad, pcg, trm, prof = steps(args.steps, profile=True)
     out = base_record(tot / wall, args.steps, args.warmup, wall, "f32", {
         "workload": f"l1-logistic-{n}x{d}-fp32-Sigma_j=1/j-rank200-resketch10",
         "n": n, "d": d, "rho": p.rho, "gamma": p.gamma, "pcg_tol": 1e-6,
-        "admm_iters_per_step": its})
+        "admm_iters_per_step": its, "true_res_every": args.true_res_every})
     # the pair launches include the logistic right-hand-side passes (same bytes)
     out["roofline"] = roofline(prof, float(n) * d * 4, n, d)
-    out["pcg_iters_mean"] = round(sum(pcg) / len(pcg), 3)
+    out["pcg_iters_mean"] = round(pcg / max(tot, 1), 3)
     out["unconverged_solves"] = bad
+    out["true_rel_res_max"] = trm
     return out
 
 
@@ -228,12 +236,14 @@ def bench_path(args, N, synth, torch):
         t0 = time.perf_counter()
         Fs = [N.nys_sketch(ctx, p.A, p.omega, prec=N.NYS_F32) for p in probs]
         states = [N.State(p.d, "cuda") for p in probs]
-        solves, pcg, bad = 0, 0, 0
+        solves, pcg, bad, trm = 0, 0, 0, -1.0
         for g in range(gammas):
             P = [N.problem(p.A, p.b, p.meta["gammas"][g]) for p in probs]
             O = [N.admm_opts(p.rho, 100, p.omega, max_iter=50, factor=Fs[k], sketch_prec=N.NYS_F32,
-                             pcg=N.pcg_opts(tol=1e-6)) for k, p in enumerate(probs)]
+                             pcg=N.pcg_opts(tol=1e-6), true_res_every=args.true_res_every)
+                 for k, p in enumerate(probs)]
             infos = N.admm_solve(ctx, P, O, states)
+            trm = max([trm] + [i.true_res_max for i in infos])
             solves += sum(i.iters for i in infos)
             pcg += sum(i.pcg_iters for i in infos)
             bad += sum(i.status != N.NYS_OK for i in infos)
@@ -241,17 +251,18 @@ def bench_path(args, N, synth, torch):
             F.close()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return wall, solves, pcg, bad, (ctx.profile_stop() if profile else None)
+        return wall, solves, pcg, bad, trm, (ctx.profile_stop() if profile else None)
 
     one_path(gammas=1)
-    wall, solves, pcg, bad, prof = one_path()
+    wall, solves, pcg, bad, trm, prof = one_path()
     out = base_record(solves / wall, 1, 1, wall, "f32", {
         "workload": f"lasso-path-{len(probs)}-instances-n5000..50000-d500..3000-fp32-"
                     f"sigma_j=j^-0.7-rank100-{args.gammas}gammas-50iters",
         "instances": len(probs), "gammas": args.gammas, "rho": 1e-3, "pcg_tol": 1e-6,
-        "total_A_bytes": total_bytes})
+        "total_A_bytes": total_bytes, "true_res_every": args.true_res_every})
     out["pcg_iters_mean"] = round(pcg / max(solves, 1), 3)
     out["unconverged_solves"] = bad
+    out["true_rel_res_max"] = trm
     out["note"] = ("matvec-pair time is not event-timed here (the batched pair is one persistent "
                    "launch per row-width bucket); see profiles/ for its rocprofv3 duration")
     return out
@@ -365,16 +376,17 @@ def main():
         torch.cuda.synchronize()
         del xs, ys
 
-    run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.warmup, args.admm_iters)
+    tre = args.true_res_every
+    run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.warmup, args.admm_iters, tre)
     print("[bench] warmup done", file=sys.stderr, flush=True)
-    plain = run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.steps, args.admm_iters,
+    plain = run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.steps, args.admm_iters, tre,
                       profile=True)
     print(f"[bench] plain fp32: {plain['solves'] / plain['wall']:.1f} solves/s", file=sys.stderr,
           flush=True)
     mixed = None
     if not args.no_mixed:
-        run_steps(N, ctx, A, prob, omega, p, N.NYS_BF16, 1, args.admm_iters)
-        mixed = run_steps(N, ctx, A, prob, omega, p, N.NYS_BF16, args.steps, args.admm_iters)
+        run_steps(N, ctx, A, prob, omega, p, N.NYS_BF16, 1, args.admm_iters, tre)
+        mixed = run_steps(N, ctx, A, prob, omega, p, N.NYS_BF16, args.steps, args.admm_iters, tre)
         print(f"[bench] mixed bf16: {mixed['solves'] / mixed['wall']:.1f} solves/s",
               file=sys.stderr, flush=True)
 
@@ -401,7 +413,7 @@ def main():
             "workload": f"lasso-{args.n}x{args.d}-fp32-sigma_j=j^-0.8-adaptive-rank-50..800",
             "n": args.n, "d": args.d, "rho": p.rho, "gamma": p.gamma, "pcg_tol": p.pcg_tol,
             "admm_iters_per_step": args.admm_iters, "ada_tol": 2.0,
-            "rank_final": plain["ranks"][-1],
+            "rank_final": plain["ranks"][-1], "true_res_every": tre,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -417,6 +429,7 @@ def main():
             "sketch_ms": round(1e3 * plain["sketch_s"] / args.steps, 2),
             "pcg_iters_mean": round(plain["pcg_mean"], 3), "pcg_iters_max": plain["pcg_max"],
             "unconverged_steps": plain["unconverged"], "kkt_eta_after_step": plain["eta"],
+            "true_rel_res_max": plain["true_res_max"],
         },
         "gemv_hbm_gbs": round(achieved, 1),
     }
@@ -427,6 +440,7 @@ def main():
             "sketch_ms": round(1e3 * mixed["sketch_s"] / args.steps, 2),
             "pcg_iters_mean": round(mixed["pcg_mean"], 3), "rank_final": mixed["ranks"][-1],
             "unconverged_steps": mixed["unconverged"], "kkt_eta_after_step": mixed["eta"],
+            "true_rel_res_max": mixed["true_res_max"],
             "vs_plain_fp32": round((mixed["solves"] / mixed["wall"]) / value, 4),
         }
     if not args.no_cpu_baseline:

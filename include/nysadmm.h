@@ -169,7 +169,8 @@ typedef struct {
   int max_iter;      /* PCG iterations; 0 means 1000 */
   int check_every;   /* iterations queued ahead of the host's convergence check (1..4;
                         0 means 2); those queued after convergence return at once */
-  int true_residual; /* 1: recompute rhs - H_rho x at the end and restart if above tol */
+  int true_residual; /* 1: recompute rhs - H_rho x at the end and restart if above tol
+                        (in ADMM at the steps chosen by nys_admm_opts.true_res_every) */
   int max_restarts;  /* restarts allowed by the true-residual check; 0 means 2 */
 } nys_pcg_opts;
 
@@ -229,6 +230,12 @@ typedef struct {
                             the previous iterate is the cold start x); 1: at every step */
   double* ws_features;   /* optional device (rank + 2): features of the step's subproblem */
   double* ws_target;     /* optional device (rank): U^T x of the step's solution */
+  int true_res_every;    /* with pcg.true_residual set: the true residual of the subproblem
+                            (one more pass over A) is computed at every k-th step (state k + 1
+                            a multiple of k) and at the step that reaches max_iter in
+                            admm_solve; the other steps stop PCG on its recursive residual
+                            and a lasso run carries H_rho x = rhs - w to the next step.
+                            0 means 1 (every step) */
 } nys_admm_opts;
 
 /* Caller-owned device FP64 d-vectors; x = z = u = 0 for a cold start.  k counts
@@ -251,6 +258,8 @@ typedef struct {
   int converged;       /* a stopping rule fired */
   nys_status status;
   int ws_used;         /* subproblems that started from the warm-start candidate */
+  double true_res_max; /* largest ||rhs - H_rho x|| / ||rhs|| over the subproblems whose true
+                          residual was computed (FP64 accumulation); -1 if none */
 } nys_admm_info;
 
 /* One iteration of Algorithm NysADMM: right-hand side (lasso: rho(z-u) + A^T b;

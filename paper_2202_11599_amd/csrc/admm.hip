@@ -221,8 +221,13 @@ nys_status kkt_and_objective(nys_ctx ctx, const nys_problem& P, const double* z,
 
 // pcg_abs > 0: the subproblem tolerance is max(pcg_abs, pcg_rel ||rhs||)
 // (the schedule of the experiments section); otherwise O.pcg as given.
+// last: the run ends with this step (its true residual is checked).
+// host_scalars: read the residual norms back (a host round trip); without
+// them the step leaves r_p, r_d and converged unset and the GPU runs on into
+// the next step without waiting for the host.
 nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, nys_factor* F,
-                     nys_admm_state* S, nys_admm_info* I, double pcg_rel, double pcg_abs) {
+                     nys_admm_state* S, nys_admm_info* I, double pcg_rel, double pcg_abs,
+                     bool last, bool host_scalars) {
   const nys_dense& A = P.A;
   const int64_t d = A.d;
   AdmmWs w;
@@ -254,6 +259,8 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
   }
   NYS_TRY_HIP(hipGetLastError());
   nys_pcg_opts po = O.pcg;
+  const int tr_every = O.true_res_every > 0 ? O.true_res_every : 1;
+  if (po.true_residual && !last && (S->k + 1) % tr_every != 0) po.true_residual = 0;
   double abs_tol = 0.0;
   if (pcg_rel > 0.0) {
     po.tol = pcg_rel;
@@ -287,19 +294,29 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
   }
   hipLaunchKernelGGL(k_prox, dim3(w.nb), dim3(256), 0, st, d, P.gamma / O.rho, S->x, S->z, S->u,
                      w.part);
-  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(256), 0, st, w.part, w.nb, nullptr, 0, w.scal);
   double s[kNS + 1];
-  NYS_TRY(read_scalars(ctx, w.scal, s, kNS + 1));
+  if (host_scalars) {
+    hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(256), 0, st, w.part, w.nb, nullptr, 0,
+                       w.scal);
+    NYS_TRY(read_scalars(ctx, w.scal, s, kNS + 1));
+  } else {
+    NYS_TRY_HIP(hipGetLastError());
+  }
   S->k += 1;
   if (I) {
     I->iters += 1;
     I->pcg_iters += pinfo.iters;
     I->pcg_max = std::max(I->pcg_max, pinfo.iters);
-    I->r_p = std::sqrt(s[0]);
-    I->r_d = O.rho * std::sqrt(s[1]);
     I->rank = (*F) ? (*F)->r : 0;
     I->status = ps;
     I->ws_used = used_alt;
+    I->true_res_max = (pinfo.true_res_norm >= 0.0 && pinfo.rhs_norm > 0.0)
+                          ? pinfo.true_res_norm / pinfo.rhs_norm
+                          : (pinfo.true_res_norm >= 0.0 ? 0.0 : -1.0);
+    I->converged = 0;
+    if (!host_scalars) return ps == NYS_ERR_MAXITER ? NYS_OK : ps;
+    I->r_p = std::sqrt(s[0]);
+    I->r_d = O.rho * std::sqrt(s[1]);
     // Section 2.1 residual stop
     bool stop = false;
     if (O.eps_rel > 0.0) {
@@ -351,7 +368,7 @@ nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, 
   if (P->loss == NYS_LOSS_LS && *F == nullptr) {
     NYS_TRY(nys_sketch(ctx, &P->A, nullptr, P->c, O->omega, O->rank, O->sketch_prec, F));
   }
-  return admm_iter(ctx, *P, *O, F, S, I, 0.0, 0.0);
+  return admm_iter(ctx, *P, *O, F, S, I, 0.0, 0.0, false, true);
 }
 
 nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_admm_opts* O,
@@ -379,7 +396,7 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
     const nys_problem& p = P[q];
     const nys_admm_opts& o = O[q];
     nys_admm_info info{};
-    info.eta = info.obj = -1.0;
+    info.eta = info.obj = info.true_res_max = -1.0;
     nys_factor F = o.factor;
     const bool own = (F == nullptr);
     nys_status s = NYS_OK;
@@ -403,16 +420,25 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
         rel = (it == 0) ? 1e-2 : o.pcg.tol;
         abs_tol = (it == 0) ? 0.0 : eps_next;
       }
-      s = admm_iter(ctx, p, o, &F, &S[q], &step, rel, abs_tol);
+      const bool last = it + 1 == max_iter;
+      const bool kkt_now = o.kkt_tol > 0.0 && (it + 1) % kkt_every == 0;
+      // the residual norms are needed on the host by the residual stopping
+      // rules, the tolerance schedule, a KKT check and at the end
+      const bool host = last || kkt_now || o.tol_schedule || o.eps_rel > 0.0 ||
+                        o.rel_change_tol > 0.0;
+      s = admm_iter(ctx, p, o, &F, &S[q], &step, rel, abs_tol, last, host);
       if (s != NYS_OK) break;
       info.iters += 1;
       info.pcg_iters += step.pcg_iters;
       info.pcg_max = std::max(info.pcg_max, step.pcg_max);
-      info.r_p = step.r_p;
-      info.r_d = step.r_d;
+      if (host) {
+        info.r_p = step.r_p;
+        info.r_d = step.r_d;
+      }
       info.rank = step.rank;
       info.status = step.status;
       info.ws_used += step.ws_used;
+      info.true_res_max = std::max(info.true_res_max, step.true_res_max);
       if (o.tol_schedule) eps_next = std::sqrt(step.r_p * step.r_d);
       bool stop = step.converged != 0;
       if (o.kkt_tol > 0.0 && ((it + 1) % kkt_every == 0 || stop)) {

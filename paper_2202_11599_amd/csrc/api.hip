@@ -331,7 +331,21 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
       break;
     }
     if (!h.done) status = NYS_ERR_MAXITER;
-    if (!o.true_residual) break;
+    if (!o.true_residual) {
+      // no true-residual pass: H_rho x of the last iterate is rhs - w, the
+      // recursive residual (consistent with x at every iteration)
+      if (hx_tag >= 0) {
+        NYS_TRY(ctx->hx.reserve(sizeof(double) * d));
+        NYS_TRY(launch_reduce_update(4, nullptr, 0, 0, nullptr, d, 0.0, nullptr,
+                                     ctx->hx.as<double>(), ws.w, rhs, nullptr, 0, nullptr, 0,
+                                     nullptr, nullptr, ws.st, st));
+        ctx->hx_key = key;
+        ctx->hx_rho = rho;
+        ctx->hx_c = c;
+        ctx->hx_tag = hx_tag + 1;
+      }
+      break;
+    }
     // true residual rhs - H_rho x with FP64 accumulation (H_rho x kept when asked)
     double* hx_out = nullptr;
     if (hx_tag >= 0) {

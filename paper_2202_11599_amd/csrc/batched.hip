@@ -138,7 +138,8 @@ __device__ double bsum1024(const double* __restrict__ a, int n, double* sh) {
   return r;
 }
 
-// op 0 iterate, 1 init (w = rhs - H x), 2 true residual, 3 plain (-> atb)
+// op 0 iterate, 1 init (w = rhs - H x), 2 true residual, 3 plain (-> atb),
+// 4 init from the carried residual w (no partials: only the norms of w and rhs)
 __global__ __launch_bounds__(1024) void k_breduce(const BInst* __restrict__ insts,
                                                   const BItem* __restrict__ items, int op) {
   const BItem it = items[blockIdx.x];
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(1024) void k_breduce(const BInst* __restrict__ inst
   const int64_t j = (int64_t)it.blk * 64 + lane;
   const int d = I.d;
   double acc = 0.0;
-  if (j < d)
+  if (j < d && op != 4)
     for (int g = grp; g < I.G; g += S) acc += I.ypart[(int64_t)g * I.ldy + j];
   part[grp][lane] = acc;
   double alpha = 0.0;
@@ -174,7 +175,11 @@ __global__ __launch_bounds__(1024) void k_breduce(const BInst* __restrict__ inst
   __syncthreads();
   if (grp != 0) return;
   double ww = 0.0, rr = 0.0;
-  if (j < d) {
+  if (j < d && op == 4) {
+    const double wj = I.w[j], r = I.rhs[j];
+    ww = wj * wj;
+    rr = r * r;
+  } else if (j < d) {
     double sum = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) sum += part[i][lane];
@@ -364,14 +369,19 @@ __global__ void k_breset(const BInst* __restrict__ insts, int count) {
   s->true_rr = -1.0;
 }
 
-// rhs = rho (z - u) + A^T b for active instances
+// rhs = rho (z - u) + A^T b for active instances; carry: the PCG residual
+// w = rhs - H_rho x of the last solve follows the change of rhs (x unchanged)
 __global__ __launch_bounds__(256) void k_brhs(const BInst* __restrict__ insts,
-                                              const BItem* __restrict__ items) {
+                                              const BItem* __restrict__ items, int carry) {
   const BItem it = items[blockIdx.x];
   const BInst& I = insts[it.inst];
   if (!I.active) return;
   const int64_t j = (int64_t)it.blk * 256 + threadIdx.x;
-  if (j < I.d) I.rhs[j] = I.rho * (I.z[j] - I.u[j]) + I.atb[j];
+  if (j < I.d) {
+    const double rn = I.rho * (I.z[j] - I.u[j]) + I.atb[j];
+    if (carry) I.w[j] += rn - I.rhs[j];
+    I.rhs[j] = rn;
+  }
 }
 
 // z = S_{gamma/rho}(x + u), u += x - z, with the kNS residual partials per block
@@ -516,10 +526,14 @@ nys_status pcg_iteration(const Batch& B, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
-nys_status bpcg_init(const Batch& B, hipStream_t st) {
+nys_status bpcg_init(const Batch& B, hipStream_t st, bool carry) {
   hipLaunchKernelGGL(k_breset, dim3((B.count + 255) / 256), dim3(256), 0, st, B.insts, B.count);
-  NYS_TRY(bgram(B, kModeHess, 0, 0, st));
-  hipLaunchKernelGGL(k_breduce, dim3(B.n64), dim3(1024), 0, st, B.insts, B.it64, 1);
+  if (carry) {
+    hipLaunchKernelGGL(k_breduce, dim3(B.n64), dim3(1024), 0, st, B.insts, B.it64, 4);
+  } else {
+    NYS_TRY(bgram(B, kModeHess, 0, 0, st));
+    hipLaunchKernelGGL(k_breduce, dim3(B.n64), dim3(1024), 0, st, B.insts, B.it64, 1);
+  }
   hipLaunchKernelGGL(k_bdot, dim3(B.ndot), dim3(256), 0, st, B.insts, B.itdot, 1);
   hipLaunchKernelGGL(k_bupdate, dim3(B.n256), dim3(256), 0, st, B.insts, B.it256, 1);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
@@ -835,9 +849,12 @@ nys_status batch_graph(nys_ctx ctx, Batch* B) {
 
 // Batched Algorithm Nystrom PCG: every active instance from its x, replays of
 // the captured iteration chunk until all have converged or hit max_iter.
-nys_status batch_pcg(nys_ctx ctx, Batch* B, int max_iter, std::vector<PcgDev>* states) {
+// carry: w already holds rhs - H_rho x (see k_brhs); check: end with the
+// FP64 true residual (which also leaves it in w).
+nys_status batch_pcg(nys_ctx ctx, Batch* B, int max_iter, std::vector<PcgDev>* states, bool carry,
+                     bool check) {
   hipStream_t st = ctx->stream;
-  NYS_TRY(bpcg_init(*B, st));
+  NYS_TRY(bpcg_init(*B, st, carry));
   NYS_TRY(batch_graph(ctx, B));
   int done_iters = 0;
   for (;;) {
@@ -848,10 +865,12 @@ nys_status batch_pcg(nys_ctx ctx, Batch* B, int max_iter, std::vector<PcgDev>* s
     const int running = *static_cast<int*>(ctx->host_pinned);
     if (running == 0 || done_iters >= max_iter + B->graph_iters) break;
   }
-  // FP64-accumulated true residual of every active instance
-  NYS_TRY(bgram(*B, kModeHess, 0, 0, st));
-  hipLaunchKernelGGL(k_breduce, dim3(B->n64), dim3(1024), 0, st, B->insts, B->it64, 2);
-  hipLaunchKernelGGL(k_bdot, dim3(B->ndot), dim3(256), 0, st, B->insts, B->itdot, 3);
+  if (check) {
+    // FP64-accumulated true residual of every active instance
+    NYS_TRY(bgram(*B, kModeHess, 0, 0, st));
+    hipLaunchKernelGGL(k_breduce, dim3(B->n64), dim3(1024), 0, st, B->insts, B->it64, 2);
+    hipLaunchKernelGGL(k_bdot, dim3(B->ndot), dim3(256), 0, st, B->insts, B->itdot, 3);
+  }
   NYS_TRY_HIP(hipGetLastError());
   states->resize(B->count);
   for (int q = 0; q < B->count; ++q)
@@ -881,10 +900,14 @@ nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
     else
       s = nys_sketch(ctx, &P[q].A, nullptr, P[q].c, O[q].omega, O[q].rank, O[q].sketch_prec, &F[q]);
   }
-  int max_iter = 0, pcg_max = 0;
+  int max_iter = 0, pcg_max = 0, tr_every = 0;
+  bool want_tr = false;
   for (int q = 0; q < count; ++q) {
     max_iter = std::max(max_iter, O[q].max_iter > 0 ? O[q].max_iter : 100);
     pcg_max = std::max(pcg_max, O[q].pcg.max_iter > 0 ? O[q].pcg.max_iter : 1000);
+    const int e = O[q].true_res_every > 0 ? O[q].true_res_every : 1;
+    tr_every = tr_every == 0 ? e : std::min(tr_every, e);
+    want_tr = want_tr || O[q].pcg.true_residual != 0;
   }
   Batch B;
   if (s == NYS_OK) s = batch_build(ctx, count, P, O, F.data(), S, pcg_max, &B);
@@ -892,7 +915,7 @@ nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
   std::vector<nys_admm_info> info(count);
   for (auto& x : info) {
     x = nys_admm_info{};
-    x.eta = x.obj = -1.0;
+    x.eta = x.obj = x.true_res_max = -1.0;
   }
   // A^T b of every instance, one batched pass
   if (s == NYS_OK) {
@@ -903,8 +926,15 @@ nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
   std::vector<double> sc((size_t)kNS * count);
   std::vector<PcgDev> pst;
   for (int it = 0; s == NYS_OK && it < max_iter; ++it) {
-    hipLaunchKernelGGL(k_brhs, dim3(B.n256), dim3(256), 0, st, B.insts, B.it256);
-    s = batch_pcg(ctx, &B, pcg_max, &pst);
+    // true residual at every tr_every-th step and at each instance's last
+    bool check = want_tr && (it + 1) % tr_every == 0;
+    for (int q = 0; q < count && want_tr && !check; ++q)
+      if (B.h[q].active && info[q].iters + 1 >= (O[q].max_iter > 0 ? O[q].max_iter : 100))
+        check = true;
+    // from the second step on, the residual of the last solve is carried
+    const int carry = it > 0 ? 1 : 0;
+    hipLaunchKernelGGL(k_brhs, dim3(B.n256), dim3(256), 0, st, B.insts, B.it256, carry);
+    s = batch_pcg(ctx, &B, pcg_max, &pst, carry != 0, check);
     if (s != NYS_OK) break;
     hipLaunchKernelGGL(k_bprox, dim3(B.n256), dim3(256), 0, st, B.insts, B.it256);
     hipLaunchKernelGGL(k_bscalars, dim3(count), dim3(256), 0, st, B.insts, count, B.scal);
@@ -927,10 +957,14 @@ nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
       f.r_p = std::sqrt(v[0]);
       f.r_d = O[q].rho * std::sqrt(v[1]);
       f.rank = F[q]->r;
+      const double res2 = check ? ps.true_rr : ps.ww;
       f.status = (ps.flags & kFlagNonfinite) ? NYS_ERR_NONFINITE
                  : (ps.flags & kFlagBreakdown) ? NYS_ERR_BREAKDOWN
-                 : (!(ps.true_rr <= ps.thr2) && !(ps.flags & kFlagZeroRhs)) ? NYS_ERR_MAXITER
-                                                                            : NYS_OK;
+                 : (!(res2 <= ps.thr2) && !(ps.flags & kFlagZeroRhs)) ? NYS_ERR_MAXITER
+                                                                     : NYS_OK;
+      if (check && ps.true_rr >= 0.0)
+        f.true_res_max = std::max(f.true_res_max,
+                                  ps.rr > 0.0 ? std::sqrt(ps.true_rr / ps.rr) : 0.0);
       S[q].k += 1;
       bool stop = (f.iters >= (O[q].max_iter > 0 ? O[q].max_iter : 100));
       if (O[q].eps_rel > 0.0) {

@@ -235,7 +235,8 @@ inline int nblk(int64_t d, int b) { return (int)((d + b - 1) / b); }
 //   op 0 (iterate): alpha = wy[k] / (sum q + rho_eff ||p||^2); x += alpha p; w -= alpha v
 //   op 1 (init):    w = rhs - v ;  ||rhs||^2 partials
 //   op 2 (true):    w = rhs - v  (true residual, FP64 accumulation); v -> x if x != NULL
-//   op 3 (plain):   out = v + beta * aux   (used for rhs/gradient assembly)
+//   op 3 (plain):   w = v
+//   op 4 (carry):   x = rhs - w  (H_rho x from the recursive residual; ypart unused)
 nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, const double* qpart,
                                 int64_t d, double rho_eff, const double* p, double* x, double* w,
                                 const double* rhs, double* wy, int k, const double* pppart,

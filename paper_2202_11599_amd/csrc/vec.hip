@@ -108,11 +108,13 @@ __global__ __launch_bounds__(256) void k_reduce_update(
       ww = wj * wj;
       rr = r * r;
       if (op == 2 && x != nullptr) x[j] = v;   // keep H_rho x for the next solve's w0
+    } else if (op == 4) {   // H_rho x = rhs - w from the recursive residual
+      x[j] = rhs[j] - w[j];
     } else {  // op 3: plain reduction
       w[j] = v;
     }
   }
-  if (op == 3) return;
+  if (op >= 3) return;
   __syncthreads();
   ww = block_sum_value(ww, sh4);
   __syncthreads();

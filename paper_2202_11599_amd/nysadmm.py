@@ -70,7 +70,7 @@ class AdmmOpts(C.Structure):
                 ("rel_change_tol", C.c_double), ("kkt_tol", C.c_double), ("kkt_every", C.c_int),
                 ("factor", C.c_void_p), ("warm_start", C.c_void_p), ("ws_analytic", C.c_int),
                 ("ws_every_step", C.c_int), ("ws_features", C.c_void_p),
-                ("ws_target", C.c_void_p)]
+                ("ws_target", C.c_void_p), ("true_res_every", C.c_int)]
 
 
 class AdmmState(C.Structure):
@@ -81,7 +81,7 @@ class AdmmInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("pcg_iters", C.c_long), ("pcg_max", C.c_int),
                 ("r_p", C.c_double), ("r_d", C.c_double), ("eta", C.c_double),
                 ("obj", C.c_double), ("rank", C.c_int), ("converged", C.c_int),
-                ("status", C.c_int), ("ws_used", C.c_int)]
+                ("status", C.c_int), ("ws_used", C.c_int), ("true_res_max", C.c_double)]
 
 
 def lib():
@@ -333,7 +333,7 @@ def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resk
               eps_abs=0.0, eps_rel=0.0, rel_change_tol=0.0, kkt_tol=0.0, kkt_every=10,
               factor: Optional["Factor"] = None, warm_start: Optional["WarmStart"] = None,
               ws_analytic=False, ws_every_step=False, ws_features: Optional[torch.Tensor] = None,
-              ws_target: Optional[torch.Tensor] = None) -> AdmmOpts:
+              ws_target: Optional[torch.Tensor] = None, true_res_every=1) -> AdmmOpts:
     for t, name in ((ws_features, "ws_features"), (ws_target, "ws_target")):
         if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous CUDA float64 tensor")
@@ -344,7 +344,7 @@ def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resk
                     None if warm_start is None else warm_start.h.value, int(bool(ws_analytic)),
                     int(bool(ws_every_step)),
                     None if ws_features is None else ws_features.data_ptr(),
-                    None if ws_target is None else ws_target.data_ptr())
+                    None if ws_target is None else ws_target.data_ptr(), int(true_res_every))
 
 
 def problem(A: torch.Tensor, b: torch.Tensor, gamma: float, loss=NYS_LOSS_LS, c: float = 0.0) -> Problem:

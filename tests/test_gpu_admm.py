@@ -231,3 +231,48 @@ def test_step_caches_do_not_leak_between_runs(N, ctx):
     fresh.close()
     assert torch.equal(z1, z2) and torch.equal(x1, x2)
     F.close()
+
+
+def test_true_residual_cadence(N, ctx):
+    # The true residual checked every 10th step (the other steps stop PCG on
+    # its recursive residual and carry H_rho x = rhs - w): the same iterates as
+    # the oracle, which forms rhs - H_rho x afresh for every subproblem.  The
+    # per-step residual norms are not read back between steps here (no stopping
+    # rule needs them); the reported r_p is the last step's.
+    p = synth.lasso_c1()
+    A, b = p.A.numpy(), p.b.numpy()
+    its = 60
+    ora = ad.admm_lasso(A, b, p.gamma, 1.0, omega_raw=p.omega.numpy().T, iters=its, pcg_tol=1e-8)
+    res = {}
+    for every in (1, 10):
+        print(f"[cadence] true residual every {every}", flush=True)
+        st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 50, max_iter=its,
+                             true_res_every=every)
+        res[every] = (st.z.cpu().numpy(), info)
+    for every, (z, info) in res.items():
+        ez = np.linalg.norm(z - ora.z) / np.linalg.norm(ora.z)
+        print(f"[cadence] every {every}: rel z diff {ez:.2e} pcg {info.pcg_iters} vs oracle "
+              f"{sum(ora.pcg_iters)} true res max {info.true_res_max:.3e} r_p {info.r_p:.6e} "
+              f"vs {ora.r_p[-1]:.6e}", flush=True)
+        assert info.iters == its
+        assert ez < 1e-6
+        assert abs(info.pcg_iters - sum(ora.pcg_iters)) <= 0.05 * sum(ora.pcg_iters)
+        assert 0.0 < info.true_res_max <= 1e-8 * (1 + 1e-6)
+        assert abs(info.r_p - ora.r_p[-1]) <= 1e-6 * ora.r_p[-1]
+    z1, z10 = res[1][0], res[10][0]
+    assert np.linalg.norm(z1 - z10) <= 1e-9 * np.linalg.norm(z1)
+
+
+def test_true_residual_cadence_logistic(N, ctx):
+    p = synth.logistic_decay(6000, 200, seed=4, dtype=torch.float64, rho=5.0, rank=30,
+                             gamma_per_row=2e-3, pcg_tol=1e-10)
+    its = 30
+    zs = []
+    for every in (1, 10):
+        st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 30, max_iter=its,
+                             resketch_every=10, true_res_every=every)
+        print(f"[cadence logistic] every {every}: pcg {info.pcg_iters} true res max "
+              f"{info.true_res_max:.3e}", flush=True)
+        assert info.iters == its and 0.0 < info.true_res_max <= 1e-10 * (1 + 1e-6)
+        zs.append(st.z.cpu().numpy())
+    assert np.linalg.norm(zs[0] - zs[1]) <= 1e-9 * np.linalg.norm(zs[0])

@@ -119,3 +119,35 @@ def test_regularisation_path_warm_started(N, ctx):
             assert np.linalg.norm(z - ex.z) <= 1e-5 * max(np.linalg.norm(ex.z), 1e-12)
     for f in F:
         f.close()
+
+
+def test_batched_true_residual_cadence(N, ctx):
+    # lockstep run with the residual of each solve carried to the next step and
+    # the true residual checked every 7th step (and at the last): the same
+    # iterates as the run that checks every step
+    probs = make(SHAPES[:4])
+    A, b, om, F = to_dev(N, ctx, probs, prec_for(N))
+    its = 20
+    out = {}
+    for every in (1, 7):
+        opts = [N.admm_opts(p.rho, 30, om[k], pcg=N.pcg_opts(tol=1e-10), max_iter=its,
+                            factor=F[k], sketch_prec=prec_for(N)(p), true_res_every=every)
+                for k, p in enumerate(probs)]
+        st = [N.State(p.d, DEV) for p in probs]
+        infos = N.admm_solve(ctx, [N.problem(A[k], b[k], p.gamma) for k, p in enumerate(probs)],
+                             opts, st)
+        out[every] = ([s.z.cpu().numpy() for s in st], infos)
+    for k in range(len(probs)):
+        z1, z7 = out[1][0][k], out[7][0][k]
+        i1, i7 = out[1][1][k], out[7][1][k]
+        e = np.linalg.norm(z1 - z7) / max(np.linalg.norm(z1), 1e-300)
+        print(f"[batched cadence] inst {k}: rel z diff {e:.2e} pcg {i1.pcg_iters}/{i7.pcg_iters} "
+              f"true res max {i1.true_res_max:.2e}/{i7.true_res_max:.2e}", flush=True)
+        assert i1.iters == its and i7.iters == its
+        assert i1.status == N.NYS_OK and i7.status == N.NYS_OK
+        assert e < 1e-8
+        assert abs(i1.pcg_iters - i7.pcg_iters) <= 2
+        for i in (i1, i7):
+            assert 0.0 < i.true_res_max <= 1e-10 * (1 + 1e-6)
+    for f in F:
+        f.close()
