@@ -383,6 +383,10 @@ def main():
                       profile=True)
     print(f"[bench] plain fp32: {plain['solves'] / plain['wall']:.1f} solves/s", file=sys.stderr,
           flush=True)
+    # the same steps with the FP64 true residual formed after every solve
+    strict = run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.steps, args.admm_iters, 1)
+    print(f"[bench] true residual every solve: {strict['solves'] / strict['wall']:.1f} solves/s",
+          file=sys.stderr, flush=True)
     mixed = None
     if not args.no_mixed:
         run_steps(N, ctx, A, prob, omega, p, N.NYS_BF16, 1, args.admm_iters, tre)
@@ -432,6 +436,12 @@ def main():
             "true_rel_res_max": plain["true_res_max"],
         },
         "gemv_hbm_gbs": round(achieved, 1),
+        "true_residual_every_solve": {
+            "solves_per_s": round(strict["solves"] / strict["wall"], 3),
+            "pcg_iters_mean": round(strict["pcg_mean"], 3),
+            "unconverged_steps": strict["unconverged"],
+            "true_rel_res_max": strict["true_res_max"],
+        },
     }
     if mixed is not None:
         out["mixed_bf16_sketch"] = {

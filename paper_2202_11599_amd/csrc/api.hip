@@ -6,6 +6,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "internal.h"
 
@@ -18,29 +19,198 @@ void set_last_hip_error(hipError_t e, const char* what, const char* file, int li
            hipGetErrorString(e), file, line);
 }
 
+// ---- block cache
+// Released device blocks are kept (up to kPoolCap bytes per process) with one
+// event per live context stream of their device, recorded at release; a block
+// is handed out again once all of its events have completed, i.e. once no work
+// that was queued when it was released can still touch it.  Library kernels
+// run only on context streams, so this is the guarantee hipFree gives, without
+// its device-wide synchronisation.  The cache of a device is emptied when its
+// last context is destroyed.
+namespace {
+struct PoolBlock {
+  void* ptr;
+  size_t bytes;
+  int device;
+  std::vector<hipEvent_t> evs;
+};
+struct Pool {
+  std::mutex mu;
+  std::vector<PoolBlock> blocks;
+  std::vector<std::pair<int, hipStream_t>> streams;
+  std::vector<std::pair<int, hipEvent_t>> spare_events;
+  size_t cached = 0;
+};
+Pool& pool() {
+  static Pool* p = new Pool();   // lives until the process ends
+  return *p;
+}
+constexpr size_t kPoolCap = size_t(4) << 30;
+
+size_t pool_round(size_t want) {
+  if (want == 0) want = 256;
+  const size_t g = want > (size_t(1) << 20) ? (size_t(2) << 20) : 4096;
+  return (want + g - 1) / g * g;
+}
+
+bool pool_ready(const PoolBlock& b) {
+  for (hipEvent_t e : b.evs) {
+    const hipError_t r = hipEventQuery(e);
+    if (r != hipSuccess) {
+      if (r != hipErrorNotReady) (void)hipGetLastError();
+      return false;
+    }
+  }
+  return true;
+}
+
+// caller holds the lock; the block's device is current
+void pool_recycle_events(Pool& P, PoolBlock& b) {
+  for (hipEvent_t e : b.evs) P.spare_events.emplace_back(b.device, e);
+  b.evs.clear();
+}
+
+// free every cached block of `device` (waits for their events)
+void pool_trim_locked(Pool& P, int device) {
+  for (size_t i = 0; i < P.blocks.size();) {
+    PoolBlock& b = P.blocks[i];
+    if (b.device != device) {
+      ++i;
+      continue;
+    }
+    for (hipEvent_t e : b.evs) (void)hipEventSynchronize(e);
+    pool_recycle_events(P, b);
+    (void)hipFree(b.ptr);
+    P.cached -= b.bytes;
+    P.blocks.erase(P.blocks.begin() + (long)i);
+  }
+  for (size_t i = 0; i < P.spare_events.size();) {
+    if (P.spare_events[i].first == device) {
+      (void)hipEventDestroy(P.spare_events[i].second);
+      P.spare_events.erase(P.spare_events.begin() + (long)i);
+    } else {
+      ++i;
+    }
+  }
+}
+}  // namespace
+
+void pool_register_stream(int device, hipStream_t st) {
+  Pool& P = pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.streams.emplace_back(device, st);
+}
+
+void pool_unregister_stream(int device, hipStream_t st) {
+  Pool& P = pool();
+  std::lock_guard<std::mutex> g(P.mu);
+  for (size_t i = 0; i < P.streams.size(); ++i)
+    if (P.streams[i].first == device && P.streams[i].second == st) {
+      P.streams.erase(P.streams.begin() + (long)i);
+      break;
+    }
+  bool live = false;
+  for (auto& s : P.streams) live = live || s.first == device;
+  if (!live) pool_trim_locked(P, device);
+}
+
 nys_status DevBuf::reserve(size_t want) {
   if (want <= bytes && ptr != nullptr) return NYS_OK;
-  if (ptr != nullptr) {
-    (void)hipDeviceSynchronize();   // kernels in flight may still use the old buffer
-    (void)hipFree(ptr);
-    ptr = nullptr;
-    bytes = 0;
+  release();
+  want = pool_round(want);
+  int dev = 0;
+  NYS_TRY_HIP(hipGetDevice(&dev));
+  Pool& P = pool();
+  {
+    std::lock_guard<std::mutex> g(P.mu);
+    long best = -1;
+    for (size_t i = 0; i < P.blocks.size(); ++i) {
+      const PoolBlock& b = P.blocks[i];
+      if (b.device != dev || b.bytes < want || b.bytes > 2 * want) continue;
+      if (best >= 0 && b.bytes >= P.blocks[(size_t)best].bytes) continue;
+      if (!pool_ready(b)) continue;
+      best = (long)i;
+    }
+    if (best >= 0) {
+      PoolBlock& b = P.blocks[(size_t)best];
+      ptr = b.ptr;
+      bytes = b.bytes;
+      device = dev;
+      pool_recycle_events(P, b);
+      P.cached -= b.bytes;
+      P.blocks.erase(P.blocks.begin() + best);
+      return NYS_OK;
+    }
   }
-  if (want == 0) want = 256;
-  want = (want + 4095) / 4096 * 4096;
   if (hipMalloc(&ptr, want) != hipSuccess) {
-    ptr = nullptr;
     (void)hipGetLastError();
-    return NYS_ERR_NOMEM;
+    // give the cached blocks of this device back and try once more
+    {
+      std::lock_guard<std::mutex> g(P.mu);
+      pool_trim_locked(P, dev);
+    }
+    if (hipMalloc(&ptr, want) != hipSuccess) {
+      ptr = nullptr;
+      (void)hipGetLastError();
+      return NYS_ERR_NOMEM;
+    }
   }
   bytes = want;
+  device = dev;
   return NYS_OK;
 }
 
 void DevBuf::release() {
-  if (ptr != nullptr) (void)hipFree(ptr);
+  if (ptr == nullptr) return;
+  Pool& P = pool();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != device) (void)hipSetDevice(device);
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> g(P.mu);
+    bool live = false;
+    for (auto& s : P.streams) live = live || s.first == device;
+    if (live && P.cached + bytes <= kPoolCap) {
+      PoolBlock b{ptr, bytes, device, {}};
+      bool ok = true;
+      for (auto& s : P.streams) {
+        if (s.first != device) continue;
+        hipEvent_t e = nullptr;
+        for (size_t i = P.spare_events.size(); i-- > 0;)
+          if (P.spare_events[i].first == device) {
+            e = P.spare_events[i].second;
+            P.spare_events.erase(P.spare_events.begin() + (long)i);
+            break;
+          }
+        if (e == nullptr && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+          ok = false;
+          break;
+        }
+        b.evs.push_back(e);
+        if (hipEventRecord(e, s.second) != hipSuccess) {
+          ok = false;
+          break;
+        }
+      }
+      if (ok) {
+        P.blocks.push_back(std::move(b));
+        P.cached += bytes;
+        cached = true;
+      } else {
+        (void)hipGetLastError();
+        pool_recycle_events(P, b);
+      }
+    }
+  }
+  if (!cached) {
+    (void)hipDeviceSynchronize();   // kernels in flight may still use the block
+    (void)hipFree(ptr);
+  }
+  if (cur != device) (void)hipSetDevice(cur);
   ptr = nullptr;
   bytes = 0;
+  device = -1;
 }
 
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
@@ -423,6 +593,7 @@ nys_status nys_ctx_create(int device, void* hip_stream, nys_ctx* out) {
     delete c;
     return NYS_ERR_NOMEM;
   }
+  pool_register_stream(device, c->stream);
   if (hipHostGetDevicePointer(&c->host_pinned_dev, c->host_pinned, 0) != hipSuccess) {
     nys_ctx_destroy(c);
     return NYS_ERR_HIP;
@@ -442,6 +613,7 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   ctx->gemm_ws.release();
   ctx->core_ws.release();
   ctx->admm_ws.release();
+  pool_unregister_stream(ctx->device, ctx->stream);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);

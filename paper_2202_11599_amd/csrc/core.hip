@@ -278,10 +278,10 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
 // tile of G becomes Q_P^T G_PQ Q_Q and V becomes V Q.
 constexpr int kJB = 16;        // block size
 constexpr int kJP = 2 * kJB;   // pair block size
-constexpr int kJT = 256;       // threads of the solve and apply workgroups
+constexpr int kJT = 256;       // threads of the apply workgroups
+constexpr int kJS = 256;       // threads of the solve workgroups
 constexpr int kJE = kJP * kJP / kJT;   // tile elements per thread
-constexpr int kJR = kJB * kJP / kJT;   // Q column updates per thread and step
-static_assert(kJB * kJB == kJT, "one 2x2 block of the pair block per thread");
+static_assert(kJB * kJB % kJS == 0 && kJB * kJP % kJS == 0, "whole 2x2 blocks per lane");
 constexpr double kJacTol = 1e-15;
 
 // Round-robin pairing of nb blocks (nb even): round t, pair k -> (a, b).
@@ -289,6 +289,14 @@ __device__ __forceinline__ void rr_pair(int nb, int t, int k, int* a, int* b) {
   auto pos = [&](int p) { return p == 0 ? 0 : ((p - 1 + t) % (nb - 1)) + 1; };
   *a = pos(k);
   *b = pos(nb - 1 - k);
+}
+
+// counters[s]: pair blocks that rotated in sweep s; counters[64 + s]: 1 if
+// the matrix after sweep s still fails the rotation criterion somewhere.
+// Sweep s (with its check) is skipped when sweep s - 1 left the matrix
+// passing; its check flag then stays 0, so every later sweep is skipped too.
+__device__ __forceinline__ bool jacobi_skip(const int* counters, int sweep) {
+  return sweep > 0 && counters[64 + sweep - 1] == 0;
 }
 
 // index of the i-th member (0..63) of pair block (a, b)
@@ -299,31 +307,30 @@ __device__ __forceinline__ int pair_index(int a, int b, int i) {
 // A rotation is applied when |a_pq| > max(tol sqrt(|a_pp a_qq|), tol * trace(G)):
 // the relative test gives small eigenvalues their accuracy, the absolute floor
 // stops rotations that only chase the rounding of the tile updates.
-__global__ __launch_bounds__(kJT) void k_jacobi_solve(const double* __restrict__ G, int R,
+__global__ __launch_bounds__(kJS) void k_jacobi_solve(const double* __restrict__ G, int R,
                                                       int round, double* __restrict__ Qbuf,
                                                       int* __restrict__ counters, int sweep,
                                                       const double* __restrict__ gnorm) {
-  if (sweep > 0 && counters[sweep - 1] == 0) return;  // converged at an earlier sweep
+  if (jacobi_skip(counters, sweep)) return;
   const double floor_abs = kJacTol * (*gnorm);
   __shared__ double S[kJP][kJP + 1];
   __shared__ double Q[kJP][kJP + 1];
   __shared__ double cs[kJB][2];
   __shared__ int pq[kJB][2];
-  __shared__ int rot_any;
   const int tid = threadIdx.x;
   const int nb = R / kJB;
   int a, b;
   rr_pair(nb, round, blockIdx.x, &a, &b);
-  for (int e = tid; e < kJP * kJP; e += kJT) {
+  for (int e = tid; e < kJP * kJP; e += kJS) {
     const int i = e / kJP, j = e % kJP;
     S[i][j] = G[(int64_t)pair_index(a, b, i) * R + pair_index(a, b, j)];
     Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  if (tid == 0) rot_any = 0;
+  bool rotated = false;
   __syncthreads();
   // one cyclic sweep of the pair block per visit (block Jacobi); the outer
-  // sweeps repeat until no block pair rotates.  Round-robin over the kJP
-  // indices: at step t rotation k pairs positions k and kJP-1-k of the
+  // sweeps repeat until the matrix passes the criterion.  Round-robin over the
+  // kJP indices: at step t rotation k pairs positions k and kJP-1-k of the
   // rotated order.
   for (int step = 0; step < kJP - 1; ++step) {
     if (tid < kJB) {
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_solve(const double* __restrict__
                                       : -1.0 / (-tau + sqrt(1.0 + tau * tau));
         c = 1.0 / sqrt(1.0 + t * t);
         sn = t * c;
-        rot_any = 1;
+        rotated = true;
       }
       cs[tid][0] = c;
       cs[tid][1] = sn;
@@ -346,11 +353,13 @@ __global__ __launch_bounds__(kJT) void k_jacobi_solve(const double* __restrict__
       pq[tid][1] = q;
     }
     __syncthreads();
-    // S <- J^T S J as independent 2x2 blocks: thread (a, b) takes rows
-    // {p_a, q_a} x columns {p_b, q_b} (row rotation, then column rotation);
-    // Q <- Q J on columns.  Blocks are disjoint, so one barrier per step.
-    {
-      const int ka = tid / kJB, kb2 = tid % kJB;   // kJB x kJB = kJT blocks
+    // S <- J^T S J as independent 2x2 blocks: block (ka, kb) covers rows
+    // {p_ka, q_ka} x columns {p_kb, q_kb} (row rotation, then column rotation);
+    // Q <- Q J on columns.  Blocks are disjoint.
+#pragma unroll
+    for (int h = 0; h < kJB * kJB / kJS; ++h) {
+      const int blk = tid + h * kJS;
+      const int ka = blk / kJB, kb2 = blk % kJB;
       const double sa = cs[ka][1], sb = cs[kb2][1];
       if (sa != 0.0 || sb != 0.0) {
         const int p = pq[ka][0], q = pq[ka][1], p2 = pq[kb2][0], q2 = pq[kb2][1];
@@ -369,25 +378,26 @@ __global__ __launch_bounds__(kJT) void k_jacobi_solve(const double* __restrict__
         }
         S[p][p2] = x00; S[p][q2] = x01; S[q][p2] = x10; S[q][q2] = x11;
       }
+    }
 #pragma unroll
-      for (int h = 0; h < kJR; ++h) {
-        const int e = tid + h * kJT;
-        const int k = e / kJP, i = e % kJP;
-        const double sn = cs[k][1];
-        if (sn != 0.0) {
-          const double c = cs[k][0];
-          const int pp = pq[k][0], qq = pq[k][1];
-          const double qp = Q[i][pp], qv = Q[i][qq];
-          Q[i][pp] = c * qp - sn * qv;
-          Q[i][qq] = sn * qp + c * qv;
-        }
+    for (int h = 0; h < kJB * kJP / kJS; ++h) {
+      const int e = tid + h * kJS;
+      const int k = e / kJP, i = e % kJP;
+      const double sn = cs[k][1];
+      if (sn != 0.0) {
+        const double c = cs[k][0];
+        const int pp = pq[k][0], qq = pq[k][1];
+        const double qp = Q[i][pp], qv = Q[i][qq];
+        Q[i][pp] = c * qp - sn * qv;
+        Q[i][qq] = sn * qp + c * qv;
       }
     }
     __syncthreads();
   }
   double* Qo = Qbuf + (int64_t)blockIdx.x * kJP * kJP;
-  for (int e = tid; e < kJP * kJP; e += kJT) Qo[e] = Q[e / kJP][e % kJP];
-  if (tid == 0 && rot_any) atomicAdd(&counters[sweep], 1);
+  for (int e = tid; e < kJP * kJP; e += kJS) Qo[e] = Q[e / kJP][e % kJP];
+  // only the first kJB threads (all in the first wavefront) compute rotations
+  if (__any(rotated) && tid == 0) atomicAdd(&counters[sweep], 1);
 }
 
 // G_out tile (P, Q) = Q_P^T G_in[P, Q] Q_Q for pair blocks P, Q of the round,
@@ -398,7 +408,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__
                                                       const double* __restrict__ Qbuf,
                                                       const int* __restrict__ counters,
                                                       int sweep) {
-  if (sweep > 0 && counters[sweep - 1] == 0) return;
+  if (jacobi_skip(counters, sweep)) return;
   __shared__ double T[kJP][kJP + 1];
   __shared__ double W[kJP][kJP + 1];
   const int tid = threadIdx.x;
@@ -476,7 +486,9 @@ __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__
 // diagonal, so the pair counts as converged when either entry passes.
 __global__ __launch_bounds__(256) void k_jacobi_check(const double* __restrict__ G, int R,
                                                      const double* __restrict__ gnorm,
-                                                     int* __restrict__ flag) {
+                                                     int* __restrict__ counters, int sweep) {
+  if (jacobi_skip(counters, sweep)) return;
+  int* flag = counters + 64 + sweep;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)R * R) return;
   const int i = (int)(e / R), j = (int)(e % R);
@@ -485,6 +497,14 @@ __global__ __launch_bounds__(256) void k_jacobi_check(const double* __restrict__
   const double apq = fmin(fabs(G[e]), fabs(G[(int64_t)j * R + i]));
   const double app = G[(int64_t)i * R + i], aqq = G[(int64_t)j * R + j];
   if (apq > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) *flag = 1;
+}
+
+// The check flag of sweep s, with the sequence number the host waits for, as
+// one 8-byte store into pinned host memory.
+__global__ void k_jacobi_report(const int* __restrict__ counters, int sweep,
+                                unsigned long long* __restrict__ slot, unsigned seq) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    *slot = ((unsigned long long)seq << 32) | (unsigned)counters[64 + sweep];
 }
 
 __global__ __launch_bounds__(256) void k_trace(const double* __restrict__ G, int R,
@@ -608,9 +628,34 @@ size_t jacobi_ws_doubles(int r) {
 // W(:, c) = v_c / sqrt(sig2_c).  ws must hold jacobi_ws_doubles(r) doubles;
 // counters (>= max_sweeps ints) and host_flag are scratch.  Returns
 // NYS_ERR_NOT_CONVERGED if a sweep still rotated after max_sweeps.
+// Wait until the device has written sequence number seq into the slot; the
+// stream is queried every few thousand polls so that a failed or drained
+// stream ends the wait with an error.
+nys_status wait_jacobi_slot(hipStream_t st, const volatile unsigned long long* slot, unsigned seq,
+                            int* val) {
+  for (long n = 1;; ++n) {
+    unsigned long long v = *slot;
+    if ((unsigned)(v >> 32) == seq) {
+      *val = (int)(unsigned)(v & 0xffffffffu);
+      return NYS_OK;
+    }
+    if (n % 4096 == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        v = *slot;
+        if ((unsigned)(v >> 32) != seq) return NYS_ERR_HIP;
+        *val = (int)(unsigned)(v & 0xffffffffu);
+        return NYS_OK;
+      }
+      if (e != hipErrorNotReady) return NYS_ERR_HIP;
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws, int* counters,
-                      int max_sweeps, void* host_pinned, double* sig2, double* W, int ldw,
-                      int* sweeps_out) {
+                      int max_sweeps, void* host_pinned, void* host_pinned_dev, int* poll_seq,
+                      double* sig2, double* W, int ldw, int* sweeps_out) {
   const int R = jacobi_pad(r);
   const int nb = R / kJB;
   const int np = nb / 2;
@@ -622,35 +667,52 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
   int* perm = reinterpret_cast<int*>(s2 + R);
   double* gnorm = s2 + 2 * R;   // perm occupies R ints = R/2 doubles
   const int64_t RR = (int64_t)R * R;
+  if (max_sweeps < 1 || max_sweeps > 60) return NYS_ERR_INVALID;
   hipLaunchKernelGGL(k_pad, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, G, r, ld, G0, R);
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, G0, R, gnorm);
   hipLaunchKernelGGL(k_eye, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, V, R);
-  // counters[s]: pair blocks that rotated in sweep s; counters[64 + s]: 1 if
-  // the matrix after sweep s still fails the criterion somewhere
-  if (max_sweeps > 60) return NYS_ERR_INVALID;
   if (hipMemsetAsync(counters, 0, sizeof(int) * 128, st) != hipSuccess) return NYS_ERR_HIP;
-  int sweeps = 0;
+  // Sweeps are enqueued one ahead of the host's reading of their check flag
+  // (written by the device into pinned memory), so the GPU does not idle on a
+  // host round trip between sweeps; a sweep enqueued after convergence returns
+  // at once.  after[s] is the buffer that holds the matrix after sweep s.
+  auto* slots_h = reinterpret_cast<volatile unsigned long long*>(
+      static_cast<char*>(host_pinned) + kJacSlotOffset);
+  auto* slots_d =
+      reinterpret_cast<unsigned long long*>(static_cast<char*>(host_pinned_dev) + kJacSlotOffset);
+  double* after[60];
+  unsigned seqs[60];
+  constexpr int kAhead = 2;
+  int enq = 0, sweeps = 0;
   bool converged = false;
   for (int s = 0; s < max_sweeps; ++s) {
-    for (int t = 0; t < nb - 1; ++t) {
-      hipLaunchKernelGGL(k_jacobi_solve, dim3(np), dim3(kJT), 0, st, G0, R, t, Qb, counters, s,
-                         gnorm);
-      hipLaunchKernelGGL(k_jacobi_apply, dim3(np * np + np * (R / kJP)), dim3(kJT), 0, st, G0,
-                         G1, V, R, t, Qb, counters, s);
-      std::swap(G0, G1);
+    while (enq < max_sweeps && enq - s < kAhead) {
+      for (int t = 0; t < nb - 1; ++t) {
+        hipLaunchKernelGGL(k_jacobi_solve, dim3(np), dim3(kJS), 0, st, G0, R, t, Qb, counters,
+                           enq, gnorm);
+        hipLaunchKernelGGL(k_jacobi_apply, dim3(np * np + np * (R / kJP)), dim3(kJT), 0, st, G0,
+                           G1, V, R, t, Qb, counters, enq);
+        std::swap(G0, G1);
+      }
+      after[enq] = G0;
+      // converged when every off-diagonal pair passes the rotation criterion,
+      // i.e. when the next sweep would not rotate
+      hipLaunchKernelGGL(k_jacobi_check, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st,
+                         G0, R, gnorm, counters, enq);
+      // sequence numbers are unique per context: stale slot contents never match
+      *poll_seq = (*poll_seq % 1000000000) + 1;
+      seqs[enq] = (unsigned)*poll_seq;
+      hipLaunchKernelGGL(k_jacobi_report, dim3(1), dim3(64), 0, st, counters, enq,
+                         slots_d + (enq % 4), seqs[enq]);
+      if (hipGetLastError() != hipSuccess) return NYS_ERR_HIP;
+      ++enq;
     }
+    int flag = 1;
+    NYS_TRY(wait_jacobi_slot(st, slots_h + (s % 4), seqs[s], &flag));
     ++sweeps;
-    // converged when every off-diagonal pair passes the rotation criterion,
-    // i.e. when the next sweep would not rotate (it is not run); checking
-    // after every sweep keeps the host-side buffer swap in step
-    hipLaunchKernelGGL(k_jacobi_check, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, G0,
-                       R, gnorm, counters + 64 + s);
-    if (hipMemcpyAsync(host_pinned, counters + 64 + s, sizeof(int), hipMemcpyDeviceToHost, st) !=
-            hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return NYS_ERR_HIP;
-    if (*static_cast<int*>(host_pinned) == 0) {
+    if (flag == 0) {
       converged = true;
+      G0 = after[s];
       break;
     }
   }

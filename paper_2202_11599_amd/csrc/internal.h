@@ -31,10 +31,15 @@ namespace nys {
 void set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
 
 // Grow-only device buffer owned by a context or factor.
+// Device buffer from the library's block cache (see pool_* in api.hip): a
+// released block is reused once the work queued on every live context stream
+// at release time has completed, so a step that rebuilds its factor does not
+// pay hipMalloc/hipFree (and the device-wide synchronisation of hipFree).
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
-  nys_status reserve(size_t want);
+  int device = -1;
+  nys_status reserve(size_t want);   // contents are not preserved when it grows
   void release();
   template <typename T>
   T* as() const { return static_cast<T*>(ptr); }
@@ -130,8 +135,8 @@ nys_status power_iter(hipStream_t st, const double* G, int r, int ld, int iters,
 int jacobi_pad(int r);
 size_t jacobi_ws_doubles(int r);
 nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws, int* counters,
-                      int max_sweeps, void* host_pinned, double* sig2, double* W, int ldw,
-                      int* sweeps_out);
+                      int max_sweeps, void* host_pinned, void* host_pinned_dev, int* poll_seq,
+                      double* sig2, double* W, int ldw, int* sweeps_out);
 // Stop when ||w|| <= max(abs_tol, tol ||rhs||) (o.tol_abs: ||w|| <= o.tol).
 // hx_tag >= 0: H_rho x saved by the previous run's true-residual pass gives w0
 // without a pass over A when that run had the same (A, D, x pointer, c, rho)
@@ -166,6 +171,7 @@ struct AtbKey {
 
 constexpr size_t kPinnedBytes = 65536;     // pinned readback area of a context
 constexpr size_t kPollOffset = 61440;      // PCG polling slots (4 x 64 bytes) in it
+constexpr size_t kJacSlotOffset = kPollOffset + 512;   // eigensolver sweep slots (4 x 8 bytes)
 
 struct nys_ctx_s {
   int device = 0;
@@ -215,6 +221,10 @@ struct nys_factor_s {
 };
 
 namespace nys {
+
+// ---- block cache (api.hip)
+void pool_register_stream(int device, hipStream_t st);
+void pool_unregister_stream(int device, hipStream_t st);
 
 // ---- gemv.hip
 GramPlan make_gram_plan(const nys_dense& A, int num_cu);

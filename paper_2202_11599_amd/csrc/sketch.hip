@@ -491,8 +491,8 @@ nys_status nys_core(nys_ctx ctx, nys_factor F, double test_mu, int* above) {
     }
   }
   int sweeps = 0;
-  NYS_TRY(jacobi_eig(st, w.G, r, r, w.jac, w.ints + 16, 40, ctx->host_pinned, w.sig2, w.W, r,
-                     &sweeps));
+  NYS_TRY(jacobi_eig(st, w.G, r, r, w.jac, w.ints + 16, 40, ctx->host_pinned,
+                     ctx->host_pinned_dev, &ctx->poll_seq, w.sig2, w.W, r, &sweeps));
   // U = B V Sigma^-1
   NYS_TRY(F->U.reserve(sizeof(double) * d * r));
   NYS_TRY(gemm64(st, (int)d, r, r, w.Bm, false, 1, d, w.W, false, r, 1, F->U.as<double>(), 1, d,
@@ -521,8 +521,7 @@ nys_status grow(nys::DevBuf& b, size_t old_bytes, size_t new_bytes, hipStream_t 
   NYS_TRY(nb.reserve(new_bytes));
   if (old_bytes > 0 && b.ptr != nullptr)
     NYS_TRY_HIP(hipMemcpyAsync(nb.ptr, b.ptr, old_bytes, hipMemcpyDeviceToDevice, st));
-  NYS_TRY_HIP(hipStreamSynchronize(st));
-  b.release();
+  b.release();   // reused only after the queued copy has run
   b = nb;
   return NYS_OK;
 }
@@ -579,7 +578,6 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
         NYS_TRY_HIP(hipMemcpy2DAsync(nb.ptr, sizeof(double) * cap, F->Mbase.ptr,
                                      sizeof(double) * F->cap, sizeof(double) * r0, r0,
                                      hipMemcpyDeviceToDevice, st));
-      NYS_TRY_HIP(hipStreamSynchronize(st));
       F->Mbase.release();
       F->Mbase = nb;
     }
@@ -676,7 +674,6 @@ nys_status sketch_and_core(nys_ctx ctx, const nys_dense& A, const double* D, dou
     nys::DevBuf saved = Mb;
     Mb = tmp;
     nys_status s = nys_core(ctx, F, test_mu, above);
-    NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
     Mb.release();
     Mb = saved;
     return s;

@@ -205,3 +205,32 @@ def test_sketch_full_size_properties(N, ctx, prec):
     assert np.all(lam[:5] <= sig2 * (1 + tol))
     assert np.all(lam[:5] >= sig2 * (1 - 1e-2))
     F.close()
+
+
+def test_repeated_sketches_reuse_device_blocks(N):
+    # Factors built, destroyed and rebuilt in a loop (their device blocks are
+    # handed out again by the library's block cache, also while the previous
+    # factor's work may still be queued): every rebuild gives bit-for-bit the
+    # same factor, on one context and on a second one created and destroyed in
+    # between; a factor that outlives its context is still destroyed cleanly.
+    d, n = 600, 8000
+    A32 = synth.decay_matrix(n, d, 0.8, seed=41).to(torch.float32).to(DEV)
+    om = synth.omega_raw(d, 160, seed=41).to(DEV)
+    c1 = N.Context()
+    ref = None
+    for k in range(4):
+        c = c1 if k != 2 else N.Context()
+        F = N.nys_sketch_adaptive(c, A32, om, 20, 160, 1e-3, 2.0, prec=N.NYS_F32)
+        U = F.U(c).clone()
+        inf = F.info()
+        if ref is None:
+            ref = (U, inf["lam"], inf["rank"])
+        else:
+            assert inf["rank"] == ref[2] and inf["lam"] == ref[1]
+            assert torch.equal(U, ref[0])
+        F.close()
+        if c is not c1:
+            c.close()
+    F = N.nys_sketch(c1, A32, om[:40].contiguous(), prec=N.NYS_F32)
+    c1.close()
+    F.close()
