@@ -647,6 +647,9 @@ nys_status nys_ctx_profile_stop(nys_ctx ctx, long* launches, double* total_ms) {
 
 nys_status nys_ctx_set_stream(nys_ctx ctx, void* hip_stream) {
   if (ctx == nullptr) return NYS_ERR_INVALID;
+  // the block cache guards released blocks with events on every live stream
+  pool_register_stream(ctx->device, static_cast<hipStream_t>(hip_stream));
+  pool_unregister_stream(ctx->device, ctx->stream);
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   return NYS_OK;
 }
