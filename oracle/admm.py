@@ -22,6 +22,10 @@ Follows Algorithm NysADMM (Section 2.3) on top of Algorithm Inexact ADMM
              absolute on ||w||, starting at 1e-2 ||rhs|| and floored at
              pcg_tol ||rhs|| (our reading).
 
+Comparison form: cg=True runs the x-update by plain CG (no preconditioner,
+no sketch) -- inexact ADMM with CG, the first row of Table
+t-ComplexityComparison -- with the same stopping rule.
+
 Readings: x = z = u = 0 initially; PCG is warm-started at the previous x; the
 returned solution is z (sparse), x is reported too; the logistic model is
 linearised at x (as printed); its factor is rebuilt every `resketch_every`
@@ -115,12 +119,13 @@ def _stop(r_p, r_d, x, z, u, rho, eps_abs, eps_rel):
 def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
                exact=False, factor=None, eps_abs=None, eps_rel=None,
                tol_schedule=False, state=None, mantissa_bits=52,
-               pcg_max_iter=1000) -> ADMMResult:
-    """Algorithm NysADMM for min 1/2||Ax - b||^2 + c/2||x||^2 + gamma||x||_1."""
+               pcg_max_iter=1000, cg=False) -> ADMMResult:
+    """Algorithm NysADMM for min 1/2||Ax - b||^2 + c/2||x||^2 + gamma||x||_1
+    (cg=True: inexact ADMM with plain CG)."""
     A = np.asarray(A, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     d = A.shape[1]
-    if not exact and factor is None:
+    if not exact and not cg and factor is None:
         factor = rand_nys_appx(A, None, c, omega_raw, mantissa_bits)
     if state is None:
         x, z, u = np.zeros(d), np.zeros(d), np.zeros(d)
@@ -131,7 +136,8 @@ def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
     if exact:   # the subproblem matrix is constant for least squares: factor once
         chol = sla.cho_factor(A.T @ A + (c + rho) * np.eye(d))
     matvec = lambda p: hessian_apply(A, None, c, p) + rho * p
-    precond = None if exact else (lambda w: precond_inverse_apply(factor.U, factor.lam, rho, w))
+    precond = None if (exact or cg) else (
+        lambda w: precond_inverse_apply(factor.U, factor.lam, rho, w))
     its, rps, rds = [], [], []
     eps_k = None
     converged = False
@@ -165,9 +171,9 @@ def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
 
 def admm_logistic(A, b, gamma, rho, omega_raw=None, iters=100, pcg_tol=1e-6,
                   resketch_every=10, exact=False, rel_change_tol=None, state=None,
-                  mantissa_bits=52, pcg_max_iter=1000) -> ADMMResult:
+                  mantissa_bits=52, pcg_max_iter=1000, cg=False) -> ADMMResult:
     """Linearised NysADMM for min -sum(b_i t_i - log(1 + e^t_i)) + gamma||x||_1,
-    t = A x, labels b in {0, 1}."""
+    t = A x, labels b in {0, 1} (cg=True: inexact ADMM with plain CG)."""
     A = np.asarray(A, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     d = A.shape[1]
@@ -186,10 +192,11 @@ def admm_logistic(A, b, gamma, rho, omega_raw=None, iters=100, pcg_tol=1e-6,
             x = dense_solve(A, w, 0.0, rho, rhs)
             its.append(0)
         else:
-            if factor is None or (resketch_every and k % resketch_every == 0):
+            if not cg and (factor is None or (resketch_every and k % resketch_every == 0)):
                 factor = rand_nys_appx(A, w, 0.0, omega_raw, mantissa_bits)
             matvec = lambda p, w=w: hessian_apply(A, w, 0.0, p) + rho * p
-            precond = lambda v, f=factor: precond_inverse_apply(f.U, f.lam, rho, v)
+            precond = None if cg else (
+                lambda v, f=factor: precond_inverse_apply(f.U, f.lam, rho, v))
             res = nys_pcg(matvec, rhs, x, precond, pcg_tol, pcg_max_iter)
             x = res.x
             its.append(res.iters)

@@ -374,6 +374,27 @@ def test_inexact_and_exact_admm_agree_on_small_c1_shape():
     assert np.linalg.norm(ex.z - nx.z) <= 1e-8 * np.linalg.norm(ex.z)
 
 
+def test_cg_admm_tracks_exact_admm():
+    # Inexact ADMM with plain CG (Table t-ComplexityComparison, first row) at a
+    # tight tolerance tracks exact-solve ADMM and builds no factor.
+    r = rng(34)
+    A = r.standard_normal((300, 80)) / np.sqrt(np.arange(1, 81))
+    x = np.zeros(80)
+    x[r.choice(80, 5, replace=False)] = r.standard_normal(5)
+    b = A @ x + 0.01 * r.standard_normal(300)
+    gamma = 0.1 * np.abs(A.T @ b).max()
+    ex = ad.admm_lasso(A, b, gamma, 0.5, exact=True, iters=80)
+    cg = ad.admm_lasso(A, b, gamma, 0.5, iters=80, pcg_tol=1e-13, cg=True)
+    assert cg.factor is None
+    assert np.linalg.norm(ex.z - cg.z) <= 1e-8 * np.linalg.norm(ex.z)
+    assert min(cg.pcg_iters[1:]) > 0
+    bl = (np.sign(A @ x + 0.3 * r.standard_normal(300)) + 1) / 2
+    exl = ad.admm_logistic(A, bl, 0.5, 1.0, iters=40, exact=True)
+    cgl = ad.admm_logistic(A, bl, 0.5, 1.0, iters=40, pcg_tol=1e-13, cg=True)
+    assert cgl.factor is None
+    assert np.linalg.norm(exl.z - cgl.z) <= 1e-8 * max(np.linalg.norm(exl.z), 1e-300)
+
+
 # ---------------------------------------------------------------- logistic
 
 def test_logistic_weight_identity_and_rhs():
