@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--true-res-every", type=int, default=10,
                     help="check the FP64 true residual of every k-th subproblem (and the last "
                          "of a run); the others stop PCG on its recursive residual")
-    ap.add_argument("--workload", choices=["lasso", "logistic", "path", "learned"],
+    ap.add_argument("--workload", choices=["lasso", "logistic", "path", "learned", "cg"],
                     default="lasso",
                     help="lasso: 100000x4000 adaptive rank (default line); logistic: 200000x2000 "
                          "l1-logistic; path: 64 uneven lasso instances x 16 gammas, batched; "
@@ -60,6 +60,13 @@ def parse():
     ap.add_argument("--copy-reference", action="store_true",
                     help="also run one 1.6 GB device copy (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+# lasso weight gamma = LASSO_GAMMA_FRAC * ||A^T b||_inf on the 100000 x 4000
+# problem: at this value a 30-iteration step from x = z = u = 0 reaches a
+# 437-sparse z with KKT residual ~5e-5 (at 0.1 the optimum has 2-4 nonzeros and
+# z stays 0 for the first ~200 iterations)
+LASSO_GAMMA_FRAC = 0.01
 
 
 def traffic_record(n, d):
@@ -216,6 +223,72 @@ def bench_logistic(args, N, synth, torch):
     return out
 
 
+def bench_cg(args, N, synth, torch):
+    """NysADMM against inexact ADMM with plain CG (Table t-ComplexityComparison)
+    on the 100000 x 4000 lasso over a path of subproblem tolerances: for each
+    tolerance, `its` ADMM iterations from a cold start with each method (NysADMM
+    including its adaptive sketch).  value = NysADMM solves/s at 1e-6."""
+    its = 10
+    p = synth.lasso_decay(args.n, args.d, 0.8, seed=0, device="cuda", dtype=torch.float32,
+                          frac=0.02, noise=0.01, gamma_frac=LASSO_GAMMA_FRAC, rho=1e-4, rank=50, s_max=800,
+                          pcg_tol=1e-6)
+    torch.cuda.synchronize()
+    A, b, omega = p.A, p.b.contiguous(), p.omega.contiguous()
+    ctx = N.Context()
+    prob = N.problem(A, b, p.gamma)
+
+    def run(tol, cg, profile=False):
+        if profile:
+            ctx.profile_start()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = None
+        if not cg:
+            F = N.nys_sketch_adaptive(ctx, A, omega, 50, 800, p.rho, 2.0, prec=N.NYS_F32)
+        rank = 0 if cg else F.info()["rank"]
+        o = N.admm_opts(p.rho, rank, None if cg else omega, sketch_prec=N.NYS_F32, max_iter=its,
+                        pcg=N.pcg_opts(tol=tol, max_iter=20000), factor=F,
+                        true_res_every=args.true_res_every)
+        st = N.State(p.d, "cuda")
+        info = N.admm_solve(ctx, [prob], [o], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if F is not None:
+            F.close()
+        prof = ctx.profile_stop() if profile else None
+        return wall, info, rank, prof
+
+    run(1e-6, False)
+    run(1e-2, True)
+    rows, value, prof = [], None, None
+    for tol in (1e-2, 1e-4, 1e-6, 1e-8):
+        wn, inn, rank, _ = run(tol, False)
+        wc, inc, _, pr = run(tol, True, profile=(tol == 1e-6))
+        prof = pr or prof
+        row = {"tol": tol,
+               "nysadmm": {"solves_per_s": round(inn.iters / wn, 3),
+                           "iters_per_solve": round(inn.pcg_iters / inn.iters, 2),
+                           "rank": rank, "eta": inn.eta},
+               "cg_admm": {"solves_per_s": round(inc.iters / wc, 3),
+                           "iters_per_solve": round(inc.pcg_iters / inc.iters, 2),
+                           "eta": inc.eta},
+               "speedup": round(wc / wn, 2)}
+        rows.append(row)
+        print(f"[bench] tol {tol:g}: NysADMM {row['nysadmm']} CG {row['cg_admm']}",
+              file=sys.stderr, flush=True)
+        if tol == 1e-6:
+            value = inn.iters / wn
+    out = base_record(value, 1, 1, its / value, "f32", {
+        "workload": f"lasso-{args.n}x{args.d}-fp32-sigma_j=j^-0.8-nysadmm-vs-cg-admm-"
+                    f"tol-path-{its}iters-cold",
+        "n": args.n, "d": args.d, "rho": p.rho, "gamma": p.gamma,
+        "admm_iters_per_point": its, "true_res_every": args.true_res_every})
+    out["roofline"] = roofline(prof, float(args.n) * args.d * 4, args.n, args.d)
+    out["roofline"]["note"] = "pair launches of the CG run at 1e-6"
+    out["tol_path"] = rows
+    return out
+
+
 def bench_path(args, N, synth, torch):
     """Regularisation path: `instances` uneven lasso problems (n in [5000,
     50000], d in [500, 3000], sigma_j = j^-0.7, rank 100, rho 1e-3), each
@@ -352,7 +425,7 @@ def main():
         from paper_2202_11599_amd import synth
         torch.cuda.set_device(0)
         fn = {"logistic": bench_logistic, "path": bench_path,
-              "learned": bench_learned}[args.workload]
+              "learned": bench_learned, "cg": bench_cg}[args.workload]
         print(json.dumps(fn(args, N, synth, torch)), flush=True)
         return
     from paper_2202_11599_amd import nysadmm as N
@@ -361,7 +434,7 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     p = synth.lasso_decay(args.n, args.d, 0.8, seed=0, device="cuda", dtype=torch.float32,
-                          frac=0.02, noise=0.01, gamma_frac=0.1, rho=1e-4, rank=50, s_max=800,
+                          frac=0.02, noise=0.01, gamma_frac=LASSO_GAMMA_FRAC, rho=1e-4, rank=50, s_max=800,
                           pcg_tol=1e-6)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
@@ -414,7 +487,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"lasso-{args.n}x{args.d}-fp32-sigma_j=j^-0.8-adaptive-rank-50..800",
+            "workload": f"lasso-{args.n}x{args.d}-fp32-sigma_j=j^-0.8-adaptive-rank-50..800-"
+                        f"gamma={LASSO_GAMMA_FRAC}||A^Tb||inf",
             "n": args.n, "d": args.d, "rho": p.rho, "gamma": p.gamma, "pcg_tol": p.pcg_tol,
             "admm_iters_per_step": args.admm_iters, "ada_tol": 2.0,
             "rank_final": plain["ranks"][-1], "true_res_every": tre,

@@ -204,12 +204,15 @@ typedef struct {
 
 typedef struct {
   double rho;            /* ADMM step size, > 0 */
-  int rank;              /* fixed rank, or the initial rank s0 of the adaptive sketch */
+  int rank;              /* fixed rank, or the initial rank s0 of the adaptive sketch;
+                            0: inexact ADMM with plain CG (no sketch, no preconditioner;
+                            the comparison method of Table t-ComplexityComparison) */
   int rank_max;          /* adaptive: s_max; <= rank means fixed rank */
   double ada_tol;        /* adaptive: Tol = 1 + epsilon of eq. (empCondNum) */
   int resketch_every;    /* logistic: rebuild the factor every k iterations (0: never) */
   nys_dtype sketch_prec; /* NYS_F64, NYS_F32 or NYS_BF16 */
-  const double* omega;   /* device FP64 column-major d x max(rank, rank_max) Gaussian entries */
+  const double* omega;   /* device FP64 column-major d x max(rank, rank_max) Gaussian entries
+                            (unused when rank = 0) */
   nys_pcg_opts pcg;      /* subproblem tolerance and limits */
   int tol_schedule;      /* 1: eps^{k+1} = sqrt(||r_p|| ||r_d||) absolute (Section 5 setup) */
   int max_iter;          /* ADMM iterations (admm_solve) */

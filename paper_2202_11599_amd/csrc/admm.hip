@@ -250,7 +250,7 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
     hipLaunchKernelGGL(k_rhs, dim3(blocks(d)), dim3(256), 0, st, d, O.rho, S->z, S->u, w.g,
                        w.rhs);
     D = w.Dw;
-    if (*F == nullptr || (O.resketch_every > 0 && S->k % O.resketch_every == 0)) {
+    if (O.rank > 0 && (*F == nullptr || (O.resketch_every > 0 && S->k % O.resketch_every == 0))) {
       nys_factor nf = nullptr;
       NYS_TRY(nys_sketch(ctx, &A, D, P.c, O.omega, O.rank, O.sketch_prec, &nf));
       if (*F != nullptr) nys_factor_destroy(*F);
@@ -342,8 +342,15 @@ nys_status validate_problem(const nys_problem* P, const nys_admm_opts* O) {
   NYS_TRY(validate_dense(&P->A));
   if (P->b == nullptr || !(P->gamma >= 0.0) || !(P->c >= 0.0)) return NYS_ERR_INVALID;
   if (P->loss != NYS_LOSS_LS && P->loss != NYS_LOSS_LOGISTIC) return NYS_ERR_INVALID;
-  if (!(O->rho > 0.0) || O->rank < 1 || O->rank >= P->A.d || O->omega == nullptr)
-    return NYS_ERR_INVALID;
+  if (!(O->rho > 0.0) || O->rank < 0 || O->rank >= P->A.d) return NYS_ERR_INVALID;
+  if (O->rank == 0) {
+    // inexact ADMM with plain CG: no sketch, no factor, no warm-start candidate
+    if (O->rank_max > 0 || O->factor != nullptr || O->warm_start != nullptr ||
+        O->ws_analytic || O->ws_features != nullptr || O->ws_target != nullptr)
+      return NYS_ERR_INVALID;
+    return NYS_OK;
+  }
+  if (O->omega == nullptr) return NYS_ERR_INVALID;
   if (O->warm_start != nullptr && !(P->gamma > 0.0)) return NYS_ERR_INVALID;
   if (O->rank_max > O->rank && (O->rank_max >= P->A.d || O->rank_max > 1024))
     return NYS_ERR_INVALID;
@@ -365,7 +372,8 @@ nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, 
   NYS_TRY_HIP(hipSetDevice(ctx->device));
   if (I) *I = nys_admm_info{};
   if (I) I->eta = I->obj = -1.0;
-  if (P->loss == NYS_LOSS_LS && *F == nullptr) {
+  if (O->rank == 0 && *F != nullptr) return NYS_ERR_INVALID;
+  if (P->loss == NYS_LOSS_LS && *F == nullptr && O->rank > 0) {
     NYS_TRY(nys_sketch(ctx, &P->A, nullptr, P->c, O->omega, O->rank, O->sketch_prec, F));
   }
   return admm_iter(ctx, *P, *O, F, S, I, 0.0, 0.0, false, true);
@@ -384,7 +392,8 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
   ctx->hx_key = AtbKey{};    // and x since an earlier solve
   bool batched = count > 1;
   for (int q = 0; q < count; ++q) {
-    if (P[q].loss != NYS_LOSS_LS || O[q].tol_schedule || O[q].kkt_tol > 0.0) batched = false;
+    if (P[q].loss != NYS_LOSS_LS || O[q].tol_schedule || O[q].kkt_tol > 0.0 || O[q].rank == 0)
+      batched = false;
     if (O[q].warm_start != nullptr || O[q].ws_analytic || O[q].ws_features != nullptr ||
         O[q].ws_target != nullptr)
       batched = false;
@@ -400,7 +409,7 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
     nys_factor F = o.factor;
     const bool own = (F == nullptr);
     nys_status s = NYS_OK;
-    if (p.loss == NYS_LOSS_LS && F == nullptr) {
+    if (p.loss == NYS_LOSS_LS && F == nullptr && o.rank > 0) {
       if (o.rank_max > o.rank && o.ada_tol >= 1.0)
         s = nys_sketch_adaptive(ctx, &p.A, nullptr, p.c, o.omega, o.rank, o.rank_max, o.rho,
                                 o.ada_tol, o.sketch_prec, &F);

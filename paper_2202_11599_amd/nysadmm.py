@@ -328,7 +328,7 @@ def pcg_solve(ctx: Context, A: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor,
     return info
 
 
-def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resketch_every=0,
+def admm_opts(rho, rank, omega_rows: Optional[torch.Tensor], rank_max=0, ada_tol=0.0, resketch_every=0,
               sketch_prec=NYS_F64, pcg: Optional[PcgOpts] = None, tol_schedule=False, max_iter=100,
               eps_abs=0.0, eps_rel=0.0, rel_change_tol=0.0, kkt_tol=0.0, kkt_every=10,
               factor: Optional["Factor"] = None, warm_start: Optional["WarmStart"] = None,
@@ -338,7 +338,8 @@ def admm_opts(rho, rank, omega_rows: torch.Tensor, rank_max=0, ada_tol=0.0, resk
         if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous CUDA float64 tensor")
     return AdmmOpts(float(rho), int(rank), int(rank_max), float(ada_tol), int(resketch_every),
-                    int(sketch_prec), omega_rows.data_ptr(), pcg or pcg_opts(), int(bool(tol_schedule)),
+                    int(sketch_prec), None if omega_rows is None else omega_rows.data_ptr(),
+                    pcg or pcg_opts(), int(bool(tol_schedule)),
                     int(max_iter), float(eps_abs), float(eps_rel), float(rel_change_tol),
                     float(kkt_tol), int(kkt_every), None if factor is None else factor.h.value,
                     None if warm_start is None else warm_start.h.value, int(bool(ws_analytic)),

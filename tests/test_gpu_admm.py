@@ -276,3 +276,38 @@ def test_true_residual_cadence_logistic(N, ctx):
         assert info.iters == its and 0.0 < info.true_res_max <= 1e-10 * (1 + 1e-6)
         zs.append(st.z.cpu().numpy())
     assert np.linalg.norm(zs[0] - zs[1]) <= 1e-9 * np.linalg.norm(zs[0])
+
+
+def test_cg_admm_parity(N, ctx):
+    # rank 0: inexact ADMM with plain CG (the comparison method of Table
+    # t-ComplexityComparison) against the oracle's CG form, lasso and logistic
+    p = small_lasso(seed=13)
+    A, b = p.A.numpy(), p.b.numpy()
+    its = 40
+    ora = ad.admm_lasso(A, b, p.gamma, p.rho, iters=its, pcg_tol=1e-10, cg=True)
+    st = N.State(p.d, DEV)
+    o = N.admm_opts(p.rho, 0, None, pcg=N.pcg_opts(tol=1e-10, max_iter=5000), max_iter=its)
+    info = N.admm_solve(ctx, [N.problem(p.A.to(DEV), p.b.to(DEV), p.gamma)], [o], [st])[0]
+    z = st.z.cpu().numpy()
+    ez = np.linalg.norm(z - ora.z) / np.linalg.norm(ora.z)
+    print(f"[cg admm] rel z diff {ez:.2e} cg iters {info.pcg_iters} vs oracle "
+          f"{sum(ora.pcg_iters)}", flush=True)
+    assert info.iters == its and info.rank == 0
+    assert ez < 1e-8
+    assert abs(info.pcg_iters - sum(ora.pcg_iters)) <= 0.02 * sum(ora.pcg_iters) + its
+    pl = synth.logistic_decay(4000, 150, seed=8, dtype=torch.float64, rho=5.0, rank=20,
+                              gamma_per_row=2e-3, pcg_tol=1e-10)
+    oral = ad.admm_logistic(pl.A.numpy(), pl.b.numpy(), pl.gamma, pl.rho, iters=20,
+                            pcg_tol=1e-10, cg=True)
+    st = N.State(pl.d, DEV)
+    o = N.admm_opts(pl.rho, 0, None, pcg=N.pcg_opts(tol=1e-10, max_iter=5000), max_iter=20)
+    N.admm_solve(ctx, [N.problem(pl.A.to(DEV), pl.b.to(DEV), pl.gamma,
+                                 loss=N.NYS_LOSS_LOGISTIC)], [o], [st])
+    zl = st.z.cpu().numpy()
+    assert np.linalg.norm(zl - oral.z) <= 1e-8 * np.linalg.norm(oral.z)
+    # rank 0 admits no factor or warm start
+    F = N.nys_sketch(ctx, p.A.to(DEV), p.omega.to(DEV), prec=N.NYS_F64)
+    with pytest.raises(N.NysError):
+        N.admm_solve(ctx, [N.problem(p.A.to(DEV), p.b.to(DEV), p.gamma)],
+                     [N.admm_opts(p.rho, 0, None, factor=F)], [N.State(p.d, DEV)])
+    F.close()
