@@ -16,6 +16,8 @@ via low-rank approximation", ICML 2022) by eye:
   admm      Algorithm NysADMM / Inexact ADMM for lasso (eq. 2) and l1-logistic
             regression (eq. 9), the residuals of Section 2.1, KKT residual (31)
   mlp       the warm-start network (not in the paper), FP64 forward/backward/Adam
+  svm       the kernel SVM dual (eq. 8) by NysADMM: RBF kernel, projection onto
+            {0 <= z <= C, b^T z = 0}, duality gap
 
 Parity status of every function is stated in its module header.
 """
