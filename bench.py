@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--true-res-every", type=int, default=10,
                     help="check the FP64 true residual of every k-th subproblem (and the last "
                          "of a run); the others stop PCG on its recursive residual")
-    ap.add_argument("--workload", choices=["lasso", "logistic", "path", "learned", "cg"],
+    ap.add_argument("--workload", choices=["lasso", "logistic", "path", "learned", "cg", "svm"],
                     default="lasso",
                     help="lasso: 100000x4000 adaptive rank (default line); logistic: 200000x2000 "
                          "l1-logistic; path: 64 uneven lasso instances x 16 gammas, batched; "
@@ -289,6 +289,65 @@ def bench_cg(args, N, synth, torch):
     return out
 
 
+def bench_svm(args, N, synth, torch):
+    """Kernel SVM dual (eq. 8) by NysADMM: n = 20000 two-class points in 16
+    dimensions, RBF kernel (gamma = 1/16), C = 1, rho = 1, rank 200, PCG tol
+    1e-6.  H = diag(b) K diag(b) is formed once (FP32, 1.6 GB, timed apart);
+    a step = its factor built once plus `admm_iters` ADMM iterations from a
+    cold start.  value = subproblem solves/s."""
+    n, p, r, its = 20000, 16, 200, args.admm_iters
+    X, b = synth.svm_points(n, p, seed=0, sep=1.5, device="cuda")
+    ctx = N.Context()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = N.kernel_rbf(ctx, X, 1.0 / p, b)
+    torch.cuda.synchronize()
+    kernel_s = time.perf_counter() - t0
+    omega = synth.omega_raw(n, r, seed=1, device="cuda").contiguous()
+
+    def steps(k, profile=False):
+        tot, pcg, bad, trm, sk, last = 0, 0, 0, -1.0, 0.0, None
+        if profile:
+            ctx.profile_start()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(k):
+            ts = time.perf_counter()
+            F = N.nys_sketch_sym(ctx, H, omega)
+            torch.cuda.synchronize()
+            sk += time.perf_counter() - ts
+            o = N.svm_opts(1.0, r, pcg=N.pcg_opts(tol=1e-6), max_iter=its, factor=F,
+                           true_res_every=args.true_res_every)
+            st = N.State(n, "cuda")
+            info = N.svm_solve(ctx, H, b, 1.0, o, st, allow=(N.NYS_OK, N.NYS_ERR_MAXITER))
+            tot += info.iters
+            pcg += info.pcg_iters
+            bad += info.status != N.NYS_OK
+            trm = max(trm, info.true_res_max)
+            last = info
+            F.close()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        return wall, tot, pcg, bad, trm, sk, last, (ctx.profile_stop() if profile else None)
+
+    steps(args.warmup)
+    wall, tot, pcg, bad, trm, sk, last, prof = steps(args.steps, profile=True)
+    out = base_record(tot / wall, args.steps, args.warmup, wall, "f32", {
+        "workload": f"kernel-svm-dual-rbf-n{n}-p{p}-C1-rank{r}-{its}iters",
+        "n": n, "p": p, "gamma": 1.0 / p, "C": 1.0, "rho": 1.0, "rank": r, "pcg_tol": 1e-6,
+        "admm_iters_per_step": its, "true_res_every": args.true_res_every})
+    out["roofline"] = roofline(prof, float(n) * n * 4, n, n)
+    out["roofline"]["kernel"] = "k_rowdot (y = H p by column blocks, FP32 H, FP64 sums)"
+    out["pcg_iters_mean"] = round(pcg / max(tot, 1), 3)
+    out["unconverged_solves"] = bad
+    out["true_rel_res_max"] = trm
+    out["sketch_ms"] = round(1e3 * sk / args.steps, 2)
+    out["kernel_matrix_ms"] = round(1e3 * kernel_s, 2)
+    out["after_step"] = {"gap_rel": last.gap_rel, "primal": last.primal, "dual": last.dual,
+                         "r_p": last.r_p, "r_d": last.r_d}
+    return out
+
+
 def bench_path(args, N, synth, torch):
     """Regularisation path: `instances` uneven lasso problems (n in [5000,
     50000], d in [500, 3000], sigma_j = j^-0.7, rank 100, rho 1e-3), each
@@ -425,7 +484,7 @@ def main():
         from paper_2202_11599_amd import synth
         torch.cuda.set_device(0)
         fn = {"logistic": bench_logistic, "path": bench_path,
-              "learned": bench_learned, "cg": bench_cg}[args.workload]
+              "learned": bench_learned, "cg": bench_cg, "svm": bench_svm}[args.workload]
         print(json.dumps(fn(args, N, synth, torch)), flush=True)
         return
     from paper_2202_11599_amd import nysadmm as N

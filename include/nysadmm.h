@@ -288,6 +288,72 @@ nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, 
 nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_admm_opts* O,
                       nys_admm_state* S, nys_admm_info* I);
 
+/* ------------------------------------------------------ kernel SVM (eq. 8) */
+
+/* H = diag(b) K diag(b) with the RBF kernel K_ij = exp(-gamma ||a_i - a_j||^2)
+ * (Section 3, support vector machine), written explicitly in FP32.
+ * X: device FP32 n x p row-major features (leading dimension ldx >= p);
+ * b: device FP64 labels (+-1), or NULL for K itself; H: device FP32 n x n
+ * row-major (ldh >= n), caller-owned.  The squared distances are formed in
+ * FP64 (FP64 products of the FP32 features), exp in FP64, then rounded. */
+nys_status nys_kernel_rbf(nys_ctx ctx, const float* X, int64_t n, int64_t p, int64_t ldx,
+                          const double* b, double gamma, float* H, int64_t ldh);
+
+/* Algorithm RandNysAppx of the explicit symmetric PSD matrix H = K + c I
+ * (K n x n, FP32 or FP64): Y = K Omega + c Omega with FP64 sums, then the FP64
+ * core as in nys_sketch.  *F == NULL creates a factor, else appends r
+ * columns.  omega: device FP64 n x r column-major Gaussian entries. */
+nys_status nys_sketch_sym(nys_ctx ctx, const nys_dense* K, double c, const double* omega, int r,
+                          nys_factor* F);
+
+/* Algorithm Nystrom PCG on (K + (c + rho) I) x = rhs for an explicit symmetric
+ * K (n x n): one pass over K per iteration, in blocks of columns.  F from
+ * nys_sketch_sym (or NULL: plain CG).  Otherwise as pcg_solve. */
+nys_status pcg_solve_sym(nys_ctx ctx, const nys_dense* K, double c, double rho, nys_factor F,
+                         const double* rhs, double* x, const nys_pcg_opts* opts,
+                         nys_pcg_info* info);
+
+typedef struct {
+  nys_dense H;       /* diag(b) K diag(b), n x n symmetric (e.g. from nys_kernel_rbf with b) */
+  const double* b;   /* device FP64 labels, +-1 */
+  double C;          /* box bound, > 0 */
+} nys_svm_problem;
+
+typedef struct {
+  double rho;          /* ADMM step size, > 0 */
+  int rank;            /* Nystrom rank (0: plain CG) */
+  const double* omega; /* device FP64 n x rank Gaussian entries (unless factor is given) */
+  nys_pcg_opts pcg;
+  int max_iter;        /* ADMM iterations; 0 means 100 */
+  double gap_tol;      /* stop when the relative duality gap <= gap_tol (<= 0: never) */
+  int gap_every;       /* gap check cadence (one pass over H each); 0 means 10 */
+  int true_res_every;  /* as in nys_admm_opts */
+  nys_factor factor;   /* optional factor of H from nys_sketch_sym (kept) */
+} nys_svm_opts;
+
+typedef struct {
+  int iters;
+  long pcg_iters;
+  int pcg_max;
+  double r_p, r_d;     /* last ||x - z||, rho ||z_old - z|| (at checks and at the end) */
+  double primal, dual; /* SVM primal (bias from the free variables) and dual objective at z */
+  double gap, gap_rel; /* primal - dual and (primal - dual) / (1 + |primal|) */
+  double bias;
+  int rank;
+  int converged;       /* the gap test fired */
+  nys_status status;
+  double true_res_max; /* as in nys_admm_info */
+} nys_svm_info;
+
+/* Algorithm NysADMM on the SVM dual: minimize 1/2 x^T H x - 1^T x subject to
+ * b^T x = 0, 0 <= x <= C.  x-update: PCG on (H + rho I) x = rho (z - u) + 1;
+ * z-update: projection of x + u onto the constraint set (clip(v - mu b, 0, C)
+ * with mu by bisection); u += x - z.  The state (x, z, u: device FP64
+ * n-vectors, x = z = u = 0 for a cold start) is updated in place; z is the
+ * feasible dual solution. */
+nys_status svm_solve(nys_ctx ctx, const nys_svm_problem* P, const nys_svm_opts* O,
+                     nys_admm_state* S, nys_svm_info* I);
+
 /* --------------------------------------------------- warm-start network */
 
 /* A small network proposing the PCG start of the ADMM subproblem in the

@@ -224,12 +224,11 @@ nys_status validate_dense(const nys_dense* A) {
 
 // Carves the PCG workspace out of the context buffers.
 nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws) {
-  const size_t ypb = align_up(sizeof(double) * ((size_t)pl.grid * pl.ldy)) +
-                     align_up(sizeof(double) * (size_t)std::max(pl.grid, 1));
+  const size_t yb = align_up(sizeof(double) * ((size_t)pl.ny() * pl.ldy));
+  const size_t ypb = yb + align_up(sizeof(double) * (size_t)std::max(pl.nq(), 1));
   NYS_TRY(ctx->ypart.reserve(ypb));
   ws->ypart = ctx->ypart.as<double>();
-  ws->qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ypart.ptr) +
-                                        align_up(sizeof(double) * ((size_t)pl.grid * pl.ldy)));
+  ws->qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ypart.ptr) + yb);
   const size_t nv = align_up(sizeof(double) * d);
   const size_t cb = align_up(sizeof(double) * 1024 * kDotSlices);
   const size_t vb = 3 * nv + cb + align_up(sizeof(double) * (size_t)(max_iter + 2));
@@ -264,8 +263,10 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
 nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int mode,
                     const double* p, const double* aux, double* auxout, double* ypart,
                     double* qpart, const int* done) {
+  if (plan.symv && (mode != kModeHess || aux != nullptr)) return NYS_ERR_INVALID;
   if (!ctx->prof_on || plan.grid == 0 || A.n == 0)
-    return launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream);
+    return plan.symv ? launch_symv(A, plan, p, ypart, qpart, done, ctx->stream)
+                     : launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream);
   if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
     for (int i = 0; i < 2; ++i) {
       // timing-only events: no system-scope fence (cache writeback) at each
@@ -275,8 +276,12 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
       ctx->prof_ev.push_back(e);
     }
   }
-  NYS_TRY(launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream,
-                      ctx->prof_ev[ctx->prof_used], ctx->prof_ev[ctx->prof_used + 1]));
+  if (plan.symv)
+    NYS_TRY(launch_symv(A, plan, p, ypart, qpart, done, ctx->stream, ctx->prof_ev[ctx->prof_used],
+                        ctx->prof_ev[ctx->prof_used + 1]));
+  else
+    NYS_TRY(launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream,
+                        ctx->prof_ev[ctx->prof_used], ctx->prof_ev[ctx->prof_used + 1]));
   ctx->prof_used += 2;
   return NYS_OK;
 }
@@ -387,7 +392,7 @@ nys_status wait_slot(hipStream_t st, const char* slot, int seq, PcgDev* out) {
 nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
                    nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
                    nys_pcg_info* info, double abs_tol, int64_t hx_tag, const double* x_alt,
-                   int* used_alt) {
+                   int* used_alt, bool symv) {
   if (used_alt) *used_alt = 0;
   const double tol_rel = o.tol_abs ? 0.0 : o.tol;
   const double tol_abs = o.tol_abs ? o.tol : abs_tol;
@@ -396,7 +401,12 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
   const int ahead = o.check_every > 0 ? std::min(o.check_every, 4) : 2;
   const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 2;
   GramPlan pl;
-  NYS_TRY(ctx_gram_plan(ctx, A, &pl));
+  if (symv) {
+    if (D != nullptr || A.n != A.d) return NYS_ERR_INVALID;
+    pl = make_symv_plan(A, ctx->num_cu);
+  } else {
+    NYS_TRY(ctx_gram_plan(ctx, A, &pl));
+  }
   PcgWs ws;
   NYS_TRY(pcg_workspace(ctx, pl, d, max_iter, &ws));
   const double rho_eff = rho + c;
@@ -424,18 +434,18 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
                                    ws.st, st));
     } else {
       NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr));
-      NYS_TRY(launch_reduce_update(1, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x, nullptr,
+      NYS_TRY(launch_reduce_update(1, ws.ypart, pl.ny(), pl.ldy, ws.qpart, d, rho_eff, x, nullptr,
                                    ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, ws.rrpart, ws.st,
-                                   st));
+                                   st, pl.nq()));
     }
     ctx->hx_key = AtbKey{};
     if (x_alt != nullptr && restarts == 0) {
       // judge: residual of the candidate start next to that of x, decided on
       // the device (the smaller ||w|| wins; ties keep x)
       NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, x_alt, D, nullptr, ws.ypart, ws.qpart, nullptr));
-      NYS_TRY(launch_reduce_update(1, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x_alt,
+      NYS_TRY(launch_reduce_update(1, ws.ypart, pl.ny(), pl.ldy, ws.qpart, d, rho_eff, x_alt,
                                    nullptr, ws.w2, rhs, ws.wy, 0, nullptr, 0, ws.wwpart2,
-                                   ws.rrpart2, ws.st, st));
+                                   ws.rrpart2, ws.st, st, pl.nq()));
       NYS_TRY(launch_judge(ws.wwpart, ws.wwpart2, ws.nred, x, x_alt, ws.w, ws.w2, d, ws.st, st));
     }
     NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred,
@@ -453,9 +463,9 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
     int seqs[4] = {0, 0, 0, 0};
     auto enqueue = [&](int k) -> nys_status {
       NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done));
-      NYS_TRY(launch_reduce_update(0, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
+      NYS_TRY(launch_reduce_update(0, ws.ypart, pl.ny(), pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
                                    ws.w, nullptr, ws.wy, k, ws.pppart, ws.nvec, ws.wwpart, nullptr,
-                                   ws.st, st));
+                                   ws.st, st, pl.nq()));
       NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred, nullptr,
                                  k, 0, tol_rel, tol_abs, st));
       // sequence numbers are unique per context, so a late write from an
@@ -523,8 +533,9 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
       hx_out = ctx->hx.as<double>();
     }
     NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr));
-    NYS_TRY(launch_reduce_update(2, ws.ypart, pl.grid, pl.ldy, ws.qpart, d, rho_eff, x, hx_out,
-                                 ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, nullptr, ws.st, st));
+    NYS_TRY(launch_reduce_update(2, ws.ypart, pl.ny(), pl.ldy, ws.qpart, d, rho_eff, x, hx_out,
+                                 ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, nullptr, ws.st, st,
+                                 pl.nq()));
     if (hx_tag >= 0) {
       ctx->hx_key = key;
       ctx->hx_rho = rho;
@@ -613,6 +624,7 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   ctx->gemm_ws.release();
   ctx->core_ws.release();
   ctx->admm_ws.release();
+  ctx->svm_ws.release();
   pool_unregister_stream(ctx->device, ctx->stream);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
@@ -762,9 +774,9 @@ nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, d
   PcgWs ws;
   NYS_TRY(pcg_workspace(ctx, pl, A->d, 1, &ws));
   NYS_TRY(ctx_gram(ctx, *A, pl, kModeHess, p, D, nullptr, ws.ypart, ws.qpart, nullptr));
-  NYS_TRY(launch_reduce_update(3, ws.ypart, pl.grid, pl.ldy, ws.qpart, A->d, rho + c, p, nullptr,
+  NYS_TRY(launch_reduce_update(3, ws.ypart, pl.ny(), pl.ldy, ws.qpart, A->d, rho + c, p, nullptr,
                                v, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, ws.st,
-                               ctx->stream));
+                               ctx->stream, pl.nq()));
   if (pv_host != nullptr) {
     NYS_TRY(launch_dot(v, p, A->d, &ws.st->true_rr, ctx->stream));
     PcgDev h;
@@ -785,6 +797,20 @@ nys_status pcg_solve(nys_ctx ctx, const nys_dense* A, const double* D, double c,
   if (F != nullptr && F->d != A->d) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
   return pcg_run(ctx, *A, D, c, rho, F, rhs, x, *opts, info);
+}
+
+nys_status pcg_solve_sym(nys_ctx ctx, const nys_dense* K, double c, double rho, nys_factor F,
+                         const double* rhs, double* x, const nys_pcg_opts* opts,
+                         nys_pcg_info* info) {
+  if (ctx == nullptr || rhs == nullptr || x == nullptr || opts == nullptr)
+    return NYS_ERR_INVALID;
+  NYS_TRY(validate_dense(K));
+  if (K->n != K->d || !(rho > 0.0) || !(c >= 0.0) || !(opts->tol >= 0.0) || opts->max_iter < 0)
+    return NYS_ERR_INVALID;
+  if (F != nullptr && F->d != K->d) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  return pcg_run(ctx, *K, nullptr, c, rho, F, rhs, x, *opts, info, 0.0, -1, nullptr, nullptr,
+                 true);
 }
 
 }  // extern "C"

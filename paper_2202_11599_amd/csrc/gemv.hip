@@ -88,6 +88,52 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_gram(
   if (tid == 0) qpart[blockIdx.x] = q;
 }
 
+// y = A p for an explicit symmetric A (kernel SVM), one block of columns per
+// blockIdx.y: the same streaming of rows as k_gram without the A^T pass; the
+// row dots of column block s go to ypart[s * ldy + row] (summed over blocks by
+// the reduction kernel) and sum_i p_i t_i to qpart[s * gridDim.x + blockIdx.x].
+template <typename T, int WAVES, int CPL, int R, bool ALIGNED>
+__global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_rowdot(
+    const T* __restrict__ A, int64_t n, int64_t ncols, int64_t ld, int slice_cols,
+    int64_t rows_per_wg, const double* __restrict__ p, double* __restrict__ ypart, int ldy,
+    double* __restrict__ qpart, const int* __restrict__ done) {
+  constexpr int NT = WAVES * 64;
+  constexpr int VN = Chunk<T>::N;
+  typedef typename Chunk<T>::V V;
+  if (done != nullptr && *done) return;
+  __shared__ double red[2][R][WAVES];
+  const int tid = threadIdx.x;
+  const int64_t c0s = (int64_t)blockIdx.y * slice_cols;
+  const int d = (int)((ncols - c0s < slice_cols) ? ncols - c0s : slice_cols);
+  const T* As = A + c0s;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = (r0 + rows_per_wg < n) ? r0 + rows_per_wg : n;
+  double pr[CPL][VN];
+#pragma unroll
+  for (int m = 0; m < CPL; ++m) {
+    const int c0 = col0<T, CPL, ALIGNED, NT>(tid, m);
+#pragma unroll
+    for (int v = 0; v < VN; ++v) pr[m][v] = (c0 + v < d) ? p[c0s + c0 + v] : 0.0;
+  }
+  double* out = ypart + (int64_t)blockIdx.y * ldy;
+  double q = 0.0;
+  int buf = 0;
+  V a0[R][CPL], a1[R][CPL];
+  T e0[R][Extra<T>::N], e1[R][Extra<T>::N];
+  double v0[R], v1[R];
+  load_group<T, CPL, R, ALIGNED, NT>(a0, e0, v0, As, p, r0, r1, d, ld, tid);
+  for (int64_t row = r0; row < r1; row += 2 * R) {
+    load_group<T, CPL, R, ALIGNED, NT>(a1, e1, v1, As, p, row + R, r1, d, ld, tid);
+    realign_group<T, CPL, R, ALIGNED, NT>(a0, e0, As, row, d, ld, tid);
+    rowdot_group<T, WAVES, CPL, R>(a0, v0, row, r1, pr, q, out, red, buf, tid);
+    if (row + R >= r1) break;
+    load_group<T, CPL, R, ALIGNED, NT>(a0, e0, v0, As, p, row + 2 * R, r1, d, ld, tid);
+    realign_group<T, CPL, R, ALIGNED, NT>(a1, e1, As, row + R, d, ld, tid);
+    rowdot_group<T, WAVES, CPL, R>(a1, v1, row + R, r1, pr, q, out, red, buf, tid);
+  }
+  if (tid == 0) qpart[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = q;
+}
+
 template <typename T, int WAVES, int CPL, int R>
 nys_status launch_r(const nys_dense& A, const GramPlan& pl, int mode, const double* p,
                     const double* aux, double* auxout, double* ypart, double* qpart,
@@ -224,6 +270,66 @@ GramPlan make_gram_plan(const nys_dense& A, int num_cu) {
   }
   finish_plan(A, num_cu, per_cu, &pl);
   return pl;
+}
+
+// Plan of the column-blocked y = A p (explicit symmetric A): blocks of 4096
+// columns (4 waves x 4 chunks of 4 floats; 2048 for FP64), rows split so that
+// blocks x row ranges give about two workgroups per CU.
+GramPlan make_symv_plan(const nys_dense& A, int num_cu) {
+  GramPlan pl;
+  pl.symv = true;
+  pl.waves = 4;
+  pl.cpl = 4;
+  pl.rows = 2;
+  const int vn = A.dtype == NYS_F64 ? 2 : 4;
+  pl.slice_cols = pl.waves * 64 * pl.cpl * vn;
+  pl.slices = (int)std::max<int64_t>(1, (A.d + pl.slice_cols - 1) / pl.slice_cols);
+  const int esize = A.dtype == NYS_F64 ? 8 : 4;
+  pl.aligned = ((uintptr_t)A.data % 16 == 0) && ((A.ld * esize) % 16 == 0);
+  pl.ldy = (int)((A.n + 63) / 64 * 64);
+  pl.per_cu = 2;
+  if (A.n <= 0) {
+    pl.grid = 0;
+    pl.rows_per_wg = 0;
+    return pl;
+  }
+  const int64_t groups = (A.n + pl.rows - 1) / pl.rows;
+  const int64_t want = std::max<int64_t>(1, (int64_t)pl.per_cu * num_cu / pl.slices);
+  const int64_t g = std::min<int64_t>(want, std::max<int64_t>(1, groups / 2));
+  pl.rows_per_wg = ((A.n + g - 1) / g + pl.rows - 1) / pl.rows * pl.rows;
+  pl.grid = (int)((A.n + pl.rows_per_wg - 1) / pl.rows_per_wg);
+  return pl;
+}
+
+nys_status launch_symv(const nys_dense& A, const GramPlan& pl, const double* p, double* ypart,
+                       double* qpart, const int* done, hipStream_t st, hipEvent_t ev0,
+                       hipEvent_t ev1) {
+  if (!pl.symv || pl.waves != 4 || pl.cpl != 4 || pl.rows != 2) return NYS_ERR_INVALID;
+  if (A.n != A.d) return NYS_ERR_INVALID;
+  if (A.n == 0 || pl.grid == 0) return NYS_OK;
+  const dim3 grid(pl.grid, pl.slices);
+#define NYS_SYMV(T, AL)                                                                        \
+  do {                                                                                         \
+    const T* a = static_cast<const T*>(A.data);                                                \
+    if (ev0 != nullptr)                                                                        \
+      hipExtLaunchKernelGGL((k_rowdot<T, 4, 4, 2, AL>), grid, dim3(256), 0, st, ev0, ev1, 0, a, \
+                            A.n, A.d, A.ld, pl.slice_cols, pl.rows_per_wg, p, ypart, pl.ldy,   \
+                            qpart, done);                                                      \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_rowdot<T, 4, 4, 2, AL>), grid, dim3(256), 0, st, a, A.n, A.d,       \
+                         A.ld, pl.slice_cols, pl.rows_per_wg, p, ypart, pl.ldy, qpart, done);  \
+  } while (0)
+  if (A.dtype == NYS_F32) {
+    if (pl.aligned) NYS_SYMV(float, true);
+    else NYS_SYMV(float, false);
+  } else if (A.dtype == NYS_F64) {
+    if (pl.aligned) NYS_SYMV(double, true);
+    else NYS_SYMV(double, false);
+  } else {
+    return NYS_ERR_INVALID;
+  }
+#undef NYS_SYMV
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
 nys_status launch_gram(const nys_dense& A, const GramPlan& pl, int mode, const double* p,

@@ -263,5 +263,51 @@ __device__ __forceinline__ void process_group(
       for (int v = 0; v < VN; ++v) yr[m][v] = fma(sv[i], (double)a[i][m][v], yr[m][v]);
 }
 
+// Row dots only (y = A p over one block of columns, A explicit and
+// symmetric in the kernel SVM): t_i = A_i p is written to out[row + i] and
+// q += pr_i t_i, with pr_i = p at the row index (loaded with the row as av).
+template <typename T, int WAVES, int CPL, int R>
+__device__ __forceinline__ void rowdot_group(const typename Chunk<T>::V (&a)[R][CPL],
+                                             const double (&av)[R], int64_t row, int64_t r1,
+                                             const double (&pr)[CPL][Chunk<T>::N], double& q,
+                                             double* __restrict__ out, double (*red)[R][WAVES],
+                                             int& buf, int tid) {
+  constexpr int VN = Chunk<T>::N;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  double t[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < CPL; ++m)
+#pragma unroll
+      for (int v = 0; v < VN; ++v) acc = fma((double)a[i][m][v], pr[m][v], acc);
+    t[i] = wave_sum(acc);
+  }
+  if (WAVES > 1) {
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) red[buf][i][wv] = t[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) sacc += red[buf][i][w];
+      t[i] = sacc;
+    }
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (row + i < r1) {
+      q = fma(av[i], t[i], q);
+      if (tid == i) out[row + i] = t[i];
+    }
+  }
+}
+
 }  // namespace gram
 }  // namespace nys

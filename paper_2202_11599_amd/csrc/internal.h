@@ -72,6 +72,14 @@ struct GramPlan {
   int64_t rows_per_wg = 0;
   bool aligned = true;
   int ldy = 0;       // leading dimension of the per-workgroup partial sums
+  // column-blocked y = A p of an explicit symmetric A (kernel SVM): blockIdx.y
+  // runs over `slices` blocks of slice_cols columns; the y partials are one
+  // n-vector per block, the q partials one per workgroup
+  bool symv = false;
+  int slices = 1;
+  int slice_cols = 0;
+  int ny() const { return symv ? slices : grid; }
+  int nq() const { return symv ? slices * grid : grid; }
 };
 
 enum GramMode : int {
@@ -147,7 +155,7 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
 nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, double rho,
                    nys_factor F, const double* rhs, double* x, const nys_pcg_opts& o,
                    nys_pcg_info* info, double abs_tol = 0.0, int64_t hx_tag = -1,
-                   const double* x_alt = nullptr, int* used_alt = nullptr);
+                   const double* x_alt = nullptr, int* used_alt = nullptr, bool symv = false);
 
 // ---- mlp.hip
 nys_status ws_propose(nys_ctx ctx, nys_ws_model m, nys_factor F, const double* rhs, double gamma,
@@ -183,6 +191,7 @@ struct nys_ctx_s {
   nys::DevBuf gemm_ws;   // sketch temporaries (T = A Omega, ...)
   nys::DevBuf core_ws;   // FP64 core temporaries
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
+  nys::DevBuf svm_ws;    // kernel SVM vectors (rhs, H z, scalars)
   void* host_pinned = nullptr;  // pinned readback area of kPinnedBytes
   void* host_pinned_dev = nullptr;  // the same memory as seen from the device
   int poll_seq = 0;              // last sequence number of a PCG state slot write
@@ -218,6 +227,7 @@ struct nys_factor_s {
   nys::DevBuf Mbase;         // FP64 cap x cap, Omega^T H Omega from T (FP32/BF16 sketches)
   std::vector<double> lam_host;
   bool use_u32 = false;
+  bool sym = false;          // factor of an explicit symmetric H = K + c I (kernel SVM)
 };
 
 namespace nys {
@@ -235,6 +245,11 @@ nys_status launch_gram(const nys_dense& A, const GramPlan& plan, int mode, const
                        const int* done, hipStream_t st,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+GramPlan make_symv_plan(const nys_dense& A, int num_cu);
+nys_status launch_symv(const nys_dense& A, const GramPlan& plan, const double* p, double* ypart,
+                       double* qpart, const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
+
 // ---- vec.hip
 constexpr int kVecBlock = 32;    // entries of y per workgroup of the preconditioner update
 constexpr int kRedBlock = 16;    // columns per workgroup of the partial reduction
@@ -251,7 +266,7 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 int64_t d, double rho_eff, const double* p, double* x, double* w,
                                 const double* rhs, double* wy, int k, const double* pppart,
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
-                                hipStream_t stream);
+                                hipStream_t stream, int Gq = -1);   // Gq: q partials (-1: G)
 // *out = a^T b (one workgroup, fixed order)
 // Judge of two PCG starts: ||w||^2 from wwpart and from wwpart2 (same fixed
 // summation order); if the second is smaller, x <- x_alt, w <- w2,

@@ -590,7 +590,12 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
   NYS_TRY(orthonormalize(ctx, Om, d, m, w));
   double* Y = F->Y.as<double>();
   const bool a32 = (A.dtype == NYS_F32);
-  if (F->prec == NYS_F64) {
+  if (F->sym) {
+    // explicit symmetric H = A + c I (kernel SVM): Y = A Omega + c Omega, FP64 sums
+    NYS_TRY_HIP(hipMemcpyAsync(Y + d * r0, Om, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
+    NYS_TRY(gemm64(st, (int)n, m, (int)d, A.data, a32, A.ld, 1, Om, false, 1, d, Y + d * r0, 1, d,
+                   1.0, c, w.split, w.split_elems));
+  } else if (F->prec == NYS_F64) {
     // T = A Omega (n x m, column-major) in FP64 tiles, Y = A^T (D o T) + c Omega
     NYS_TRY(ctx->gemm_ws.reserve(sizeof(double) * n * m + 256));
     double* T = ctx->gemm_ws.as<double>();
@@ -684,7 +689,7 @@ nys_status sketch_and_core(nys_ctx ctx, const nys_dense& A, const double* D, dou
 // One round of the sketch: extend *F by m columns and rebuild its core.
 nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double c,
                         const double* omega, int r, nys_dtype prec, nys_factor* F,
-                        double test_mu, int* above) {
+                        double test_mu, int* above, bool sym = false) {
   if (ctx == nullptr || F == nullptr || omega == nullptr) return NYS_ERR_INVALID;
   NYS_TRY(validate_dense(A));
   if (!(c >= 0.0) || r < 1) return NYS_ERR_INVALID;
@@ -693,7 +698,9 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
   if (A->d > (int64_t)1 << 30 || A->n > ((int64_t)1 << 31) - 1) return NYS_ERR_INVALID;
   const int r_old = (*F != nullptr) ? (*F)->r : 0;
   if (r_old + r >= A->d || r_old + r > 1024) return NYS_ERR_INVALID;
-  if (*F != nullptr && ((*F)->d != A->d || (*F)->prec != prec)) return NYS_ERR_INVALID;
+  if (*F != nullptr && ((*F)->d != A->d || (*F)->prec != prec || (*F)->sym != sym))
+    return NYS_ERR_INVALID;
+  if (sym && (D != nullptr || A->n != A->d || prec != NYS_F64)) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
   nys_factor f = *F;
   bool created = false;
@@ -703,6 +710,7 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
     f->d = A->d;
     f->device = ctx->device;
     f->prec = prec;
+    f->sym = sym;
     f->mantissa_bits = (prec == NYS_F64) ? 52 : 23;
     created = true;
   }
@@ -724,6 +732,11 @@ extern "C" {
 nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c,
                       const double* omega, int r, nys_dtype prec, nys_factor* F) {
   return sketch_round(ctx, A, D, c, omega, r, prec, F, -1.0, nullptr);
+}
+
+nys_status nys_sketch_sym(nys_ctx ctx, const nys_dense* K, double c, const double* omega, int r,
+                          nys_factor* F) {
+  return sketch_round(ctx, K, nullptr, c, omega, r, NYS_F64, F, -1.0, nullptr, true);
 }
 
 nys_status nys_sketch_adaptive(nys_ctx ctx, const nys_dense* A, const double* D, double c,

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_reduce_update(
     int64_t d, double rho_eff, const double* __restrict__ p, double* __restrict__ x,
     double* __restrict__ w, const double* __restrict__ rhs, double* __restrict__ wy, int k,
     const double* __restrict__ pppart, int npp, double* __restrict__ wwpart,
-    double* __restrict__ rrpart, PcgDev* __restrict__ st) {
+    double* __restrict__ rrpart, PcgDev* __restrict__ st, int Gq) {
   if (op == 0 && st->done) return;
   constexpr int RJ = kRedBlock;
   constexpr int S = 256 / RJ;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_reduce_update(
   double alpha = 0.0;
   if (op == 0) {
     // q = sum qpart, pp = sum pppart (fixed order, identical in every workgroup)
-    const double qs = block_sum_array(qpart, G, sh4);
+    const double qs = block_sum_array(qpart, Gq, sh4);
     __syncthreads();
     const double ps = block_sum_array(pppart, npp, sh4);
     const double pv = qs + rho_eff * ps;
@@ -342,10 +342,10 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 int64_t d, double rho_eff, const double* p, double* x, double* w,
                                 const double* rhs, double* wy, int k, const double* pppart,
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
-                                hipStream_t stream) {
+                                hipStream_t stream, int Gq) {
   hipLaunchKernelGGL(k_reduce_update, dim3(nblk(d, kRedBlock)), dim3(256), 0, stream, op, ypart,
                      G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp, wwpart, rrpart,
-                     st);
+                     st, Gq < 0 ? G : Gq);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 

@@ -32,7 +32,8 @@ EXPORTS = [
     "nys_factor_info", "nys_factor_get_U", "nys_factor_destroy", "nys_hessian_apply",
     "nys_precond_apply", "pcg_solve", "admm_step", "admm_solve", "nys_ws_param_count",
     "nys_ws_create", "nys_ws_get_params", "nys_ws_forward", "nys_ws_loss_grad",
-    "nys_ws_train_step", "nys_ws_destroy",
+    "nys_ws_train_step", "nys_ws_destroy", "nys_kernel_rbf", "nys_sketch_sym", "pcg_solve_sym",
+    "svm_solve",
 ]
 
 
@@ -71,6 +72,24 @@ class AdmmOpts(C.Structure):
                 ("factor", C.c_void_p), ("warm_start", C.c_void_p), ("ws_analytic", C.c_int),
                 ("ws_every_step", C.c_int), ("ws_features", C.c_void_p),
                 ("ws_target", C.c_void_p), ("true_res_every", C.c_int)]
+
+
+class SvmProblem(C.Structure):
+    _fields_ = [("H", Dense), ("b", C.c_void_p), ("C", C.c_double)]
+
+
+class SvmOpts(C.Structure):
+    _fields_ = [("rho", C.c_double), ("rank", C.c_int), ("omega", C.c_void_p), ("pcg", PcgOpts),
+                ("max_iter", C.c_int), ("gap_tol", C.c_double), ("gap_every", C.c_int),
+                ("true_res_every", C.c_int), ("factor", C.c_void_p)]
+
+
+class SvmInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("pcg_iters", C.c_long), ("pcg_max", C.c_int),
+                ("r_p", C.c_double), ("r_d", C.c_double), ("primal", C.c_double),
+                ("dual", C.c_double), ("gap", C.c_double), ("gap_rel", C.c_double),
+                ("bias", C.c_double), ("rank", C.c_int), ("converged", C.c_int),
+                ("status", C.c_int), ("true_res_max", C.c_double)]
 
 
 class AdmmState(C.Structure):
@@ -120,6 +139,10 @@ def lib():
         "nys_ws_loss_grad": (i32, [vp, vp, vp, vp, vp, i32, P(dbl), vp]),
         "nys_ws_train_step": (i32, [vp, vp, vp, vp, vp, i32, dbl, P(dbl)]),
         "nys_ws_destroy": (i32, [vp]),
+        "nys_kernel_rbf": (i32, [vp, vp, i64, i64, i64, vp, dbl, vp, i64]),
+        "nys_sketch_sym": (i32, [vp, P(Dense), dbl, vp, i32, P(vp)]),
+        "pcg_solve_sym": (i32, [vp, P(Dense), dbl, dbl, vp, vp, vp, P(PcgOpts), P(PcgInfo)]),
+        "svm_solve": (i32, [vp, P(SvmProblem), P(SvmOpts), P(AdmmState), P(SvmInfo)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -325,6 +348,75 @@ def pcg_solve(ctx: Context, A: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor,
     st = lib().pcg_solve(ctx.h, C.byref(dA), _ptr(D), float(c), float(rho),
                          None if F is None else F.h, _ptr(rhs), _ptr(x), C.byref(o), C.byref(info))
     _check(st, "pcg_solve", ok=tuple(allow))
+    return info
+
+
+def kernel_rbf(ctx: Context, X: torch.Tensor, gamma: float, b: Optional[torch.Tensor] = None,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """H = diag(b) K diag(b) (K without b) for the RBF kernel of the rows of
+    X (CUDA float32, n x p, unit column stride); returns the FP32 n x n matrix."""
+    if X.dim() != 2 or not X.is_cuda or X.dtype != torch.float32 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D CUDA float32 tensor with unit column stride")
+    n, p = X.shape
+    if b is not None:
+        _vec(b, n, "b")
+    H = torch.empty((n, n), dtype=torch.float32, device=X.device) if out is None else out
+    if H.shape != (n, n) or H.dtype != torch.float32 or H.stride(1) != 1:
+        raise ValueError("out must be a float32 n x n tensor with unit column stride")
+    ldx = X.stride(0) if n > 1 else p
+    _check(lib().nys_kernel_rbf(ctx.h, _ptr(X), n, p, max(ldx, p), _ptr(b), float(gamma), _ptr(H),
+                                H.stride(0) if n > 1 else n), "nys_kernel_rbf")
+    return H
+
+
+def nys_sketch_sym(ctx: Context, K: torch.Tensor, omega_rows: torch.Tensor, c: float = 0.0,
+                   factor: Optional["Factor"] = None) -> "Factor":
+    """Algorithm RandNysAppx of the explicit symmetric K + c I (FP64 core)."""
+    dK = dense(K)
+    r, d = omega_rows.shape
+    _vec(omega_rows.reshape(-1), r * d, "omega")
+    h = C.c_void_p(None if factor is None else factor.h.value)
+    _check(lib().nys_sketch_sym(ctx.h, C.byref(dK), float(c), _ptr(omega_rows), int(r), C.byref(h)),
+           "nys_sketch_sym")
+    if factor is not None:
+        factor.h = h
+        return factor
+    return Factor(h, d)
+
+
+def pcg_solve_sym(ctx: Context, K: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor, rho: float,
+                  F: Optional["Factor"] = None, c: float = 0.0, opts: Optional[PcgOpts] = None,
+                  allow=(NYS_OK,)) -> PcgInfo:
+    """Solve (K + (c + rho) I) x = rhs in place for an explicit symmetric K."""
+    dK = dense(K)
+    _vec(rhs, K.shape[0], "rhs")
+    _vec(x, K.shape[0], "x")
+    o = opts or pcg_opts()
+    info = PcgInfo()
+    st = lib().pcg_solve_sym(ctx.h, C.byref(dK), float(c), float(rho), None if F is None else F.h,
+                             _ptr(rhs), _ptr(x), C.byref(o), C.byref(info))
+    _check(st, "pcg_solve_sym", ok=tuple(allow))
+    return info
+
+
+def svm_opts(rho, rank, omega_rows: Optional[torch.Tensor] = None, pcg: Optional[PcgOpts] = None,
+             max_iter=100, gap_tol=0.0, gap_every=10, true_res_every=1,
+             factor: Optional["Factor"] = None) -> SvmOpts:
+    return SvmOpts(float(rho), int(rank), None if omega_rows is None else omega_rows.data_ptr(),
+                   pcg or pcg_opts(), int(max_iter), float(gap_tol), int(gap_every),
+                   int(true_res_every), None if factor is None else factor.h.value)
+
+
+def svm_solve(ctx: Context, H: torch.Tensor, b: torch.Tensor, Cbox: float, opts: SvmOpts,
+              state: "State", allow=(NYS_OK,)) -> SvmInfo:
+    """NysADMM on the kernel SVM dual with H = diag(b) K diag(b)."""
+    _vec(b, H.shape[0], "b")
+    P = SvmProblem(dense(H), b.data_ptr(), float(Cbox))
+    S = state.c()
+    info = SvmInfo()
+    _check(lib().svm_solve(ctx.h, C.byref(P), C.byref(opts), C.byref(S), C.byref(info)),
+           "svm_solve", ok=tuple(allow))
+    state.k = S.k
     return info
 
 

@@ -218,3 +218,14 @@ def warmstart_draws(a: torch.Tensor, draws: int, per_draw: int, seed: int,
             lr = math.log(rho_range[0]) + float(u[2 * j + 1]) * math.log(rho_range[1] / rho_range[0])
             out.append((b, gmax * math.exp(lg), math.exp(lr)))
     return out
+
+
+def svm_points(n: int, p: int, seed: int = 0, sep: float = 1.0, device="cpu"):
+    """Two-class points for the kernel SVM: labels b = +-1 with probability
+    1/2 each, features a_i = N(0, I_p) + sep * b_i * 1 / sqrt(p), stored FP32
+    (n x p); labels FP64.  The classes overlap (margin violations at every
+    C), so the dual has variables at 0, at C and in between."""
+    u = torch.rand(n, generator=_gen(seed, "unif", device), device=device, dtype=torch.float64)
+    b = torch.where(u < 0.5, -1.0, 1.0).to(torch.float64)
+    X = gaussian((n, p), seed, "G", device) + sep * b[:, None] / math.sqrt(p)
+    return X.to(torch.float32).contiguous(), b.contiguous()
