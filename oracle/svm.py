@@ -159,16 +159,17 @@ def nys_factor_of(H, omega_raw, c=0.0, mantissa_bits=52) -> NysFactor:
 
 
 def admm_svm(K, b, C, rho, omega_raw=None, iters=100, pcg_tol=1e-8, exact=False,
-             gap_tol=None, gap_every=10, pcg_max_iter=5000, mantissa_bits=52) -> SVMResult:
-    """Algorithm NysADMM on the kernel SVM dual (eq. 8)."""
+             gap_tol=None, gap_every=10, pcg_max_iter=5000, mantissa_bits=52,
+             factor=None) -> SVMResult:
+    """Algorithm NysADMM on the kernel SVM dual (eq. 8); `factor` (of H) may
+    be given instead of the Gaussian entries."""
     b = np.asarray(b, dtype=np.float64)
     H = svm_hessian(K, b)
     n = H.shape[0]
     x, z, u = np.zeros(n), np.zeros(n), np.zeros(n)
-    factor = None
     if exact:
         L = np.linalg.cholesky(H + rho * np.eye(n))
-    else:
+    elif factor is None:
         factor = nys_factor_of(H, omega_raw, 0.0, mantissa_bits)
     matvec = lambda p: H @ p + rho * p
     precond = None if exact else (lambda w: precond_inverse_apply(factor.U, factor.lam, rho, w))
