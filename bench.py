@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--true-res-every", type=int, default=10,
                     help="check the FP64 true residual of every k-th subproblem (and the last "
                          "of a run); the others stop PCG on its recursive residual")
-    ap.add_argument("--workload", choices=["lasso", "logistic", "path", "learned", "cg", "svm"],
+    ap.add_argument("--workload",
+                    choices=["lasso", "logistic", "path", "learned", "cg", "svm", "sparse"],
                     default="lasso",
                     help="lasso: 100000x4000 adaptive rank (default line); logistic: 200000x2000 "
                          "l1-logistic; path: 64 uneven lasso instances x 16 gammas, batched; "
@@ -387,6 +388,65 @@ def svm_cpu_baseline(H, b, omega, rho, iters_per_solve, cpu_iters):
     }
 
 
+def bench_sparse(args, N, synth, torch):
+    """Sparse lasso shaped like E2006.train (16087 x 150348, 0.8% nonzero):
+    bag-of-words rows with Zipf column popularity, unit-norm rows; gamma =
+    0.01 ||A^T b||_inf, rho = 1e-3, rank 50 (FP64 sketch), PCG tol 1e-6; a step
+    = factor built + `admm_iters` iterations from a cold start."""
+    n, d, dens, r, rho, its = 16087, 150348, 0.008, 50, 1e-3, args.admm_iters
+    rp, col, val, b, gamma, _ = synth.sparse_lasso(n, d, dens, seed=0, device="cuda")
+    torch.cuda.synchronize()
+    ctx = N.Context()
+    S = N.SparseMatrix(ctx, rp, col, val, (n, d))
+    omega = synth.omega_raw(d, r, seed=1, device="cuda").contiguous()
+    prob = N.problem(S, b.contiguous(), gamma)
+
+    def steps(k, profile=False):
+        tot, pcg, bad, trm, sk, eta = 0, 0, 0, -1.0, 0.0, None
+        if profile:
+            ctx.profile_start()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(k):
+            ts = time.perf_counter()
+            F = N.nys_sketch(ctx, S, omega, prec=N.NYS_F64)
+            torch.cuda.synchronize()
+            sk += time.perf_counter() - ts
+            o = N.admm_opts(rho, r, omega, sketch_prec=N.NYS_F64, max_iter=its,
+                            pcg=N.pcg_opts(tol=1e-6, max_iter=2000), factor=F,
+                            true_res_every=args.true_res_every)
+            st = N.State(d, "cuda")
+            info = N.admm_solve(ctx, [prob], [o], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
+            tot += info.iters
+            pcg += info.pcg_iters
+            bad += info.status != N.NYS_OK
+            trm = max(trm, info.true_res_max)
+            eta = info.eta
+            F.close()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        return wall, tot, pcg, bad, trm, sk, eta, (ctx.profile_stop() if profile else None)
+
+    steps(args.warmup)
+    wall, tot, pcg, bad, trm, sk, eta, prof = steps(args.steps, profile=True)
+    nnz = S.nnz
+    out = base_record(tot / wall, args.steps, args.warmup, wall, "f32", {
+        "workload": f"sparse-lasso-E2006-shape-{n}x{d}-nnz{nnz}-rank{r}-{its}iters",
+        "n": n, "d": d, "nnz": nnz, "rho": rho, "gamma": gamma, "rank": r, "pcg_tol": 1e-6,
+        "admm_iters_per_step": its, "true_res_every": args.true_res_every})
+    # CSR pass: rowptr, colidx, val, p, s; CSC pass: colptr, rows, values, s, y
+    alg = 16.0 * nnz + 4.0 * (n + 1) + 4.0 * (d + 1) + 16.0 * n + 16.0 * d
+    out["roofline"] = roofline(prof, alg, n, d)
+    out["roofline"]["kernel"] = "k_csr_pass + k_csc_pass (sparse A^T D A p, FP32 values, FP64 sums)"
+    out["pcg_iters_mean"] = round(pcg / max(tot, 1), 3)
+    out["unconverged_solves"] = bad
+    out["true_rel_res_max"] = trm
+    out["sketch_ms"] = round(1e3 * sk / args.steps, 2)
+    out["kkt_eta_after_step"] = eta
+    S.close()
+    return out
+
+
 def bench_path(args, N, synth, torch):
     """Regularisation path: `instances` uneven lasso problems (n in [5000,
     50000], d in [500, 3000], sigma_j = j^-0.7, rank 100, rho 1e-3), each
@@ -523,7 +583,8 @@ def main():
         from paper_2202_11599_amd import synth
         torch.cuda.set_device(0)
         fn = {"logistic": bench_logistic, "path": bench_path,
-              "learned": bench_learned, "cg": bench_cg, "svm": bench_svm}[args.workload]
+              "learned": bench_learned, "cg": bench_cg, "svm": bench_svm,
+              "sparse": bench_sparse}[args.workload]
         print(json.dumps(fn(args, N, synth, torch)), flush=True)
         return
     from paper_2202_11599_amd import nysadmm as N

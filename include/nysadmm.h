@@ -60,18 +60,23 @@ typedef enum {
   NYS_ERR_NOT_CONVERGED = 8  /* the FP64 eigensolver of the factor core did not converge */
 } nys_status;
 
-typedef enum { NYS_F32 = 0, NYS_F64 = 1, NYS_BF16 = 2 } nys_dtype;
+typedef enum { NYS_F32 = 0, NYS_F64 = 1, NYS_BF16 = 2, NYS_CSR = 3 } nys_dtype;
 typedef enum { NYS_LOSS_LS = 0, NYS_LOSS_LOGISTIC = 1 } nys_loss;
 
 typedef struct nys_ctx_s* nys_ctx;
 typedef struct nys_factor_s* nys_factor;
 typedef struct nys_ws_model_s* nys_ws_model;
+typedef struct nys_sparse_s* nys_sparse;
 
-/* Dense row-major matrix: element (i, j) at data + i*ld + j. */
+/* Dense row-major matrix: element (i, j) at data + i*ld + j.
+ * dtype NYS_CSR describes a sparse matrix instead: data is a nys_sparse
+ * handle from nys_sparse_create, n and d its shape, ld = d; every entry point
+ * that takes an A accepts it (the sketch then runs in FP64, sketch_prec
+ * NYS_F64; the batched path takes dense instances only). */
 typedef struct {
   int64_t n, d, ld;
-  nys_dtype dtype;   /* NYS_F32 or NYS_F64 */
-  const void* data;  /* device */
+  nys_dtype dtype;   /* NYS_F32, NYS_F64, or NYS_CSR */
+  const void* data;  /* device (a nys_sparse handle for NYS_CSR) */
 } nys_dense;
 
 /* ----------------------------------------------------------------- context */
@@ -287,6 +292,19 @@ nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, 
  * one after another.  Arrays have length count. */
 nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_admm_opts* O,
                       nys_admm_state* S, nys_admm_info* I);
+
+/* ------------------------------------------------------------ sparse A */
+
+/* A sparse matrix for the matvec pair A^T (D (A p)) (E2006/sector-like data,
+ * Section 5).  rowptr (n + 1), colidx (nnz) and val (nnz, FP32) are device
+ * arrays in CSR order (column indices within a row in any order, no
+ * duplicates); they stay owned by the caller and must outlive the handle.
+ * The library builds a column-major copy (CSC, rows ascending within a
+ * column) for the A^T pass; every product is an FP64 product of the stored
+ * FP32 value, every sum FP64 in a fixed order.  nnz < 2^31. */
+nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, const int* rowptr,
+                             const int* colidx, const float* val, nys_sparse* out);
+nys_status nys_sparse_destroy(nys_sparse S);
 
 /* ------------------------------------------------------ kernel SVM (eq. 8) */
 

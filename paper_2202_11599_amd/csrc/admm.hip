@@ -168,13 +168,14 @@ nys_status gram_pass(nys_ctx ctx, const nys_dense& A, int mode, const double* p,
   PcgWs ws;
   NYS_TRY(pcg_workspace(ctx, pl, A.d, 1, &ws));
   NYS_TRY(ctx_gram(ctx, A, pl, mode, p, aux, auxout, ws.ypart, ws.qpart, nullptr));
-  NYS_TRY(launch_reduce_update(3, ws.ypart, pl.grid, pl.ldy, ws.qpart, A.d, 0.0, nullptr, nullptr,
+  // y and q partial counts come from the plan (one y partial for sparse A)
+  NYS_TRY(launch_reduce_update(3, ws.ypart, pl.ny(), pl.ldy, ws.qpart, A.d, 0.0, nullptr, nullptr,
                                out, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, ws.st,
-                               ctx->stream));
+                               ctx->stream, pl.nq()));
   if (want_q) {
     // q partials are summed together with the KKT scalars by the caller
     hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(256), 0, ctx->stream, w.part, 0, ws.qpart,
-                       pl.grid, w.scal);
+                       pl.nq(), w.scal);
   }
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
@@ -392,7 +393,8 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
   ctx->hx_key = AtbKey{};    // and x since an earlier solve
   bool batched = count > 1;
   for (int q = 0; q < count; ++q) {
-    if (P[q].loss != NYS_LOSS_LS || O[q].tol_schedule || O[q].kkt_tol > 0.0 || O[q].rank == 0)
+    if (P[q].loss != NYS_LOSS_LS || O[q].tol_schedule || O[q].kkt_tol > 0.0 || O[q].rank == 0 ||
+        P[q].A.dtype == NYS_CSR)
       batched = false;
     if (O[q].warm_start != nullptr || O[q].ws_analytic || O[q].ws_features != nullptr ||
         O[q].ws_target != nullptr)

@@ -218,6 +218,10 @@ size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 nys_status validate_dense(const nys_dense* A) {
   if (A == nullptr || A->data == nullptr) return NYS_ERR_INVALID;
   if (A->n < 0 || A->d < 1 || A->ld < A->d) return NYS_ERR_INVALID;
+  if (A->dtype == NYS_CSR) {
+    const nys_sparse_s* S = static_cast<const nys_sparse_s*>(A->data);
+    return (S->n == A->n && S->d == A->d) ? NYS_OK : NYS_ERR_INVALID;
+  }
   if (A->dtype != NYS_F32 && A->dtype != NYS_F64) return NYS_ERR_INVALID;
   return NYS_OK;
 }
@@ -264,6 +268,20 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
                     const double* p, const double* aux, double* auxout, double* ypart,
                     double* qpart, const int* done) {
   if (plan.symv && (mode != kModeHess || aux != nullptr)) return NYS_ERR_INVALID;
+  if (plan.sparse != nullptr) {
+    const bool ev = ctx->prof_on;
+    if (ev && ctx->prof_used + 2 > ctx->prof_ev.size())
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        NYS_TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+        ctx->prof_ev.push_back(e);
+      }
+    NYS_TRY(launch_sparse_pair(plan.sparse, plan, mode, p, aux, auxout, ypart, qpart, done,
+                               ctx->stream, ev ? ctx->prof_ev[ctx->prof_used] : nullptr,
+                               ev ? ctx->prof_ev[ctx->prof_used + 1] : nullptr));
+    if (ev) ctx->prof_used += 2;
+    return NYS_OK;
+  }
   if (!ctx->prof_on || plan.grid == 0 || A.n == 0)
     return plan.symv ? launch_symv(A, plan, p, ypart, qpart, done, ctx->stream)
                      : launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream);
@@ -287,6 +305,10 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
 }
 
 nys_status ctx_gram_plan(nys_ctx ctx, const nys_dense& A, GramPlan* out) {
+  if (const nys_sparse_s* S = as_sparse(A)) {
+    *out = make_sparse_plan(S);
+    return NYS_OK;
+  }
   const char* forced = getenv("NYSADMM_GRAM_PLAN");
   const char* tune = getenv("NYSADMM_TUNE");
   if (forced != nullptr || (tune != nullptr && tune[0] == '0') || A.n < 4096) {

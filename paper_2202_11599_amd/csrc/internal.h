@@ -78,7 +78,9 @@ struct GramPlan {
   bool symv = false;
   int slices = 1;
   int slice_cols = 0;
-  int ny() const { return symv ? slices : grid; }
+  // sparse A (CSR + CSC passes): y is one n-vector, q one partial per row workgroup
+  const nys_sparse_s* sparse = nullptr;
+  int ny() const { return sparse ? 1 : (symv ? slices : grid); }
   int nq() const { return symv ? slices * grid : grid; }
 };
 
@@ -210,6 +212,19 @@ struct nys_ctx_s {
   long prof_skipped = 0;         // timed launches that returned at once (PCG already done)
 };
 
+struct nys_sparse_s {
+  int64_t n = 0, d = 0, nnz = 0;
+  int device = 0;
+  const int* rowptr = nullptr;   // caller's CSR arrays
+  const int* colidx = nullptr;
+  const float* val = nullptr;
+  nys::DevBuf csc;               // colptr (d + 1 ints), rows (nnz ints), values (nnz floats)
+  int* colptr() const { return csc.as<int>(); }
+  int* rows() const { return csc.as<int>() + (d + 1); }
+  float* cvals() const { return reinterpret_cast<float*>(csc.as<int>() + (d + 1) + nnz); }
+  nys::DevBuf s;                 // the n-vector s = f(A p) between the two passes
+};
+
 struct nys_factor_s {
   int64_t d = 0;
   int r = 0;
@@ -249,6 +264,20 @@ GramPlan make_symv_plan(const nys_dense& A, int num_cu);
 nys_status launch_symv(const nys_dense& A, const GramPlan& plan, const double* p, double* ypart,
                        double* qpart, const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
+
+// ---- sparse.hip
+GramPlan make_sparse_plan(const nys_sparse_s* S);
+nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& plan, int mode,
+                              const double* p, const double* aux, double* auxout, double* ypart,
+                              double* qpart, const int* done, hipStream_t st,
+                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Y[:, 0:m] (column-major, ld d) = A^T (D (A Om)) + c Om for sparse A, FP64 sums;
+// Om column-major d x m.  ws holds (n + 2 d) m doubles.
+nys_status sparse_sketch(const nys_sparse_s* S, const double* D, double c, const double* Om, int m,
+                         double* Y, double* ws, hipStream_t st);
+inline const nys_sparse_s* as_sparse(const nys_dense& A) {
+  return A.dtype == NYS_CSR ? static_cast<const nys_sparse_s*>(A.data) : nullptr;
+}
 
 // ---- vec.hip
 constexpr int kVecBlock = 32;    // entries of y per workgroup of the preconditioner update

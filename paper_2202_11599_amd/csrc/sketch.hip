@@ -590,7 +590,11 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
   NYS_TRY(orthonormalize(ctx, Om, d, m, w));
   double* Y = F->Y.as<double>();
   const bool a32 = (A.dtype == NYS_F32);
-  if (F->sym) {
+  if (const nys_sparse_s* SP = as_sparse(A)) {
+    // sparse A: Y = A^T (D (A Omega)) + c Omega by two sparse-times-dense passes
+    NYS_TRY(ctx->gemm_ws.reserve(sizeof(double) * (size_t)(n + 2 * d) * m + 256));
+    NYS_TRY(sparse_sketch(SP, D, c, Om, m, Y + d * r0, ctx->gemm_ws.as<double>(), st));
+  } else if (F->sym) {
     // explicit symmetric H = A + c I (kernel SVM): Y = A Omega + c Omega, FP64 sums
     NYS_TRY_HIP(hipMemcpyAsync(Y + d * r0, Om, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
     NYS_TRY(gemm64(st, (int)n, m, (int)d, A.data, a32, A.ld, 1, Om, false, 1, d, Y + d * r0, 1, d,
@@ -700,7 +704,9 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
   if (r_old + r >= A->d || r_old + r > 1024) return NYS_ERR_INVALID;
   if (*F != nullptr && ((*F)->d != A->d || (*F)->prec != prec || (*F)->sym != sym))
     return NYS_ERR_INVALID;
-  if (sym && (D != nullptr || A->n != A->d || prec != NYS_F64)) return NYS_ERR_INVALID;
+  if (sym && (D != nullptr || A->n != A->d || prec != NYS_F64 || A->dtype == NYS_CSR))
+    return NYS_ERR_INVALID;
+  if (A->dtype == NYS_CSR && prec != NYS_F64) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
   nys_factor f = *F;
   bool created = false;

@@ -1,0 +1,389 @@
+// Sparse A (CSR) for the NysADMM hot path: the matvec pair A^T (D (A p)) as
+// two streaming passes, a row pass over the CSR arrays (t = A p and the mode
+// epilogue s = f(t)) and a column pass over a CSC copy (y = A^T s), and the
+// sketch A^T (D (A Omega)) as two sparse-times-dense products.  One wavefront
+// per row (column); every sum is FP64 in a fixed order, so results are
+// bitwise reproducible.  The CSC copy is built once by a deterministic
+// counting transpose: rows are split into blocks, each block's column counts
+// are prefix-summed across blocks, and each block places its entries row by
+// row (within a row the columns are distinct, so no two lanes share a slot).
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "internal.h"
+
+#include "gram_device.h"
+
+namespace nys {
+namespace {
+
+using gram::sigm;
+using gram::wave_sum;
+
+constexpr int kTBlocks = 64;   // row blocks of the transpose
+
+// *bad = 1 unless rowptr is non-decreasing (its ends were checked on the host)
+__global__ __launch_bounds__(256) void k_tr_check_rows(const int* __restrict__ rowptr, int64_t n,
+                                                       int* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n && rowptr[i + 1] < rowptr[i]) *bad = 1;
+}
+
+// cnt[b * d + j] = entries of column j in row block b; *bad = 1 on a column
+// index outside [0, d) (not counted)
+__global__ __launch_bounds__(256) void k_tr_count(const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col, int64_t n,
+                                                  int64_t d, int64_t rows_per_blk,
+                                                  int* __restrict__ cnt, int* __restrict__ bad) {
+  const int b = blockIdx.y;
+  const int64_t r0 = (int64_t)b * rows_per_blk;
+  const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_blk);
+  if (r0 >= r1) return;
+  const int64_t k0 = rowptr[r0], k1 = rowptr[r1];
+  for (int64_t k = k0 + (int64_t)blockIdx.x * 256 + threadIdx.x; k < k1;
+       k += (int64_t)gridDim.x * 256) {
+    const int j = col[k];
+    if (j < 0 || j >= d) {
+      *bad = 1;
+      continue;
+    }
+    atomicAdd(&cnt[(int64_t)b * d + j], 1);   // integer counts: order-free
+  }
+}
+
+// colptr[j] (exclusive) and, in place, cnt[b * d + j] <- start of block b's
+// entries of column j.  One workgroup; threads own contiguous column ranges.
+__global__ __launch_bounds__(1024) void k_tr_scan(int* __restrict__ cnt, int64_t d, int nblk,
+                                                  int* __restrict__ colptr) {
+  __shared__ long long part[1024];
+  const int64_t per = (d + 1023) / 1024;
+  const int64_t j0 = std::min<int64_t>(d, threadIdx.x * per);
+  const int64_t j1 = std::min<int64_t>(d, j0 + per);
+  long long s = 0;
+  for (int64_t j = j0; j < j1; ++j)
+    for (int b = 0; b < nblk; ++b) s += cnt[(int64_t)b * d + j];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const long long v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  long long acc = part[threadIdx.x];
+  for (int64_t j = j0; j < j1; ++j) {
+    colptr[j] = (int)acc;
+    for (int b = 0; b < nblk; ++b) {
+      const int c = cnt[(int64_t)b * d + j];
+      cnt[(int64_t)b * d + j] = (int)acc;
+      acc += c;
+    }
+  }
+  if (j1 == d && j0 < j1) colptr[d] = (int)acc;
+  if (d == 0 && threadIdx.x == 0) colptr[0] = 0;
+}
+
+// Block b places its rows in order: each lane takes distinct columns of one
+// row, so the slot counters cnt[b * d + col] are bumped without conflicts.
+__global__ __launch_bounds__(64) void k_tr_fill(const int* __restrict__ rowptr,
+                                                const int* __restrict__ col,
+                                                const float* __restrict__ val, int64_t n,
+                                                int64_t d, int64_t rows_per_blk,
+                                                int* __restrict__ cnt, int* __restrict__ rows,
+                                                float* __restrict__ cval) {
+  const int b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * rows_per_blk;
+  const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_blk);
+  int* c = cnt + (int64_t)b * d;
+  for (int64_t i = r0; i < r1; ++i) {
+    for (int64_t k = rowptr[i] + threadIdx.x; k < rowptr[i + 1]; k += 64) {
+      const int j = col[k];
+      const int pos = c[j];
+      c[j] = pos + 1;
+      rows[pos] = (int)i;
+      cval[pos] = val[k];
+    }
+    __syncthreads();   // one wavefront: orders the counter updates row by row
+  }
+}
+
+// Row pass: t_i = A_i p (one wavefront per row), s_i = f_mode(t_i) into s,
+// per-workgroup sum of the mode's q term into qpart.
+__global__ __launch_bounds__(256) void k_csr_pass(const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col,
+                                                  const float* __restrict__ val, int64_t n,
+                                                  int mode, const double* __restrict__ p,
+                                                  const double* __restrict__ aux,
+                                                  double* __restrict__ auxout,
+                                                  double* __restrict__ s,
+                                                  double* __restrict__ qpart,
+                                                  const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  __shared__ double qs[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  double q = 0.0;
+  if (i < n) {
+    double acc = 0.0;
+    if (mode != kModeTOnly)
+      for (int64_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += 64)
+        acc = fma((double)val[k], p[col[k]], acc);
+    const double t = wave_sum(acc);
+    if (lane == 0) {
+      double si = 0.0;
+      if (mode == kModeHess) {
+        si = (aux != nullptr ? aux[i] : 1.0) * t;
+        q = si * t;
+      } else if (mode == kModeLsGrad) {
+        si = t - aux[i];
+        q = si * si;
+      } else if (mode == kModeLogit || mode == kModeLogGrad) {
+        const double bi = aux[i];
+        const double sg = sigm(t);
+        q = log1p(exp(-fabs(t))) + fmax(t, 0.0) - bi * t;
+        if (mode == kModeLogit) {
+          const double w = sg * sigm(-t);
+          si = w * t + bi - sg;
+          if (auxout != nullptr) auxout[i] = w;
+        } else {
+          si = sg - bi;
+        }
+      } else {   // kModeTOnly
+        si = aux[i];
+      }
+      s[i] = si;
+    }
+  }
+  if (lane == 0) qs[wv] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) qpart[blockIdx.x] = ((qs[0] + qs[1]) + qs[2]) + qs[3];
+}
+
+// Column pass: y_j = sum over column j of A_ij s_i (one wavefront per column).
+__global__ __launch_bounds__(256) void k_csc_pass(const int* __restrict__ colptr,
+                                                  const int* __restrict__ rows,
+                                                  const float* __restrict__ cval, int64_t d,
+                                                  const double* __restrict__ s,
+                                                  double* __restrict__ y,
+                                                  const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= d) return;
+  double acc = 0.0;
+  for (int64_t k = colptr[j] + lane; k < colptr[j + 1]; k += 64)
+    acc = fma((double)cval[k], s[rows[k]], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) y[j] = acc;
+}
+
+// Omega (column-major d x m) -> row-major d x m
+__global__ void k_cm_to_rm(const double* __restrict__ cm, int64_t d, int m,
+                           double* __restrict__ rm) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= d * m) return;
+  const int64_t j = e / m, c = e % m;
+  rm[e] = cm[c * d + j];
+}
+
+// Y column-major (ld d) <- Yrm (row-major d x m) + c Om (column-major)
+__global__ void k_rm_to_cm(const double* __restrict__ rm, int64_t d, int m, double c,
+                           const double* __restrict__ Om, double* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= d * m) return;
+  const int64_t col = e / d, j = e % d;
+  Y[e] = rm[j * m + col] + c * Om[e];
+}
+
+// T = D (A Om) row by row (row-major n x m): one wavefront per row, each lane
+// owning columns lane, lane + 64, ... of a 256-column chunk (blockIdx.y).
+__global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rowptr,
+                                                  const int* __restrict__ col,
+                                                  const float* __restrict__ val, int64_t n,
+                                                  int m, const double* __restrict__ B,
+                                                  const double* __restrict__ D,
+                                                  double* __restrict__ T) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int c0 = blockIdx.y * 256 + lane;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    const double v = val[k];
+    const double* b = B + (int64_t)col[k] * m;
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      if (c0 + 64 * h < m) acc[h] = fma(v, b[c0 + 64 * h], acc[h]);
+  }
+  const double di = D != nullptr ? D[i] : 1.0;
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+    if (c0 + 64 * h < m) T[i * m + c0 + 64 * h] = di * acc[h];
+}
+
+// Yrm = A^T T column by column (row-major d x m), the same layout of lanes
+__global__ __launch_bounds__(256) void k_csc_spmm(const int* __restrict__ colptr,
+                                                  const int* __restrict__ rows,
+                                                  const float* __restrict__ cval, int64_t d,
+                                                  int m, const double* __restrict__ T,
+                                                  double* __restrict__ Y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= d) return;
+  const int c0 = blockIdx.y * 256 + lane;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = colptr[j]; k < colptr[j + 1]; ++k) {
+    const double v = cval[k];
+    const double* t = T + (int64_t)rows[k] * m;
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      if (c0 + 64 * h < m) acc[h] = fma(v, t[c0 + 64 * h], acc[h]);
+  }
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+    if (c0 + 64 * h < m) Y[j * m + c0 + 64 * h] = acc[h];
+}
+
+inline unsigned nb256(int64_t x) { return (unsigned)((x + 255) / 256); }
+
+}  // namespace
+
+GramPlan make_sparse_plan(const nys_sparse_s* S) {
+  GramPlan pl;
+  pl.sparse = S;
+  pl.grid = (int)std::max<int64_t>(1, (S->n + 3) / 4);   // row-pass workgroups (q partials)
+  pl.ldy = (int)((S->d + 63) / 64 * 64);
+  pl.rows_per_wg = 4;
+  return pl;
+}
+
+nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& pl, int mode,
+                              const double* p, const double* aux, double* auxout, double* ypart,
+                              double* qpart, const int* done, hipStream_t st, hipEvent_t ev0,
+                              hipEvent_t ev1) {
+  if (S == nullptr || pl.sparse != S) return NYS_ERR_INVALID;
+  double* s = S->s.as<double>();
+  if (ev0 != nullptr) NYS_TRY_HIP(hipEventRecord(ev0, st));
+  if (S->n > 0)
+    hipLaunchKernelGGL(k_csr_pass, dim3(pl.grid), dim3(256), 0, st, S->rowptr, S->colidx, S->val,
+                       S->n, mode, p, aux, auxout, s, qpart, done);
+  else
+    NYS_TRY_HIP(hipMemsetAsync(qpart, 0, sizeof(double), st));
+  hipLaunchKernelGGL(k_csc_pass, dim3((unsigned)((S->d + 3) / 4)), dim3(256), 0, st, S->colptr(),
+                     S->rows(), S->cvals(), S->d, s, ypart, done);
+  if (ev1 != nullptr) NYS_TRY_HIP(hipEventRecord(ev1, st));
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status sparse_sketch(const nys_sparse_s* S, const double* D, double c, const double* Om, int m,
+                         double* Y, double* ws, hipStream_t st) {
+  const int64_t n = S->n, d = S->d;
+  double* Orm = ws;                  // d x m
+  double* T = ws + d * m;            // n x m
+  double* Yrm = T + n * m;           // d x m
+  const unsigned cchunks = (unsigned)((m + 255) / 256);
+  hipLaunchKernelGGL(k_cm_to_rm, dim3(nb256(d * m)), dim3(256), 0, st, Om, d, m, Orm);
+  if (n > 0)
+    hipLaunchKernelGGL(k_csr_spmm, dim3((unsigned)((n + 3) / 4), cchunks), dim3(256), 0, st,
+                       S->rowptr, S->colidx, S->val, n, m, Orm, D, T);
+  hipLaunchKernelGGL(k_csc_spmm, dim3((unsigned)((d + 3) / 4), cchunks), dim3(256), 0, st,
+                     S->colptr(), S->rows(), S->cvals(), d, m, T, Yrm);
+  hipLaunchKernelGGL(k_rm_to_cm, dim3(nb256(d * m)), dim3(256), 0, st, Yrm, d, m, c, Om, Y);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+}  // namespace nys
+
+using namespace nys;
+
+extern "C" {
+
+nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, const int* rowptr,
+                             const int* colidx, const float* val, nys_sparse* out) {
+  if (ctx == nullptr || out == nullptr || n < 0 || d < 1 || nnz < 0 ||
+      nnz > ((int64_t)1 << 31) - 1 || n > ((int64_t)1 << 31) - 2 ||
+      d > ((int64_t)1 << 31) - 2 || rowptr == nullptr ||
+      (nnz > 0 && (colidx == nullptr || val == nullptr)))
+    return NYS_ERR_INVALID;
+  *out = nullptr;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  // rowptr must describe nnz entries: check its ends on the host
+  int ends[2] = {0, 0};
+  NYS_TRY_HIP(hipMemcpyAsync(&ends[0], rowptr, sizeof(int), hipMemcpyDeviceToHost, st));
+  NYS_TRY_HIP(hipMemcpyAsync(&ends[1], rowptr + n, sizeof(int), hipMemcpyDeviceToHost, st));
+  NYS_TRY_HIP(hipStreamSynchronize(st));
+  if (ends[0] != 0 || ends[1] != nnz) return NYS_ERR_INVALID;
+  nys_sparse_s* S = new (std::nothrow) nys_sparse_s();
+  if (S == nullptr) return NYS_ERR_NOMEM;
+  S->n = n;
+  S->d = d;
+  S->nnz = nnz;
+  S->device = ctx->device;
+  S->rowptr = rowptr;
+  S->colidx = colidx;
+  S->val = val;
+  nys_status s = S->csc.reserve(sizeof(int) * (size_t)(d + 1 + 2 * nnz) + 256);
+  if (s == NYS_OK) s = S->s.reserve(sizeof(double) * (size_t)std::max<int64_t>(n, 1));
+  nys::DevBuf cnt;
+  const int64_t rpb = std::max<int64_t>(1, (n + kTBlocks - 1) / kTBlocks);
+  const int nblk = (int)std::max<int64_t>(1, (n + rpb - 1) / rpb);
+  // counts of every row block, then one int flagging malformed input
+  if (s == NYS_OK) s = cnt.reserve(sizeof(int) * ((size_t)nblk * d + 1));
+  int* bad = cnt.ptr ? cnt.as<int>() + (size_t)nblk * d : nullptr;
+  if (s == NYS_OK &&
+      hipMemsetAsync(cnt.ptr, 0, sizeof(int) * ((size_t)nblk * d + 1), st) != hipSuccess)
+    s = NYS_ERR_HIP;
+  // validate before any entry is read through rowptr: rows non-decreasing
+  // (with the ends checked above, every rowptr value lies in [0, nnz]); then
+  // the counts, which flag column indices outside [0, d)
+  auto check = [&]() {
+    int hbad = 0;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return NYS_ERR_HIP;
+    return hbad ? NYS_ERR_INVALID : NYS_OK;
+  };
+  if (s == NYS_OK && n > 0) {
+    hipLaunchKernelGGL(k_tr_check_rows, dim3(nb256(n)), dim3(256), 0, st, rowptr, n, bad);
+    s = check();
+  }
+  if (s == NYS_OK && n > 0 && nnz > 0) {
+    hipLaunchKernelGGL(k_tr_count, dim3(64, nblk), dim3(256), 0, st, rowptr, colidx, n, d, rpb,
+                       cnt.as<int>(), bad);
+    s = check();
+  }
+  if (s == NYS_OK) {
+    hipLaunchKernelGGL(k_tr_scan, dim3(1), dim3(1024), 0, st, cnt.as<int>(), d, nblk,
+                       S->colptr());
+    if (n > 0 && nnz > 0)
+      hipLaunchKernelGGL(k_tr_fill, dim3(nblk), dim3(64), 0, st, rowptr, colidx, val, n, d, rpb,
+                         cnt.as<int>(), S->rows(), S->cvals());
+    if (hipGetLastError() != hipSuccess) s = NYS_ERR_HIP;
+  }
+  cnt.release();
+  if (s != NYS_OK) {
+    S->csc.release();
+    S->s.release();
+    delete S;
+    return s;
+  }
+  *out = S;
+  return NYS_OK;
+}
+
+nys_status nys_sparse_destroy(nys_sparse S) {
+  if (S == nullptr) return NYS_ERR_INVALID;
+  (void)hipSetDevice(S->device);
+  S->csc.release();
+  S->s.release();
+  delete S;
+  return NYS_OK;
+}
+
+}  // extern "C"

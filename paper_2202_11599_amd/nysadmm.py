@@ -23,7 +23,7 @@ _lib = None
 
 NYS_OK, NYS_ERR_INVALID, NYS_ERR_HIP, NYS_ERR_NOT_SPD, NYS_ERR_BREAKDOWN, NYS_ERR_MAXITER, \
     NYS_ERR_NONFINITE, NYS_ERR_NOMEM, NYS_ERR_NOT_CONVERGED = range(9)
-NYS_F32, NYS_F64, NYS_BF16 = 0, 1, 2
+NYS_F32, NYS_F64, NYS_BF16, NYS_CSR = 0, 1, 2, 3
 NYS_LOSS_LS, NYS_LOSS_LOGISTIC = 0, 1
 
 EXPORTS = [
@@ -33,7 +33,7 @@ EXPORTS = [
     "nys_precond_apply", "pcg_solve", "admm_step", "admm_solve", "nys_ws_param_count",
     "nys_ws_create", "nys_ws_get_params", "nys_ws_forward", "nys_ws_loss_grad",
     "nys_ws_train_step", "nys_ws_destroy", "nys_kernel_rbf", "nys_sketch_sym", "pcg_solve_sym",
-    "svm_solve",
+    "svm_solve", "nys_sparse_create", "nys_sparse_destroy",
 ]
 
 
@@ -143,6 +143,8 @@ def lib():
         "nys_sketch_sym": (i32, [vp, P(Dense), dbl, vp, i32, P(vp)]),
         "pcg_solve_sym": (i32, [vp, P(Dense), dbl, dbl, vp, vp, vp, P(PcgOpts), P(PcgInfo)]),
         "svm_solve": (i32, [vp, P(SvmProblem), P(SvmOpts), P(AdmmState), P(SvmInfo)]),
+        "nys_sparse_create": (i32, [vp, i64, i64, i64, vp, vp, vp, P(vp)]),
+        "nys_sparse_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -174,8 +176,11 @@ def _vec(t: torch.Tensor, n: int, name: str):
     return t
 
 
-def dense(A: torch.Tensor) -> Dense:
-    """Describe a row-major (n, d) tensor (contiguous rows, any row stride)."""
+def dense(A) -> Dense:
+    """Describe a row-major (n, d) tensor (contiguous rows, any row stride), or
+    a SparseMatrix."""
+    if isinstance(A, SparseMatrix):
+        return A.descriptor()
     if A.dim() != 2 or not A.is_cuda or A.stride(1) != 1:
         raise ValueError("A must be a 2-D CUDA tensor with unit column stride")
     dt = {torch.float32: NYS_F32, torch.float64: NYS_F64}.get(A.dtype)
@@ -221,6 +226,51 @@ class Context:
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value is not None:
             lib().nys_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SparseMatrix:
+    """A CSR matrix on the device (int32 rowptr and column indices, float32
+    values, CUDA tensors kept alive here) with the library's column-major copy
+    for the A^T pass.  Accepted wherever an A is."""
+
+    def __init__(self, ctx: "Context", rowptr: torch.Tensor, colidx: torch.Tensor, val: torch.Tensor,
+                 shape):
+        n, d = int(shape[0]), int(shape[1])
+        for t, dt, name in ((rowptr, torch.int32, "rowptr"), (colidx, torch.int32, "colidx"),
+                            (val, torch.float32, "val")):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous CUDA {dt} tensor")
+        if rowptr.numel() != n + 1 or colidx.numel() != val.numel():
+            raise ValueError("rowptr needs n + 1 entries and colidx/val one per nonzero")
+        self._keep = (rowptr, colidx, val)
+        self.shape = (n, d)
+        self.nnz = int(val.numel())
+        h = C.c_void_p()
+        _check(lib().nys_sparse_create(ctx.h, n, d, self.nnz, _ptr(rowptr), _ptr(colidx), _ptr(val),
+                                       C.byref(h)), "nys_sparse_create")
+        self.h = h
+
+    @staticmethod
+    def from_torch(ctx: "Context", M: torch.Tensor) -> "SparseMatrix":
+        """From a torch sparse CSR tensor (any device/dtype; moved to CUDA FP32)."""
+        M = M.to_sparse_csr()
+        return SparseMatrix(ctx, M.crow_indices().to(torch.int32).cuda().contiguous(),
+                            M.col_indices().to(torch.int32).cuda().contiguous(),
+                            M.values().to(torch.float32).cuda().contiguous(), M.shape)
+
+    def descriptor(self) -> Dense:
+        return Dense(self.shape[0], self.shape[1], self.shape[1], NYS_CSR, self.h.value)
+
+    def close(self):
+        if self.h:
+            lib().nys_sparse_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):

@@ -229,3 +229,55 @@ def svm_points(n: int, p: int, seed: int = 0, sep: float = 1.0, device="cpu"):
     b = torch.where(u < 0.5, -1.0, 1.0).to(torch.float64)
     X = gaussian((n, p), seed, "G", device) + sep * b[:, None] / math.sqrt(p)
     return X.to(torch.float32).contiguous(), b.contiguous()
+
+
+def sparse_text_like(n: int, d: int, density: float, seed: int = 0, device="cpu",
+                     zipf: float = 1.1):
+    """A sparse n x d matrix shaped like bag-of-words data (E2006, sector):
+    about density * d distinct columns per row, drawn with a Zipf popularity
+    (column j with weight (j + 1)^-zipf, so a few columns are dense and most
+    are rare), positive values |N(0, 1)| + 0.1, each row scaled to unit norm.
+    Returns CSR arrays (rowptr int32 n + 1, colidx int32, val float32, sorted
+    columns within each row)."""
+    per = max(1, int(round(density * d)))
+    g = _gen(seed, "shape", device)
+    w = torch.arange(1, d + 1, device=device, dtype=torch.float64) ** (-zipf)
+    cdf = torch.cumsum(w, 0)
+    cdf = cdf / cdf[-1]
+    u = torch.rand(n * per, generator=g, device=device, dtype=torch.float64)
+    cols = torch.searchsorted(cdf, u).clamp_(max=d - 1)
+    rows = torch.arange(n, device=device, dtype=torch.int64).repeat_interleave(per)
+    key = torch.unique(rows * d + cols)            # sorted, distinct (row, col)
+    r = key // d
+    c = (key % d).to(torch.int32)
+    counts = torch.bincount(r, minlength=n)
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    rowptr[1:] = torch.cumsum(counts, 0)
+    v = gaussian((key.numel(),), seed, "misc", device).abs() + 0.1
+    nrm = torch.zeros(n, dtype=torch.float64, device=device).index_add_(0, r, v * v).sqrt()
+    v = v / nrm[r]
+    return rowptr.to(torch.int32), c.contiguous(), v.to(torch.float32).contiguous()
+
+
+def sparse_lasso(n: int, d: int, density: float, seed: int = 0, device="cpu", frac=0.01,
+                 noise=0.01, gamma_frac=0.01):
+    """Lasso data on a sparse_text_like matrix: x* with frac * d nonzeros
+    N(0, 1) on the most popular columns' range, b = A x* + noise, gamma =
+    gamma_frac ||A^T b||_inf.  Returns (rowptr, colidx, val, b, gamma, x*);
+    A^T b is formed here from the CSR arrays in FP64 (input preparation, not
+    the method)."""
+    rowptr, col, val = sparse_text_like(n, d, density, seed, device)
+    k = max(1, int(frac * d))
+    xs = torch.zeros(d, dtype=torch.float64, device=device)
+    idx = torch.randperm(min(d, 10 * k), generator=_gen(seed, "support", device),
+                         device=device)[:k]
+    xs[idx] = gaussian((k,), seed, "xval", device)
+    counts = (rowptr[1:] - rowptr[:-1]).to(torch.int64)
+    r = torch.arange(n, device=device).repeat_interleave(counts)
+    ax = torch.zeros(n, dtype=torch.float64, device=device).index_add_(
+        0, r, val.double() * xs[col.long()])
+    b = ax + noise * gaussian((n,), seed, "noise", device)
+    atb = torch.zeros(d, dtype=torch.float64, device=device).index_add_(
+        0, col.long(), val.double() * b[r])
+    gamma = float(gamma_frac * atb.abs().max())
+    return rowptr, col, val, b, gamma, xs
