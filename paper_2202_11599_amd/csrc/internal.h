@@ -223,6 +223,11 @@ struct nys_sparse_s {
   int* rows() const { return csc.as<int>() + (d + 1); }
   float* cvals() const { return reinterpret_cast<float*>(csc.as<int>() + (d + 1) + nnz); }
   nys::DevBuf s;                 // the n-vector s = f(A p) between the two passes
+  // columns binned by length for the A^T pass: short ones (<= kShortCol
+  // entries) by groups of 8 lanes, medium ones by a wavefront, long ones
+  // (> kLongCol) by a workgroup; cols holds the three lists back to back
+  nys::DevBuf bins;
+  int nshort = 0, nmed = 0, nlong = 0;
 };
 
 struct nys_factor_s {

@@ -22,6 +22,22 @@ using gram::sigm;
 using gram::wave_sum;
 
 constexpr int kTBlocks = 64;   // row blocks of the transpose
+constexpr int kShortCol = 32;  // columns with at most this many entries: 8 lanes each
+constexpr int kLongCol = 2048; // columns with more: a 256-thread workgroup each
+
+// Column j goes to list 0 (short), 1 (medium) or 2 (long); counts[3] are the
+// list lengths (the order inside a list does not affect any result: each
+// column is summed by one group on its own).
+__global__ __launch_bounds__(256) void k_bin_cols(const int* __restrict__ colptr, int64_t d,
+                                                  int* __restrict__ lists,
+                                                  int* __restrict__ counts) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= d) return;
+  const int len = colptr[j + 1] - colptr[j];
+  const int b = len <= kShortCol ? 0 : (len <= kLongCol ? 1 : 2);
+  const int pos = atomicAdd(&counts[b], 1);
+  lists[(int64_t)b * d + pos] = (int)j;
+}
 
 // *bad = 1 unless rowptr is non-decreasing (its ends were checked on the host)
 __global__ __launch_bounds__(256) void k_tr_check_rows(const int* __restrict__ rowptr, int64_t n,
@@ -163,22 +179,68 @@ __global__ __launch_bounds__(256) void k_csr_pass(const int* __restrict__ rowptr
   if (threadIdx.x == 0) qpart[blockIdx.x] = ((qs[0] + qs[1]) + qs[2]) + qs[3];
 }
 
-// Column pass: y_j = sum over column j of A_ij s_i (one wavefront per column).
-__global__ __launch_bounds__(256) void k_csc_pass(const int* __restrict__ colptr,
+// Column pass: y_j = sum over column j of A_ij s_i.  Short columns: 8 lanes
+// per column (8 columns per wavefront); medium: one wavefront; long: one
+// 256-thread workgroup.  Fixed summation order per column.
+__global__ __launch_bounds__(256) void k_csc_short(const int* __restrict__ colptr,
+                                                   const int* __restrict__ rows,
+                                                   const float* __restrict__ cval,
+                                                   const int* __restrict__ list, int cnt,
+                                                   const double* __restrict__ s,
+                                                   double* __restrict__ y,
+                                                   const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int g = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3);
+  const int sub = threadIdx.x & 7;
+  double acc = 0.0;
+  int j = -1;
+  if (g < cnt) {
+    j = list[g];
+    for (int k = colptr[j] + sub; k < colptr[j + 1]; k += 8)
+      acc = fma((double)cval[k], s[rows[k]], acc);
+  }
+  acc += __shfl_xor(acc, 4, 8);
+  acc += __shfl_xor(acc, 2, 8);
+  acc += __shfl_xor(acc, 1, 8);
+  if (j >= 0 && sub == 0) y[j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_csc_wave(const int* __restrict__ colptr,
                                                   const int* __restrict__ rows,
-                                                  const float* __restrict__ cval, int64_t d,
+                                                  const float* __restrict__ cval,
+                                                  const int* __restrict__ list, int cnt,
                                                   const double* __restrict__ s,
                                                   double* __restrict__ y,
                                                   const int* __restrict__ done) {
   if (done != nullptr && *done) return;
   const int lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= d) return;
+  const int g = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
+  if (g >= cnt) return;
+  const int j = list[g];
   double acc = 0.0;
-  for (int64_t k = colptr[j] + lane; k < colptr[j + 1]; k += 64)
+  for (int k = colptr[j] + lane; k < colptr[j + 1]; k += 64)
     acc = fma((double)cval[k], s[rows[k]], acc);
   acc = wave_sum(acc);
   if (lane == 0) y[j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_csc_block(const int* __restrict__ colptr,
+                                                   const int* __restrict__ rows,
+                                                   const float* __restrict__ cval,
+                                                   const int* __restrict__ list,
+                                                   const double* __restrict__ s,
+                                                   double* __restrict__ y,
+                                                   const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  __shared__ double red[4];
+  const int j = list[blockIdx.x];
+  double acc = 0.0;
+  for (int k = colptr[j] + threadIdx.x; k < colptr[j + 1]; k += 256)
+    acc = fma((double)cval[k], s[rows[k]], acc);
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) y[j] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // Omega (column-major d x m) -> row-major d x m
@@ -273,8 +335,16 @@ nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& pl, int mod
                        S->n, mode, p, aux, auxout, s, qpart, done);
   else
     NYS_TRY_HIP(hipMemsetAsync(qpart, 0, sizeof(double), st));
-  hipLaunchKernelGGL(k_csc_pass, dim3((unsigned)((S->d + 3) / 4)), dim3(256), 0, st, S->colptr(),
-                     S->rows(), S->cvals(), S->d, s, ypart, done);
+  const int* lists = S->bins.as<int>();
+  if (S->nshort > 0)
+    hipLaunchKernelGGL(k_csc_short, dim3((unsigned)((S->nshort + 31) / 32)), dim3(256), 0, st,
+                       S->colptr(), S->rows(), S->cvals(), lists, S->nshort, s, ypart, done);
+  if (S->nmed > 0)
+    hipLaunchKernelGGL(k_csc_wave, dim3((unsigned)((S->nmed + 3) / 4)), dim3(256), 0, st,
+                       S->colptr(), S->rows(), S->cvals(), lists + S->d, S->nmed, s, ypart, done);
+  if (S->nlong > 0)
+    hipLaunchKernelGGL(k_csc_block, dim3((unsigned)S->nlong), dim3(256), 0, st, S->colptr(),
+                       S->rows(), S->cvals(), lists + 2 * S->d, s, ypart, done);
   if (ev1 != nullptr) NYS_TRY_HIP(hipEventRecord(ev1, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
@@ -366,10 +436,30 @@ nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, con
                          cnt.as<int>(), S->rows(), S->cvals());
     if (hipGetLastError() != hipSuccess) s = NYS_ERR_HIP;
   }
+  // column bins for the A^T pass: three lists of d slots and their lengths
+  if (s == NYS_OK) s = S->bins.reserve(sizeof(int) * (size_t)(3 * d + 3));
+  if (s == NYS_OK) {
+    int* lists = S->bins.as<int>();
+    int* counts = lists + 3 * d;
+    int hc[3] = {0, 0, 0};
+    if (hipMemsetAsync(counts, 0, sizeof(int) * 3, st) != hipSuccess) s = NYS_ERR_HIP;
+    if (s == NYS_OK) {
+      hipLaunchKernelGGL(k_bin_cols, dim3(nb256(d)), dim3(256), 0, st, S->colptr(), d, lists,
+                         counts);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(hc, counts, sizeof(int) * 3, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        s = NYS_ERR_HIP;
+    }
+    S->nshort = hc[0];
+    S->nmed = hc[1];
+    S->nlong = hc[2];
+  }
   cnt.release();
   if (s != NYS_OK) {
     S->csc.release();
     S->s.release();
+    S->bins.release();
     delete S;
     return s;
   }
@@ -382,6 +472,7 @@ nys_status nys_sparse_destroy(nys_sparse S) {
   (void)hipSetDevice(S->device);
   S->csc.release();
   S->s.release();
+  S->bins.release();
   delete S;
   return NYS_OK;
 }
