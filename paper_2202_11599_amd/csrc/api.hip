@@ -234,7 +234,7 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
   ws->ypart = ctx->ypart.as<double>();
   ws->qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ypart.ptr) + yb);
   const size_t nv = align_up(sizeof(double) * d);
-  const size_t cb = align_up(sizeof(double) * 1024 * kDotSlices);
+  const size_t cb = align_up(sizeof(double) * 1024 * kDotSlicesMax);
   const size_t vb = 3 * nv + cb + align_up(sizeof(double) * (size_t)(max_iter + 2));
   NYS_TRY(ctx->vecs.reserve(vb));
   char* v = static_cast<char*>(ctx->vecs.ptr);
@@ -483,13 +483,19 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
     const int limit = max_iter - total_iters;
     char* slots = static_cast<char*>(ctx->host_pinned) + kPollOffset;
     int seqs[4] = {0, 0, 0, 0};
+    // large d: p^T v and ||w||^2 summed once per iteration (their partial
+    // counts grow with d) instead of by every workgroup of the vector kernels
+    const bool pre = d > kPreReduceDim;
     auto enqueue = [&](int k) -> nys_status {
       NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done));
+      if (pre)
+        NYS_TRY(launch_pcg_scalar(0, ws.qpart, pl.nq(), ws.pppart, ws.nvec, rho_eff, ws.st, st));
       NYS_TRY(launch_reduce_update(0, ws.ypart, pl.ny(), pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
                                    ws.w, nullptr, ws.wy, k, ws.pppart, ws.nvec, ws.wwpart, nullptr,
-                                   ws.st, st, pl.nq()));
+                                   ws.st, st, pl.nq(), pre));
+      if (pre) NYS_TRY(launch_pcg_scalar(1, ws.wwpart, ws.nred, nullptr, 0, 0.0, ws.st, st));
       NYS_TRY(launch_precond_dot(U, u32, d, r, ws.w, ws.cvec, ws.st, ws.wwpart, ws.nred, nullptr,
-                                 k, 0, tol_rel, tol_abs, st));
+                                 k, 0, tol_rel, tol_abs, st, pre));
       // sequence numbers are unique per context, so a late write from an
       // earlier solve's queued iteration can never be taken for this one
       const int seq = ctx->poll_seq = (ctx->poll_seq % 1000000000) + 1;
@@ -497,7 +503,8 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
       PcgDev* slot_dev = reinterpret_cast<PcgDev*>(static_cast<char*>(ctx->host_pinned_dev) +
                                                    kPollOffset + 64 * (k % 4));
       NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, k,
-                                    ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st, slot_dev, seq));
+                                    ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st, slot_dev, seq,
+                                    pre));
       return NYS_OK;
     };
     int it = 0, consumed = 0;

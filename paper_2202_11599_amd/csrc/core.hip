@@ -201,6 +201,132 @@ __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int
     for (int i = k + 1; i < r; ++i) M[(int64_t)i * ld + k] = 0.0;  // below the diagonal
 }
 
+// ---- blocked Cholesky for r > kCholOneWg (same contract as k_chol_upper)
+constexpr int kCholOneWg = 256;
+constexpr int kLB = 64;
+
+// Diagonal block M[kb:kb+b, kb:kb+b] <- its upper Cholesky factor (LDS).
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int ld, int kb, int b,
+                                                   int* __restrict__ fail) {
+  __shared__ double C[kLB][kLB + 1];
+  __shared__ double rowv[kLB];
+  __shared__ int bad;
+  if (*fail) return;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < b * b; e += 256) {
+    const int i = e / b, j = e % b;
+    C[i][j] = (j >= i) ? M[(int64_t)(kb + i) * ld + kb + j] : 0.0;
+  }
+  __syncthreads();
+  for (int i = 0; i < b; ++i) {
+    if (tid >= i && tid < b) {
+      const double dii = C[i][i];
+      if (tid == i && (!(dii > 0.0) || !isfinite(dii))) bad = 1;
+      const double piv = sqrt(fabs(dii));
+      rowv[tid] = (tid == i) ? piv : C[i][tid] / piv;
+    }
+    __syncthreads();
+    if (bad) break;
+    if (tid >= i && tid < b) C[i][tid] = rowv[tid];
+    for (int e = tid; e < b * b; e += 256) {
+      const int pp = e / b, q = e % b;
+      if (pp > i && q >= pp) C[pp][q] -= rowv[pp] * rowv[q];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) *fail = 1;
+    return;
+  }
+  for (int e = tid; e < b * b; e += 256) {
+    const int i = e / b, j = e % b;
+    if (j >= i) M[(int64_t)(kb + i) * ld + kb + j] = C[i][j];
+  }
+}
+
+// Block row X = C_kk^-T M[kb:kb+b, kb+b:]: a workgroup per kLB columns, one
+// column per thread, forward substitution against C_kk in LDS.
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int ld, int kb, int b,
+                                                    int nrest, int* __restrict__ fail) {
+  __shared__ double C[kLB][kLB + 1];
+  __shared__ double P[kLB][kLB + 1];
+  if (*fail) return;
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * kLB;
+  const int nc = min(kLB, nrest - c0);
+  for (int e = tid; e < b * b; e += 256) {
+    const int i = e / b, j = e % b;
+    C[i][j] = (j >= i) ? M[(int64_t)(kb + i) * ld + kb + j] : 0.0;
+  }
+  for (int e = tid; e < b * nc; e += 256) {
+    const int i = e / nc, jj = e % nc;
+    P[i][jj] = M[(int64_t)(kb + i) * ld + kb + b + c0 + jj];
+  }
+  __syncthreads();
+  if (tid < nc) {
+    for (int i = 0; i < b; ++i) {
+      double sacc = P[i][tid];
+      for (int l = 0; l < i; ++l) sacc = fma(-C[l][i], P[l][tid], sacc);
+      P[i][tid] = sacc / C[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < b * nc; e += 256) {
+    const int i = e / nc, jj = e % nc;
+    M[(int64_t)(kb + i) * ld + kb + b + c0 + jj] = P[i][jj];
+  }
+}
+
+// Trailing update M[p][q] -= sum_i X[i][p] X[i][q] on the upper triangle:
+// one workgroup per kLB x kLB tile (ti <= tj), X's two column blocks in LDS.
+__global__ __launch_bounds__(256) void k_chol_trail(double* __restrict__ M, int ld, int kb, int b,
+                                                    int nrest, int tc, int* __restrict__ fail) {
+  __shared__ double Xp[kLB][kLB + 1];
+  __shared__ double Xq[kLB][kLB + 1];
+  if (*fail) return;
+  // tile index -> (ti, tj) with ti <= tj, row-major over the upper triangle
+  int t = blockIdx.x, ti = 0;
+  while (t >= tc - ti) {
+    t -= tc - ti;
+    ++ti;
+  }
+  const int tj = ti + t;
+  const int tid = threadIdx.x;
+  const int p0 = ti * kLB, q0 = tj * kLB;
+  const int np = min(kLB, nrest - p0), nq = min(kLB, nrest - q0);
+  const int64_t c = kb + b;   // first trailing index
+  for (int e = tid; e < b * kLB; e += 256) {
+    const int i = e / kLB, jj = e % kLB;
+    Xp[i][jj] = jj < np ? M[(int64_t)(kb + i) * ld + c + p0 + jj] : 0.0;
+    Xq[i][jj] = jj < nq ? M[(int64_t)(kb + i) * ld + c + q0 + jj] : 0.0;
+  }
+  __syncthreads();
+  // 16 outputs per thread: rows pr = tid / 16 + 16 a, columns qc = tid % 16 + 16 e
+  const int pr0 = tid >> 4, qc0 = tid & 15;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int pp = pr0 + 16 * a;
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+      const int qq = qc0 + 16 * e2;
+      if (pp >= np || qq >= nq) continue;
+      if (ti == tj && qq < pp) continue;   // upper triangle only
+      double sacc = 0.0;
+      for (int i = 0; i < b; ++i) sacc = fma(Xp[i][pp], Xq[i][qq], sacc);
+      M[(c + p0 + pp) * ld + c + q0 + qq] -= sacc;
+    }
+  }
+}
+
+__global__ void k_chol_zero_lower(double* __restrict__ M, int r, int ld,
+                                  const int* __restrict__ fail) {
+  if (*fail) return;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= r) return;
+  for (int i = k + 1; i < r; ++i) M[(int64_t)i * ld + k] = 0.0;
+}
+
 // Z = C^-1 for upper triangular C (r x r, row-major, ld); one wavefront per
 // column k, back substitution Z(i,k) = -(sum_{l=i+1..k} C(i,l) Z(l,k)) / C(i,i).
 __global__ __launch_bounds__(256) void k_trinv_upper(const double* __restrict__ Cm, int r, int ld,
@@ -599,7 +725,26 @@ nys_status gemm64(hipStream_t st, int M, int N, int K, const void* A, bool a_f32
 
 nys_status chol_upper(hipStream_t st, double* M, int r, int ld, int* fail) {
   if (r > 1024) return NYS_ERR_INVALID;
-  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, st, M, r, ld, fail);
+  if (r <= kCholOneWg) {
+    hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, st, M, r, ld, fail);
+    return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+  }
+  // blocked right-looking form for larger r: per block row, the diagonal
+  // block (one workgroup), the block row (a workgroup per kLB columns) and the
+  // trailing update (a workgroup per kLB x kLB tile of the upper triangle)
+  for (int kb = 0; kb < r; kb += kLB) {
+    const int b = std::min(kLB, r - kb);
+    const int nrest = r - kb - b;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, M, ld, kb, b, fail);
+    if (nrest > 0) {
+      const int tc = (nrest + kLB - 1) / kLB;
+      hipLaunchKernelGGL(k_chol_panel, dim3(tc), dim3(256), 0, st, M, ld, kb, b, nrest, fail);
+      hipLaunchKernelGGL(k_chol_trail, dim3(tc * (tc + 1) / 2), dim3(256), 0, st, M, ld, kb, b,
+                         nrest, tc, fail);
+    }
+  }
+  hipLaunchKernelGGL(k_chol_zero_lower, dim3((unsigned)((r + 255) / 256)), dim3(256), 0, st, M, r,
+                     ld, fail);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 

@@ -56,7 +56,10 @@ struct PcgDev {
   double ww;     // last ||w||^2
   double rr;     // ||rhs||^2
   double true_rr;// last ||rhs - H_rho x||^2
+  double pv;     // p^T H_rho p of the iteration (pre-reduced path)
+  double wwn;    // ||w||^2 after the update (pre-reduced path)
 };
+static_assert(sizeof(PcgDev) <= 64, "PCG state must fit a 64-byte host slot");
 constexpr int kFlagBreakdown = 1;
 constexpr int kFlagNonfinite = 2;
 constexpr int kFlagZeroRhs = 4;
@@ -287,7 +290,16 @@ inline const nys_sparse_s* as_sparse(const nys_dense& A) {
 // ---- vec.hip
 constexpr int kVecBlock = 32;    // entries of y per workgroup of the preconditioner update
 constexpr int kRedBlock = 16;    // columns per workgroup of the partial reduction
-constexpr int kDotSlices = 8;    // d-slices of the U^T w partial sums
+constexpr int kDotSlicesMax = 64; // d-slices of the U^T w partial sums (buffer size)
+// slices for dimension d: 8, or one per 4096 entries up to 64 for large d
+inline int dot_slices(int64_t d) {
+  const int64_t s = (d + 4095) / 4096;
+  return (int)(s < 8 ? 8 : (s > kDotSlicesMax ? kDotSlicesMax : s));
+}
+// Above this dimension the PCG scalars (p^T v, ||w||^2) are summed once per
+// iteration by a one-workgroup kernel instead of by every workgroup of the
+// vector kernels (whose partial counts grow with d).
+constexpr int64_t kPreReduceDim = 32768;
 inline int nblk(int64_t d, int b) { return (int)((d + b - 1) / b); }
 
 // v = sum_g ypart[g] + rho_eff * p ; then per `op`:
@@ -300,7 +312,12 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 int64_t d, double rho_eff, const double* p, double* x, double* w,
                                 const double* rhs, double* wy, int k, const double* pppart,
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
-                                hipStream_t stream, int Gq = -1);   // Gq: q partials (-1: G)
+                                hipStream_t stream, int Gq = -1,   // Gq: q partials (-1: G)
+                                bool pre = false);                 // alpha from st->pv
+// st->pv = sum(a) + rho_eff sum(b) (op 0) or st->wwn = sum(a) (op 1), one
+// workgroup, fixed order; skipped once st->done is set
+nys_status launch_pcg_scalar(int op, const double* a, int na, const double* b, int nb,
+                             double rho_eff, PcgDev* st, hipStream_t stream);
 // *out = a^T b (one workgroup, fixed order)
 // Judge of two PCG starts: ||w||^2 from wwpart and from wwpart2 (same fixed
 // summation order); if the second is smaller, x <- x_alt, w <- w2,
@@ -320,12 +337,12 @@ nys_status launch_dot(const double* a, const double* b, int64_t d, double* out,
 nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const double* w,
                               double* cvec, PcgDev* st, const double* wwpart, int nww,
                               const double* rrpart, int k, int mode, double tol_rel,
-                              double tol_abs, hipStream_t stream);
+                              double tol_abs, hipStream_t stream, bool pre = false);
 // mode 0: PCG iteration k (p = y + beta p), 1: PCG init (p = y), 2: standalone y = P^-1 w
 nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, const double* lam,
                                  double lam_s, double rho, const double* cvec, const double* w,
                                  double* p, double* wy, int k, const double* wwpart, int nww,
                                  double* pppart, const PcgDev* st, int mode, hipStream_t stream,
-                                 PcgDev* host_slot = nullptr, int seq = 0);
+                                 PcgDev* host_slot = nullptr, int seq = 0, bool pre = false);
 
 }  // namespace nys

@@ -39,16 +39,19 @@ __device__ __forceinline__ double wmax(double v) {
   return v;
 }
 
-// 1024-thread block reductions in a fixed order; every thread gets the result
+// Block reductions over NW wavefronts in a fixed order; every thread gets the
+// result
 enum RedOp { kSum, kMin, kMax };
-template <RedOp OP>
+template <RedOp OP, int NW = 16>
 __device__ double block_reduce(double v, double* sh) {
   v = OP == kSum ? wsum(v) : (OP == kMin ? wmin(v) : wmax(v));
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = sh[0];
-  for (int i = 1; i < 16; ++i) r = OP == kSum ? r + sh[i] : (OP == kMin ? fmin(r, sh[i]) : fmax(r, sh[i]));
+  for (int i = 1; i < NW; ++i)
+    r = OP == kSum ? r + sh[i] : (OP == kMin ? fmin(r, sh[i]) : fmax(r, sh[i]));
+  __syncthreads();
   return r;
 }
 
@@ -93,77 +96,153 @@ __global__ void k_svm_rhs(int64_t n, double rho, const double* __restrict__ z,
 
 constexpr int kSvmNS = 8;   // scalars of the projection pass
 
-__device__ double phi(const double* __restrict__ x, const double* __restrict__ u,
-                      const double* __restrict__ b, int64_t n, double C, double mu, double* sh) {
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
-    const double bi = b[i];
-    s += bi * fmin(fmax(x[i] + u[i] - mu * bi, 0.0), C);
+// Sum of NV values over a block of NW wavefronts in a fixed order; every
+// thread gets the sums.
+template <int NV, int NW>
+__device__ void block_sums(double (&v)[NV], double* sh) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wsum(v[k]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * NW + (threadIdx.x >> 6)] = v[k];
   }
-  return block_reduce<kSum>(s, sh);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double r = 0.0;
+    for (int w = 0; w < NW; ++w) r += sh[k * NW + w];
+    v[k] = r;
+  }
+  __syncthreads();
+}
+
+// phi(mu) = b^T clip(v - mu b, 0, C) and the four clip counts (b = +1 at C,
+// b = +1 at 0, b = -1 at 0, b = -1 at C).  Each count moves one way as mu
+// grows, so equal counts at both ends of a bracket mean no entry changes
+// side inside it and phi is linear there.  VPT > 0: the thread's entries
+// i = tid + kPT k are held in registers (v, sign bits); VPT = 0: read v = x
+// + u and b from memory.
+constexpr int kPT = 512;   // threads of the projection workgroup
+template <int VPT>
+__device__ void phi_counts(const double (&vr)[VPT > 0 ? VPT : 1], unsigned long long sgn,
+                           const double* __restrict__ x, const double* __restrict__ u,
+                           const double* __restrict__ b, int64_t n, double C, double mu,
+                           double (&out)[5], double* sh) {
+  double f = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
+  auto one = [&](double v, bool pos) {
+    if (pos) {
+      const double a = v - mu;
+      f += fmin(fmax(a, 0.0), C);
+      c1 += (a >= C) ? 1.0 : 0.0;
+      c2 += (a <= 0.0) ? 1.0 : 0.0;
+    } else {
+      const double a = v + mu;
+      f -= fmin(fmax(a, 0.0), C);
+      c3 += (a <= 0.0) ? 1.0 : 0.0;
+      c4 += (a >= C) ? 1.0 : 0.0;
+    }
+  };
+  if (VPT > 0) {
+#pragma unroll
+    for (int k = 0; k < (VPT > 0 ? VPT : 1); ++k)
+      if ((int64_t)threadIdx.x + kPT * k < n) one(vr[k], (sgn >> k) & 1ull);
+  } else {
+    for (int64_t i = threadIdx.x; i < n; i += kPT) one(x[i] + u[i], b[i] > 0.0);
+  }
+  out[0] = f;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+  out[4] = c4;
+  block_sums<5, kPT / 64>(out, sh);
 }
 
 // z = projection of v = x + u onto {0 <= z <= C, b^T z = 0}, u += x - z, and
 // out[0..7] = ||x - z||^2, ||z_old - z||^2, ||x||^2, ||z||^2, ||u||^2, b^T z,
-// mu, bisection steps.  One workgroup; every decision is block-uniform.
-__global__ __launch_bounds__(1024) void k_svm_project(int64_t n, const double* __restrict__ x,
+// mu, bisection steps.  One workgroup; every decision is block-uniform:
+// bisection until the clip counts agree at both ends of the bracket, then
+// the exact secant step on the linear piece.
+template <int VPT>
+__global__ __launch_bounds__(kPT) void k_svm_project(int64_t n, const double* __restrict__ x,
                                                       const double* __restrict__ b, double C,
                                                       double* __restrict__ z,
                                                       double* __restrict__ u,
                                                       double* __restrict__ out) {
-  __shared__ double sh[16];
+  __shared__ double sh[6 * (kPT / 64)];
+  double vr[VPT > 0 ? VPT : 1];
+  unsigned long long sgn = 0;
   // bracket: below lo every b = +1 entry clips to C and every b = -1 entry to
   // 0 (phi >= 0); above hi the reverse (phi <= 0)
   double lo_l = 0.0, hi_l = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
-    const double v = x[i] + u[i];
-    if (b[i] > 0.0) {
+  auto brk = [&](double v, bool pos) {
+    if (pos) {
       lo_l = fmin(lo_l, v - C);
       hi_l = fmax(hi_l, v);
     } else {
       lo_l = fmin(lo_l, -v);
       hi_l = fmax(hi_l, C - v);
     }
+  };
+  if (VPT > 0) {
+#pragma unroll
+    for (int k = 0; k < (VPT > 0 ? VPT : 1); ++k) {
+      const int64_t i = (int64_t)threadIdx.x + kPT * k;
+      vr[k] = 0.0;
+      if (i < n) {
+        vr[k] = x[i] + u[i];
+        const bool pos = b[i] > 0.0;
+        if (pos) sgn |= 1ull << k;
+        brk(vr[k], pos);
+      }
+    }
+  } else {
+    vr[0] = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kPT) brk(x[i] + u[i], b[i] > 0.0);
   }
-  double lo = block_reduce<kMin>(lo_l, sh);
-  double hi = block_reduce<kMax>(hi_l, sh);
-  double flo = phi(x, u, b, n, C, lo, sh);
-  double fhi = phi(x, u, b, n, C, hi, sh);
+  double lo = block_reduce<kMin, kPT / 64>(lo_l, sh);
+  double hi = block_reduce<kMax, kPT / 64>(hi_l, sh);
+  double elo[5], ehi[5], emid[5];
+  phi_counts<VPT>(vr, sgn, x, u, b, n, C, lo, elo, sh);
+  phi_counts<VPT>(vr, sgn, x, u, b, n, C, hi, ehi, sh);
   int steps = 0;
   for (; steps < 200; ++steps) {
+    if (elo[1] == ehi[1] && elo[2] == ehi[2] && elo[3] == ehi[3] && elo[4] == ehi[4]) break;
     const double mid = 0.5 * (lo + hi);
     if (!(mid > lo && mid < hi)) break;
-    const double f = phi(x, u, b, n, C, mid, sh);
-    if (f > 0.0) {
+    phi_counts<VPT>(vr, sgn, x, u, b, n, C, mid, emid, sh);
+    if (emid[0] > 0.0) {
       lo = mid;
-      flo = f;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) elo[k] = emid[k];
     } else {
       hi = mid;
-      fhi = f;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) ehi[k] = emid[k];
     }
   }
-  // phi is linear on a bracket without breakpoints: one secant step
+  const double flo = elo[0], fhi = ehi[0];
+  // phi is linear on the final bracket: one secant step
   double mu = (flo == fhi) ? lo : lo + flo * (hi - lo) / (flo - fhi);
   mu = fmin(fmax(mu, lo), hi);
-  double s[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+  double st[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t i = threadIdx.x; i < n; i += kPT) {
     const double xi = x[i], ui = u[i], bi = b[i], zo = z[i];
     const double zn = fmin(fmax(xi + ui - mu * bi, 0.0), C);
     const double un = ui + xi - zn;
     z[i] = zn;
     u[i] = un;
-    s[0] = fma(xi - zn, xi - zn, s[0]);
-    s[1] = fma(zo - zn, zo - zn, s[1]);
-    s[2] = fma(xi, xi, s[2]);
-    s[3] = fma(zn, zn, s[3]);
-    s[4] = fma(un, un, s[4]);
-    s[5] = fma(bi, zn, s[5]);
+    st[0] = fma(xi - zn, xi - zn, st[0]);
+    st[1] = fma(zo - zn, zo - zn, st[1]);
+    st[2] = fma(xi, xi, st[2]);
+    st[3] = fma(zn, zn, st[3]);
+    st[4] = fma(un, un, st[4]);
+    st[5] = fma(bi, zn, st[5]);
   }
-  for (int k = 0; k < 6; ++k) {
-    const double r = block_reduce<kSum>(s[k], sh);
-    if (threadIdx.x == 0) out[k] = r;
-  }
+  block_sums<6, kPT / 64>(st, sh);
   if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[k] = st[k];
     out[6] = mu;
     out[7] = steps;
   }
@@ -174,7 +253,7 @@ __global__ __launch_bounds__(1024) void k_svm_project(int64_t n, const double* _
 // b_i - g_i, out[3] = free count, out[4] = max over the lower-bound set of
 // b_i - g_i, out[5] = min over the upper-bound set; pass 1: out[6] = sum of
 // max(0, 1 - w_i - b_i beta).
-__global__ __launch_bounds__(1024) void k_svm_gap(int64_t n, const double* __restrict__ z,
+__global__ __launch_bounds__(kPT) void k_svm_gap(int64_t n, const double* __restrict__ z,
                                                   const double* __restrict__ w,
                                                   const double* __restrict__ b, double C,
                                                   int pass, double beta,
@@ -182,7 +261,7 @@ __global__ __launch_bounds__(1024) void k_svm_gap(int64_t n, const double* __res
   __shared__ double sh[16];
   if (pass == 0) {
     double zw = 0.0, sz = 0.0, fs = 0.0, fc = 0.0, lo = -INFINITY, hi = INFINITY;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    for (int64_t i = threadIdx.x; i < n; i += kPT) {
       const double zi = z[i], bi = b[i], wi = w[i];
       const double r = bi - bi * wi;   // b_i - g_i
       zw = fma(zi, wi, zw);
@@ -196,12 +275,12 @@ __global__ __launch_bounds__(1024) void k_svm_gap(int64_t n, const double* __res
         hi = fmin(hi, r);    // z = 0, b = -1  or  z = C, b = +1
       }
     }
-    const double a0 = block_reduce<kSum>(zw, sh);
-    const double a1 = block_reduce<kSum>(sz, sh);
-    const double a2 = block_reduce<kSum>(fs, sh);
-    const double a3 = block_reduce<kSum>(fc, sh);
-    const double a4 = block_reduce<kMax>(lo, sh);
-    const double a5 = block_reduce<kMin>(hi, sh);
+    const double a0 = block_reduce<kSum, kPT / 64>(zw, sh);
+    const double a1 = block_reduce<kSum, kPT / 64>(sz, sh);
+    const double a2 = block_reduce<kSum, kPT / 64>(fs, sh);
+    const double a3 = block_reduce<kSum, kPT / 64>(fc, sh);
+    const double a4 = block_reduce<kMax, kPT / 64>(lo, sh);
+    const double a5 = block_reduce<kMin, kPT / 64>(hi, sh);
     if (threadIdx.x == 0) {
       out[0] = a0;
       out[1] = a1;
@@ -212,8 +291,8 @@ __global__ __launch_bounds__(1024) void k_svm_gap(int64_t n, const double* __res
     }
   } else {
     double hs = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) hs += fmax(0.0, 1.0 - w[i] - b[i] * beta);
-    const double a6 = block_reduce<kSum>(hs, sh);
+    for (int64_t i = threadIdx.x; i < n; i += kPT) hs += fmax(0.0, 1.0 - w[i] - b[i] * beta);
+    const double a6 = block_reduce<kSum, kPT / 64>(hs, sh);
     if (threadIdx.x == 0) out[6] = a6;
   }
 }
@@ -258,7 +337,7 @@ nys_status svm_gap(nys_ctx ctx, const nys_svm_problem& P, const double* z, const
                    nys_svm_info* I) {
   const int64_t n = P.H.n;
   NYS_TRY(svm_matvec(ctx, P.H, z, ws.w));
-  hipLaunchKernelGGL(k_svm_gap, dim3(1), dim3(1024), 0, ctx->stream, n, z, ws.w, P.b, P.C, 0, 0.0,
+  hipLaunchKernelGGL(k_svm_gap, dim3(1), dim3(kPT), 0, ctx->stream, n, z, ws.w, P.b, P.C, 0, 0.0,
                      ws.scal + 16);
   double g[6];
   NYS_TRY(read_svm(ctx, ws.scal + 16, g, 6));
@@ -270,7 +349,7 @@ nys_status svm_gap(nys_ctx ctx, const nys_svm_problem& P, const double* z, const
   } else {
     beta = std::isfinite(g[4]) ? g[4] : (std::isfinite(g[5]) ? g[5] : 0.0);
   }
-  hipLaunchKernelGGL(k_svm_gap, dim3(1), dim3(1024), 0, ctx->stream, n, z, ws.w, P.b, P.C, 1,
+  hipLaunchKernelGGL(k_svm_gap, dim3(1), dim3(kPT), 0, ctx->stream, n, z, ws.w, P.b, P.C, 1,
                      beta, ws.scal + 16);
   double hinge;
   NYS_TRY(read_svm(ctx, ws.scal + 22, &hinge, 1));
@@ -360,8 +439,16 @@ nys_status svm_solve(nys_ctx ctx, const nys_svm_problem* P, const nys_svm_opts* 
       s = ps;
       break;
     }
-    hipLaunchKernelGGL(k_svm_project, dim3(1), dim3(1024), 0, st, n, S->x, P->b, P->C, S->z, S->u,
-                       ws.scal);
+    // entries of v held in registers when n <= 512 x 64, else read per step
+    if (n <= kPT * 16)
+      hipLaunchKernelGGL(k_svm_project<16>, dim3(1), dim3(kPT), 0, st, n, S->x, P->b, P->C, S->z,
+                         S->u, ws.scal);
+    else if (n <= kPT * 64)
+      hipLaunchKernelGGL(k_svm_project<64>, dim3(1), dim3(kPT), 0, st, n, S->x, P->b, P->C,
+                         S->z, S->u, ws.scal);
+    else
+      hipLaunchKernelGGL(k_svm_project<0>, dim3(1), dim3(kPT), 0, st, n, S->x, P->b, P->C,
+                         S->z, S->u, ws.scal);
     S->k += 1;
     info.iters += 1;
     info.pcg_iters += pinfo.iters;

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_reduce_update(
     int64_t d, double rho_eff, const double* __restrict__ p, double* __restrict__ x,
     double* __restrict__ w, const double* __restrict__ rhs, double* __restrict__ wy, int k,
     const double* __restrict__ pppart, int npp, double* __restrict__ wwpart,
-    double* __restrict__ rrpart, PcgDev* __restrict__ st, int Gq) {
+    double* __restrict__ rrpart, PcgDev* __restrict__ st, int Gq, int pre) {
   if (op == 0 && st->done) return;
   constexpr int RJ = kRedBlock;
   constexpr int S = 256 / RJ;
@@ -72,11 +72,17 @@ __global__ __launch_bounds__(256) void k_reduce_update(
 
   double alpha = 0.0;
   if (op == 0) {
-    // q = sum qpart, pp = sum pppart (fixed order, identical in every workgroup)
-    const double qs = block_sum_array(qpart, Gq, sh4);
-    __syncthreads();
-    const double ps = block_sum_array(pppart, npp, sh4);
-    const double pv = qs + rho_eff * ps;
+    // q = sum qpart, pp = sum pppart (fixed order, identical in every
+    // workgroup), or the sum made once by k_pcg_scalar (pre)
+    double pv;
+    if (pre) {
+      pv = st->pv;
+    } else {
+      const double qs = block_sum_array(qpart, Gq, sh4);
+      __syncthreads();
+      const double ps = block_sum_array(pppart, npp, sh4);
+      pv = qs + rho_eff * ps;
+    }
     if (!(pv > 0.0)) {
       if (blockIdx.x == 0 && tid == 0) {
         st->flags |= (pv != pv) ? kFlagNonfinite : kFlagBreakdown;
@@ -129,18 +135,20 @@ __global__ __launch_bounds__(256) void k_reduce_update(
 // mode 1: PCG init (threshold from ||rhs||, test, then c = U^T w)
 // mode 2: standalone c = U^T w
 // mode 3: record sum(wwpart) as the true residual, no dots
-// c is left as kDotSlices partial sums over slices of d (cvec[s * 1024 + i]),
-// added in slice order by k_precond_update.
+// c is left as dot_slices(d) partial sums over slices of d (cvec[s * 1024 +
+// i], one slice per blockIdx.y), added in slice order by k_precond_update.
+// pre: ||w||^2 was summed once by k_pcg_scalar into st->wwn.
 template <typename UT>
 __global__ __launch_bounds__(256) void k_precond_dot(
     const UT* __restrict__ U, int64_t d, int r, const double* __restrict__ w,
     double* __restrict__ cvec, PcgDev* __restrict__ st, const double* __restrict__ wwpart,
-    int nww, const double* __restrict__ rrpart, int k, int mode, double tol_rel, double tol_abs) {
+    int nww, const double* __restrict__ rrpart, int k, int mode, double tol_rel, double tol_abs,
+    int pre) {
   __shared__ double sh4[4];
   const int tid = threadIdx.x;
   if (mode == 0 || mode == 1) {
     if (st->done) return;
-    const double ww = block_sum_array(wwpart, nww, sh4);
+    const double ww = (pre && mode == 0) ? st->wwn : block_sum_array(wwpart, nww, sh4);
     double thr2;
     bool zero_rhs = false;
     if (mode == 1) {
@@ -175,7 +183,8 @@ __global__ __launch_bounds__(256) void k_precond_dot(
   const int lane = tid & 63;
   const int col = blockIdx.x * 4 + (tid >> 6);
   if (col >= r) return;
-  const int64_t chunk = ((d + kDotSlices - 1) / kDotSlices + 63) / 64 * 64;
+  const int nsl = (int)gridDim.y;
+  const int64_t chunk = ((d + nsl - 1) / nsl + 63) / 64 * 64;
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = j0 + chunk < d ? j0 + chunk : d;
   const UT* u = U + (int64_t)col * d;
@@ -196,7 +205,7 @@ __global__ __launch_bounds__(256) void k_precond_update(
     double rho, const double* __restrict__ cvec, const double* __restrict__ w,
     double* __restrict__ p, double* __restrict__ wy, int k, const double* __restrict__ wwpart,
     int nww, double* __restrict__ pppart, const PcgDev* __restrict__ st, int mode,
-    PcgDev* __restrict__ host_slot, int seq) {
+    PcgDev* __restrict__ host_slot, int seq, int nsl, int pre) {
   // host_slot (pinned host memory, may be NULL): receives the state at the end
   // of the iteration, read by the host once the kernel has completed
   if (mode != 2 && st->done) {
@@ -216,15 +225,14 @@ __global__ __launch_bounds__(256) void k_precond_update(
   double sc = 0.0;
   for (int i = tid; i < r; i += 256) {
     double ci = 0.0;
-#pragma unroll
-    for (int sl = 0; sl < kDotSlices; ++sl) ci += cvec[sl * 1024 + i];
+    for (int sl = 0; sl < nsl; ++sl) ci += cvec[sl * 1024 + i];
     const double s = (lam_s + rho) / (lam[i] + rho) - 1.0;
     g[i] = s * ci;
     sc += s * ci * ci;
   }
   double wy_new = 0.0;
   if (mode != 2) {
-    const double ww = block_sum_array(wwpart, nww, sh4);
+    const double ww = (pre && mode == 0) ? st->wwn : block_sum_array(wwpart, nww, sh4);
     __syncthreads();
     wy_new = ww + block_sum_value(sc, sh4);
   } else {
@@ -265,6 +273,34 @@ __global__ __launch_bounds__(256) void k_precond_update(
         *host_slot = h;
       }
     }
+  }
+}
+
+// st->pv = sum(a) + rho_eff sum(b) (op 0), st->wwn = sum(a) (op 1): the
+// PCG scalars summed once per iteration, in a fixed order, for large d
+__global__ __launch_bounds__(1024) void k_pcg_scalar(int op, const double* __restrict__ a, int na,
+                                                     const double* __restrict__ b, int nb,
+                                                     double rho_eff, PcgDev* __restrict__ st) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  auto bsum = [&](const double* v, int cnt) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += 1024) s += v[i];
+    s = wave_sum(s);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < 16; ++i) r += sh[i];
+    __syncthreads();
+    return r;
+  };
+  const double sa = bsum(a, na);
+  if (op == 0) {
+    const double sb = bsum(b, nb);
+    if (threadIdx.x == 0) st->pv = sa + rho_eff * sb;
+  } else {
+    if (threadIdx.x == 0) st->wwn = sa;
   }
 }
 
@@ -342,27 +378,33 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 int64_t d, double rho_eff, const double* p, double* x, double* w,
                                 const double* rhs, double* wy, int k, const double* pppart,
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
-                                hipStream_t stream, int Gq) {
+                                hipStream_t stream, int Gq, bool pre) {
   hipLaunchKernelGGL(k_reduce_update, dim3(nblk(d, kRedBlock)), dim3(256), 0, stream, op, ypart,
                      G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp, wwpart, rrpart,
-                     st, Gq < 0 ? G : Gq);
+                     st, Gq < 0 ? G : Gq, pre ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status launch_pcg_scalar(int op, const double* a, int na, const double* b, int nb,
+                             double rho_eff, PcgDev* st, hipStream_t stream) {
+  hipLaunchKernelGGL(k_pcg_scalar, dim3(1), dim3(1024), 0, stream, op, a, na, b, nb, rho_eff, st);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
 nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const double* w,
                               double* cvec, PcgDev* st, const double* wwpart, int nww,
                               const double* rrpart, int k, int mode, double tol_rel,
-                              double tol_abs, hipStream_t stream) {
+                              double tol_abs, hipStream_t stream, bool pre) {
   const unsigned gx = r > 0 ? (unsigned)((r + 3) / 4) : 1u;
-  const dim3 grid(gx, (mode == 0 || mode == 1 || mode == 2) ? kDotSlices : 1);
+  const dim3 grid(gx, (mode == 0 || mode == 1 || mode == 2) ? dot_slices(d) : 1);
   if (u32)
     hipLaunchKernelGGL(k_precond_dot<float>, grid, dim3(256), 0, stream,
                        static_cast<const float*>(U), d, r, w, cvec, st, wwpart, nww, rrpart, k,
-                       mode, tol_rel, tol_abs);
+                       mode, tol_rel, tol_abs, pre ? 1 : 0);
   else
     hipLaunchKernelGGL(k_precond_dot<double>, grid, dim3(256), 0, stream,
                        static_cast<const double*>(U), d, r, w, cvec, st, wwpart, nww, rrpart, k,
-                       mode, tol_rel, tol_abs);
+                       mode, tol_rel, tol_abs, pre ? 1 : 0);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
@@ -370,17 +412,18 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
                                  double lam_s, double rho, const double* cvec, const double* w,
                                  double* p, double* wy, int k, const double* wwpart, int nww,
                                  double* pppart, const PcgDev* st, int mode, hipStream_t stream,
-                                 PcgDev* host_slot, int seq) {
+                                 PcgDev* host_slot, int seq, bool pre) {
   if (r > 1024) return NYS_ERR_INVALID;
   const int grid = nblk(d, kVecBlock);
+  const int nsl = dot_slices(d);
   if (u32)
     hipLaunchKernelGGL(k_precond_update<float>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const float*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
-                       wwpart, nww, pppart, st, mode, host_slot, seq);
+                       wwpart, nww, pppart, st, mode, host_slot, seq, nsl, pre ? 1 : 0);
   else
     hipLaunchKernelGGL(k_precond_update<double>, dim3(grid), dim3(256), 0, stream,
                        static_cast<const double*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
-                       wwpart, nww, pppart, st, mode, host_slot, seq);
+                       wwpart, nww, pppart, st, mode, host_slot, seq, nsl, pre ? 1 : 0);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 

@@ -234,3 +234,23 @@ def test_repeated_sketches_reuse_device_blocks(N):
     F = N.nys_sketch(c1, A32, om[:40].contiguous(), prec=N.NYS_F32)
     c1.close()
     F.close()
+
+
+@pytest.mark.parametrize("r", [300, 700])
+def test_sketch_fp64_large_rank_blocked_cholesky(N, ctx, r):
+    # ranks above 256 take the blocked multi-workgroup Cholesky (orthonormal
+    # blocks of Omega by CholeskyQR2 and the shifted core), with a ragged last
+    # block at r = 300 and 700
+    n, d = 4000, 1500
+    A64 = synth.decay_matrix(n, d, 0.6, seed=r)
+    om = synth.omega_raw(d, r, seed=r + 1)
+    print(f"[sketch large rank] r={r}", flush=True)
+    F = N.nys_sketch(ctx, A64.to(DEV), om.to(DEV), prec=N.NYS_F64)
+    H, U, lam, inf = hhat(F, ctx)
+    f = ny.rand_nys_appx(A64.numpy(), None, 0.0, om.numpy().T)
+    e = rel(H, f.dense())
+    print(f"[sketch large rank] r={r} rel(Hhat)={e:.3e} nu={inf['nu']:.3e}/{f.nu:.3e}", flush=True)
+    assert e < 1e-10 and inf["nu"] == f.nu
+    # U = B V Sigma^-1 is orthonormal to rounding: ~1e-12 per entry at r = 700
+    assert np.linalg.norm(U.T @ U - np.eye(r)) < 1e-11 * r
+    F.close()

@@ -140,3 +140,28 @@ def test_sparse_deterministic_and_invalid(N, ctx):
     short[-1] -= 1                         # does not end at nnz
     with pytest.raises(N.NysError):
         N.SparseMatrix(ctx, short.to(DEV), c.to(DEV), v.to(DEV), (n, d))
+
+
+def test_sparse_large_d_pcg(N, ctx):
+    # d > 32768: the PCG scalars are summed by a one-workgroup kernel and U^T w
+    # is split into more slices; iterates against the oracle's PCG
+    from oracle import pcg as opcg
+    n, d, r, rho = 1000, 40000, 30, 1e-2
+    S, A = make(N, ctx, n, d, 0.002, seed=12)
+    om = synth.omega_raw(d, r, seed=13)
+    F = N.nys_sketch(ctx, S, om.to(DEV), prec=N.NYS_F64)
+    f = ny.rand_nys_appx(A, None, 0.0, om.numpy().T)
+    rhs_np = np.random.default_rng(14).standard_normal(d)
+    x = torch.zeros(d, dtype=torch.float64, device=DEV)
+    info = N.pcg_solve(ctx, S, torch.tensor(rhs_np, device=DEV), x, rho, F,
+                       opts=N.pcg_opts(tol=1e-10, max_iter=2000))
+    ora = opcg.nys_pcg(lambda v: A.T @ (A @ v) + rho * v, rhs_np, np.zeros(d),
+                       lambda w: ny.precond_inverse_apply(f.U, f.lam, rho, w), 1e-10, 2000)
+    e = np.linalg.norm(x.cpu().numpy() - ora.x) / np.linalg.norm(ora.x)
+    print(f"[sparse large d] iters {info.iters} oracle {ora.iters} rel diff {e:.2e} true res "
+          f"{info.true_res_norm / info.rhs_norm:.2e}", flush=True)
+    assert abs(info.iters - ora.iters) <= max(1, int(np.ceil(0.03 * ora.iters)))
+    assert info.true_res_norm <= 1e-10 * info.rhs_norm * (1 + 1e-6)
+    assert e < 1e-7
+    F.close()
+    S.close()
