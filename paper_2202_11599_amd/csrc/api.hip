@@ -244,7 +244,8 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
   ws->wy = reinterpret_cast<double*>(v + 2 * nv + cb);
   ws->w2 = reinterpret_cast<double*>(v + 2 * nv + cb +
                                      align_up(sizeof(double) * (size_t)(max_iter + 2)));
-  ws->nred = nblk(d, kRedBlock);
+  ws->rj = red_block(pl.ny());
+  ws->nred = nblk(d, ws->rj);
   ws->nvec = nblk(d, kVecBlock);
   const size_t sb = align_up(sizeof(PcgDev)) + 4 * align_up(sizeof(double) * ws->nred) +
                     align_up(sizeof(double) * ws->nvec);
@@ -453,7 +454,7 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
       // H_rho x0 from the previous solve's true-residual pass (x0 unchanged)
       NYS_TRY(launch_reduce_update(1, ws.ypart, 0, pl.ldy, ws.qpart, d, 1.0, ctx->hx.as<double>(),
                                    nullptr, ws.w, rhs, ws.wy, 0, nullptr, 0, ws.wwpart, ws.rrpart,
-                                   ws.st, st));
+                                   ws.st, st, -1, false, ws.rj));
     } else {
       NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, x, D, nullptr, ws.ypart, ws.qpart, nullptr));
       NYS_TRY(launch_reduce_update(1, ws.ypart, pl.ny(), pl.ldy, ws.qpart, d, rho_eff, x, nullptr,

@@ -111,8 +111,9 @@ struct PcgWs {
   double* w2 = nullptr;          // residual of a candidate start (judge)
   double* wwpart2 = nullptr;
   double* rrpart2 = nullptr;
-  int nred = 0;
+  int nred = 0;     // ||w||^2 partials: nblk(d, rj)
   int nvec = 0;
+  int rj = 16;     // columns per workgroup of the partial reduction (red_block(ny))
 };
 
 // ---- api.hip
@@ -290,6 +291,10 @@ inline const nys_sparse_s* as_sparse(const nys_dense& A) {
 // ---- vec.hip
 constexpr int kVecBlock = 32;    // entries of y per workgroup of the preconditioner update
 constexpr int kRedBlock = 16;    // columns per workgroup of the partial reduction
+// columns per workgroup of the partial reduction for G partial rows: 16
+// columns x 16 slices of the partials for large G, one column per thread
+// (all 256 lanes busy) when there are few partial rows to add
+inline int red_block(int G) { return G <= 16 ? 256 : kRedBlock; }
 constexpr int kDotSlicesMax = 64; // d-slices of the U^T w partial sums (buffer size)
 // slices for dimension d: 8, or one per 4096 entries up to 64 for large d
 inline int dot_slices(int64_t d) {
@@ -313,7 +318,9 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 const double* rhs, double* wy, int k, const double* pppart,
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
                                 hipStream_t stream, int Gq = -1,   // Gq: q partials (-1: G)
-                                bool pre = false);                 // alpha from st->pv
+                                bool pre = false,                  // alpha from st->pv
+                                int rj = 0);  // columns per workgroup (0: red_block(G)); the
+                                              // ||w||^2 partials number nblk(d, rj)
 // st->pv = sum(a) + rho_eff sum(b) (op 0) or st->wwn = sum(a) (op 1), one
 // workgroup, fixed order; skipped once st->done is set
 nys_status launch_pcg_scalar(int op, const double* a, int na, const double* b, int nb,

@@ -17,10 +17,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// a[t] + a[t + step] + ... (indices below n) with four loads in flight: four
+// running sums, combined in a fixed order
+__device__ __forceinline__ double strided_sum(const double* __restrict__ a, int n, int t,
+                                              int step) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = t;
+  for (; i + 3 * step < n; i += 4 * step) {
+    s0 += a[i];
+    s1 += a[i + step];
+    s2 += a[i + 2 * step];
+    s3 += a[i + 3 * step];
+  }
+  for (; i < n; i += step) s0 += a[i];
+  return (s0 + s1) + (s2 + s3);
+}
+
 // Sum of a[0..n) with a 256-thread block in a fixed order; every thread gets it.
 __device__ double block_sum_array(const double* __restrict__ a, int n, double* sh4) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += a[i];
+  double s = strided_sum(a, n, threadIdx.x, 256);
   s = wave_sum(s);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = s;
@@ -37,8 +52,9 @@ __device__ double block_sum_value(double v, double* sh4) {
   return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
-// 256 threads: kRedBlock columns x (256 / kRedBlock) slices of the workgroup
-// partials, combined in a fixed order through LDS.
+// 256 threads: RJ columns x (256 / RJ) slices of the workgroup partials,
+// combined in a fixed order through LDS.
+template <int RJ>
 __global__ __launch_bounds__(256) void k_reduce_update(
     int op, const double* __restrict__ ypart, int G, int ldy, const double* __restrict__ qpart,
     int64_t d, double rho_eff, const double* __restrict__ p, double* __restrict__ x,
@@ -46,7 +62,6 @@ __global__ __launch_bounds__(256) void k_reduce_update(
     const double* __restrict__ pppart, int npp, double* __restrict__ wwpart,
     double* __restrict__ rrpart, PcgDev* __restrict__ st, int Gq, int pre) {
   if (op == 0 && st->done) return;
-  constexpr int RJ = kRedBlock;
   constexpr int S = 256 / RJ;
   __shared__ double part[S][RJ];
   __shared__ double sh4[4];
@@ -188,8 +203,18 @@ __global__ __launch_bounds__(256) void k_precond_dot(
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = j0 + chunk < d ? j0 + chunk : d;
   const UT* u = U + (int64_t)col * d;
-  double acc = 0.0;
-  for (int64_t j = j0 + lane; j < j1; j += 64) acc = fma((double)u[j], w[j], acc);
+  // eight running sums so that eight loads of U (and of w) are in flight per
+  // lane; combined in a fixed order
+  double a[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) a[t] = 0.0;
+  int64_t j = j0 + lane;
+  for (; j + 7 * 64 < j1; j += 8 * 64) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) a[t] = fma((double)u[j + 64 * t], w[j + 64 * t], a[t]);
+  }
+  for (; j < j1; j += 64) a[0] = fma((double)u[j], w[j], a[0]);
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   acc = wave_sum(acc);
   if (lane == 0) cvec[(int64_t)blockIdx.y * 1024 + col] = acc;
 }
@@ -224,8 +249,7 @@ __global__ __launch_bounds__(256) void k_precond_update(
   const int tid = threadIdx.x;
   double sc = 0.0;
   for (int i = tid; i < r; i += 256) {
-    double ci = 0.0;
-    for (int sl = 0; sl < nsl; ++sl) ci += cvec[sl * 1024 + i];
+    const double ci = strided_sum(cvec + i, nsl * 1024, 0, 1024);   // slices in order
     const double s = (lam_s + rho) / (lam[i] + rho) - 1.0;
     g[i] = s * ci;
     sc += s * ci * ci;
@@ -242,8 +266,20 @@ __global__ __launch_bounds__(256) void k_precond_update(
   const int64_t j = (int64_t)blockIdx.x * VJ + jl;
   double part = 0.0;
   if (j < d) {
+    // eight running sums over the rank index (i = sl, sl + VS, ...) so that
+    // eight loads of U are in flight per lane; combined in a fixed order
     const UT* u = U + j;
-    for (int i = sl; i < r; i += VS) part = fma((double)u[(int64_t)i * d], g[i], part);
+    double a[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) a[t] = 0.0;
+    int i = sl;
+    for (; i + 7 * VS < r; i += 8 * VS) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        a[t] = fma((double)u[(int64_t)(i + t * VS) * d], g[i + t * VS], a[t]);
+    }
+    for (; i < r; i += VS) a[0] = fma((double)u[(int64_t)i * d], g[i], a[0]);
+    part = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   ys[sl][jl] = part;
   __syncthreads();
@@ -284,8 +320,7 @@ __global__ __launch_bounds__(1024) void k_pcg_scalar(int op, const double* __res
   __shared__ double sh[16];
   if (st->done) return;
   auto bsum = [&](const double* v, int cnt) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < cnt; i += 1024) s += v[i];
+    double s = strided_sum(v, cnt, threadIdx.x, 1024);
     s = wave_sum(s);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
@@ -346,8 +381,16 @@ __global__ __launch_bounds__(256) void k_ut_v(const double* __restrict__ U, int6
   const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (col >= r) return;
   const double* u = U + (int64_t)col * d;
-  double acc = 0.0;
-  for (int64_t j = lane; j < d; j += 64) acc = fma(u[j], v[j], acc);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t j = lane;
+  for (; j + 192 < d; j += 256) {
+    a0 = fma(u[j], v[j], a0);
+    a1 = fma(u[j + 64], v[j + 64], a1);
+    a2 = fma(u[j + 128], v[j + 128], a2);
+    a3 = fma(u[j + 192], v[j + 192], a3);
+  }
+  for (; j < d; j += 64) a0 = fma(u[j], v[j], a0);
+  double acc = (a0 + a1) + (a2 + a3);
   acc = wave_sum(acc);
   if (lane == 0) out[col] = acc;
 }
@@ -361,9 +404,16 @@ __global__ __launch_bounds__(256) void k_u_c(const double* __restrict__ U, int64
   __syncthreads();
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= d) return;
-  double acc = 0.0;
-  for (int i = 0; i < r; ++i) acc = fma(U[(int64_t)i * d + j], cs[i], acc);
-  out[j] = acc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = 0;
+  for (; i + 3 < r; i += 4) {
+    a0 = fma(U[(int64_t)i * d + j], cs[i], a0);
+    a1 = fma(U[(int64_t)(i + 1) * d + j], cs[i + 1], a1);
+    a2 = fma(U[(int64_t)(i + 2) * d + j], cs[i + 2], a2);
+    a3 = fma(U[(int64_t)(i + 3) * d + j], cs[i + 3], a3);
+  }
+  for (; i < r; ++i) a0 = fma(U[(int64_t)i * d + j], cs[i], a0);
+  out[j] = (a0 + a1) + (a2 + a3);
 }
 
 }  // namespace
@@ -378,10 +428,18 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 int64_t d, double rho_eff, const double* p, double* x, double* w,
                                 const double* rhs, double* wy, int k, const double* pppart,
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
-                                hipStream_t stream, int Gq, bool pre) {
-  hipLaunchKernelGGL(k_reduce_update, dim3(nblk(d, kRedBlock)), dim3(256), 0, stream, op, ypart,
-                     G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp, wwpart, rrpart,
-                     st, Gq < 0 ? G : Gq, pre ? 1 : 0);
+                                hipStream_t stream, int Gq, bool pre, int rj) {
+  if (rj == 0) rj = red_block(G);
+  if (rj == 256)
+    hipLaunchKernelGGL(k_reduce_update<256>, dim3(nblk(d, 256)), dim3(256), 0, stream, op, ypart,
+                       G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp, wwpart,
+                       rrpart, st, Gq < 0 ? G : Gq, pre ? 1 : 0);
+  else if (rj == kRedBlock)
+    hipLaunchKernelGGL(k_reduce_update<kRedBlock>, dim3(nblk(d, kRedBlock)), dim3(256), 0, stream,
+                       op, ypart, G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp,
+                       wwpart, rrpart, st, Gq < 0 ? G : Gq, pre ? 1 : 0);
+  else
+    return NYS_ERR_INVALID;
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
