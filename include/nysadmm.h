@@ -366,7 +366,8 @@ typedef struct {
 /* Algorithm NysADMM on the SVM dual: minimize 1/2 x^T H x - 1^T x subject to
  * b^T x = 0, 0 <= x <= C.  x-update: PCG on (H + rho I) x = rho (z - u) + 1;
  * z-update: projection of x + u onto the constraint set (clip(v - mu b, 0, C)
- * with mu by bisection); u += x - z.  The state (x, z, u: device FP64
+ * with the root mu of b^T z(mu) = 0 found exactly by safeguarded Newton steps
+ * on that piecewise-linear function); u += x - z.  The state (x, z, u: device FP64
  * n-vectors, x = z = u = 0 for a cold start) is updated in place; z is the
  * feasible dual solution. */
 nys_status svm_solve(nys_ctx ctx, const nys_svm_problem* P, const nys_svm_opts* O,

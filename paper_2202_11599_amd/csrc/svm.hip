@@ -10,7 +10,8 @@
 //   x   PCG on (H + rho I) x = rho (z - u) + 1, Nystrom-preconditioned, one
 //       column-blocked pass over H per iteration (k_rowdot)
 //   z   projection of x + u onto {0 <= z <= C, b^T z = 0}: clip(v - mu b)
-//       with the multiplier mu found by bisection (one workgroup)
+//       with the multiplier mu found by safeguarded Newton steps on the
+//       piecewise-linear b^T z(mu) (one workgroup)
 //   u   u + x - z
 // and every gap_every iterations the duality gap between the SVM primal (bias
 // from the free variables, as LIBSVM) and the dual at the feasible z.
@@ -97,7 +98,9 @@ __global__ void k_svm_rhs(int64_t n, double rho, const double* __restrict__ z,
 constexpr int kSvmNS = 8;   // scalars of the projection pass
 
 // Sum of NV values over a block of NW wavefronts in a fixed order; every
-// thread gets the sums.
+// thread gets the sums.  sh holds (NW + 1) NV doubles.  Thread k < NV adds the
+// NW wavefront partials of value k, so each thread reads NV sums back rather
+// than all NV x NW partials.
 template <int NV, int NW>
 __device__ void block_sums(double (&v)[NV], double* sh) {
 #pragma unroll
@@ -108,39 +111,46 @@ __device__ void block_sums(double (&v)[NV], double* sh) {
     for (int k = 0; k < NV; ++k) sh[k * NW + (threadIdx.x >> 6)] = v[k];
   }
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
+  if (threadIdx.x < NV) {
     double r = 0.0;
-    for (int w = 0; w < NW; ++w) r += sh[k * NW + w];
-    v[k] = r;
+    for (int w = 0; w < NW; ++w) r += sh[threadIdx.x * NW + w];
+    sh[NV * NW + threadIdx.x] = r;
   }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = sh[NV * NW + k];
   __syncthreads();
 }
 
 // phi(mu) = b^T clip(v - mu b, 0, C) and the four clip counts (b = +1 at C,
-// b = +1 at 0, b = -1 at 0, b = -1 at C).  Each count moves one way as mu
-// grows, so equal counts at both ends of a bracket mean no entry changes
-// side inside it and phi is linear there.  VPT > 0: the thread's entries
-// i = tid + kPT k are held in registers (v, sign bits); VPT = 0: read v = x
-// + u and b from memory.
+// b = +1 at 0, b = -1 at 0, b = -1 at C) at the three points mu[0..2] in one
+// pass: out[5 m + 0] = phi(mu[m]), out[5 m + 1..4] = the counts.  Each count
+// moves one way as mu grows, so equal counts at both ends of a bracket mean no
+// entry changes side inside it and phi is linear there; n minus the counts is
+// the number of free entries, the slope of -phi.  VPT > 0: the thread's
+// entries i = tid + kPT k are held in registers (v, sign bits); VPT = 0: read
+// v = x + u and b from memory.
 constexpr int kPT = 512;   // threads of the projection workgroup
+constexpr int kPM = 3;     // points per pass
 template <int VPT>
 __device__ void phi_counts(const double (&vr)[VPT > 0 ? VPT : 1], unsigned long long sgn,
                            const double* __restrict__ x, const double* __restrict__ u,
-                           const double* __restrict__ b, int64_t n, double C, double mu,
-                           double (&out)[5], double* sh) {
-  double f = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
+                           const double* __restrict__ b, int64_t n, double C,
+                           const double (&mu)[kPM], double (&out)[5 * kPM], double* sh) {
+  double f[kPM];
+  int cnt[4 * kPM];   // per-thread counts (integers: fewer registers)
+#pragma unroll
+  for (int m = 0; m < kPM; ++m) f[m] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4 * kPM; ++k) cnt[k] = 0;
   auto one = [&](double v, bool pos) {
-    if (pos) {
-      const double a = v - mu;
-      f += fmin(fmax(a, 0.0), C);
-      c1 += (a >= C) ? 1.0 : 0.0;
-      c2 += (a <= 0.0) ? 1.0 : 0.0;
-    } else {
-      const double a = v + mu;
-      f -= fmin(fmax(a, 0.0), C);
-      c3 += (a <= 0.0) ? 1.0 : 0.0;
-      c4 += (a >= C) ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = 0; m < kPM; ++m) {
+      const double a = pos ? v - mu[m] : v + mu[m];
+      const double c = fmin(fmax(a, 0.0), C);
+      f[m] += pos ? c : -c;
+      cnt[4 * m + (pos ? 0 : 3)] += (a >= C) ? 1 : 0;
+      cnt[4 * m + (pos ? 1 : 2)] += (a <= 0.0) ? 1 : 0;
     }
   };
   if (VPT > 0) {
@@ -150,26 +160,32 @@ __device__ void phi_counts(const double (&vr)[VPT > 0 ? VPT : 1], unsigned long 
   } else {
     for (int64_t i = threadIdx.x; i < n; i += kPT) one(x[i] + u[i], b[i] > 0.0);
   }
-  out[0] = f;
-  out[1] = c1;
-  out[2] = c2;
-  out[3] = c3;
-  out[4] = c4;
-  block_sums<5, kPT / 64>(out, sh);
+#pragma unroll
+  for (int m = 0; m < kPM; ++m) {
+    out[5 * m] = f[m];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[5 * m + 1 + q] = (double)cnt[4 * m + q];
+  }
+  block_sums<5 * kPM, kPT / 64>(out, sh);
 }
 
 // z = projection of v = x + u onto {0 <= z <= C, b^T z = 0}, u += x - z, and
 // out[0..7] = ||x - z||^2, ||z_old - z||^2, ||x||^2, ||z||^2, ||u||^2, b^T z,
-// mu, bisection steps.  One workgroup; every decision is block-uniform:
-// bisection until the clip counts agree at both ends of the bracket, then
-// the exact secant step on the linear piece.
+// mu, passes.  One workgroup; every decision is block-uniform (all threads
+// hold the same sums).  phi is non-increasing and piecewise linear in mu; the
+// bracket [lo, hi] (phi(lo) > 0 >= phi(hi)) shrinks by passes that each
+// evaluate three points: a Newton step from either end along the slope given
+// by that end's free count (exact when that end lies on the root's linear
+// piece) and the midpoint (which bounds the work by that of bisection).  Once
+// the counts agree at both ends, the secant step on the linear piece is exact.
 template <int VPT>
 __global__ __launch_bounds__(kPT) void k_svm_project(int64_t n, const double* __restrict__ x,
                                                       const double* __restrict__ b, double C,
                                                       double* __restrict__ z,
                                                       double* __restrict__ u,
                                                       double* __restrict__ out) {
-  __shared__ double sh[6 * (kPT / 64)];
+  __shared__ double sh[5 * kPM * (kPT / 64 + 1)];
+  if (n <= 0) return;
   double vr[VPT > 0 ? VPT : 1];
   unsigned long long sgn = 0;
   // bracket: below lo every b = +1 entry clips to C and every b = -1 entry to
@@ -184,16 +200,30 @@ __global__ __launch_bounds__(kPT) void k_svm_project(int64_t n, const double* __
       hi_l = fmax(hi_l, C - v);
     }
   };
+  constexpr int CH = VPT >= 8 ? 8 : (VPT > 0 ? VPT : 1);   // entries loaded together
   if (VPT > 0) {
 #pragma unroll
-    for (int k = 0; k < (VPT > 0 ? VPT : 1); ++k) {
-      const int64_t i = (int64_t)threadIdx.x + kPT * k;
-      vr[k] = 0.0;
-      if (i < n) {
-        vr[k] = x[i] + u[i];
-        const bool pos = b[i] > 0.0;
-        if (pos) sgn |= 1ull << k;
-        brk(vr[k], pos);
+    for (int k0 = 0; k0 < (VPT > 0 ? VPT : 1); k0 += CH) {
+      // in-bounds loads for every lane (index 0 past the end), issued together
+      double xs[CH], us[CH], bs[CH];
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const int64_t i = (int64_t)threadIdx.x + kPT * (k0 + t);
+        const int64_t ic = i < n ? i : 0;
+        xs[t] = x[ic];
+        us[t] = u[ic];
+        bs[t] = b[ic];
+      }
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const int64_t i = (int64_t)threadIdx.x + kPT * (k0 + t);
+        vr[k0 + t] = 0.0;
+        if (i < n) {
+          vr[k0 + t] = xs[t] + us[t];
+          const bool pos = bs[t] > 0.0;
+          if (pos) sgn |= 1ull << (k0 + t);
+          brk(vr[k0 + t], pos);
+        }
       }
     }
   } else {
@@ -202,34 +232,57 @@ __global__ __launch_bounds__(kPT) void k_svm_project(int64_t n, const double* __
   }
   double lo = block_reduce<kMin, kPT / 64>(lo_l, sh);
   double hi = block_reduce<kMax, kPT / 64>(hi_l, sh);
-  double elo[5], ehi[5], emid[5];
-  phi_counts<VPT>(vr, sgn, x, u, b, n, C, lo, elo, sh);
-  phi_counts<VPT>(vr, sgn, x, u, b, n, C, hi, ehi, sh);
-  int steps = 0;
-  for (; steps < 200; ++steps) {
+  double elo[5], ehi[5], e[5 * kPM];
+  {
+    const double m0[kPM] = {lo, hi, hi};
+    phi_counts<VPT>(vr, sgn, x, u, b, n, C, m0, e, sh);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      elo[k] = e[k];
+      ehi[k] = e[5 + k];
+    }
+  }
+  const double nd = (double)n;
+  int passes = 1;
+  for (; passes < 200; ++passes) {
     if (elo[1] == ehi[1] && elo[2] == ehi[2] && elo[3] == ehi[3] && elo[4] == ehi[4]) break;
+    if (elo[0] == 0.0 || ehi[0] == 0.0) break;   // an end is a root
     const double mid = 0.5 * (lo + hi);
     if (!(mid > lo && mid < hi)) break;
-    phi_counts<VPT>(vr, sgn, x, u, b, n, C, mid, emid, sh);
-    if (emid[0] > 0.0) {
-      lo = mid;
+    double m[kPM];
+    const double flo = nd - (((elo[1] + elo[2]) + elo[3]) + elo[4]);
+    const double fhi = nd - (((ehi[1] + ehi[2]) + ehi[3]) + ehi[4]);
+    m[0] = flo > 0.0 ? lo + elo[0] / flo : mid;
+    m[1] = fhi > 0.0 ? hi + ehi[0] / fhi : mid;
+    m[2] = mid;
+    if (!(m[0] > lo && m[0] < hi)) m[0] = mid;
+    if (!(m[1] > lo && m[1] < hi)) m[1] = mid;
+    phi_counts<VPT>(vr, sgn, x, u, b, n, C, m, e, sh);
+    // lo = the largest point with phi > 0, hi = the smallest with phi <= 0
 #pragma unroll
-      for (int k = 0; k < 5; ++k) elo[k] = emid[k];
-    } else {
-      hi = mid;
+    for (int q = 0; q < kPM; ++q) {
+      if (e[5 * q] > 0.0) {
+        if (m[q] > lo) {
+          lo = m[q];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) ehi[k] = emid[k];
+          for (int k = 0; k < 5; ++k) elo[k] = e[5 * q + k];
+        }
+      } else if (m[q] < hi) {
+        hi = m[q];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ehi[k] = e[5 * q + k];
+      }
     }
   }
   const double flo = elo[0], fhi = ehi[0];
-  // phi is linear on the final bracket: one secant step
+  // phi is linear on the final bracket: one secant step (exact; an end that
+  // is a root is returned as it is)
   double mu = (flo == fhi) ? lo : lo + flo * (hi - lo) / (flo - fhi);
   mu = fmin(fmax(mu, lo), hi);
   double st[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t i = threadIdx.x; i < n; i += kPT) {
-    const double xi = x[i], ui = u[i], bi = b[i], zo = z[i];
-    const double zn = fmin(fmax(xi + ui - mu * bi, 0.0), C);
-    const double un = ui + xi - zn;
+  auto fin = [&](int64_t i, double v, double bi, double xi, double zo) {
+    const double zn = fmin(fmax(v - mu * bi, 0.0), C);
+    const double un = v - zn;            // u + x - z with v = x + u
     z[i] = zn;
     u[i] = un;
     st[0] = fma(xi - zn, xi - zn, st[0]);
@@ -238,13 +291,32 @@ __global__ __launch_bounds__(kPT) void k_svm_project(int64_t n, const double* __
     st[3] = fma(zn, zn, st[3]);
     st[4] = fma(un, un, st[4]);
     st[5] = fma(bi, zn, st[5]);
+  };
+  // eight entries per lane per trip, their loads issued together (in-bounds
+  // index 0 for lanes past the end); v = x + u again, as in the first pass
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * kPT) {
+    double xs[8], us[8], bs[8], zs[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t i = i0 + kPT * t;
+      const int64_t ic = i < n ? i : 0;
+      xs[t] = x[ic];
+      us[t] = u[ic];
+      bs[t] = b[ic];
+      zs[t] = z[ic];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t i = i0 + kPT * t;
+      if (i < n) fin(i, xs[t] + us[t], bs[t], xs[t], zs[t]);
+    }
   }
   block_sums<6, kPT / 64>(st, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) out[k] = st[k];
     out[6] = mu;
-    out[7] = steps;
+    out[7] = passes;
   }
 }
 

@@ -11,7 +11,9 @@ Parity contract:
     iteration count within 3% of the oracle's (about 160 iterations here);
   * svm_solve iterates within 1e-8 of the oracle's after the same iterations,
     the duality gap equal to the oracle's evaluation, and the dual objective
-    within 1e-6 of LIBSVM's at a converged run.
+    within 1e-6 of LIBSVM's at a converged run;
+  * the projection alone within 1e-12 of the oracle's, ties and roots on a
+    breakpoint included, u = v - z exactly.
 """
 import numpy as np
 import pytest
@@ -158,6 +160,50 @@ def test_svm_converges_to_libsvm_optimum(N, ctx):
           f"{d_sk:.10f}", flush=True)
     assert info.converged == 1
     assert abs(d_gpu - d_sk) <= 1e-6 * abs(d_sk)
+
+
+@pytest.mark.parametrize("n,labels,quant", [
+    (1, "mixed", 0), (7, "mixed", 8), (1000, "mixed", 8), (6000, "pos", 0), (6000, "neg", 4),
+    (20000, "mixed", 8), (20000, "mixed", 0), (40000, "mixed", 8)])
+def test_projection_matches_oracle(N, ctx, n, labels, quant):
+    """The z-update alone: with H = 0, rho = 1 and a cold x, the x-update is
+    x = z0 - u0 + 1 exactly, so v = x + u0 is set by the test; entries on a
+    grid of 1/quant put the root on a breakpoint and give ties.  Sizes cover
+    the three register layouts of the projection (n <= 8192, <= 32768,
+    larger), one entry, and labels of one sign (z = 0)."""
+    rng = np.random.default_rng(1000 + n + quant + len(labels))
+    Cb = 1.0
+    b = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    if labels == "pos":
+        b[:] = 1.0
+    elif labels == "neg":
+        b[:] = -1.0
+    z0 = rng.uniform(-1.5, 2.5, n)
+    u0 = rng.uniform(-1.0, 1.0, n)
+    if quant:
+        z0 = np.round(z0 * quant) / quant
+        u0 = np.round(u0 * quant) / quant
+    H = torch.zeros(n, n, dtype=torch.float32, device=DEV)
+    st = N.State(n, DEV)
+    st.z.copy_(torch.from_numpy(z0))
+    st.u.copy_(torch.from_numpy(u0))
+    bt = torch.from_numpy(b).to(DEV)
+    o = N.svm_opts(1.0, 0, pcg=N.pcg_opts(tol=1e-12), max_iter=1)
+    N.svm_solve(ctx, H, bt, Cb, o, st, allow=(N.NYS_OK, N.NYS_ERR_MAXITER))
+    x = st.x.cpu().numpy()
+    v = x + u0
+    zo, mu = osvm.project(v, b, Cb)
+    z = st.z.cpu().numpy()
+    u = st.u.cpu().numpy()
+    err = float(np.abs(z - zo).max())
+    print(f"[svm project] n={n} labels={labels} quant={quant} max |z - oracle| {err:.2e} "
+          f"b^T z {float(b @ z):.2e} mu {mu:.6f}", flush=True)
+    if quant:
+        assert np.array_equal(x, z0 - u0 + 1.0)
+    assert err <= 1e-12
+    assert np.array_equal(u, v - z)
+    assert z.min() >= 0.0 and z.max() <= Cb
+    assert abs(float(b @ z)) <= 1e-12 * max(1.0, float(np.abs(z).sum()))
 
 
 def test_svm_invalid_arguments(N, ctx):
