@@ -295,7 +295,8 @@ def bench_svm(args, N, synth, torch):
     dimensions, RBF kernel (gamma = 1/16), C = 1, rho = 10, rank 800, PCG tol
     1e-6, stopped at a relative duality gap of 1e-4 (the paper's SVM stop,
     checked every 10 iterations).  H = diag(b) K diag(b) is formed once (FP32,
-    1.6 GB, timed apart); a step = the factor built plus one solve to the gap
+    1.6 GB, timed apart); a step = the factor built (Y = H Omega with FP32
+    products, FP64 core) plus one solve to the gap
     from a cold start.  value = subproblem solves/s over the steps."""
     n, p, r, rho = 20000, 16, 800, 10.0
     X, b = synth.svm_points(n, p, seed=0, sep=1.5, device="cuda")
@@ -315,7 +316,7 @@ def bench_svm(args, N, synth, torch):
         t1 = time.perf_counter()
         for _ in range(k):
             ts = time.perf_counter()
-            F = N.nys_sketch_sym(ctx, H, omega)
+            F = N.nys_sketch_sym(ctx, H, omega, prec=N.NYS_F32)
             torch.cuda.synchronize()
             sk += time.perf_counter() - ts
             o = N.svm_opts(rho, r, pcg=N.pcg_opts(tol=1e-6), max_iter=1000, factor=F,
@@ -337,7 +338,7 @@ def bench_svm(args, N, synth, torch):
     out = base_record(tot / wall, args.steps, args.warmup, wall, "f32", {
         "workload": f"kernel-svm-dual-rbf-n{n}-p{p}-C1-rho{rho:g}-rank{r}-to-gap-1e-4",
         "n": n, "p": p, "gamma": 1.0 / p, "C": 1.0, "rho": rho, "rank": r, "pcg_tol": 1e-6,
-        "gap_tol": 1e-4, "true_res_every": args.true_res_every})
+        "gap_tol": 1e-4, "true_res_every": args.true_res_every, "sketch": "fp32 products, fp64 core"})
     out["roofline"] = roofline(prof, float(n) * n * 4, n, n)
     out["roofline"]["kernel"] = "k_rowdot (y = H p by column blocks, FP32 H, FP64 sums)"
     out["admm_iters_per_solve_to_gap"] = round(tot / args.steps, 1)
@@ -354,7 +355,7 @@ def bench_svm(args, N, synth, torch):
     # the factor built once and its time added to every point
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    F = N.nys_sketch_sym(ctx, H, omega)
+    F = N.nys_sketch_sym(ctx, H, omega, prec=N.NYS_F32)
     torch.cuda.synchronize()
     sk_s = time.perf_counter() - ts
     path = []

@@ -318,11 +318,15 @@ nys_status nys_kernel_rbf(nys_ctx ctx, const float* X, int64_t n, int64_t p, int
                           const double* b, double gamma, float* H, int64_t ldh);
 
 /* Algorithm RandNysAppx of the explicit symmetric PSD matrix H = K + c I
- * (K n x n, FP32 or FP64): Y = K Omega + c Omega with FP64 sums, then the FP64
- * core as in nys_sketch.  *F == NULL creates a factor, else appends r
- * columns.  omega: device FP64 n x r column-major Gaussian entries. */
+ * (K n x n, FP32 or FP64), then the FP64 core as in nys_sketch.
+ * prec NYS_F64: Y = K Omega + c Omega with FP64 sums; NYS_F32 (FP32 K only):
+ * Omega rounded to FP32 and K Omega by FP32 MFMA tiles with FP32 sums, the
+ * shift nu set for 23 mantissa bits and U kept in FP32 for the
+ * preconditioner, as in nys_sketch.  *F == NULL creates a factor, else
+ * appends r columns (same prec).  omega: device FP64 n x r column-major
+ * Gaussian entries. */
 nys_status nys_sketch_sym(nys_ctx ctx, const nys_dense* K, double c, const double* omega, int r,
-                          nys_factor* F);
+                          nys_dtype prec, nys_factor* F);
 
 /* Algorithm Nystrom PCG on (K + (c + rho) I) x = rhs for an explicit symmetric
  * K (n x n): one pass over K per iteration, in blocks of columns.  F from

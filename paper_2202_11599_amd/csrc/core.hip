@@ -432,7 +432,30 @@ __device__ __forceinline__ int pair_index(int a, int b, int i) {
 
 // A rotation is applied when |a_pq| > max(tol sqrt(|a_pp a_qq|), tol * trace(G)):
 // the relative test gives small eigenvalues their accuracy, the absolute floor
-// stops rotations that only chase the rounding of the tile updates.
+// stops rotations that only chase the rounding of the tile updates.  Compared
+// in squares (no square root).
+__device__ __forceinline__ bool jac_rotates(double apq, double app, double aqq, double floor_abs) {
+  return apq != 0.0 &&
+         apq * apq > fmax(kJacTol * kJacTol * fabs(app * aqq), floor_abs * floor_abs);
+}
+
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by
+// two Newton steps (y <- y (3 - x y^2) / 2, y <- y (2 - x y)), within a few
+// ulp: the rotation needs no correctly rounded result, and this chain is a
+// fraction of the length of the library's sqrt and division
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
 __global__ __launch_bounds__(kJS) void k_jacobi_solve(const double* __restrict__ G, int R,
                                                       int round, double* __restrict__ Qbuf,
                                                       int* __restrict__ counters, int sweep,
@@ -465,11 +488,22 @@ __global__ __launch_bounds__(kJS) void k_jacobi_solve(const double* __restrict__
       if (p > q) { const int t = p; p = q; q = t; }
       const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
       double c = 1.0, sn = 0.0;
-      if (fabs(apq) > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs) && apq != 0.0) {
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                      : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-        c = 1.0 / sqrt(1.0 + t * t);
+      if (jac_rotates(apq, app, aqq, floor_abs)) {
+        // t = tan of the angle that zeroes a_pq, the root of t^2 + 2 tau t - 1
+        // of smaller magnitude (tau = theta / a_pq, theta = (a_qq - a_pp) / 2):
+        // t = sign(theta) a_pq / (|theta| + sqrt(theta^2 + a_pq^2))
+        const double theta = 0.5 * (aqq - app);
+        const double h2 = fma(theta, theta, apq * apq);
+        double t;
+        if (h2 > 1e-280 && h2 < 1e280) {
+          const double h = h2 * rsq_nr(h2);
+          t = apq * rcp_nr(fabs(theta) + h);
+        } else {   // squares near the ends of the range: no squaring
+          const double tau = theta / apq;
+          t = copysign(1.0 / (fabs(tau) + sqrt(1.0 + tau * tau)), apq);
+        }
+        if (theta < 0.0) t = -t;
+        c = rsq_nr(fma(t, t, 1.0));
         sn = t * c;
         rotated = true;
       }
@@ -622,7 +656,7 @@ __global__ __launch_bounds__(256) void k_jacobi_check(const double* __restrict__
   const double floor_abs = kJacTol * (*gnorm);
   const double apq = fmin(fabs(G[e]), fabs(G[(int64_t)j * R + i]));
   const double app = G[(int64_t)i * R + i], aqq = G[(int64_t)j * R + j];
-  if (apq > fmax(kJacTol * sqrt(fabs(app * aqq)), floor_abs)) *flag = 1;
+  if (jac_rotates(apq, app, aqq, floor_abs)) *flag = 1;
 }
 
 // The check flag of sweep s, with the sequence number the host waits for, as

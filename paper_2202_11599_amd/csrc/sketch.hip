@@ -278,6 +278,15 @@ __global__ void k_sk2_reduce(const float* __restrict__ Yp, int S, int ncols, int
   Y[o] = s + coef * Om[o];
 }
 
+// Y(:, c) = T(:, c) + coef * Omega(:, c) in FP64, c < m (T: FP32, pitch ldt)
+__global__ void k_sym_y(const float* __restrict__ T, int64_t ldt, int d, int m,
+                        const double* __restrict__ Om, double coef, double* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)m * d) return;
+  const int c = (int)(e / d), j = (int)(e % d);
+  Y[e] = (double)T[(int64_t)c * ldt + j] + coef * Om[e];
+}
+
 // Round the FP64 Omega block to the sketch precision: the low-precision copy
 // (rows = columns, pitch ldo, zero padded to nrows_pad x ldo) and the FP64
 // value of the rounded entries written back into Omega.
@@ -442,9 +451,10 @@ nys_status nys_core(nys_ctx ctx, nys_factor F, double test_mu, int* above) {
   // Omega^T Omega
   NYS_TRY(gemm64(st, r, r, (int)d, Om, false, d, 1, Om, false, 1, d, w.GO, r, 1, 1.0, 0.0,
                  w.split, w.split_elems));
-  // base core matrix Omega^T Y (FP64 form) or the stored T^T D T + c Omega^T Omega
+  // base core matrix Omega^T Y (FP64 form; also for an explicit symmetric
+  // matrix) or the stored T^T D T + c Omega^T Omega
   const double* base;
-  if (F->prec == NYS_F64) {
+  if (F->prec == NYS_F64 || F->sym) {
     NYS_TRY(gemm64(st, r, r, (int)d, Om, false, d, 1, Y, false, 1, d, w.G, r, 1, 1.0, 0.0,
                    w.split, w.split_elems));
     base = w.G;
@@ -594,11 +604,30 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
     // sparse A: Y = A^T (D (A Omega)) + c Omega by two sparse-times-dense passes
     NYS_TRY(ctx->gemm_ws.reserve(sizeof(double) * (size_t)(n + 2 * d) * m + 256));
     NYS_TRY(sparse_sketch(SP, D, c, Om, m, Y + d * r0, ctx->gemm_ws.as<double>(), st));
-  } else if (F->sym) {
+  } else if (F->sym && F->prec == NYS_F64) {
     // explicit symmetric H = A + c I (kernel SVM): Y = A Omega + c Omega, FP64 sums
     NYS_TRY_HIP(hipMemcpyAsync(Y + d * r0, Om, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
     NYS_TRY(gemm64(st, (int)n, m, (int)d, A.data, a32, A.ld, 1, Om, false, 1, d, Y + d * r0, 1, d,
                    1.0, c, w.split, w.split_elems));
+  } else if (F->sym) {
+    // the same in FP32: Omega rounded to FP32 (the rounded values written
+    // back, so the core sees the Omega the products used), Y = A Omega by the
+    // FP32-MFMA tiles of the first sketch pass, then Y + c Omega in FP64
+    const int ldo = (int)((d + 31) / 32 * 32);
+    const int NB = m <= 64 ? 4 : (m <= 128 ? 8 : 16);
+    const int NP = 16 * NB;
+    const int npass = (m + NP - 1) / NP;
+    const int nrows_pad = npass * NP;
+    const int64_t ldt = (n + 7) / 8 * 8;
+    NYS_TRY(ctx->gemm_ws.reserve(align_up((size_t)nrows_pad * ldo * 4)));
+    void* Olp = ctx->gemm_ws.ptr;
+    hipLaunchKernelGGL(k_round_omega<false>, dim3(blocks((int64_t)nrows_pad * ldo)), dim3(256), 0,
+                       st, Om, (int)d, m, Olp, ldo, nrows_pad);
+    const int vec = (((uintptr_t)A.data % 16) == 0 && (A.ld % 4) == 0) ? 1 : 0;
+    float* T = F->T.as<float>();
+    NYS_TRY(launch_sk1<false>(NB, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+    hipLaunchKernelGGL(k_sym_y, dim3(blocks((int64_t)m * d)), dim3(256), 0, st, T + ldt * r0, ldt,
+                       (int)d, m, Om, c, Y + d * r0);
   } else if (F->prec == NYS_F64) {
     // T = A Omega (n x m, column-major) in FP64 tiles, Y = A^T (D o T) + c Omega
     NYS_TRY(ctx->gemm_ws.reserve(sizeof(double) * n * m + 256));
@@ -673,7 +702,7 @@ nys_status sketch_and_core(nys_ctx ctx, const nys_dense& A, const double* D, dou
                            const double* omega, int m, nys_factor F, double test_mu = -1.0,
                            int* above = nullptr) {
   NYS_TRY(sketch_block(ctx, A, D, c, omega, m, F));
-  if (F->prec != NYS_F64 && F->cap != F->r) {
+  if (F->prec != NYS_F64 && !F->sym && F->cap != F->r) {
     // compact Mbase (cap pitch) into core order (r pitch) in gemm_ws
     nys::DevBuf& Mb = F->Mbase;
     nys::DevBuf tmp;
@@ -704,7 +733,7 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
   if (r_old + r >= A->d || r_old + r > 1024) return NYS_ERR_INVALID;
   if (*F != nullptr && ((*F)->d != A->d || (*F)->prec != prec || (*F)->sym != sym))
     return NYS_ERR_INVALID;
-  if (sym && (D != nullptr || A->n != A->d || prec != NYS_F64 || A->dtype == NYS_CSR))
+  if (sym && (D != nullptr || A->n != A->d || prec == NYS_BF16 || A->dtype == NYS_CSR))
     return NYS_ERR_INVALID;
   if (A->dtype == NYS_CSR && prec != NYS_F64) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
@@ -741,8 +770,8 @@ nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c
 }
 
 nys_status nys_sketch_sym(nys_ctx ctx, const nys_dense* K, double c, const double* omega, int r,
-                          nys_factor* F) {
-  return sketch_round(ctx, K, nullptr, c, omega, r, NYS_F64, F, -1.0, nullptr, true);
+                          nys_dtype prec, nys_factor* F) {
+  return sketch_round(ctx, K, nullptr, c, omega, r, prec, F, -1.0, nullptr, true);
 }
 
 nys_status nys_sketch_adaptive(nys_ctx ctx, const nys_dense* A, const double* D, double c,

@@ -489,7 +489,7 @@ nys_status svm_solve(nys_ctx ctx, const nys_svm_problem* P, const nys_svm_opts* 
   info.gap = info.gap_rel = info.primal = info.dual = info.true_res_max = -1.0;
   nys_factor F = O->factor;
   const bool own = (F == nullptr && O->rank > 0);
-  if (own) NYS_TRY(nys_sketch_sym(ctx, &P->H, 0.0, O->omega, O->rank, &F));
+  if (own) NYS_TRY(nys_sketch_sym(ctx, &P->H, 0.0, O->omega, O->rank, NYS_F64, &F));
   info.rank = F ? F->r : 0;
   SvmWs ws;
   nys_status s = svm_workspace(ctx, n, &ws);

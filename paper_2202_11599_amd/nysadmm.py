@@ -140,7 +140,7 @@ def lib():
         "nys_ws_train_step": (i32, [vp, vp, vp, vp, vp, i32, dbl, P(dbl)]),
         "nys_ws_destroy": (i32, [vp]),
         "nys_kernel_rbf": (i32, [vp, vp, i64, i64, i64, vp, dbl, vp, i64]),
-        "nys_sketch_sym": (i32, [vp, P(Dense), dbl, vp, i32, P(vp)]),
+        "nys_sketch_sym": (i32, [vp, P(Dense), dbl, vp, i32, i32, P(vp)]),
         "pcg_solve_sym": (i32, [vp, P(Dense), dbl, dbl, vp, vp, vp, P(PcgOpts), P(PcgInfo)]),
         "svm_solve": (i32, [vp, P(SvmProblem), P(SvmOpts), P(AdmmState), P(SvmInfo)]),
         "nys_sparse_create": (i32, [vp, i64, i64, i64, vp, vp, vp, P(vp)]),
@@ -420,14 +420,15 @@ def kernel_rbf(ctx: Context, X: torch.Tensor, gamma: float, b: Optional[torch.Te
 
 
 def nys_sketch_sym(ctx: Context, K: torch.Tensor, omega_rows: torch.Tensor, c: float = 0.0,
-                   factor: Optional["Factor"] = None) -> "Factor":
-    """Algorithm RandNysAppx of the explicit symmetric K + c I (FP64 core)."""
+                   factor: Optional["Factor"] = None, prec: int = NYS_F64) -> "Factor":
+    """Algorithm RandNysAppx of the explicit symmetric K + c I (FP64 core;
+    K Omega in FP64, or in FP32 with prec=NYS_F32)."""
     dK = dense(K)
     r, d = omega_rows.shape
     _vec(omega_rows.reshape(-1), r * d, "omega")
     h = C.c_void_p(None if factor is None else factor.h.value)
-    _check(lib().nys_sketch_sym(ctx.h, C.byref(dK), float(c), _ptr(omega_rows), int(r), C.byref(h)),
-           "nys_sketch_sym")
+    _check(lib().nys_sketch_sym(ctx.h, C.byref(dK), float(c), _ptr(omega_rows), int(r), int(prec),
+                                C.byref(h)), "nys_sketch_sym")
     if factor is not None:
         factor.h = h
         return factor

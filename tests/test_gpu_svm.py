@@ -6,7 +6,8 @@ Parity contract:
     FP32 (relative 2^-23);
   * y = H p by column blocks (several blocks, a ragged last block, rows off
     the 16-byte grid) at 1e-12 relative to the FP64 product of the stored H;
-  * the Nystrom factor of the explicit H equal to the oracle's (1e-10);
+  * the Nystrom factor of the explicit H equal to the oracle's (1e-10), and
+    with FP32 products within 1e-5 of the oracle's (shift for 23 bits);
   * PCG on (H + rho I) x = rhs within kappa * tol of the dense solve and its
     iteration count within 3% of the oracle's (about 160 iterations here);
   * svm_solve iterates within 1e-8 of the oracle's after the same iterations,
@@ -112,6 +113,39 @@ def test_sketch_and_pcg_match_oracle(N, ctx):
     assert ex <= kap * 1e-10
     # CG over ~160 iterations drifts by rounding: the count agrees to 3%
     assert abs(info.iters - ora.iters) <= max(1, int(np.ceil(0.03 * ora.iters)))
+    F.close()
+
+
+def test_sketch_fp32_matches_oracle(N, ctx):
+    """FP32 products for Y = H Omega (Omega rounded to FP32): the factor within
+    FP32 rounding of the FP64 oracle's with the shift set for 23 mantissa bits,
+    the same shift, and PCG with the FP32 U taking the oracle's iterations."""
+    n, p, r, rho = 5000, 40, 60, 1e-2
+    X, b, gamma, _ = problem(n, p, 5)
+    H = N.kernel_rbf(ctx, X.to(DEV), gamma, b.to(DEV))
+    Hd = H.cpu().double().numpy()
+    om = synth.omega_raw(n, r, seed=6)
+    F = N.nys_sketch_sym(ctx, H, om.to(DEV), prec=N.NYS_F32)
+    f = osvm.nys_factor_of(Hd, om.numpy().T, mantissa_bits=23)
+    U = F.U(ctx).cpu().numpy().T
+    lam = np.array(F.info()["lam"])
+    e = np.linalg.norm((U * lam) @ U.T - f.dense()) / np.linalg.norm(f.dense())
+    print(f"[svm sketch fp32] rel(Hhat) {e:.2e} nu {F.info()['nu']:.3e}/{f.nu:.3e}", flush=True)
+    assert e < 1e-5 and F.info()["nu"] == f.nu
+    assert np.linalg.norm(U.T @ U - np.eye(r)) < 1e-8
+    rhs_np = np.random.default_rng(7).standard_normal(n)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = N.pcg_solve_sym(ctx, H, torch.tensor(rhs_np, device=DEV), x, rho, F,
+                           opts=N.pcg_opts(tol=1e-10))
+    ora = opcg.nys_pcg(lambda v: Hd @ v + rho * v, rhs_np, np.zeros(n),
+                       lambda w: precond_inverse_apply(f.U, f.lam, rho, w), 1e-10)
+    res = np.linalg.norm(Hd @ x.cpu().numpy() + rho * x.cpu().numpy() - rhs_np)
+    print(f"[svm pcg fp32 factor] iters {info.iters} oracle {ora.iters} rel res "
+          f"{res / np.linalg.norm(rhs_np):.2e}", flush=True)
+    assert res <= 1e-10 * np.linalg.norm(rhs_np) * 1.01
+    assert abs(info.iters - ora.iters) <= max(2, int(np.ceil(0.03 * ora.iters)))
+    with pytest.raises(N.NysError):   # one precision per factor
+        N.nys_sketch_sym(ctx, H, om.to(DEV), factor=F, prec=N.NYS_F64)
     F.close()
 
 
