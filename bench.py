@@ -92,6 +92,7 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, prof
     import torch
     infos = []
     ranks = []
+    step_rates = []
     sketch_s = 0.0
     bad = 0
     tr_max = -1.0
@@ -115,6 +116,8 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, prof
         tr_max = max(tr_max, info.true_res_max)
         bad += info.status != N.NYS_OK
         F.close()
+        torch.cuda.synchronize()
+        step_rates.append(info.iters / (time.perf_counter() - ts))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = ctx.profile_stop() if profile else None
@@ -122,7 +125,18 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, prof
     return dict(wall=wall, sketch_s=sketch_s, ranks=ranks,
                 pcg_mean=sum(i for i, _, _, _ in infos) / max(solves, 1),
                 pcg_max=max(m for _, _, m, _ in infos), solves=solves, unconverged=bad, prof=prof,
-                eta=infos[-1][3], true_res_max=tr_max)
+                eta=infos[-1][3], true_res_max=tr_max, step_rates=step_rates)
+
+
+def solve_roofline(run, launches, n, d):
+    r = run["ranks"][-1]
+    b_it = 4.0 * n * d + 2 * 4.0 * d * r + 12 * 8.0 * d
+    passes = launches / max(run["solves"], 1)
+    bound = PEAK_HBM_GBS * 1e9 / (passes * b_it)
+    meas = run["solves"] / (run["wall"] - run["sketch_s"])
+    return {"bytes_per_pcg_iteration": b_it, "pair_passes_per_solve": round(passes, 3),
+            "solves_per_s_bound": round(bound, 1), "solves_per_s_excl_sketch": round(meas, 3),
+            "frac": round(meas / bound, 4)}
 
 
 def cpu_baseline(A, b, omega, p, admm_iters, cpu_iters):
@@ -690,7 +704,13 @@ def main():
             "pcg_iters_mean": round(plain["pcg_mean"], 3), "pcg_iters_max": plain["pcg_max"],
             "unconverged_steps": plain["unconverged"], "kkt_eta_after_step": plain["eta"],
             "true_rel_res_max": plain["true_res_max"],
+            "per_step_solves_per_s": {"min": round(min(plain["step_rates"]), 3),
+                                      "max": round(max(plain["step_rates"]), 3)},
         },
+        # whole-solve roofline (sketch excluded): per PCG iteration the method
+        # must move A once (fused pair), U twice (FP32) and about 12 FP64
+        # d-vectors; the pair passes per solve are those the event timing saw
+        "solve_roofline": solve_roofline(plain, launches, args.n, args.d),
         "gemv_hbm_gbs": round(achieved, 1),
         "true_residual_every_solve": {
             "solves_per_s": round(strict["solves"] / strict["wall"], 3),

@@ -267,7 +267,8 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
 
 nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int mode,
                     const double* p, const double* aux, double* auxout, double* ypart,
-                    double* qpart, const int* done) {
+                    double* qpart, const int* done, PcgDev* note, int note_seq) {
+  if (note != nullptr && done == nullptr) return NYS_ERR_INVALID;
   if (plan.symv && (mode != kModeHess || aux != nullptr)) return NYS_ERR_INVALID;
   if (plan.sparse != nullptr) {
     const bool ev = ctx->prof_on;
@@ -279,13 +280,22 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
       }
     NYS_TRY(launch_sparse_pair(plan.sparse, plan, mode, p, aux, auxout, ypart, qpart, done,
                                ctx->stream, ev ? ctx->prof_ev[ctx->prof_used] : nullptr,
-                               ev ? ctx->prof_ev[ctx->prof_used + 1] : nullptr));
+                               ev ? ctx->prof_ev[ctx->prof_used + 1] : nullptr, note,
+                               note_seq));
     if (ev) ctx->prof_used += 2;
     return NYS_OK;
   }
-  if (!ctx->prof_on || plan.grid == 0 || A.n == 0)
-    return plan.symv ? launch_symv(A, plan, p, ypart, qpart, done, ctx->stream)
-                     : launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream);
+  if (plan.grid == 0 || A.n == 0) {
+    // nothing to launch: publish the state from a one-thread kernel instead
+    if (note != nullptr) NYS_TRY(launch_note(reinterpret_cast<const PcgDev*>(done), note, note_seq,
+                                             ctx->stream));
+    return NYS_OK;
+  }
+  if (!ctx->prof_on)
+    return plan.symv ? launch_symv(A, plan, p, ypart, qpart, done, ctx->stream, nullptr, nullptr,
+                                   note, note_seq)
+                     : launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream,
+                                   nullptr, nullptr, note, note_seq);
   if (ctx->prof_used + 2 > ctx->prof_ev.size()) {
     for (int i = 0; i < 2; ++i) {
       // timing-only events: no system-scope fence (cache writeback) at each
@@ -297,10 +307,11 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
   }
   if (plan.symv)
     NYS_TRY(launch_symv(A, plan, p, ypart, qpart, done, ctx->stream, ctx->prof_ev[ctx->prof_used],
-                        ctx->prof_ev[ctx->prof_used + 1]));
+                        ctx->prof_ev[ctx->prof_used + 1], note, note_seq));
   else
     NYS_TRY(launch_gram(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream,
-                        ctx->prof_ev[ctx->prof_used], ctx->prof_ev[ctx->prof_used + 1]));
+                        ctx->prof_ev[ctx->prof_used], ctx->prof_ev[ctx->prof_used + 1], note,
+                        note_seq));
   ctx->prof_used += 2;
   return NYS_OK;
 }
@@ -476,19 +487,26 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
     NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, 0,
                                   ws.wwpart, ws.nred, ws.pppart, ws.st, 1, st));
     // Iterations are enqueued `ahead` at a time beyond the last state the host
-    // has read: the last kernel of each iteration writes the device state with
-    // a sequence number into a pinned host slot, and the host waits only for
-    // the oldest iteration in flight, so the GPU never idles on a host round
-    // trip or an event marker.  Iterations queued after convergence return at
-    // once (every kernel checks PcgDev::done).
+    // has read: the state after each iteration reaches a pinned host slot with
+    // a sequence number (copied there by the first thread of the next
+    // iteration's matvec kernel, or by a one-thread kernel when no iteration
+    // follows), and the host waits only for the oldest iteration in flight, so
+    // the GPU never idles on a host round trip or an event marker.  Iterations
+    // queued after convergence return at once (every kernel checks
+    // PcgDev::done).
     const int limit = max_iter - total_iters;
     char* slots = static_cast<char*>(ctx->host_pinned) + kPollOffset;
     int seqs[4] = {0, 0, 0, 0};
+    auto slot_dev = [&](int k) {
+      return reinterpret_cast<PcgDev*>(static_cast<char*>(ctx->host_pinned_dev) + kPollOffset +
+                                       64 * (k % 4));
+    };
     // large d: p^T v and ||w||^2 summed once per iteration (their partial
     // counts grow with d) instead of by every workgroup of the vector kernels
     const bool pre = d > kPreReduceDim;
     auto enqueue = [&](int k) -> nys_status {
-      NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done));
+      NYS_TRY(ctx_gram(ctx, A, pl, kModeHess, ws.p, D, nullptr, ws.ypart, ws.qpart, &ws.st->done,
+                       k > 0 ? slot_dev(k - 1) : nullptr, k > 0 ? seqs[(k - 1) % 4] : 0));
       if (pre)
         NYS_TRY(launch_pcg_scalar(0, ws.qpart, pl.nq(), ws.pppart, ws.nvec, rho_eff, ws.st, st));
       NYS_TRY(launch_reduce_update(0, ws.ypart, pl.ny(), pl.ldy, ws.qpart, d, rho_eff, ws.p, x,
@@ -501,10 +519,8 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
       // earlier solve's queued iteration can never be taken for this one
       const int seq = ctx->poll_seq = (ctx->poll_seq % 1000000000) + 1;
       seqs[k % 4] = seq;
-      PcgDev* slot_dev = reinterpret_cast<PcgDev*>(static_cast<char*>(ctx->host_pinned_dev) +
-                                                   kPollOffset + 64 * (k % 4));
       NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, k,
-                                    ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st, slot_dev, seq,
+                                    ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st, nullptr, seq,
                                     pre));
       return NYS_OK;
     };
@@ -518,6 +534,9 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
         NYS_TRY(read_pcg_state(ctx, ws, &h));
         break;
       }
+      // no iteration follows the oldest one in flight: publish its state
+      if (it == consumed + 1)
+        NYS_TRY(launch_note(ws.st, slot_dev(consumed), seqs[consumed % 4], st));
       NYS_TRY(wait_slot(st, slots + 64 * (consumed % 4), seqs[consumed % 4], &h));
       ++consumed;
       if (h.done) break;

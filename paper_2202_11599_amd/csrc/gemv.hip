@@ -36,10 +36,11 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_gram(
     const T* __restrict__ A, int64_t n, int d, int64_t ld, int64_t rows_per_wg, int mode,
     const double* __restrict__ p, const double* __restrict__ aux, double* __restrict__ auxout,
     double* __restrict__ ypart, int ldy, double* __restrict__ qpart,
-    const int* __restrict__ done) {
+    const int* __restrict__ done, PcgDev* __restrict__ note, int note_seq) {
   constexpr int NT = WAVES * 64;
   constexpr int VN = Chunk<T>::N;
   typedef typename Chunk<T>::V V;
+  publish_state(done, note, note_seq);
   if (done != nullptr && *done) return;
 
   __shared__ double red[2][R][WAVES];
@@ -96,10 +97,12 @@ template <typename T, int WAVES, int CPL, int R, bool ALIGNED>
 __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_rowdot(
     const T* __restrict__ A, int64_t n, int64_t ncols, int64_t ld, int slice_cols,
     int64_t rows_per_wg, const double* __restrict__ p, double* __restrict__ ypart, int ldy,
-    double* __restrict__ qpart, const int* __restrict__ done) {
+    double* __restrict__ qpart, const int* __restrict__ done, PcgDev* __restrict__ note,
+    int note_seq) {
   constexpr int NT = WAVES * 64;
   constexpr int VN = Chunk<T>::N;
   typedef typename Chunk<T>::V V;
+  publish_state(done, note, note_seq);
   if (done != nullptr && *done) return;
   __shared__ double red[2][R][WAVES];
   const int tid = threadIdx.x;
@@ -137,26 +140,27 @@ __global__ __launch_bounds__(WAVES * 64, (WAVES >= 4 ? 2 : 1)) void k_rowdot(
 template <typename T, int WAVES, int CPL, int R>
 nys_status launch_r(const nys_dense& A, const GramPlan& pl, int mode, const double* p,
                     const double* aux, double* auxout, double* ypart, double* qpart,
-                    const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                    const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                    PcgDev* note, int note_seq) {
   const T* a = static_cast<const T*>(A.data);
   // with events, the dispatch itself stamps the kernel's start and end
   if (ev0 != nullptr) {
     if (pl.aligned)
       hipExtLaunchKernelGGL((k_gram<T, WAVES, CPL, R, true>), dim3(pl.grid), dim3(WAVES * 64), 0,
                             st, ev0, ev1, 0, a, A.n, (int)A.d, A.ld, pl.rows_per_wg, mode, p,
-                            aux, auxout, ypart, pl.ldy, qpart, done);
+                            aux, auxout, ypart, pl.ldy, qpart, done, note, note_seq);
     else
       hipExtLaunchKernelGGL((k_gram<T, WAVES, CPL, R, false>), dim3(pl.grid), dim3(WAVES * 64),
                             0, st, ev0, ev1, 0, a, A.n, (int)A.d, A.ld, pl.rows_per_wg, mode, p,
-                            aux, auxout, ypart, pl.ldy, qpart, done);
+                            aux, auxout, ypart, pl.ldy, qpart, done, note, note_seq);
   } else if (pl.aligned) {
     hipLaunchKernelGGL((k_gram<T, WAVES, CPL, R, true>), dim3(pl.grid), dim3(WAVES * 64), 0, st,
                        a, A.n, (int)A.d, A.ld, pl.rows_per_wg, mode, p, aux, auxout, ypart,
-                       pl.ldy, qpart, done);
+                       pl.ldy, qpart, done, note, note_seq);
   } else {
     hipLaunchKernelGGL((k_gram<T, WAVES, CPL, R, false>), dim3(pl.grid), dim3(WAVES * 64), 0, st,
                        a, A.n, (int)A.d, A.ld, pl.rows_per_wg, mode, p, aux, auxout, ypart,
-                       pl.ldy, qpart, done);
+                       pl.ldy, qpart, done, note, note_seq);
   }
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
@@ -164,10 +168,12 @@ nys_status launch_r(const nys_dense& A, const GramPlan& pl, int mode, const doub
 template <typename T>
 nys_status launch_dt(const nys_dense& A, const GramPlan& pl, int mode, const double* p,
                      const double* aux, double* auxout, double* ypart, double* qpart,
-                     const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                     const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                     PcgDev* note, int note_seq) {
 #define NYS_CASE(W, C, RR)                                                                  \
   if (pl.waves == W && pl.cpl == C && pl.rows == RR)                                        \
-    return launch_r<T, W, C, RR>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1);
+    return launch_r<T, W, C, RR>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1, \
+                                 note, note_seq);
   NYS_CASE(1, 2, 4) NYS_CASE(2, 2, 4) NYS_CASE(4, 2, 4) NYS_CASE(8, 2, 4)
   NYS_CASE(1, 2, 8) NYS_CASE(2, 2, 8) NYS_CASE(4, 2, 8) NYS_CASE(8, 2, 8)
   NYS_CASE(1, 3, 2) NYS_CASE(2, 3, 2) NYS_CASE(4, 3, 2) NYS_CASE(8, 3, 2)
@@ -303,7 +309,7 @@ GramPlan make_symv_plan(const nys_dense& A, int num_cu) {
 
 nys_status launch_symv(const nys_dense& A, const GramPlan& pl, const double* p, double* ypart,
                        double* qpart, const int* done, hipStream_t st, hipEvent_t ev0,
-                       hipEvent_t ev1) {
+                       hipEvent_t ev1, PcgDev* note, int note_seq) {
   if (!pl.symv || pl.waves != 4 || pl.cpl != 4 || pl.rows != 2) return NYS_ERR_INVALID;
   if (A.n != A.d) return NYS_ERR_INVALID;
   if (A.n == 0 || pl.grid == 0) return NYS_OK;
@@ -314,10 +320,11 @@ nys_status launch_symv(const nys_dense& A, const GramPlan& pl, const double* p, 
     if (ev0 != nullptr)                                                                        \
       hipExtLaunchKernelGGL((k_rowdot<T, 4, 4, 2, AL>), grid, dim3(256), 0, st, ev0, ev1, 0, a, \
                             A.n, A.d, A.ld, pl.slice_cols, pl.rows_per_wg, p, ypart, pl.ldy,   \
-                            qpart, done);                                                      \
+                            qpart, done, note, note_seq);                                      \
     else                                                                                       \
       hipLaunchKernelGGL((k_rowdot<T, 4, 4, 2, AL>), grid, dim3(256), 0, st, a, A.n, A.d,       \
-                         A.ld, pl.slice_cols, pl.rows_per_wg, p, ypart, pl.ldy, qpart, done);  \
+                         A.ld, pl.slice_cols, pl.rows_per_wg, p, ypart, pl.ldy, qpart, done,   \
+                         note, note_seq);                                                      \
   } while (0)
   if (A.dtype == NYS_F32) {
     if (pl.aligned) NYS_SYMV(float, true);
@@ -334,14 +341,17 @@ nys_status launch_symv(const nys_dense& A, const GramPlan& pl, const double* p, 
 
 nys_status launch_gram(const nys_dense& A, const GramPlan& pl, int mode, const double* p,
                        const double* aux, double* auxout, double* ypart, double* qpart,
-                       const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                       const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                       PcgDev* note, int note_seq) {
   const int vn = A.dtype == NYS_F64 ? 2 : 4;
   if ((int64_t)pl.waves * 64 * pl.cpl * vn < A.d) return NYS_ERR_INVALID;
   if (A.n == 0 || pl.grid == 0) return NYS_OK;
   if (A.dtype == NYS_F64)
-    return launch_dt<double>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1);
+    return launch_dt<double>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1, note,
+                             note_seq);
   if (A.dtype == NYS_F32)
-    return launch_dt<float>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1);
+    return launch_dt<float>(A, pl, mode, p, aux, auxout, ypart, qpart, done, st, ev0, ev1, note,
+                            note_seq);
   return NYS_ERR_INVALID;
 }
 

@@ -60,6 +60,22 @@ struct PcgDev {
   double wwn;    // ||w||^2 after the update (pre-reduced path)
 };
 static_assert(sizeof(PcgDev) <= 64, "PCG state must fit a 64-byte host slot");
+
+#ifdef __HIPCC__
+// The host learns that a PCG iteration has finished from a copy of the state
+// in pinned host memory.  The matvec kernel of the next iteration makes that
+// copy with its first thread, before it reads the state itself: a kernel that
+// writes host memory waits at its end for the write to land, which costs a
+// long kernel nothing but would stall the short kernels that end an
+// iteration.  done = &PcgDev::done (the first member).
+__device__ __forceinline__ void publish_state(const int* done, PcgDev* note, int seq) {
+  if (note != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    PcgDev h = *reinterpret_cast<const PcgDev*>(done);
+    h.k = seq;
+    *note = h;
+  }
+}
+#endif
 constexpr int kFlagBreakdown = 1;
 constexpr int kFlagNonfinite = 2;
 constexpr int kFlagZeroRhs = 4;
@@ -123,9 +139,12 @@ size_t align_up(size_t x);
 // NYSADMM_GRAM_PLAN forces a shape, NYSADMM_TUNE=0 uses the heuristic.
 nys_status ctx_gram_plan(nys_ctx ctx, const nys_dense& A, GramPlan* out);
 // launch_gram on the context's stream, timed when profiling is on
+// note (may be NULL): pinned host slot that the launch's first thread fills
+// with the PCG state *done belongs to (done = &PcgDev::done), sequence number
+// note_seq, before the kernel reads it (see publish_state)
 nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int mode,
                     const double* p, const double* aux, double* auxout, double* ypart,
-                    double* qpart, const int* done);
+                    double* qpart, const int* done, PcgDev* note = nullptr, int note_seq = 0);
 nys_status validate_dense(const nys_dense* A);
 nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws);
 nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out);
@@ -267,19 +286,21 @@ std::vector<GramPlan> gram_candidates(const nys_dense& A, int num_cu);
 nys_status launch_gram(const nys_dense& A, const GramPlan& plan, int mode, const double* p,
                        const double* aux, double* auxout, double* ypart, double* qpart,
                        const int* done, hipStream_t st,
-                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                       PcgDev* note = nullptr, int note_seq = 0);
 
 GramPlan make_symv_plan(const nys_dense& A, int num_cu);
 nys_status launch_symv(const nys_dense& A, const GramPlan& plan, const double* p, double* ypart,
                        double* qpart, const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
-                       hipEvent_t ev1 = nullptr);
+                       hipEvent_t ev1 = nullptr, PcgDev* note = nullptr, int note_seq = 0);
 
 // ---- sparse.hip
 GramPlan make_sparse_plan(const nys_sparse_s* S);
 nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& plan, int mode,
                               const double* p, const double* aux, double* auxout, double* ypart,
                               double* qpart, const int* done, hipStream_t st,
-                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                              PcgDev* note = nullptr, int note_seq = 0);
 // Y[:, 0:m] (column-major, ld d) = A^T (D (A Om)) + c Om for sparse A, FP64 sums;
 // Om column-major d x m.  ws holds (n + 2 d) m doubles.
 nys_status sparse_sketch(const nys_sparse_s* S, const double* D, double c, const double* Om, int m,
@@ -321,6 +342,9 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 bool pre = false,                  // alpha from st->pv
                                 int rj = 0);  // columns per workgroup (0: red_block(G)); the
                                               // ||w||^2 partials number nblk(d, rj)
+// *slot = *st with k = seq (one thread): publish_state for an iteration that
+// no matvec launch follows
+nys_status launch_note(const PcgDev* st, PcgDev* slot, int seq, hipStream_t stream);
 // st->pv = sum(a) + rho_eff sum(b) (op 0) or st->wwn = sum(a) (op 1), one
 // workgroup, fixed order; skipped once st->done is set
 nys_status launch_pcg_scalar(int op, const double* a, int na, const double* b, int nb,

@@ -137,7 +137,9 @@ __global__ __launch_bounds__(256) void k_csr_pass(const int* __restrict__ rowptr
                                                   double* __restrict__ auxout,
                                                   double* __restrict__ s,
                                                   double* __restrict__ qpart,
-                                                  const int* __restrict__ done) {
+                                                  const int* __restrict__ done,
+                                                  PcgDev* __restrict__ note, int note_seq) {
+  publish_state(done, note, note_seq);
   if (done != nullptr && *done) return;
   __shared__ double qs[4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -326,15 +328,18 @@ GramPlan make_sparse_plan(const nys_sparse_s* S) {
 nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& pl, int mode,
                               const double* p, const double* aux, double* auxout, double* ypart,
                               double* qpart, const int* done, hipStream_t st, hipEvent_t ev0,
-                              hipEvent_t ev1) {
+                              hipEvent_t ev1, PcgDev* note, int note_seq) {
   if (S == nullptr || pl.sparse != S) return NYS_ERR_INVALID;
   double* s = S->s.as<double>();
   if (ev0 != nullptr) NYS_TRY_HIP(hipEventRecord(ev0, st));
   if (S->n > 0)
     hipLaunchKernelGGL(k_csr_pass, dim3(pl.grid), dim3(256), 0, st, S->rowptr, S->colidx, S->val,
-                       S->n, mode, p, aux, auxout, s, qpart, done);
-  else
+                       S->n, mode, p, aux, auxout, s, qpart, done, note, note_seq);
+  else {
     NYS_TRY_HIP(hipMemsetAsync(qpart, 0, sizeof(double), st));
+    if (note != nullptr)
+      NYS_TRY(launch_note(reinterpret_cast<const PcgDev*>(done), note, note_seq, st));
+  }
   const int* lists = S->bins.as<int>();
   if (S->nshort > 0)
     hipLaunchKernelGGL(k_csc_short, dim3((unsigned)((S->nshort + 31) / 32)), dim3(256), 0, st,

@@ -339,6 +339,10 @@ __global__ __launch_bounds__(1024) void k_pcg_scalar(int op, const double* __res
   }
 }
 
+__global__ void k_note(const PcgDev* __restrict__ st, PcgDev* __restrict__ slot, int seq) {
+  publish_state(&st->done, slot, seq);
+}
+
 __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a,
                                              const double* __restrict__ b, int64_t d,
                                              double* __restrict__ out) {
@@ -440,6 +444,11 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                        wwpart, rrpart, st, Gq < 0 ? G : Gq, pre ? 1 : 0);
   else
     return NYS_ERR_INVALID;
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status launch_note(const PcgDev* st, PcgDev* slot, int seq, hipStream_t stream) {
+  hipLaunchKernelGGL(k_note, dim3(1), dim3(64), 0, stream, st, slot, seq);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 

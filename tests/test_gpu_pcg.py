@@ -231,3 +231,29 @@ def test_pcg_deterministic(N, ctx):
         N.pcg_solve(ctx, A, rhs, x, 1e-3, opts=N.pcg_opts(tol=1e-8))
         outs.append(x.cpu())
     assert torch.equal(outs[0], outs[1])
+
+
+def test_pcg_host_cadence_and_limits(N, ctx):
+    """The host learns of iteration k from the pinned slot that the matvec of
+    iteration k + 1 fills (or a one-thread kernel, when no iteration follows):
+    iterates, counts and status do not depend on how many iterations are in
+    flight (check_every 1..6) and at every iteration limit."""
+    A64 = synth.decay_matrix(3000, 300, 0.8, seed=21)
+    A = A64.to(torch.float32).to(DEV)
+    rhs = synth.gaussian((300,), seed=22).to(DEV)
+    for mi in (1, 2, 3, 7, 1000):
+        ref = None
+        for ce in (0, 1, 2, 3, 4, 6):
+            x = torch.zeros(300, dtype=torch.float64, device=DEV)
+            info = N.pcg_solve(ctx, A, rhs, x, 1e-3,
+                               opts=N.pcg_opts(tol=1e-10, max_iter=mi, check_every=ce),
+                               allow=(N.NYS_OK, N.NYS_ERR_MAXITER))
+            got = (info.iters, info.status, x.cpu())
+            if ref is None:
+                ref = got
+                print(f"[pcg cadence] max_iter {mi}: iters {info.iters} status {info.status}",
+                      flush=True)
+            else:
+                assert got[0] == ref[0] and got[1] == ref[1] and torch.equal(got[2], ref[2]), \
+                    (mi, ce)
+        assert ref[0] <= mi and (ref[1] == N.NYS_ERR_MAXITER) == (mi < 1000)
