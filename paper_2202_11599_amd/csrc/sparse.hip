@@ -127,6 +127,27 @@ __global__ __launch_bounds__(64) void k_tr_fill(const int* __restrict__ rowptr,
   }
 }
 
+// sum over k = k0, k0 + step, ... (below k1) of v[k] x[idx[k]]: four terms in
+// flight per lane (their index and value loads issued together, then the
+// four gathers), four running sums combined in a fixed order
+__device__ __forceinline__ double gather_dot(const int* __restrict__ idx,
+                                             const float* __restrict__ v,
+                                             const double* __restrict__ x, int64_t k0, int64_t k1,
+                                             int step) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t k = k0;
+  for (; k + 3 * step < k1; k += 4 * step) {
+    const int i0 = idx[k], i1 = idx[k + step], i2 = idx[k + 2 * step], i3 = idx[k + 3 * step];
+    const float v0 = v[k], v1 = v[k + step], v2 = v[k + 2 * step], v3 = v[k + 3 * step];
+    a0 = fma((double)v0, x[i0], a0);
+    a1 = fma((double)v1, x[i1], a1);
+    a2 = fma((double)v2, x[i2], a2);
+    a3 = fma((double)v3, x[i3], a3);
+  }
+  for (; k < k1; k += step) a0 = fma((double)v[k], x[idx[k]], a0);
+  return (a0 + a1) + (a2 + a3);
+}
+
 // Row pass: t_i = A_i p (one wavefront per row), s_i = f_mode(t_i) into s,
 // per-workgroup sum of the mode's q term into qpart.
 __global__ __launch_bounds__(256) void k_csr_pass(const int* __restrict__ rowptr,
@@ -147,9 +168,7 @@ __global__ __launch_bounds__(256) void k_csr_pass(const int* __restrict__ rowptr
   double q = 0.0;
   if (i < n) {
     double acc = 0.0;
-    if (mode != kModeTOnly)
-      for (int64_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += 64)
-        acc = fma((double)val[k], p[col[k]], acc);
+    if (mode != kModeTOnly) acc = gather_dot(col, val, p, rowptr[i] + lane, rowptr[i + 1], 64);
     const double t = wave_sum(acc);
     if (lane == 0) {
       double si = 0.0;
@@ -198,8 +217,7 @@ __global__ __launch_bounds__(256) void k_csc_short(const int* __restrict__ colpt
   int j = -1;
   if (g < cnt) {
     j = list[g];
-    for (int k = colptr[j] + sub; k < colptr[j + 1]; k += 8)
-      acc = fma((double)cval[k], s[rows[k]], acc);
+    acc = gather_dot(rows, cval, s, colptr[j] + sub, colptr[j + 1], 8);
   }
   acc += __shfl_xor(acc, 4, 8);
   acc += __shfl_xor(acc, 2, 8);
@@ -219,9 +237,7 @@ __global__ __launch_bounds__(256) void k_csc_wave(const int* __restrict__ colptr
   const int g = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
   if (g >= cnt) return;
   const int j = list[g];
-  double acc = 0.0;
-  for (int k = colptr[j] + lane; k < colptr[j + 1]; k += 64)
-    acc = fma((double)cval[k], s[rows[k]], acc);
+  double acc = gather_dot(rows, cval, s, colptr[j] + lane, colptr[j + 1], 64);
   acc = wave_sum(acc);
   if (lane == 0) y[j] = acc;
 }
@@ -236,9 +252,7 @@ __global__ __launch_bounds__(256) void k_csc_block(const int* __restrict__ colpt
   if (done != nullptr && *done) return;
   __shared__ double red[4];
   const int j = list[blockIdx.x];
-  double acc = 0.0;
-  for (int k = colptr[j] + threadIdx.x; k < colptr[j + 1]; k += 256)
-    acc = fma((double)cval[k], s[rows[k]], acc);
+  double acc = gather_dot(rows, cval, s, colptr[j] + threadIdx.x, colptr[j + 1], 256);
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -265,6 +279,56 @@ __global__ void k_rm_to_cm(const double* __restrict__ rm, int64_t d, int m, doub
 
 // T = D (A Om) row by row (row-major n x m): one wavefront per row, each lane
 // owning columns lane, lane + 64, ... of a 256-column chunk (blockIdx.y).
+// acc[h] = sum over k0 <= k < k1 of v[k] B[idx[k] * m + c0 + 64 h] (h < NH,
+// columns below m; lanes past m load column 0 and add zero): four nonzeros in
+// flight per lane with no branch around the loads, four running sums per
+// column combined in a fixed order
+template <int NH>
+__device__ __forceinline__ void spmm_acc(const int* __restrict__ idx, const float* __restrict__ v,
+                                         const double* __restrict__ B, int64_t k0, int64_t k1,
+                                         int m, int c0, double (&acc)[4]) {
+  int cc[NH];
+  bool ok[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    ok[h] = c0 + 64 * h < m;
+    cc[h] = ok[h] ? c0 + 64 * h : 0;
+  }
+  double a[4][NH];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int h = 0; h < NH; ++h) a[u][h] = 0.0;
+  int64_t k = k0;
+  for (; k + 3 < k1; k += 4) {
+    double bv[4][NH];
+    float vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      vv[u] = v[k + u];
+      const double* b = B + (int64_t)idx[k + u] * m;
+#pragma unroll
+      for (int h = 0; h < NH; ++h) bv[u][h] = b[cc[h]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int h = 0; h < NH; ++h) a[u][h] = fma((double)vv[u], ok[h] ? bv[u][h] : 0.0, a[u][h]);
+  }
+  for (; k < k1; ++k) {
+    const double vv = v[k];
+    const double* b = B + (int64_t)idx[k] * m;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) a[0][h] = fma(vv, ok[h] ? b[cc[h]] : 0.0, a[0][h]);
+  }
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+    acc[h] = h < NH ? (a[0][h < NH ? h : 0] + a[1][h < NH ? h : 0]) +
+                          (a[2][h < NH ? h : 0] + a[3][h < NH ? h : 0])
+                    : 0.0;
+}
+
+template <int NH>
 __global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rowptr,
                                                   const int* __restrict__ col,
                                                   const float* __restrict__ val, int64_t n,
@@ -275,14 +339,8 @@ __global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rowptr
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
   const int c0 = blockIdx.y * 256 + lane;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const double v = val[k];
-    const double* b = B + (int64_t)col[k] * m;
-#pragma unroll
-    for (int h = 0; h < 4; ++h)
-      if (c0 + 64 * h < m) acc[h] = fma(v, b[c0 + 64 * h], acc[h]);
-  }
+  double acc[4];
+  spmm_acc<NH>(col, val, B, rowptr[i], rowptr[i + 1], m, c0, acc);
   const double di = D != nullptr ? D[i] : 1.0;
 #pragma unroll
   for (int h = 0; h < 4; ++h)
@@ -290,6 +348,7 @@ __global__ __launch_bounds__(256) void k_csr_spmm(const int* __restrict__ rowptr
 }
 
 // Yrm = A^T T column by column (row-major d x m), the same layout of lanes
+template <int NH>
 __global__ __launch_bounds__(256) void k_csc_spmm(const int* __restrict__ colptr,
                                                   const int* __restrict__ rows,
                                                   const float* __restrict__ cval, int64_t d,
@@ -299,14 +358,8 @@ __global__ __launch_bounds__(256) void k_csc_spmm(const int* __restrict__ colptr
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= d) return;
   const int c0 = blockIdx.y * 256 + lane;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t k = colptr[j]; k < colptr[j + 1]; ++k) {
-    const double v = cval[k];
-    const double* t = T + (int64_t)rows[k] * m;
-#pragma unroll
-    for (int h = 0; h < 4; ++h)
-      if (c0 + 64 * h < m) acc[h] = fma(v, t[c0 + 64 * h], acc[h]);
-  }
+  double acc[4];
+  spmm_acc<NH>(rows, cval, T, colptr[j], colptr[j + 1], m, c0, acc);
 #pragma unroll
   for (int h = 0; h < 4; ++h)
     if (c0 + 64 * h < m) Y[j * m + c0 + 64 * h] = acc[h];
@@ -362,11 +415,22 @@ nys_status sparse_sketch(const nys_sparse_s* S, const double* D, double c, const
   double* Yrm = T + n * m;           // d x m
   const unsigned cchunks = (unsigned)((m + 255) / 256);
   hipLaunchKernelGGL(k_cm_to_rm, dim3(nb256(d * m)), dim3(256), 0, st, Om, d, m, Orm);
-  if (n > 0)
-    hipLaunchKernelGGL(k_csr_spmm, dim3((unsigned)((n + 3) / 4), cchunks), dim3(256), 0, st,
-                       S->rowptr, S->colidx, S->val, n, m, Orm, D, T);
-  hipLaunchKernelGGL(k_csc_spmm, dim3((unsigned)((d + 3) / 4), cchunks), dim3(256), 0, st,
-                     S->colptr(), S->rows(), S->cvals(), d, m, T, Yrm);
+  // column blocks of 64 per lane group actually used (one 256-column chunk
+  // per blockIdx.y; NH = 4 once m exceeds 192)
+  const int nh = m >= 256 ? 4 : (m + 63) / 64;
+#define NYS_SPMM(NH)                                                                           \
+  do {                                                                                         \
+    if (n > 0)                                                                                 \
+      hipLaunchKernelGGL(k_csr_spmm<NH>, dim3((unsigned)((n + 3) / 4), cchunks), dim3(256), 0,  \
+                         st, S->rowptr, S->colidx, S->val, n, m, Orm, D, T);                   \
+    hipLaunchKernelGGL(k_csc_spmm<NH>, dim3((unsigned)((d + 3) / 4), cchunks), dim3(256), 0,    \
+                       st, S->colptr(), S->rows(), S->cvals(), d, m, T, Yrm);                  \
+  } while (0)
+  if (nh == 1) NYS_SPMM(1);
+  else if (nh == 2) NYS_SPMM(2);
+  else if (nh == 3) NYS_SPMM(3);
+  else NYS_SPMM(4);
+#undef NYS_SPMM
   hipLaunchKernelGGL(k_rm_to_cm, dim3(nb256(d * m)), dim3(256), 0, st, Yrm, d, m, c, Om, Y);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }

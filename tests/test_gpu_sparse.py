@@ -62,8 +62,9 @@ def test_sparse_pair_matches_oracle(N, ctx, n, d, dens):
     S.close()
 
 
-def test_sparse_sketch_matches_oracle(N, ctx):
-    n, d, r = 1500, 3000, 60
+@pytest.mark.parametrize("r", [60, 130, 300])   # 1, 3 and 4 column groups per lane, 2 chunks
+def test_sparse_sketch_matches_oracle(N, ctx, r):
+    n, d = 1500, 3000
     S, A = make(N, ctx, n, d, 0.01, seed=5)
     om = synth.omega_raw(d, r, seed=6)
     F = N.nys_sketch(ctx, S, om.to(DEV), prec=N.NYS_F64)
@@ -71,7 +72,7 @@ def test_sparse_sketch_matches_oracle(N, ctx):
     U = F.U(ctx).cpu().numpy().T
     lam = np.array(F.info()["lam"])
     e = np.linalg.norm((U * lam) @ U.T - f.dense()) / np.linalg.norm(f.dense())
-    print(f"[sparse sketch] rel(Hhat) {e:.2e} nu {F.info()['nu']:.3e}/{f.nu:.3e}", flush=True)
+    print(f"[sparse sketch] r={r} rel(Hhat) {e:.2e} nu {F.info()['nu']:.3e}/{f.nu:.3e}", flush=True)
     assert e < 1e-10 and F.info()["nu"] == f.nu
     with pytest.raises(N.NysError):      # the sparse sketch is FP64 only
         N.nys_sketch(ctx, S, om.to(DEV), prec=N.NYS_F32)
