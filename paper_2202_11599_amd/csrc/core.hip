@@ -95,6 +95,61 @@ __global__ __launch_bounds__(256) void k_split_reduce(int M, int N, int S,
   *c = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * *c);
 }
 
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by
+// two Newton steps (y <- y (3 - x y^2) / 2, y <- y (2 - x y)), within a few
+// ulp: the rotation needs no correctly rounded result, and this chain is a
+// fraction of the length of the library's sqrt and division
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
+// pivot of a Cholesky step: sqrt(d) and 1/sqrt(d) (d > 0); the Newton-refined
+// estimate for normal d, the library's square root and division otherwise
+__device__ __forceinline__ void chol_pivot(double dii, double* piv, double* rinv) {
+  if (dii > 1e-280 && dii < 1e280) {
+    *rinv = rsq_nr(dii);
+    *piv = dii * *rinv;
+  } else {
+    *piv = sqrt(fabs(dii));
+    *rinv = 1.0 / *piv;
+  }
+}
+
+// P <- C^-T P for the upper-triangular b x b block C (rdiag = 1 / diag(C)),
+// P b x nc, right-looking: at step i every thread of column c forms
+// x = P[i][c] / C[i][i] and its row group (NT / WC groups) takes x C[i][j]
+// off the rows j > i it owns; one barrier per step.  The finished row i is
+// stored one step later (nobody reads it then), by row group 0.
+template <int CB, int WC, int NT>
+__device__ __forceinline__ void right_looking_solve(double (&C)[CB][CB + 1],
+                                                    double (&P)[CB][WC + 1],
+                                                    const double* rdiag, int b, int nc, int tid) {
+  constexpr int NG = NT / WC;
+  const int c = tid % WC, jr = tid / WC;
+  double prev = 0.0;
+  for (int i = 0; i < b; ++i) {
+    double x = 0.0;
+    if (c < nc) {
+      x = P[i][c] * rdiag[i];
+      if (jr == 0 && i > 0) P[i - 1][c] = prev;
+      for (int j = i + 1 + jr; j < b; j += NG) P[j][c] = fma(-C[i][j], x, P[j][c]);
+    }
+    prev = x;
+    __syncthreads();
+  }
+  if (c < nc && jr == 0 && b > 0) P[b - 1][c] = prev;
+}
+
 // Upper Cholesky factor C (C^T C = M) in place, row-major with leading
 // dimension ld, lower triangle set to zero; only the upper triangle of M is
 // read.  One workgroup of 1024 threads, right-looking by blocks of kCB rows:
@@ -110,6 +165,7 @@ __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int
   __shared__ double C[kCB][kCB + 1];
   __shared__ double P[kCB][kCW + 1];
   __shared__ double rowv[kCB];
+  __shared__ double rdiag[kCB];
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
@@ -123,20 +179,21 @@ __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int
     }
     __syncthreads();
     // diagonal block: row i of the factor, then the update of the block below it
+    // thread (p, q) = (tid / kCB, tid % kCB) of the b x b block (b <= kCB)
+    const int tp = tid / kCB, tq = tid % kCB;
     for (int i = 0; i < b; ++i) {
       if (tid >= i && tid < b) {
         const double dii = C[i][i];
         if (tid == i && (!(dii > 0.0) || !isfinite(dii))) bad = 1;
-        const double piv = sqrt(fabs(dii));
-        rowv[tid] = (tid == i) ? piv : C[i][tid] / piv;
+        double piv, rinv;
+        chol_pivot(dii, &piv, &rinv);
+        rowv[tid] = (tid == i) ? piv : C[i][tid] * rinv;
+        if (tid == i) rdiag[i] = rinv;
       }
       __syncthreads();
       if (bad) break;
       if (tid >= i && tid < b) C[i][tid] = rowv[tid];
-      for (int e = tid; e < b * b; e += 1024) {
-        const int p = e / b, q = e % b;
-        if (p > i && q >= p) C[p][q] -= rowv[p] * rowv[q];
-      }
+      if (tp < b && tq < b && tp > i && tq >= tp) C[tp][tq] -= rowv[tp] * rowv[tq];
       __syncthreads();
     }
     if (bad) break;
@@ -154,13 +211,7 @@ __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int
         P[i][jj] = M[(int64_t)(kb + i) * ld + kb + b + c0 + jj];
       }
       __syncthreads();
-      if (tid < nc) {
-        for (int i = 0; i < b; ++i) {
-          double sacc = P[i][tid];
-          for (int l = 0; l < i; ++l) sacc = fma(-C[l][i], P[l][tid], sacc);
-          P[i][tid] = sacc / C[i][i];
-        }
-      }
+      right_looking_solve<kCB, kCW, 1024>(C, P, rdiag, b, nc, tid);
       __syncthreads();
       for (int e = tid; e < b * nc; e += 1024) {
         const int i = e / nc, jj = e % nc;
@@ -219,19 +270,23 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int l
     C[i][j] = (j >= i) ? M[(int64_t)(kb + i) * ld + kb + j] : 0.0;
   }
   __syncthreads();
+  // thread column q = tid % kLB, rows p = tid / kLB + 4 k of the b x b block
+  const int tq = tid % kLB;
   for (int i = 0; i < b; ++i) {
     if (tid >= i && tid < b) {
       const double dii = C[i][i];
       if (tid == i && (!(dii > 0.0) || !isfinite(dii))) bad = 1;
-      const double piv = sqrt(fabs(dii));
-      rowv[tid] = (tid == i) ? piv : C[i][tid] / piv;
+      double piv, rinv;
+      chol_pivot(dii, &piv, &rinv);
+      rowv[tid] = (tid == i) ? piv : C[i][tid] * rinv;
     }
     __syncthreads();
     if (bad) break;
     if (tid >= i && tid < b) C[i][tid] = rowv[tid];
-    for (int e = tid; e < b * b; e += 256) {
-      const int pp = e / b, q = e % b;
-      if (pp > i && q >= pp) C[pp][q] -= rowv[pp] * rowv[q];
+    if (tq < b) {
+      const double rq = rowv[tq];
+      for (int pp = tid / kLB; pp <= tq; pp += 256 / kLB)
+        if (pp > i) C[pp][tq] -= rowv[pp] * rq;
     }
     __syncthreads();
   }
@@ -251,6 +306,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int 
                                                     int nrest, int* __restrict__ fail) {
   __shared__ double C[kLB][kLB + 1];
   __shared__ double P[kLB][kLB + 1];
+  __shared__ double rdiag[kLB];
   if (*fail) return;
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * kLB;
@@ -264,13 +320,9 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ M, int 
     P[i][jj] = M[(int64_t)(kb + i) * ld + kb + b + c0 + jj];
   }
   __syncthreads();
-  if (tid < nc) {
-    for (int i = 0; i < b; ++i) {
-      double sacc = P[i][tid];
-      for (int l = 0; l < i; ++l) sacc = fma(-C[l][i], P[l][tid], sacc);
-      P[i][tid] = sacc / C[i][i];
-    }
-  }
+  if (tid < b) rdiag[tid] = 1.0 / C[tid][tid];
+  __syncthreads();
+  right_looking_solve<kLB, kLB, 256>(C, P, rdiag, b, nc, tid);
   __syncthreads();
   for (int e = tid; e < b * nc; e += 256) {
     const int i = e / nc, jj = e % nc;
@@ -439,23 +491,6 @@ __device__ __forceinline__ bool jac_rotates(double apq, double app, double aqq, 
          apq * apq > fmax(kJacTol * kJacTol * fabs(app * aqq), floor_abs * floor_abs);
 }
 
-// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by
-// two Newton steps (y <- y (3 - x y^2) / 2, y <- y (2 - x y)), within a few
-// ulp: the rotation needs no correctly rounded result, and this chain is a
-// fraction of the length of the library's sqrt and division
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = fma(y, fma(-x, y, 1.0), y);
-  y = fma(y, fma(-x, y, 1.0), y);
-  return y;
-}
 __global__ __launch_bounds__(kJS) void k_jacobi_solve(const double* __restrict__ G, int R,
                                                       int round, double* __restrict__ Qbuf,
                                                       int* __restrict__ counters, int sweep,

@@ -70,20 +70,20 @@ __global__ __launch_bounds__(256) void k_reduce_update(
   const int grp = tid / RJ;
   const int64_t j = (int64_t)blockIdx.x * RJ + lane;
 
-  // four independent running sums (rows g, g+S, g+2S, g+3S, ...) keep
-  // several loads in flight; combined in a fixed order
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  // eight independent running sums (rows g, g+S, ..., g+7S, ...) keep eight
+  // loads in flight per lane; combined in a fixed order
+  double a[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) a[t] = 0.0;
   if (j < d) {
     int g = grp;
-    for (; g + 3 * S < G; g += 4 * S) {
-      a0 += ypart[(int64_t)g * ldy + j];
-      a1 += ypart[(int64_t)(g + S) * ldy + j];
-      a2 += ypart[(int64_t)(g + 2 * S) * ldy + j];
-      a3 += ypart[(int64_t)(g + 3 * S) * ldy + j];
+    for (; g + 7 * S < G; g += 8 * S) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) a[t] += ypart[(int64_t)(g + t * S) * ldy + j];
     }
-    for (; g < G; g += S) a0 += ypart[(int64_t)g * ldy + j];
+    for (; g < G; g += S) a[0] += ypart[(int64_t)g * ldy + j];
   }
-  part[grp][lane] = (a0 + a1) + (a2 + a3);
+  part[grp][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 
   double alpha = 0.0;
   if (op == 0) {
