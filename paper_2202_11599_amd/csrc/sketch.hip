@@ -78,32 +78,65 @@ __global__ __launch_bounds__(256) void k_sk1(const float* __restrict__ A, int64_
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = (f4)0.0f;
 
-  for (int k0 = 0; k0 < d; k0 += kBK) {
-    // stage the Omega tile (NP columns x 32 k) in LDS
-    if (BF) {
-      const __bf16* O = static_cast<const __bf16*>(Olp);
-      __bf16* Os = reinterpret_cast<__bf16*>(smem);
-      for (int e = tid; e < NP * 4; e += 256) {   // 16-byte chunks
+  // The next step's Omega tile and A rows are loaded into registers while the
+  // current step's MFMAs run (the loads are issued before them), then stored
+  // to LDS after the barrier that ends the step.
+  constexpr int OC = BF ? NP * 4 / 256 : NP * 8 / 256;   // 16-byte Omega chunks per thread
+  static_assert(OC >= 1 && (BF ? NP * 4 : NP * 8) % 256 == 0, "whole chunks per thread");
+  f8 afn[2];
+  // 16-byte Omega chunks of this thread, held as separate values (an array
+  // of them would be placed in scratch memory)
+  uint4 ob0, ob1, ob2, ob3, ob4, ob5, ob6, ob7;
+  auto chunk = [&](int c) __attribute__((always_inline)) -> uint4& {
+    return c == 0 ? ob0 : c == 1 ? ob1 : c == 2 ? ob2 : c == 3 ? ob3
+         : c == 4 ? ob4 : c == 5 ? ob5 : c == 6 ? ob6 : ob7;
+  };
+  static_assert(OC <= 8, "at most eight chunks per thread");
+  auto load_omega = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < OC; ++c) {
+      const int e = tid + 256 * c;
+      if (BF) {
         const int nn = e >> 2, kk = (e & 3) * 8;
-        const uint4 v = *reinterpret_cast<const uint4*>(O + (int64_t)(n0 + nn) * ldo + k0 + kk);
-        *reinterpret_cast<uint4*>(Os + nn * kOPad + kk) = v;
-      }
-    } else {
-      const float* O = static_cast<const float*>(Olp);
-      float* Os = reinterpret_cast<float*>(smem);
-      for (int e = tid; e < NP * 8; e += 256) {
+        chunk(c) = *reinterpret_cast<const uint4*>(static_cast<const __bf16*>(Olp) +
+                                                   (int64_t)(n0 + nn) * ldo + k0 + kk);
+      } else {
         const int nn = e >> 3, kk = (e & 7) * 4;
-        const f4 v = *reinterpret_cast<const f4*>(O + (int64_t)(n0 + nn) * ldo + k0 + kk);
-        *reinterpret_cast<f4*>(Os + nn * kOPad + kk) = v;
+        chunk(c) = *reinterpret_cast<const uint4*>(static_cast<const float*>(Olp) +
+                                                   (int64_t)(n0 + nn) * ldo + k0 + kk);
       }
     }
-    __syncthreads();
-    f8 af[2];
+  };
+  auto store_omega = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < OC; ++c) {
+      const int e = tid + 256 * c;
+      if (BF) {
+        const int nn = e >> 2, kk = (e & 3) * 8;
+        *reinterpret_cast<uint4*>(reinterpret_cast<__bf16*>(smem) + nn * kOPad + kk) = chunk(c);
+      } else {
+        const int nn = e >> 3, kk = (e & 7) * 4;
+        *reinterpret_cast<uint4*>(reinterpret_cast<float*>(smem) + nn * kOPad + kk) = chunk(c);
+      }
+    }
+  };
+  auto load_a = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
       const int64_t row = m0 + 16 * mb + m;
       const int kk = k0 + 8 * q;
-      af[mb] = (row < n) ? load8(A + row * ld + kk, d - kk, vec) : (f8)0.0f;
+      afn[mb] = (row < n) ? load8(A + row * ld + kk, d - kk, vec) : (f8)0.0f;
+    }
+  };
+  load_omega(0);
+  load_a(0);
+  for (int k0 = 0; k0 < d; k0 += kBK) {
+    store_omega();
+    __syncthreads();
+    f8 af[2] = {afn[0], afn[1]};
+    if (k0 + kBK < d) {
+      load_omega(k0 + kBK);
+      load_a(k0 + kBK);
     }
     if (BF) {
       const bf16x8 a0 = to_bf16(af[0]), a1 = to_bf16(af[1]);
@@ -166,55 +199,71 @@ __global__ __launch_bounds__(256) void k_sk2(const float* __restrict__ A, int64_
 #pragma unroll
     for (int t = 0; t < NBW; ++t) acc[mb][t] = (f4)0.0f;
 
-  for (int64_t i0 = i_beg; i0 < i_end; i0 += kBK) {
-    // A tile rows i0..i0+31, columns j0..j0+127 -> LDS as [j][i]
-    {
-      const int kk = tid >> 3;            // row within the tile
-      const int jc = (tid & 7) * 16;      // 16 columns
-      const int64_t i = i0 + kk;
-      float vals[16];
-      if (i < i_end) {
-        const float* src = A + i * ld + j0 + jc;
-        const int valid = d - (j0 + jc);
-        const f8 x0 = load8(src, valid, vec);
-        const f8 x1 = load8(src + 8, valid - 8, vec);
+  // The next step's A tile and B fragments are loaded into registers while
+  // the current step's MFMAs run, and the A tile is stored to LDS (transposed)
+  // after the barrier that ends the step.
+  float vals[16];
+  f8 bfn[NBW];
+  const int kk_t = tid >> 3;            // row within the tile
+  const int jc_t = (tid & 7) * 16;      // 16 columns
+  auto load_tile = [&](int64_t i0) __attribute__((always_inline)) {
+    const int64_t i = i0 + kk_t;
+    if (i < i_end) {
+      const float* src = A + i * ld + j0 + jc_t;
+      const int valid = d - (j0 + jc_t);
+      const f8 x0 = load8(src, valid, vec);
+      const f8 x1 = load8(src + 8, valid - 8, vec);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          vals[v] = x0[v];
-          vals[v + 8] = x1[v];
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) vals[v] = 0.0f;
+      for (int v = 0; v < 8; ++v) {
+        vals[v] = x0[v];
+        vals[v + 8] = x1[v];
       }
-      if (BF) {
-        __bf16* As = reinterpret_cast<__bf16*>(smem);
+    } else {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) As[(jc + v) * kOPad + kk] = (__bf16)vals[v];
-      } else {
-        float* As = reinterpret_cast<float*>(smem);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) As[(jc + v) * kOPad + kk] = vals[v];
-      }
+      for (int v = 0; v < 16; ++v) vals[v] = 0.0f;
     }
+  };
+  auto store_tile = [&]() __attribute__((always_inline)) {
+    if (BF) {
+      __bf16* As = reinterpret_cast<__bf16*>(smem);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) As[(jc_t + v) * kOPad + kk_t] = (__bf16)vals[v];
+    } else {
+      float* As = reinterpret_cast<float*>(smem);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) As[(jc_t + v) * kOPad + kk_t] = vals[v];
+    }
+  };
+  // B fragments: (D o T)[i0 + 8q .. +7][c], c = 16 nb + m
+  auto load_b = [&](int64_t i0) __attribute__((always_inline)) {
+    const int64_t ib = i0 + 8 * q;
+    const int valid = (int)((i_end - ib) < 8 ? (i_end - ib) : 8);
+    f8 dv;
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+      dv[v] = (D != nullptr && v < valid) ? (float)D[ib + v] : 1.0f;
+#pragma unroll
+    for (int t = 0; t < NBW; ++t) {
+      const int c = (wv + 4 * t) * 16 + m;
+      f8 x = (c < ncols && valid > 0) ? load8(T + (int64_t)(col0 + c) * ldt + ib, valid, true)
+                                      : (f8)0.0f;
+      if (D != nullptr) x = x * dv;
+      bfn[t] = x;
+    }
+  };
+  if (i_beg < i_end) {
+    load_tile(i_beg);
+    load_b(i_beg);
+  }
+  for (int64_t i0 = i_beg; i0 < i_end; i0 += kBK) {
+    store_tile();
     __syncthreads();
-    // B fragments: (D o T)[i0 + 8q .. +7][c], c = 16 nb + m
     f8 bfr[NBW];
-    {
-      const int64_t ib = i0 + 8 * q;
-      const int valid = (int)((i_end - ib) < 8 ? (i_end - ib) : 8);
-      f8 dv;
 #pragma unroll
-      for (int v = 0; v < 8; ++v)
-        dv[v] = (D != nullptr && v < valid) ? (float)D[ib + v] : 1.0f;
-#pragma unroll
-      for (int t = 0; t < NBW; ++t) {
-        const int c = (wv + 4 * t) * 16 + m;
-        f8 x = (c < ncols && valid > 0) ? load8(T + (int64_t)(col0 + c) * ldt + ib, valid, true)
-                                        : (f8)0.0f;
-        if (D != nullptr) x = x * dv;
-        bfr[t] = x;
-      }
+    for (int t = 0; t < NBW; ++t) bfr[t] = bfn[t];
+    if (i0 + kBK < i_end) {
+      load_tile(i0 + kBK);
+      load_b(i0 + kBK);
     }
     if (BF) {
       const __bf16* As = reinterpret_cast<const __bf16*>(smem);
