@@ -253,7 +253,7 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
     D = w.Dw;
     if (O.rank > 0 && (*F == nullptr || (O.resketch_every > 0 && S->k % O.resketch_every == 0))) {
       nys_factor nf = nullptr;
-      NYS_TRY(nys_sketch(ctx, &A, D, P.c, O.omega, O.rank, O.sketch_prec, &nf));
+      NYS_TRY(sketch_rebuild(ctx, &A, D, P.c, O.omega, O.rank, O.sketch_prec, *F, &nf));
       if (*F != nullptr) nys_factor_destroy(*F);
       *F = nf;
     }

@@ -718,6 +718,14 @@ __global__ void k_eye(double* __restrict__ V, int R) {
   if (e < (int64_t)R * R) V[e] = (e / R == e % R) ? 1.0 : 0.0;
 }
 
+// V (R x R row-major) = the column-major r x r basis B0, identity on the padding
+__global__ void k_pad_basis(const double* __restrict__ B0, int r, double* __restrict__ V, int R) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)R * R) return;
+  const int k = (int)(e / R), c = (int)(e % R);
+  V[e] = (k < r && c < r) ? B0[(int64_t)c * r + k] : (k == c ? 1.0 : 0.0);
+}
+
 // Pad the r x r matrix (ld) into an R x R zero-padded matrix.
 __global__ void k_pad(const double* __restrict__ A, int r, int ld, double* __restrict__ P, int R) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -869,7 +877,7 @@ nys_status wait_jacobi_slot(hipStream_t st, const volatile unsigned long long* s
 
 nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws, int* counters,
                       int max_sweeps, void* host_pinned, void* host_pinned_dev, int* poll_seq,
-                      double* sig2, double* W, int ldw, int* sweeps_out) {
+                      double* sig2, double* W, int ldw, int* sweeps_out, const double* V0) {
   const int R = jacobi_pad(r);
   const int nb = R / kJB;
   const int np = nb / 2;
@@ -884,7 +892,11 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
   if (max_sweeps < 1 || max_sweeps > 60) return NYS_ERR_INVALID;
   hipLaunchKernelGGL(k_pad, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, G, r, ld, G0, R);
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, st, G0, R, gnorm);
-  hipLaunchKernelGGL(k_eye, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, V, R);
+  if (V0 != nullptr)
+    hipLaunchKernelGGL(k_pad_basis, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, V0, r,
+                       V, R);
+  else
+    hipLaunchKernelGGL(k_eye, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st, V, R);
   if (hipMemsetAsync(counters, 0, sizeof(int) * 128, st) != hipSuccess) return NYS_ERR_HIP;
   // Sweeps are enqueued one ahead of the host's reading of their check flag
   // (written by the device into pinned memory), so the GPU does not idle on a

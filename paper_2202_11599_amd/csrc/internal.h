@@ -167,9 +167,18 @@ nys_status trinv_upper(hipStream_t st, const double* Cm, int r, int ld, double* 
 nys_status power_iter(hipStream_t st, const double* G, int r, int ld, int iters, double* out);
 int jacobi_pad(int r);
 size_t jacobi_ws_doubles(int r);
+// V0 (may be NULL): r x r column-major orthonormal start basis (the
+// eigenvectors come out as V0 times the accumulated rotations); identity if NULL
+// ---- sketch.hip
+// A fresh factor of rank r (as nys_sketch) whose eigensolver starts from the
+// projection of prev's U when prev has the same rank and dimension.
+nys_status sketch_rebuild(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                          const double* omega, int r, nys_dtype prec, nys_factor prev,
+                          nys_factor* F);
 nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws, int* counters,
                       int max_sweeps, void* host_pinned, void* host_pinned_dev, int* poll_seq,
-                      double* sig2, double* W, int ldw, int* sweeps_out);
+                      double* sig2, double* W, int ldw, int* sweeps_out,
+                      const double* V0 = nullptr);
 // Stop when ||w|| <= max(abs_tol, tol ||rhs||) (o.tol_abs: ||w|| <= o.tol).
 // hx_tag >= 0: H_rho x saved by the previous run's true-residual pass gives w0
 // without a pass over A when that run had the same (A, D, x pointer, c, rho)
@@ -271,6 +280,9 @@ struct nys_factor_s {
   std::vector<double> lam_host;
   bool use_u32 = false;
   bool sym = false;          // factor of an explicit symmetric H = K + c I (kernel SVM)
+  // non-owning, set only while a rebuild runs: the previous factor's U (d x r
+  // FP64), whose projection starts the eigensolver near its answer
+  const double* basis_hint = nullptr;
 };
 
 namespace nys {

@@ -18,6 +18,8 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <cstdio>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -327,6 +329,30 @@ __global__ void k_sk2_reduce(const float* __restrict__ Yp, int S, int ncols, int
   Y[o] = s + coef * Om[o];
 }
 
+// *out = max over i, j of |G(i, j) - [i == j]| for the r x r row-major G
+// (one workgroup; NaN propagates as a failure)
+__global__ __launch_bounds__(1024) void k_orth_err(const double* __restrict__ G, int r,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[16];
+  double m = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)r * r; e += 1024) {
+    const int64_t i = e / r, j = e % r;
+    const double v = fabs(G[e] - (i == j ? 1.0 : 0.0));
+    m = (v > m || v != v) ? v : m;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = (o > m || o != o) ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int k = 1; k < 16; ++k) t = (sh[k] > t || sh[k] != sh[k]) ? sh[k] : t;
+    *out = t;
+  }
+}
+
 // Y(:, c) = T(:, c) + coef * Omega(:, c) in FP64, c < m (T: FP32, pitch ldt)
 __global__ void k_sym_y(const float* __restrict__ T, int64_t ldt, int d, int m,
                         const double* __restrict__ Om, double coef, double* __restrict__ Y) {
@@ -459,8 +485,11 @@ double eps_of(double x, int mbits) {
 
 // Thin QR of the Gaussian block by CholeskyQR2 (two passes of Gram ->
 // Cholesky -> Q = X R^-1), in place on Om (d x m, column-major).
-nys_status orthonormalize(nys_ctx ctx, double* Om, int64_t d, int m, const CoreWs& w) {
+// tmp: d x m scratch (w.Bm when NULL)
+nys_status orthonormalize(nys_ctx ctx, double* Om, int64_t d, int m, const CoreWs& w,
+                          double* tmp = nullptr) {
   hipStream_t st = ctx->stream;
+  if (tmp == nullptr) tmp = w.Bm;
   for (int pass = 0; pass < 2; ++pass) {
     NYS_TRY(gemm64(st, m, m, (int)d, Om, false, d, 1, Om, false, 1, d, w.M, m, 1, 1.0, 0.0,
                    w.split, w.split_elems));
@@ -471,9 +500,9 @@ nys_status orthonormalize(nys_ctx ctx, double* Om, int64_t d, int m, const CoreW
     if (fail) return NYS_ERR_NOT_SPD;   // Gaussian block without full column rank
     NYS_TRY(trinv_upper(st, w.M, m, m, w.Cinv, m));
     // Bm = Om Rinv  (d x m col-major), then copy back
-    NYS_TRY(gemm64(st, (int)d, m, m, Om, false, 1, d, w.Cinv, false, m, 1, w.Bm, 1, d, 1.0, 0.0,
+    NYS_TRY(gemm64(st, (int)d, m, m, Om, false, 1, d, w.Cinv, false, m, 1, tmp, 1, d, 1.0, 0.0,
                    w.split, w.split_elems));
-    NYS_TRY_HIP(hipMemcpyAsync(Om, w.Bm, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
+    NYS_TRY_HIP(hipMemcpyAsync(Om, tmp, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
   }
   return NYS_OK;
 }
@@ -550,8 +579,47 @@ nys_status nys_core(nys_ctx ctx, nys_factor F, double test_mu, int* above) {
     }
   }
   int sweeps = 0;
-  NYS_TRY(jacobi_eig(st, w.G, r, r, w.jac, w.ints + 16, 40, ctx->host_pinned,
-                     ctx->host_pinned_dev, &ctx->poll_seq, w.sig2, w.W, r, &sweeps));
+  // Rebuild with the previous factor's U at hand: V0 = orthonormalised
+  // B^T U_prev spans nearly the eigenvectors of G when the operator moved
+  // little (the logistic weights between refreshes), so the eigensolver
+  // starts from G' = V0^T G V0, nearly diagonal, and needs a few sweeps
+  // instead of about ten.  The result is G's eigendecomposition either way;
+  // if V0 is not of full rank the solver starts from the identity.
+  const double* V0 = nullptr;
+  const double* Gj = w.G;
+  if (F->basis_hint != nullptr) {
+    double* Vb = w.GO;   // r x r column-major (free after the shifted Cholesky)
+    NYS_TRY(gemm64(st, r, r, (int)d, w.Bm, false, d, 1, F->basis_hint, false, 1, d, Vb, 1, r,
+                   1.0, 0.0, w.split, w.split_elems));
+    nys_status so = orthonormalize(ctx, Vb, r, r, w, w.W);
+    if (so == NYS_OK) {
+      // CholeskyQR2 is exact to rounding only for a well-conditioned V0:
+      // accept the basis when max |V0^T V0 - I| <= 1e-13 r
+      NYS_TRY(gemm64(st, r, r, r, Vb, false, r, 1, Vb, false, 1, r, w.GY, r, 1, 1.0, 0.0,
+                     w.split, w.split_elems));
+      hipLaunchKernelGGL(k_orth_err, dim3(1), dim3(1024), 0, st, w.GY, r, w.scal + 8);
+      double err = 0.0;
+      NYS_TRY(read_back(ctx, w.scal + 8, sizeof(double), &err));
+      if (!(err <= 1e-13 * r)) so = NYS_ERR_NOT_SPD;
+    }
+    if (so == NYS_OK) {
+      // G' = V0^T (G V0): T1 (column-major) in GY, G' (row-major) in M
+      NYS_TRY(gemm64(st, r, r, r, w.G, false, r, 1, Vb, false, 1, r, w.GY, 1, r, 1.0, 0.0,
+                     w.split, w.split_elems));
+      NYS_TRY(gemm64(st, r, r, r, Vb, false, r, 1, w.GY, false, 1, r, w.M, r, 1, 1.0, 0.0,
+                     w.split, w.split_elems));
+      V0 = Vb;
+      Gj = w.M;
+    } else if (so != NYS_ERR_NOT_SPD) {
+      return so;
+    }
+  }
+  NYS_TRY(jacobi_eig(st, Gj, r, r, w.jac, w.ints + 16, 40, ctx->host_pinned,
+                     ctx->host_pinned_dev, &ctx->poll_seq, w.sig2, w.W, r, &sweeps, V0));
+  if (getenv("NYSADMM_VERBOSE"))
+    fprintf(stderr, "[nysadmm] eigensolver r=%d sweeps=%d start=%s\n", r, sweeps,
+            V0 != nullptr ? "previous-basis" : (F->basis_hint != nullptr ? "identity-fallback"
+                                                                          : "identity"));
   // U = B V Sigma^-1
   NYS_TRY(F->U.reserve(sizeof(double) * d * r));
   NYS_TRY(gemm64(st, (int)d, r, r, w.Bm, false, 1, d, w.W, false, r, 1, F->U.as<double>(), 1, d,
@@ -771,7 +839,8 @@ nys_status sketch_and_core(nys_ctx ctx, const nys_dense& A, const double* D, dou
 // One round of the sketch: extend *F by m columns and rebuild its core.
 nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double c,
                         const double* omega, int r, nys_dtype prec, nys_factor* F,
-                        double test_mu, int* above, bool sym = false) {
+                        double test_mu, int* above, bool sym = false,
+                        const double* basis_hint = nullptr) {
   if (ctx == nullptr || F == nullptr || omega == nullptr) return NYS_ERR_INVALID;
   NYS_TRY(validate_dense(A));
   if (!(c >= 0.0) || r < 1) return NYS_ERR_INVALID;
@@ -798,13 +867,26 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
     f->mantissa_bits = (prec == NYS_F64) ? 52 : 23;
     created = true;
   }
+  f->basis_hint = (basis_hint != nullptr && r_old == 0) ? basis_hint : nullptr;
   nys_status s = sketch_and_core(ctx, *A, D, c, omega, r, f, test_mu, above);
+  f->basis_hint = nullptr;
   if (s != NYS_OK) {
     if (created) nys_factor_destroy(f);
     return s;
   }
   *F = f;
   return NYS_OK;
+}
+
+// Rebuild of a factor with the previous one's U as the eigensolver's start
+// basis (same rank and dimension); otherwise as a fresh nys_sketch.
+nys_status sketch_rebuild(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                          const double* omega, int r, nys_dtype prec, nys_factor prev,
+                          nys_factor* F) {
+  const bool hint = prev != nullptr && prev->r == r && prev->d == A->d && !prev->sym &&
+                    prev->lam_host.size() == (size_t)r;
+  return sketch_round(ctx, A, D, c, omega, r, prec, F, -1.0, nullptr, false,
+                      hint ? prev->U.as<double>() : nullptr);
 }
 
 }  // namespace nys

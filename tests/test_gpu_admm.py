@@ -170,6 +170,32 @@ def test_logistic_parity(N, ctx):
     assert abs(info.obj - ad.logistic_objective(A, b, p.gamma, z)) <= 1e-10 * abs(info.obj)
 
 
+def test_logistic_refresh_starts_eigensolver_from_previous_basis(N, ctx, capfd, monkeypatch):
+    """Refreshing the factor (every 10 iterations, new weights D) starts the
+    eigensolver from the previous factor's basis projected on the new sketch:
+    the rebuilt factors need fewer sweeps than the first one, and the run
+    equals the oracle's (whose eigendecompositions start from scratch)."""
+    monkeypatch.setenv("NYSADMM_VERBOSE", "1")
+    p = synth.logistic_decay(6000, 200, seed=4, dtype=torch.float64, rho=5.0, rank=30,
+                             gamma_per_row=2e-3, pcg_tol=1e-10)
+    A, b = p.A.numpy(), p.b.numpy()
+    its = 40
+    ora = ad.admm_logistic(A, b, p.gamma, p.rho, omega_raw=p.omega.numpy().T, iters=its,
+                           pcg_tol=1e-10, resketch_every=10)
+    capfd.readouterr()
+    st, info = run_solve(N, ctx, p, p.A.to(DEV), p.b.to(DEV), 30, max_iter=its, resketch_every=10)
+    err = capfd.readouterr().err
+    runs = [ln for ln in err.splitlines() if ln.startswith("[nysadmm] eigensolver r=30 ")]
+    sweeps = [int(ln.split("sweeps=")[1].split()[0]) for ln in runs]
+    starts = [ln.split("start=")[1] for ln in runs]
+    print(f"[refresh] sweeps {sweeps} starts {starts}", flush=True)
+    assert len(runs) == 4 and starts[0] == "identity"
+    assert all(s == "previous-basis" for s in starts[1:])
+    assert max(sweeps[1:]) < sweeps[0]
+    z = st.z.cpu().numpy()
+    assert np.linalg.norm(z - ora.z) / np.linalg.norm(ora.z) < 1e-7
+
+
 def test_logistic_optimum_and_rel_change_stop(N, ctx):
     p = synth.logistic_decay(4000, 100, seed=6, dtype=torch.float64, rho=2.0, rank=20,
                              gamma_per_row=3e-3, pcg_tol=1e-10)
