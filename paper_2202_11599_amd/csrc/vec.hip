@@ -278,7 +278,17 @@ __global__ __launch_bounds__(256) void k_precond_update(
       for (int t = 0; t < 8; ++t)
         a[t] = fma((double)u[(int64_t)(i + t * VS) * d], g[i + t * VS], a[t]);
     }
-    for (; i < r; i += VS) a[0] = fma((double)u[(int64_t)i * d], g[i], a[0]);
+    // the (fewer than eight) remaining terms, their loads issued together:
+    // an index past r reads row r - 1 and adds nothing
+    if (i < r) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int it = i + t * VS;
+        const int ic = it < r ? it : r - 1;
+        const double v = fma((double)u[(int64_t)ic * d], g[ic], a[t]);
+        a[t] = it < r ? v : a[t];
+      }
+    }
     part = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   ys[sl][jl] = part;
