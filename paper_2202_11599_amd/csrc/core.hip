@@ -82,17 +82,41 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, int kchunk,
     }
 }
 
+// C = alpha * sum_z ws[z] + beta C over the S split-K partials.  A workgroup
+// covers 16 outputs with 16 groups of lanes; group g adds the partials
+// z = g, g + 16, ... with eight loads in flight, the groups are combined in
+// LDS in a fixed order (for few outputs S is large: up to 1024).
+constexpr int kSrOut = 16;
 __global__ __launch_bounds__(256) void k_split_reduce(int M, int N, int S,
                                                       const double* __restrict__ ws,
                                                       double* __restrict__ C, int64_t scm,
                                                       int64_t scn, double alpha, double beta) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)M * N) return;
-  const int m = (int)(idx / N), n = (int)(idx % N);
-  double s = 0.0;
-  for (int z = 0; z < S; ++z) s += ws[(int64_t)z * M * N + idx];
-  double* c = C + (int64_t)m * scm + (int64_t)n * scn;
-  *c = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * *c);
+  constexpr int G = 256 / kSrOut;
+  __shared__ double part[G][kSrOut];
+  const int o = threadIdx.x % kSrOut, g = threadIdx.x / kSrOut;
+  const int64_t idx = (int64_t)blockIdx.x * kSrOut + o;
+  const int64_t tot = (int64_t)M * N;
+  double a[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) a[t] = 0.0;
+  if (idx < tot) {
+    int z = g;
+    for (; z + 7 * G < S; z += 8 * G) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) a[t] += ws[(int64_t)(z + t * G) * tot + idx];
+    }
+    for (; z < S; z += G) a[0] += ws[(int64_t)z * tot + idx];
+  }
+  part[g][o] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  __syncthreads();
+  if (g == 0 && idx < tot) {
+    double s = 0.0;
+#pragma unroll
+    for (int h = 0; h < G; ++h) s += part[h][o];
+    const int m = (int)(idx / N), n = (int)(idx % N);
+    double* c = C + (int64_t)m * scm + (int64_t)n * scn;
+    *c = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * *c);
+  }
 }
 
 // 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by
@@ -793,8 +817,8 @@ nys_status gemm64(hipStream_t st, int M, int N, int K, const void* A, bool a_f32
   if (hipGetLastError() != hipSuccess) return NYS_ERR_HIP;
   if (S > 1) {
     const int64_t tot = (int64_t)M * N;
-    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
-                       S, split_ws, C, scm, scn, alpha, beta);
+    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((tot + kSrOut - 1) / kSrOut)), dim3(256), 0,
+                       st, M, N, S, split_ws, C, scm, scn, alpha, beta);
     if (hipGetLastError() != hipSuccess) return NYS_ERR_HIP;
   }
   return NYS_OK;
