@@ -529,6 +529,7 @@ __global__ __launch_bounds__(kJS) void k_jacobi_solve(const double* __restrict__
   const int nb = R / kJB;
   int a, b;
   rr_pair(nb, round, blockIdx.x, &a, &b);
+  #pragma unroll   // constant trip count: the loads issue together
   for (int e = tid; e < kJP * kJP; e += kJS) {
     const int i = e / kJP, j = e % kJP;
     S[i][j] = G[(int64_t)pair_index(a, b, i) * R + pair_index(a, b, j)];
@@ -614,6 +615,7 @@ __global__ __launch_bounds__(kJS) void k_jacobi_solve(const double* __restrict__
     __syncthreads();
   }
   double* Qo = Qbuf + (int64_t)blockIdx.x * kJP * kJP;
+  #pragma unroll   // constant trip count: the loads issue together
   for (int e = tid; e < kJP * kJP; e += kJS) Qo[e] = Q[e / kJP][e % kJP];
   // only the first kJB threads (all in the first wavefront) compute rotations
   if (__any(rotated) && tid == 0) atomicAdd(&counters[sweep], 1);
@@ -641,6 +643,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__
     rr_pair(nb, round, Qi, &qa, &qb);
     const double* QP = Qbuf + (int64_t)P * kJP * kJP;
     const double* QQ = Qbuf + (int64_t)Qi * kJP * kJP;
+    #pragma unroll   // constant trip count: the loads issue together
     for (int e = tid; e < kJP * kJP; e += kJT) {
       const int i = e / kJP, j = e % kJP;
       T[i][j] = Gin[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)];
@@ -680,6 +683,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__
     int pa, pb;
     rr_pair(nb, round, P, &pa, &pb);
     const double* QP = Qbuf + (int64_t)P * kJP * kJP;
+    #pragma unroll   // constant trip count: the loads issue together
     for (int e = tid; e < kJP * kJP; e += kJT) {
       const int i = e / kJP, j = e % kJP;
       T[i][j] = V[(int64_t)(rc * kJP + i) * R + pair_index(pa, pb, j)];
