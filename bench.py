@@ -3,7 +3,7 @@
 
 Workload: lasso, A 100000 x 4000 FP32 with singular values j^-0.8 (random
 orthogonal factors), x* 2% sparse, b = A x* + 0.01 noise,
-gamma = 0.1 ||A^T b||_inf, rho = 1e-4, adaptive Nystrom rank 50 -> 800 with
+gamma = 0.01 ||A^T b||_inf, rho = 1e-4, adaptive Nystrom rank 50 -> 800 with
 Tol = 2, subproblem tolerance 1e-6 (relative residual, FP64-accumulated true
 residual checked), PCG warm-started at the previous x.
 
@@ -15,7 +15,9 @@ steps, the sketch cost included (amortised over the step's solves).
 
 Also reported: the same steps with the BF16-MFMA sketch ("mixed"), the
 matvec-pair kernel's achieved HBM bandwidth measured with HIP events around
-every launch in the timed region, and the FP64 CPU oracle timed on a bounded
+every launch in the timed region (with the HBM bytes from the committed
+rocprofv3 counter record when it was taken on the current kernel source), the
+whole-solve roofline fraction, and the FP64 CPU oracle timed on a bounded
 sample on this host (cpu_baseline).
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
