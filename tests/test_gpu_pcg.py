@@ -136,6 +136,25 @@ def test_precond_apply_parity(N, ctx):
     F.close()
 
 
+@pytest.mark.parametrize("d,r", [(7, 1), (100, 9), (4097, 17), (4096, 64), (40000, 65),
+                                 (150000, 50), (20000, 800)])
+def test_precond_apply_shapes(N, ctx, d, r):
+    """P^-1 w for an imported factor (random orthonormal U, descending
+    Lambda) across dimensions and ranks: slice counts of U^T w from 8 to 37,
+    ranks that leave each lane fewer than eight terms, r up to 800."""
+    rng = np.random.default_rng(d + r)
+    U, _ = np.linalg.qr(rng.standard_normal((d, r)))
+    lam = np.sort(rng.uniform(0.0, 10.0, r))[::-1].copy()
+    F = N.nys_factor_import(ctx, torch.from_numpy(U.T.copy()).to(DEV), lam, 1e-12)
+    w = rng.standard_normal(d)
+    y = N.nys_precond_apply(ctx, F, 0.5, torch.from_numpy(w).to(DEV)).cpu().numpy()
+    ref = ny.precond_inverse_apply(U, lam, 0.5, w)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    print(f"[precond] d={d} r={r} rel err {err:.2e}", flush=True)
+    assert err <= 1e-13
+    F.close()
+
+
 def test_pcg_c1_first_subproblem(N, ctx):
     # The lasso 2000 x 500 workload's first x-subproblem: rhs = A^T b
     # (z = u = 0), rho = 1, rank-50 factor, tol 1e-10 (FP64).
