@@ -415,8 +415,18 @@ __global__ __launch_bounds__(256) void k_trinv_upper(const double* __restrict__ 
   const double zkk = 1.0 / Cm[(int64_t)k * ld + k];
   z[k] = zkk;
   for (int i = k - 1; i >= 0; --i) {
-    double s = 0.0;
-    for (int l = i + 1 + lane; l <= k; l += 64) s = fma(Cm[(int64_t)i * ld + l], z[l], s);
+    // four running sums so that four loads of row i are in flight per lane
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const double* ci = Cm + (int64_t)i * ld;
+    int l = i + 1 + lane;
+    for (; l + 192 <= k; l += 256) {
+      s0 = fma(ci[l], z[l], s0);
+      s1 = fma(ci[l + 64], z[l + 64], s1);
+      s2 = fma(ci[l + 128], z[l + 128], s2);
+      s3 = fma(ci[l + 192], z[l + 192], s3);
+    }
+    for (; l <= k; l += 64) s0 = fma(ci[l], z[l], s0);
+    double s = (s0 + s1) + (s2 + s3);
     s = wave_sum(s);
     const double zi = -s / Cm[(int64_t)i * ld + i];
     z[i] = zi;  // every lane writes the same value, so each lane reads its own write
@@ -437,8 +447,19 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
   int stable = 0;
   for (int it = 0; it <= iters; ++it) {
     double y = 0.0;
-    if (i < r)
-      for (int k = 0; k < r; ++k) y = fma(G[(int64_t)k * ld + i], x[k], y);
+    if (i < r) {
+      // eight running sums so that eight loads of G are in flight
+      double a[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) a[t] = 0.0;
+      int k = 0;
+      for (; k + 7 < r; k += 8) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a[t] = fma(G[(int64_t)(k + t) * ld + i], x[k + t], a[t]);
+      }
+      for (; k < r; ++k) a[0] = fma(G[(int64_t)k * ld + i], x[k], a[0]);
+      y = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
     // Rayleigh quotient x^T G x (x normalised) and ||y||^2
     double xy = (i < r) ? x[i] * y : 0.0, yy = y * y;
     xy = wave_sum(xy);
