@@ -642,6 +642,27 @@ __global__ __launch_bounds__(kJS) void k_jacobi_solve(const double* __restrict__
   if (__any(rotated) && tid == 0) atomicAdd(&counters[sweep], 1);
 }
 
+// o[a][b] = sum_l X(l, ii + 16a) Y(l, jj + 16b) over l in order (the two
+// 32 x 32 operands in LDS; X read as X[l][i] when XT, else X[i][l]): each
+// thread owns a 2 x 2 block of outputs, four LDS reads per four FMAs
+static_assert(kJP == 32 && kJT == 256, "tile_mm: 16 x 16 threads, 2 x 2 outputs each");
+template <bool XT>
+__device__ __forceinline__ void tile_mm(const double (&X)[kJP][kJP + 1],
+                                        const double (&Y)[kJP][kJP + 1], int ii, int jj,
+                                        double (&o)[2][2]) {
+  o[0][0] = o[0][1] = o[1][0] = o[1][1] = 0.0;
+#pragma unroll 8
+  for (int l = 0; l < kJP; ++l) {
+    const double a0 = XT ? X[l][ii] : X[ii][l];
+    const double a1 = XT ? X[l][ii + 16] : X[ii + 16][l];
+    const double b0 = Y[l][jj], b1 = Y[l][jj + 16];
+    o[0][0] = fma(a0, b0, o[0][0]);
+    o[0][1] = fma(a0, b1, o[0][1]);
+    o[1][0] = fma(a1, b0, o[1][0]);
+    o[1][1] = fma(a1, b1, o[1][1]);
+  }
+}
+
 // G_out tile (P, Q) = Q_P^T G_in[P, Q] Q_Q for pair blocks P, Q of the round,
 // and V[rows, P] <- V[rows, P] Q_P (extra workgroups).
 __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__ Gin,
@@ -671,33 +692,29 @@ __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__
       W[i][j] = QQ[e];
     }
     __syncthreads();
+    const int ii = tid >> 4, jj = tid & 15;
     // X = T * Q_Q
-    double x[kJE];
-#pragma unroll
-    for (int t = 0; t < kJE; ++t) {
-      const int e = tid + t * kJT;
-      const int i = e / kJP, j = e % kJP;
-      double sacc = 0.0;
-      for (int l = 0; l < kJP; ++l) sacc = fma(T[i][l], W[l][j], sacc);
-      x[t] = sacc;
-    }
+    double o[2][2];
+    tile_mm<false>(T, W, ii, jj, o);
     __syncthreads();
 #pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) T[ii + 16 * a][jj + 16 * b] = o[a][b];
+#pragma unroll
     for (int t = 0; t < kJE; ++t) {
       const int e = tid + t * kJT;
-      T[e / kJP][e % kJP] = x[t];
       W[e / kJP][e % kJP] = QP[e];
     }
     __syncthreads();
     // out = Q_P^T * X
+    tile_mm<true>(W, T, ii, jj, o);
 #pragma unroll
-    for (int t = 0; t < kJE; ++t) {
-      const int e = tid + t * kJT;
-      const int i = e / kJP, j = e % kJP;
-      double sacc = 0.0;
-      for (int l = 0; l < kJP; ++l) sacc = fma(W[l][i], T[l][j], sacc);
-      Gout[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)] = sacc;
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        Gout[(int64_t)pair_index(pa, pb, ii + 16 * a) * R + pair_index(qa, qb, jj + 16 * b)] =
+            o[a][b];
   } else {
     const int v = bid - np * np;
     const int P = v % np, rc = v / np;
@@ -711,14 +728,14 @@ __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__
       W[i][j] = QP[e];
     }
     __syncthreads();
+    const int ii = tid >> 4, jj = tid & 15;
+    double o[2][2];
+    tile_mm<false>(T, W, ii, jj, o);
 #pragma unroll
-    for (int t = 0; t < kJE; ++t) {
-      const int e = tid + t * kJT;
-      const int i = e / kJP, j = e % kJP;
-      double sacc = 0.0;
-      for (int l = 0; l < kJP; ++l) sacc = fma(T[i][l], W[l][j], sacc);
-      V[(int64_t)(rc * kJP + i) * R + pair_index(pa, pb, j)] = sacc;
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        V[(int64_t)(rc * kJP + ii + 16 * a) * R + pair_index(pa, pb, jj + 16 * b)] = o[a][b];
   }
 }
 
