@@ -52,9 +52,10 @@ __device__ double block_sum_value(double v, double* sh4) {
   return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
-// 256 threads: RJ columns x (256 / RJ) slices of the workgroup partials,
-// combined in a fixed order through LDS.
-template <int RJ>
+// 256 threads: RJ lanes x (256 / RJ) slices of the workgroup partials, each
+// lane summing VW adjacent columns; the slices are combined in a fixed order
+// through LDS.
+template <int RJ, int VW>
 __global__ __launch_bounds__(256) void k_reduce_update(
     int op, const double* __restrict__ ypart, int G, int ldy, const double* __restrict__ qpart,
     int64_t d, double rho_eff, const double* __restrict__ p, double* __restrict__ x,
@@ -63,27 +64,65 @@ __global__ __launch_bounds__(256) void k_reduce_update(
     double* __restrict__ rrpart, PcgDev* __restrict__ st, int Gq, int pre) {
   if (op == 0 && st->done) return;
   constexpr int S = 256 / RJ;
-  __shared__ double part[S][RJ];
+  constexpr int CW = RJ * VW;   // columns per workgroup
+  __shared__ double part[S][CW];
   __shared__ double sh4[4];
   const int tid = threadIdx.x;
   const int lane = tid % RJ;
   const int grp = tid / RJ;
-  const int64_t j = (int64_t)blockIdx.x * RJ + lane;
 
-  // eight independent running sums (rows g, g+S, ..., g+7S, ...) keep eight
-  // loads in flight per lane; combined in a fixed order
-  double a[8];
+  if constexpr (VW == 1) {
+    // eight independent running sums (rows g, g+S, ..., g+7S, ...) keep eight
+    // loads in flight per lane; combined in a fixed order
+    const int64_t j = (int64_t)blockIdx.x * RJ + lane;
+    double a[8];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) a[t] = 0.0;
-  if (j < d) {
-    int g = grp;
-    for (; g + 7 * S < G; g += 8 * S) {
+    for (int t = 0; t < 8; ++t) a[t] = 0.0;
+    if (j < d) {
+      int g = grp;
+      for (; g + 7 * S < G; g += 8 * S) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) a[t] += ypart[(int64_t)(g + t * S) * ldy + j];
+        for (int t = 0; t < 8; ++t) a[t] += ypart[(int64_t)(g + t * S) * ldy + j];
+      }
+      for (; g < G; g += S) a[0] += ypart[(int64_t)g * ldy + j];
     }
-    for (; g < G; g += S) a[0] += ypart[(int64_t)g * ldy + j];
+    part[grp][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  } else {
+    // two adjacent columns per 16-byte load (ldy even, ypart 16-byte aligned;
+    // the column past an odd d lies inside the padded row and is dropped) and
+    // sixteen rows per lane issued together: a row past G reads row G - 1 and
+    // adds nothing.  Sixteen running sums, combined in a fixed order.
+    static_assert(VW == 2, "two columns per lane");
+    const int64_t j = (int64_t)blockIdx.x * CW + 2 * lane;
+    double2 a[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) a[t] = make_double2(0.0, 0.0);
+    if (j < d) {
+      for (int g = grp; g < G; g += 16 * S) {
+        double2 v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const int gt = g + t * S;
+          const int gc = gt < G ? gt : G - 1;
+          v[t] = *reinterpret_cast<const double2*>(ypart + (int64_t)gc * ldy + j);
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const bool in = g + t * S < G;
+          a[t].x += in ? v[t].x : 0.0;
+          a[t].y += in ? v[t].y : 0.0;
+        }
+      }
+    }
+    double2 q[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      q[t].x = (a[4 * t].x + a[4 * t + 1].x) + (a[4 * t + 2].x + a[4 * t + 3].x);
+      q[t].y = (a[4 * t].y + a[4 * t + 1].y) + (a[4 * t + 2].y + a[4 * t + 3].y);
+    }
+    part[grp][2 * lane] = (q[0].x + q[1].x) + (q[2].x + q[3].x);
+    part[grp][2 * lane + 1] = (q[0].y + q[1].y) + (q[2].y + q[3].y);
   }
-  part[grp][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 
   double alpha = 0.0;
   if (op == 0) {
@@ -110,11 +149,13 @@ __global__ __launch_bounds__(256) void k_reduce_update(
   }
   __syncthreads();
 
+  // thread tid < CW finishes column blockIdx.x * CW + tid
+  const int64_t j = (int64_t)blockIdx.x * CW + tid;
   double ww = 0.0, rr = 0.0;
-  if (grp == 0 && j < d) {
+  if (tid < CW && j < d) {
     double sum = 0.0;
 #pragma unroll
-    for (int i = 0; i < S; ++i) sum += part[i][lane];
+    for (int i = 0; i < S; ++i) sum += part[i][tid];
     const double pj = (p != nullptr) ? p[j] : 0.0;
     const double v = sum + rho_eff * pj;
     if (op == 0) {
@@ -444,14 +485,20 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                 int npp, double* wwpart, double* rrpart, PcgDev* st,
                                 hipStream_t stream, int Gq, bool pre, int rj) {
   if (rj == 0) rj = red_block(G);
+  // the wide form reads column pairs: rows of even length, 16-byte aligned
+  const bool wide = (ldy % 2 == 0) && (reinterpret_cast<uintptr_t>(ypart) % 16 == 0);
   if (rj == 256)
-    hipLaunchKernelGGL(k_reduce_update<256>, dim3(nblk(d, 256)), dim3(256), 0, stream, op, ypart,
-                       G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp, wwpart,
+    hipLaunchKernelGGL((k_reduce_update<256, 1>), dim3(nblk(d, 256)), dim3(256), 0, stream, op,
+                       ypart, G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp, wwpart,
                        rrpart, st, Gq < 0 ? G : Gq, pre ? 1 : 0);
+  else if (rj == kRedBlock && wide)
+    hipLaunchKernelGGL((k_reduce_update<kRedBlock / 2, 2>), dim3(nblk(d, kRedBlock)), dim3(256),
+                       0, stream, op, ypart, G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k,
+                       pppart, npp, wwpart, rrpart, st, Gq < 0 ? G : Gq, pre ? 1 : 0);
   else if (rj == kRedBlock)
-    hipLaunchKernelGGL(k_reduce_update<kRedBlock>, dim3(nblk(d, kRedBlock)), dim3(256), 0, stream,
-                       op, ypart, G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart, npp,
-                       wwpart, rrpart, st, Gq < 0 ? G : Gq, pre ? 1 : 0);
+    hipLaunchKernelGGL((k_reduce_update<kRedBlock, 1>), dim3(nblk(d, kRedBlock)), dim3(256), 0,
+                       stream, op, ypart, G, ldy, qpart, d, rho_eff, p, x, w, rhs, wy, k, pppart,
+                       npp, wwpart, rrpart, st, Gq < 0 ? G : Gq, pre ? 1 : 0);
   else
     return NYS_ERR_INVALID;
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
