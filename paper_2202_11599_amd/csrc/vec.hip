@@ -52,6 +52,51 @@ __device__ double block_sum_value(double v, double* sh4) {
   return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
+// Block sums whose loads are issued early: pre_load puts a[t + 256 i]
+// (i < 4, thread t) in registers for n <= kPreMax without waiting for them (an
+// index past n reads a[n - 1], dropped by pre_sum); pre_sum adds them in
+// ascending i and sums over the block.  Larger n is summed by block_sum_array.
+constexpr int kPreMax = 1024;
+__device__ __forceinline__ void pre_load(const double* __restrict__ a, int n, double v[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = 0.0;
+  if (n > 0 && n <= kPreMax) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = (int)threadIdx.x + 256 * i;
+      v[i] = a[e < n ? e : n - 1];
+    }
+  }
+}
+__device__ __forceinline__ double pre_sum(const double* __restrict__ a, int n, const double v[4],
+                                          double* sh4) {
+  if (n > kPreMax) return block_sum_array(a, n, sh4);
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s += ((int)threadIdx.x + 256 * i < n) ? v[i] : 0.0;
+  return block_sum_value(s, sh4);
+}
+
+// c[0] + c[1024] + ... + c[(nsl - 1) * 1024] with eight loads in flight (an
+// index past nsl reads the last slice and adds nothing); eight running sums
+// combined in a fixed order
+__device__ __forceinline__ double slice_sum(const double* __restrict__ c, int nsl) {
+  double s[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) s[t] = 0.0;
+  for (int h0 = 0; h0 < nsl; h0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int h = h0 + t;
+      v[t] = c[(int64_t)(h < nsl ? h : nsl - 1) * 1024];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s[t] += (h0 + t < nsl) ? v[t] : 0.0;
+  }
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 // 256 threads: RJ lanes x (256 / RJ) slices of the workgroup partials, each
 // lane summing VW adjacent columns; the slices are combined in a fixed order
 // through LDS.
@@ -62,7 +107,6 @@ __global__ __launch_bounds__(256) void k_reduce_update(
     double* __restrict__ w, const double* __restrict__ rhs, double* __restrict__ wy, int k,
     const double* __restrict__ pppart, int npp, double* __restrict__ wwpart,
     double* __restrict__ rrpart, PcgDev* __restrict__ st, int Gq, int pre) {
-  if (op == 0 && st->done) return;
   constexpr int S = 256 / RJ;
   constexpr int CW = RJ * VW;   // columns per workgroup
   __shared__ double part[S][CW];
@@ -70,6 +114,29 @@ __global__ __launch_bounds__(256) void k_reduce_update(
   const int tid = threadIdx.x;
   const int lane = tid % RJ;
   const int grp = tid / RJ;
+  // thread tid < CW finishes column blockIdx.x * CW + tid; its entries and the
+  // partials of the step's scalars are loaded before the partial sums, so the
+  // round trips overlap
+  const int64_t jf = (int64_t)blockIdx.x * CW + tid;
+  const bool own = tid < CW && jf < d;
+  double qv[4], pv4[4];
+  pre_load(qpart, (op == 0 && !pre) ? Gq : 0, qv);
+  pre_load(pppart, (op == 0 && !pre) ? npp : 0, pv4);
+  const double wyk = (op == 0) ? wy[k] : 0.0;
+  if (op == 0 && st->done) return;
+  double pj = 0.0, xj = 0.0, wj = 0.0, rj = 0.0;
+  if (own) {
+    if (p != nullptr) pj = p[jf];
+    if (op == 0) {
+      xj = x[jf];
+      wj = w[jf];
+    } else if (op == 1 || op == 2) {
+      rj = rhs[jf];
+    } else if (op == 4) {
+      rj = rhs[jf];
+      wj = w[jf];
+    }
+  }
 
   if constexpr (VW == 1) {
     // eight independent running sums (rows g, g+S, ..., g+7S, ...) keep eight
@@ -132,9 +199,9 @@ __global__ __launch_bounds__(256) void k_reduce_update(
     if (pre) {
       pv = st->pv;
     } else {
-      const double qs = block_sum_array(qpart, Gq, sh4);
+      const double qs = pre_sum(qpart, Gq, qv, sh4);
       __syncthreads();
-      const double ps = block_sum_array(pppart, npp, sh4);
+      const double ps = pre_sum(pppart, npp, pv4, sh4);
       pv = qs + rho_eff * ps;
     }
     if (!(pv > 0.0)) {
@@ -145,33 +212,30 @@ __global__ __launch_bounds__(256) void k_reduce_update(
       }
       return;
     }
-    alpha = wy[k] / pv;
+    alpha = wyk / pv;
   }
   __syncthreads();
 
-  // thread tid < CW finishes column blockIdx.x * CW + tid
-  const int64_t j = (int64_t)blockIdx.x * CW + tid;
+  const int64_t j = jf;
   double ww = 0.0, rr = 0.0;
-  if (tid < CW && j < d) {
+  if (own) {
     double sum = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) sum += part[i][tid];
-    const double pj = (p != nullptr) ? p[j] : 0.0;
     const double v = sum + rho_eff * pj;
     if (op == 0) {
-      x[j] += alpha * pj;
-      const double wj = w[j] - alpha * v;
-      w[j] = wj;
-      ww = wj * wj;
+      x[j] = xj + alpha * pj;
+      const double wn = wj - alpha * v;
+      w[j] = wn;
+      ww = wn * wn;
     } else if (op == 1 || op == 2) {
-      const double r = rhs[j];
-      const double wj = r - v;
-      w[j] = wj;
-      ww = wj * wj;
-      rr = r * r;
+      const double wn = rj - v;
+      w[j] = wn;
+      ww = wn * wn;
+      rr = rj * rj;
       if (op == 2 && x != nullptr) x[j] = v;   // keep H_rho x for the next solve's w0
     } else if (op == 4) {   // H_rho x = rhs - w from the recursive residual
-      x[j] = rhs[j] - w[j];
+      x[j] = rj - wj;
     } else {  // op 3: plain reduction
       w[j] = v;
     }
@@ -202,13 +266,54 @@ __global__ __launch_bounds__(256) void k_precond_dot(
     int pre) {
   __shared__ double sh4[4];
   const int tid = threadIdx.x;
+  // the partials of the norms are loaded with the state, and this
+  // workgroup's slice of U^T w is summed before the test, so their round
+  // trips overlap
+  double wv[4], rv[4];
+  pre_load(wwpart, ((mode == 0 && !pre) || mode == 1 || mode == 3) ? nww : 0, wv);
+  pre_load(rrpart, mode == 1 ? nww : 0, rv);
+  if ((mode == 0 || mode == 1) && st->done) return;
+  // partial c = U^T w over d-slice blockIdx.y: cpart[slice * 1024 + col]
+  const int lane = tid & 63;
+  const int col = blockIdx.x * 4 + (tid >> 6);
+  double acc = 0.0;
+  if (mode != 3 && col < r) {
+    const int nsl = (int)gridDim.y;
+    const int64_t chunk = ((d + nsl - 1) / nsl + 63) / 64 * 64;
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < d ? j0 + chunk : d;
+    const UT* u = U + (int64_t)col * d;
+    // eight running sums so that eight loads of U (and of w) are in flight
+    // per lane; combined in a fixed order
+    double a[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) a[t] = 0.0;
+    int64_t j = j0 + lane;
+    for (; j + 7 * 64 < j1; j += 8 * 64) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) a[t] = fma((double)u[j + 64 * t], w[j + 64 * t], a[t]);
+    }
+    // the (fewer than eight) remaining terms, their loads issued together: an
+    // index past the slice reads its last entry and adds nothing
+    if (j < j1) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int64_t jt = j + 64 * t;
+        const int64_t jc = jt < j1 ? jt : j1 - 1;
+        const double v = fma((double)u[jc], w[jc], a[t]);
+        a[t] = jt < j1 ? v : a[t];
+      }
+    }
+    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    acc = wave_sum(acc);
+  }
   if (mode == 0 || mode == 1) {
-    if (st->done) return;
-    const double ww = (pre && mode == 0) ? st->wwn : block_sum_array(wwpart, nww, sh4);
+    const double ww = (pre && mode == 0) ? st->wwn : pre_sum(wwpart, nww, wv, sh4);
     double thr2;
     bool zero_rhs = false;
     if (mode == 1) {
-      const double rr = block_sum_array(rrpart, nww, sh4);
+      __syncthreads();
+      const double rr = pre_sum(rrpart, nww, rv, sh4);
       thr2 = fmax(tol_abs * tol_abs, tol_rel * tol_rel * rr);
       zero_rhs = (rr == 0.0);
       if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
@@ -231,33 +336,11 @@ __global__ __launch_bounds__(256) void k_precond_dot(
       return;
     }
   } else if (mode == 3) {
-    const double ww = block_sum_array(wwpart, nww, sh4);
+    const double ww = pre_sum(wwpart, nww, wv, sh4);
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) st->true_rr = ww;
     return;
   }
-  // partial c = U^T w over d-slice blockIdx.y: cpart[slice * 1024 + col]
-  const int lane = tid & 63;
-  const int col = blockIdx.x * 4 + (tid >> 6);
-  if (col >= r) return;
-  const int nsl = (int)gridDim.y;
-  const int64_t chunk = ((d + nsl - 1) / nsl + 63) / 64 * 64;
-  const int64_t j0 = (int64_t)blockIdx.y * chunk;
-  const int64_t j1 = j0 + chunk < d ? j0 + chunk : d;
-  const UT* u = U + (int64_t)col * d;
-  // eight running sums so that eight loads of U (and of w) are in flight per
-  // lane; combined in a fixed order
-  double a[8];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) a[t] = 0.0;
-  int64_t j = j0 + lane;
-  for (; j + 7 * 64 < j1; j += 8 * 64) {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) a[t] = fma((double)u[j + 64 * t], w[j + 64 * t], a[t]);
-  }
-  for (; j < j1; j += 64) a[0] = fma((double)u[j], w[j], a[0]);
-  double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  acc = wave_sum(acc);
-  if (lane == 0) cvec[(int64_t)blockIdx.y * 1024 + col] = acc;
+  if (col < r && lane == 0) cvec[(int64_t)blockIdx.y * 1024 + col] = acc;
 }
 
 // y = w + U (s o c), s_i = (lambda_s + rho)/(lambda_i + rho) - 1 ;
@@ -265,7 +348,7 @@ __global__ __launch_bounds__(256) void k_precond_dot(
 // mode 0: p = y + beta p (beta = (w^T y)/wy[k]), wy[k+1] = w^T y
 // mode 1: p = y, wy[0] = w^T y
 // mode 2: p (output) = y, standalone apply
-template <typename UT>
+template <typename UT, int NU>
 __global__ __launch_bounds__(256) void k_precond_update(
     const UT* __restrict__ U, int64_t d, int r, const double* __restrict__ lam, double lam_s,
     double rho, const double* __restrict__ cvec, const double* __restrict__ w,
@@ -274,6 +357,25 @@ __global__ __launch_bounds__(256) void k_precond_update(
     PcgDev* __restrict__ host_slot, int seq, int nsl, int pre) {
   // host_slot (pinned host memory, may be NULL): receives the state at the end
   // of the iteration, read by the host once the kernel has completed
+  constexpr int VJ = kVecBlock;        // entries of y per workgroup
+  constexpr int VS = 256 / VJ;         // slices of the rank index
+  __shared__ double g[1024];
+  __shared__ double ys[VS][VJ];
+  __shared__ double sh4[4];
+  const int tid = threadIdx.x;
+  const int jl = tid % VJ, sl = tid / VJ;
+  const int64_t j = (int64_t)blockIdx.x * VJ + jl;
+  const UT* u = U + j;
+  // loaded with the state, so the round trips overlap: the partials of
+  // ||w||^2, this lane's entries of w and p, and wy[k]
+  double wv[4];
+  pre_load(wwpart, (mode != 2 && !(pre && mode == 0)) ? nww : 0, wv);
+  double wj = 0.0, pold = 0.0;
+  if (sl == 0 && j < d) {
+    wj = w[j];
+    if (mode == 0) pold = p[j];
+  }
+  const double wyk = (mode == 0) ? wy[k] : 0.0;
   if (mode != 2 && st->done) {
     if (host_slot != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
       PcgDev h = *st;
@@ -282,66 +384,77 @@ __global__ __launch_bounds__(256) void k_precond_update(
     }
     return;
   }
-  constexpr int VJ = kVecBlock;        // entries of y per workgroup
-  constexpr int VS = 256 / VJ;         // slices of the rank index
-  __shared__ double g[1024];
-  __shared__ double ys[VS][VJ];
-  __shared__ double sh4[4];
-  const int tid = threadIdx.x;
+  // the lane's first NU terms of U (rank i = sl + VS t; an index past r reads
+  // row r - 1, dropped below), loaded with the slices of c
+  UT u0[NU];
+#pragma unroll
+  for (int t = 0; t < NU; ++t) u0[t] = UT(0);
+  if (j < d && r > 0) {
+#pragma unroll
+    for (int t = 0; t < NU; ++t) {
+      const int it = sl + t * VS;
+      u0[t] = u[(int64_t)(it < r ? it : r - 1) * d];
+    }
+  }
   double sc = 0.0;
   for (int i = tid; i < r; i += 256) {
-    const double ci = strided_sum(cvec + i, nsl * 1024, 0, 1024);   // slices in order
+    const double ci = slice_sum(cvec + i, nsl);   // slices in a fixed order
     const double s = (lam_s + rho) / (lam[i] + rho) - 1.0;
     g[i] = s * ci;
     sc += s * ci * ci;
   }
   double wy_new = 0.0;
   if (mode != 2) {
-    const double ww = (pre && mode == 0) ? st->wwn : block_sum_array(wwpart, nww, sh4);
+    const double ww = (pre && mode == 0) ? st->wwn : pre_sum(wwpart, nww, wv, sh4);
     __syncthreads();
     wy_new = ww + block_sum_value(sc, sh4);
   } else {
     __syncthreads();
   }
-  const int jl = tid % VJ, sl = tid / VJ;
-  const int64_t j = (int64_t)blockIdx.x * VJ + jl;
   double part = 0.0;
-  if (j < d) {
-    // eight running sums over the rank index (i = sl, sl + VS, ...) so that
-    // eight loads of U are in flight per lane; combined in a fixed order
-    const UT* u = U + j;
-    double a[8];
+  if (j < d && r > 0) {
+    // NU running sums over the rank index (i = sl, sl + VS, ...), combined in
+    // a fixed order; after the preloaded terms, NU loads of U are in flight
+    // per lane, the last (partial) group issued together with clamped indices
+    double a[NU];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) a[t] = 0.0;
-    int i = sl;
-    for (; i + 7 * VS < r; i += 8 * VS) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-        a[t] = fma((double)u[(int64_t)(i + t * VS) * d], g[i + t * VS], a[t]);
+    for (int t = 0; t < NU; ++t) {
+      const int it = sl + t * VS;
+      const int ic = it < r ? it : r - 1;
+      a[t] = it < r ? (double)u0[t] * g[ic] : 0.0;
     }
-    // the (fewer than eight) remaining terms, their loads issued together:
-    // an index past r reads row r - 1 and adds nothing
-    if (i < r) {
+    for (int i = sl + NU * VS; i < r; i += NU * VS) {
+      UT v[NU];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < NU; ++t) {
+        const int it = i + t * VS;
+        v[t] = u[(int64_t)(it < r ? it : r - 1) * d];
+      }
+#pragma unroll
+      for (int t = 0; t < NU; ++t) {
         const int it = i + t * VS;
         const int ic = it < r ? it : r - 1;
-        const double v = fma((double)u[(int64_t)ic * d], g[ic], a[t]);
-        a[t] = it < r ? v : a[t];
+        const double f = fma((double)v[t], g[ic], a[t]);
+        a[t] = it < r ? f : a[t];
       }
     }
-    part = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    double q[NU / 4];
+#pragma unroll
+    for (int t = 0; t < NU / 4; ++t)
+      q[t] = (a[4 * t] + a[4 * t + 1]) + (a[4 * t + 2] + a[4 * t + 3]);
+    part = (q[0] + q[1]);
+    if constexpr (NU == 16) part += (q[2] + q[3]);
   }
   ys[sl][jl] = part;
   __syncthreads();
   double pj = 0.0;
   if (sl == 0 && j < d) {
-    double y = w[j];
+    double y = wj;
 #pragma unroll
     for (int h = 0; h < VS; ++h) y += ys[h][jl];
     if (mode == 0) {
-      const double beta = wy_new / wy[k];
-      pj = y + beta * p[j];
+      const double beta = wy_new / wyk;
+      pj = y + beta * pold;
     } else {
       pj = y;
     }
@@ -540,14 +653,23 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
   if (r > 1024) return NYS_ERR_INVALID;
   const int grid = nblk(d, kVecBlock);
   const int nsl = dot_slices(d);
-  if (u32)
-    hipLaunchKernelGGL(k_precond_update<float>, dim3(grid), dim3(256), 0, stream,
-                       static_cast<const float*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
-                       wwpart, nww, pppart, st, mode, host_slot, seq, nsl, pre ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_precond_update<double>, dim3(grid), dim3(256), 0, stream,
-                       static_cast<const double*>(U), d, r, lam, lam_s, rho, cvec, w, p, wy, k,
-                       wwpart, nww, pppart, st, mode, host_slot, seq, nsl, pre ? 1 : 0);
+  // eight rank terms per lane in flight up to rank 64 (every term in one
+  // group); sixteen up to rank 256, where the pass is latency bound and the
+  // lane's terms fit two groups; eight above, where U streams from HBM and
+  // the clamped tail of a wider group only adds loads
+  const int vs = 256 / kVecBlock;
+  const bool wide = r > 8 * vs && r <= 32 * vs;
+  auto go = [&](auto kern, const auto* u) {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, stream, u, d, r, lam, lam_s, rho, cvec, w,
+                       p, wy, k, wwpart, nww, pppart, st, mode, host_slot, seq, nsl, pre ? 1 : 0);
+  };
+  if (u32) {
+    const float* u = static_cast<const float*>(U);
+    if (wide) go(k_precond_update<float, 16>, u); else go(k_precond_update<float, 8>, u);
+  } else {
+    const double* u = static_cast<const double*>(U);
+    if (wide) go(k_precond_update<double, 16>, u); else go(k_precond_update<double, 8>, u);
+  }
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
