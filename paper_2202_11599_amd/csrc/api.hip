@@ -399,14 +399,16 @@ nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out) {
 
 // Wait until the kernel of PCG iteration seq-1 has written its state into the
 // pinned slot (sequence number seq in PcgDev::k).  The wait spins on the host
-// memory; every few thousand polls the stream is queried so that a failed
-// stream returns an error, and a stream that has drained without the slot
-// being written is reported as an internal error.
+// memory; once the slot has stayed unwritten for a few milliseconds the stream
+// is queried (PollPace) so that a failed stream returns an error, and a stream
+// that has drained without the slot being written is reported as an internal
+// error.
 nys_status wait_slot(hipStream_t st, const char* slot, int seq, PcgDev* out) {
   const volatile PcgDev* v = reinterpret_cast<const volatile PcgDev*>(slot);
+  PollPace pace;
   for (long n = 1;; ++n) {
     if (v->k == seq) break;
-    if (n % 4096 == 0) {
+    if (pace.due(n)) {
       const hipError_t e = hipStreamQuery(st);
       if (e == hipSuccess) {
         if (v->k == seq) break;

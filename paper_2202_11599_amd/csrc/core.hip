@@ -916,18 +916,19 @@ size_t jacobi_ws_doubles(int r) {
 // W(:, c) = v_c / sqrt(sig2_c).  ws must hold jacobi_ws_doubles(r) doubles;
 // counters (>= max_sweeps ints) and host_flag are scratch.  Returns
 // NYS_ERR_NOT_CONVERGED if a sweep still rotated after max_sweeps.
-// Wait until the device has written sequence number seq into the slot; the
-// stream is queried every few thousand polls so that a failed or drained
-// stream ends the wait with an error.
+// Wait until the device has written sequence number seq into the slot; once
+// the slot has stayed unwritten for a few milliseconds the stream is queried
+// (PollPace) so that a failed or drained stream ends the wait with an error.
 nys_status wait_jacobi_slot(hipStream_t st, const volatile unsigned long long* slot, unsigned seq,
                             int* val) {
+  PollPace pace;
   for (long n = 1;; ++n) {
     unsigned long long v = *slot;
     if ((unsigned)(v >> 32) == seq) {
       *val = (int)(unsigned)(v & 0xffffffffu);
       return NYS_OK;
     }
-    if (n % 4096 == 0) {
+    if (pace.due(n)) {
       const hipError_t e = hipStreamQuery(st);
       if (e == hipSuccess) {
         v = *slot;

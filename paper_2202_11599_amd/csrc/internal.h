@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -27,6 +28,26 @@
   } while (0)
 
 namespace nys {
+
+// Pacing of the host's spin-waits on pinned slots.  Querying the stream is a
+// runtime call that, while kernels are queued, can append a marker packet
+// behind the last of them, and the next dispatch then waits for that marker;
+// so the wait queries the stream (to end with an error when the stream failed
+// or drained without writing the slot) only once the slot has stayed unwritten
+// for kPollQueryMs, and then every kPollQueryMs.
+constexpr int kPollQueryMs = 5;
+struct PollPace {
+  std::chrono::steady_clock::time_point next =
+      std::chrono::steady_clock::now() + std::chrono::milliseconds(kPollQueryMs);
+  // true when poll n (n >= 1) should query the stream
+  bool due(long n) {
+    if ((n & 255) != 0) return false;
+    const auto now = std::chrono::steady_clock::now();
+    if (now < next) return false;
+    next = now + std::chrono::milliseconds(kPollQueryMs);
+    return true;
+  }
+};
 
 void set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
 
