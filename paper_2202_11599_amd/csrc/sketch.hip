@@ -490,20 +490,23 @@ nys_status orthonormalize(nys_ctx ctx, double* Om, int64_t d, int m, const CoreW
                           double* tmp = nullptr) {
   hipStream_t st = ctx->stream;
   if (tmp == nullptr) tmp = w.Bm;
+  // one failure flag for both passes, read once at the end: after a failed
+  // factorisation the remaining kernels run on meaningless values (their
+  // indexing does not depend on them) and the result is discarded
+  NYS_TRY_HIP(hipMemsetAsync(w.ints, 0, sizeof(int), st));
   for (int pass = 0; pass < 2; ++pass) {
     NYS_TRY(gemm64(st, m, m, (int)d, Om, false, d, 1, Om, false, 1, d, w.M, m, 1, 1.0, 0.0,
                    w.split, w.split_elems));
-    NYS_TRY_HIP(hipMemsetAsync(w.ints, 0, sizeof(int), st));
     NYS_TRY(chol_upper(st, w.M, m, m, w.ints));
-    int fail = 0;
-    NYS_TRY(read_back(ctx, w.ints, sizeof(int), &fail));
-    if (fail) return NYS_ERR_NOT_SPD;   // Gaussian block without full column rank
     NYS_TRY(trinv_upper(st, w.M, m, m, w.Cinv, m));
     // Bm = Om Rinv  (d x m col-major), then copy back
     NYS_TRY(gemm64(st, (int)d, m, m, Om, false, 1, d, w.Cinv, false, m, 1, tmp, 1, d, 1.0, 0.0,
                    w.split, w.split_elems));
     NYS_TRY_HIP(hipMemcpyAsync(Om, tmp, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
   }
+  int fail = 0;
+  NYS_TRY(read_back(ctx, w.ints, sizeof(int), &fail));
+  if (fail) return NYS_ERR_NOT_SPD;   // Gaussian block without full column rank
   return NYS_OK;
 }
 
