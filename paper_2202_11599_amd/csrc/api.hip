@@ -459,7 +459,7 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
   nys_status status = NYS_OK;
   double true_rr = -1.0;
   for (;;) {
-    NYS_TRY_HIP(hipMemsetAsync(ws.st, 0, sizeof(PcgDev), st));
+    NYS_TRY(launch_zero_state(ws.st, st));
     // w0 = rhs - H_rho x0 ; y0 = P^-1 w0 ; p0 = y0
     const AtbKey key{A.data, D, A.n, d, A.ld, x};
     if (hx_tag >= 0 && restarts == 0 && ctx->hx_tag == hx_tag && ctx->hx_key == key &&

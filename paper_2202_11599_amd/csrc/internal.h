@@ -377,6 +377,7 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                                               // ||w||^2 partials number nblk(d, rj)
 // *slot = *st with k = seq (one thread): publish_state for an iteration that
 // no matvec launch follows
+nys_status launch_zero_state(PcgDev* st, hipStream_t stream);
 nys_status launch_note(const PcgDev* st, PcgDev* slot, int seq, hipStream_t stream);
 // st->pv = sum(a) + rho_eff sum(b) (op 0) or st->wwn = sum(a) (op 1), one
 // workgroup, fixed order; skipped once st->done is set

@@ -476,6 +476,14 @@ __global__ __launch_bounds__(256) void k_precond_update(
   }
 }
 
+// Clears the PCG state at the start of a solve (one lane per 4-byte word; a
+// plain kernel launch costs the host less than a runtime fill)
+__global__ void k_zero_state(PcgDev* __restrict__ st) {
+  constexpr int kWords = (int)(sizeof(PcgDev) / sizeof(int));
+  static_assert(sizeof(PcgDev) % sizeof(int) == 0 && kWords <= 64, "state words");
+  if ((int)threadIdx.x < kWords) reinterpret_cast<int*>(st)[threadIdx.x] = 0;
+}
+
 // st->pv = sum(a) + rho_eff sum(b) (op 0), st->wwn = sum(a) (op 1): the
 // PCG scalars summed once per iteration, in a fixed order, for large d
 __global__ __launch_bounds__(1024) void k_pcg_scalar(int op, const double* __restrict__ a, int na,
@@ -614,6 +622,11 @@ nys_status launch_reduce_update(int op, const double* ypart, int G, int ldy, con
                        npp, wwpart, rrpart, st, Gq < 0 ? G : Gq, pre ? 1 : 0);
   else
     return NYS_ERR_INVALID;
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status launch_zero_state(PcgDev* st, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, stream, st);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
