@@ -95,6 +95,16 @@ def kkt_eta_logistic(A, b, gamma, x):
     return float(num / (1.0 + np.linalg.norm(x) + np.linalg.norm(g)))
 
 
+def rel_change_inf(z_old, z):
+    """||z - z_old||_inf / ||z_old||_inf, the relative change of the iterate
+    used as the stopping rule of the logistic experiments (Section 5); None
+    when z_old = 0 (the rule cannot fire)."""
+    den = float(np.abs(z_old).max())
+    if den == 0.0:
+        return None
+    return float(np.abs(z - z_old).max()) / den
+
+
 @dataclasses.dataclass
 class ADMMResult:
     x: np.ndarray
@@ -106,6 +116,8 @@ class ADMMResult:
     r_d: list
     converged: bool = False
     factor: object = None
+    tols: list = dataclasses.field(default_factory=list)   # absolute PCG tolerance per step
+    z_hist: list = None                                     # z after each step (record=True)
 
 
 def _stop(r_p, r_d, x, z, u, rho, eps_abs, eps_rel):
@@ -119,7 +131,7 @@ def _stop(r_p, r_d, x, z, u, rho, eps_abs, eps_rel):
 def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
                exact=False, factor=None, eps_abs=None, eps_rel=None,
                tol_schedule=False, state=None, mantissa_bits=52,
-               pcg_max_iter=1000, cg=False) -> ADMMResult:
+               pcg_max_iter=1000, cg=False, record=False) -> ADMMResult:
     """Algorithm NysADMM for min 1/2||Ax - b||^2 + c/2||x||^2 + gamma||x||_1
     (cg=True: inexact ADMM with plain CG)."""
     A = np.asarray(A, dtype=np.float64)
@@ -138,7 +150,8 @@ def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
     matvec = lambda p: hessian_apply(A, None, c, p) + rho * p
     precond = None if (exact or cg) else (
         lambda w: precond_inverse_apply(factor.U, factor.lam, rho, w))
-    its, rps, rds = [], [], []
+    its, rps, rds, tols = [], [], [], []
+    zh = [] if record else None
     eps_k = None
     converged = False
     for k in range(iters):
@@ -147,12 +160,14 @@ def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
             x = sla.cho_solve(chol, rhs)
             its.append(0)
         else:
+            nr = np.linalg.norm(rhs)
             if tol_schedule:
-                nr = np.linalg.norm(rhs)
                 tol_abs_val = 1e-2 * nr if eps_k is None else max(eps_k, pcg_tol * nr)
                 res = nys_pcg(matvec, rhs, x, precond, tol_abs_val, pcg_max_iter, tol_abs=True)
+                tols.append(tol_abs_val)
             else:
                 res = nys_pcg(matvec, rhs, x, precond, pcg_tol, pcg_max_iter)
+                tols.append(pcg_tol * nr)
             x = res.x
             its.append(res.iters)
         z_old = z
@@ -162,16 +177,18 @@ def admm_lasso(A, b, gamma, rho, omega_raw=None, c=0.0, iters=300, pcg_tol=1e-8,
         r_d = float(rho * np.linalg.norm(z_old - z))
         rps.append(r_p)
         rds.append(r_d)
+        if record:
+            zh.append(z.copy())
         eps_k = math.sqrt(r_p * r_d)
         if _stop(r_p, r_d, x, z, u, rho, eps_abs, eps_rel):
             converged = True
             break
-    return ADMMResult(x, z, u, len(its), its, rps, rds, converged, factor)
+    return ADMMResult(x, z, u, len(its), its, rps, rds, converged, factor, tols, zh)
 
 
 def admm_logistic(A, b, gamma, rho, omega_raw=None, iters=100, pcg_tol=1e-6,
                   resketch_every=10, exact=False, rel_change_tol=None, state=None,
-                  mantissa_bits=52, pcg_max_iter=1000, cg=False) -> ADMMResult:
+                  mantissa_bits=52, pcg_max_iter=1000, cg=False, record=False) -> ADMMResult:
     """Linearised NysADMM for min -sum(b_i t_i - log(1 + e^t_i)) + gamma||x||_1,
     t = A x, labels b in {0, 1} (cg=True: inexact ADMM with plain CG)."""
     A = np.asarray(A, dtype=np.float64)
@@ -183,6 +200,7 @@ def admm_logistic(A, b, gamma, rho, omega_raw=None, iters=100, pcg_tol=1e-6,
         x, z, u = (np.array(v, dtype=np.float64) for v in state)
     factor = None
     its, rps, rds = [], [], []
+    zh = [] if record else None
     converged = False
     for k in range(iters):
         t = A @ x
@@ -205,9 +223,11 @@ def admm_logistic(A, b, gamma, rho, omega_raw=None, iters=100, pcg_tol=1e-6,
         u = u + x - z
         rps.append(float(np.linalg.norm(x - z)))
         rds.append(float(rho * np.linalg.norm(z_old - z)))
+        if record:
+            zh.append(z.copy())
         if rel_change_tol is not None and k > 0:
-            den = np.abs(z_old).max()
-            if den > 0 and np.abs(z - z_old).max() / den < rel_change_tol:
+            ch = rel_change_inf(z_old, z)
+            if ch is not None and ch < rel_change_tol:
                 converged = True
                 break
-    return ADMMResult(x, z, u, len(its), its, rps, rds, converged, factor)
+    return ADMMResult(x, z, u, len(its), its, rps, rds, converged, factor, None, zh)
