@@ -25,7 +25,12 @@
  *    load path; any ld is accepted.
  *  - Every vector (D, b, rhs, x, z, u, w, y) is FP64 and contiguous.  D is an
  *    n-vector of non-negative Hessian weights (H^l of the loss, Section 2.1);
- *    D == NULL means the identity (least squares).
+ *    D == NULL means the identity (least squares).  Entry points that take a
+ *    caller's D (nys_sketch, nys_sketch_adaptive, nys_hessian_apply,
+ *    pcg_solve) check it on the device first and synchronise the stream:
+ *    a negative weight gives NYS_ERR_INVALID, a NaN or infinite one
+ *    NYS_ERR_NONFINITE.  A NaN or infinity in A, b or rhs surfaces as
+ *    NYS_ERR_NONFINITE from the first residual or sketch norm it reaches.
  *  - The Gaussian test-matrix entries `omega` are drawn by the caller (the
  *    library draws no random numbers): FP64, column-major d x r (column k at
  *    omega + k*d).  The library orthonormalises them (thin QR, as in
@@ -202,9 +207,12 @@ nys_status pcg_solve(nys_ctx ctx, const nys_dense* A, const double* D, double c,
 typedef struct {
   nys_loss loss;     /* NYS_LOSS_LS: 1/2||Ax - b||^2; NYS_LOSS_LOGISTIC: -sum(b t - log(1+e^t)), t = Ax */
   nys_dense A;
-  const double* b;   /* device FP64 n-vector; labels in {0,1} for the logistic loss */
+  const double* b;   /* device FP64 n-vector; labels in {0,1} for the logistic loss (eq. 9),
+                        checked on the device by admm_step / admm_solve (NYS_ERR_INVALID
+                        otherwise, NYS_ERR_NONFINITE for NaN/Inf) */
   double gamma;      /* l1 weight, >= 0 */
-  double c;          /* smooth ridge part c/2 ||x||^2, >= 0 (elastic net: c = 1 - gamma) */
+  double c;          /* smooth ridge part c/2 ||x||^2, >= 0 (elastic net: c = 1 - gamma);
+                        must be 0 for the logistic loss (eq. 9 has no ridge term) */
 } nys_problem;
 
 typedef struct {
@@ -264,10 +272,13 @@ typedef struct {
   double obj;          /* objective at z, -1 if not computed */
   int rank;            /* Nystrom rank in use */
   int converged;       /* a stopping rule fired */
-  nys_status status;
+  nys_status status;   /* the first status other than NYS_OK met by any subproblem of the
+                          call (NYS_ERR_MAXITER: some PCG solve stopped at pcg.max_iter above
+                          its tolerance; the run went on), else NYS_OK */
   int ws_used;         /* subproblems that started from the warm-start candidate */
   double true_res_max; /* largest ||rhs - H_rho x|| / ||rhs|| over the subproblems whose true
                           residual was computed (FP64 accumulation); -1 if none */
+  int maxiter_solves;  /* subproblems whose PCG stopped at pcg.max_iter above tolerance */
 } nys_admm_info;
 
 /* One iteration of Algorithm NysADMM: right-hand side (lasso: rho(z-u) + A^T b;
@@ -363,8 +374,9 @@ typedef struct {
   double bias;
   int rank;
   int converged;       /* the gap test fired */
-  nys_status status;
+  nys_status status;   /* as in nys_admm_info */
   double true_res_max; /* as in nys_admm_info */
+  int maxiter_solves;  /* as in nys_admm_info */
 } nys_svm_info;
 
 /* Algorithm NysADMM on the SVM dual: minimize 1/2 x^T H x - 1^T x subject to

@@ -18,8 +18,6 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libnysadmm.so")
-PROBE_SRC = os.path.join(PKG, "probe", "gram_probe.cpp")
-PROBE = os.path.join(PKG, "gram_probe")
 
 ARCH = os.environ.get("NYSADMM_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
@@ -68,16 +66,6 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
-    # C driver of the ABI: bandwidth probe and counter target
-    cmd = [_hipcc(), "-O2", "-std=c++17", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
-           PROBE_SRC, "-o", PROBE + ".tmp", "-L", PKG, "-lnysadmm", f"-Wl,-rpath,{PKG}",
-           "-Wl,-rpath,$ORIGIN"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"probe build failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

@@ -310,6 +310,7 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
     I->pcg_max = std::max(I->pcg_max, pinfo.iters);
     I->rank = (*F) ? (*F)->r : 0;
     I->status = ps;
+    I->maxiter_solves = ps == NYS_ERR_MAXITER ? 1 : 0;
     I->ws_used = used_alt;
     I->true_res_max = (pinfo.true_res_norm >= 0.0 && pinfo.rhs_norm > 0.0)
                           ? pinfo.true_res_norm / pinfo.rhs_norm
@@ -343,6 +344,9 @@ nys_status validate_problem(const nys_problem* P, const nys_admm_opts* O) {
   NYS_TRY(validate_dense(&P->A));
   if (P->b == nullptr || !(P->gamma >= 0.0) || !(P->c >= 0.0)) return NYS_ERR_INVALID;
   if (P->loss != NYS_LOSS_LS && P->loss != NYS_LOSS_LOGISTIC) return NYS_ERR_INVALID;
+  // eq. (9) has no ridge term: the logistic objective and KKT residual are
+  // defined for c = 0 only
+  if (P->loss == NYS_LOSS_LOGISTIC && P->c != 0.0) return NYS_ERR_INVALID;
   if (!(O->rho > 0.0) || O->rank < 0 || O->rank >= P->A.d) return NYS_ERR_INVALID;
   if (O->rank == 0) {
     // inexact ADMM with plain CG: no sketch, no factor, no warm-start candidate
@@ -371,6 +375,8 @@ nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, 
   if (S->x == nullptr || S->z == nullptr || S->u == nullptr) return NYS_ERR_INVALID;
   if (*F != nullptr && (*F)->d != P->A.d) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  // logistic labels b in {0, 1} (eq. 9)
+  if (P->loss == NYS_LOSS_LOGISTIC) NYS_TRY(check_vector(ctx, P->b, P->A.n, 1));
   if (I) *I = nys_admm_info{};
   if (I) I->eta = I->obj = -1.0;
   if (O->rank == 0 && *F != nullptr) return NYS_ERR_INVALID;
@@ -389,6 +395,8 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
     if (S[q].x == nullptr || S[q].z == nullptr || S[q].u == nullptr) return NYS_ERR_INVALID;
   }
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  for (int q = 0; q < count; ++q)
+    if (P[q].loss == NYS_LOSS_LOGISTIC) NYS_TRY(check_vector(ctx, P[q].b, P[q].A.n, 1));
   ctx->atb_key = AtbKey{};   // b may have changed in place since an earlier call
   ctx->hx_key = AtbKey{};    // and x since an earlier solve
   bool batched = count > 1;
@@ -447,7 +455,8 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
         info.r_d = step.r_d;
       }
       info.rank = step.rank;
-      info.status = step.status;
+      if (info.status == NYS_OK) info.status = step.status;   // sticky: first non-OK
+      info.maxiter_solves += step.maxiter_solves;
       info.ws_used += step.ws_used;
       info.true_res_max = std::max(info.true_res_max, step.true_res_max);
       if (o.tol_schedule) eps_next = std::sqrt(step.r_p * step.r_d);

@@ -226,6 +226,22 @@ nys_status validate_dense(const nys_dense* A) {
   return NYS_OK;
 }
 
+nys_status check_vector(nys_ctx ctx, const double* v, int64_t n, int kind) {
+  if (v == nullptr || n <= 0) return NYS_OK;
+  NYS_TRY(ctx->check.reserve(256));
+  int* flag = ctx->check.as<int>();
+  NYS_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+  NYS_TRY(launch_check_vec(v, n, kind, flag, ctx->stream));
+  NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, flag, sizeof(int), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  int bits = 0;
+  std::memcpy(&bits, ctx->host_pinned, sizeof(int));
+  if (bits & kCheckNonfinite) return NYS_ERR_NONFINITE;
+  if (bits & kCheckBad) return NYS_ERR_INVALID;
+  return NYS_OK;
+}
+
 // Carves the PCG workspace out of the context buffers.
 nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws) {
   const size_t yb = align_up(sizeof(double) * ((size_t)pl.ny() * pl.ldy));
@@ -235,15 +251,14 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
   ws->qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ypart.ptr) + yb);
   const size_t nv = align_up(sizeof(double) * d);
   const size_t cb = align_up(sizeof(double) * 1024 * kDotSlicesMax);
-  const size_t vb = 3 * nv + cb + align_up(sizeof(double) * (size_t)(max_iter + 2));
+  const size_t vb = 3 * nv + cb + align_up(sizeof(double) * kWyRing);
   NYS_TRY(ctx->vecs.reserve(vb));
   char* v = static_cast<char*>(ctx->vecs.ptr);
   ws->w = reinterpret_cast<double*>(v);
   ws->p = reinterpret_cast<double*>(v + nv);
   ws->cvec = reinterpret_cast<double*>(v + 2 * nv);
   ws->wy = reinterpret_cast<double*>(v + 2 * nv + cb);
-  ws->w2 = reinterpret_cast<double*>(v + 2 * nv + cb +
-                                     align_up(sizeof(double) * (size_t)(max_iter + 2)));
+  ws->w2 = reinterpret_cast<double*>(v + 2 * nv + cb + align_up(sizeof(double) * kWyRing));
   ws->rj = red_block(pl.ny());
   ws->nred = nblk(d, ws->rj);
   ws->nvec = nblk(d, kVecBlock);
@@ -676,6 +691,7 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   ctx->core_ws.release();
   ctx->admm_ws.release();
   ctx->svm_ws.release();
+  ctx->check.release();
   pool_unregister_stream(ctx->device, ctx->stream);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
@@ -820,6 +836,7 @@ nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, d
   NYS_TRY(validate_dense(A));
   if (!(rho + c >= 0.0)) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  NYS_TRY(check_vector(ctx, D, A->n, 0));
   GramPlan pl;
   NYS_TRY(ctx_gram_plan(ctx, *A, &pl));
   PcgWs ws;
@@ -847,6 +864,7 @@ nys_status pcg_solve(nys_ctx ctx, const nys_dense* A, const double* D, double c,
     return NYS_ERR_INVALID;
   if (F != nullptr && F->d != A->d) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  NYS_TRY(check_vector(ctx, D, A->n, 0));
   return pcg_run(ctx, *A, D, c, rho, F, rhs, x, *opts, info);
 }
 

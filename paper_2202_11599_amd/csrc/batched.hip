@@ -170,7 +170,7 @@ __global__ __launch_bounds__(1024) void k_breduce(const BInst* __restrict__ inst
       }
       return;
     }
-    alpha = I.wy[k] / pv;
+    alpha = I.wy[k & (kWyRing - 1)] / pv;
   }
   __syncthreads();
   if (grp != 0) return;
@@ -308,7 +308,7 @@ __device__ void bupdate_body(const BInst& I, int blk, int mode) {
     double y = I.w[j];
     const UT* u = static_cast<const UT*>(I.U) + j;
     for (int i = 0; i < r; ++i) y = fma((double)u[(int64_t)i * I.d], g[i], y);
-    pj = (mode == 0) ? y + (wy_new / I.wy[k]) * I.p[j] : y;
+    pj = (mode == 0) ? y + (wy_new / I.wy[k & (kWyRing - 1)]) * I.p[j] : y;
     I.p[j] = pj;
   }
   double pp = wave_sum(pj * pj);
@@ -317,7 +317,7 @@ __device__ void bupdate_body(const BInst& I, int blk, int mode) {
   __syncthreads();
   if (tid == 0) {
     I.pppart[blk] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
-    if (blk == 0) I.wy[mode == 1 ? 0 : k + 1] = wy_new;
+    if (blk == 0) I.wy[mode == 1 ? 0 : (k + 1) & (kWyRing - 1)] = wy_new;
   }
 }
 
@@ -611,7 +611,7 @@ nys_status batch_build(nys_ctx ctx, int count, const nys_problem* P, const nys_a
     const int ldy = (int)((d + 63) / 64 * 64);
     off[q] = bytes;
     bytes += 5 * au(sizeof(double) * d) + au(sizeof(double) * 1024) +
-             au(sizeof(double) * (max_iter + 2)) + au(sizeof(double) * (size_t)G * ldy) +
+             au(sizeof(double) * kWyRing) + au(sizeof(double) * (size_t)G * ldy) +
              au(sizeof(double) * G) + 3 * au(sizeof(double) * ((d + 63) / 64)) +
              au(sizeof(double) * ((d + 255) / 256)) + au(sizeof(double) * kNS * ((d + 255) / 256)) +
              au(sizeof(PcgDev));
@@ -682,7 +682,7 @@ nys_status batch_build(nys_ctx ctx, int count, const nys_problem* P, const nys_a
     I.atb = take(au(sizeof(double) * d));
     (void)take(au(sizeof(double) * d));
     I.cvec = take(au(sizeof(double) * 1024));
-    I.wy = take(au(sizeof(double) * (max_iter + 2)));
+    I.wy = take(au(sizeof(double) * kWyRing));
     I.ypart = take(au(sizeof(double) * (size_t)G * ldy));
     I.qpart = take(au(sizeof(double) * G));
     I.G = G;
@@ -958,10 +958,13 @@ nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
       f.r_d = O[q].rho * std::sqrt(v[1]);
       f.rank = F[q]->r;
       const double res2 = check ? ps.true_rr : ps.ww;
-      f.status = (ps.flags & kFlagNonfinite) ? NYS_ERR_NONFINITE
-                 : (ps.flags & kFlagBreakdown) ? NYS_ERR_BREAKDOWN
-                 : (!(res2 <= ps.thr2) && !(ps.flags & kFlagZeroRhs)) ? NYS_ERR_MAXITER
-                                                                     : NYS_OK;
+      const nys_status step_status =
+          (ps.flags & kFlagNonfinite) ? NYS_ERR_NONFINITE
+          : (ps.flags & kFlagBreakdown) ? NYS_ERR_BREAKDOWN
+          : (!(res2 <= ps.thr2) && !(ps.flags & kFlagZeroRhs)) ? NYS_ERR_MAXITER
+                                                              : NYS_OK;
+      if (step_status == NYS_ERR_MAXITER) f.maxiter_solves += 1;
+      if (f.status == NYS_OK) f.status = step_status;   // sticky: first non-OK
       if (check && ps.true_rr >= 0.0)
         f.true_res_max = std::max(f.true_res_max,
                                   ps.rr > 0.0 ? std::sqrt(ps.true_rr / ps.rr) : 0.0);
@@ -980,7 +983,7 @@ nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
         stop = true;
         f.converged = 1;
       }
-      if (f.status == NYS_ERR_NONFINITE || f.status == NYS_ERR_BREAKDOWN) stop = true;
+      if (step_status == NYS_ERR_NONFINITE || step_status == NYS_ERR_BREAKDOWN) stop = true;
       if (stop) {
         h.active = 0;
         changed = true;

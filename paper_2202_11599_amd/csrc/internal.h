@@ -97,6 +97,10 @@ __device__ __forceinline__ void publish_state(const int* done, PcgDev* note, int
   }
 }
 #endif
+// w^T y of PCG iteration k lives in wy[k % kWyRing]: iteration k reads entry
+// k and writes entry k + 1, and the kernels of one solve run in stream order,
+// so a ring of four suffices whatever max_iter is.
+constexpr int kWyRing = 4;
 constexpr int kFlagBreakdown = 1;
 constexpr int kFlagNonfinite = 2;
 constexpr int kFlagZeroRhs = 4;
@@ -167,6 +171,9 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
                     const double* p, const double* aux, double* auxout, double* ypart,
                     double* qpart, const int* done, PcgDev* note = nullptr, int note_seq = 0);
 nys_status validate_dense(const nys_dense* A);
+// Device check of a caller's n-vector (kind as launch_check_vec); synchronises.
+// NYS_ERR_NONFINITE for NaN/Inf, NYS_ERR_INVALID for a broken rule.
+nys_status check_vector(nys_ctx ctx, const double* v, int64_t n, int kind);
 nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws);
 nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out);
 
@@ -247,6 +254,7 @@ struct nys_ctx_s {
   nys::DevBuf core_ws;   // FP64 core temporaries
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
   nys::DevBuf svm_ws;    // kernel SVM vectors (rhs, H z, scalars)
+  nys::DevBuf check;     // flag word of the argument checks
   void* host_pinned = nullptr;  // pinned readback area of kPinnedBytes
   void* host_pinned_dev = nullptr;  // the same memory as seen from the device
   int poll_seq = 0;              // last sequence number of a PCG state slot write
@@ -397,6 +405,11 @@ nys_status launch_u_c(const double* U, int64_t d, int r, const double* c, double
                       hipStream_t stream);
 nys_status launch_dot(const double* a, const double* b, int64_t d, double* out,
                       hipStream_t stream);
+// flags |= kCheck* bits of the caller vector v (n entries): kind 0 weights
+// (v >= 0), kind 1 labels (v in {0, 1}); NaN/Inf set kCheckNonfinite
+constexpr int kCheckBad = 1;
+constexpr int kCheckNonfinite = 2;
+nys_status launch_check_vec(const double* v, int64_t n, int kind, int* flags, hipStream_t stream);
 // mode 0: PCG iteration k test + dots, 1: PCG init (threshold from ||rhs||) test + dots,
 // 2: dots only, 3: store sum(wwpart) into st->true_rr
 nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const double* w,

@@ -900,6 +900,13 @@ extern "C" {
 
 nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c,
                       const double* omega, int r, nys_dtype prec, nys_factor* F) {
+  if (ctx == nullptr || F == nullptr || omega == nullptr) return NYS_ERR_INVALID;
+  NYS_TRY(validate_dense(A));
+  if (D != nullptr) {
+    // the weights are the Hessian of a convex loss, D >= 0 (Section 2.1)
+    NYS_TRY_HIP(hipSetDevice(ctx->device));
+    NYS_TRY(check_vector(ctx, D, A->n, 0));
+  }
   return sketch_round(ctx, A, D, c, omega, r, prec, F, -1.0, nullptr);
 }
 
@@ -915,6 +922,10 @@ nys_status nys_sketch_adaptive(nys_ctx ctx, const nys_dense* A, const double* D,
   NYS_TRY(validate_dense(A));
   if (s0 < 1 || s_max < s0 || s_max >= A->d || s_max > 1024 || !(rho > 0.0) || !(tol >= 1.0))
     return NYS_ERR_INVALID;
+  if (D != nullptr) {
+    NYS_TRY_HIP(hipSetDevice(ctx->device));
+    NYS_TRY(check_vector(ctx, D, A->n, 0));
+  }
   // kappa = (lambda_s + rho) / rho <= tol  <=>  lambda_s <= (tol - 1) rho, so a
   // round that does not stop is recognised by the inertia of G - (nu + (tol - 1) rho) I
   // and the eigendecomposition is only computed in the final round.

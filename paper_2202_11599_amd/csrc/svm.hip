@@ -525,7 +525,8 @@ nys_status svm_solve(nys_ctx ctx, const nys_svm_problem* P, const nys_svm_opts* 
     info.iters += 1;
     info.pcg_iters += pinfo.iters;
     info.pcg_max = std::max(info.pcg_max, pinfo.iters);
-    info.status = ps;
+    if (info.status == NYS_OK) info.status = ps;   // sticky: first non-OK
+    if (ps == NYS_ERR_MAXITER) info.maxiter_solves += 1;
     if (pinfo.true_res_norm >= 0.0)
       info.true_res_max = std::max(info.true_res_max, pinfo.rhs_norm > 0.0
                                                           ? pinfo.true_res_norm / pinfo.rhs_norm

@@ -6,6 +6,8 @@
 // order, which makes the value identical across workgroups without a grid
 // barrier.  Kernels of an iteration return at once when PcgDev::done is set,
 // so the host can enqueue several iterations between convergence checks.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace nys {
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(256) void k_reduce_update(
   double qv[4], pv4[4];
   pre_load(qpart, (op == 0 && !pre) ? Gq : 0, qv);
   pre_load(pppart, (op == 0 && !pre) ? npp : 0, pv4);
-  const double wyk = (op == 0) ? wy[k] : 0.0;
+  const double wyk = (op == 0) ? wy[k & (kWyRing - 1)] : 0.0;
   if (op == 0 && st->done) return;
   double pj = 0.0, xj = 0.0, wj = 0.0, rj = 0.0;
   if (own) {
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256) void k_precond_update(
     wj = w[j];
     if (mode == 0) pold = p[j];
   }
-  const double wyk = (mode == 0) ? wy[k] : 0.0;
+  const double wyk = (mode == 0) ? wy[k & (kWyRing - 1)] : 0.0;
   if (mode != 2 && st->done) {
     if (host_slot != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
       PcgDev h = *st;
@@ -466,7 +468,7 @@ __global__ __launch_bounds__(256) void k_precond_update(
   if (tid == 0) {
     pppart[blockIdx.x] = pp;
     if (blockIdx.x == 0) {
-      wy[mode == 1 ? 0 : k + 1] = wy_new;
+      wy[mode == 1 ? 0 : (k + 1) & (kWyRing - 1)] = wy_new;
       if (host_slot != nullptr) {
         PcgDev h = *st;
         h.k = seq;            // sequence number the host waits for
@@ -592,7 +594,33 @@ __global__ __launch_bounds__(256) void k_u_c(const double* __restrict__ U, int64
   out[j] = (a0 + a1) + (a2 + a3);
 }
 
+// Argument check of a caller's n-vector: bit kCheckBad when an entry breaks
+// the rule of `kind` (0 weights: v >= 0; 1 labels: v in {0, 1}), bit
+// kCheckNonfinite when an entry is NaN or infinite.  One atomicOr per wave
+// that found something.
+__global__ __launch_bounds__(256) void k_check_vec(const double* __restrict__ v, int64_t n,
+                                                   int kind, int* __restrict__ flags) {
+  int bits = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const double x = v[i];
+    if (!(fabs(x) <= 1.7976931348623157e308)) bits |= kCheckNonfinite;
+    else if (kind == 0 ? !(x >= 0.0) : !(x == 0.0 || x == 1.0)) bits |= kCheckBad;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off, 64);
+  if ((threadIdx.x & 63) == 0 && bits != 0) atomicOr(flags, bits);
+}
+
 }  // namespace
+
+nys_status launch_check_vec(const double* v, int64_t n, int kind, int* flags,
+                            hipStream_t stream) {
+  if (n <= 0) return NYS_OK;
+  const int64_t g = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_check_vec, dim3((unsigned)g), dim3(256), 0, stream, v, n, kind, flags);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
 
 nys_status launch_dot(const double* a, const double* b, int64_t d, double* out,
                       hipStream_t stream) {

@@ -89,7 +89,7 @@ class SvmInfo(C.Structure):
                 ("r_p", C.c_double), ("r_d", C.c_double), ("primal", C.c_double),
                 ("dual", C.c_double), ("gap", C.c_double), ("gap_rel", C.c_double),
                 ("bias", C.c_double), ("rank", C.c_int), ("converged", C.c_int),
-                ("status", C.c_int), ("true_res_max", C.c_double)]
+                ("status", C.c_int), ("true_res_max", C.c_double), ("maxiter_solves", C.c_int)]
 
 
 class AdmmState(C.Structure):
@@ -100,7 +100,8 @@ class AdmmInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("pcg_iters", C.c_long), ("pcg_max", C.c_int),
                 ("r_p", C.c_double), ("r_d", C.c_double), ("eta", C.c_double),
                 ("obj", C.c_double), ("rank", C.c_int), ("converged", C.c_int),
-                ("status", C.c_int), ("ws_used", C.c_int), ("true_res_max", C.c_double)]
+                ("status", C.c_int), ("ws_used", C.c_int), ("true_res_max", C.c_double),
+                ("maxiter_solves", C.c_int)]
 
 
 def lib():
@@ -450,12 +451,20 @@ def pcg_solve_sym(ctx: Context, K: torch.Tensor, rhs: torch.Tensor, x: torch.Ten
     return info
 
 
+def _keep(struct, *objs):
+    """Attach the tensors and handles whose addresses `struct` holds, so that
+    they live as long as the struct does (ctypes stores only the raw pointer)."""
+    struct._keep = tuple(o for o in objs if o is not None)
+    return struct
+
+
 def svm_opts(rho, rank, omega_rows: Optional[torch.Tensor] = None, pcg: Optional[PcgOpts] = None,
              max_iter=100, gap_tol=0.0, gap_every=10, true_res_every=1,
              factor: Optional["Factor"] = None) -> SvmOpts:
-    return SvmOpts(float(rho), int(rank), None if omega_rows is None else omega_rows.data_ptr(),
-                   pcg or pcg_opts(), int(max_iter), float(gap_tol), int(gap_every),
-                   int(true_res_every), None if factor is None else factor.h.value)
+    o = SvmOpts(float(rho), int(rank), None if omega_rows is None else omega_rows.data_ptr(),
+                pcg or pcg_opts(), int(max_iter), float(gap_tol), int(gap_every),
+                int(true_res_every), None if factor is None else factor.h.value)
+    return _keep(o, omega_rows, factor)
 
 
 def svm_solve(ctx: Context, H: torch.Tensor, b: torch.Tensor, Cbox: float, opts: SvmOpts,
@@ -480,20 +489,21 @@ def admm_opts(rho, rank, omega_rows: Optional[torch.Tensor], rank_max=0, ada_tol
     for t, name in ((ws_features, "ws_features"), (ws_target, "ws_target")):
         if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous CUDA float64 tensor")
-    return AdmmOpts(float(rho), int(rank), int(rank_max), float(ada_tol), int(resketch_every),
-                    int(sketch_prec), None if omega_rows is None else omega_rows.data_ptr(),
-                    pcg or pcg_opts(), int(bool(tol_schedule)),
-                    int(max_iter), float(eps_abs), float(eps_rel), float(rel_change_tol),
-                    float(kkt_tol), int(kkt_every), None if factor is None else factor.h.value,
-                    None if warm_start is None else warm_start.h.value, int(bool(ws_analytic)),
-                    int(bool(ws_every_step)),
-                    None if ws_features is None else ws_features.data_ptr(),
-                    None if ws_target is None else ws_target.data_ptr(), int(true_res_every))
+    o = AdmmOpts(float(rho), int(rank), int(rank_max), float(ada_tol), int(resketch_every),
+                 int(sketch_prec), None if omega_rows is None else omega_rows.data_ptr(),
+                 pcg or pcg_opts(), int(bool(tol_schedule)),
+                 int(max_iter), float(eps_abs), float(eps_rel), float(rel_change_tol),
+                 float(kkt_tol), int(kkt_every), None if factor is None else factor.h.value,
+                 None if warm_start is None else warm_start.h.value, int(bool(ws_analytic)),
+                 int(bool(ws_every_step)),
+                 None if ws_features is None else ws_features.data_ptr(),
+                 None if ws_target is None else ws_target.data_ptr(), int(true_res_every))
+    return _keep(o, omega_rows, factor, warm_start, ws_features, ws_target)
 
 
 def problem(A: torch.Tensor, b: torch.Tensor, gamma: float, loss=NYS_LOSS_LS, c: float = 0.0) -> Problem:
     _vec(b, A.shape[0], "b")
-    return Problem(int(loss), dense(A), b.data_ptr(), float(gamma), float(c))
+    return _keep(Problem(int(loss), dense(A), b.data_ptr(), float(gamma), float(c)), A, b)
 
 
 class State:

@@ -58,3 +58,50 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(N.Dense) == 40
     assert ctypes.sizeof(N.PcgOpts) == 32
     assert ctypes.sizeof(N.PcgInfo) == 40
+
+
+def test_struct_layouts_match_c_compiler(tmp_path):
+    # every option/info struct of the header, as gcc lays it out, against the
+    # ctypes mirror of the binding (size and the offset of the last field)
+    from paper_2202_11599_amd import nysadmm as N
+    pairs = [("nys_dense", N.Dense, "data"), ("nys_pcg_opts", N.PcgOpts, "max_restarts"),
+             ("nys_pcg_info", N.PcgInfo, "status"), ("nys_problem", N.Problem, "c"),
+             ("nys_admm_opts", N.AdmmOpts, "true_res_every"),
+             ("nys_admm_state", N.AdmmState, "k"),
+             ("nys_admm_info", N.AdmmInfo, "maxiter_solves"),
+             ("nys_svm_problem", N.SvmProblem, "C"), ("nys_svm_opts", N.SvmOpts, "factor"),
+             ("nys_svm_info", N.SvmInfo, "maxiter_solves")]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "nysadmm.h"', "int main(void){"]
+    for cname, _, last in pairs:
+        src.append(f'printf("%zu %zu\\n", sizeof({cname}), offsetof({cname}, {last}));')
+    src.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for (cname, cls, last), line in zip(pairs, out):
+        size, off = map(int, line.split())
+        assert ctypes.sizeof(cls) == size, cname
+        assert getattr(cls, last).offset == off, cname
+
+
+def test_option_structs_keep_their_tensors_alive():
+    # the structs carry raw device addresses; the binding must hold the
+    # tensors (and handles) they point to for as long as the struct lives
+    import gc
+    import weakref
+    import torch
+    from paper_2202_11599_amd import nysadmm as N
+    om = torch.zeros(3, 8, dtype=torch.float64)
+    refs = [weakref.ref(om)]
+    o = N.admm_opts(1.0, 3, om)
+    s = N.svm_opts(1.0, 3, om)
+    del om
+    gc.collect()
+    assert refs[0]() is not None
+    assert o.omega == refs[0]().data_ptr() and s.omega == refs[0]().data_ptr()
+    del o, s
+    gc.collect()
+    assert refs[0]() is None
