@@ -48,11 +48,13 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
-    ap.add_argument("--true-res-every", type=int, default=10,
+    ap.add_argument("--true-res-every", type=int, default=1,
                     help="check the FP64 true residual of every k-th subproblem (and the last "
-                         "of a run); the others stop PCG on its recursive residual")
+                         "of a run); the others stop PCG on its recursive residual (the "
+                         "headline checks every solve; a 1-in-10 variant is reported beside it)")
     ap.add_argument("--workload",
-                    choices=["lasso", "logistic", "path", "learned", "cg", "svm", "sparse"],
+                    choices=["lasso", "logistic", "path", "learned", "cg", "svm", "sparse",
+                             "precision_path"],
                     default="lasso",
                     help="lasso: 100000x4000 adaptive rank (default line); logistic: 200000x2000 "
                          "l1-logistic; path: 64 uneven lasso instances x 16 gammas, batched; "
@@ -62,6 +64,12 @@ def parse():
     ap.add_argument("--gammas", type=int, default=16)
     ap.add_argument("--copy-reference", action="store_true",
                     help="also run one 1.6 GB device copy (reference for HBM byte counters)")
+    ap.add_argument("--host-data", action="store_true",
+                    help="draw the lasso matrix on the host and copy it over (same recipe, "
+                         "another random stream; for runs under a counter-collecting profiler)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs of this bench (FETCH_SIZE, then "
+                         "WRITE_SIZE, with --copy-reference) into profiles/gram_traffic.json")
     return ap.parse_args()
 
 
@@ -76,22 +84,104 @@ def traffic_record(n, d):
     """HBM bytes per matvec-pair launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "gram_traffic.json")
-    csrc = os.path.join(ROOT, "paper_2202_11599_amd", "csrc")
     try:
         rec = json.load(open(path))
-        h = hashlib.sha256()
-        for f in ("gemv.hip", "gram_device.h"):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-        sha = h.hexdigest()
-        if rec.get("kernel_source_sha256") != sha or rec.get("n") != n or rec.get("d") != d:
+        if rec.get("kernel_source_sha256") != kernel_source_sha() or rec.get("n") != n or \
+                rec.get("d") != d:
             return None
         return rec.get("bytes_per_launch")
     except Exception:
         return None
 
 
+def failed_solves(N, info):
+    """Subproblems of an ADMM run that did not reach the PCG tolerance (stopped
+    at max_iter), plus one if the run itself ended on another error."""
+    return int(info.maxiter_solves) + int(info.status not in (N.NYS_OK, N.NYS_ERR_MAXITER))
+
+
+def kernel_source_sha():
+    csrc = os.path.join(ROOT, "paper_2202_11599_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("gemv.hip", "gram_device.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def _pmc_rows(d, counter):
+    """(kernel name, counter value) per dispatch from a rocprofv3 --pmc csv run."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"]),
+                                 int(r.get("Dispatch_Id", 0))))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {d}")
+    return rows
+
+
+def pmc_summary(fetch_dir, write_dir, n, d, commands):
+    """HBM bytes per full matvec-pair launch from FETCH_SIZE / WRITE_SIZE (KiB
+    per dispatch), each scaled by what the same counter reads for the
+    1.6e9-byte device copy of the same run.  Full passes are the dispatches of
+    the most frequent k_gram instantiation that read at least half of the
+    largest; launches queued past PCG convergence return at once and read
+    almost nothing."""
+    import statistics
+    out = {}
+    for key, dd, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _pmc_rows(dd, counter)
+        gram = [r for r in rows if "k_gram" in r[0]]
+        names = {}
+        for r in gram:
+            names[r[0]] = names.get(r[0], 0) + 1
+        kname = max(names, key=names.get)
+        vals = [v for nm, v, _ in gram if nm == kname]
+        top = max(vals)
+        full = [v for v in vals if v >= 0.5 * top] if key == "fetch" else None
+        out[key] = dict(kernel=kname, values=vals, full=full,
+                        copy=max(v for nm, v, _ in rows if "k_gram" not in nm))
+    # a write-counter dispatch is a full pass when its fetch twin is (same order)
+    f, w = out["fetch"], out["write"]
+    fvals, wvals = f["values"], w["values"]
+    m = min(len(fvals), len(wvals))
+    wfull = [wvals[i] for i in range(m) if fvals[i] >= 0.5 * max(fvals)]
+    fetch_kib = statistics.mean(f["full"])
+    write_kib = statistics.mean(wfull)
+    copy_bytes = 1.6e9
+    ff = copy_bytes / (f["copy"] * 1024)
+    wf = copy_bytes / (w["copy"] * 1024)
+    rec = {
+        "kernel": f["kernel"],
+        "kernel_source_sha256": kernel_source_sha(),
+        "kernel_source": ["paper_2202_11599_amd/csrc/gemv.hip",
+                          "paper_2202_11599_amd/csrc/gram_device.h"],
+        "n": n, "d": d,
+        "full_passes": len(f["full"]),
+        "fetch_kib_per_dispatch": round(fetch_kib, 1),
+        "write_kib_per_dispatch": round(write_kib, 1),
+        "copy_reference": {"bytes": int(copy_bytes), "fetch_kib": round(f["copy"], 1),
+                           "write_kib": round(w["copy"], 1)},
+        "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+        "bytes_per_launch": int(round(fetch_kib * 1024 * ff + write_kib * 1024 * wf)),
+        "algorithmic_bytes_per_launch": float(n) * d * 4,
+        "commands": commands,
+        "note": ("per dispatch: mean over the full passes of the matvec-pair kernel in the bench "
+                 "run (launches queued past PCG convergence excluded); factors scale the counters "
+                 "so that the 1.6e9-byte device copy of the same run reads 1.6e9 fetched and "
+                 "1.6e9 written bytes"),
+    }
+    return rec
+
+
 def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, profile=False):
     import torch
+    if steps <= 0:
+        return None
     infos = []
     ranks = []
     step_rates = []
@@ -116,7 +206,7 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, prof
         info = N.admm_solve(ctx, [prob], [opts], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
         infos.append((info.pcg_iters, info.iters, info.pcg_max, info.eta))
         tr_max = max(tr_max, info.true_res_max)
-        bad += info.status != N.NYS_OK
+        bad += failed_solves(N, info)
         F.close()
         torch.cuda.synchronize()
         step_rates.append(info.iters / (time.perf_counter() - ts))
@@ -220,7 +310,7 @@ def bench_logistic(args, N, synth, torch):
             info = N.admm_solve(ctx, [prob], [opts], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
             tot += info.iters
             pcg += info.pcg_iters
-            bad += info.status != N.NYS_OK
+            bad += failed_solves(N, info)
             trm = max(trm, info.true_res_max)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -341,7 +431,7 @@ def bench_svm(args, N, synth, torch):
             info = N.svm_solve(ctx, H, b, 1.0, o, st, allow=(N.NYS_OK, N.NYS_ERR_MAXITER))
             tot += info.iters
             pcg += info.pcg_iters
-            bad += (info.status != N.NYS_OK) + (info.converged != 1)
+            bad += failed_solves(N, info) + (info.converged != 1)
             trm = max(trm, info.true_res_max)
             last = info
             F.close()
@@ -427,6 +517,85 @@ def svm_cpu_baseline(H, b, omega, rho, iters_per_solve, cpu_iters):
     }
 
 
+def bench_precision_path(args, N, synth, torch):
+    """Lasso precision path on an STL-10-shaped matrix (Section 5, Figure
+    precisionpath; Table dataset: 13000 x 27648, dense): time from a cold start
+    until the relative KKT residual eq. (31) falls below eps, for eps from 1 to
+    1e-3, NysADMM (rank 50, the paper's sketch size, FP32 sketch) against
+    inexact ADMM with plain CG, both with the paper's subproblem tolerance
+    eps^{k+1} = sqrt(r_p r_d) and gamma = 1.  The data set is not available:
+    A = 100 Q1 diag(j^-0.5) Q2^T (Haar factors, FP32), x* 2% sparse,
+    b = A x* + N(0, 1) noise; rho = 10.  The matrix is wider than one
+    workgroup's row, so every pair takes the two-pass wide form (A read
+    twice).  eta is checked every 5 iterations (one more pair each, timed).
+    value = NysADMM subproblem solves/s over its run to eps = 1e-2."""
+    n, d, r, rho, gamma = 13000, 27648, 50, 10.0, 1.0
+    t0 = time.perf_counter()
+    a64 = synth.decay_matrix(n, d, 0.5, seed=0, device="cuda")
+    A = (100.0 * a64).to(torch.float32).contiguous()
+    del a64
+    x = synth.sparse_truth(d, 0.02, 0, "cuda")
+    b = (A.double() @ x + synth.gaussian((n,), 0, "noise", "cuda")).contiguous()
+    omega = synth.omega_raw(d, r, seed=0, device="cuda").contiguous()
+    torch.cuda.synchronize()
+    print(f"[bench] generated {n}x{d} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    ctx = N.Context()
+    prob = N.problem(A, b, gamma)
+
+    def run(eps, cg, profile=False):
+        if profile:
+            ctx.profile_start()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o = N.admm_opts(rho, 0 if cg else r, None if cg else omega, sketch_prec=N.NYS_F32,
+                        pcg=N.pcg_opts(tol=1e-6, max_iter=20000), tol_schedule=True,
+                        max_iter=5000, kkt_tol=eps, kkt_every=5,
+                        true_res_every=args.true_res_every)
+        st = N.State(d, "cuda")
+        info = N.admm_solve(ctx, [prob], [o], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        prof = ctx.profile_stop() if profile else None
+        return wall, info, prof
+
+    run(1e-1, False)
+    run(1e-1, True)
+    rows, value, prof = [], None, None
+    for eps in (1.0, 1e-1, 1e-2, 1e-3):
+        wn, inn, pr = run(eps, False, profile=(eps == 1e-2))
+        prof = pr or prof
+        wc, inc, _ = run(eps, True)
+        row = {"eps": eps,
+               "nysadmm": {"seconds": round(wn, 4), "admm_iters": inn.iters,
+                           "pcg_iters": inn.pcg_iters, "eta": inn.eta,
+                           "converged": inn.converged, "unconverged_solves": failed_solves(N, inn)},
+               "cg_admm": {"seconds": round(wc, 4), "admm_iters": inc.iters,
+                           "pcg_iters": inc.pcg_iters, "eta": inc.eta,
+                           "converged": inc.converged, "unconverged_solves": failed_solves(N, inc)},
+               "speedup": round(wc / wn, 2)}
+        rows.append(row)
+        print(f"[bench] eps {eps:g}: NysADMM {row['nysadmm']} CG {row['cg_admm']}",
+              file=sys.stderr, flush=True)
+        if eps == 1e-2:
+            value = inn.iters / wn
+    out = base_record(value, 1, 1, 0.0, "f32", {
+        "workload": f"lasso-precision-path-stl10-shape-{n}x{d}-fp32-sigma_j=100j^-0.5-"
+                    f"gamma=1-rho=10-rank{r}-nysadmm-vs-cg-admm",
+        "n": n, "d": d, "rho": rho, "gamma": gamma, "rank": r, "kkt_every": 5,
+        "tol_schedule": "sqrt(r_p r_d)"})
+    out["ms_per_step"] = None
+    out["roofline"] = roofline(prof, 2.0 * n * d * 4, n, d)
+    out["roofline"]["kernel"] = ("wide pair: row dots per column block + epilogue + A^T pass "
+                                 "(A read twice)")
+    out["roofline"]["traffic"] = None
+    out["roofline"]["note"] = "pair launches of the NysADMM run to eps = 1e-2; 2 n d 4 bytes each"
+    out["precision_path"] = rows
+    out["paper_context"] = ("paper, Tables lassolowres/lassohighres, STL-10 on 128 CPU cores: "
+                            "NysADMM 165 s at eps 1e-1, 406 s at 1e-2 (real data, not comparable)")
+    return out
+
+
 def bench_sparse(args, N, synth, torch):
     """Sparse lasso shaped like E2006.train (16087 x 150348, 0.8% nonzero):
     bag-of-words rows with Zipf column popularity, unit-norm rows; gamma =
@@ -458,7 +627,7 @@ def bench_sparse(args, N, synth, torch):
             info = N.admm_solve(ctx, [prob], [o], [st], allow=(N.NYS_OK, N.NYS_ERR_MAXITER))[0]
             tot += info.iters
             pcg += info.pcg_iters
-            bad += info.status != N.NYS_OK
+            bad += failed_solves(N, info)
             trm = max(trm, info.true_res_max)
             eta = info.eta
             F.close()
@@ -516,7 +685,7 @@ def bench_path(args, N, synth, torch):
             trm = max([trm] + [i.true_res_max for i in infos])
             solves += sum(i.iters for i in infos)
             pcg += sum(i.pcg_iters for i in infos)
-            bad += sum(i.status != N.NYS_OK for i in infos)
+            bad += sum(failed_solves(N, i) for i in infos)
         for F in Fs:
             F.close()
         torch.cuda.synchronize()
@@ -611,6 +780,20 @@ def bench_learned(args, N, synth, torch):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        cmd = ("cd /tmp && export TMPDIR=/tmp && cd $R && timeout -s KILL 300 rocprofv3 --pmc {c} "
+               "--kernel-include-regex 'k_gram|elementwise|copy' -d {d} -o run --output-format csv "
+               "-- python bench.py --steps 1 --warmup 0 --admm-iters 5 --no-mixed "
+               "--no-cpu-baseline --copy-reference --host-data")
+        rec = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n, args.d,
+                          [cmd.format(c="FETCH_SIZE", d="gpurun_out/pmc_fetch"),
+                           cmd.format(c="WRITE_SIZE", d="gpurun_out/pmc_write")])
+        path = os.path.join(ROOT, "profiles", "gram_traffic.json")
+        with open(path, "w") as fh:
+            json.dump(rec, fh, indent=2)
+            fh.write("\n")
+        print(json.dumps(rec, indent=2))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
               f"(--gpus {args.gpus} requested); run with --gpus 1", file=sys.stderr)
@@ -623,7 +806,7 @@ def main():
         torch.cuda.set_device(0)
         fn = {"logistic": bench_logistic, "path": bench_path,
               "learned": bench_learned, "cg": bench_cg, "svm": bench_svm,
-              "sparse": bench_sparse}[args.workload]
+              "sparse": bench_sparse, "precision_path": bench_precision_path}[args.workload]
         print(json.dumps(fn(args, N, synth, torch)), flush=True)
         return
     from paper_2202_11599_amd import nysadmm as N
@@ -631,9 +814,11 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    p = synth.lasso_decay(args.n, args.d, 0.8, seed=0, device="cuda", dtype=torch.float32,
-                          frac=0.02, noise=0.01, gamma_frac=LASSO_GAMMA_FRAC, rho=1e-4, rank=50, s_max=800,
-                          pcg_tol=1e-6)
+    p = synth.lasso_decay(args.n, args.d, 0.8, seed=0, device="cpu" if args.host_data else "cuda",
+                          dtype=torch.float32, frac=0.02, noise=0.01, gamma_frac=LASSO_GAMMA_FRAC,
+                          rho=1e-4, rank=50, s_max=800, pcg_tol=1e-6)
+    if args.host_data:
+        p.A, p.b, p.omega = p.A.cuda(), p.b.cuda(), p.omega.cuda()
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     print(f"[bench] generated {args.n}x{args.d} in {gen_s:.1f} s", file=sys.stderr, flush=True)
@@ -654,10 +839,11 @@ def main():
                       profile=True)
     print(f"[bench] plain fp32: {plain['solves'] / plain['wall']:.1f} solves/s", file=sys.stderr,
           flush=True)
-    # the same steps with the FP64 true residual formed after every solve
-    strict = run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.steps, args.admm_iters, 1)
-    print(f"[bench] true residual every solve: {strict['solves'] / strict['wall']:.1f} solves/s",
-          file=sys.stderr, flush=True)
+    # the same steps with the FP64 true residual formed at every 10th solve only
+    # (the others stop on the recursive residual and carry H_rho x = rhs - w)
+    carried = run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.steps, args.admm_iters, 10)
+    print(f"[bench] true residual every 10th solve: "
+          f"{carried['solves'] / carried['wall']:.1f} solves/s", file=sys.stderr, flush=True)
     mixed = None
     if not args.no_mixed:
         run_steps(N, ctx, A, prob, omega, p, N.NYS_BF16, 1, args.admm_iters, tre)
@@ -704,7 +890,7 @@ def main():
             "solves_per_s_excl_sketch": round(plain["solves"] / (plain["wall"] - plain["sketch_s"]), 3),
             "sketch_ms": round(1e3 * plain["sketch_s"] / args.steps, 2),
             "pcg_iters_mean": round(plain["pcg_mean"], 3), "pcg_iters_max": plain["pcg_max"],
-            "unconverged_steps": plain["unconverged"], "kkt_eta_after_step": plain["eta"],
+            "unconverged_solves": plain["unconverged"], "kkt_eta_after_step": plain["eta"],
             "true_rel_res_max": plain["true_res_max"],
             "per_step_solves_per_s": {"min": round(min(plain["step_rates"]), 3),
                                       "max": round(max(plain["step_rates"]), 3)},
@@ -714,11 +900,11 @@ def main():
         # d-vectors; the pair passes per solve are those the event timing saw
         "solve_roofline": solve_roofline(plain, launches, args.n, args.d),
         "gemv_hbm_gbs": round(achieved, 1),
-        "true_residual_every_solve": {
-            "solves_per_s": round(strict["solves"] / strict["wall"], 3),
-            "pcg_iters_mean": round(strict["pcg_mean"], 3),
-            "unconverged_steps": strict["unconverged"],
-            "true_rel_res_max": strict["true_res_max"],
+        "true_residual_every_10th_solve": {
+            "solves_per_s": round(carried["solves"] / carried["wall"], 3),
+            "pcg_iters_mean": round(carried["pcg_mean"], 3),
+            "unconverged_solves": carried["unconverged"],
+            "true_rel_res_max": carried["true_res_max"],
         },
     }
     if mixed is not None:
@@ -727,7 +913,7 @@ def main():
             "solves_per_s_excl_sketch": round(mixed["solves"] / (mixed["wall"] - mixed["sketch_s"]), 3),
             "sketch_ms": round(1e3 * mixed["sketch_s"] / args.steps, 2),
             "pcg_iters_mean": round(mixed["pcg_mean"], 3), "rank_final": mixed["ranks"][-1],
-            "unconverged_steps": mixed["unconverged"], "kkt_eta_after_step": mixed["eta"],
+            "unconverged_solves": mixed["unconverged"], "kkt_eta_after_step": mixed["eta"],
             "true_rel_res_max": mixed["true_res_max"],
             "vs_plain_fp32": round((mixed["solves"] / mixed["wall"]) / value, 4),
         }

@@ -96,6 +96,40 @@ const char* nys_status_string(nys_status s);
 /* Bytes of device workspace currently held by the context. */
 size_t nys_ctx_workspace_bytes(nys_ctx ctx);
 
+/* Caller-supplied device memory (the boundary's "PyTorch for device memory"):
+ *
+ * nys_workspace_query writes to *bytes an upper bound of the device memory
+ * that admm_solve needs for `count` problems shaped like A at Nystrom rank at
+ * most r_max (r_max = 0: plain CG), any sketch precision and loss: the
+ * matvec partial sums (and the launch-shape tuner's trial buffer), the PCG
+ * and ADMM vectors, the sketch and FP64-core temporaries, max(count, 2)
+ * factors with their sketch state (two for a logistic refresh, one per
+ * instance when count > 1 runs batched), the batched path's buffers, and for
+ * a CSR A the handle's CSC copy; plus 1/8 + 16 MiB for the first-fit
+ * carving.  It covers one call at a time on the context; factors kept across
+ * calls, the warm-start network and pcg/sketch calls on wider shapes need
+ * their own share.
+ *
+ * nys_ctx_set_workspace hands the context [dev_ptr, dev_ptr + bytes), device
+ * memory of the context's device owned by the caller (e.g. a torch tensor).
+ * From then on every device buffer the library would allocate while serving a
+ * call on this context -- its own buffers, the factors and sparse handles it
+ * creates, the batched path's buffers -- is carved from that range, and a
+ * request that does not fit returns NYS_ERR_NOMEM; the library calls no
+ * hipMalloc for them (hipGraph instantiation in the batched path keeps its
+ * own runtime memory).  Setting a workspace releases the context's current
+ * buffers (the cached A^T b and H_rho x are recomputed at the next step);
+ * dev_ptr = NULL, bytes = 0 returns to the library's own allocation.
+ * Factors and sparse handles carved from the range keep their blocks until
+ * destroyed: destroy them before the caller frees the memory.  Blocks are
+ * reused in stream order; nys_ctx_set_stream synchronises the old stream of a
+ * context with a workspace.  nys_ctx_workspace_peak gives the largest number
+ * of bytes of the range in use at once since it was set (0 without one). */
+nys_status nys_workspace_query(nys_ctx ctx, const nys_dense* A, int r_max, int count,
+                               size_t* bytes);
+nys_status nys_ctx_set_workspace(nys_ctx ctx, void* dev_ptr, size_t bytes);
+size_t nys_ctx_workspace_peak(nys_ctx ctx);
+
 /* Kernel timing (instrumentation, not part of the method): while enabled the
  * library brackets every launch of the fused matvec-pair kernel with HIP
  * events on the context's stream.  nys_ctx_profile_stop synchronises the
@@ -162,6 +196,7 @@ nys_status nys_factor_destroy(nys_factor F);
  * p, v: device FP64 d-vectors, not overlapping.  rho + c >= 0. */
 nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, double c,
                              double rho, const double* p, double* v, double* pv_host);
+
 
 /* --------------------------------------------------------- preconditioner */
 
@@ -409,6 +444,17 @@ size_t nys_ws_param_count(int n_in, int hidden, int n_out);
 nys_status nys_ws_create(nys_ctx ctx, int n_in, int hidden, int n_out, const double* params_host,
                          const double* in_mean, const double* in_std, const double* out_scale,
                          int analytic_skip, nys_ws_model* out);
+/* Arithmetic of the network from now on (the parameters carry over):
+ *  NYS_F64   FP64 throughout (the default; matches the FP64 oracle to rounding);
+ *  NYS_F32   FP32 master weights, activations, gradients and Adam state, matrix
+ *            products on FP32 MFMA with FP32 accumulation;
+ *  NYS_BF16  as NYS_F32 with every matrix-product operand (weights, activations,
+ *            back-propagated gradients) rounded to BF16 for BF16 MFMA with FP32
+ *            accumulation; the FP32 master weights take the Adam steps.
+ * Switching to FP32/BF16 rounds the parameters to FP32 master copies; switching
+ * back widens them.  Adam state restarts.  Inputs, targets, weights, outputs
+ * and gradients cross the ABI in FP64 whatever the precision. */
+nys_status nys_ws_set_precision(nys_ctx ctx, nys_ws_model m, nys_dtype prec);
 nys_status nys_ws_get_params(nys_ctx ctx, nys_ws_model m, double* params_host);
 /* out (device, batch x n_out) = o for the batch x n_in device rows X */
 nys_status nys_ws_forward(nys_ctx ctx, nys_ws_model m, const double* X, int batch, double* out);

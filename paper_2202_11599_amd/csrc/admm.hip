@@ -138,13 +138,21 @@ struct AdmmWs {
 
 constexpr int kWsScratch = 4 * 1024 + 8;   // warm-start scratch (rank <= 1024)
 
+size_t admm_ws_bytes_of(int64_t n, int64_t d) {
+  const size_t vd = align_up(sizeof(double) * d);
+  const size_t vn = align_up(sizeof(double) * std::max<int64_t>(n, 1));
+  const size_t pb = align_up(sizeof(double) * kNS * nblk(d, 256));
+  const size_t sc = align_up(sizeof(double) * (kNS + 1));
+  return 4 * vd + vn + pb + sc + sizeof(double) * kWsScratch;
+}
+
 nys_status admm_workspace(nys_ctx ctx, int64_t n, int64_t d, AdmmWs* w) {
   w->nb = nblk(d, 256);
   const size_t vd = align_up(sizeof(double) * d);
   const size_t vn = align_up(sizeof(double) * std::max<int64_t>(n, 1));
   const size_t pb = align_up(sizeof(double) * kNS * w->nb);
   const size_t sc = align_up(sizeof(double) * (kNS + 1));
-  NYS_TRY(ctx->admm_ws.reserve(4 * vd + vn + pb + sc + sizeof(double) * kWsScratch));
+  NYS_TRY(ctx->admm_ws.reserve(admm_ws_bytes_of(n, d)));
   char* p = static_cast<char*>(ctx->admm_ws.ptr);
   w->atb = reinterpret_cast<double*>(p);
   w->rhs = reinterpret_cast<double*>(p + vd);
@@ -333,6 +341,8 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
   return ps == NYS_ERR_MAXITER ? NYS_OK : ps;
 }
 
+size_t admm_ws_bytes(int64_t n, int64_t d) { return admm_ws_bytes_of(n, d); }
+
 nys_status admm_kkt(nys_ctx ctx, const nys_problem& P, const double* z, double* eta, double* obj) {
   AdmmWs w;
   NYS_TRY(admm_workspace(ctx, P.A.n, P.A.d, &w));
@@ -375,6 +385,7 @@ nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, 
   if (S->x == nullptr || S->z == nullptr || S->u == nullptr) return NYS_ERR_INVALID;
   if (*F != nullptr && (*F)->d != P->A.d) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   // logistic labels b in {0, 1} (eq. 9)
   if (P->loss == NYS_LOSS_LOGISTIC) NYS_TRY(check_vector(ctx, P->b, P->A.n, 1));
   if (I) *I = nys_admm_info{};
@@ -395,6 +406,7 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
     if (S[q].x == nullptr || S[q].z == nullptr || S[q].u == nullptr) return NYS_ERR_INVALID;
   }
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   for (int q = 0; q < count; ++q)
     if (P[q].loss == NYS_LOSS_LOGISTIC) NYS_TRY(check_vector(ctx, P[q].b, P[q].A.n, 1));
   ctx->atb_key = AtbKey{};   // b may have changed in place since an earlier call
@@ -402,7 +414,7 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
   bool batched = count > 1;
   for (int q = 0; q < count; ++q) {
     if (P[q].loss != NYS_LOSS_LS || O[q].tol_schedule || O[q].kkt_tol > 0.0 || O[q].rank == 0 ||
-        P[q].A.dtype == NYS_CSR)
+        P[q].A.dtype == NYS_CSR || P[q].A.d > gram_max_cols(P[q].A.dtype))
       batched = false;
     if (O[q].warm_start != nullptr || O[q].ws_analytic || O[q].ws_features != nullptr ||
         O[q].ws_target != nullptr)

@@ -114,9 +114,76 @@ void pool_unregister_stream(int device, hipStream_t st) {
   if (!live) pool_trim_locked(P, device);
 }
 
+// ---- caller workspaces
+namespace {
+thread_local std::shared_ptr<Arena> tls_arena;
+constexpr size_t kArenaGrain = 256;
+}  // namespace
+
+Arena::Arena(void* p, size_t n, int dev) : device(dev) {
+  // the usable range starts at the first 256-byte boundary
+  const uintptr_t b = reinterpret_cast<uintptr_t>(p);
+  const uintptr_t a = (b + kArenaGrain - 1) / kArenaGrain * kArenaGrain;
+  const size_t skip = (size_t)(a - b);
+  base = reinterpret_cast<char*>(a);
+  bytes = n > skip ? (n - skip) / kArenaGrain * kArenaGrain : 0;
+  if (bytes > 0) free_blocks[0] = bytes;
+}
+
+void* Arena::alloc(size_t want) {
+  want = (std::max<size_t>(want, 1) + kArenaGrain - 1) / kArenaGrain * kArenaGrain;
+  std::lock_guard<std::mutex> g(mu);
+  for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+    if (it->second < want) continue;
+    const size_t off = it->first, sz = it->second;
+    free_blocks.erase(it);
+    if (sz > want) free_blocks[off + want] = sz - want;
+    in_use += want;
+    peak = std::max(peak, in_use);
+    return base + off;
+  }
+  return nullptr;
+}
+
+void Arena::free(void* p, size_t n) {
+  if (p == nullptr) return;
+  n = (std::max<size_t>(n, 1) + kArenaGrain - 1) / kArenaGrain * kArenaGrain;
+  std::lock_guard<std::mutex> g(mu);
+  size_t off = (size_t)(static_cast<char*>(p) - base);
+  in_use -= std::min(in_use, n);
+  auto next = free_blocks.lower_bound(off);
+  if (next != free_blocks.end() && off + n == next->first) {
+    n += next->second;
+    next = free_blocks.erase(next);
+  }
+  if (next != free_blocks.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      off = prev->first;
+      n += prev->second;
+      free_blocks.erase(prev);
+    }
+  }
+  free_blocks[off] = n;
+}
+
+CtxScope::CtxScope(nys_ctx ctx) : prev_(tls_arena) { tls_arena = ctx ? ctx->arena : nullptr; }
+CtxScope::~CtxScope() { tls_arena = prev_; }
+
 nys_status DevBuf::reserve(size_t want) {
   if (want <= bytes && ptr != nullptr) return NYS_OK;
   release();
+  if (std::shared_ptr<Arena> ar = tls_arena) {
+    // carved from the caller's workspace; never hipMalloc
+    want = (std::max<size_t>(want, 1) + kArenaGrain - 1) / kArenaGrain * kArenaGrain;
+    void* p = ar->alloc(want);
+    if (p == nullptr) return NYS_ERR_NOMEM;
+    ptr = p;
+    bytes = want;
+    device = ar->device;
+    arena = ar;
+    return NYS_OK;
+  }
   want = pool_round(want);
   int dev = 0;
   NYS_TRY_HIP(hipGetDevice(&dev));
@@ -162,6 +229,15 @@ nys_status DevBuf::reserve(size_t want) {
 
 void DevBuf::release() {
   if (ptr == nullptr) return;
+  if (arena) {
+    // the context's later work is ordered after every use of the block
+    arena->free(ptr, bytes);
+    arena.reset();
+    ptr = nullptr;
+    bytes = 0;
+    device = -1;
+    return;
+  }
   Pool& P = pool();
   int cur = 0;
   (void)hipGetDevice(&cur);
@@ -245,7 +321,8 @@ nys_status check_vector(nys_ctx ctx, const double* v, int64_t n, int kind) {
 // Carves the PCG workspace out of the context buffers.
 nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws) {
   const size_t yb = align_up(sizeof(double) * ((size_t)pl.ny() * pl.ldy));
-  const size_t ypb = yb + align_up(sizeof(double) * (size_t)std::max(pl.nq(), 1));
+  const size_t ypb = yb + align_up(sizeof(double) * (size_t)std::max(pl.nq(), 1)) +
+                     align_up(sizeof(double) * pl.tmp_doubles());
   NYS_TRY(ctx->ypart.reserve(ypb));
   ws->ypart = ctx->ypart.as<double>();
   ws->qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ypart.ptr) + yb);
@@ -300,6 +377,20 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
     if (ev) ctx->prof_used += 2;
     return NYS_OK;
   }
+  if (plan.wide) {
+    const bool ev = ctx->prof_on;
+    if (ev && ctx->prof_used + 2 > ctx->prof_ev.size())
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        NYS_TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+        ctx->prof_ev.push_back(e);
+      }
+    NYS_TRY(launch_wide(A, plan, mode, p, aux, auxout, ypart, qpart, done, ctx->stream,
+                        ev ? ctx->prof_ev[ctx->prof_used] : nullptr,
+                        ev ? ctx->prof_ev[ctx->prof_used + 1] : nullptr, note, note_seq));
+    if (ev && plan.grid > 0 && A.n > 0) ctx->prof_used += 2;
+    return NYS_OK;
+  }
   if (plan.grid == 0 || A.n == 0) {
     // nothing to launch: publish the state from a one-thread kernel instead
     if (note != nullptr) NYS_TRY(launch_note(reinterpret_cast<const PcgDev*>(done), note, note_seq,
@@ -334,6 +425,11 @@ nys_status ctx_gram(nys_ctx ctx, const nys_dense& A, const GramPlan& plan, int m
 nys_status ctx_gram_plan(nys_ctx ctx, const nys_dense& A, GramPlan* out) {
   if (const nys_sparse_s* S = as_sparse(A)) {
     *out = make_sparse_plan(S);
+    return NYS_OK;
+  }
+  if (A.d > gram_max_cols(A.dtype)) {
+    // wider than one workgroup's row: the two-pass form, one fixed shape
+    *out = make_wide_plan(A, ctx->num_cu);
     return NYS_OK;
   }
   const char* forced = getenv("NYSADMM_GRAM_PLAN");
@@ -726,6 +822,8 @@ nys_status nys_ctx_profile_stop(nys_ctx ctx, long* launches, double* total_ms) {
 
 nys_status nys_ctx_set_stream(nys_ctx ctx, void* hip_stream) {
   if (ctx == nullptr) return NYS_ERR_INVALID;
+  // workspace blocks are reused in stream order: finish the old stream's work
+  if (ctx->arena) NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
   // the block cache guards released blocks with events on every live stream
   pool_register_stream(ctx->device, static_cast<hipStream_t>(hip_stream));
   pool_unregister_stream(ctx->device, ctx->stream);
@@ -739,6 +837,101 @@ size_t nys_ctx_workspace_bytes(nys_ctx ctx) {
          ctx->core_ws.bytes + ctx->admm_ws.bytes;
 }
 
+nys_status nys_ctx_set_workspace(nys_ctx ctx, void* dev_ptr, size_t bytes) {
+  if (ctx == nullptr || (dev_ptr == nullptr) != (bytes == 0)) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  if (dev_ptr != nullptr) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, dev_ptr) != hipSuccess) {
+      (void)hipGetLastError();
+      return NYS_ERR_INVALID;
+    }
+    if (at.type != hipMemoryTypeDevice || at.device != ctx->device) return NYS_ERR_INVALID;
+  }
+  // the context's own buffers go back to where they came from; the cached
+  // A^T b and H_rho x go with them
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->ypart.release();
+  ctx->hx.release();
+  ctx->vecs.release();
+  ctx->small.release();
+  ctx->gemm_ws.release();
+  ctx->core_ws.release();
+  ctx->admm_ws.release();
+  ctx->svm_ws.release();
+  ctx->check.release();
+  ctx->atb_key = AtbKey{};
+  ctx->atb_next_k = -1;
+  ctx->hx_key = AtbKey{};
+  ctx->hx_tag = -1;
+  if (dev_ptr == nullptr) {
+    ctx->arena.reset();
+    return NYS_OK;
+  }
+  auto ar = std::make_shared<Arena>(dev_ptr, bytes, ctx->device);
+  if (ar->bytes == 0) return NYS_ERR_INVALID;
+  ctx->arena = ar;
+  return NYS_OK;
+}
+
+size_t nys_ctx_workspace_peak(nys_ctx ctx) {
+  if (ctx == nullptr || !ctx->arena) return 0;
+  std::lock_guard<std::mutex> g(ctx->arena->mu);
+  return ctx->arena->peak;
+}
+
+nys_status nys_workspace_query(nys_ctx ctx, const nys_dense* A, int r_max, int count,
+                               size_t* bytes) {
+  if (ctx == nullptr || bytes == nullptr || count < 1) return NYS_ERR_INVALID;
+  NYS_TRY(validate_dense(A));
+  if (r_max < 0 || r_max >= A->d || r_max > 1024) return NYS_ERR_INVALID;
+  const int64_t n = A->n, d = A->d;
+  size_t total = 0;
+  // matvec partial sums (the widest launch shape the tuner may pick), twice:
+  // the tuner's trial buffer and the kept one
+  size_t part = 0;
+  if (const nys_sparse_s* S = as_sparse(*A)) {
+    const GramPlan pl = make_sparse_plan(S);
+    part = align_up(sizeof(double) * (size_t)pl.ny() * pl.ldy) +
+           align_up(sizeof(double) * (size_t)std::max(pl.nq(), 1));
+    total += sparse_handle_bytes(n, d, S->nnz);
+  } else {
+    std::vector<GramPlan> c;
+    if (d > gram_max_cols(A->dtype)) {
+      c.push_back(make_wide_plan(*A, ctx->num_cu));
+    } else {
+      c = gram_candidates(*A, ctx->num_cu);
+      c.push_back(make_gram_plan(*A, ctx->num_cu));
+    }
+    for (const GramPlan& pl : c)
+      part = std::max(part, align_up(sizeof(double) * (size_t)pl.ny() * pl.ldy) +
+                                align_up(sizeof(double) * (size_t)std::max(pl.nq(), 1)) +
+                                align_up(sizeof(double) * pl.tmp_doubles()));
+  }
+  total += 2 * part + align_up(sizeof(double) * d);
+  // PCG vectors and scalars, H_rho x, the argument-check flag
+  const size_t nv = align_up(sizeof(double) * d);
+  total += 3 * nv + align_up(sizeof(double) * 1024 * kDotSlicesMax) +
+           align_up(sizeof(double) * kWyRing);
+  total += align_up(sizeof(PcgDev)) + 4 * align_up(sizeof(double) * (size_t)nblk(d, kRedBlock)) +
+           align_up(sizeof(double) * (size_t)nblk(d, kVecBlock));
+  total += nv + 256;
+  // ADMM vectors
+  total += admm_ws_bytes(n, d);
+  // sketch temporaries and the factors alive at once: one per instance when
+  // they run batched, two for a logistic refresh (old and new)
+  if (r_max > 0) {
+    size_t tmp = 0, factor = 0;
+    sketch_ws_bytes(*A, r_max, r_max, ctx->num_cu, &tmp, &factor);
+    total += tmp + (size_t)std::max(count, 2) * factor;
+  }
+  if (count > 1) total += batch_workspace_bytes(count, n, d, std::max(r_max, 1));
+  // first-fit fragmentation and 256-byte granularity
+  total += total / 8 + (size_t(16) << 20);
+  *bytes = total;
+  return NYS_OK;
+}
+
 nys_status nys_factor_import(nys_ctx ctx, int64_t d, int r, const double* U,
                              const double* lambda_host, double nu, nys_factor* F) {
   if (ctx == nullptr || F == nullptr || U == nullptr || lambda_host == nullptr)
@@ -749,6 +942,7 @@ nys_status nys_factor_import(nys_ctx ctx, int64_t d, int r, const double* U,
     if (i > 0 && lambda_host[i] > lambda_host[i - 1]) return NYS_ERR_INVALID;
   }
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   nys_factor f = new (std::nothrow) nys_factor_s();
   if (f == nullptr) return NYS_ERR_NOMEM;
   f->d = d;
@@ -815,6 +1009,7 @@ nys_status nys_precond_apply(nys_ctx ctx, nys_factor F, double rho, const double
   if (!(rho > 0.0) || F->r < 1) return NYS_ERR_INVALID;
   if (w == y) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   PcgWs ws;
   GramPlan pl;
   pl.grid = 0;
@@ -836,6 +1031,7 @@ nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, d
   NYS_TRY(validate_dense(A));
   if (!(rho + c >= 0.0)) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   NYS_TRY(check_vector(ctx, D, A->n, 0));
   GramPlan pl;
   NYS_TRY(ctx_gram_plan(ctx, *A, &pl));
@@ -864,6 +1060,7 @@ nys_status pcg_solve(nys_ctx ctx, const nys_dense* A, const double* D, double c,
     return NYS_ERR_INVALID;
   if (F != nullptr && F->d != A->d) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   NYS_TRY(check_vector(ctx, D, A->n, 0));
   return pcg_run(ctx, *A, D, c, rho, F, rhs, x, *opts, info);
 }
@@ -878,6 +1075,7 @@ nys_status pcg_solve_sym(nys_ctx ctx, const nys_dense* K, double c, double rho, 
     return NYS_ERR_INVALID;
   if (F != nullptr && F->d != K->d) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   return pcg_run(ctx, *K, nullptr, c, rho, F, rhs, x, *opts, info, 0.0, -1, nullptr, nullptr,
                  true);
 }

@@ -597,24 +597,28 @@ void make_tiles(const Bucket& b, const std::vector<BInst>& h, std::vector<BTile>
 }
 
 // Lay out the batch: per-instance vectors, partial sums sized for the finest
+constexpr int64_t kFinest = 128;   // finest tiling the tuner may choose
+
+// device bytes of one instance's vectors and partial sums in the batch buffer
+size_t inst_bytes(int64_t n, int64_t d) {
+  const int G = (int)((n + kFinest - 1) / kFinest);
+  const int ldy = (int)((d + 63) / 64 * 64);
+  return 5 * au(sizeof(double) * d) + au(sizeof(double) * 1024) + au(sizeof(double) * kWyRing) +
+         au(sizeof(double) * (size_t)G * ldy) + au(sizeof(double) * G) +
+         3 * au(sizeof(double) * ((d + 63) / 64)) + au(sizeof(double) * ((d + 255) / 256)) +
+         au(sizeof(double) * kNS * ((d + 255) / 256)) + au(sizeof(PcgDev));
+}
+
 // tiling, tile and item lists; bucket the instances by row width.
 nys_status batch_build(nys_ctx ctx, int count, const nys_problem* P, const nys_admm_opts* O,
                        nys_factor* F, nys_admm_state* S, int max_iter, Batch* B) {
   B->count = count;
   B->h.assign(count, BInst{});
-  constexpr int64_t kFinest = 128;   // finest tiling the tuner may choose
   size_t bytes = au(sizeof(BInst) * count);
   std::vector<size_t> off(count);
   for (int q = 0; q < count; ++q) {
-    const int64_t d = P[q].A.d, n = P[q].A.n;
-    const int G = (int)((n + kFinest - 1) / kFinest);
-    const int ldy = (int)((d + 63) / 64 * 64);
     off[q] = bytes;
-    bytes += 5 * au(sizeof(double) * d) + au(sizeof(double) * 1024) +
-             au(sizeof(double) * kWyRing) + au(sizeof(double) * (size_t)G * ldy) +
-             au(sizeof(double) * G) + 3 * au(sizeof(double) * ((d + 63) / 64)) +
-             au(sizeof(double) * ((d + 255) / 256)) + au(sizeof(double) * kNS * ((d + 255) / 256)) +
-             au(sizeof(PcgDev));
+    bytes += inst_bytes(P[q].A.n, P[q].A.d);
   }
   // buckets by row width
   std::map<std::pair<int, int>, std::vector<int>> groups;   // (f64|aligned, cover class)
@@ -880,6 +884,19 @@ nys_status batch_pcg(nys_ctx ctx, Batch* B, int max_iter, std::vector<PcgDev>* s
 }
 
 }  // namespace
+
+// Device bytes batch_build takes for `count` instances of shape n x d at rank r
+// (the same sums as batch_build).
+size_t batch_workspace_bytes(int count, int64_t n, int64_t d, int r) {
+  const size_t tiles = (size_t)count * (size_t)((n + kFinest - 1) / kFinest);
+  const size_t n64 = (size_t)count * (size_t)((d + 63) / 64);
+  const size_t ndot = (size_t)count * (size_t)std::max(1, (r + 3) / 4);
+  const size_t n256 = (size_t)count * (size_t)((d + 255) / 256);
+  return au(sizeof(BInst) * count) + (size_t)count * inst_bytes(n, d) +
+         au(sizeof(BTile) * std::max<size_t>(tiles, 1)) + au(sizeof(BItem) * n64) +
+         au(sizeof(BItem) * ndot) + au(sizeof(BItem) * n256) + au(sizeof(int)) +
+         au(sizeof(double) * kNS * count);
+}
 
 // Lockstep NysADMM over `count` least-squares problems (see batched.hip header).
 nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,

@@ -184,6 +184,8 @@ nys_status launch_dt(const nys_dense& A, const GramPlan& pl, int mode, const dou
 
 }  // namespace
 
+int64_t gram_max_cols(nys_dtype dt) { return dt == NYS_F64 ? 8 * 64 * 4 * 2 : 8 * 64 * 4 * 4; }
+
 static void finish_plan(const nys_dense& A, int num_cu, int per_cu, GramPlan* pl) {
   const int esize = A.dtype == NYS_F64 ? 8 : 4;
   pl->aligned = ((uintptr_t)A.data % 16 == 0) && ((A.ld * esize) % 16 == 0);

@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -51,19 +53,51 @@ struct PollPace {
 
 void set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
 
+// A caller-provided device workspace (nys_ctx_set_workspace): first-fit
+// blocks of 256-byte granularity carved from [base, base + bytes), adjacent
+// free blocks merged.  All work of the context that owns it runs on one
+// stream, so a released block can be handed out again at once (later work on
+// that stream is ordered after the work that used it).
+struct Arena {
+  char* base = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+  std::mutex mu;
+  std::map<size_t, size_t> free_blocks;   // offset -> size
+  size_t in_use = 0, peak = 0;
+  Arena(void* p, size_t n, int dev);
+  void* alloc(size_t want);              // nullptr when nothing fits
+  void free(void* p, size_t n);
+};
+
 // Grow-only device buffer owned by a context or factor.
 // Device buffer from the library's block cache (see pool_* in api.hip): a
 // released block is reused once the work queued on every live context stream
 // at release time has completed, so a step that rebuilds its factor does not
 // pay hipMalloc/hipFree (and the device-wide synchronisation of hipFree).
+// While a CtxScope of a context with a workspace is active on the thread, the
+// block is carved from that workspace instead (and returned to it).
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
   int device = -1;
+  std::shared_ptr<Arena> arena;      // the workspace the block came from, if any
   nys_status reserve(size_t want);   // contents are not preserved when it grows
   void release();
   template <typename T>
   T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Entry points bind their context for their duration: DevBuf::reserve then
+// carves from the context's workspace when it has one.  Nested scopes of the
+// same context are harmless; the previous binding is restored on exit.
+struct CtxScope {
+  explicit CtxScope(nys_ctx ctx);
+  ~CtxScope();
+  CtxScope(const CtxScope&) = delete;
+  CtxScope& operator=(const CtxScope&) = delete;
+ private:
+  std::shared_ptr<Arena> prev_;
 };
 
 // Device-side PCG bookkeeping.  Written only by kernels; read by the host at
@@ -124,8 +158,18 @@ struct GramPlan {
   int slice_cols = 0;
   // sparse A (CSR + CSC passes): y is one n-vector, q one partial per row workgroup
   const nys_sparse_s* sparse = nullptr;
+  // wide dense A (wide.hip): row dots per column block (slices x grid
+  // workgroups), then one epilogue kernel of mgrid workgroups (the q
+  // partials), then the A^T pass over the same blocks (grid y partials of
+  // ldy columns).  The per-block row dots (slices x ldt) and the n-vector s
+  // follow the q partials in the partial-sum buffer (wide_tmp).
+  bool wide = false;
+  int mgrid = 0;
+  int64_t ldt = 0;
   int ny() const { return sparse ? 1 : (symv ? slices : grid); }
-  int nq() const { return symv ? slices * grid : grid; }
+  int nq() const { return symv ? slices * grid : (wide ? mgrid : grid); }
+  // doubles the partial-sum buffer needs after the y and q partials
+  size_t tmp_doubles() const { return wide ? (size_t)(slices + 1) * (size_t)ldt : 0; }
 };
 
 enum GramMode : int {
@@ -176,6 +220,13 @@ nys_status validate_dense(const nys_dense* A);
 nys_status check_vector(nys_ctx ctx, const double* v, int64_t n, int kind);
 nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_iter, PcgWs* ws);
 nys_status read_pcg_state(nys_ctx ctx, const PcgWs& ws, PcgDev* out);
+
+// ---- workspace accounting (each next to the code whose buffers it counts)
+size_t admm_ws_bytes(int64_t n, int64_t d);                                   // admm.hip
+size_t batch_workspace_bytes(int count, int64_t n, int64_t d, int r);         // batched.hip
+void sketch_ws_bytes(const nys_dense& A, int m, int r, int num_cu, size_t* tmp,
+                     size_t* factor);                                          // sketch.hip
+size_t sparse_handle_bytes(int64_t n, int64_t d, int64_t nnz);               // sparse.hip
 
 // ---- admm.hip / batched.hip
 // relative KKT residual (eq. 31 or its logistic form) and objective at z
@@ -255,6 +306,7 @@ struct nys_ctx_s {
   nys::DevBuf admm_ws;   // ADMM vectors (A^T b, rhs, weights, ...)
   nys::DevBuf svm_ws;    // kernel SVM vectors (rhs, H z, scalars)
   nys::DevBuf check;     // flag word of the argument checks
+  std::shared_ptr<nys::Arena> arena;   // caller's workspace (nys_ctx_set_workspace), or none
   void* host_pinned = nullptr;  // pinned readback area of kPinnedBytes
   void* host_pinned_dev = nullptr;  // the same memory as seen from the device
   int poll_seq = 0;              // last sequence number of a PCG state slot write
@@ -322,6 +374,9 @@ void pool_unregister_stream(int device, hipStream_t st);
 
 // ---- gemv.hip
 GramPlan make_gram_plan(const nys_dense& A, int num_cu);
+// columns one workgroup of the fused matvec covers (the widest plan): d above
+// this takes the two-pass wide form
+int64_t gram_max_cols(nys_dtype dt);
 std::vector<GramPlan> gram_candidates(const nys_dense& A, int num_cu);
 // Launch the fused pass  t = A p;  s = mode(t);  y_g = sum_{rows of g} s_i A_i.
 nys_status launch_gram(const nys_dense& A, const GramPlan& plan, int mode, const double* p,
@@ -333,6 +388,15 @@ nys_status launch_gram(const nys_dense& A, const GramPlan& plan, int mode, const
 GramPlan make_symv_plan(const nys_dense& A, int num_cu);
 nys_status launch_symv(const nys_dense& A, const GramPlan& plan, const double* p, double* ypart,
                        double* qpart, const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr, PcgDev* note = nullptr, int note_seq = 0);
+
+// ---- wide.hip
+GramPlan make_wide_plan(const nys_dense& A, int num_cu);
+// start of the wide form's temporaries: after the q partials of the plan
+double* wide_tmp(const GramPlan& pl, double* qpart);
+nys_status launch_wide(const nys_dense& A, const GramPlan& plan, int mode, const double* p,
+                       const double* aux, double* auxout, double* ypart, double* qpart,
+                       const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr, PcgDev* note = nullptr, int note_seq = 0);
 
 // ---- sparse.hip

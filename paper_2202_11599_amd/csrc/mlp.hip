@@ -8,9 +8,17 @@
 // start that is exact on span(U) for exact eigenvectors.
 // gelu(a) = a/2 (1 + erf(a/sqrt 2)).  Training minimises the weighted squared
 // error (1/B) sum w_ik (o_ik - t_ik)^2 on standardised targets t = c* / s_out
-// with Adam (bias-corrected).  Everything is FP64 on the GPU: the matrix
-// products use the library's tiled FP64 GEMM, the rest small elementwise and
-// reduction kernels here.
+// with Adam (bias-corrected).
+//
+// Precisions (nys_ws_set_precision):
+//   FP64  everything FP64: the library's tiled FP64 GEMM and the elementwise
+//         kernels here (the form that matches the FP64 oracle to rounding);
+//   FP32  FP32 master weights, activations, gradients and Adam state; the
+//         matrix products on FP32 MFMA (16x16x4) with FP32 accumulation;
+//   BF16  as FP32, but every matrix-product operand (weights, activations,
+//         back-propagated gradients) rounded to BF16 for the BF16 MFMA
+//         (16x16x32) with FP32 accumulation; master weights, the elementwise
+//         work (bias, GELU, loss) and Adam stay FP32.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -139,6 +147,166 @@ __global__ void k_scale(const double* __restrict__ o, const double* __restrict__
   c[i] = v;
 }
 
+// ------------------------------------------------ FP32 / BF16-MFMA form
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float gelu_f(float a) {
+  return 0.5f * a * (1.0f + erff(a * 0.70710678118654752440f));
+}
+__device__ __forceinline__ float gelu_grad_f(float a) {
+  return 0.5f * (1.0f + erff(a * 0.70710678118654752440f)) +
+         a * expf(-0.5f * a * a) * 0.39894228040143267794f;
+}
+
+// C(m, n) = alpha sum_k A(m, k) B(k, n) + beta C(m, n), FP32 in memory,
+// A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn], C(m, n) = C[m scm + n scn].
+// Workgroup: 4 wavefronts, a 32 x 32 tile of C; wavefront w owns the 16 x 16
+// block (w & 1, w >> 1).  Per K step of 32, lane (q = lane / 16, i = lane % 16)
+// takes A(row i, k0 + 8q .. 8q + 7) and B(k0 + 8q .. 8q + 7, column i), zero
+// outside the matrices; the accumulator element v of the lane is C(4q + v, i).
+// BF: the eight operands are rounded to BF16 and one 16x16x32 BF16 MFMA
+// consumes them; otherwise eight 16x16x4 FP32 MFMAs (lane group q supplies
+// k = 8q + s at step s).  The operands are tiny and cache-resident, so they
+// are read straight from memory without staging.
+template <bool BF>
+__global__ __launch_bounds__(256) void k_mlp_gemm(int M, int N, int K, const float* __restrict__ A,
+                                                  int64_t sam, int64_t sak,
+                                                  const float* __restrict__ B, int64_t sbk,
+                                                  int64_t sbn, float* __restrict__ C, int64_t scm,
+                                                  int64_t scn, float alpha, float beta) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = lane >> 4, i = lane & 15;
+  const int row0 = blockIdx.x * 32 + 16 * (w & 1);
+  const int col0 = blockIdx.y * 32 + 16 * (w >> 1);
+  const int ar = row0 + i, bc = col0 + i;
+  f4_t acc = (f4_t)0.0f;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    float av[8], bv[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = k0 + 8 * q + s;
+      av[s] = (ar < M && k < K) ? A[(int64_t)ar * sam + (int64_t)k * sak] : 0.0f;
+      bv[s] = (bc < N && k < K) ? B[(int64_t)k * sbk + (int64_t)bc * sbn] : 0.0f;
+    }
+    if constexpr (BF) {
+      bf16x8_t a8, b8;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        a8[s] = (__bf16)av[s];
+        b8[s] = (__bf16)bv[s];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8, acc, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = row0 + 4 * q + v;
+    if (r < M && bc < N) {
+      float* c = C + (int64_t)r * scm + (int64_t)bc * scn;
+      *c = beta == 0.0f ? alpha * acc[v] : alpha * acc[v] + beta * *c;
+    }
+  }
+}
+
+__global__ void k_bias_gelu_f(float* __restrict__ A, const float* __restrict__ bias, int64_t M,
+                              int N, float* __restrict__ H) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * N) return;
+  const float a = A[e] + bias[e % N];
+  A[e] = a;
+  H[e] = gelu_f(a);
+}
+
+__global__ void k_bias_f(float* __restrict__ A, const float* __restrict__ bias, int64_t M, int N) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < M * N) A[e] += bias[e % N];
+}
+
+// Xn = (X - mu) / sigma from the FP64 feature rows, rounded to FP32
+__global__ void k_standardise_f(const double* __restrict__ X, const float* __restrict__ mu,
+                                const float* __restrict__ sig, int64_t M, int N,
+                                float* __restrict__ Xn) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < M * N) Xn[e] = ((float)X[e] - mu[e % N]) / sig[e % N];
+}
+
+// g = 2 w (o - t) / B in FP32 from FP32 outputs and FP64 targets/weights;
+// the loss terms are summed in FP64 (per block, fixed order)
+__global__ __launch_bounds__(256) void k_loss_grad_f(const float* __restrict__ O,
+                                                     const double* __restrict__ Tg,
+                                                     const double* __restrict__ W, int64_t MN,
+                                                     int B, float* __restrict__ G,
+                                                     double* __restrict__ part) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double l = 0.0;
+  if (e < MN) {
+    const float r = O[e] - (float)Tg[e];
+    const float w = W ? (float)W[e] : 1.0f;
+    l = (double)w * (double)r * (double)r / B;
+    G[e] = 2.0f * w * r / (float)B;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// column sums of G (M x N), one thread per column, fixed order, FP32
+__global__ void k_colsum_f(const float* __restrict__ G, int64_t M, int N, float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= N) return;
+  float s = 0.0f;
+  for (int64_t i = 0; i < M; ++i) s += G[i * N + c];
+  out[c] = s;
+}
+
+__global__ void k_gelu_back_f(const float* __restrict__ gH, const float* __restrict__ A, int64_t n,
+                              float* __restrict__ gA) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) gA[e] = gH[e] * gelu_grad_f(A[e]);
+}
+
+__global__ void k_adam_f(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                         float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                         float c1, float c2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const float ge = g[e];
+  const float me = b1 * m[e] + (1.0f - b1) * ge;
+  const float ve = b2 * v[e] + (1.0f - b2) * ge * ge;
+  m[e] = me;
+  v[e] = ve;
+  p[e] -= lr * (me / c1) / (sqrtf(ve / c2) + eps);
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ x, int64_t n, float* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) y[e] = (float)x[e];
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ x, int64_t n, double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) y[e] = (double)x[e];
+}
+
+// c = o * s_out (+ u / (lambda + rho)) from the FP32 network output
+__global__ void k_scale_f(const float* __restrict__ o, const float* __restrict__ s, int n,
+                          const double* __restrict__ u, const double* __restrict__ lam, double rho,
+                          double* __restrict__ c) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double v = (double)o[i] * (double)s[i];
+  if (u != nullptr) v += u[i] / (lam[i] + rho);
+  c[i] = v;
+}
+
 }  // namespace
 }  // namespace nys
 
@@ -152,6 +320,11 @@ struct nys_ws_model_s {
   nys::DevBuf grads;
   nys::DevBuf act;            // activations workspace
   int64_t act_batch = 0;
+  // FP32 / BF16-MFMA form: FP32 master weights (and mu, sigma, s_out), Adam
+  // state, gradients and activations
+  nys_dtype prec = NYS_F64;
+  nys::DevBuf params32, adam32, grads32, act32;
+  long t32 = 0;
 };
 
 namespace nys {
@@ -261,6 +434,118 @@ nys_status ws_backward(nys_ctx ctx, nys_ws_model m, const double* Tg, const doub
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
+// ---- FP32 / BF16-MFMA form
+struct WsPtrs32 {
+  float *W1, *b1, *W2, *b2, *W3, *b3, *mu, *sig, *sout;
+};
+
+WsPtrs32 ws_ptrs32(nys_ws_model m, float* base) {
+  WsPtrs32 p;
+  const int ni = m->n_in, h = m->hidden, no = m->n_out;
+  p.W1 = base;
+  p.b1 = p.W1 + (size_t)ni * h;
+  p.W2 = p.b1 + h;
+  p.b2 = p.W2 + (size_t)h * h;
+  p.W3 = p.b2 + h;
+  p.b3 = p.W3 + (size_t)h * no;
+  p.mu = p.b3 + no;
+  p.sig = p.mu + ni;
+  p.sout = p.sig + ni;
+  return p;
+}
+
+struct Act32 {
+  float *Xn, *A1, *H1, *A2, *H2, *O, *G, *gH, *gA;
+  double* part;
+};
+
+nys_status ws_act32(nys_ws_model m, int64_t B, Act32* a) {
+  const int ni = m->n_in, h = m->hidden, no = m->n_out;
+  const size_t nf = (size_t)B * (ni + 6 * h + 2 * no);
+  const size_t nd = blocks(B * std::max(no, h)) + 64;
+  NYS_TRY(m->act32.reserve(sizeof(float) * nf + 256 + sizeof(double) * nd));
+  float* p = m->act32.as<float>();
+  a->Xn = p;
+  p += B * ni;
+  a->A1 = p;
+  p += B * h;
+  a->H1 = p;
+  p += B * h;
+  a->A2 = p;
+  p += B * h;
+  a->H2 = p;
+  p += B * h;
+  a->O = p;
+  p += B * no;
+  a->G = p;
+  p += B * no;
+  a->gH = p;
+  p += B * h;
+  a->gA = p;
+  a->part = reinterpret_cast<double*>(m->act32.as<char>() + align_up(sizeof(float) * nf));
+  return NYS_OK;
+}
+
+nys_status mlp_gemm(hipStream_t st, bool bf, int M, int N, int K, const float* A, int64_t sam,
+                    int64_t sak, const float* B, int64_t sbk, int64_t sbn, float* C, int64_t scm,
+                    int64_t scn) {
+  const dim3 grid((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));
+  if (bf)
+    hipLaunchKernelGGL(k_mlp_gemm<true>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn,
+                       C, scm, scn, 1.0f, 0.0f);
+  else
+    hipLaunchKernelGGL(k_mlp_gemm<false>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk,
+                       sbn, C, scm, scn, 1.0f, 0.0f);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status ws_forward32(nys_ctx ctx, nys_ws_model m, const double* X, int64_t B, Act32* a) {
+  hipStream_t st = ctx->stream;
+  const bool bf = m->prec == NYS_BF16;
+  const int ni = m->n_in, h = m->hidden, no = m->n_out;
+  WsPtrs32 p = ws_ptrs32(m, m->params32.as<float>());
+  hipLaunchKernelGGL(k_standardise_f, dim3(blocks(B * ni)), dim3(256), 0, st, X, p.mu, p.sig, B,
+                     ni, a->Xn);
+  NYS_TRY(mlp_gemm(st, bf, (int)B, h, ni, a->Xn, ni, 1, p.W1, h, 1, a->A1, h, 1));
+  hipLaunchKernelGGL(k_bias_gelu_f, dim3(blocks(B * h)), dim3(256), 0, st, a->A1, p.b1, B, h,
+                     a->H1);
+  NYS_TRY(mlp_gemm(st, bf, (int)B, h, h, a->H1, h, 1, p.W2, h, 1, a->A2, h, 1));
+  hipLaunchKernelGGL(k_bias_gelu_f, dim3(blocks(B * h)), dim3(256), 0, st, a->A2, p.b2, B, h,
+                     a->H2);
+  NYS_TRY(mlp_gemm(st, bf, (int)B, no, h, a->H2, h, 1, p.W3, no, 1, a->O, no, 1));
+  hipLaunchKernelGGL(k_bias_f, dim3(blocks(B * no)), dim3(256), 0, st, a->O, p.b3, B, no);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+nys_status ws_backward32(nys_ctx ctx, nys_ws_model m, const double* Tg, const double* Wt,
+                         int64_t B, Act32* a, double* loss_dev) {
+  hipStream_t st = ctx->stream;
+  const bool bf = m->prec == NYS_BF16;
+  const int ni = m->n_in, h = m->hidden, no = m->n_out;
+  WsPtrs32 p = ws_ptrs32(m, m->params32.as<float>());
+  WsPtrs32 g = ws_ptrs32(m, m->grads32.as<float>());
+  const unsigned nb = blocks(B * no);
+  hipLaunchKernelGGL(k_loss_grad_f, dim3(nb), dim3(256), 0, st, a->O, Tg, Wt, B * no, (int)B,
+                     a->G, a->part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, a->part, (int)nb, loss_dev);
+  // layer 3: gW3 = H2^T G, gb3 = 1^T G, gH2 = G W3^T
+  NYS_TRY(mlp_gemm(st, bf, h, no, (int)B, a->H2, 1, h, a->G, no, 1, g.W3, no, 1));
+  hipLaunchKernelGGL(k_colsum_f, dim3(blocks(no)), dim3(256), 0, st, a->G, B, no, g.b3);
+  NYS_TRY(mlp_gemm(st, bf, (int)B, h, no, a->G, no, 1, p.W3, 1, no, a->gH, h, 1));
+  hipLaunchKernelGGL(k_gelu_back_f, dim3(blocks(B * h)), dim3(256), 0, st, a->gH, a->A2, B * h,
+                     a->gA);
+  // layer 2
+  NYS_TRY(mlp_gemm(st, bf, h, h, (int)B, a->H1, 1, h, a->gA, h, 1, g.W2, h, 1));
+  hipLaunchKernelGGL(k_colsum_f, dim3(blocks(h)), dim3(256), 0, st, a->gA, B, h, g.b2);
+  NYS_TRY(mlp_gemm(st, bf, (int)B, h, h, a->gA, h, 1, p.W2, 1, h, a->gH, h, 1));
+  hipLaunchKernelGGL(k_gelu_back_f, dim3(blocks(B * h)), dim3(256), 0, st, a->gH, a->A1, B * h,
+                     a->gA);
+  // layer 1
+  NYS_TRY(mlp_gemm(st, bf, ni, h, (int)B, a->Xn, 1, ni, a->gA, h, 1, g.W1, h, 1));
+  hipLaunchKernelGGL(k_colsum_f, dim3(blocks(h)), dim3(256), 0, st, a->gA, B, h, g.b1);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
 // x0 = U c with c = s_out * MLP((f - mu)/sigma) [+ (Lambda + rho I)^-1 U^T rhs],
 // f = [U^T rhs, log gamma, log rho].
 // scratch: >= 2 r + 2 + n_out doubles (device).
@@ -278,12 +563,21 @@ nys_status ws_propose(nys_ctx ctx, nys_ws_model m, nys_factor F, const double* r
                      std::log(rho), f);
   if (feat_out != nullptr)
     NYS_TRY_HIP(hipMemcpyAsync(feat_out, f, sizeof(double) * (r + 2), hipMemcpyDeviceToDevice, st));
-  Act a;
-  NYS_TRY(ws_act(m, 1, &a));
-  NYS_TRY(ws_forward(ctx, m, f, 1, &a));
-  WsPtrs p = ws_ptrs(m, m->params.as<double>());
-  hipLaunchKernelGGL(k_scale, dim3(blocks(r)), dim3(256), 0, st, a.O, p.sout, r,
-                     m->skip ? cU : nullptr, F->lam.as<double>(), rho, c);
+  if (m->prec != NYS_F64) {
+    Act32 a;
+    NYS_TRY(ws_act32(m, 1, &a));
+    NYS_TRY(ws_forward32(ctx, m, f, 1, &a));
+    WsPtrs32 p = ws_ptrs32(m, m->params32.as<float>());
+    hipLaunchKernelGGL(k_scale_f, dim3(blocks(r)), dim3(256), 0, st, a.O, p.sout, r,
+                       m->skip ? cU : nullptr, F->lam.as<double>(), rho, c);
+  } else {
+    Act a;
+    NYS_TRY(ws_act(m, 1, &a));
+    NYS_TRY(ws_forward(ctx, m, f, 1, &a));
+    WsPtrs p = ws_ptrs(m, m->params.as<double>());
+    hipLaunchKernelGGL(k_scale, dim3(blocks(r)), dim3(256), 0, st, a.O, p.sout, r,
+                       m->skip ? cU : nullptr, F->lam.as<double>(), rho, c);
+  }
   NYS_TRY(launch_u_c(U, F->d, r, c, x0, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
@@ -336,6 +630,7 @@ nys_status nys_ws_create(nys_ctx ctx, int n_in, int hidden, int n_out, const dou
   if (n_in < 1 || hidden < 1 || n_out < 1 || hidden > 4096) return NYS_ERR_INVALID;
   if (analytic_skip != 0 && n_in != n_out + 2) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   nys_ws_model m = new (std::nothrow) nys_ws_model_s();
   if (m == nullptr) return NYS_ERR_NOMEM;
   m->n_in = n_in;
@@ -374,8 +669,50 @@ nys_status nys_ws_create(nys_ctx ctx, int n_in, int hidden, int n_out, const dou
   return NYS_OK;
 }
 
+nys_status nys_ws_set_precision(nys_ctx ctx, nys_ws_model m, nys_dtype prec) {
+  if (ctx == nullptr || m == nullptr) return NYS_ERR_INVALID;
+  if (prec != NYS_F64 && prec != NYS_F32 && prec != NYS_BF16) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
+  hipStream_t st = ctx->stream;
+  const int64_t np = (int64_t)ws_count(m->n_in, m->hidden, m->n_out);
+  const int64_t tot = np + 2 * (int64_t)m->n_in + m->n_out;
+  const bool was32 = m->prec != NYS_F64, now32 = prec != NYS_F64;
+  if (now32 && !was32) {
+    // FP32 master copy of the FP64 parameters (and statistics); fresh Adam state
+    NYS_TRY(m->params32.reserve(sizeof(float) * tot));
+    NYS_TRY(m->grads32.reserve(sizeof(float) * tot));
+    NYS_TRY(m->adam32.reserve(sizeof(float) * 2 * np));
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(blocks(tot)), dim3(256), 0, st, m->params.as<double>(),
+                       tot, m->params32.as<float>());
+    NYS_TRY_HIP(hipMemsetAsync(m->adam32.ptr, 0, sizeof(float) * 2 * np, st));
+    m->t32 = 0;
+  } else if (was32 && !now32) {
+    // back to FP64: the FP32 master weights become the parameters
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks(tot)), dim3(256), 0, st, m->params32.as<float>(),
+                       tot, m->params.as<double>());
+    NYS_TRY_HIP(hipMemsetAsync(m->adam.ptr, 0, sizeof(double) * 2 * np, st));
+    m->t = 0;
+  }
+  NYS_TRY_HIP(hipGetLastError());
+  NYS_TRY_HIP(hipStreamSynchronize(st));
+  m->prec = prec;
+  return NYS_OK;
+}
+
 nys_status nys_ws_get_params(nys_ctx ctx, nys_ws_model m, double* params_host) {
   if (ctx == nullptr || m == nullptr || params_host == nullptr) return NYS_ERR_INVALID;
+  if (m->prec != NYS_F64) {
+    // the FP32 master weights, widened
+    NYS_TRY_HIP(hipSetDevice(ctx->device));
+    const int64_t np = (int64_t)ws_count(m->n_in, m->hidden, m->n_out);
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks(np)), dim3(256), 0, ctx->stream,
+                       m->params32.as<float>(), np, m->grads.as<double>());
+    NYS_TRY_HIP(hipMemcpyAsync(params_host, m->grads.ptr, sizeof(double) * np,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    return NYS_OK;
+  }
   NYS_TRY_HIP(hipMemcpyAsync(params_host, m->params.ptr,
                              sizeof(double) * ws_count(m->n_in, m->hidden, m->n_out),
                              hipMemcpyDeviceToHost, ctx->stream));
@@ -387,6 +724,15 @@ nys_status nys_ws_forward(nys_ctx ctx, nys_ws_model m, const double* X, int batc
   if (ctx == nullptr || m == nullptr || X == nullptr || out == nullptr || batch < 1)
     return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
+  if (m->prec != NYS_F64) {
+    Act32 a;
+    NYS_TRY(ws_act32(m, batch, &a));
+    NYS_TRY(ws_forward32(ctx, m, X, batch, &a));
+    const int64_t no = (int64_t)batch * m->n_out;
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks(no)), dim3(256), 0, ctx->stream, a.O, no, out);
+    return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+  }
   Act a;
   NYS_TRY(ws_act(m, batch, &a));
   NYS_TRY(ws_forward(ctx, m, X, batch, &a));
@@ -400,15 +746,28 @@ nys_status nys_ws_loss_grad(nys_ctx ctx, nys_ws_model m, const double* X, const 
   if (ctx == nullptr || m == nullptr || X == nullptr || T == nullptr || batch < 1)
     return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
-  Act a;
-  NYS_TRY(ws_act(m, batch, &a));
-  NYS_TRY(ws_forward(ctx, m, X, batch, &a));
-  double* loss_dev = a.part + blocks((int64_t)batch * std::max(m->n_out, m->hidden)) + 1;
-  NYS_TRY(ws_backward(ctx, m, T, W, batch, &a, loss_dev));
-  if (grad_out != nullptr)
-    NYS_TRY_HIP(hipMemcpyAsync(grad_out, m->grads.ptr,
-                               sizeof(double) * ws_count(m->n_in, m->hidden, m->n_out),
-                               hipMemcpyDeviceToDevice, ctx->stream));
+  nys::CtxScope ctx_scope(ctx);
+  const int64_t np = (int64_t)ws_count(m->n_in, m->hidden, m->n_out);
+  double* loss_dev = nullptr;
+  if (m->prec != NYS_F64) {
+    Act32 a;
+    NYS_TRY(ws_act32(m, batch, &a));
+    NYS_TRY(ws_forward32(ctx, m, X, batch, &a));
+    loss_dev = a.part + blocks((int64_t)batch * std::max(m->n_out, m->hidden)) + 1;
+    NYS_TRY(ws_backward32(ctx, m, T, W, batch, &a, loss_dev));
+    if (grad_out != nullptr)
+      hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks(np)), dim3(256), 0, ctx->stream,
+                         m->grads32.as<float>(), np, grad_out);
+  } else {
+    Act a;
+    NYS_TRY(ws_act(m, batch, &a));
+    NYS_TRY(ws_forward(ctx, m, X, batch, &a));
+    loss_dev = a.part + blocks((int64_t)batch * std::max(m->n_out, m->hidden)) + 1;
+    NYS_TRY(ws_backward(ctx, m, T, W, batch, &a, loss_dev));
+    if (grad_out != nullptr)
+      NYS_TRY_HIP(hipMemcpyAsync(grad_out, m->grads.ptr, sizeof(double) * np,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+  }
   if (loss_host != nullptr) {
     NYS_TRY_HIP(hipMemcpyAsync(ctx->host_pinned, loss_dev, sizeof(double), hipMemcpyDeviceToHost,
                                ctx->stream));
@@ -423,6 +782,17 @@ nys_status nys_ws_train_step(nys_ctx ctx, nys_ws_model m, const double* X, const
   if (!(lr > 0.0)) return NYS_ERR_INVALID;
   NYS_TRY(nys_ws_loss_grad(ctx, m, X, T, W, batch, loss_host, nullptr));
   const int64_t np = (int64_t)ws_count(m->n_in, m->hidden, m->n_out);
+  if (m->prec != NYS_F64) {
+    m->t32 += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)m->t32));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)m->t32));
+    float* mm = m->adam32.as<float>();
+    hipLaunchKernelGGL(k_adam_f, dim3(blocks(np)), dim3(256), 0, ctx->stream,
+                       m->params32.as<float>(), m->grads32.as<float>(), mm, mm + np, np, (float)lr,
+                       b1, b2, 1e-8f, c1, c2);
+    return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+  }
   m->t += 1;
   const double b1 = 0.9, b2 = 0.999;
   const double c1 = 1.0 - std::pow(b1, (double)m->t), c2 = 1.0 - std::pow(b2, (double)m->t);
@@ -440,6 +810,10 @@ nys_status nys_ws_destroy(nys_ws_model m) {
   m->adam.release();
   m->grads.release();
   m->act.release();
+  m->params32.release();
+  m->adam32.release();
+  m->grads32.release();
+  m->act32.release();
   delete m;
   return NYS_OK;
 }

@@ -436,14 +436,25 @@ struct CoreWs {
   size_t split_elems;
 };
 
+size_t core_split_elems(int64_t d, int r) {
+  return std::max<size_t>((size_t)16 * r * r, (size_t)4 * d * std::min(r, 64));
+}
+
+size_t core_ws_bytes_of(int64_t d, int r) {
+  const size_t rr = align_up(sizeof(double) * (size_t)r * r);
+  const size_t dr = align_up(sizeof(double) * (size_t)d * r);
+  const size_t jac = align_up(sizeof(double) * jacobi_ws_doubles(r));
+  const size_t split = align_up(sizeof(double) * core_split_elems(d, r));
+  return 6 * rr + dr + jac + split + align_up(sizeof(double) * 1024) + 4096 + 4096;
+}
+
 nys_status core_workspace(nys_ctx ctx, int64_t d, int r, CoreWs* w) {
   const size_t rr = align_up(sizeof(double) * (size_t)r * r);
   const size_t dr = align_up(sizeof(double) * (size_t)d * r);
   const size_t jac = align_up(sizeof(double) * jacobi_ws_doubles(r));
-  w->split_elems = std::max<size_t>((size_t)16 * r * r, (size_t)4 * d * std::min(r, 64));
+  w->split_elems = core_split_elems(d, r);
   const size_t split = align_up(sizeof(double) * w->split_elems);
-  const size_t total = 6 * rr + dr + jac + split + align_up(sizeof(double) * 1024) + 4096 + 4096;
-  NYS_TRY(ctx->core_ws.reserve(total));
+  NYS_TRY(ctx->core_ws.reserve(core_ws_bytes_of(d, r)));
   char* p = static_cast<char*>(ctx->core_ws.ptr);
   auto take = [&](size_t b) { char* q = p; p += b; return reinterpret_cast<double*>(q); };
   w->GY = take(rr);
@@ -687,6 +698,32 @@ nys_status launch_sk2(int NB, const nys_dense& A, int vec, const double* D, cons
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
+// Launch shape and temporaries of the FP32/BF16-MFMA sketch of m columns.
+struct Sk32Shape {
+  int ldo, NB, NP, npass, nrows_pad, ldy, S;
+  int64_t ldt, slice;
+  size_t olp_b, yp_b;
+};
+Sk32Shape sk32_shape(int64_t n, int64_t d, int m, int num_cu, bool bf) {
+  Sk32Shape s;
+  s.ldo = (int)((d + 31) / 32 * 32);
+  s.NB = m <= 64 ? 4 : (m <= 128 ? 8 : 16);
+  s.NP = 16 * s.NB;
+  s.npass = (m + s.NP - 1) / s.NP;
+  s.nrows_pad = s.npass * s.NP;
+  s.ldt = (n + 7) / 8 * 8;
+  s.ldy = (int)((d + 3) / 4 * 4);
+  // split-K over rows of A: about 4 workgroups per CU
+  const int jt = (int)((d + 127) / 128);
+  s.S = std::max(1, std::min<int>((int)((n + 255) / 256), (4 * num_cu) / jt));
+  s.slice = (n + s.S - 1) / s.S;
+  s.slice = (s.slice + kBK - 1) / kBK * kBK;
+  s.S = (int)((n + s.slice - 1) / s.slice);
+  s.olp_b = align_up((size_t)s.nrows_pad * s.ldo * (bf ? 2 : 4));
+  s.yp_b = align_up(sizeof(float) * (size_t)s.S * m * s.ldy);
+  return s;
+}
+
 // Sketch one block of m new columns into F (columns r_old .. r_old+m-1).
 nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double c,
                         const double* omega, int m, nys_factor F) {
@@ -760,22 +797,13 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
   } else {
     if (!a32) return NYS_ERR_INVALID;
     const bool bf = (F->prec == NYS_BF16);
-    const int ldo = (int)((d + 31) / 32 * 32);
-    const int NB = m <= 64 ? 4 : (m <= 128 ? 8 : 16);
-    const int NP = 16 * NB;
-    const int npass = (m + NP - 1) / NP;
-    const int nrows_pad = npass * NP;
-    const int64_t ldt = (n + 7) / 8 * 8;
-    const int ldy = (int)((d + 3) / 4 * 4);
-    // split-K over rows of A: about 4 workgroups per CU
-    const int jt = (int)((d + 127) / 128);
-    int S = std::max(1, std::min<int>((int)((n + 255) / 256), (4 * ctx->num_cu) / jt));
-    int64_t slice = (n + S - 1) / S;
-    slice = (slice + kBK - 1) / kBK * kBK;
-    S = (int)((n + slice - 1) / slice);
-    const size_t olp_b = align_up((size_t)nrows_pad * ldo * (bf ? 2 : 4));
-    const size_t yp_b = align_up(sizeof(float) * (size_t)S * m * ldy);
-    NYS_TRY(ctx->gemm_ws.reserve(olp_b + yp_b));
+    const Sk32Shape sh = sk32_shape(n, d, m, ctx->num_cu, bf);
+    const int ldo = sh.ldo, NB = sh.NB, NP = sh.NP, npass = sh.npass, nrows_pad = sh.nrows_pad;
+    const int64_t ldt = sh.ldt;
+    const int ldy = sh.ldy, S = sh.S;
+    const int64_t slice = sh.slice;
+    const size_t olp_b = sh.olp_b;
+    NYS_TRY(ctx->gemm_ws.reserve(sh.olp_b + sh.yp_b));
     void* Olp = ctx->gemm_ws.ptr;
     float* Yp = reinterpret_cast<float*>(static_cast<char*>(ctx->gemm_ws.ptr) + olp_b);
     if (bf)
@@ -858,6 +886,7 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
     return NYS_ERR_INVALID;
   if (A->dtype == NYS_CSR && prec != NYS_F64) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   nys_factor f = *F;
   bool created = false;
   if (f == nullptr) {
@@ -883,6 +912,32 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
 
 // Rebuild of a factor with the previous one's U as the eigensolver's start
 // basis (same rank and dimension); otherwise as a fresh nys_sketch.
+// Upper bounds of the device bytes a sketch call holds in the context (the
+// GEMM temporaries of the largest form and the FP64 core workspace) for
+// blocks of at most m columns and a total rank of at most r (*tmp), and of
+// the buffers of one factor of rank r (capacity at most min(2 r, d - 1)), the
+// transient copies made while its capacity grows included (*factor_out).
+void sketch_ws_bytes(const nys_dense& A, int m, int r, int num_cu, size_t* tmp,
+                     size_t* factor_out) {
+  const int64_t n = A.n, d = A.d;
+  size_t g = sizeof(double) * (size_t)n * m + 256;                       // FP64 form
+  g = std::max(g, sizeof(double) * (size_t)(n + 2 * d) * m + 256);       // sparse form
+  if (A.dtype == NYS_F32) {
+    const Sk32Shape s = sk32_shape(n, d, m, num_cu, false);               // FP32 >= BF16
+    g = std::max(g, s.olp_b + s.yp_b);
+  }
+  const int64_t cap = std::min<int64_t>(2 * (int64_t)r, d - 1);
+  const int64_t ldt = (n + 7) / 8 * 8;
+  const size_t grown = 2 * sizeof(double) * (size_t)(d * cap) +                   // Omega, Y
+                       (A.dtype == NYS_F32 ? sizeof(float) * (size_t)(ldt * cap) +   // T
+                                                 sizeof(double) * (size_t)(cap * cap)  // Mbase
+                                           : 0);
+  const size_t factor = 12 * (size_t)d * r + sizeof(double) * (size_t)r +            // U, U32, lambda
+                        sizeof(double) * (size_t)r * r + grown;                       // core copy
+  *tmp = g + core_ws_bytes_of(d, r);
+  *factor_out = factor + grown;   // + one growth transient
+}
+
 nys_status sketch_rebuild(nys_ctx ctx, const nys_dense* A, const double* D, double c,
                           const double* omega, int r, nys_dtype prec, nys_factor prev,
                           nys_factor* F) {
@@ -905,6 +960,7 @@ nys_status nys_sketch(nys_ctx ctx, const nys_dense* A, const double* D, double c
   if (D != nullptr) {
     // the weights are the Hessian of a convex loss, D >= 0 (Section 2.1)
     NYS_TRY_HIP(hipSetDevice(ctx->device));
+    nys::CtxScope ctx_scope(ctx);
     NYS_TRY(check_vector(ctx, D, A->n, 0));
   }
   return sketch_round(ctx, A, D, c, omega, r, prec, F, -1.0, nullptr);
@@ -924,6 +980,7 @@ nys_status nys_sketch_adaptive(nys_ctx ctx, const nys_dense* A, const double* D,
     return NYS_ERR_INVALID;
   if (D != nullptr) {
     NYS_TRY_HIP(hipSetDevice(ctx->device));
+    nys::CtxScope ctx_scope(ctx);
     NYS_TRY(check_vector(ctx, D, A->n, 0));
   }
   // kappa = (lambda_s + rho) / rho <= tol  <=>  lambda_s <= (tol - 1) rho, so a

@@ -437,6 +437,18 @@ nys_status sparse_sketch(const nys_sparse_s* S, const double* D, double c, const
 
 }  // namespace nys
 
+namespace nys {
+// device bytes nys_sparse_create holds at once (CSC copy, s vector, column
+// bins, and the transient per-block column counts)
+size_t sparse_handle_bytes(int64_t n, int64_t d, int64_t nnz) {
+  const int64_t rpb = std::max<int64_t>(1, (n + kTBlocks - 1) / kTBlocks);
+  const int64_t nblk = std::max<int64_t>(1, (n + rpb - 1) / rpb);
+  return (sizeof(int) * (size_t)(d + 1 + 2 * nnz) + 256) +
+         sizeof(double) * (size_t)std::max<int64_t>(n, 1) +
+         sizeof(int) * ((size_t)nblk * d + 1) + sizeof(int) * (size_t)(3 * d + 3) + 4 * 256;
+}
+}  // namespace nys
+
 using namespace nys;
 
 extern "C" {
@@ -450,6 +462,7 @@ nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, con
     return NYS_ERR_INVALID;
   *out = nullptr;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   hipStream_t st = ctx->stream;
   // rowptr must describe nnz entries: check its ends on the host
   int ends[2] = {0, 0};

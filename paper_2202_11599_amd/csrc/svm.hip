@@ -450,6 +450,7 @@ nys_status nys_kernel_rbf(nys_ctx ctx, const float* X, int64_t n, int64_t p, int
       !(gamma > 0.0) || n > ((int64_t)1 << 31) - 1 || p > ((int64_t)1 << 31) - 1)
     return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   hipStream_t st = ctx->stream;
   // G rows in blocks of at most 2^25 doubles (256 MB)
   int64_t blk = std::max<int64_t>(64, ((int64_t)1 << 25) / n / 64 * 64);
@@ -484,6 +485,7 @@ nys_status svm_solve(nys_ctx ctx, const nys_svm_problem* P, const nys_svm_opts* 
   if (S->x == nullptr || S->z == nullptr || S->u == nullptr) return NYS_ERR_INVALID;
   if (O->factor != nullptr && (O->factor->d != n || !O->factor->sym)) return NYS_ERR_INVALID;
   NYS_TRY_HIP(hipSetDevice(ctx->device));
+  nys::CtxScope ctx_scope(ctx);
   hipStream_t st = ctx->stream;
   nys_svm_info info{};
   info.gap = info.gap_rel = info.primal = info.dual = info.true_res_max = -1.0;

@@ -34,6 +34,8 @@ EXPORTS = [
     "nys_ws_create", "nys_ws_get_params", "nys_ws_forward", "nys_ws_loss_grad",
     "nys_ws_train_step", "nys_ws_destroy", "nys_kernel_rbf", "nys_sketch_sym", "pcg_solve_sym",
     "svm_solve", "nys_sparse_create", "nys_sparse_destroy",
+    "nys_workspace_query", "nys_ctx_set_workspace", "nys_ctx_workspace_peak",
+    "nys_ws_set_precision",
 ]
 
 
@@ -120,6 +122,9 @@ def lib():
         "nys_ctx_destroy": (i32, [vp]),
         "nys_ctx_set_stream": (i32, [vp, vp]),
         "nys_ctx_workspace_bytes": (C.c_size_t, [vp]),
+        "nys_workspace_query": (i32, [vp, P(Dense), i32, i32, P(C.c_size_t)]),
+        "nys_ctx_set_workspace": (i32, [vp, vp, C.c_size_t]),
+        "nys_ctx_workspace_peak": (C.c_size_t, [vp]),
         "nys_ctx_profile_start": (i32, [vp]),
         "nys_ctx_profile_stop": (i32, [vp, P(C.c_long), P(dbl)]),
         "nys_sketch": (i32, [vp, P(Dense), vp, dbl, vp, i32, i32, P(vp)]),
@@ -136,6 +141,7 @@ def lib():
         "nys_ws_param_count": (C.c_size_t, [i32, i32, i32]),
         "nys_ws_create": (i32, [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl), P(dbl), i32, P(vp)]),
         "nys_ws_get_params": (i32, [vp, vp, P(dbl)]),
+        "nys_ws_set_precision": (i32, [vp, vp, i32]),
         "nys_ws_forward": (i32, [vp, vp, vp, i32, vp]),
         "nys_ws_loss_grad": (i32, [vp, vp, vp, vp, vp, i32, P(dbl), vp]),
         "nys_ws_train_step": (i32, [vp, vp, vp, vp, vp, i32, dbl, P(dbl)]),
@@ -220,6 +226,33 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return int(lib().nys_ctx_workspace_bytes(self.h))
+
+    def workspace_query(self, A, r_max: int, count: int = 1) -> int:
+        """Device bytes admm_solve needs for `count` problems shaped like A at
+        rank <= r_max when the memory comes from set_workspace."""
+        dA = dense(A)
+        out = C.c_size_t()
+        _check(lib().nys_workspace_query(self.h, C.byref(dA), int(r_max), int(count),
+                                         C.byref(out)), "nys_workspace_query")
+        return int(out.value)
+
+    def set_workspace(self, buf: Optional[torch.Tensor]):
+        """Carve every device buffer of this context from `buf` (a CUDA tensor
+        the caller keeps alive; its bytes are used); None returns to the
+        library's own allocation."""
+        if buf is None:
+            _check(lib().nys_ctx_set_workspace(self.h, None, 0), "nys_ctx_set_workspace")
+            self._workspace = None
+            return
+        if not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("workspace must be a contiguous CUDA tensor")
+        _check(lib().nys_ctx_set_workspace(self.h, C.c_void_p(buf.data_ptr()),
+                                           buf.numel() * buf.element_size()),
+               "nys_ctx_set_workspace")
+        self._workspace = buf
+
+    def workspace_peak(self) -> int:
+        return int(lib().nys_ctx_workspace_peak(self.h))
 
     def synchronize(self):
         self._stream.synchronize()
@@ -590,6 +623,11 @@ class WarmStart:
                 or X.shape[1] != n:
             raise ValueError(f"{name} must be a contiguous CUDA float64 (batch, {n}) tensor")
         return X
+
+    def set_precision(self, prec: int):
+        """NYS_F64 (default), NYS_F32 or NYS_BF16 (FP32 master weights, MFMA products)."""
+        _check(lib().nys_ws_set_precision(self.ctx.h, self.h, int(prec)), "nys_ws_set_precision")
+        self.prec = int(prec)
 
     def params(self) -> torch.Tensor:
         out = torch.empty(self.count, dtype=torch.float64)

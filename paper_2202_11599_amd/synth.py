@@ -53,10 +53,12 @@ def haar_orthonormal(rows: int, cols: int, seed: int, tag: str, device="cpu") ->
 
 
 def decay_matrix(n: int, d: int, alpha: float, seed: int, device="cpu") -> torch.Tensor:
-    """A = Q1 diag(j^-alpha) Q2^T with Haar factors (FP64, exact singular values)."""
-    sigma = torch.arange(1, d + 1, device=device, dtype=torch.float64).pow(-alpha)
-    q1 = haar_orthonormal(n, d, seed, "Q1", device)
-    q2 = haar_orthonormal(d, d, seed, "Q2", device)
+    """A = Q1 diag(j^-alpha) Q2^T with Haar factors (FP64, exact singular values
+    j^-alpha, j = 1..min(n, d)); Q1 is n x k, Q2 is d x k, k = min(n, d)."""
+    k = min(n, d)
+    sigma = torch.arange(1, k + 1, device=device, dtype=torch.float64).pow(-alpha)
+    q1 = haar_orthonormal(n, k, seed, "Q1", device)
+    q2 = haar_orthonormal(d, k, seed, "Q2", device)
     a = (q1 * sigma) @ q2.T
     del q1
     return a

@@ -10,7 +10,13 @@ module only orders the calls and prepares the training set:
              solution, both written on the device by the library;
   * fit      standardises features and targets, weights the squared error by
              (lambda_k + rho) / rho (the error of x0 = U c in the norm of
-             H + rho I, up to a constant) and takes Adam steps on minibatches;
+             H + rho I, up to a constant) and takes Adam steps on minibatches
+             in the network's precision (BF16 MFMA products with FP32 master
+             weights by default); with a validation set it keeps the weights
+             of the best validation loss seen (early stopping: the recorded
+             subproblems of one ADMM run are strongly correlated, so a network
+             of this size memorises them long before it stops improving on
+             new right-hand sides);
   * run_arm  solves a family with one start rule: the previous iterate only,
              the network's proposal judged against it, or the analytic proposal
              U (Lambda + rho I)^-1 U^T rhs judged against it.
@@ -60,22 +66,39 @@ def init_params(n_in: int, hidden: int, n_out: int, seed: int) -> torch.Tensor:
     return torch.cat(parts)
 
 
-def fit(ctx: N.Context, X: torch.Tensor, T: torch.Tensor, lam: Sequence[float],
-        hidden: int = 256, steps: int = 2000, batch: int = 256, lr: float = 1e-3,
-        seed: int = 0, log_every: int = 0, analytic_skip: bool = True):
-    """Train a warm-start network on (X, T); returns (model, loss history).
-    analytic_skip: the network learns c* - (Lambda + rho I)^-1 U^T rhs."""
-    n_in, n_out = X.shape[1], T.shape[1]
-    lam_t = torch.as_tensor(list(lam), dtype=torch.float64, device=X.device)
+def _targets(X, T, lam_t, analytic_skip):
+    n_out = T.shape[1]
     rho = torch.exp(X[:, -1])
     if analytic_skip:
         T = T - X[:, :n_out] / (lam_t[None, :] + rho[:, None])
+    return T, rho
+
+
+def fit(ctx: N.Context, X: torch.Tensor, T: torch.Tensor, lam: Sequence[float],
+        hidden: int = 256, steps: int = 2000, batch: int = 256, lr: float = 1e-3,
+        seed: int = 0, log_every: int = 0, analytic_skip: bool = True,
+        prec: int = N.NYS_BF16, val=None, val_every: int = 50):
+    """Train a warm-start network on (X, T); returns (model, loss history).
+    analytic_skip: the network learns c* - (Lambda + rho I)^-1 U^T rhs.
+    prec: the network's arithmetic (NYS_BF16, NYS_F32 or NYS_F64).
+    val: optional held-out (X, T) rows; the weights with the lowest
+    validation loss (checked every val_every steps) are the ones returned."""
+    n_in, n_out = X.shape[1], T.shape[1]
+    lam_t = torch.as_tensor(list(lam), dtype=torch.float64, device=X.device)
+    T, rho = _targets(X, T, lam_t, analytic_skip)
     mu = X.mean(0)
     sd = X.std(0).clamp_min(1e-12)
     s_out = T.std(0).clamp_min(1e-30)
     Tn = (T / s_out).contiguous()
     W = (lam_t[None, :] + rho[:, None]) / rho[:, None] * (s_out[None, :] ** 2)
-    W = (W / W.mean()).contiguous()
+    wscale = W.mean()
+    W = (W / wscale).contiguous()
+    if val is not None:
+        Xv = val[0].contiguous()
+        Tv, rv = _targets(Xv, val[1], lam_t, analytic_skip)
+        Tvn = (Tv / s_out).contiguous()
+        Wv = ((lam_t[None, :] + rv[:, None]) / rv[:, None] * (s_out[None, :] ** 2) /
+              wscale).contiguous()
     params = init_params(n_in, hidden, n_out, seed)
     if analytic_skip:
         # start close to the analytic proposal: small last layer
@@ -83,11 +106,18 @@ def fit(ctx: N.Context, X: torch.Tensor, T: torch.Tensor, lam: Sequence[float],
         params[w3:w3 + hidden * n_out] *= 0.01
     model = N.WarmStart(ctx, n_in, hidden, n_out, params, mu.cpu(), sd.cpu(), s_out.cpu(),
                         analytic_skip=analytic_skip)
+    if prec != N.NYS_F64:
+        model.set_precision(prec)
     g = torch.Generator().manual_seed(seed + 1)
     m = X.shape[0]
     hist = []
     perm = torch.randperm(m, generator=g)
     pos = 0
+    best = (math.inf, None, -1)
+    if val is not None:
+        # the untrained network (close to the analytic start) is a candidate too
+        lv, _ = model.loss_grad(Xv, Tvn, Wv, want_grad=False)
+        best = (lv, model.params(), -1)
     for k in range(steps):
         if pos + batch > m:
             perm = torch.randperm(m, generator=g)
@@ -98,6 +128,19 @@ def fit(ctx: N.Context, X: torch.Tensor, T: torch.Tensor, lam: Sequence[float],
                                 lr=lr)
         if log_every and (k % log_every == 0 or k == steps - 1):
             hist.append((k, loss))
+        if val is not None and (k % val_every == val_every - 1 or k == steps - 1):
+            lv, _ = model.loss_grad(Xv, Tvn, Wv, want_grad=False)
+            if lv < best[0]:
+                best = (lv, model.params(), k)
+    if val is not None and best[1] is not None:
+        # the weights of the best validation loss, in the same precision
+        model.close()
+        model = N.WarmStart(ctx, n_in, hidden, n_out, best[1], mu.cpu(), sd.cpu(), s_out.cpu(),
+                            analytic_skip=analytic_skip)
+        if prec != N.NYS_F64:
+            model.set_precision(prec)
+        model.best_step = best[2]
+        model.best_val_loss = best[0]
     return model, hist
 
 
