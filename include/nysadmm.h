@@ -197,6 +197,21 @@ nys_status nys_factor_destroy(nys_factor F);
 nys_status nys_hessian_apply(nys_ctx ctx, const nys_dense* A, const double* D, double c,
                              double rho, const double* p, double* v, double* pv_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as nys_hessian_apply, computed without any allocation.  Its
+ * workgroup partial sums live in a static scratch array of 16 MiB + 33 KiB
+ * that the library holds on every device it runs on until the process ends
+ * (looked up by nys_ctx_create); the launch uses the heuristic shape with at
+ * most as many workgroups as that array holds partial rows (no autotuning,
+ * which would allocate).  Limits: dense A (NYS_F32 with d <= 8192, NYS_F64
+ * with d <= 4096); a sparse A or a wider one gives NYS_ERR_INVALID.  Calls on
+ * one device share the array: calls that overlap on one device (from
+ * different streams or contexts) race and must be serialised by the caller;
+ * calls on one stream are ordered.  With D != NULL or pv_host != NULL the
+ * call synchronises the stream (D is checked as in nys_hessian_apply). */
+nys_status nys_hessian_apply_noalloc(nys_ctx ctx, const nys_dense* A, const double* D, double c,
+                                     double rho, const double* p, double* v, double* pv_host);
 
 /* --------------------------------------------------------- preconditioner */
 

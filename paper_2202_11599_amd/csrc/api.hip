@@ -771,6 +771,11 @@ nys_status nys_ctx_create(int device, void* hip_stream, nys_ctx* out) {
     nys_ctx_destroy(c);
     return NYS_ERR_HIP;
   }
+  const nys_status ns = noalloc_init(device);
+  if (ns != NYS_OK) {
+    nys_ctx_destroy(c);
+    return ns;
+  }
   *out = c;
   return NYS_OK;
 }

@@ -280,6 +280,17 @@ GramPlan make_gram_plan(const nys_dense& A, int num_cu) {
   return pl;
 }
 
+// The heuristic plan with at most max_grid workgroups (longer row ranges per
+// workgroup), for callers whose partial-sum buffer has a fixed size.
+GramPlan make_gram_plan_capped(const nys_dense& A, int num_cu, int64_t max_grid) {
+  GramPlan pl = make_gram_plan(A, num_cu);
+  if (max_grid < 1 || pl.grid <= max_grid || A.n <= 0) return pl;
+  const int R = pl.rows;
+  pl.rows_per_wg = ((A.n + max_grid - 1) / max_grid + R - 1) / R * R;
+  pl.grid = (int)((A.n + pl.rows_per_wg - 1) / pl.rows_per_wg);
+  return pl;
+}
+
 // Plan of the column-blocked y = A p (explicit symmetric A): blocks of 4096
 // columns (4 waves x 4 chunks of 4 floats; 2048 for FP64), rows split so that
 // blocks x row ranges give about two workgroups per CU.

@@ -368,12 +368,18 @@ struct nys_factor_s {
 
 namespace nys {
 
+// ---- noalloc.hip
+// Look up the device address of the library's static scratch array on the
+// current device (once per device; called by nys_ctx_create).
+nys_status noalloc_init(int device);
+
 // ---- block cache (api.hip)
 void pool_register_stream(int device, hipStream_t st);
 void pool_unregister_stream(int device, hipStream_t st);
 
 // ---- gemv.hip
 GramPlan make_gram_plan(const nys_dense& A, int num_cu);
+GramPlan make_gram_plan_capped(const nys_dense& A, int num_cu, int64_t max_grid);
 // columns one workgroup of the fused matvec covers (the widest plan): d above
 // this takes the two-pass wide form
 int64_t gram_max_cols(nys_dtype dt);

@@ -33,7 +33,7 @@ EXPORTS = [
     "nys_precond_apply", "pcg_solve", "admm_step", "admm_solve", "nys_ws_param_count",
     "nys_ws_create", "nys_ws_get_params", "nys_ws_forward", "nys_ws_loss_grad",
     "nys_ws_train_step", "nys_ws_destroy", "nys_kernel_rbf", "nys_sketch_sym", "pcg_solve_sym",
-    "svm_solve", "nys_sparse_create", "nys_sparse_destroy",
+    "svm_solve", "nys_sparse_create", "nys_sparse_destroy", "nys_hessian_apply_noalloc",
     "nys_workspace_query", "nys_ctx_set_workspace", "nys_ctx_workspace_peak",
     "nys_ws_set_precision",
 ]
@@ -134,6 +134,7 @@ def lib():
         "nys_factor_get_U": (i32, [vp, vp, vp]),
         "nys_factor_destroy": (i32, [vp]),
         "nys_hessian_apply": (i32, [vp, P(Dense), vp, dbl, dbl, vp, vp, P(dbl)]),
+        "nys_hessian_apply_noalloc": (i32, [vp, P(Dense), vp, dbl, dbl, vp, vp, P(dbl)]),
         "nys_precond_apply": (i32, [vp, vp, dbl, vp, vp]),
         "pcg_solve": (i32, [vp, P(Dense), vp, dbl, dbl, vp, vp, vp, P(PcgOpts), P(PcgInfo)]),
         "admm_step": (i32, [vp, P(Problem), P(AdmmOpts), P(vp), P(AdmmState), P(AdmmInfo)]),
@@ -402,6 +403,23 @@ def nys_hessian_apply(ctx: Context, A: torch.Tensor, p: torch.Tensor, rho: float
     _check(lib().nys_hessian_apply(ctx.h, C.byref(dA), _ptr(D), float(c), float(rho), _ptr(p), _ptr(v),
                                    C.byref(pv) if want_pv else None), "nys_hessian_apply")
     return (v, pv.value) if want_pv else v
+
+
+def nys_hessian_apply_noalloc(ctx: Context, A: torch.Tensor, p: torch.Tensor, out: torch.Tensor,
+                              rho: float = 0.0, D: Optional[torch.Tensor] = None, c: float = 0.0,
+                              want_pv: bool = False):
+    """nys_hessian_apply without device allocation in the library (scratch is
+    the library's static array); `out` is the caller's FP64 d-vector."""
+    dA = dense(A)
+    _vec(p, A.shape[1], "p")
+    _vec(out, A.shape[1], "out")
+    if D is not None:
+        _vec(D, A.shape[0], "D")
+    pv = C.c_double()
+    _check(lib().nys_hessian_apply_noalloc(ctx.h, C.byref(dA), _ptr(D), float(c), float(rho),
+                                           _ptr(p), _ptr(out), C.byref(pv) if want_pv else None),
+           "nys_hessian_apply_noalloc")
+    return (out, pv.value) if want_pv else out
 
 
 def nys_precond_apply(ctx: Context, F: Factor, rho: float, w: torch.Tensor,
