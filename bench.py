@@ -54,7 +54,7 @@ def parse():
                          "headline checks every solve; a 1-in-10 variant is reported beside it)")
     ap.add_argument("--workload",
                     choices=["lasso", "logistic", "path", "learned", "cg", "svm", "sparse",
-                             "precision_path"],
+                             "precision_path", "sketch"],
                     default="lasso",
                     help="lasso: 100000x4000 adaptive rank (default line); logistic: 200000x2000 "
                          "l1-logistic; path: 64 uneven lasso instances x 16 gammas, batched; "
@@ -517,6 +517,51 @@ def svm_cpu_baseline(H, b, omega, rho, iters_per_solve, cpu_iters):
     }
 
 
+def bench_sketch(args, N, synth, torch):
+    """The sketch alone on the 100000 x 4000 FP32 lasso matrix: one fixed-rank
+    Algorithm RandNysAppx per rank r in {50, 100, 200} and sketch precision
+    (FP32 MFMA, BF16 MFMA), each timed over --steps calls after a warm-up
+    call (the FP64 core included).  The MFMA kernels' own durations and
+    utilisation come from rocprofv3 runs of this workload: T = A Omega and
+    Y = A^T T each do 2 n d r flops and read A once (n d 4 bytes), so their
+    bound is min(MFMA peak, (r / 2 flop per byte) x 8 TB/s).
+    value = sketches/s at r = 200, FP32."""
+    n, d = args.n, args.d
+    p = synth.lasso_decay(n, d, 0.8, seed=0, device="cpu" if args.host_data else "cuda",
+                          dtype=torch.float32, frac=0.02, noise=0.01, gamma_frac=LASSO_GAMMA_FRAC,
+                          rho=1e-4, rank=50, s_max=800, pcg_tol=1e-6)
+    A, omega = p.A.cuda(), p.omega.cuda().contiguous()
+    ctx = N.Context()
+    rows = []
+    value = None
+    for prec, pname in ((N.NYS_F32, "fp32"), (N.NYS_BF16, "bf16")):
+        for r in (50, 100, 200):
+            om = omega[:r].contiguous()
+            N.nys_sketch(ctx, A, om, prec=prec).close()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                F = N.nys_sketch(ctx, A, om, prec=prec)
+                F.close()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            flops = 4.0 * n * d * r
+            rows.append({"prec": pname, "rank": r, "ms_per_sketch": round(ms, 3),
+                         "gemm_flops": flops,
+                         "mfma_peak_tflops": 157.3 if pname == "fp32" else 2500.0,
+                         "hbm_bound_tflops": round(r / 2.0 * 8.0, 1)})
+            print(f"[bench] sketch {pname} r={r}: {ms:.2f} ms", file=sys.stderr, flush=True)
+            if pname == "fp32" and r == 200:
+                value = 1e3 / ms
+    out = base_record(value, args.steps, 1, 1e3 / value, "f32", {
+        "workload": f"sketch-{n}x{d}-fp32-sigma_j=j^-0.8-fixed-rank-50-100-200-fp32-bf16",
+        "n": n, "d": d})
+    out["unit"] = "sketches/s"
+    out["metric"] = "Nystrom sketches/s (fixed rank) on the lasso matrix"
+    out["sketch"] = rows
+    return out
+
+
 def bench_precision_path(args, N, synth, torch):
     """Lasso precision path on an STL-10-shaped matrix (Section 5, Figure
     precisionpath; Table dataset: 13000 x 27648, dense): time from a cold start
@@ -693,7 +738,7 @@ def bench_path(args, N, synth, torch):
         return wall, solves, pcg, bad, trm, (ctx.profile_stop() if profile else None)
 
     one_path(gammas=1)
-    wall, solves, pcg, bad, trm, prof = one_path()
+    wall, solves, pcg, bad, trm, prof = one_path(profile=True)
     out = base_record(solves / wall, 1, 1, wall, "f32", {
         "workload": f"lasso-path-{len(probs)}-instances-n5000..50000-d500..3000-fp32-"
                     f"sigma_j=j^-0.7-rank100-{args.gammas}gammas-50iters",
@@ -702,8 +747,14 @@ def bench_path(args, N, synth, torch):
     out["pcg_iters_mean"] = round(pcg / max(solves, 1), 3)
     out["unconverged_solves"] = bad
     out["true_rel_res_max"] = trm
-    out["note"] = ("matvec-pair time is not event-timed here (the batched pair is one persistent "
-                   "launch per row-width bucket); see profiles/ for its rocprofv3 duration")
+    # the timed passes are the true-residual passes of every ADMM step, outside
+    # the captured PCG graphs: one batched pair launch per row-width bucket
+    # over all instances (all stay active through the fixed 50 iterations)
+    out["roofline"] = roofline(prof, total_bytes, None, None)
+    out["roofline"]["kernel"] = ("k_bgram (batched fused pair, one launch per row-width bucket; "
+                                 "timed over the true-residual passes)")
+    out["roofline"]["traffic"] = None
+    out["roofline"]["alg_bytes_per_launch_note"] = "sum over instances of n_i d_i 4 bytes"
     return out
 
 
@@ -781,13 +832,16 @@ def bench_learned(args, N, synth, torch):
 def main():
     args = parse()
     if args.pmc_summary:
-        cmd = ("cd /tmp && export TMPDIR=/tmp && cd $R && timeout -s KILL 300 rocprofv3 --pmc {c} "
-               "--kernel-include-regex 'k_gram|elementwise|copy' -d {d} -o run --output-format csv "
-               "-- python bench.py --steps 1 --warmup 0 --admm-iters 5 --no-mixed "
-               "--no-cpu-baseline --copy-reference --host-data")
+        # R = the repository root
+        cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 400 rocprofv3 --pmc {c} "
+               "--kernel-include-regex 'k_gram|elementwise|copy' -d $R/{d} -o run "
+               "--output-format csv -- python $R/bench.py --steps 1 --warmup 0 --admm-iters 5 "
+               "--no-mixed --no-cpu-baseline --copy-reference --host-data")
         rec = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.n, args.d,
                           [cmd.format(c="FETCH_SIZE", d="gpurun_out/pmc_fetch"),
-                           cmd.format(c="WRITE_SIZE", d="gpurun_out/pmc_write")])
+                           cmd.format(c="WRITE_SIZE", d="gpurun_out/pmc_write"),
+                           "cd $R && python bench.py --pmc-summary gpurun_out/pmc_fetch "
+                           "gpurun_out/pmc_write"])
         path = os.path.join(ROOT, "profiles", "gram_traffic.json")
         with open(path, "w") as fh:
             json.dump(rec, fh, indent=2)
@@ -806,7 +860,8 @@ def main():
         torch.cuda.set_device(0)
         fn = {"logistic": bench_logistic, "path": bench_path,
               "learned": bench_learned, "cg": bench_cg, "svm": bench_svm,
-              "sparse": bench_sparse, "precision_path": bench_precision_path}[args.workload]
+              "sparse": bench_sparse, "precision_path": bench_precision_path,
+              "sketch": bench_sketch}[args.workload]
         print(json.dumps(fn(args, N, synth, torch)), flush=True)
         return
     from paper_2202_11599_amd import nysadmm as N

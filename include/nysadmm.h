@@ -132,7 +132,9 @@ size_t nys_ctx_workspace_peak(nys_ctx ctx);
 
 /* Kernel timing (instrumentation, not part of the method): while enabled the
  * library brackets every launch of the fused matvec-pair kernel with HIP
- * events on the context's stream.  nys_ctx_profile_stop synchronises the
+ * events on the context's stream (in the batched path: every true-residual
+ * pass, one launch per row-width bucket over all active instances, outside
+ * the captured PCG graphs).  nys_ctx_profile_stop synchronises the
  * stream, writes the number of launches that did a full pass (launches queued
  * past PCG convergence return at once and are not counted) and the summed
  * duration in ms of all timed launches, and disables the timing. */

@@ -870,8 +870,25 @@ nys_status batch_pcg(nys_ctx ctx, Batch* B, int max_iter, std::vector<PcgDev>* s
     if (running == 0 || done_iters >= max_iter + B->graph_iters) break;
   }
   if (check) {
-    // FP64-accumulated true residual of every active instance
+    // FP64-accumulated true residual of every active instance: a full pass
+    // over each active instance's A, bracketed by timing events while the
+    // context's kernel timing is on
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->prof_on) {
+      while (ctx->prof_used + 2 > ctx->prof_ev.size()) {
+        hipEvent_t e;
+        NYS_TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+        ctx->prof_ev.push_back(e);
+      }
+      e0 = ctx->prof_ev[ctx->prof_used];
+      e1 = ctx->prof_ev[ctx->prof_used + 1];
+      NYS_TRY_HIP(hipEventRecord(e0, st));
+    }
     NYS_TRY(bgram(*B, kModeHess, 0, 0, st));
+    if (e1 != nullptr) {
+      NYS_TRY_HIP(hipEventRecord(e1, st));
+      ctx->prof_used += 2;
+    }
     hipLaunchKernelGGL(k_breduce, dim3(B->n64), dim3(1024), 0, st, B->insts, B->it64, 2);
     hipLaunchKernelGGL(k_bdot, dim3(B->ndot), dim3(256), 0, st, B->insts, B->itdot, 3);
   }
@@ -1017,6 +1034,10 @@ nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
   if (B.graph != nullptr) (void)hipGraphExecDestroy(B.graph);
   (void)hipStreamSynchronize(st);
   B.dev.release();
+  // only the batched passes are timed: the closing per-instance KKT passes
+  // would mix single-matrix launches into the batched average
+  const bool prof_on = ctx->prof_on;
+  ctx->prof_on = false;
   for (int q = 0; q < count; ++q) {
     if (s == NYS_OK) {
       nys_status ks = admm_kkt(ctx, P[q], S[q].z, &info[q].eta, &info[q].obj);
@@ -1025,6 +1046,7 @@ nys_status admm_solve_batched(nys_ctx ctx, int count, const nys_problem* P,
     if (owned[q] && F[q] != nullptr) nys_factor_destroy(F[q]);
     if (I) I[q] = info[q];
   }
+  ctx->prof_on = prof_on;
   return s;
 }
 
