@@ -40,16 +40,24 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, int kchunk,
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  // consecutive threads take consecutive elements along whichever index has
+  // unit stride (k for the Gram-type products X^T Y of column-major X, Y;
+  // m or n otherwise), so every load instruction reads whole cache lines
+  const bool ak = (sak == 1 && sam != 1), bk = (sbk == 1 && sbn != 1);
   for (int k0 = kb; k0 < ke; k0 += 16) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = tid + e * 256;
-      const int mm = idx & 63, kk = idx >> 6;
-      const int gk = k0 + kk;
-      As[kk][mm] = (m0 + mm < M && gk < ke) ? (double)A[(int64_t)(m0 + mm) * sam + (int64_t)gk * sak] : 0.0;
-      Bs[kk][mm] = (n0 + mm < N && gk < ke)
-                       ? (double)B[(int64_t)gk * sbk + (int64_t)(n0 + mm) * sbn] * (wk ? wk[gk] : 1.0)
+      const int mm = ak ? (idx >> 4) : (idx & 63), ka = ak ? (idx & 15) : (idx >> 6);
+      const int nn = bk ? (idx >> 4) : (idx & 63), kb2 = bk ? (idx & 15) : (idx >> 6);
+      const int gka = k0 + ka, gkb = k0 + kb2;
+      As[ka][mm] = (m0 + mm < M && gka < ke)
+                       ? (double)A[(int64_t)(m0 + mm) * sam + (int64_t)gka * sak]
                        : 0.0;
+      Bs[kb2][nn] = (n0 + nn < N && gkb < ke)
+                        ? (double)B[(int64_t)gkb * sbk + (int64_t)(n0 + nn) * sbn] *
+                              (wk ? wk[gkb] : 1.0)
+                        : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -494,17 +502,28 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
 }
 
 // ------------------------------------------------------------ Jacobi
-// Two-sided block Jacobi on the symmetric R x R matrix G (R a multiple of 32,
-// row-major), blocks of 16 indices, block pairs chosen round-robin.  Each
-// workgroup diagonalises one 32 x 32 pair block in LDS by one cyclic Jacobi
-// sweep with parallel rotation ordering and writes its rotation Q; then every
-// tile of G becomes Q_P^T G_PQ Q_Q and V becomes V Q.
+// Two-sided block Jacobi on the symmetric R x R matrix H (R a multiple of 32,
+// row-major), blocks of 16 indices, block pairs chosen round-robin (nb - 1
+// rounds of nb / 2 disjoint pairs per sweep).  Within a visit of the pair
+// block (a, b) only the pairs (i in a, j in b) are rotated, 16 at a time:
+// step s pairs index k of a with index (k + s) mod 16 of b, so every cross
+// pair is rotated once per visit.  The pairs inside a block are rotated in the
+// first round of each sweep (a cyclic round-robin over the 16 indices of each
+// block of the pair, before the cross steps).  Every off-diagonal pair is
+// therefore rotated once per sweep, in about R sequential steps, half of what
+// a full cyclic sweep of each 32 x 32 pair block per round would take.
+//
+// A round is one launch: nb / 2 workgroups solve the pair blocks of round t
+// (forming each 32 x 32 pair block from H_{t-1} and the rotations Q^{t-1} of
+// the previous round, so that they need not wait for the full update), and
+// the remaining workgroups form H_t = Q^{t-1 T} H_{t-1} Q^{t-1} tile by tile
+// and accumulate V <- V Q^{t-1}.  The last round's update is a launch of its
+// own, followed by the convergence check.
 constexpr int kJB = 16;        // block size
 constexpr int kJP = 2 * kJB;   // pair block size
-constexpr int kJT = 256;       // threads of the apply workgroups
-constexpr int kJS = 256;       // threads of the solve workgroups
+constexpr int kJT = 256;       // threads of every Jacobi workgroup
 constexpr int kJE = kJP * kJP / kJT;   // tile elements per thread
-static_assert(kJB * kJB % kJS == 0 && kJB * kJP % kJS == 0, "whole 2x2 blocks per lane");
+constexpr int kJU = kJB * (kJB + 1) / 2;   // upper 2x2 blocks of a step
 constexpr double kJacTol = 1e-15;
 
 // Round-robin pairing of nb blocks (nb even): round t, pair k -> (a, b).
@@ -512,6 +531,19 @@ __device__ __forceinline__ void rr_pair(int nb, int t, int k, int* a, int* b) {
   auto pos = [&](int p) { return p == 0 ? 0 : ((p - 1 + t) % (nb - 1)) + 1; };
   *a = pos(k);
   *b = pos(nb - 1 - k);
+}
+
+// The pair k of round t that holds block x, and whether x is its second member.
+__device__ __forceinline__ void rr_locate(int nb, int t, int x, int* k, int* h) {
+  int p = 0;
+  if (x != 0) p = ((x - 1 - t) % (nb - 1) + (nb - 1)) % (nb - 1) + 1;
+  if (p < nb / 2) {
+    *k = p;
+    *h = 0;
+  } else {
+    *k = nb - 1 - p;
+    *h = 1;
+  }
 }
 
 // counters[s]: pair blocks that rotated in sweep s; counters[64 + s]: 1 if
@@ -522,12 +554,12 @@ __device__ __forceinline__ bool jacobi_skip(const int* counters, int sweep) {
   return sweep > 0 && counters[64 + sweep - 1] == 0;
 }
 
-// index of the i-th member (0..63) of pair block (a, b)
+// index of the i-th member (0..31) of pair block (a, b)
 __device__ __forceinline__ int pair_index(int a, int b, int i) {
   return i < kJB ? a * kJB + i : b * kJB + (i - kJB);
 }
 
-// A rotation is applied when |a_pq| > max(tol sqrt(|a_pp a_qq|), tol * trace(G)):
+// A rotation is applied when |a_pq| > max(tol sqrt(|a_pp a_qq|), tol * trace(H)):
 // the relative test gives small eigenvalues their accuracy, the absolute floor
 // stops rotations that only chase the rounding of the tile updates.  Compared
 // in squares (no square root).
@@ -536,110 +568,142 @@ __device__ __forceinline__ bool jac_rotates(double apq, double app, double aqq, 
          apq * apq > fmax(kJacTol * kJacTol * fabs(app * aqq), floor_abs * floor_abs);
 }
 
-__global__ __launch_bounds__(kJS) void k_jacobi_solve(const double* __restrict__ G, int R,
-                                                      int round, double* __restrict__ Qbuf,
-                                                      int* __restrict__ counters, int sweep,
-                                                      const double* __restrict__ gnorm) {
-  if (jacobi_skip(counters, sweep)) return;
-  const double floor_abs = kJacTol * (*gnorm);
-  __shared__ double S[kJP][kJP + 1];
-  __shared__ double Q[kJP][kJP + 1];
-  __shared__ double cs[kJB][2];
-  __shared__ int pq[kJB][2];
-  const int tid = threadIdx.x;
-  const int nb = R / kJB;
-  int a, b;
-  rr_pair(nb, round, blockIdx.x, &a, &b);
-  #pragma unroll   // constant trip count: the loads issue together
-  for (int e = tid; e < kJP * kJP; e += kJS) {
-    const int i = e / kJP, j = e % kJP;
-    S[i][j] = G[(int64_t)pair_index(a, b, i) * R + pair_index(a, b, j)];
-    Q[i][j] = (i == j) ? 1.0 : 0.0;
+// The rotation (c, s) of positions p < q that zeroes a_pq, with the inner
+// angle |phi| <= pi / 4: theta = (a_qq - a_pp) / 2, h = sqrt(theta^2 + a_pq^2),
+// cos 2 phi = |theta| / h, c^2 = (1 + cos 2 phi) / 2 and s = sign(theta) a_pq /
+// (2 h c).  c^2 has no cancellation, and c^2 + s^2 = 1 to rounding because
+// sin^2 2 phi = 1 - cos^2 2 phi.  s = 0 means no rotation.
+__device__ __forceinline__ double2 jac_rotation(double apq, double app, double aqq,
+                                                double floor_abs, bool* rotated) {
+  if (!jac_rotates(apq, app, aqq, floor_abs)) return make_double2(1.0, 0.0);
+  *rotated = true;
+  const double theta = 0.5 * (aqq - app);
+  const double h2 = fma(theta, theta, apq * apq);
+  double c, s;
+  if (h2 > 1e-280 && h2 < 1e280) {
+    const double rh = rsq_nr(h2);
+    const double c2 = fma(0.5 * fabs(theta), rh, 0.5);
+    const double rc = rsq_nr(c2);
+    c = c2 * rc;
+    s = 0.5 * apq * rh * rc;
+  } else {   // squares near the ends of the range: the tangent form, no squaring
+    const double tau = theta / apq;
+    const double t = copysign(1.0 / (fabs(tau) + sqrt(1.0 + tau * tau)), apq);
+    c = 1.0 / sqrt(fma(t, t, 1.0));
+    s = t * c;
   }
-  bool rotated = false;
-  __syncthreads();
-  // one cyclic sweep of the pair block per visit (block Jacobi); the outer
-  // sweeps repeat until the matrix passes the criterion.  Round-robin over the
-  // kJP indices: at step t rotation k pairs positions k and kJP-1-k of the
-  // rotated order.
-  for (int step = 0; step < kJP - 1; ++step) {
-    if (tid < kJB) {
-      auto pos = [&](int p) { return p == 0 ? 0 : ((p - 1 + step) % (kJP - 1)) + 1; };
-      int p = pos(tid), q = pos(kJP - 1 - tid);
-      if (p > q) { const int t = p; p = q; q = t; }
-      const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
-      double c = 1.0, sn = 0.0;
-      if (jac_rotates(apq, app, aqq, floor_abs)) {
-        // t = tan of the angle that zeroes a_pq, the root of t^2 + 2 tau t - 1
-        // of smaller magnitude (tau = theta / a_pq, theta = (a_qq - a_pp) / 2):
-        // t = sign(theta) a_pq / (|theta| + sqrt(theta^2 + a_pq^2))
-        const double theta = 0.5 * (aqq - app);
-        const double h2 = fma(theta, theta, apq * apq);
-        double t;
-        if (h2 > 1e-280 && h2 < 1e280) {
-          const double h = h2 * rsq_nr(h2);
-          t = apq * rcp_nr(fabs(theta) + h);
-        } else {   // squares near the ends of the range: no squaring
-          const double tau = theta / apq;
-          t = copysign(1.0 / (fabs(tau) + sqrt(1.0 + tau * tau)), apq);
-        }
-        if (theta < 0.0) t = -t;
-        c = rsq_nr(fma(t, t, 1.0));
-        sn = t * c;
-        rotated = true;
-      }
-      cs[tid][0] = c;
-      cs[tid][1] = sn;
-      pq[tid][0] = p;
-      pq[tid][1] = q;
-    }
-    __syncthreads();
-    // S <- J^T S J as independent 2x2 blocks: block (ka, kb) covers rows
-    // {p_ka, q_ka} x columns {p_kb, q_kb} (row rotation, then column rotation);
-    // Q <- Q J on columns.  Blocks are disjoint.
-#pragma unroll
-    for (int h = 0; h < kJB * kJB / kJS; ++h) {
-      const int blk = tid + h * kJS;
-      const int ka = blk / kJB, kb2 = blk % kJB;
-      const double sa = cs[ka][1], sb = cs[kb2][1];
-      if (sa != 0.0 || sb != 0.0) {
-        const int p = pq[ka][0], q = pq[ka][1], p2 = pq[kb2][0], q2 = pq[kb2][1];
-        double x00 = S[p][p2], x01 = S[p][q2], x10 = S[q][p2], x11 = S[q][q2];
-        if (sa != 0.0) {
-          const double c = cs[ka][0];
-          const double y00 = c * x00 - sa * x10, y01 = c * x01 - sa * x11;
-          const double y10 = sa * x00 + c * x10, y11 = sa * x01 + c * x11;
-          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-        }
-        if (sb != 0.0) {
-          const double c = cs[kb2][0];
-          const double y00 = c * x00 - sb * x01, y01 = sb * x00 + c * x01;
-          const double y10 = c * x10 - sb * x11, y11 = sb * x10 + c * x11;
-          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-        }
-        S[p][p2] = x00; S[p][q2] = x01; S[q][p2] = x10; S[q][q2] = x11;
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < kJB * kJP / kJS; ++h) {
-      const int e = tid + h * kJS;
-      const int k = e / kJP, i = e % kJP;
-      const double sn = cs[k][1];
-      if (sn != 0.0) {
-        const double c = cs[k][0];
-        const int pp = pq[k][0], qq = pq[k][1];
-        const double qp = Q[i][pp], qv = Q[i][qq];
-        Q[i][pp] = c * qp - sn * qv;
-        Q[i][qq] = sn * qp + c * qv;
-      }
-    }
-    __syncthreads();
+  return make_double2(c, theta < 0.0 ? -s : s);
+}
+
+// (x00 x01; x10 x11) <- J_a^T X J_b for the rotations ra (rows) and rb (columns)
+__device__ __forceinline__ void blk_rotate(double2 ra, double2 rb, double& x00, double& x01,
+                                           double& x10, double& x11) {
+  if (ra.y != 0.0) {
+    const double c = ra.x, s = ra.y;
+    const double y00 = c * x00 - s * x10, y01 = c * x01 - s * x11;
+    const double y10 = s * x00 + c * x10, y11 = s * x01 + c * x11;
+    x00 = y00; x01 = y01; x10 = y10; x11 = y11;
   }
-  double* Qo = Qbuf + (int64_t)blockIdx.x * kJP * kJP;
-  #pragma unroll   // constant trip count: the loads issue together
-  for (int e = tid; e < kJP * kJP; e += kJS) Qo[e] = Q[e / kJP][e % kJP];
-  // only the first kJB threads (all in the first wavefront) compute rotations
-  if (__any(rotated) && tid == 0) atomicAdd(&counters[sweep], 1);
+  if (rb.y != 0.0) {
+    const double c = rb.x, s = rb.y;
+    const double y00 = c * x00 - s * x01, y01 = s * x00 + c * x01;
+    const double y10 = c * x10 - s * x11, y11 = s * x10 + c * x11;
+    x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+  }
+}
+
+__device__ __forceinline__ int rr16(int x, int st) { return x == 0 ? 0 : ((x - 1 + st) % 15) + 1; }
+
+// Positions p < q of rotation k (0..15) at step st of a visit.  INTRA steps:
+// rotations 0..7 pair positions of the first block (round-robin over its 16
+// indices), 8..15 those of the second.  Cross steps: k with 16 + (k + st) % 16.
+template <bool INTRA>
+__device__ __forceinline__ void step_pair(int k, int st, int* p, int* q) {
+  if (INTRA) {
+    const int blk = k >> 3, kk = k & 7;
+    int x = rr16(kk, st), y = rr16(15 - kk, st);
+    if (x > y) {
+      const int t = x;
+      x = y;
+      y = t;
+    }
+    *p = kJB * blk + x;
+    *q = kJB * blk + y;
+  } else {
+    *p = k;
+    *q = kJB + ((k + st) & (kJB - 1));
+  }
+}
+
+// The 2x2 block of rotations (ka, kb), ka <= kb, of the step, and its mirror.
+// S stays exactly symmetric: the block and its transpose get the same values,
+// and the rotated pair's off-diagonal entry is set to zero.
+template <bool INTRA>
+__device__ __forceinline__ void upd_block(double (&S)[kJP][kJP + 1], const double2* C, int st,
+                                          int ka, int kb) {
+  const double2 ra = C[ka], rb = C[kb];
+  if (ra.y == 0.0 && rb.y == 0.0) return;
+  int p, q, p2, q2;
+  step_pair<INTRA>(ka, st, &p, &q);
+  step_pair<INTRA>(kb, st, &p2, &q2);
+  double x00 = S[p][p2], x01 = S[p][q2], x10 = S[q][p2], x11 = S[q][q2];
+  blk_rotate(ra, rb, x00, x01, x10, x11);
+  if (ka == kb) {
+    S[p][p] = x00;
+    S[q][q] = x11;
+    S[p][q] = 0.0;
+    S[q][p] = 0.0;
+  } else {
+    S[p][p2] = x00; S[p][q2] = x01; S[q][p2] = x10; S[q][q2] = x11;
+    S[p2][p] = x00; S[q2][p] = x01; S[p2][q] = x10; S[q2][q] = x11;
+  }
+}
+
+// Q <- Q J over the 16 rotations of the step: two (row, rotation) pairs per thread
+template <bool INTRA>
+__device__ __forceinline__ void upd_q(double (&Q)[kJP][kJP + 1], const double2* C, int st,
+                                      int tid) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + kJT * h;
+    const int i = e >> 4, k = e & (kJB - 1);
+    const double2 r = C[k];
+    if (r.y != 0.0) {
+      int p, q;
+      step_pair<INTRA>(k, st, &p, &q);
+      const double qp = Q[i][p], qv = Q[i][q];
+      Q[i][p] = r.x * qp - r.y * qv;
+      Q[i][q] = r.y * qp + r.x * qv;
+    }
+  }
+}
+static_assert(kJP * kJB == 2 * kJT, "two (row, rotation) pairs per thread");
+
+// e-th upper 2x2 block (ka <= kb), row-major over the upper triangle
+__device__ __forceinline__ void upper_block(int e, int* ka, int* kb) {
+  int a = 0;
+  while (e >= kJB - a) {
+    e -= kJB - a;
+    ++a;
+  }
+  *ka = a;
+  *kb = a + e;
+}
+// e-th upper block that is neither diagonal nor (a, a + 1) nor (0, 15): the
+// 104 blocks the rotation lanes do not own in the cross steps
+constexpr int kJOther = kJU - 2 * kJB;
+__device__ __forceinline__ void other_block(int e, int* ka, int* kb) {
+  *ka = *kb = 0;
+  for (int a = 0; a < kJB; ++a) {
+    const int lo = a + 2, hi = (a == 0) ? kJB - 2 : kJB - 1;
+    const int n = hi >= lo ? hi - lo + 1 : 0;
+    if (e < n) {
+      *ka = a;
+      *kb = lo + e;
+      return;
+    }
+    e -= n;
+  }
 }
 
 // o[a][b] = sum_l X(l, ii + 16a) Y(l, jj + 16b) over l in order (the two
@@ -663,73 +727,66 @@ __device__ __forceinline__ void tile_mm(const double (&X)[kJP][kJP + 1],
   }
 }
 
-// G_out tile (P, Q) = Q_P^T G_in[P, Q] Q_Q for pair blocks P, Q of the round,
-// and V[rows, P] <- V[rows, P] Q_P (extra workgroups).
-__global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__ Gin,
-                                                      double* __restrict__ Gout,
-                                                      double* __restrict__ V, int R, int round,
-                                                      const double* __restrict__ Qbuf,
-                                                      const int* __restrict__ counters,
-                                                      int sweep) {
-  if (jacobi_skip(counters, sweep)) return;
-  __shared__ double T[kJP][kJP + 1];
-  __shared__ double W[kJP][kJP + 1];
+// Update workgroup v of round t: v < np^2 forms tile (P, Q) of
+// Hout = Q_P^T Hin[P, Q] Q_Q; the others take V[rows, P] <- V[rows, P] Q_P.
+__device__ __forceinline__ void jacobi_update(const double* __restrict__ Hin,
+                                              double* __restrict__ Hout, double* __restrict__ V,
+                                              int R, int t, const double* __restrict__ Qbuf,
+                                              int v, double (&T)[kJP][kJP + 1],
+                                              double (&W)[kJP][kJP + 1]) {
   const int tid = threadIdx.x;
   const int nb = R / kJB;
   const int np = nb / 2;
-  const int bid = blockIdx.x;
-  if (bid < np * np) {
-    const int P = bid / np, Qi = bid % np;
+  const int ii = tid >> 4, jj = tid & 15;
+  double o[2][2];
+  if (v < np * np) {
+    const int P = v / np, Qi = v % np;
     int pa, pb, qa, qb;
-    rr_pair(nb, round, P, &pa, &pb);
-    rr_pair(nb, round, Qi, &qa, &qb);
+    rr_pair(nb, t, P, &pa, &pb);
+    rr_pair(nb, t, Qi, &qa, &qb);
     const double* QP = Qbuf + (int64_t)P * kJP * kJP;
     const double* QQ = Qbuf + (int64_t)Qi * kJP * kJP;
-    #pragma unroll   // constant trip count: the loads issue together
-    for (int e = tid; e < kJP * kJP; e += kJT) {
+#pragma unroll
+    for (int h = 0; h < kJE; ++h) {
+      const int e = tid + h * kJT;
       const int i = e / kJP, j = e % kJP;
-      T[i][j] = Gin[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)];
+      T[i][j] = Hin[(int64_t)pair_index(pa, pb, i) * R + pair_index(qa, qb, j)];
       W[i][j] = QQ[e];
     }
     __syncthreads();
-    const int ii = tid >> 4, jj = tid & 15;
-    // X = T * Q_Q
-    double o[2][2];
-    tile_mm<false>(T, W, ii, jj, o);
+    tile_mm<false>(T, W, ii, jj, o);   // X = T Q_Q
     __syncthreads();
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) T[ii + 16 * a][jj + 16 * b] = o[a][b];
 #pragma unroll
-    for (int t = 0; t < kJE; ++t) {
-      const int e = tid + t * kJT;
+    for (int h = 0; h < kJE; ++h) {
+      const int e = tid + h * kJT;
       W[e / kJP][e % kJP] = QP[e];
     }
     __syncthreads();
-    // out = Q_P^T * X
-    tile_mm<true>(W, T, ii, jj, o);
+    tile_mm<true>(W, T, ii, jj, o);    // Q_P^T X
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
-        Gout[(int64_t)pair_index(pa, pb, ii + 16 * a) * R + pair_index(qa, qb, jj + 16 * b)] =
+        Hout[(int64_t)pair_index(pa, pb, ii + 16 * a) * R + pair_index(qa, qb, jj + 16 * b)] =
             o[a][b];
   } else {
-    const int v = bid - np * np;
-    const int P = v % np, rc = v / np;
+    const int w = v - np * np;
+    const int P = w % np, rc = w / np;
     int pa, pb;
-    rr_pair(nb, round, P, &pa, &pb);
+    rr_pair(nb, t, P, &pa, &pb);
     const double* QP = Qbuf + (int64_t)P * kJP * kJP;
-    #pragma unroll   // constant trip count: the loads issue together
-    for (int e = tid; e < kJP * kJP; e += kJT) {
+#pragma unroll
+    for (int h = 0; h < kJE; ++h) {
+      const int e = tid + h * kJT;
       const int i = e / kJP, j = e % kJP;
       T[i][j] = V[(int64_t)(rc * kJP + i) * R + pair_index(pa, pb, j)];
       W[i][j] = QP[e];
     }
     __syncthreads();
-    const int ii = tid >> 4, jj = tid & 15;
-    double o[2][2];
     tile_mm<false>(T, W, ii, jj, o);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -739,9 +796,222 @@ __global__ __launch_bounds__(kJT) void k_jacobi_apply(const double* __restrict__
   }
 }
 
+// S <- the pair block (a, b) of H_t = Q^{t-1 T} H_{t-1} Q^{t-1}, from H_{t-1}
+// (Hin) and the previous round's rotations: with block a in pair P1 of round
+// t - 1 (half h1) and b in P2 (half h2), M_i the 16 columns of Q_{P_i} that
+// belong to the block, S_aa = M1^T H[P1, P1] M1, S_bb = M2^T H[P2, P2] M2 and
+// S_ab = M1^T H[P1, P2] M2.  S_aa and S_bb are made exactly symmetric (upper
+// triangle kept).
+struct PairForm {
+  double T[3][kJP][kJP + 1];
+  double M[2][kJP][kJB + 1];
+  double X[3][kJP][kJB + 1];
+};
+__device__ __forceinline__ void form_pair(const double* __restrict__ Hin,
+                                          const double* __restrict__ Qprev, int R, int t, int a,
+                                          int b, PairForm& F, double (&S)[kJP][kJP + 1]) {
+  const int tid = threadIdx.x;
+  const int nb = R / kJB;
+  int P[2], hf[2];
+  rr_locate(nb, t - 1, a, &P[0], &hf[0]);
+  rr_locate(nb, t - 1, b, &P[1], &hf[1]);
+  int m0[2], m1[2];
+  rr_pair(nb, t - 1, P[0], &m0[0], &m1[0]);
+  rr_pair(nb, t - 1, P[1], &m0[1], &m1[1]);
+  // tiles (P1, P1), (P2, P2), (P1, P2) and the two column blocks of Q
+#pragma unroll
+  for (int h = 0; h < kJE; ++h) {
+    const int e = tid + h * kJT;
+    const int i = e / kJP, j = e % kJP;
+    const int r0 = pair_index(m0[0], m1[0], i), r1 = pair_index(m0[1], m1[1], i);
+    const int c0 = pair_index(m0[0], m1[0], j), c1 = pair_index(m0[1], m1[1], j);
+    F.T[0][i][j] = Hin[(int64_t)r0 * R + c0];
+    F.T[1][i][j] = Hin[(int64_t)r1 * R + c1];
+    F.T[2][i][j] = Hin[(int64_t)r0 * R + c1];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + h * kJT;   // 512 = 32 x 16 per block
+    const int i = e >> 4, c = e & 15;
+    F.M[0][i][c] = Qprev[(int64_t)P[0] * kJP * kJP + i * kJP + kJB * hf[0] + c];
+    F.M[1][i][c] = Qprev[(int64_t)P[1] * kJP * kJP + i * kJP + kJB * hf[1] + c];
+  }
+  __syncthreads();
+  // X0 = T0 M1, X1 = T1 M2, X2 = T2 M2: 3 x 512 outputs, 6 per thread
+#pragma unroll
+  for (int h = 0; h < 6; ++h) {
+    const int e = tid + h * kJT;
+    const int which = e >> 9, i = (e >> 4) & 31, c = e & 15;
+    const int mi = which == 0 ? 0 : 1;
+    double s = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < kJP; ++l) s = fma(F.T[which][i][l], F.M[mi][l][c], s);
+    F.X[which][i][c] = s;
+  }
+  __syncthreads();
+  // S_aa = M1^T X0, S_bb = M2^T X1, S_ab = M1^T X2: 3 x 256 outputs
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    const int i = tid >> 4, j = tid & 15;
+    const int mi = h == 1 ? 1 : 0;
+    double s = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < kJP; ++l) s = fma(F.M[mi][l][i], F.X[h][l][j], s);
+    if (h == 0) {
+      if (i <= j) { S[i][j] = s; S[j][i] = s; }
+    } else if (h == 1) {
+      if (i <= j) { S[kJB + i][kJB + j] = s; S[kJB + j][kJB + i] = s; }
+    } else {
+      S[i][kJB + j] = s;
+      S[kJB + j][i] = s;
+    }
+  }
+}
+
+// One round of the sweep.  Workgroups 0 .. nb/2 - 1 solve the pair blocks of
+// round t and write Qcur; with FIRST (round 0) they take the pair block from
+// Hin directly and rotate the intra-block pairs first, otherwise they form it
+// from Hin = H_{t-1} and Qprev, and the further workgroups write
+// Hout = H_t and update V with Qprev.
+//
+// In the cross steps the rotation lanes (0..15) own the diagonal block of
+// their rotation and the block (k, k + 1) (lane 15: (0, 15)); after applying
+// the step they hold every entry that the next step's rotation k needs
+// (a_kk, a_kq and, from lane k + 1, a_qq), so the next rotation is formed
+// before the barrier and a step takes one barrier.
+template <bool FIRST>
+__global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__ Hin,
+                                                      double* __restrict__ Hout,
+                                                      double* __restrict__ V, int R, int round,
+                                                      const double* __restrict__ Qprev,
+                                                      double* __restrict__ Qcur,
+                                                      int* __restrict__ counters, int sweep,
+                                                      const double* __restrict__ gnorm) {
+  if (jacobi_skip(counters, sweep)) return;
+  __shared__ double S[kJP][kJP + 1];
+  __shared__ double Q[kJP][kJP + 1];
+  __shared__ double2 cs[2][kJB];
+  __shared__ PairForm F;
+  const int tid = threadIdx.x;
+  const int nb = R / kJB;
+  const int np = nb / 2;
+  if (!FIRST && (int)blockIdx.x >= np) {
+    jacobi_update(Hin, Hout, V, R, round - 1, Qprev, blockIdx.x - np, F.T[0], F.T[1]);
+    return;
+  }
+  const double floor_abs = kJacTol * (*gnorm);
+  int a, b;
+  rr_pair(nb, round, blockIdx.x, &a, &b);
+  if (FIRST) {
+#pragma unroll
+    for (int h = 0; h < kJE; ++h) {
+      const int e = tid + h * kJT;
+      const int i = e / kJP, j = e % kJP;
+      // upper triangle of the pair block, mirrored (H is symmetric up to rounding)
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      S[i][j] = Hin[(int64_t)pair_index(a, b, lo) * R + pair_index(a, b, hi)];
+    }
+  } else {
+    form_pair(Hin, Qprev, R, round, a, b, F, S);
+  }
+#pragma unroll
+  for (int h = 0; h < kJE; ++h) {
+    const int e = tid + h * kJT;
+    Q[e / kJP][e % kJP] = (e / kJP == e % kJP) ? 1.0 : 0.0;
+  }
+  bool rotated = false;
+  __syncthreads();
+  if (FIRST) {
+    int gka = 0, gkb = 0;
+    const bool gblk = tid < kJU;
+    if (gblk) upper_block(tid, &gka, &gkb);
+    for (int st = 0; st < kJB - 1; ++st) {
+      if (tid < kJB) {
+        int p, q;
+        step_pair<true>(tid, st, &p, &q);
+        cs[0][tid] = jac_rotation(S[p][q], S[p][p], S[q][q], floor_abs, &rotated);
+      }
+      __syncthreads();
+      if (gblk) upd_block<true>(S, cs[0], st, gka, gkb);
+      upd_q<true>(Q, cs[0], st, tid);
+      __syncthreads();
+    }
+  }
+  // cross steps
+  int oka = 0, okb = 0;
+  const bool oblk = tid >= 64 && tid < 64 + kJOther;
+  if (oblk) other_block(tid - 64, &oka, &okb);
+  double app = 0.0, apq = 0.0, aqq = 0.0;
+  if (tid < kJB) {
+    app = S[tid][tid];
+    apq = S[tid][kJB + tid];
+    aqq = S[kJB + tid][kJB + tid];
+    cs[0][tid] = jac_rotation(apq, app, aqq, floor_abs, &rotated);
+  }
+  __syncthreads();
+  for (int st = 0; st < kJB; ++st) {
+    const double2* C = cs[st & 1];
+    if (tid < kJB) {
+      const int k = tid, k1 = (k + 1) & (kJB - 1);
+      const int ka = (k < kJB - 1) ? k : 0, kb = (k < kJB - 1) ? k1 : kJB - 1;
+      const int p = ka, q = kJB + ((ka + st) & (kJB - 1));
+      const int p2 = kb, q2 = kJB + ((kb + st) & (kJB - 1));
+      double x00 = S[p][p2], x01 = S[p][q2], x10 = S[q][p2], x11 = S[q][q2];
+      const double2 rk = C[k], ra = C[ka], rb = C[kb];
+      // the diagonal block of rotation k, from the registers
+      double d00 = app, d01 = apq, d10 = apq, d11 = aqq;
+      if (rk.y != 0.0) {
+        const int qk = kJB + ((k + st) & (kJB - 1));
+        blk_rotate(rk, rk, d00, d01, d10, d11);
+        S[k][k] = d00;
+        S[qk][qk] = d11;
+        S[k][qk] = 0.0;
+        S[qk][k] = 0.0;
+      }
+      if (ra.y != 0.0 || rb.y != 0.0) {
+        blk_rotate(ra, rb, x00, x01, x10, x11);
+        S[p][p2] = x00; S[p][q2] = x01; S[q][p2] = x10; S[q][q2] = x11;
+        S[p2][p] = x00; S[q2][p] = x01; S[p2][q] = x10; S[q2][q] = x11;
+      }
+      const double nx11 = __shfl(d11, k1, 64);
+      if (st + 1 < kJB) {
+        app = d00;
+        aqq = nx11;
+        apq = (k < kJB - 1) ? x01 : x10;
+        cs[(st + 1) & 1][k] = jac_rotation(apq, app, aqq, floor_abs, &rotated);
+      }
+    } else if (oblk) {
+      upd_block<false>(S, C, st, oka, okb);
+    }
+    upd_q<false>(Q, C, st, tid);
+    __syncthreads();
+  }
+  double* Qo = Qcur + (int64_t)blockIdx.x * kJP * kJP;
+#pragma unroll
+  for (int h = 0; h < kJE; ++h) {
+    const int e = tid + h * kJT;
+    Qo[e] = Q[e / kJP][e % kJP];
+  }
+  // only the first kJB threads (all in the first wavefront) compute rotations
+  if (__any(rotated) && tid == 0) atomicAdd(&counters[sweep], 1);
+}
+
+// The update of the last round of a sweep (no solve follows in its launch).
+__global__ __launch_bounds__(kJT) void k_jacobi_update(const double* __restrict__ Hin,
+                                                       double* __restrict__ Hout,
+                                                       double* __restrict__ V, int R, int round,
+                                                       const double* __restrict__ Qbuf,
+                                                       const int* __restrict__ counters,
+                                                       int sweep) {
+  if (jacobi_skip(counters, sweep)) return;
+  __shared__ double T[kJP][kJP + 1];
+  __shared__ double W[kJP][kJP + 1];
+  jacobi_update(Hin, Hout, V, R, round, Qbuf, blockIdx.x, T, W);
+}
+
 // *out = trace of the R x R matrix (one workgroup)
 // flag = 1 if some off-diagonal pair of G fails the rotation criterion of
-// k_jacobi_solve (a further sweep would rotate); 0 stays otherwise.  The
+// the pair solves (a further sweep would rotate); 0 stays otherwise.  The
 // updated G is symmetric only up to the rounding of the tile products, and a
 // pair block reads whichever of G(i,j), G(j,i) its local order puts above the
 // diagonal, so the pair counts as converged when either entry passes.
@@ -908,7 +1178,7 @@ int jacobi_pad(int r) { return std::max(kJP, (r + kJP - 1) / kJP * kJP); }
 size_t jacobi_ws_doubles(int r) {
   const int R = jacobi_pad(r);
   const int np = R / kJP;
-  return 2 * (size_t)R * R + (size_t)R * R + (size_t)np * kJP * kJP + 2 * (size_t)R + 128;
+  return 2 * (size_t)R * R + (size_t)R * R + 2 * (size_t)np * kJP * kJP + 2 * (size_t)R + 128;
 }
 
 // Eigendecomposition of the symmetric r x r matrix G (row-major, ld) by block
@@ -951,8 +1221,8 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
   double* G0 = ws;
   double* G1 = G0 + (size_t)R * R;
   double* V = G1 + (size_t)R * R;
-  double* Qb = V + (size_t)R * R;
-  double* s2 = Qb + (size_t)np * kJP * kJP;
+  double* Qr[2] = {V + (size_t)R * R, V + (size_t)R * R + (size_t)np * kJP * kJP};
+  double* s2 = Qr[1] + (size_t)np * kJP * kJP;
   int* perm = reinterpret_cast<int*>(s2 + R);
   double* gnorm = s2 + 2 * R;   // perm occupies R ints = R/2 doubles
   const int64_t RR = (int64_t)R * R;
@@ -980,13 +1250,19 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
   bool converged = false;
   for (int s = 0; s < max_sweeps; ++s) {
     while (enq < max_sweeps && enq - s < kAhead) {
-      for (int t = 0; t < nb - 1; ++t) {
-        hipLaunchKernelGGL(k_jacobi_solve, dim3(np), dim3(kJS), 0, st, G0, R, t, Qb, counters,
-                           enq, gnorm);
-        hipLaunchKernelGGL(k_jacobi_apply, dim3(np * np + np * (R / kJP)), dim3(kJT), 0, st, G0,
-                           G1, V, R, t, Qb, counters, enq);
+      // round t's launch solves round t and applies round t - 1 (G0 = H_{t-1}
+      // in, G1 = H_t out); the last round's update is a launch of its own
+      const unsigned nupd = (unsigned)(np * np + np * (R / kJP));
+      hipLaunchKernelGGL(k_jacobi_round<true>, dim3(np), dim3(kJT), 0, st, G0, G1, V, R, 0,
+                         Qr[1], Qr[0], counters, enq, gnorm);
+      for (int t = 1; t < nb - 1; ++t) {
+        hipLaunchKernelGGL(k_jacobi_round<false>, dim3(np + nupd), dim3(kJT), 0, st, G0, G1, V,
+                           R, t, Qr[(t - 1) & 1], Qr[t & 1], counters, enq, gnorm);
         std::swap(G0, G1);
       }
+      hipLaunchKernelGGL(k_jacobi_update, dim3(nupd), dim3(kJT), 0, st, G0, G1, V, R, nb - 2,
+                         Qr[(nb - 2) & 1], counters, enq);
+      std::swap(G0, G1);
       after[enq] = G0;
       // converged when every off-diagonal pair passes the rotation criterion,
       // i.e. when the next sweep would not rotate
