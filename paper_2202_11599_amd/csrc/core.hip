@@ -18,10 +18,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------ FP64 GEMM
-// C(m,n) = alpha sum_k A(m,k) B(k,n) + beta C(m,n), A(m,k) = A[m*sam + k*sak],
-// B(k,n) = B[k*sbk + n*sbn], C(m,n) = C[m*scm + n*scn].  64x64 tiles, 4x4 per
-// thread.  With gridDim.z > 1 each z handles a K chunk and writes the raw sum
-// to C + z*split_stride (layout m*N + n); k_split_reduce finishes.
+// C(m,n) = alpha sum_k A(m,k) w_k B(k,n) + beta C(m,n), A(m,k) = A[m*sam + k*sak],
+// B(k,n) = B[k*sbk + n*sbn], C(m,n) = C[m*scm + n*scn], w_k = wk[k] or 1.
+// FP64 matrix cores (16x16x4 FP64 MFMA, FP32 operands widened on load): a
+// workgroup computes a 64 x 64 tile, wavefront w the 32 x 32 quarter
+// (w >> 1, w & 1) as 2 x 2 MFMA blocks, K in steps of 16 through LDS with the
+// next step's operands loaded into registers while the current step's MFMAs
+// run.  With gridDim.z > 1 each z handles a K chunk and writes the raw sum to
+// C + z*split_stride (layout m*N + n); k_split_reduce finishes.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, int kchunk,
                                                const TA* __restrict__ A, int64_t sam, int64_t sak,
@@ -31,63 +37,84 @@ __global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, int kchunk,
                                                const double* __restrict__ wk) {
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = 32 * (wv >> 1), wn = 32 * (wv & 1);
   const int kb = blockIdx.z * kchunk;
   const int ke = min(K, kb + kchunk);
-  double acc[4][4];
+  d4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < 2; ++j) acc[i][j] = (d4)0.0;
   // consecutive threads take consecutive elements along whichever index has
   // unit stride (k for the Gram-type products X^T Y of column-major X, Y;
   // m or n otherwise), so every load instruction reads whole cache lines
   const bool ak = (sak == 1 && sam != 1), bk = (sbk == 1 && sbn != 1);
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  double an[4], bn[4];
+  auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = tid + e * 256;
       const int mm = ak ? (idx >> 4) : (idx & 63), ka = ak ? (idx & 15) : (idx >> 6);
       const int nn = bk ? (idx >> 4) : (idx & 63), kb2 = bk ? (idx & 15) : (idx >> 6);
       const int gka = k0 + ka, gkb = k0 + kb2;
-      As[ka][mm] = (m0 + mm < M && gka < ke)
-                       ? (double)A[(int64_t)(m0 + mm) * sam + (int64_t)gka * sak]
-                       : 0.0;
-      Bs[kb2][nn] = (n0 + nn < N && gkb < ke)
-                        ? (double)B[(int64_t)gkb * sbk + (int64_t)(n0 + nn) * sbn] *
-                              (wk ? wk[gkb] : 1.0)
-                        : 0.0;
+      an[e] = (m0 + mm < M && gka < ke) ? (double)A[(int64_t)(m0 + mm) * sam + (int64_t)gka * sak]
+                                        : 0.0;
+      bn[e] = (n0 + nn < N && gkb < ke)
+                  ? (double)B[(int64_t)gkb * sbk + (int64_t)(n0 + nn) * sbn] * (wk ? wk[gkb] : 1.0)
+                  : 0.0;
     }
+  };
+  auto store = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      const int mm = ak ? (idx >> 4) : (idx & 63), ka = ak ? (idx & 15) : (idx >> 6);
+      const int nn = bk ? (idx >> 4) : (idx & 63), kb2 = bk ? (idx & 15) : (idx >> 6);
+      As[ka][mm] = an[e];
+      Bs[kb2][nn] = bn[e];
+    }
+  };
+  const int fi = lane & 15, fk = lane >> 4;   // MFMA operand: row/column fi, k fk
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    store();
     __syncthreads();
+    if (k0 + 16 < ke) load(k0 + 16);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+    for (int kk = 0; kk < 16; kk += 4) {
+      double a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < 2; ++i) a[i] = As[kk + fk][wm + 16 * i + fi];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + fk][wn + 16 * j + fi];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // FP64 16x16 result layout: lane (fk, fi) holds rows fk + 4 v of column fi,
+  // so acc[i][j][v] = C(m0 + wm + 16 i + fk + 4 v, n0 + wn + 16 j + fi)
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gm = m0 + ty + 16 * i, gn = n0 + tx + 16 * j;
-      if (gm < M && gn < N) {
-        if (gridDim.z > 1) {
-          C[blockIdx.z * split_stride + (int64_t)gm * N + gn] = acc[i][j];
-        } else {
-          double* c = C + (int64_t)gm * scm + (int64_t)gn * scn;
-          *c = (beta == 0.0) ? alpha * acc[i][j] : fma(alpha, acc[i][j], beta * *c);
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm + 16 * i + fk + 4 * v, gn = n0 + wn + 16 * j + fi;
+        if (gm < M && gn < N) {
+          if (gridDim.z > 1) {
+            C[blockIdx.z * split_stride + (int64_t)gm * N + gn] = acc[i][j][v];
+          } else {
+            double* c = C + (int64_t)gm * scm + (int64_t)gn * scn;
+            *c = (beta == 0.0) ? alpha * acc[i][j][v] : fma(alpha, acc[i][j][v], beta * *c);
+          }
         }
       }
-    }
 }
 
 // C = alpha * sum_z ws[z] + beta C over the S split-K partials.  A workgroup
@@ -182,26 +209,34 @@ __device__ __forceinline__ void right_looking_solve(double (&C)[CB][CB + 1],
   if (c < nc && jr == 0 && b > 0) P[b - 1][c] = prev;
 }
 
+// Order the wavefront's own LDS accesses around this point (a barrier for a
+// single wavefront: its LDS operations complete in issue order).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Upper Cholesky factor C (C^T C = M) in place, row-major with leading
-// dimension ld, lower triangle set to zero; only the upper triangle of M is
-// read.  One workgroup of 1024 threads, right-looking by blocks of kCB rows:
-// the diagonal block is factored in LDS, the block row of C is formed by
-// forward substitution against it (one thread per column), and the trailing
-// upper triangle takes the rank-kCB update.  *fail = 1 on a non-positive or
-// non-finite pivot.
+// dimension ld; only the upper triangle of M is read, and the strict lower
+// triangle receives C^T (M[j][i] = C[i][j]), so that column l of C is
+// contiguous in row l.  One workgroup of 1024 threads, right-looking by
+// blocks of kCB rows, four barriers per block: the diagonal block is factored
+// in LDS by one wavefront, the block row of C is formed by forward
+// substitution against it (one thread per column, all columns at once), and
+// the trailing upper triangle takes the rank-kCB update.  *fail = 1 on a
+// non-positive or non-finite pivot.
 constexpr int kCB = 32;
-constexpr int kCW = 256;   // block-row columns staged in LDS at a time
+constexpr int kCholOneWg = 256;
 
 __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int r, int ld,
                                                      int* __restrict__ fail) {
   __shared__ double C[kCB][kCB + 1];
-  __shared__ double P[kCB][kCW + 1];
-  __shared__ double rowv[kCB];
+  __shared__ double P[kCB][kCholOneWg + 1];
   __shared__ double rdiag[kCB];
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   if (tid == 0) bad = 0;
-  __syncthreads();
   for (int kb = 0; kb < r; kb += kCB) {
     const int b = (r - kb < kCB) ? r - kb : kCB;
     const int nrest = r - kb - b;
@@ -210,82 +245,75 @@ __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int
       C[i][j] = (j >= i) ? M[(int64_t)(kb + i) * ld + kb + j] : 0.0;
     }
     __syncthreads();
-    // diagonal block: row i of the factor, then the update of the block below it
-    // thread (p, q) = (tid / kCB, tid % kCB) of the b x b block (b <= kCB)
-    const int tp = tid / kCB, tq = tid % kCB;
-    for (int i = 0; i < b; ++i) {
-      if (tid >= i && tid < b) {
+    if (tid < 64) {
+      // the diagonal block by the first wavefront: lane pair (q, half) owns
+      // column q's rows p = half, half + 2, ... of the trailing update
+      const int q = lane >> 1, half = lane & 1;
+      for (int i = 0; i < b; ++i) {
         const double dii = C[i][i];
-        if (tid == i && (!(dii > 0.0) || !isfinite(dii))) bad = 1;
+        if (!(dii > 0.0) || !isfinite(dii)) {
+          if (lane == 0) bad = 1;
+          break;
+        }
         double piv, rinv;
         chol_pivot(dii, &piv, &rinv);
-        rowv[tid] = (tid == i) ? piv : C[i][tid] * rinv;
-        if (tid == i) rdiag[i] = rinv;
-      }
-      __syncthreads();
-      if (bad) break;
-      if (tid >= i && tid < b) C[i][tid] = rowv[tid];
-      if (tp < b && tq < b && tp > i && tq >= tp) C[tp][tq] -= rowv[tp] * rowv[tq];
-      __syncthreads();
-    }
-    if (bad) break;
-    for (int e = tid; e < b * b; e += 1024) {
-      const int i = e / b, j = e % b;
-      if (j >= i) M[(int64_t)(kb + i) * ld + kb + j] = C[i][j];
-    }
-    // block row: C_kk^T X = M[kb.., kb+b..], one column per thread, in LDS
-    // chunks of kCW columns; the trailing update reads the block row from LDS
-    // when it fits in one chunk, else from global memory
-    for (int c0 = 0; c0 < nrest; c0 += kCW) {
-      const int nc = (nrest - c0 < kCW) ? nrest - c0 : kCW;
-      for (int e = tid; e < b * nc; e += 1024) {
-        const int i = e / nc, jj = e % nc;
-        P[i][jj] = M[(int64_t)(kb + i) * ld + kb + b + c0 + jj];
-      }
-      __syncthreads();
-      right_looking_solve<kCB, kCW, 1024>(C, P, rdiag, b, nc, tid);
-      __syncthreads();
-      for (int e = tid; e < b * nc; e += 1024) {
-        const int i = e / nc, jj = e % nc;
-        M[(int64_t)(kb + i) * ld + kb + b + c0 + jj] = P[i][jj];
-      }
-      if (nrest > kCW) __syncthreads();
-    }
-    // trailing upper triangle: M[p][q] -= sum_i X[i][p] X[i][q], p <= q
-    const int64_t nt = (int64_t)nrest * nrest;
-    if (nrest <= kCW) {
-      for (int64_t e = tid; e < nt; e += 1024) {
-        const int pp = (int)(e / nrest), qq = (int)(e % nrest);
-        if (qq < pp) continue;
-        double sacc = 0.0;
-        for (int i = 0; i < b; ++i) sacc = fma(P[i][pp], P[i][qq], sacc);
-        M[(int64_t)(kb + b + pp) * ld + kb + b + qq] -= sacc;
-      }
-    } else {
-      __syncthreads();
-      for (int64_t e = tid; e < nt; e += 1024) {
-        const int pp = (int)(e / nrest), qq = (int)(e % nrest);
-        if (qq < pp) continue;
-        const int64_t p = kb + b + pp, q = kb + b + qq;
-        double sacc = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < b; ++i)
-          sacc = fma(M[(int64_t)(kb + i) * ld + p], M[(int64_t)(kb + i) * ld + q], sacc);
-        M[p * ld + q] -= sacc;
+        const double ciq = (q > i && q < b) ? C[i][q] * rinv : 0.0;
+        wave_lds_sync();
+        if (q > i && q < b && half == 0) C[i][q] = ciq;
+        if (lane == 0) {
+          C[i][i] = piv;
+          rdiag[i] = rinv;
+        }
+        wave_lds_sync();
+        if (q > i && q < b)
+          for (int p = i + 1 + half; p <= q; p += 2) C[p][q] = fma(-C[i][p], ciq, C[p][q]);
+        wave_lds_sync();
       }
     }
     __syncthreads();
+    if (bad) break;
+    for (int e = tid; e < b * b; e += 1024) {
+      const int i = e / b, j = e % b;
+      if (j >= i) {
+        M[(int64_t)(kb + i) * ld + kb + j] = C[i][j];
+        if (j > i) M[(int64_t)(kb + j) * ld + kb + i] = C[i][j];
+      }
+    }
+    // block row X = C_kk^-T M[kb:kb+b, kb+b:]: thread c owns column c
+    if (tid < nrest) {
+      const int c = tid;
+      double x[kCB];
+#pragma unroll
+      for (int i = 0; i < kCB; ++i) x[i] = (i < b) ? M[(int64_t)(kb + i) * ld + kb + b + c] : 0.0;
+#pragma unroll
+      for (int i = 0; i < kCB; ++i) {
+        if (i < b) {
+          double s = x[i];
+#pragma unroll
+          for (int l = 0; l < i; ++l) s = fma(-C[l][i], x[l], s);
+          x[i] = s * rdiag[i];
+          P[i][c] = x[i];
+          M[(int64_t)(kb + i) * ld + kb + b + c] = x[i];
+          M[(int64_t)(kb + b + c) * ld + kb + i] = x[i];
+        }
+      }
+    }
+    __syncthreads();
+    // trailing upper triangle: M[p][q] -= sum_i X[i][p] X[i][q], p <= q
+    const int64_t nt = (int64_t)nrest * nrest;
+    for (int64_t e = tid; e < nt; e += 1024) {
+      const int pp = (int)(e / nrest), qq = (int)(e % nrest);
+      if (qq < pp) continue;
+      double sacc = 0.0;
+      for (int i = 0; i < b; ++i) sacc = fma(P[i][pp], P[i][qq], sacc);
+      M[(int64_t)(kb + b + pp) * ld + kb + b + qq] -= sacc;
+    }
+    __syncthreads();
   }
-  if (bad) {
-    if (tid == 0) *fail = 1;
-    return;
-  }
-  for (int k = tid; k < r; k += 1024)
-    for (int i = k + 1; i < r; ++i) M[(int64_t)i * ld + k] = 0.0;  // below the diagonal
+  if (bad && tid == 0) *fail = 1;
 }
 
 // ---- blocked Cholesky for r > kCholOneWg (same contract as k_chol_upper)
-constexpr int kCholOneWg = 256;
 constexpr int kLB = 64;
 
 // Diagonal block M[kb:kb+b, kb:kb+b] <- its upper Cholesky factor (LDS).
@@ -403,79 +431,106 @@ __global__ __launch_bounds__(256) void k_chol_trail(double* __restrict__ M, int 
   }
 }
 
-__global__ void k_chol_zero_lower(double* __restrict__ M, int r, int ld,
-                                  const int* __restrict__ fail) {
+// strict lower triangle <- the transpose of the upper factor
+__global__ void k_chol_mirror_lower(double* __restrict__ M, int r, int ld,
+                                    const int* __restrict__ fail) {
   if (*fail) return;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= r) return;
-  for (int i = k + 1; i < r; ++i) M[(int64_t)i * ld + k] = 0.0;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r * r) return;
+  const int i = (int)(e / r), j = (int)(e % r);
+  if (i > j) M[(int64_t)i * ld + j] = M[(int64_t)j * ld + i];
 }
 
-// Z = C^-1 for upper triangular C (r x r, row-major, ld); one wavefront per
-// column k, back substitution Z(i,k) = -(sum_{l=i+1..k} C(i,l) Z(l,k)) / C(i,i).
+// Z = C^-1 for the upper triangular C (r x r, row-major, ld) in the layout
+// chol_upper leaves (strict lower triangle = C^T, so column l of C is row l).
+// One wavefront per column k, right-looking back substitution: the partial
+// sums s_i = sum_{l' > l} C(i, l') z_l' of the rows i < l still open stay in
+// registers (row i in lane i % 64, slot i / 64).  At step l (k down to 0) the
+// owner of row l forms z_l = ([l == k] - s_l) / C(l, l), every lane reads it
+// (readlane), and the open rows add C(i, l) z_l; column l of C is fetched D
+// steps ahead into a register ring.
+template <int NS, int D>
 __global__ __launch_bounds__(256) void k_trinv_upper(const double* __restrict__ Cm, int r, int ld,
                                                      double* __restrict__ Z, int ldz) {
-  __shared__ double zc[4][1024];
+  __shared__ double rd[64 * NS];
+  for (int i = threadIdx.x; i < r; i += 256) rd[i] = 1.0 / Cm[(int64_t)i * ld + i];
+  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int k = blockIdx.x * 4 + wv;
   if (k >= r) return;
-  double* z = zc[wv];
-  const double zkk = 1.0 / Cm[(int64_t)k * ld + k];
-  z[k] = zkk;
-  for (int i = k - 1; i >= 0; --i) {
-    // four running sums so that four loads of row i are in flight per lane
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const double* ci = Cm + (int64_t)i * ld;
-    int l = i + 1 + lane;
-    for (; l + 192 <= k; l += 256) {
-      s0 = fma(ci[l], z[l], s0);
-      s1 = fma(ci[l + 64], z[l + 64], s1);
-      s2 = fma(ci[l + 128], z[l + 128], s2);
-      s3 = fma(ci[l + 192], z[l + 192], s3);
+  for (int i = k + 1 + lane; i < r; i += 64) Z[(int64_t)i * ldz + k] = 0.0;
+  double s[NS], ring[D][NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) s[j] = 0.0;
+  auto fetch = [&](int l, double (&dst)[NS]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int i = lane + 64 * j;
+      dst[j] = (l > 0 && i < l) ? Cm[(int64_t)l * ld + i] : 0.0;
     }
-    for (; l <= k; l += 64) s0 = fma(ci[l], z[l], s0);
-    double s = (s0 + s1) + (s2 + s3);
-    s = wave_sum(s);
-    const double zi = -s / Cm[(int64_t)i * ld + i];
-    z[i] = zi;  // every lane writes the same value, so each lane reads its own write
+  };
+#pragma unroll
+  for (int u = 0; u < D; ++u) fetch(k - u, ring[u]);
+  for (int l0 = k; l0 >= 0; l0 -= D) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int l = l0 - u;
+      if (l < 0) break;
+      const int js = l >> 6, ol = l & 63;
+      double t = s[0];
+#pragma unroll
+      for (int j = 1; j < NS; ++j) t = (js == j) ? s[j] : t;
+      const int lo = __builtin_amdgcn_readlane(__double2loint(t), ol);
+      const int hi = __builtin_amdgcn_readlane(__double2hiint(t), ol);
+      const double z = ((l == k ? 1.0 : 0.0) - __hiloint2double(hi, lo)) * rd[l];
+      if (lane == 0) Z[(int64_t)l * ldz + k] = z;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) s[j] = fma(ring[u][j], z, s[j]);
+      fetch(l - D, ring[u]);
+    }
   }
-  for (int i = lane; i < r; i += 64) Z[(int64_t)i * ldz + k] = (i <= k) ? z[i] : 0.0;
 }
 
 // Largest eigenvalue of the symmetric psd r x r matrix G by power iteration
-// (x <- G x / ||G x||), Rayleigh quotient written to *out.
+// (x <- G x / ||G x||), Rayleigh quotient written to *out (the iterations
+// taken to out[1]).  y = G x is summed by np groups of threads, each over a
+// contiguous range of k (np = 1024 / r rounded up to 64), the group sums
+// added in a fixed order.
 __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ G, int r, int ld,
                                                      int iters, double* __restrict__ out) {
   __shared__ double x[1024];
+  __shared__ double part[1024];
   __shared__ double red[16];
-  const int i = threadIdx.x, lane = i & 63, wv = i >> 6;
-  if (i < r) x[i] = 1.0 / sqrt((double)r) * (1.0 + 1e-3 * (double)(i % 7));
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int r64 = (r + 63) / 64 * 64;
+  const int np = 1024 / r64;   // 1 .. 16
+  const int i = t % r64, g = t / r64;
+  const int kper = (r + np - 1) / np;
+  const int kb = g * kper, ke = min(r, kb + kper);
+  if (t < r) x[t] = 1.0 / sqrt((double)r) * (1.0 + 1e-3 * (double)(t % 7));
   __syncthreads();
   double lam = 0.0;
-  int stable = 0;
-  for (int it = 0; it <= iters; ++it) {
-    double y = 0.0;
-    if (i < r) {
-      // eight running sums so that eight loads of G are in flight
-      double a[8];
+  int stable = 0, it = 0;
+  for (; it <= iters; ++it) {
+    if (g < np && i < r) {
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      int k = kb;
+      for (; k + 3 < ke; k += 4) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) a[t] = 0.0;
-      int k = 0;
-      for (; k + 7 < r; k += 8) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) a[t] = fma(G[(int64_t)(k + t) * ld + i], x[k + t], a[t]);
+        for (int u = 0; u < 4; ++u) a[u] = fma(G[(int64_t)(k + u) * ld + i], x[k + u], a[u]);
       }
-      for (; k < r; ++k) a[0] = fma(G[(int64_t)k * ld + i], x[k], a[0]);
-      y = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+      for (; k < ke; ++k) a[0] = fma(G[(int64_t)k * ld + i], x[k], a[0]);
+      part[t] = (a[0] + a[1]) + (a[2] + a[3]);
     }
+    __syncthreads();
+    double y = 0.0;
+    if (t < r)
+      for (int h = 0; h < np; ++h) y += part[h * r64 + t];
     // Rayleigh quotient x^T G x (x normalised) and ||y||^2
-    double xy = (i < r) ? x[i] * y : 0.0, yy = y * y;
+    double xy = (t < r) ? x[t] * y : 0.0, yy = y * y;
     xy = wave_sum(xy);
     yy = wave_sum(yy);
-    __syncthreads();
-    if (lane == 0) {
-      red[wv] = xy;
-    }
+    if (lane == 0) red[wv] = xy;
     __syncthreads();
     double sxy = 0.0;
     for (int w = 0; w < 16; ++w) sxy += red[w];
@@ -486,7 +541,6 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
     for (int w = 0; w < 16; ++w) syy += red[w];
     const double lam_prev = lam;
     lam = sxy;
-    __syncthreads();
     if (syy <= 0.0 || !isfinite(syy)) {
       lam = 0.0;
       break;
@@ -495,10 +549,13 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
     // quotient has settled to 1e-13 for 4 consecutive iterations
     stable = (it > 0 && fabs(lam - lam_prev) <= 1e-13 * lam) ? stable + 1 : 0;
     if (stable >= 4) break;
-    if (i < r) x[i] = y / sqrt(syy);
+    if (t < r) x[t] = y / sqrt(syy);
     __syncthreads();
   }
-  if (i == 0) *out = lam;
+  if (t == 0) {
+    out[0] = lam;
+    out[1] = (double)it;
+  }
 }
 
 // ------------------------------------------------------------ Jacobi
@@ -1156,14 +1213,20 @@ nys_status chol_upper(hipStream_t st, double* M, int r, int ld, int* fail) {
                          nrest, tc, fail);
     }
   }
-  hipLaunchKernelGGL(k_chol_zero_lower, dim3((unsigned)((r + 255) / 256)), dim3(256), 0, st, M, r,
-                     ld, fail);
+  hipLaunchKernelGGL(k_chol_mirror_lower, dim3((unsigned)(((int64_t)r * r + 255) / 256)), dim3(256),
+                     0, st, M, r, ld, fail);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
 nys_status trinv_upper(hipStream_t st, const double* Cm, int r, int ld, double* Z, int ldz) {
   if (r > 1024) return NYS_ERR_INVALID;
-  hipLaunchKernelGGL(k_trinv_upper, dim3((r + 3) / 4), dim3(256), 0, st, Cm, r, ld, Z, ldz);
+  const dim3 grid((r + 3) / 4);
+  if (r <= 256)
+    hipLaunchKernelGGL((k_trinv_upper<4, 16>), grid, dim3(256), 0, st, Cm, r, ld, Z, ldz);
+  else if (r <= 512)
+    hipLaunchKernelGGL((k_trinv_upper<8, 8>), grid, dim3(256), 0, st, Cm, r, ld, Z, ldz);
+  else
+    hipLaunchKernelGGL((k_trinv_upper<16, 4>), grid, dim3(256), 0, st, Cm, r, ld, Z, ldz);
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
