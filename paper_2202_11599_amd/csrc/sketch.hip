@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 
@@ -28,6 +29,7 @@ namespace nys {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f8 __attribute__((ext_vector_type(8)));
 
@@ -59,261 +61,444 @@ __device__ __forceinline__ f8 load8(const float* p, int valid, bool vec) {
   return r;
 }
 
-// T(:, col0 + c) = A Omega_lp(:, c), c < ncols.  Workgroup: 128 rows x 16*NB
-// columns; wavefront w owns rows [32w, 32w + 32) (two 16-row MFMA blocks) and
-// every column block.  Omega_lp is (rows = columns of Omega) x ldo with zero
-// padding up to ldo (a multiple of 32) and up to 16*NB rows.
+// T(:, col0 + c) = A Omega_lp(:, c), c < ncols.  A workgroup of NW
+// wavefronts (blockDim = 64 NW) covers 16 NW rows; wavefront w owns the
+// 16-row block blockIdx.x * NW + w and all NB column blocks (16 NB columns
+// from 16 NB blockIdx.y).  The Omega tile (16 NB x 32 per K step) goes
+// through double-buffered LDS and is shared by the NW wavefronts; each
+// wavefront reads its A rows straight from memory in MFMA operand order,
+// the next step's rows and Omega tile loaded while the current step's MFMAs
+// run (one barrier per step).  Omega_lp is (rows = columns of Omega) x ldo
+// with zero padding up to ldo (a multiple of 32) and up to 16 NB rows.
+constexpr int kSkMaxChunks = 4;   // 16-byte Omega chunks staged per thread
+constexpr int kSk1MaxW = 13;      // wavefronts per first-pass workgroup, at most
 template <bool BF, int NB>
-__global__ __launch_bounds__(256) void k_sk1(const float* __restrict__ A, int64_t n, int d,
-                                             int64_t ld, int vec, const void* __restrict__ Olp,
-                                             int ldo, float* __restrict__ T, int64_t ldt,
-                                             int col0, int ncols) {
+__global__ __launch_bounds__(64 * kSk1MaxW) void k_sk1(const float* __restrict__ A, int64_t n, int d,
+                                              int64_t ld, int vec, const void* __restrict__ Olp,
+                                              int ldo, float* __restrict__ T, int64_t ldt,
+                                              int col0, int ncols) {
   constexpr int NP = 16 * NB;
-  __shared__ __attribute__((aligned(32))) char smem[NP * kOPad * (BF ? 2 : 4)];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int TILE = NP * kOPad * (BF ? 2 : 4);
+  __shared__ __attribute__((aligned(32))) char smem[2 * TILE];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
   const int q = lane >> 4, m = lane & 15;
-  const int64_t m0 = (int64_t)blockIdx.x * 128 + 32 * wv;
+  const int64_t m0 = ((int64_t)blockIdx.x * (nthr >> 6) + wv) * 16;
   const int n0 = blockIdx.y * NP;
-  f4 acc[2][NB];
+  f4 acc[NB];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = (f4)0.0f;
-
-  // The next step's Omega tile and A rows are loaded into registers while the
-  // current step's MFMAs run (the loads are issued before them), then stored
-  // to LDS after the barrier that ends the step.
-  constexpr int OC = BF ? NP * 4 / 256 : NP * 8 / 256;   // 16-byte Omega chunks per thread
-  static_assert(OC >= 1 && (BF ? NP * 4 : NP * 8) % 256 == 0, "whole chunks per thread");
-  f8 afn[2];
-  // 16-byte Omega chunks of this thread, held as separate values (an array
-  // of them would be placed in scratch memory)
-  uint4 ob0, ob1, ob2, ob3, ob4, ob5, ob6, ob7;
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = (f4)0.0f;
+  constexpr int NCH = BF ? NP * 4 : NP * 8;   // 16-byte chunks of one Omega tile
+  // staged chunks as separate values (an indexed array would go to scratch);
+  // the host launches at least NCH / (64 kSkMaxChunks) wavefronts
+  uint4 ob0, ob1, ob2, ob3;
   auto chunk = [&](int c) __attribute__((always_inline)) -> uint4& {
-    return c == 0 ? ob0 : c == 1 ? ob1 : c == 2 ? ob2 : c == 3 ? ob3
-         : c == 4 ? ob4 : c == 5 ? ob5 : c == 6 ? ob6 : ob7;
+    return c == 0 ? ob0 : c == 1 ? ob1 : c == 2 ? ob2 : ob3;
   };
-  static_assert(OC <= 8, "at most eight chunks per thread");
   auto load_omega = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int c = 0; c < OC; ++c) {
-      const int e = tid + 256 * c;
-      if (BF) {
-        const int nn = e >> 2, kk = (e & 3) * 8;
-        chunk(c) = *reinterpret_cast<const uint4*>(static_cast<const __bf16*>(Olp) +
-                                                   (int64_t)(n0 + nn) * ldo + k0 + kk);
-      } else {
-        const int nn = e >> 3, kk = (e & 7) * 4;
-        chunk(c) = *reinterpret_cast<const uint4*>(static_cast<const float*>(Olp) +
-                                                   (int64_t)(n0 + nn) * ldo + k0 + kk);
+    for (int c = 0; c < kSkMaxChunks; ++c) {
+      const int e = tid + nthr * c;
+      if (e < NCH) {
+        if (BF) {
+          const int nn = e >> 2, kk = (e & 3) * 8;
+          chunk(c) = *reinterpret_cast<const uint4*>(static_cast<const __bf16*>(Olp) +
+                                                     (int64_t)(n0 + nn) * ldo + k0 + kk);
+        } else {
+          const int nn = e >> 3, kk = (e & 7) * 4;
+          chunk(c) = *reinterpret_cast<const uint4*>(static_cast<const float*>(Olp) +
+                                                     (int64_t)(n0 + nn) * ldo + k0 + kk);
+        }
       }
     }
   };
-  auto store_omega = [&]() __attribute__((always_inline)) {
+  auto store_omega = [&](char* buf) __attribute__((always_inline)) {
 #pragma unroll
-    for (int c = 0; c < OC; ++c) {
-      const int e = tid + 256 * c;
-      if (BF) {
-        const int nn = e >> 2, kk = (e & 3) * 8;
-        *reinterpret_cast<uint4*>(reinterpret_cast<__bf16*>(smem) + nn * kOPad + kk) = chunk(c);
-      } else {
-        const int nn = e >> 3, kk = (e & 7) * 4;
-        *reinterpret_cast<uint4*>(reinterpret_cast<float*>(smem) + nn * kOPad + kk) = chunk(c);
+    for (int c = 0; c < kSkMaxChunks; ++c) {
+      const int e = tid + nthr * c;
+      if (e < NCH) {
+        if (BF) {
+          const int nn = e >> 2, kk = (e & 3) * 8;
+          *reinterpret_cast<uint4*>(reinterpret_cast<__bf16*>(buf) + nn * kOPad + kk) = chunk(c);
+        } else {
+          const int nn = e >> 3, kk = (e & 7) * 4;
+          *reinterpret_cast<uint4*>(reinterpret_cast<float*>(buf) + nn * kOPad + kk) = chunk(c);
+        }
       }
     }
   };
-  auto load_a = [&](int k0) __attribute__((always_inline)) {
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      const int64_t row = m0 + 16 * mb + m;
-      const int kk = k0 + 8 * q;
-      afn[mb] = (row < n) ? load8(A + row * ld + kk, d - kk, vec) : (f8)0.0f;
-    }
+  const int64_t row = m0 + m;
+  auto load_a = [&](int k0) __attribute__((always_inline)) -> f8 {
+    const int kk = k0 + 8 * q;
+    return (row < n && kk < d) ? load8(A + row * ld + kk, d - kk, vec) : (f8)0.0f;
   };
   load_omega(0);
-  load_a(0);
+  f8 an = load_a(0);
+  store_omega(smem);
+  __syncthreads();
+  int cur = 0;
   for (int k0 = 0; k0 < d; k0 += kBK) {
-    store_omega();
-    __syncthreads();
-    f8 af[2] = {afn[0], afn[1]};
-    if (k0 + kBK < d) {
+    const f8 af = an;
+    const bool more = k0 + kBK < d;
+    if (more) {
       load_omega(k0 + kBK);
-      load_a(k0 + kBK);
+      an = load_a(k0 + kBK);
     }
-    if (BF) {
-      const bf16x8 a0 = to_bf16(af[0]), a1 = to_bf16(af[1]);
-      const __bf16* Os = reinterpret_cast<const __bf16*>(smem);
+    const char* buf = smem + cur * TILE;
+    if constexpr (BF) {
+      const bf16x8 a0 = to_bf16(af);
+      const __bf16* Os = reinterpret_cast<const __bf16*>(buf);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Os + (nb * 16 + m) * kOPad + 8 * q);
-        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[0][nb], 0, 0, 0);
-        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc[1][nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[nb], 0, 0, 0);
       }
     } else {
-      const float* Os = reinterpret_cast<const float*>(smem);
+      const float* Os = reinterpret_cast<const float*>(buf);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const f8 bv = *reinterpret_cast<const f8*>(Os + (nb * 16 + m) * kOPad + 8 * q);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0][s], bv[s], acc[0][nb], 0, 0, 0);
-          acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1][s], bv[s], acc[1][nb], 0, 0, 0);
+        for (int s = 0; s < 8; ++s)
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s], bv[s], acc[nb], 0, 0, 0);
+      }
+    }
+    if (more) store_omega(smem + (cur ^ 1) * TILE);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // 16x16 FP32 result layout: lane (q, m) holds rows 4 q + v of column m
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int c = n0 + nb * 16 + m;
+    if (c >= ncols) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = m0 + 4 * q + v;
+      if (r < n) T[(int64_t)(col0 + c) * ldt + r] = acc[nb][v];
+    }
+  }
+}
+
+// Ypart[s][c][j] = sum_{i in slice s} A[i][j] D[i] T[i][c]  (j < d, c < ncols).
+// A workgroup of kSk2W wavefronts covers 32 kSk2W columns j of A and all NB
+// sketch column blocks; wavefront w owns the j blocks 2w, 2w + 1.  Per K step
+// of 32 rows i, (D o T) for the NB blocks is staged in double-buffered LDS
+// (column-major, as T is stored; for BF16 as hi and lo parts, so only A is
+// rounded to BF16) and shared by the wavefronts, while each wavefront reads
+// its A^T operand straight from memory: lane (q, m) takes A[i0 + 8q + s][j]
+// for s < 8, 64 contiguous bytes per 16 lanes, so A needs no transpose.
+constexpr int kSk2W = 8;
+constexpr int kTPad = 40;   // LDS pitch (elements) of a staged T column (16-byte rows)
+template <bool BF, int NB>
+__global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A, int64_t n, int d,
+                                                    int64_t ld, const double* __restrict__ D,
+                                                    const float* __restrict__ T, int64_t ldt,
+                                                    int col0, int ncols, int64_t slice,
+                                                    float* __restrict__ Yp, int ldy) {
+  constexpr int NP = 16 * NB;
+  constexpr int TILE = NP * kTPad * 4;   // one buffer: FP32 (D o T), or bf16 hi + lo
+  constexpr int NT = 64 * kSk2W;
+  __shared__ __attribute__((aligned(32))) char smem[2 * TILE];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int q = lane >> 4, m = lane & 15;
+  const int j0 = blockIdx.x * 32 * kSk2W + 32 * wv;
+  const int64_t i_beg = (int64_t)blockIdx.y * slice;
+  const int64_t i_end = (i_beg + slice < n) ? i_beg + slice : n;
+  f4 acc[2][NB];
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[jb][nb] = (f4)0.0f;
+  // (D o T) tile: NP columns x 32 rows, thread tid stages 4 consecutive rows
+  // of one column per item: items e = tid + NT u, column e >> 3, rows 4 (e & 7)
+  constexpr int NIT = (NP * 8 + NT - 1) / NT;
+  f4 tv[NIT];
+  auto load_t = [&](int64_t i0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int e = tid + NT * u;
+      const int c = e >> 3, rr = (e & 7) * 4;
+      f4 x = (f4)0.0f;
+      if (e < NP * 8 && c < ncols) {
+        const int64_t ib = i0 + rr;
+        const float* src = T + (int64_t)(col0 + c) * ldt + ib;
+        if (ib + 3 < i_end) {
+          x = *reinterpret_cast<const f4*>(src);   // ldt and ib are multiples of 4
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (ib + v < i_end) x[v] = src[v];
+        }
+        if (D != nullptr) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) x[v] *= (ib + v < i_end) ? (float)D[ib + v] : 0.0f;
+        }
+      }
+      tv[u] = x;
+    }
+  };
+  auto store_t = [&](char* buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int e = tid + NT * u;
+      if (e < NP * 8) {
+        const int c = e >> 3, rr = (e & 7) * 4;
+        if (BF) {
+          __bf16* hi = reinterpret_cast<__bf16*>(buf);
+          __bf16* lo = hi + NP * kTPad;
+          bf16x4 h, l;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            h[v] = (__bf16)tv[u][v];
+            l[v] = (__bf16)(tv[u][v] - (float)h[v]);
+          }
+          *reinterpret_cast<bf16x4*>(hi + c * kTPad + rr) = h;
+          *reinterpret_cast<bf16x4*>(lo + c * kTPad + rr) = l;
+        } else {
+          *reinterpret_cast<f4*>(reinterpret_cast<float*>(buf) + c * kTPad + rr) = tv[u];
         }
       }
     }
-    __syncthreads();
-  }
+  };
+  // A^T operand: lane (q, m), j block jb: A[i0 + 8q + s][j0 + 16 jb + m], s < 8
+  f8 an[2];
+  auto load_a = [&](int64_t i0) __attribute__((always_inline)) {
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+    for (int jb = 0; jb < 2; ++jb) {
+      const int j = j0 + 16 * jb + m;
+      const int64_t ib = i0 + 8 * q;
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        an[jb][s] = (j < d && ib + s < i_end) ? A[(ib + s) * ld + j] : 0.0f;
+    }
+  };
+  if (i_beg < i_end) {
+    load_t(i_beg);
+    load_a(i_beg);
+    store_t(smem);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t i0 = i_beg; i0 < i_end; i0 += kBK) {
+    const f8 a0 = an[0], a1 = an[1];
+    const bool more = i0 + kBK < i_end;
+    if (more) {
+      load_t(i0 + kBK);
+      load_a(i0 + kBK);
+    }
+    const char* buf = smem + cur * TILE;
+    if constexpr (BF) {
+      const bf16x8 b0 = to_bf16(a0), b1 = to_bf16(a1);
+      const __bf16* hi = reinterpret_cast<const __bf16*>(buf);
+      const __bf16* lo = hi + NP * kTPad;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int off = (nb * 16 + m) * kTPad + 8 * q;
+        const bf16x8 th = *reinterpret_cast<const bf16x8*>(hi + off);
+        const bf16x8 tl = *reinterpret_cast<const bf16x8*>(lo + off);
+        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0, th, acc[0][nb], 0, 0, 0);
+        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0, tl, acc[0][nb], 0, 0, 0);
+        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1, th, acc[1][nb], 0, 0, 0);
+        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1, tl, acc[1][nb], 0, 0, 0);
+      }
+    } else {
+      const float* Ts = reinterpret_cast<const float*>(buf);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const f8 bv = *reinterpret_cast<const f8*>(Ts + (nb * 16 + m) * kTPad + 8 * q);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], bv[s], acc[0][nb], 0, 0, 0);
+          acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], bv[s], acc[1][nb], 0, 0, 0);
+        }
+      }
+    }
+    if (more) store_t(smem + (cur ^ 1) * TILE);
+    __syncthreads();
+    cur ^= 1;
+  }
+  float* Ys = Yp + (int64_t)blockIdx.y * ncols * ldy;
+#pragma unroll
+  for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int c = n0 + nb * 16 + m;
+      const int c = nb * 16 + m;
       if (c >= ncols) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + 16 * mb + 4 * q + v;
-        if (row < n) T[(int64_t)(col0 + c) * ldt + row] = acc[mb][nb][v];
+        const int j = j0 + 16 * jb + 4 * q + v;
+        if (j < d) Ys[(int64_t)c * ldy + j] = acc[jb][nb][v];
       }
     }
 }
 
-// Ypart[s][c][j] = sum_{i in slice s} A[i][j] D[i] T[i][c]  (j < d, c < ncols).
-// Workgroup: 128 columns j of A x all 16*NB sketch columns; the A^T tile goes
-// through LDS (transposed), wavefront w owns column blocks w, w+4, ...  BF16
-// form: T o D is split into bf16 hi + lo parts (two MFMAs), so only A is
-// rounded to BF16.
-template <bool BF, int NB>
-__global__ __launch_bounds__(256) void k_sk2(const float* __restrict__ A, int64_t n, int d,
-                                             int64_t ld, int vec, const double* __restrict__ D,
-                                             const float* __restrict__ T, int64_t ldt, int col0,
-                                             int ncols, int64_t slice, float* __restrict__ Yp,
-                                             int ldy) {
-  constexpr int NBW = NB / 4;
-  __shared__ __attribute__((aligned(32))) char smem[128 * kOPad * (BF ? 2 : 4)];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int q = lane >> 4, m = lane & 15;
-  const int j0 = blockIdx.x * 128;
-  const int64_t i_beg = (int64_t)blockIdx.y * slice;
-  const int64_t i_end = (i_beg + slice < n) ? i_beg + slice : n;
-  f4 acc[8][NBW];
-#pragma unroll
-  for (int mb = 0; mb < 8; ++mb)
-#pragma unroll
-    for (int t = 0; t < NBW; ++t) acc[mb][t] = (f4)0.0f;
+// Mb(i, r0 + j) = sum_k T(k, i) D_k T(k, r0 + j), i < r1, j < m: the FP64
+// core matrix T^T D T of the FP32/BF16 forms (FP32 T; each product is exact
+// in FP64).  Workgroup g sums the rows k of one contiguous slice on the FP64
+// matrix cores: the slice's T rows, 32 at a time and all r1 (+ padding)
+// columns, are staged in double-buffered LDS in T's own column-major order,
+// and wavefront w owns the output blocks w, w + kGtW, ... of the list of
+// 16 x 16 blocks (row-major; only blocks bi <= bj when the product is the
+// square r0 = 0, m = r1 one).  Partial sums go to Wp[g][block][16 x 16];
+// k_gram_t_reduce adds them in slice order.
+typedef double d4g __attribute__((ext_vector_type(4)));
+constexpr int kGtW = 8;        // wavefronts per workgroup
+constexpr int kGtMaxB = 12;    // output blocks per wavefront, at most
+constexpr int kGtMaxC = 272;   // staged columns: r1 + padding
+constexpr int kGtPad = 36;     // LDS pitch (floats) of a staged column
 
-  // The next step's A tile and B fragments are loaded into registers while
-  // the current step's MFMAs run, and the A tile is stored to LDS (transposed)
-  // after the barrier that ends the step.
-  float vals[16];
-  f8 bfn[NBW];
-  const int kk_t = tid >> 3;            // row within the tile
-  const int jc_t = (tid & 7) * 16;      // 16 columns
-  auto load_tile = [&](int64_t i0) __attribute__((always_inline)) {
-    const int64_t i = i0 + kk_t;
-    if (i < i_end) {
-      const float* src = A + i * ld + j0 + jc_t;
-      const int valid = d - (j0 + jc_t);
-      const f8 x0 = load8(src, valid, vec);
-      const f8 x1 = load8(src + 8, valid - 8, vec);
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        vals[v] = x0[v];
-        vals[v + 8] = x1[v];
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < 16; ++v) vals[v] = 0.0f;
-    }
-  };
-  auto store_tile = [&]() __attribute__((always_inline)) {
-    if (BF) {
-      __bf16* As = reinterpret_cast<__bf16*>(smem);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) As[(jc_t + v) * kOPad + kk_t] = (__bf16)vals[v];
-    } else {
-      float* As = reinterpret_cast<float*>(smem);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) As[(jc_t + v) * kOPad + kk_t] = vals[v];
-    }
-  };
-  // B fragments: (D o T)[i0 + 8q .. +7][c], c = 16 nb + m
-  auto load_b = [&](int64_t i0) __attribute__((always_inline)) {
-    const int64_t ib = i0 + 8 * q;
-    const int valid = (int)((i_end - ib) < 8 ? (i_end - ib) : 8);
-    f8 dv;
-#pragma unroll
-    for (int v = 0; v < 8; ++v)
-      dv[v] = (D != nullptr && v < valid) ? (float)D[ib + v] : 1.0f;
-#pragma unroll
-    for (int t = 0; t < NBW; ++t) {
-      const int c = (wv + 4 * t) * 16 + m;
-      f8 x = (c < ncols && valid > 0) ? load8(T + (int64_t)(col0 + c) * ldt + ib, valid, true)
-                                      : (f8)0.0f;
-      if (D != nullptr) x = x * dv;
-      bfn[t] = x;
-    }
-  };
-  if (i_beg < i_end) {
-    load_tile(i_beg);
-    load_b(i_beg);
+__device__ __forceinline__ void gram_block(int b, int RB, int CB, bool sym, int* bi, int* bj) {
+  if (!sym) {
+    *bi = b / CB;
+    *bj = b % CB;
+    return;
   }
-  for (int64_t i0 = i_beg; i0 < i_end; i0 += kBK) {
-    store_tile();
-    __syncthreads();
-    f8 bfr[NBW];
+  int i = 0;
+  while (b >= RB - i) {
+    b -= RB - i;
+    ++i;
+  }
+  *bi = i;
+  *bj = i + b;
+}
+
+__global__ __launch_bounds__(64 * kGtW) void k_gram_t(const float* __restrict__ T, int64_t ldt,
+                                                      int64_t n, const double* __restrict__ D,
+                                                      int r1, int r0, int m, int sym,
+                                                      int64_t slice, double* __restrict__ Wp) {
+  __shared__ __attribute__((aligned(16))) float Ts[2][kGtMaxC][kGtPad];
+  __shared__ double Ds[2][32];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int fi = lane & 15, fk = lane >> 4;
+  const int RB = (r1 + 15) / 16, CB = (m + 15) / 16;
+  const int nblk = sym ? RB * (RB + 1) / 2 : RB * CB;
+  const int ncol = max(16 * RB, r0 + 16 * CB);   // staged columns (zero past r1)
+  int bi[kGtMaxB], bj[kGtMaxB];
 #pragma unroll
-    for (int t = 0; t < NBW; ++t) bfr[t] = bfn[t];
-    if (i0 + kBK < i_end) {
-      load_tile(i0 + kBK);
-      load_b(i0 + kBK);
-    }
-    if (BF) {
-      const __bf16* As = reinterpret_cast<const __bf16*>(smem);
-      bf16x8 bh[NBW], bl[NBW];
+  for (int t = 0; t < kGtMaxB; ++t) {
+    const int b = wv + kGtW * t;
+    int x = 0, y = 0;
+    if (b < nblk) gram_block(b, RB, CB, sym != 0, &x, &y);
+    // wavefront-uniform: keep them in scalar registers
+    bi[t] = __builtin_amdgcn_readfirstlane(x);
+    bj[t] = __builtin_amdgcn_readfirstlane(y);
+  }
+  d4g acc[kGtMaxB];
 #pragma unroll
-      for (int t = 0; t < NBW; ++t) {
-        bh[t] = to_bf16(bfr[t]);
-        f8 rest;
+  for (int t = 0; t < kGtMaxB; ++t) acc[t] = (d4g)0.0;
+  const int64_t kb = (int64_t)blockIdx.x * slice;
+  const int64_t ke = (kb + slice < n) ? kb + slice : n;
+  // staging items: (column c, 4-row group g4), 8 per column
+  constexpr int NIT = (kGtMaxC * 8 + 64 * kGtW - 1) / (64 * kGtW);
+  f4 tv[NIT];
+  double dv = 1.0;
+  auto load = [&](int64_t k0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) rest[v] = bfr[t][v] - (float)bh[t][v];
-        bl[t] = to_bf16(rest);
-      }
+    for (int u = 0; u < NIT; ++u) {
+      const int e = tid + 64 * kGtW * u;
+      const int c = e >> 3, g4 = (e & 7) * 4;
+      f4 x = (f4)0.0f;
+      if (c < r1 && e < ncol * 8) {
+        const int64_t k = k0 + g4;
+        const float* src = T + (int64_t)c * ldt + k;
+        if (k + 3 < ke) {
+          x = *reinterpret_cast<const f4*>(src);   // ldt and k are multiples of 4
+        } else {
 #pragma unroll
-      for (int mb = 0; mb < 8; ++mb) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(As + (mb * 16 + m) * kOPad + 8 * q);
-#pragma unroll
-        for (int t = 0; t < NBW; ++t) {
-          acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh[t], acc[mb][t], 0, 0, 0);
-          acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[t], acc[mb][t], 0, 0, 0);
+          for (int v = 0; v < 4; ++v)
+            if (k + v < ke) x[v] = src[v];
         }
       }
-    } else {
-      const float* As = reinterpret_cast<const float*>(smem);
-#pragma unroll
-      for (int mb = 0; mb < 8; ++mb) {
-        const f8 av = *reinterpret_cast<const f8*>(As + (mb * 16 + m) * kOPad + 8 * q);
-#pragma unroll
-        for (int t = 0; t < NBW; ++t)
-#pragma unroll
-          for (int s = 0; s < 8; ++s)
-            acc[mb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bfr[t][s], acc[mb][t], 0, 0, 0);
-      }
+      tv[u] = x;
     }
-    __syncthreads();
+    if (tid < 32) dv = (D != nullptr && k0 + tid < ke) ? D[k0 + tid] : 1.0;
+  };
+  auto store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int e = tid + 64 * kGtW * u;
+      const int c = e >> 3, g4 = (e & 7) * 4;
+      if (e < ncol * 8) *reinterpret_cast<f4*>(&Ts[buf][c][g4]) = tv[u];
+    }
+    if (tid < 32) Ds[buf][tid] = dv;
+  };
+  if (kb < ke) {
+    load(kb);
+    store(0);
   }
-  float* Ys = Yp + (int64_t)blockIdx.y * ncols * ldy;
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += 32) {
+    const bool more = k0 + 32 < ke;
+    if (more) load(k0 + 32);
 #pragma unroll
-  for (int mb = 0; mb < 8; ++mb)
+    for (int kk = 0; kk < 32; kk += 4) {
+      const double w = Ds[cur][kk + fk];
 #pragma unroll
-    for (int t = 0; t < NBW; ++t) {
-      const int c = (wv + 4 * t) * 16 + m;
-      if (c >= ncols) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = j0 + mb * 16 + 4 * q + v;
-        if (j < d) Ys[(int64_t)c * ldy + j] = acc[mb][t][v];
+      for (int t = 0; t < kGtMaxB; ++t) {
+        if (wv + kGtW * t < nblk) {
+          const double a = (double)Ts[cur][16 * bi[t] + fi][kk + fk] * w;
+          const double b = (double)Ts[cur][r0 + 16 * bj[t] + fi][kk + fk];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        }
       }
     }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // FP64 16x16 result layout: lane (fk, fi) holds rows fk + 4 v of column fi
+#pragma unroll
+  for (int t = 0; t < kGtMaxB; ++t) {
+    const int b = wv + kGtW * t;
+    if (b < nblk) {
+      double* o = Wp + ((int64_t)blockIdx.x * nblk + b) * 256;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[(fk + 4 * v) * 16 + fi] = acc[t][v];
+    }
+  }
+}
+
+// Mb[i * ldm + r0 + j] = sum over the G slices of the partial blocks (slice
+// order); with sym the lower triangle reads the transposed upper block.
+__global__ void k_gram_t_reduce(const double* __restrict__ Wp, int G, int r1, int r0, int m,
+                                int sym, double* __restrict__ Mb, int ldm) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)r1 * m) return;
+  const int i = (int)(e / m), j = (int)(e % m);
+  const int RB = (r1 + 15) / 16, CB = (m + 15) / 16;
+  const int nblk = sym ? RB * (RB + 1) / 2 : RB * CB;
+  int bi = i >> 4, bj = j >> 4, ii = i & 15, jj = j & 15;
+  if (sym && bi > bj) {
+    const int t = bi; bi = bj; bj = t;
+    const int u = ii; ii = jj; jj = u;
+  }
+  const int b = sym ? bi * RB - bi * (bi - 1) / 2 + (bj - bi) : bi * CB + bj;
+  double s = 0.0;
+  for (int g = 0; g < G; ++g) s += Wp[((int64_t)g * nblk + b) * 256 + ii * 16 + jj];
+  Mb[(int64_t)i * ldm + r0 + j] = s;
+}
+
+// Launch shape of k_gram_t: usable when ceil(blocks / kGtW) <= kGtMaxB and
+// the staged columns fit; returns the partial-buffer bytes (0 = not usable).
+struct GramTShape {
+  int G, nblk;
+  int64_t slice;
+  size_t wp_b;
+};
+GramTShape gram_t_shape(int64_t n, int r1, int r0, int m, int num_cu) {
+  GramTShape g{0, 0, 0, 0};
+  const bool sym = (r0 == 0 && m == r1);
+  const int RB = (r1 + 15) / 16, CB = (m + 15) / 16;
+  const int nblk = sym ? RB * (RB + 1) / 2 : RB * CB;
+  const int ncol = std::max(16 * RB, r0 + 16 * CB);
+  if ((nblk + kGtW - 1) / kGtW > kGtMaxB || ncol > kGtMaxC) return g;
+  g.nblk = nblk;
+  g.G = (int)std::max<int64_t>(1, std::min<int64_t>(num_cu, (n + 31) / 32));
+  g.slice = ((n + g.G - 1) / g.G + 31) / 32 * 32;
+  g.G = (int)((n + g.slice - 1) / g.slice);
+  g.wp_b = align_up(sizeof(double) * (size_t)g.G * nblk * 256);
+  return g;
 }
 
 // Y(:, col0 + c) = sum_s Ypart[s][c] + coef * Omega(:, col0 + c)   (FP64)
@@ -667,55 +852,100 @@ nys_status grow(nys::DevBuf& b, size_t old_bytes, size_t new_bytes, hipStream_t 
   return NYS_OK;
 }
 
+#define NYS_NB_SWITCH(NB, X) \
+  switch (NB) {                 \
+    case 1: X(1); break;        \
+    case 2: X(2); break;        \
+    case 3: X(3); break;        \
+    case 4: X(4); break;        \
+    case 5: X(5); break;        \
+    case 6: X(6); break;        \
+    case 7: X(7); break;        \
+    case 8: X(8); break;        \
+    case 9: X(9); break;        \
+    case 10: X(10); break;      \
+    case 11: X(11); break;      \
+    case 12: X(12); break;      \
+    case 13: X(13); break;      \
+    case 14: X(14); break;      \
+    case 15: X(15); break;      \
+    default: X(16); break;      \
+  }
+
 template <bool BF>
-nys_status launch_sk1(int NB, const nys_dense& A, int vec, const void* Olp, int ldo, float* T,
-                      int64_t ldt, int col0, int ncols, int npass, hipStream_t st) {
-  dim3 grid((unsigned)((A.n + 127) / 128), npass);
+nys_status launch_sk1(int NB, int NW, const nys_dense& A, int vec, const void* Olp, int ldo,
+                      float* T, int64_t ldt, int col0, int ncols, int npass, hipStream_t st) {
+  const int64_t nblk = (A.n + 15) / 16;
+  dim3 grid((unsigned)((nblk + NW - 1) / NW), npass);
   const float* a = static_cast<const float*>(A.data);
-#define NYS_SK1(N)                                                                            \
-  hipLaunchKernelGGL((k_sk1<BF, N>), grid, dim3(256), 0, st, a, A.n, (int)A.d, A.ld, vec, Olp, \
-                     ldo, T, ldt, col0, ncols)
-  if (NB == 4) NYS_SK1(4);
-  else if (NB == 8) NYS_SK1(8);
-  else NYS_SK1(16);
+#define NYS_SK1(N)                                                                              \
+  hipLaunchKernelGGL((k_sk1<BF, N>), grid, dim3(64 * NW), 0, st, a, A.n, (int)A.d, A.ld, vec,  \
+                     Olp, ldo, T, ldt, col0, ncols)
+  NYS_NB_SWITCH(NB, NYS_SK1)
 #undef NYS_SK1
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
 template <bool BF>
-nys_status launch_sk2(int NB, const nys_dense& A, int vec, const double* D, const float* T,
-                      int64_t ldt, int col0, int ncols, int64_t slice, int S, float* Yp, int ldy,
+nys_status launch_sk2(int NB, const nys_dense& A, const double* D, const float* T, int64_t ldt,
+                      int col0, int ncols, int64_t slice, int S, float* Yp, int ldy,
                       hipStream_t st) {
-  dim3 grid((unsigned)((A.d + 127) / 128), S);
+  dim3 grid((unsigned)((A.d + 32 * kSk2W - 1) / (32 * kSk2W)), S);
   const float* a = static_cast<const float*>(A.data);
-#define NYS_SK2(N)                                                                            \
-  hipLaunchKernelGGL((k_sk2<BF, N>), grid, dim3(256), 0, st, a, A.n, (int)A.d, A.ld, vec, D, T, \
-                     ldt, col0, ncols, slice, Yp, ldy)
-  if (NB == 4) NYS_SK2(4);
-  else if (NB == 8) NYS_SK2(8);
-  else NYS_SK2(16);
+#define NYS_SK2(N)                                                                              \
+  hipLaunchKernelGGL((k_sk2<BF, N>), grid, dim3(64 * kSk2W), 0, st, a, A.n, (int)A.d, A.ld, D,  \
+                     T, ldt, col0, ncols, slice, Yp, ldy)
+  NYS_NB_SWITCH(NB, NYS_SK2)
 #undef NYS_SK2
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
 // Launch shape and temporaries of the FP32/BF16-MFMA sketch of m columns.
 struct Sk32Shape {
-  int ldo, NB, NP, npass, nrows_pad, ldy, S;
+  int ldo, NB, NP, npass, nrows_pad, ldy, S, NW;
   int64_t ldt, slice;
   size_t olp_b, yp_b;
 };
+// Wavefronts per workgroup of the first pass: each takes a 16-row block, and
+// the count is chosen so that the last round of workgroups fills the device
+// as fully as possible (rounds = ceil(workgroups / resident workgroups)).
+int sk1_waves(int64_t n, int NB, bool bf, int num_cu) {
+  const int64_t nblk = (n + 15) / 16;
+  const size_t lds = 2 * (size_t)16 * NB * kOPad * (bf ? 2 : 4);
+  const int by_lds = std::max<int>(1, (int)((160 * 1024) / lds));
+  const int nch = 16 * NB * (bf ? 4 : 8);   // 16-byte chunks of an Omega tile
+  const int lo = std::max(4, (nch + 64 * kSkMaxChunks - 1) / (64 * kSkMaxChunks));
+  int best = kSk1MaxW;
+  double best_eff = -1.0;
+  for (int nw = lo; nw <= kSk1MaxW; ++nw) {
+    // up to 4 wavefronts per SIMD (128 registers each)
+    const int per_cu = std::max(1, std::min(by_lds, 16 / nw));
+    const int64_t slots = (int64_t)per_cu * num_cu;
+    const int64_t tiles = (nblk + nw - 1) / nw;
+    const int64_t rounds = (tiles + slots - 1) / slots;
+    const double eff = (double)tiles / (double)(rounds * slots);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = nw;
+    }
+  }
+  return best;
+}
 Sk32Shape sk32_shape(int64_t n, int64_t d, int m, int num_cu, bool bf) {
   Sk32Shape s;
   s.ldo = (int)((d + 31) / 32 * 32);
-  s.NB = m <= 64 ? 4 : (m <= 128 ? 8 : 16);
+  s.NB = std::min(16, (m + 15) / 16);
   s.NP = 16 * s.NB;
   s.npass = (m + s.NP - 1) / s.NP;
   s.nrows_pad = s.npass * s.NP;
   s.ldt = (n + 7) / 8 * 8;
   s.ldy = (int)((d + 3) / 4 * 4);
-  // split-K over rows of A: about 4 workgroups per CU
-  const int jt = (int)((d + 127) / 128);
-  s.S = std::max(1, std::min<int>((int)((n + 255) / 256), (4 * num_cu) / jt));
+  s.NW = sk1_waves(n, s.NB, bf, num_cu);
+  // split-K over rows of A for the second pass: one resident workgroup per CU
+  // (the accumulators of 32 columns x 16 NB per wavefront), S slices so that
+  // the j tiles x slices fill the device once
+  const int jt = (int)((d + 32 * kSk2W - 1) / (32 * kSk2W));
+  s.S = std::max(1, std::min<int>((int)((n + 255) / 256), num_cu / jt));
   s.slice = (n + s.S - 1) / s.S;
   s.slice = (s.slice + kBK - 1) / kBK * kBK;
   s.S = (int)((n + s.slice - 1) / s.slice);
@@ -770,19 +1000,16 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
     // the same in FP32: Omega rounded to FP32 (the rounded values written
     // back, so the core sees the Omega the products used), Y = A Omega by the
     // FP32-MFMA tiles of the first sketch pass, then Y + c Omega in FP64
-    const int ldo = (int)((d + 31) / 32 * 32);
-    const int NB = m <= 64 ? 4 : (m <= 128 ? 8 : 16);
-    const int NP = 16 * NB;
-    const int npass = (m + NP - 1) / NP;
-    const int nrows_pad = npass * NP;
-    const int64_t ldt = (n + 7) / 8 * 8;
+    const Sk32Shape sh = sk32_shape(n, d, m, ctx->num_cu, false);
+    const int ldo = sh.ldo, NB = sh.NB, npass = sh.npass, nrows_pad = sh.nrows_pad;
+    const int64_t ldt = sh.ldt;
     NYS_TRY(ctx->gemm_ws.reserve(align_up((size_t)nrows_pad * ldo * 4)));
     void* Olp = ctx->gemm_ws.ptr;
     hipLaunchKernelGGL(k_round_omega<false>, dim3(blocks((int64_t)nrows_pad * ldo)), dim3(256), 0,
                        st, Om, (int)d, m, Olp, ldo, nrows_pad);
     const int vec = (((uintptr_t)A.data % 16) == 0 && (A.ld % 4) == 0) ? 1 : 0;
     float* T = F->T.as<float>();
-    NYS_TRY(launch_sk1<false>(NB, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+    NYS_TRY(launch_sk1<false>(NB, sh.NW, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
     hipLaunchKernelGGL(k_sym_y, dim3(blocks((int64_t)m * d)), dim3(256), 0, st, T + ldt * r0, ldt,
                        (int)d, m, Om, c, Y + d * r0);
   } else if (F->prec == NYS_F64) {
@@ -815,23 +1042,35 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
     const int vec = (((uintptr_t)A.data % 16) == 0 && (A.ld % 4) == 0) ? 1 : 0;
     float* T = F->T.as<float>();
     if (bf)
-      NYS_TRY(launch_sk1<true>(NB, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+      NYS_TRY(launch_sk1<true>(NB, sh.NW, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
     else
-      NYS_TRY(launch_sk1<false>(NB, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+      NYS_TRY(launch_sk1<false>(NB, sh.NW, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
     for (int p = 0; p < npass; ++p) {
       const int cols = std::min(NP, m - p * NP);
       if (bf)
-        NYS_TRY(launch_sk2<true>(NB, A, vec, D, T, ldt, r0 + p * NP, cols, slice, S, Yp, ldy, st));
+        NYS_TRY(launch_sk2<true>(NB, A, D, T, ldt, r0 + p * NP, cols, slice, S, Yp, ldy, st));
       else
-        NYS_TRY(launch_sk2<false>(NB, A, vec, D, T, ldt, r0 + p * NP, cols, slice, S, Yp, ldy, st));
+        NYS_TRY(launch_sk2<false>(NB, A, D, T, ldt, r0 + p * NP, cols, slice, S, Yp, ldy, st));
       hipLaunchKernelGGL(k_sk2_reduce, dim3(blocks((int64_t)cols * d)), dim3(256), 0, st, Yp, S,
                          cols, ldy, (int)d, F->Omega.as<double>(), c, Y, r0 + p * NP);
     }
     // new columns of the core matrix: Mbase[:, r0:r1] = T^T D T[:, r0:r1] + c Omega^T Omega_new
     double* Mb = F->Mbase.as<double>();
     const int ldm = F->cap;
-    NYS_TRY(gemm64(st, r1, m, (int)n, T, true, ldt, 1, T + ldt * r0, true, 1, ldt, Mb + r0, ldm, 1,
-                   1.0, 0.0, w.split, w.split_elems, D));
+    const GramTShape gs = gram_t_shape(n, r1, r0, m, ctx->num_cu);
+    if (gs.wp_b > 0) {
+      // the partials reuse the temporaries after the Y reduction (stream order)
+      NYS_TRY(ctx->gemm_ws.reserve(std::max(sh.olp_b + sh.yp_b, gs.wp_b)));
+      double* Wp = ctx->gemm_ws.as<double>();
+      const int sym = (r0 == 0 && m == r1) ? 1 : 0;
+      hipLaunchKernelGGL(k_gram_t, dim3(gs.G), dim3(64 * kGtW), 0, st, T, ldt, n, D, r1, r0, m,
+                         sym, gs.slice, Wp);
+      hipLaunchKernelGGL(k_gram_t_reduce, dim3(blocks((int64_t)r1 * m)), dim3(256), 0, st, Wp,
+                         gs.G, r1, r0, m, sym, Mb, ldm);
+    } else {
+      NYS_TRY(gemm64(st, r1, m, (int)n, T, true, ldt, 1, T + ldt * r0, true, 1, ldt, Mb + r0, ldm,
+                     1, 1.0, 0.0, w.split, w.split_elems, D));
+    }
     if (c != 0.0)
       NYS_TRY(gemm64(st, r1, m, (int)d, F->Omega.ptr, false, d, 1, Om, false, 1, d, Mb + r0, ldm,
                      1, c, 1.0, w.split, w.split_elems));
@@ -925,6 +1164,10 @@ void sketch_ws_bytes(const nys_dense& A, int m, int r, int num_cu, size_t* tmp,
   if (A.dtype == NYS_F32) {
     const Sk32Shape s = sk32_shape(n, d, m, num_cu, false);               // FP32 >= BF16
     g = std::max(g, s.olp_b + s.yp_b);
+    // T^T D T partials of the largest block: the first (square) block of m
+    // columns or an appended block of m columns on a rank of at most r
+    g = std::max(g, gram_t_shape(n, m, 0, m, num_cu).wp_b);
+    if (r > m) g = std::max(g, gram_t_shape(n, r, r - m, m, num_cu).wp_b);
   }
   const int64_t cap = std::min<int64_t>(2 * (int64_t)r, d - 1);
   const int64_t ldt = (n + 7) / 8 * 8;
