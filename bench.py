@@ -649,6 +649,16 @@ def bench_precision_path(args, N, synth, torch):
     return out
 
 
+def copy_reference(torch):
+    """A plain 1.6e9-byte device copy (400M floats): the reference a counter
+    run scales FETCH_SIZE / WRITE_SIZE by."""
+    xs = torch.empty(400_000_000, dtype=torch.float32, device="cuda")
+    ys = torch.empty_like(xs)
+    ys.copy_(xs)
+    torch.cuda.synchronize()
+    del xs, ys
+
+
 def bench_sparse(args, N, synth, torch):
     """Sparse lasso shaped like E2006.train (16087 x 150348, 0.8% nonzero):
     bag-of-words rows with Zipf column popularity, unit-norm rows; gamma =
@@ -661,6 +671,8 @@ def bench_sparse(args, N, synth, torch):
     S = N.SparseMatrix(ctx, rp, col, val, (n, d))
     omega = synth.omega_raw(d, r, seed=1, device="cuda").contiguous()
     prob = N.problem(S, b.contiguous(), gamma)
+    if args.copy_reference:
+        copy_reference(torch)
 
     def steps(k, profile=False):
         tot, pcg, bad, trm, sk, eta = 0, 0, 0, -1.0, 0.0, None
@@ -889,11 +901,7 @@ def main():
     ctx = N.Context()
     prob = N.problem(A, b, p.gamma)
     if args.copy_reference:
-        xs = torch.empty(400_000_000, dtype=torch.float32, device="cuda")
-        ys = torch.empty_like(xs)
-        ys.copy_(xs)
-        torch.cuda.synchronize()
-        del xs, ys
+        copy_reference(torch)
 
     tre = args.true_res_every
     run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.warmup, args.admm_iters, tre)

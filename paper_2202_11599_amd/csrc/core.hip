@@ -581,7 +581,6 @@ constexpr int kJP = 2 * kJB;   // pair block size
 constexpr int kJT = 256;       // threads of every Jacobi workgroup
 constexpr int kJE = kJP * kJP / kJT;   // tile elements per thread
 constexpr int kJU = kJB * (kJB + 1) / 2;   // upper 2x2 blocks of a step
-constexpr double kJacTol = 1e-15;
 
 // Round-robin pairing of nb blocks (nb even): round t, pair k -> (a, b).
 __device__ __forceinline__ void rr_pair(int nb, int t, int k, int* a, int* b) {
@@ -616,13 +615,14 @@ __device__ __forceinline__ int pair_index(int a, int b, int i) {
   return i < kJB ? a * kJB + i : b * kJB + (i - kJB);
 }
 
-// A rotation is applied when |a_pq| > max(tol sqrt(|a_pp a_qq|), tol * trace(H)):
+// A rotation is applied when |a_pq| > max(tol sqrt(|a_pp a_qq|), tol * trace(H))
+// (tol: 1e-15 for FP64 factors, looser where the sketch itself is FP32):
 // the relative test gives small eigenvalues their accuracy, the absolute floor
 // stops rotations that only chase the rounding of the tile updates.  Compared
 // in squares (no square root).
-__device__ __forceinline__ bool jac_rotates(double apq, double app, double aqq, double floor_abs) {
-  return apq != 0.0 &&
-         apq * apq > fmax(kJacTol * kJacTol * fabs(app * aqq), floor_abs * floor_abs);
+__device__ __forceinline__ bool jac_rotates(double apq, double app, double aqq, double tol,
+                                            double floor_abs) {
+  return apq != 0.0 && apq * apq > fmax(tol * tol * fabs(app * aqq), floor_abs * floor_abs);
 }
 
 // The rotation (c, s) of positions p < q that zeroes a_pq, with the inner
@@ -630,9 +630,9 @@ __device__ __forceinline__ bool jac_rotates(double apq, double app, double aqq, 
 // cos 2 phi = |theta| / h, c^2 = (1 + cos 2 phi) / 2 and s = sign(theta) a_pq /
 // (2 h c).  c^2 has no cancellation, and c^2 + s^2 = 1 to rounding because
 // sin^2 2 phi = 1 - cos^2 2 phi.  s = 0 means no rotation.
-__device__ __forceinline__ double2 jac_rotation(double apq, double app, double aqq,
+__device__ __forceinline__ double2 jac_rotation(double apq, double app, double aqq, double tol,
                                                 double floor_abs, bool* rotated) {
-  if (!jac_rotates(apq, app, aqq, floor_abs)) return make_double2(1.0, 0.0);
+  if (!jac_rotates(apq, app, aqq, tol, floor_abs)) return make_double2(1.0, 0.0);
   *rotated = true;
   const double theta = 0.5 * (aqq - app);
   const double h2 = fma(theta, theta, apq * apq);
@@ -943,7 +943,8 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
                                                       const double* __restrict__ Qprev,
                                                       double* __restrict__ Qcur,
                                                       int* __restrict__ counters, int sweep,
-                                                      const double* __restrict__ gnorm) {
+                                                      const double* __restrict__ gnorm,
+                                                      double tol) {
   if (jacobi_skip(counters, sweep)) return;
   __shared__ double S[kJP][kJP + 1];
   __shared__ double Q[kJP][kJP + 1];
@@ -956,7 +957,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
     jacobi_update(Hin, Hout, V, R, round - 1, Qprev, blockIdx.x - np, F.T[0], F.T[1]);
     return;
   }
-  const double floor_abs = kJacTol * (*gnorm);
+  const double floor_abs = tol * (*gnorm);
   int a, b;
   rr_pair(nb, round, blockIdx.x, &a, &b);
   if (FIRST) {
@@ -986,7 +987,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
       if (tid < kJB) {
         int p, q;
         step_pair<true>(tid, st, &p, &q);
-        cs[0][tid] = jac_rotation(S[p][q], S[p][p], S[q][q], floor_abs, &rotated);
+        cs[0][tid] = jac_rotation(S[p][q], S[p][p], S[q][q], tol, floor_abs, &rotated);
       }
       __syncthreads();
       if (gblk) upd_block<true>(S, cs[0], st, gka, gkb);
@@ -1003,7 +1004,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
     app = S[tid][tid];
     apq = S[tid][kJB + tid];
     aqq = S[kJB + tid][kJB + tid];
-    cs[0][tid] = jac_rotation(apq, app, aqq, floor_abs, &rotated);
+    cs[0][tid] = jac_rotation(apq, app, aqq, tol, floor_abs, &rotated);
   }
   __syncthreads();
   for (int st = 0; st < kJB; ++st) {
@@ -1035,7 +1036,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
         app = d00;
         aqq = nx11;
         apq = (k < kJB - 1) ? x01 : x10;
-        cs[(st + 1) & 1][k] = jac_rotation(apq, app, aqq, floor_abs, &rotated);
+        cs[(st + 1) & 1][k] = jac_rotation(apq, app, aqq, tol, floor_abs, &rotated);
       }
     } else if (oblk) {
       upd_block<false>(S, C, st, oka, okb);
@@ -1074,17 +1075,18 @@ __global__ __launch_bounds__(kJT) void k_jacobi_update(const double* __restrict_
 // diagonal, so the pair counts as converged when either entry passes.
 __global__ __launch_bounds__(256) void k_jacobi_check(const double* __restrict__ G, int R,
                                                      const double* __restrict__ gnorm,
-                                                     int* __restrict__ counters, int sweep) {
+                                                     int* __restrict__ counters, int sweep,
+                                                     double tol) {
   if (jacobi_skip(counters, sweep)) return;
   int* flag = counters + 64 + sweep;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)R * R) return;
   const int i = (int)(e / R), j = (int)(e % R);
   if (j <= i) return;
-  const double floor_abs = kJacTol * (*gnorm);
+  const double floor_abs = tol * (*gnorm);
   const double apq = fmin(fabs(G[e]), fabs(G[(int64_t)j * R + i]));
   const double app = G[(int64_t)i * R + i], aqq = G[(int64_t)j * R + j];
-  if (jac_rotates(apq, app, aqq, floor_abs)) *flag = 1;
+  if (jac_rotates(apq, app, aqq, tol, floor_abs)) *flag = 1;
 }
 
 // The check flag of sweep s, with the sequence number the host waits for, as
@@ -1277,7 +1279,8 @@ nys_status wait_jacobi_slot(hipStream_t st, const volatile unsigned long long* s
 
 nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws, int* counters,
                       int max_sweeps, void* host_pinned, void* host_pinned_dev, int* poll_seq,
-                      double* sig2, double* W, int ldw, int* sweeps_out, const double* V0) {
+                      double* sig2, double* W, int ldw, int* sweeps_out, const double* V0,
+                      double tol) {
   const int R = jacobi_pad(r);
   const int nb = R / kJB;
   const int np = nb / 2;
@@ -1317,10 +1320,10 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
       // in, G1 = H_t out); the last round's update is a launch of its own
       const unsigned nupd = (unsigned)(np * np + np * (R / kJP));
       hipLaunchKernelGGL(k_jacobi_round<true>, dim3(np), dim3(kJT), 0, st, G0, G1, V, R, 0,
-                         Qr[1], Qr[0], counters, enq, gnorm);
+                         Qr[1], Qr[0], counters, enq, gnorm, tol);
       for (int t = 1; t < nb - 1; ++t) {
         hipLaunchKernelGGL(k_jacobi_round<false>, dim3(np + nupd), dim3(kJT), 0, st, G0, G1, V,
-                           R, t, Qr[(t - 1) & 1], Qr[t & 1], counters, enq, gnorm);
+                           R, t, Qr[(t - 1) & 1], Qr[t & 1], counters, enq, gnorm, tol);
         std::swap(G0, G1);
       }
       hipLaunchKernelGGL(k_jacobi_update, dim3(nupd), dim3(kJT), 0, st, G0, G1, V, R, nb - 2,
@@ -1330,7 +1333,7 @@ nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws
       // converged when every off-diagonal pair passes the rotation criterion,
       // i.e. when the next sweep would not rotate
       hipLaunchKernelGGL(k_jacobi_check, dim3((unsigned)((RR + 255) / 256)), dim3(256), 0, st,
-                         G0, R, gnorm, counters, enq);
+                         G0, R, gnorm, counters, enq, tol);
       // sequence numbers are unique per context: stale slot contents never match
       *poll_seq = (*poll_seq % 1000000000) + 1;
       seqs[enq] = (unsigned)*poll_seq;

@@ -257,7 +257,7 @@ nys_status sketch_rebuild(nys_ctx ctx, const nys_dense* A, const double* D, doub
 nys_status jacobi_eig(hipStream_t st, const double* G, int r, int ld, double* ws, int* counters,
                       int max_sweeps, void* host_pinned, void* host_pinned_dev, int* poll_seq,
                       double* sig2, double* W, int ldw, int* sweeps_out,
-                      const double* V0 = nullptr);
+                      const double* V0 = nullptr, double tol = 1e-15);
 // Stop when ||w|| <= max(abs_tol, tol ||rhs||) (o.tol_abs: ||w|| <= o.tol).
 // hx_tag >= 0: H_rho x saved by the previous run's true-residual pass gives w0
 // without a pass over A when that run had the same (A, D, x pointer, c, rho)

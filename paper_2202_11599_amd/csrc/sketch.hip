@@ -474,9 +474,20 @@ __global__ void k_gram_t_reduce(const double* __restrict__ Wp, int G, int r1, in
     const int u = ii; ii = jj; jj = u;
   }
   const int b = sym ? bi * RB - bi * (bi - 1) / 2 + (bj - bi) : bi * CB + bj;
-  double s = 0.0;
-  for (int g = 0; g < G; ++g) s += Wp[((int64_t)g * nblk + b) * 256 + ii * 16 + jj];
-  Mb[(int64_t)i * ldm + r0 + j] = s;
+  // eight interleaved partial sums (slices g = u mod 8), combined in a fixed
+  // order: eight loads in flight, the same result on every call
+  const double* src = Wp + (int64_t)b * 256 + ii * 16 + jj;
+  const int64_t step = (int64_t)nblk * 256;
+  double a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = 0.0;
+  int g = 0;
+  for (; g + 7 < G; g += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += src[(int64_t)(g + u) * step];
+  }
+  for (; g < G; ++g) a[0] += src[(int64_t)g * step];
+  Mb[(int64_t)i * ldm + r0 + j] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 // Launch shape of k_gram_t: usable when ceil(blocks / kGtW) <= kGtMaxB and
