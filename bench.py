@@ -182,7 +182,8 @@ def pmc_summary(fetch_dir, write_dir, n, d, commands):
     return rec
 
 
-def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, profile=False):
+def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, profile=False,
+              pcg_timing=False):
     import torch
     if steps <= 0:
         return None
@@ -194,6 +195,8 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, prof
     tr_max = -1.0
     if profile:
         ctx.profile_start()
+    if pcg_timing:
+        ctx.profile_pcg_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -217,8 +220,12 @@ def run_steps(N, ctx, A, prob, omega, p, prec, steps, admm_iters, tr_every, prof
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = ctx.profile_stop() if profile else None
+    pcg = None
+    if pcg_timing:
+        pcg = ctx.profile_pcg()
+        ctx.profile_pcg_enable(False)
     solves = sum(n for _, n, _, _ in infos)
-    return dict(wall=wall, sketch_s=sketch_s, ranks=ranks,
+    return dict(wall=wall, sketch_s=sketch_s, ranks=ranks, pcg=pcg,
                 pcg_mean=sum(i for i, _, _, _ in infos) / max(solves, 1),
                 pcg_max=max(m for _, _, m, _ in infos), solves=solves, unconverged=bad, prof=prof,
                 eta=infos[-1][3], true_res_max=tr_max, step_rates=step_rates)
@@ -233,6 +240,23 @@ def solve_roofline(run, launches, n, d):
     return {"bytes_per_pcg_iteration": b_it, "pair_passes_per_solve": round(passes, 3),
             "solves_per_s_bound": round(bound, 1), "solves_per_s_excl_sketch": round(meas, 3),
             "frac": round(meas / bound, 4)}
+
+
+def host_description():
+    """Model, sockets, cores and threads of the host (lscpu), and nproc."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                     "CPU(s)", "NUMA node(s)"):
+                info[k] = v
+    except Exception:
+        pass
+    return info
 
 
 def cpu_baseline(A, b, omega, p, admm_iters, cpu_iters):
@@ -256,8 +280,22 @@ def cpu_baseline(A, b, omega, p, admm_iters, cpu_iters):
     r = ad.admm_lasso(A64, b64, p.gamma, p.rho, factor=f, iters=cpu_iters, pcg_tol=p.pcg_tol)
     t_iter = (time.perf_counter() - t0) / cpu_iters
     step = t_sketch + admm_iters * t_iter
+    # the same oracle iteration on one thread (the sketch is not repeated)
+    t1 = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            ad.admm_lasso(A64, b64, p.gamma, p.rho, factor=f, iters=1, pcg_tol=p.pcg_tol)
+            t1 = time.perf_counter() - t0
+    except Exception:
+        t1 = None
     return {
         "value": admm_iters / step, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+        "host": host_description(),
+        "single_thread": None if t1 is None else {
+            "solves_per_s_excl_sketch": round(1.0 / t1, 4), "seconds_per_iteration": round(t1, 3),
+            "note": "one NysADMM iteration of the oracle with BLAS limited to one thread"},
         "sample": (f"FP64 NumPy oracle on this host: adaptive sketch (rank {f.rank}, "
                    f"{t_sketch:.1f} s) and {cpu_iters} NysADMM iterations "
                    f"({t_iter:.2f} s each, {np.mean(r.pcg_iters):.1f} PCG iterations) on the same "
@@ -910,6 +948,10 @@ def main():
                       profile=True)
     print(f"[bench] plain fp32: {plain['solves'] / plain['wall']:.1f} solves/s", file=sys.stderr,
           flush=True)
+    # rate (i), PCG alone: the same steps again with HIP events around each
+    # subproblem's PCG solve (kept out of the headline run)
+    pcgrun = run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.steps, args.admm_iters, tre,
+                       pcg_timing=True)
     # the same steps with the FP64 true residual formed at every 10th solve only
     # (the others stop on the recursive residual and carry H_rho x = rhs - w)
     carried = run_steps(N, ctx, A, prob, omega, p, N.NYS_F32, args.steps, args.admm_iters, 10)
@@ -970,6 +1012,12 @@ def main():
         # must move A once (fused pair), U twice (FP32) and about 12 FP64
         # d-vectors; the pair passes per solve are those the event timing saw
         "solve_roofline": solve_roofline(plain, launches, args.n, args.d),
+        # rate (i): the subproblems' PCG solves alone (right-hand sides, prox
+        # and dual updates, and the sketch excluded)
+        "pcg_only": {"solves": pcgrun["pcg"][0], "pcg_ms_total": round(pcgrun["pcg"][1], 3),
+                     "solves_per_s": round(pcgrun["pcg"][0] / (pcgrun["pcg"][1] / 1e3), 3)
+                     if pcgrun["pcg"][1] > 0 else None,
+                     "note": "same steps, separate run, events around every PCG solve"},
         "gemv_hbm_gbs": round(achieved, 1),
         "true_residual_every_10th_solve": {
             "solves_per_s": round(carried["solves"] / carried["wall"], 3),

@@ -140,6 +140,14 @@ size_t nys_ctx_workspace_peak(nys_ctx ctx);
  * duration in ms of all timed launches, and disables the timing. */
 nys_status nys_ctx_profile_start(nys_ctx ctx);
 nys_status nys_ctx_profile_stop(nys_ctx ctx, long* launches, double* total_ms);
+/* PCG timing (instrumentation, separate from the above): while enabled
+ * (on = 1; enabling it clears the record) admm_step / admm_solve (one problem
+ * at a time) bracket each subproblem's PCG solve with HIP events on the
+ * context's stream.  nys_ctx_profile_pcg synchronises the stream and writes
+ * the number of solves timed and their summed duration in ms (the rate of
+ * PCG alone); the record stays until timing is enabled again. */
+nys_status nys_ctx_profile_pcg_enable(nys_ctx ctx, int on);
+nys_status nys_ctx_profile_pcg(nys_ctx ctx, long* solves, double* total_ms);
 
 /* ------------------------------------------------------------------ sketch */
 

@@ -293,8 +293,22 @@ nys_status admm_iter(nys_ctx ctx, const nys_problem& P, const nys_admm_opts& O, 
   int used_alt = 0;
   // lasso: within a run x is only changed by PCG, so H_rho x carries over
   // from one step's solve to the next (tagged with the step counter)
+  // instrumentation: HIP events around the PCG solve (rate of PCG alone)
+  const bool tpcg = ctx->pcg_time_on;
+  if (tpcg) {
+    while (ctx->pcg_ev.size() < ctx->pcg_used + 2) {
+      hipEvent_t e;
+      NYS_TRY_HIP(hipEventCreate(&e));
+      ctx->pcg_ev.push_back(e);
+    }
+    NYS_TRY_HIP(hipEventRecord(ctx->pcg_ev[ctx->pcg_used], st));
+  }
   nys_status ps = pcg_run(ctx, A, D, P.c, O.rho, *F, w.rhs, S->x, po, &pinfo, abs_tol,
                           P.loss == NYS_LOSS_LS ? (int64_t)S->k : -1, x_alt, &used_alt);
+  if (tpcg) {
+    NYS_TRY_HIP(hipEventRecord(ctx->pcg_ev[ctx->pcg_used + 1], st));
+    ctx->pcg_used += 2;
+  }
   if (*F != nullptr && O.ws_target != nullptr && (ps == NYS_OK || ps == NYS_ERR_MAXITER))
     NYS_TRY(ws_record(ctx, *F, nullptr, P.gamma, O.rho, S->x, nullptr, O.ws_target, w.wss));
   if (ps != NYS_OK && ps != NYS_ERR_MAXITER) {

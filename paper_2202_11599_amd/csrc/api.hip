@@ -796,6 +796,7 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   pool_unregister_stream(ctx->device, ctx->stream);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->pcg_ev) (void)hipEventDestroy(e);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return NYS_OK;
@@ -806,6 +807,27 @@ nys_status nys_ctx_profile_start(nys_ctx ctx) {
   ctx->prof_on = true;
   ctx->prof_used = 0;
   ctx->prof_skipped = 0;
+  return NYS_OK;
+}
+
+nys_status nys_ctx_profile_pcg_enable(nys_ctx ctx, int on) {
+  if (ctx == nullptr) return NYS_ERR_INVALID;
+  if (on && !ctx->pcg_time_on) ctx->pcg_used = 0;
+  ctx->pcg_time_on = on != 0;
+  return NYS_OK;
+}
+
+nys_status nys_ctx_profile_pcg(nys_ctx ctx, long* solves, double* total_ms) {
+  if (ctx == nullptr) return NYS_ERR_INVALID;
+  NYS_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < ctx->pcg_used; i += 2) {
+    float ms = 0.f;
+    NYS_TRY_HIP(hipEventElapsedTime(&ms, ctx->pcg_ev[i], ctx->pcg_ev[i + 1]));
+    tot += ms;
+  }
+  if (solves) *solves = (long)(ctx->pcg_used / 2);
+  if (total_ms) *total_ms = tot;
   return NYS_OK;
 }
 

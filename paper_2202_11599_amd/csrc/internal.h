@@ -323,6 +323,9 @@ struct nys_ctx_s {
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used = 0;
   long prof_skipped = 0;         // timed launches that returned at once (PCG already done)
+  bool pcg_time_on = false;        // time each ADMM subproblem's PCG solve with events
+  std::vector<hipEvent_t> pcg_ev;  // their event pairs
+  size_t pcg_used = 0;
 };
 
 struct nys_sparse_s {

@@ -25,18 +25,42 @@ constexpr int kTBlocks = 64;   // row blocks of the transpose
 constexpr int kShortCol = 32;  // columns with at most this many entries: 8 lanes each
 constexpr int kLongCol = 2048; // columns with more: a 256-thread workgroup each
 
-// Column j goes to list 0 (short), 1 (medium) or 2 (long); counts[3] are the
-// list lengths (the order inside a list does not affect any result: each
-// column is summed by one group on its own).
-__global__ __launch_bounds__(256) void k_bin_cols(const int* __restrict__ colptr, int64_t d,
-                                                  int* __restrict__ lists,
-                                                  int* __restrict__ counts) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= d) return;
+// Column j goes to list 0 (short), 1 (medium) or 2 (long), each list in
+// increasing column order (so a pass over a list reads the CSC arrays in
+// storage order); counts[3] are the list lengths.  One workgroup: thread t
+// counts its contiguous range of columns per class, the counts are
+// prefix-summed, and each thread places its range in order.
+__device__ __forceinline__ int col_class(const int* __restrict__ colptr, int64_t j) {
   const int len = colptr[j + 1] - colptr[j];
-  const int b = len <= kShortCol ? 0 : (len <= kLongCol ? 1 : 2);
-  const int pos = atomicAdd(&counts[b], 1);
-  lists[(int64_t)b * d + pos] = (int)j;
+  return len <= kShortCol ? 0 : (len <= kLongCol ? 1 : 2);
+}
+__global__ __launch_bounds__(1024) void k_bin_cols(const int* __restrict__ colptr, int64_t d,
+                                                   int* __restrict__ lists,
+                                                   int* __restrict__ counts) {
+  __shared__ int part[3][1024];
+  const int t = threadIdx.x;
+  const int64_t per = (d + 1023) / 1024;
+  const int64_t j0 = std::min<int64_t>(d, t * per), j1 = std::min<int64_t>(d, j0 + per);
+  int c[3] = {0, 0, 0};
+  for (int64_t j = j0; j < j1; ++j) ++c[col_class(colptr, j)];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) part[b][t] = c[b];
+  __syncthreads();
+  if (t < 3) {
+    int acc = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int v = part[t][i];
+      part[t][i] = acc;
+      acc += v;
+    }
+    counts[t] = acc;
+  }
+  __syncthreads();
+  int pos[3] = {part[0][t], part[1][t], part[2][t]};
+  for (int64_t j = j0; j < j1; ++j) {
+    const int b = col_class(colptr, j);
+    lists[(int64_t)b * d + pos[b]++] = (int)j;
+  }
 }
 
 // *bad = 1 unless rowptr is non-decreasing (its ends were checked on the host)
@@ -127,25 +151,39 @@ __global__ __launch_bounds__(64) void k_tr_fill(const int* __restrict__ rowptr,
   }
 }
 
-// sum over k = k0, k0 + step, ... (below k1) of v[k] x[idx[k]]: four terms in
-// flight per lane (their index and value loads issued together, then the
-// four gathers), four running sums combined in a fixed order
+// sum over k = k0, k0 + step, ... (below k1) of v[k] x[idx[k]]: eight terms
+// in flight per lane (their index and value loads issued together, then the
+// eight gathers), eight running sums combined in a fixed order, then the
+// remaining terms four and one at a time
 __device__ __forceinline__ double gather_dot(const int* __restrict__ idx,
                                              const float* __restrict__ v,
                                              const double* __restrict__ x, int64_t k0, int64_t k1,
                                              int step) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = 0.0;
   int64_t k = k0;
+  for (; k + 7 * step < k1; k += 8 * step) {
+    int ii[8];
+    float vv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      ii[u] = idx[k + u * step];
+      vv[u] = v[k + u * step];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = fma((double)vv[u], x[ii[u]], a[u]);
+  }
   for (; k + 3 * step < k1; k += 4 * step) {
     const int i0 = idx[k], i1 = idx[k + step], i2 = idx[k + 2 * step], i3 = idx[k + 3 * step];
     const float v0 = v[k], v1 = v[k + step], v2 = v[k + 2 * step], v3 = v[k + 3 * step];
-    a0 = fma((double)v0, x[i0], a0);
-    a1 = fma((double)v1, x[i1], a1);
-    a2 = fma((double)v2, x[i2], a2);
-    a3 = fma((double)v3, x[i3], a3);
+    a[0] = fma((double)v0, x[i0], a[0]);
+    a[1] = fma((double)v1, x[i1], a[1]);
+    a[2] = fma((double)v2, x[i2], a[2]);
+    a[3] = fma((double)v3, x[i3], a[3]);
   }
-  for (; k < k1; k += step) a0 = fma((double)v[k], x[idx[k]], a0);
-  return (a0 + a1) + (a2 + a3);
+  for (; k < k1; k += step) a[0] = fma((double)v[k], x[idx[k]], a[0]);
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 // Row pass: t_i = A_i p (one wavefront per row), s_i = f_mode(t_i) into s,
@@ -200,63 +238,52 @@ __global__ __launch_bounds__(256) void k_csr_pass(const int* __restrict__ rowptr
   if (threadIdx.x == 0) qpart[blockIdx.x] = ((qs[0] + qs[1]) + qs[2]) + qs[3];
 }
 
-// Column pass: y_j = sum over column j of A_ij s_i.  Short columns: 8 lanes
-// per column (8 columns per wavefront); medium: one wavefront; long: one
-// 256-thread workgroup.  Fixed summation order per column.
-__global__ __launch_bounds__(256) void k_csc_short(const int* __restrict__ colptr,
-                                                   const int* __restrict__ rows,
-                                                   const float* __restrict__ cval,
-                                                   const int* __restrict__ list, int cnt,
-                                                   const double* __restrict__ s,
-                                                   double* __restrict__ y,
-                                                   const int* __restrict__ done) {
-  if (done != nullptr && *done) return;
-  const int g = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3);
-  const int sub = threadIdx.x & 7;
-  double acc = 0.0;
-  int j = -1;
-  if (g < cnt) {
-    j = list[g];
-    acc = gather_dot(rows, cval, s, colptr[j] + sub, colptr[j + 1], 8);
-  }
-  acc += __shfl_xor(acc, 4, 8);
-  acc += __shfl_xor(acc, 2, 8);
-  acc += __shfl_xor(acc, 1, 8);
-  if (j >= 0 && sub == 0) y[j] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_csc_wave(const int* __restrict__ colptr,
+// Column pass: y_j = sum over column j of A_ij s_i, one launch for the three
+// column lists: workgroups [0, nlong) take one long column each (256
+// threads), the next ceil(nmed / 4) one medium column per wavefront, the
+// rest 32 short columns each (8 lanes per column).  Long columns come first
+// so that the longest work is dispatched first.  Fixed summation order per
+// column.
+__global__ __launch_bounds__(256) void k_csc_pass(const int* __restrict__ colptr,
                                                   const int* __restrict__ rows,
                                                   const float* __restrict__ cval,
-                                                  const int* __restrict__ list, int cnt,
+                                                  const int* __restrict__ lists, int64_t d,
+                                                  int nshort, int nmed, int nlong,
                                                   const double* __restrict__ s,
                                                   double* __restrict__ y,
                                                   const int* __restrict__ done) {
   if (done != nullptr && *done) return;
-  const int lane = threadIdx.x & 63;
-  const int g = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
-  if (g >= cnt) return;
-  const int j = list[g];
-  double acc = gather_dot(rows, cval, s, colptr[j] + lane, colptr[j + 1], 64);
-  acc = wave_sum(acc);
-  if (lane == 0) y[j] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_csc_block(const int* __restrict__ colptr,
-                                                   const int* __restrict__ rows,
-                                                   const float* __restrict__ cval,
-                                                   const int* __restrict__ list,
-                                                   const double* __restrict__ s,
-                                                   double* __restrict__ y,
-                                                   const int* __restrict__ done) {
-  if (done != nullptr && *done) return;
-  __shared__ double red[4];
-  const int j = list[blockIdx.x];
-  double acc = gather_dot(rows, cval, s, colptr[j] + threadIdx.x, colptr[j + 1], 256);
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) y[j] = ((red[0] + red[1]) + red[2]) + red[3];
+  const int bid = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int gm = (nmed + 3) / 4;
+  if (bid < nlong) {
+    __shared__ double red[4];
+    const int j = lists[2 * d + bid];
+    double acc = gather_dot(rows, cval, s, colptr[j] + tid, colptr[j + 1], 256);
+    acc = wave_sum(acc);
+    if (lane == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) y[j] = ((red[0] + red[1]) + red[2]) + red[3];
+  } else if (bid < nlong + gm) {
+    const int g = (bid - nlong) * 4 + (tid >> 6);
+    if (g >= nmed) return;
+    const int j = lists[d + g];
+    double acc = gather_dot(rows, cval, s, colptr[j] + lane, colptr[j + 1], 64);
+    acc = wave_sum(acc);
+    if (lane == 0) y[j] = acc;
+  } else {
+    const int g = (bid - nlong - gm) * 32 + (tid >> 3);
+    const int sub = tid & 7;
+    double acc = 0.0;
+    int j = -1;
+    if (g < nshort) {
+      j = lists[g];
+      acc = gather_dot(rows, cval, s, colptr[j] + sub, colptr[j + 1], 8);
+    }
+    acc += __shfl_xor(acc, 4, 8);
+    acc += __shfl_xor(acc, 2, 8);
+    acc += __shfl_xor(acc, 1, 8);
+    if (j >= 0 && sub == 0) y[j] = acc;
+  }
 }
 
 // Omega (column-major d x m) -> row-major d x m
@@ -394,15 +421,10 @@ nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& pl, int mod
       NYS_TRY(launch_note(reinterpret_cast<const PcgDev*>(done), note, note_seq, st));
   }
   const int* lists = S->bins.as<int>();
-  if (S->nshort > 0)
-    hipLaunchKernelGGL(k_csc_short, dim3((unsigned)((S->nshort + 31) / 32)), dim3(256), 0, st,
-                       S->colptr(), S->rows(), S->cvals(), lists, S->nshort, s, ypart, done);
-  if (S->nmed > 0)
-    hipLaunchKernelGGL(k_csc_wave, dim3((unsigned)((S->nmed + 3) / 4)), dim3(256), 0, st,
-                       S->colptr(), S->rows(), S->cvals(), lists + S->d, S->nmed, s, ypart, done);
-  if (S->nlong > 0)
-    hipLaunchKernelGGL(k_csc_block, dim3((unsigned)S->nlong), dim3(256), 0, st, S->colptr(),
-                       S->rows(), S->cvals(), lists + 2 * S->d, s, ypart, done);
+  const int64_t gcsc = (int64_t)S->nlong + (S->nmed + 3) / 4 + (S->nshort + 31) / 32;
+  if (gcsc > 0)
+    hipLaunchKernelGGL(k_csc_pass, dim3((unsigned)gcsc), dim3(256), 0, st, S->colptr(), S->rows(),
+                       S->cvals(), lists, S->d, S->nshort, S->nmed, S->nlong, s, ypart, done);
   if (ev1 != nullptr) NYS_TRY_HIP(hipEventRecord(ev1, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
@@ -526,8 +548,7 @@ nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, con
     int hc[3] = {0, 0, 0};
     if (hipMemsetAsync(counts, 0, sizeof(int) * 3, st) != hipSuccess) s = NYS_ERR_HIP;
     if (s == NYS_OK) {
-      hipLaunchKernelGGL(k_bin_cols, dim3(nb256(d)), dim3(256), 0, st, S->colptr(), d, lists,
-                         counts);
+      hipLaunchKernelGGL(k_bin_cols, dim3(1), dim3(1024), 0, st, S->colptr(), d, lists, counts);
       if (hipGetLastError() != hipSuccess ||
           hipMemcpyAsync(hc, counts, sizeof(int) * 3, hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)

@@ -28,7 +28,7 @@ NYS_LOSS_LS, NYS_LOSS_LOGISTIC = 0, 1
 
 EXPORTS = [
     "nys_status_string", "nys_ctx_create", "nys_ctx_destroy", "nys_ctx_set_stream",
-    "nys_ctx_workspace_bytes", "nys_ctx_profile_start", "nys_ctx_profile_stop", "nys_sketch", "nys_sketch_adaptive", "nys_factor_import",
+    "nys_ctx_workspace_bytes", "nys_ctx_profile_start", "nys_ctx_profile_stop", "nys_ctx_profile_pcg", "nys_ctx_profile_pcg_enable", "nys_sketch", "nys_sketch_adaptive", "nys_factor_import",
     "nys_factor_info", "nys_factor_get_U", "nys_factor_destroy", "nys_hessian_apply",
     "nys_precond_apply", "pcg_solve", "admm_step", "admm_solve", "nys_ws_param_count",
     "nys_ws_create", "nys_ws_get_params", "nys_ws_forward", "nys_ws_loss_grad",
@@ -127,6 +127,8 @@ def lib():
         "nys_ctx_workspace_peak": (C.c_size_t, [vp]),
         "nys_ctx_profile_start": (i32, [vp]),
         "nys_ctx_profile_stop": (i32, [vp, P(C.c_long), P(dbl)]),
+        "nys_ctx_profile_pcg": (i32, [vp, P(C.c_long), P(dbl)]),
+        "nys_ctx_profile_pcg_enable": (i32, [vp, i32]),
         "nys_sketch": (i32, [vp, P(Dense), vp, dbl, vp, i32, i32, P(vp)]),
         "nys_sketch_adaptive": (i32, [vp, P(Dense), vp, dbl, vp, i32, i32, dbl, dbl, i32, P(vp)]),
         "nys_factor_import": (i32, [vp, i64, i32, vp, P(dbl), dbl, P(vp)]),
@@ -223,6 +225,16 @@ class Context:
         """(launches, total_ms) of the matvec-pair kernel since profile_start."""
         n, ms = C.c_long(), C.c_double()
         _check(lib().nys_ctx_profile_stop(self.h, C.byref(n), C.byref(ms)), "nys_ctx_profile_stop")
+        return n.value, ms.value
+
+    def profile_pcg_enable(self, on: bool = True):
+        """Time each ADMM subproblem's PCG solve with HIP events (clears the record)."""
+        _check(lib().nys_ctx_profile_pcg_enable(self.h, int(bool(on))), "nys_ctx_profile_pcg_enable")
+
+    def profile_pcg(self):
+        """(solves, total_ms) of the PCG solves timed since profile_pcg_enable."""
+        n, ms = C.c_long(), C.c_double()
+        _check(lib().nys_ctx_profile_pcg(self.h, C.byref(n), C.byref(ms)), "nys_ctx_profile_pcg")
         return n.value, ms.value
 
     def workspace_bytes(self) -> int:
