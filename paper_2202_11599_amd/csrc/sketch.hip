@@ -62,9 +62,10 @@ __device__ __forceinline__ f8 load8(const float* p, int valid, bool vec) {
 }
 
 // T(:, col0 + c) = A Omega_lp(:, c), c < ncols.  A workgroup of NW
-// wavefronts (blockDim = 64 NW) covers 16 NW rows; wavefront w owns the
-// 16-row block blockIdx.x * NW + w and all NB column blocks (16 NB columns
-// from 16 NB blockIdx.y).  The Omega tile (16 NB x 32 per K step) goes
+// wavefronts (blockDim = 64 NW) covers 16 RB NW rows; wavefront w owns RB
+// consecutive 16-row blocks (RB = 2 for at most 5 column blocks, so that a K
+// step holds enough MFMA work, else 1) and all NB column blocks (16 NB
+// columns from 16 NB blockIdx.y).  The Omega tile (16 NB x 32 per K step) goes
 // through double-buffered LDS and is shared by the NW wavefronts; each
 // wavefront reads its A rows straight from memory in MFMA operand order,
 // the next step's rows and Omega tile loaded while the current step's MFMAs
@@ -72,21 +73,32 @@ __device__ __forceinline__ f8 load8(const float* p, int valid, bool vec) {
 // with zero padding up to ldo (a multiple of 32) and up to 16 NB rows.
 constexpr int kSkMaxChunks = 4;   // 16-byte Omega chunks staged per thread
 constexpr int kSk1MaxW = 13;      // wavefronts per first-pass workgroup, at most
+constexpr int sk1_row_blocks(int NB) { return NB <= 5 ? 2 : 1; }
+// wavefronts per first-pass workgroup, at most: the two-block form and the
+// widest column tiles need more than 128 registers per lane, so at most 8 or
+// 12 wavefronts (3 per SIMD resident)
+constexpr int sk1_max_waves(int NB) {
+  return sk1_row_blocks(NB) == 2 ? 8 : (NB >= 14 ? 12 : kSk1MaxW);
+}
+constexpr int sk2_col_blocks(int) { return 2; }
 template <bool BF, int NB>
-__global__ __launch_bounds__(64 * kSk1MaxW) void k_sk1(const float* __restrict__ A, int64_t n, int d,
+__global__ __launch_bounds__(64 * sk1_max_waves(NB)) void k_sk1(const float* __restrict__ A, int64_t n, int d,
                                               int64_t ld, int vec, const void* __restrict__ Olp,
                                               int ldo, float* __restrict__ T, int64_t ldt,
                                               int col0, int ncols) {
   constexpr int NP = 16 * NB;
+  constexpr int RB = sk1_row_blocks(NB);
   constexpr int TILE = NP * kOPad * (BF ? 2 : 4);
   __shared__ __attribute__((aligned(32))) char smem[2 * TILE];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
   const int q = lane >> 4, m = lane & 15;
-  const int64_t m0 = ((int64_t)blockIdx.x * (nthr >> 6) + wv) * 16;
+  const int64_t m0 = ((int64_t)blockIdx.x * (nthr >> 6) + wv) * 16 * RB;
   const int n0 = blockIdx.y * NP;
-  f4 acc[NB];
+  f4 acc[RB][NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = (f4)0.0f;
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = (f4)0.0f;
   constexpr int NCH = BF ? NP * 4 : NP * 8;   // 16-byte chunks of one Omega tile
   // staged chunks as separate values (an indexed array would go to scratch);
   // the host launches at least NCH / (64 kSkMaxChunks) wavefronts
@@ -126,31 +138,42 @@ __global__ __launch_bounds__(64 * kSk1MaxW) void k_sk1(const float* __restrict__
       }
     }
   };
-  const int64_t row = m0 + m;
-  auto load_a = [&](int k0) __attribute__((always_inline)) -> f8 {
+  f8 an[RB];
+  auto load_a = [&](int k0) __attribute__((always_inline)) {
     const int kk = k0 + 8 * q;
-    return (row < n && kk < d) ? load8(A + row * ld + kk, d - kk, vec) : (f8)0.0f;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t row = m0 + 16 * rb + m;
+      an[rb] = (row < n && kk < d) ? load8(A + row * ld + kk, d - kk, vec) : (f8)0.0f;
+    }
   };
   load_omega(0);
-  f8 an = load_a(0);
+  load_a(0);
   store_omega(smem);
   __syncthreads();
   int cur = 0;
   for (int k0 = 0; k0 < d; k0 += kBK) {
-    const f8 af = an;
+    f8 af[RB];
+    bf16x8 ab[RB];   // BF16: converted before the next step's loads are issued
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      if constexpr (BF) ab[rb] = to_bf16(an[rb]);
+      else af[rb] = an[rb];
+    }
     const bool more = k0 + kBK < d;
     if (more) {
       load_omega(k0 + kBK);
-      an = load_a(k0 + kBK);
+      load_a(k0 + kBK);
     }
     const char* buf = smem + cur * TILE;
     if constexpr (BF) {
-      const bf16x8 a0 = to_bf16(af);
       const __bf16* Os = reinterpret_cast<const __bf16*>(buf);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Os + (nb * 16 + m) * kOPad + 8 * q);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[nb], 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[rb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[rb], bv, acc[rb][nb], 0, 0, 0);
       }
     } else {
       const float* Os = reinterpret_cast<const float*>(buf);
@@ -159,7 +182,10 @@ __global__ __launch_bounds__(64 * kSk1MaxW) void k_sk1(const float* __restrict__
         const f8 bv = *reinterpret_cast<const f8*>(Os + (nb * 16 + m) * kOPad + 8 * q);
 #pragma unroll
         for (int s = 0; s < 8; ++s)
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[s], bv[s], acc[nb], 0, 0, 0);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            acc[rb][nb] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(af[rb][s], bv[s], acc[rb][nb], 0, 0, 0);
       }
     }
     if (more) store_omega(smem + (cur ^ 1) * TILE);
@@ -168,20 +194,23 @@ __global__ __launch_bounds__(64 * kSk1MaxW) void k_sk1(const float* __restrict__
   }
   // 16x16 FP32 result layout: lane (q, m) holds rows 4 q + v of column m
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int c = n0 + nb * 16 + m;
-    if (c >= ncols) continue;
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = m0 + 4 * q + v;
-      if (r < n) T[(int64_t)(col0 + c) * ldt + r] = acc[nb][v];
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = n0 + nb * 16 + m;
+      if (c >= ncols) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = m0 + 16 * rb + 4 * q + v;
+        if (r < n) T[(int64_t)(col0 + c) * ldt + r] = acc[rb][nb][v];
+      }
     }
-  }
 }
 
 // Ypart[s][c][j] = sum_{i in slice s} A[i][j] D[i] T[i][c]  (j < d, c < ncols).
-// A workgroup of kSk2W wavefronts covers 32 kSk2W columns j of A and all NB
-// sketch column blocks; wavefront w owns the j blocks 2w, 2w + 1.  Per K step
+// A workgroup of kSk2W wavefronts covers 16 JB kSk2W columns j of A and all
+// NB sketch column blocks; wavefront w owns JB = 2 consecutive 16-column
+// blocks of A (four per wavefront at small NB measured no faster).  Per K step
 // of 32 rows i, (D o T) for the NB blocks is staged in double-buffered LDS
 // (column-major, as T is stored; for BF16 as hi and lo parts, so only A is
 // rounded to BF16) and shared by the wavefronts, while each wavefront reads
@@ -196,17 +225,18 @@ __global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A,
                                                     int col0, int ncols, int64_t slice,
                                                     float* __restrict__ Yp, int ldy) {
   constexpr int NP = 16 * NB;
+  constexpr int JB = sk2_col_blocks(NB);
   constexpr int TILE = NP * kTPad * 4;   // one buffer: FP32 (D o T), or bf16 hi + lo
   constexpr int NT = 64 * kSk2W;
   __shared__ __attribute__((aligned(32))) char smem[2 * TILE];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int q = lane >> 4, m = lane & 15;
-  const int j0 = blockIdx.x * 32 * kSk2W + 32 * wv;
+  const int j0 = blockIdx.x * 16 * JB * kSk2W + 16 * JB * wv;
   const int64_t i_beg = (int64_t)blockIdx.y * slice;
   const int64_t i_end = (i_beg + slice < n) ? i_beg + slice : n;
-  f4 acc[2][NB];
+  f4 acc[JB][NB];
 #pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
+  for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[jb][nb] = (f4)0.0f;
   // (D o T) tile: NP columns x 32 rows, thread tid stages 4 consecutive rows
@@ -261,10 +291,10 @@ __global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A,
     }
   };
   // A^T operand: lane (q, m), j block jb: A[i0 + 8q + s][j0 + 16 jb + m], s < 8
-  f8 an[2];
+  f8 an[JB];
   auto load_a = [&](int64_t i0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb) {
+    for (int jb = 0; jb < JB; ++jb) {
       const int j = j0 + 16 * jb + m;
       const int64_t ib = i0 + 8 * q;
 #pragma unroll
@@ -280,7 +310,9 @@ __global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A,
   __syncthreads();
   int cur = 0;
   for (int64_t i0 = i_beg; i0 < i_end; i0 += kBK) {
-    const f8 a0 = an[0], a1 = an[1];
+    f8 a[JB];
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) a[jb] = an[jb];
     const bool more = i0 + kBK < i_end;
     if (more) {
       load_t(i0 + kBK);
@@ -288,7 +320,9 @@ __global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A,
     }
     const char* buf = smem + cur * TILE;
     if constexpr (BF) {
-      const bf16x8 b0 = to_bf16(a0), b1 = to_bf16(a1);
+      bf16x8 b[JB];
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) b[jb] = to_bf16(a[jb]);
       const __bf16* hi = reinterpret_cast<const __bf16*>(buf);
       const __bf16* lo = hi + NP * kTPad;
 #pragma unroll
@@ -296,10 +330,11 @@ __global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A,
         const int off = (nb * 16 + m) * kTPad + 8 * q;
         const bf16x8 th = *reinterpret_cast<const bf16x8*>(hi + off);
         const bf16x8 tl = *reinterpret_cast<const bf16x8*>(lo + off);
-        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0, th, acc[0][nb], 0, 0, 0);
-        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0, tl, acc[0][nb], 0, 0, 0);
-        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1, th, acc[1][nb], 0, 0, 0);
-        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1, tl, acc[1][nb], 0, 0, 0);
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) {
+          acc[jb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[jb], th, acc[jb][nb], 0, 0, 0);
+          acc[jb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[jb], tl, acc[jb][nb], 0, 0, 0);
+        }
       }
     } else {
       const float* Ts = reinterpret_cast<const float*>(buf);
@@ -307,10 +342,10 @@ __global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A,
       for (int nb = 0; nb < NB; ++nb) {
         const f8 bv = *reinterpret_cast<const f8*>(Ts + (nb * 16 + m) * kTPad + 8 * q);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], bv[s], acc[0][nb], 0, 0, 0);
-          acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], bv[s], acc[1][nb], 0, 0, 0);
-        }
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+            acc[jb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jb][s], bv[s], acc[jb][nb], 0, 0, 0);
       }
     }
     if (more) store_t(smem + (cur ^ 1) * TILE);
@@ -319,7 +354,7 @@ __global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A,
   }
   float* Ys = Yp + (int64_t)blockIdx.y * ncols * ldy;
 #pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
+  for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int c = nb * 16 + m;
@@ -886,8 +921,8 @@ nys_status grow(nys::DevBuf& b, size_t old_bytes, size_t new_bytes, hipStream_t 
 template <bool BF>
 nys_status launch_sk1(int NB, int NW, const nys_dense& A, int vec, const void* Olp, int ldo,
                       float* T, int64_t ldt, int col0, int ncols, int npass, hipStream_t st) {
-  const int64_t nblk = (A.n + 15) / 16;
-  dim3 grid((unsigned)((nblk + NW - 1) / NW), npass);
+  const int rows = 16 * NW * sk1_row_blocks(NB);
+  dim3 grid((unsigned)((A.n + rows - 1) / rows), npass);
   const float* a = static_cast<const float*>(A.data);
 #define NYS_SK1(N)                                                                              \
   hipLaunchKernelGGL((k_sk1<BF, N>), grid, dim3(64 * NW), 0, st, a, A.n, (int)A.d, A.ld, vec,  \
@@ -901,7 +936,8 @@ template <bool BF>
 nys_status launch_sk2(int NB, const nys_dense& A, const double* D, const float* T, int64_t ldt,
                       int col0, int ncols, int64_t slice, int S, float* Yp, int ldy,
                       hipStream_t st) {
-  dim3 grid((unsigned)((A.d + 32 * kSk2W - 1) / (32 * kSk2W)), S);
+  const int cols = 16 * kSk2W * sk2_col_blocks(NB);
+  dim3 grid((unsigned)((A.d + cols - 1) / cols), S);
   const float* a = static_cast<const float*>(A.data);
 #define NYS_SK2(N)                                                                              \
   hipLaunchKernelGGL((k_sk2<BF, N>), grid, dim3(64 * kSk2W), 0, st, a, A.n, (int)A.d, A.ld, D,  \
@@ -921,16 +957,18 @@ struct Sk32Shape {
 // the count is chosen so that the last round of workgroups fills the device
 // as fully as possible (rounds = ceil(workgroups / resident workgroups)).
 int sk1_waves(int64_t n, int NB, bool bf, int num_cu) {
-  const int64_t nblk = (n + 15) / 16;
+  const int rb = sk1_row_blocks(NB);
+  const int64_t nblk = (n + 16 * rb - 1) / (16 * rb);
   const size_t lds = 2 * (size_t)16 * NB * kOPad * (bf ? 2 : 4);
   const int by_lds = std::max<int>(1, (int)((160 * 1024) / lds));
   const int nch = 16 * NB * (bf ? 4 : 8);   // 16-byte chunks of an Omega tile
   const int lo = std::max(4, (nch + 64 * kSkMaxChunks - 1) / (64 * kSkMaxChunks));
-  int best = kSk1MaxW;
+  const int hi = rb == 2 ? 8 : (NB >= 14 ? 12 : kSk1MaxW);   // sk1_max_waves
+  const int waves_cu = (rb == 2 || NB >= 14) ? 12 : 16;       // 3 or 4 resident per SIMD
+  int best = hi;
   double best_eff = -1.0;
-  for (int nw = lo; nw <= kSk1MaxW; ++nw) {
-    // up to 4 wavefronts per SIMD (128 registers each)
-    const int per_cu = std::max(1, std::min(by_lds, 16 / nw));
+  for (int nw = std::min(lo, hi); nw <= hi; ++nw) {
+    const int per_cu = std::max(1, std::min(by_lds, waves_cu / nw));
     const int64_t slots = (int64_t)per_cu * num_cu;
     const int64_t tiles = (nblk + nw - 1) / nw;
     const int64_t rounds = (tiles + slots - 1) / slots;
@@ -955,7 +993,8 @@ Sk32Shape sk32_shape(int64_t n, int64_t d, int m, int num_cu, bool bf) {
   // split-K over rows of A for the second pass: one resident workgroup per CU
   // (the accumulators of 32 columns x 16 NB per wavefront), S slices so that
   // the j tiles x slices fill the device once
-  const int jt = (int)((d + 32 * kSk2W - 1) / (32 * kSk2W));
+  const int jcols = 16 * kSk2W * sk2_col_blocks(s.NB);
+  const int jt = (int)((d + jcols - 1) / jcols);
   s.S = std::max(1, std::min<int>((int)((n + 255) / 256), num_cu / jt));
   s.slice = (n + s.S - 1) / s.S;
   s.slice = (s.slice + kBK - 1) / kBK * kBK;
