@@ -217,62 +217,89 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// x from lane l of the wavefront (l wave-uniform)
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+// e-th tile (I, J), I <= J, of the upper triangle of an n x n grid of tiles,
+// row-major
+__device__ __forceinline__ void upper_tile(int e, int n, int* I, int* J) {
+  int a = 0;
+  while (e >= n - a) {
+    e -= n - a;
+    ++a;
+  }
+  *I = a;
+  *J = a + e;
+}
+
 // Upper Cholesky factor C (C^T C = M) in place, row-major with leading
 // dimension ld; only the upper triangle of M is read, and the strict lower
 // triangle receives C^T (M[j][i] = C[i][j]), so that column l of C is
-// contiguous in row l.  One workgroup of 1024 threads, right-looking by
+// contiguous in row l.  One workgroup of 512 threads, right-looking by
 // blocks of kCB rows, four barriers per block: the diagonal block is factored
-// in LDS by one wavefront, the block row of C is formed by forward
-// substitution against it (one thread per column, all columns at once), and
-// the trailing upper triangle takes the rank-kCB update.  *fail = 1 on a
-// non-positive or non-finite pivot.
+// in the registers of the first wavefront (lane j holds column j; the entries
+// C[i][p] of the rank-1 updates are read from their lanes), the block row of
+// C is formed by forward substitution against it (one thread per column, all
+// columns at once), and the trailing upper triangle takes the rank-kCB update
+// as 16 x 16 tiles on the FP64 matrix cores.  *fail = 1 on a non-positive or
+// non-finite pivot.
 constexpr int kCB = 32;
 constexpr int kCholOneWg = 256;
+constexpr int kCholT = 512;   // threads of k_chol_upper
 
-__global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int r, int ld,
+__global__ __launch_bounds__(kCholT) void k_chol_upper(double* __restrict__ M, int r, int ld,
                                                      int* __restrict__ fail) {
   __shared__ double C[kCB][kCB + 1];
   __shared__ double P[kCB][kCholOneWg + 1];
   __shared__ double rdiag[kCB];
   __shared__ int bad;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid == 0) bad = 0;
   for (int kb = 0; kb < r; kb += kCB) {
     const int b = (r - kb < kCB) ? r - kb : kCB;
     const int nrest = r - kb - b;
-    for (int e = tid; e < b * b; e += 1024) {
+    for (int e = tid; e < b * b; e += kCholT) {
       const int i = e / b, j = e % b;
       C[i][j] = (j >= i) ? M[(int64_t)(kb + i) * ld + kb + j] : 0.0;
     }
     __syncthreads();
     if (tid < 64) {
-      // the diagonal block by the first wavefront: lane pair (q, half) owns
-      // column q's rows p = half, half + 2, ... of the trailing update
-      const int q = lane >> 1, half = lane & 1;
-      for (int i = 0; i < b; ++i) {
-        const double dii = C[i][i];
-        if (!(dii > 0.0) || !isfinite(dii)) {
-          if (lane == 0) bad = 1;
-          break;
-        }
+      // lane j (mod 32) holds column j, padded to 32 x 32 with the identity
+      // beyond b; entries below the diagonal are carried but never read
+      const int j = lane & (kCB - 1);
+      double col[kCB];
+#pragma unroll
+      for (int p = 0; p < kCB; ++p)
+        col[p] = (p < b && j < b && p <= j) ? C[p][j] : (p == j ? 1.0 : 0.0);
+      bool ok = true;
+      double rj = 1.0;
+#pragma unroll
+      for (int i = 0; i < kCB; ++i) {
+        const double dii = readlane_f64(col[i], i);
+        ok = ok && (dii > 0.0) && isfinite(dii);
         double piv, rinv;
         chol_pivot(dii, &piv, &rinv);
-        const double ciq = (q > i && q < b) ? C[i][q] * rinv : 0.0;
-        wave_lds_sync();
-        if (q > i && q < b && half == 0) C[i][q] = ciq;
-        if (lane == 0) {
-          C[i][i] = piv;
-          rdiag[i] = rinv;
-        }
-        wave_lds_sync();
-        if (q > i && q < b)
-          for (int p = i + 1 + half; p <= q; p += 2) C[p][q] = fma(-C[i][p], ciq, C[p][q]);
-        wave_lds_sync();
+        col[i] = (j == i) ? piv : col[i] * rinv;
+        if (j == i) rj = rinv;
+#pragma unroll
+        for (int p = 0; p < kCB; ++p)
+          if (p > i) col[p] = fma(-readlane_f64(col[i], p), col[i], col[p]);
       }
+      if (lane < b) {
+#pragma unroll
+        for (int p = 0; p < kCB; ++p)
+          if (p <= j) C[p][j] = col[p];
+        rdiag[j] = rj;
+      }
+      if (!ok && lane == 0) bad = 1;
     }
     __syncthreads();
     if (bad) break;
-    for (int e = tid; e < b * b; e += 1024) {
+    for (int e = tid; e < b * b; e += kCholT) {
       const int i = e / b, j = e % b;
       if (j >= i) {
         M[(int64_t)(kb + i) * ld + kb + j] = C[i][j];
@@ -299,14 +326,34 @@ __global__ __launch_bounds__(1024) void k_chol_upper(double* __restrict__ M, int
       }
     }
     __syncthreads();
-    // trailing upper triangle: M[p][q] -= sum_i X[i][p] X[i][q], p <= q
-    const int64_t nt = (int64_t)nrest * nrest;
-    for (int64_t e = tid; e < nt; e += 1024) {
-      const int pp = (int)(e / nrest), qq = (int)(e % nrest);
-      if (qq < pp) continue;
-      double sacc = 0.0;
-      for (int i = 0; i < b; ++i) sacc = fma(P[i][pp], P[i][qq], sacc);
-      M[(int64_t)(kb + b + pp) * ld + kb + b + qq] -= sacc;
+    // trailing upper triangle: M[p][q] -= sum_i X[i][p] X[i][q], p <= q, by
+    // 16 x 16 tiles (FP64 MFMA 16x16x4: lane (fk, fi) supplies X[k0 + fk][.. + fi]
+    // of both operands and holds rows fk + 4 v of column fi).  nrest > 0
+    // implies b = kCB.  Columns of P at or beyond nrest hold stale values;
+    // they only reach outputs outside the trailing block, which are not
+    // written.  Diagonal tiles also write their lower half, which the lower
+    // triangle's C^T entries of later blocks overwrite.
+    if (nrest > 0) {
+      const int nt = (nrest + 15) >> 4;
+      const int fi = lane & 15, fk = lane >> 4;
+      for (int u = wv; u < nt * (nt + 1) / 2; u += kCholT / 64) {
+        int I, J;
+        upper_tile(u, nt, &I, &J);
+        d4 acc = (d4)0.0;
+#pragma unroll
+        for (int k0 = 0; k0 < kCB; k0 += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[k0 + fk][16 * I + fi],
+                                                     P[k0 + fk][16 * J + fi], acc, 0, 0, 0);
+        const int qq = 16 * J + fi;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int pp = 16 * I + fk + 4 * v;
+          if (pp < nrest && qq < nrest) {
+            double* m = M + (int64_t)(kb + b + pp) * ld + kb + b + qq;
+            *m -= acc[v];
+          }
+        }
+      }
     }
     __syncthreads();
   }
@@ -736,6 +783,40 @@ __device__ __forceinline__ void upd_q(double (&Q)[kJP][kJP + 1], const double2* 
 }
 static_assert(kJP * kJB == 2 * kJT, "two (row, rotation) pairs per thread");
 
+// The same over the threads t = 0 .. 191 of wavefronts 1-3 (pairs t, t + 192,
+// t + 384): every load of the step is issued before the first store (the
+// pairs touch disjoint entries of Q).
+constexpr int kJQT = kJT - 64;
+constexpr int kJQN = (kJP * kJB + kJQT - 1) / kJQT;
+__device__ __forceinline__ void upd_q_cross(double (&Q)[kJP][kJP + 1], const double2* C, int st,
+                                            int t) {
+  double2 r[kJQN];
+  double qp[kJQN], qv[kJQN];
+  int row[kJQN], pp[kJQN], qq[kJQN];
+#pragma unroll
+  for (int h = 0; h < kJQN; ++h) {
+    const int e = t + kJQT * h;
+    const int k = e & (kJB - 1);
+    row[h] = e >> 4;
+    step_pair<false>(k, st, &pp[h], &qq[h]);
+    r[h] = (e < kJP * kJB) ? C[k] : make_double2(1.0, 0.0);
+  }
+#pragma unroll
+  for (int h = 0; h < kJQN; ++h) {
+    if (r[h].y != 0.0) {
+      qp[h] = Q[row[h]][pp[h]];
+      qv[h] = Q[row[h]][qq[h]];
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < kJQN; ++h) {
+    if (r[h].y != 0.0) {
+      Q[row[h]][pp[h]] = r[h].x * qp[h] - r[h].y * qv[h];
+      Q[row[h]][qq[h]] = r[h].y * qp[h] + r[h].x * qv[h];
+    }
+  }
+}
+
 // e-th upper 2x2 block (ka <= kb), row-major over the upper triangle
 __device__ __forceinline__ void upper_block(int e, int* ka, int* kb) {
   int a = 0;
@@ -894,33 +975,44 @@ __device__ __forceinline__ void form_pair(const double* __restrict__ Hin,
     F.M[1][i][c] = Qprev[(int64_t)P[1] * kJP * kJP + i * kJP + kJB * hf[1] + c];
   }
   __syncthreads();
-  // X0 = T0 M1, X1 = T1 M2, X2 = T2 M2: 3 x 512 outputs, 6 per thread
+  // FP64 MFMA 16x16x4: lane (fk, fi) = (lane >> 4, lane & 15) supplies
+  // A(fi, k0 + fk) and B(k0 + fk, fi) and holds D(fk + 4 v, fi) in acc[v].
+  // X0 = T0 M1, X1 = T1 M2, X2 = T2 M2: six 16 x 16 tiles (matrix tt >> 1,
+  // row half tt & 1), K = 32; wavefronts 0, 1 take two, 2, 3 one.
+  const int lane = tid & 63, wv = tid >> 6;
+  const int fi = lane & 15, fk = lane >> 4;
+  for (int tt = wv; tt < 6; tt += 4) {
+    const int which = tt >> 1, rh = tt & 1, mi = which == 0 ? 0 : 1;
+    d4 acc = (d4)0.0;
 #pragma unroll
-  for (int h = 0; h < 6; ++h) {
-    const int e = tid + h * kJT;
-    const int which = e >> 9, i = (e >> 4) & 31, c = e & 15;
-    const int mi = which == 0 ? 0 : 1;
-    double s = 0.0;
-#pragma unroll 8
-    for (int l = 0; l < kJP; ++l) s = fma(F.T[which][i][l], F.M[mi][l][c], s);
-    F.X[which][i][c] = s;
+    for (int k0 = 0; k0 < kJP; k0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(F.T[which][kJB * rh + fi][k0 + fk],
+                                                 F.M[mi][k0 + fk][fi], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) F.X[which][kJB * rh + fk + 4 * v][fi] = acc[v];
   }
   __syncthreads();
-  // S_aa = M1^T X0, S_bb = M2^T X1, S_ab = M1^T X2: 3 x 256 outputs
+  // S_aa = M1^T X0, S_bb = M2^T X1, S_ab = M1^T X2: one 16 x 16 tile per
+  // wavefront 0..2
+  if (wv < 3) {
+    const int h = wv, mi = h == 1 ? 1 : 0;
+    d4 acc = (d4)0.0;
 #pragma unroll
-  for (int h = 0; h < 3; ++h) {
-    const int i = tid >> 4, j = tid & 15;
-    const int mi = h == 1 ? 1 : 0;
-    double s = 0.0;
-#pragma unroll 8
-    for (int l = 0; l < kJP; ++l) s = fma(F.M[mi][l][i], F.X[h][l][j], s);
-    if (h == 0) {
-      if (i <= j) { S[i][j] = s; S[j][i] = s; }
-    } else if (h == 1) {
-      if (i <= j) { S[kJB + i][kJB + j] = s; S[kJB + j][kJB + i] = s; }
-    } else {
-      S[i][kJB + j] = s;
-      S[kJB + j][i] = s;
+    for (int k0 = 0; k0 < kJP; k0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(F.M[mi][k0 + fk][fi], F.X[h][k0 + fk][fi], acc,
+                                                 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = fk + 4 * v, j = fi;
+      const double sv = acc[v];
+      if (h == 0) {
+        if (i <= j) { S[i][j] = sv; S[j][i] = sv; }
+      } else if (h == 1) {
+        if (i <= j) { S[kJB + i][kJB + j] = sv; S[kJB + j][kJB + i] = sv; }
+      } else {
+        S[i][kJB + j] = sv;
+        S[kJB + j][i] = sv;
+      }
     }
   }
 }
@@ -935,7 +1027,9 @@ __device__ __forceinline__ void form_pair(const double* __restrict__ Hin,
 // their rotation and the block (k, k + 1) (lane 15: (0, 15)); after applying
 // the step they hold every entry that the next step's rotation k needs
 // (a_kk, a_kq and, from lane k + 1, a_qq), so the next rotation is formed
-// before the barrier and a step takes one barrier.
+// before the barrier and a step takes one barrier.  The other 104 blocks and
+// the columns of Q are updated by wavefronts 1-3, so the rotation lanes'
+// chain (block update, next rotation) is the only work of wavefront 0.
 template <bool FIRST>
 __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__ Hin,
                                                       double* __restrict__ Hout,
@@ -1038,10 +1132,12 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
         apq = (k < kJB - 1) ? x01 : x10;
         cs[(st + 1) & 1][k] = jac_rotation(apq, app, aqq, tol, floor_abs, &rotated);
       }
-    } else if (oblk) {
-      upd_block<false>(S, C, st, oka, okb);
+    } else if (tid >= 64) {
+      // wavefronts 1-3: the other blocks, then Q (wavefront 0 carries the
+      // rotation lanes' dependent chain alone)
+      if (oblk) upd_block<false>(S, C, st, oka, okb);
+      upd_q_cross(Q, C, st, tid - 64);
     }
-    upd_q<false>(Q, C, st, tid);
     __syncthreads();
   }
   double* Qo = Qcur + (int64_t)blockIdx.x * kJP * kJP;
@@ -1198,7 +1294,7 @@ nys_status gemm64(hipStream_t st, int M, int N, int K, const void* A, bool a_f32
 nys_status chol_upper(hipStream_t st, double* M, int r, int ld, int* fail) {
   if (r > 1024) return NYS_ERR_INVALID;
   if (r <= kCholOneWg) {
-    hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, st, M, r, ld, fail);
+    hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(kCholT), 0, st, M, r, ld, fail);
     return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
   }
   // blocked right-looking form for larger r: per block row, the diagonal

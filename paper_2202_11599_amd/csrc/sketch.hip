@@ -725,30 +725,50 @@ double eps_of(double x, int mbits) {
   return std::ldexp(1.0, e - 1 - mbits);
 }
 
-// Thin QR of the Gaussian block by CholeskyQR2 (two passes of Gram ->
-// Cholesky -> Q = X R^-1), in place on Om (d x m, column-major).
-// tmp: d x m scratch (w.Bm when NULL)
+// Thin QR of a block by CholeskyQR (Gram -> Cholesky -> Q = X R^-1), in
+// place on Om (d x m, column-major).  After each pass the Gram of the result
+// is formed and max |Q^T Q - I| read back; a second pass runs only when it
+// exceeds 1e-14 m.  A Gaussian block with d well above m has condition number
+// near (1 + sqrt(m/d)) / (1 - sqrt(m/d)) (below 3 for d >= 4m), so one pass
+// leaves Q orthonormal to about 1e-15 and the second pass (CholeskyQR2) is
+// needed only for nearly square or ill-conditioned blocks.  The Nystrom
+// approximation depends on range(Omega) only; the shifted core uses the
+// computed Omega^T Omega, not the identity.  *err_out (optional): the final
+// max |Q^T Q - I|.  tmp: d x m scratch (w.Bm when NULL)
 nys_status orthonormalize(nys_ctx ctx, double* Om, int64_t d, int m, const CoreWs& w,
-                          double* tmp = nullptr) {
+                          double* tmp = nullptr, double* err_out = nullptr) {
   hipStream_t st = ctx->stream;
   if (tmp == nullptr) tmp = w.Bm;
-  // one failure flag for both passes, read once at the end: after a failed
-  // factorisation the remaining kernels run on meaningless values (their
-  // indexing does not depend on them) and the result is discarded
+  // the Cholesky failure flag in ints[0] (never reset between the passes:
+  // after a failed factorisation the remaining kernels run on meaningless
+  // values, their indexing does not depend on them, and the result is
+  // discarded) and the orthogonality error as a double at ints[2..3], read
+  // back together
+  double* err_dev = reinterpret_cast<double*>(w.ints + 2);
   NYS_TRY_HIP(hipMemsetAsync(w.ints, 0, sizeof(int), st));
+  NYS_TRY(gemm64(st, m, m, (int)d, Om, false, d, 1, Om, false, 1, d, w.M, m, 1, 1.0, 0.0,
+                 w.split, w.split_elems));
+  double err = 0.0;
   for (int pass = 0; pass < 2; ++pass) {
-    NYS_TRY(gemm64(st, m, m, (int)d, Om, false, d, 1, Om, false, 1, d, w.M, m, 1, 1.0, 0.0,
-                   w.split, w.split_elems));
     NYS_TRY(chol_upper(st, w.M, m, m, w.ints));
     NYS_TRY(trinv_upper(st, w.M, m, m, w.Cinv, m));
     // Bm = Om Rinv  (d x m col-major), then copy back
     NYS_TRY(gemm64(st, (int)d, m, m, Om, false, 1, d, w.Cinv, false, m, 1, tmp, 1, d, 1.0, 0.0,
                    w.split, w.split_elems));
     NYS_TRY_HIP(hipMemcpyAsync(Om, tmp, sizeof(double) * d * m, hipMemcpyDeviceToDevice, st));
+    // Q^T Q: the acceptance test, and the next pass's Gram
+    NYS_TRY(gemm64(st, m, m, (int)d, Om, false, d, 1, Om, false, 1, d, w.M, m, 1, 1.0, 0.0,
+                   w.split, w.split_elems));
+    hipLaunchKernelGGL(k_orth_err, dim3(1), dim3(1024), 0, st, w.M, m, err_dev);
+    unsigned char hb[16];
+    NYS_TRY(read_back(ctx, w.ints, sizeof(hb), hb));
+    int fail = 0;
+    std::memcpy(&fail, hb, sizeof(int));
+    std::memcpy(&err, hb + 8, sizeof(double));
+    if (fail) return NYS_ERR_NOT_SPD;   // block without full column rank
+    if (err <= 1e-14 * m) break;
   }
-  int fail = 0;
-  NYS_TRY(read_back(ctx, w.ints, sizeof(int), &fail));
-  if (fail) return NYS_ERR_NOT_SPD;   // Gaussian block without full column rank
+  if (err_out) *err_out = err;
   return NYS_OK;
 }
 
@@ -836,17 +856,11 @@ nys_status nys_core(nys_ctx ctx, nys_factor F, double test_mu, int* above) {
     double* Vb = w.GO;   // r x r column-major (free after the shifted Cholesky)
     NYS_TRY(gemm64(st, r, r, (int)d, w.Bm, false, d, 1, F->basis_hint, false, 1, d, Vb, 1, r,
                    1.0, 0.0, w.split, w.split_elems));
-    nys_status so = orthonormalize(ctx, Vb, r, r, w, w.W);
-    if (so == NYS_OK) {
-      // CholeskyQR2 is exact to rounding only for a well-conditioned V0:
-      // accept the basis when max |V0^T V0 - I| <= 1e-13 r
-      NYS_TRY(gemm64(st, r, r, r, Vb, false, r, 1, Vb, false, 1, r, w.GY, r, 1, 1.0, 0.0,
-                     w.split, w.split_elems));
-      hipLaunchKernelGGL(k_orth_err, dim3(1), dim3(1024), 0, st, w.GY, r, w.scal + 8);
-      double err = 0.0;
-      NYS_TRY(read_back(ctx, w.scal + 8, sizeof(double), &err));
-      if (!(err <= 1e-13 * r)) so = NYS_ERR_NOT_SPD;
-    }
+    double err = 0.0;
+    nys_status so = orthonormalize(ctx, Vb, r, r, w, w.W, &err);
+    // CholeskyQR is exact to rounding only for a well-conditioned V0:
+    // accept the basis when max |V0^T V0 - I| <= 1e-13 r
+    if (so == NYS_OK && !(err <= 1e-13 * r)) so = NYS_ERR_NOT_SPD;
     if (so == NYS_OK) {
       // G' = V0^T (G V0): T1 (column-major) in GY, G' (row-major) in M
       NYS_TRY(gemm64(st, r, r, r, w.G, false, r, 1, Vb, false, 1, r, w.GY, 1, r, 1.0, 0.0,
