@@ -341,9 +341,11 @@ struct nys_sparse_s {
   nys::DevBuf s;                 // the n-vector s = f(A p) between the two passes
   // columns binned by length for the A^T pass: short ones (<= kShortCol
   // entries) by groups of 8 lanes, medium ones by a wavefront, long ones
-  // (> kLongCol) by a workgroup; cols holds the three lists back to back
+  // (> kLongCol) by a workgroup; bins holds the three lists of (column,
+  // begin, end) triples back to back (d slots each), then their lengths
   nys::DevBuf bins;
   int nshort = 0, nmed = 0, nlong = 0;
+  int num_cu = 256;              // CUs of the device (row-pass grid)
 };
 
 struct nys_factor_s {

@@ -27,15 +27,17 @@ constexpr int kLongCol = 2048; // columns with more: a 256-thread workgroup each
 
 // Column j goes to list 0 (short), 1 (medium) or 2 (long), each list in
 // increasing column order (so a pass over a list reads the CSC arrays in
-// storage order); counts[3] are the list lengths.  One workgroup: thread t
-// counts its contiguous range of columns per class, the counts are
-// prefix-summed, and each thread places its range in order.
+// storage order) as the triple (j, colptr[j], colptr[j + 1]), so that the
+// column pass finds a column's range with one load; counts[3] are the list
+// lengths.  One workgroup: thread t counts its contiguous range of columns
+// per class, the counts are prefix-summed, and each thread places its range
+// in order.
 __device__ __forceinline__ int col_class(const int* __restrict__ colptr, int64_t j) {
   const int len = colptr[j + 1] - colptr[j];
   return len <= kShortCol ? 0 : (len <= kLongCol ? 1 : 2);
 }
 __global__ __launch_bounds__(1024) void k_bin_cols(const int* __restrict__ colptr, int64_t d,
-                                                   int* __restrict__ lists,
+                                                   int4* __restrict__ lists,
                                                    int* __restrict__ counts) {
   __shared__ int part[3][1024];
   const int t = threadIdx.x;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(1024) void k_bin_cols(const int* __restrict__ colpt
   int pos[3] = {part[0][t], part[1][t], part[2][t]};
   for (int64_t j = j0; j < j1; ++j) {
     const int b = col_class(colptr, j);
-    lists[(int64_t)b * d + pos[b]++] = (int)j;
+    lists[(int64_t)b * d + pos[b]++] = make_int4((int)j, colptr[j], colptr[j + 1], 0);
   }
 }
 
@@ -151,75 +153,79 @@ __global__ __launch_bounds__(64) void k_tr_fill(const int* __restrict__ rowptr,
   }
 }
 
-// sum over k = k0, k0 + step, ... (below k1) of v[k] x[idx[k]]: eight terms
+// sum over k = k0, k0 + step, ... (below k1) of v[k] x[idx[k]]: four terms
 // in flight per lane (their index and value loads issued together, then the
-// eight gathers), eight running sums combined in a fixed order, then the
-// remaining terms four and one at a time
+// four gathers), four running sums combined in a fixed order, then the
+// remaining terms one at a time.  x[i] is read from xl (LDS) for i < head.
+// (Eight or more terms in flight per lane measured slower at the E2006.train
+// shape: the extra registers cost more occupancy than the longer batches
+// save.)
 __device__ __forceinline__ double gather_dot(const int* __restrict__ idx,
                                              const float* __restrict__ v,
-                                             const double* __restrict__ x, int64_t k0, int64_t k1,
-                                             int step) {
-  double a[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) a[u] = 0.0;
+                                             const double* __restrict__ x, const double* xl,
+                                             int head, int64_t k0, int64_t k1, int step) {
+  auto X = [&](int i) { return i < head ? xl[i] : x[i]; };
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int64_t k = k0;
-  for (; k + 7 * step < k1; k += 8 * step) {
-    int ii[8];
-    float vv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      ii[u] = idx[k + u * step];
-      vv[u] = v[k + u * step];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = fma((double)vv[u], x[ii[u]], a[u]);
-  }
   for (; k + 3 * step < k1; k += 4 * step) {
     const int i0 = idx[k], i1 = idx[k + step], i2 = idx[k + 2 * step], i3 = idx[k + 3 * step];
     const float v0 = v[k], v1 = v[k + step], v2 = v[k + 2 * step], v3 = v[k + 3 * step];
-    a[0] = fma((double)v0, x[i0], a[0]);
-    a[1] = fma((double)v1, x[i1], a[1]);
-    a[2] = fma((double)v2, x[i2], a[2]);
-    a[3] = fma((double)v3, x[i3], a[3]);
+    a0 = fma((double)v0, X(i0), a0);
+    a1 = fma((double)v1, X(i1), a1);
+    a2 = fma((double)v2, X(i2), a2);
+    a3 = fma((double)v3, X(i3), a3);
   }
-  for (; k < k1; k += step) a[0] = fma((double)v[k], x[idx[k]], a[0]);
-  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  for (; k < k1; k += step) a0 = fma((double)v[k], X(idx[k]), a0);
+  return (a0 + a1) + (a2 + a3);
 }
 
 // Row pass: t_i = A_i p (one wavefront per row), s_i = f_mode(t_i) into s,
-// per-workgroup sum of the mode's q term into qpart.
-__global__ __launch_bounds__(256) void k_csr_pass(const int* __restrict__ rowptr,
-                                                  const int* __restrict__ col,
-                                                  const float* __restrict__ val, int64_t n,
-                                                  int mode, const double* __restrict__ p,
-                                                  const double* __restrict__ aux,
-                                                  double* __restrict__ auxout,
-                                                  double* __restrict__ s,
-                                                  double* __restrict__ qpart,
-                                                  const int* __restrict__ done,
-                                                  PcgDev* __restrict__ note, int note_seq) {
+// per-workgroup sum of the mode's q term into qpart.  Persistent workgroups
+// of 1024 threads (one per CU): the first kCsrHead entries of p are staged in
+// LDS, where the gathers of the popular (low-index) columns of bag-of-words
+// data land, and wavefront w of workgroup g takes rows g * 16 + w, then
+// every 16 * gridDim.x rows on; its q terms are added in row order, the 16
+// wavefronts' sums in wavefront order.
+constexpr int kCsrT = 1024;
+constexpr int kCsrHead = 16384;
+__global__ __launch_bounds__(kCsrT) void k_csr_pass(const int* __restrict__ rowptr,
+                                                    const int* __restrict__ col,
+                                                    const float* __restrict__ val, int64_t n,
+                                                    int64_t d, int mode,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ aux,
+                                                    double* __restrict__ auxout,
+                                                    double* __restrict__ s,
+                                                    double* __restrict__ qpart,
+                                                    const int* __restrict__ done,
+                                                    PcgDev* __restrict__ note, int note_seq) {
   publish_state(done, note, note_seq);
   if (done != nullptr && *done) return;
-  __shared__ double qs[4];
+  __shared__ double pl[kCsrHead];
+  __shared__ double qs[kCsrT / 64];
+  const int head = (mode == kModeTOnly) ? 0 : (int)(d < kCsrHead ? d : kCsrHead);
+  for (int i = threadIdx.x; i < head; i += kCsrT) pl[i] = p[i];
+  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   double q = 0.0;
-  if (i < n) {
+  const int64_t stride = (int64_t)gridDim.x * (kCsrT / 64);
+  for (int64_t i = (int64_t)blockIdx.x * (kCsrT / 64) + wv; i < n; i += stride) {
     double acc = 0.0;
-    if (mode != kModeTOnly) acc = gather_dot(col, val, p, rowptr[i] + lane, rowptr[i + 1], 64);
+    if (mode != kModeTOnly) acc = gather_dot(col, val, p, pl, head, rowptr[i] + lane,
+                                             rowptr[i + 1], 64);
     const double t = wave_sum(acc);
     if (lane == 0) {
-      double si = 0.0;
+      double si = 0.0, qi = 0.0;
       if (mode == kModeHess) {
         si = (aux != nullptr ? aux[i] : 1.0) * t;
-        q = si * t;
+        qi = si * t;
       } else if (mode == kModeLsGrad) {
         si = t - aux[i];
-        q = si * si;
+        qi = si * si;
       } else if (mode == kModeLogit || mode == kModeLogGrad) {
         const double bi = aux[i];
         const double sg = sigm(t);
-        q = log1p(exp(-fabs(t))) + fmax(t, 0.0) - bi * t;
+        qi = log1p(exp(-fabs(t))) + fmax(t, 0.0) - bi * t;
         if (mode == kModeLogit) {
           const double w = sg * sigm(-t);
           si = w * t + bi - sg;
@@ -231,23 +237,27 @@ __global__ __launch_bounds__(256) void k_csr_pass(const int* __restrict__ rowptr
         si = aux[i];
       }
       s[i] = si;
+      q += qi;
     }
   }
   if (lane == 0) qs[wv] = q;
   __syncthreads();
-  if (threadIdx.x == 0) qpart[blockIdx.x] = ((qs[0] + qs[1]) + qs[2]) + qs[3];
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < kCsrT / 64; ++w) r += qs[w];
+    qpart[blockIdx.x] = r;
+  }
 }
 
 // Column pass: y_j = sum over column j of A_ij s_i, one launch for the three
-// column lists: workgroups [0, nlong) take one long column each (256
-// threads), the next ceil(nmed / 4) one medium column per wavefront, the
-// rest 32 short columns each (8 lanes per column).  Long columns come first
-// so that the longest work is dispatched first.  Fixed summation order per
-// column.
-__global__ __launch_bounds__(256) void k_csc_pass(const int* __restrict__ colptr,
-                                                  const int* __restrict__ rows,
+// column lists (triples (j, begin, end)): workgroups [0, nlong) take one long
+// column each (256 threads), the next ceil(nmed / 4) one medium column per
+// wavefront, the rest 32 short columns each (8 lanes per column).  Long
+// columns come first so that the longest work is dispatched first.  Fixed
+// summation order per column.
+__global__ __launch_bounds__(256) void k_csc_pass(const int* __restrict__ rows,
                                                   const float* __restrict__ cval,
-                                                  const int* __restrict__ lists, int64_t d,
+                                                  const int4* __restrict__ lists, int64_t d,
                                                   int nshort, int nmed, int nlong,
                                                   const double* __restrict__ s,
                                                   double* __restrict__ y,
@@ -257,27 +267,28 @@ __global__ __launch_bounds__(256) void k_csc_pass(const int* __restrict__ colptr
   const int gm = (nmed + 3) / 4;
   if (bid < nlong) {
     __shared__ double red[4];
-    const int j = lists[2 * d + bid];
-    double acc = gather_dot(rows, cval, s, colptr[j] + tid, colptr[j + 1], 256);
+    const int4 c = lists[2 * d + bid];
+    double acc = gather_dot(rows, cval, s, nullptr, 0, c.y + tid, c.z, 256);
     acc = wave_sum(acc);
     if (lane == 0) red[tid >> 6] = acc;
     __syncthreads();
-    if (tid == 0) y[j] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (tid == 0) y[c.x] = ((red[0] + red[1]) + red[2]) + red[3];
   } else if (bid < nlong + gm) {
     const int g = (bid - nlong) * 4 + (tid >> 6);
     if (g >= nmed) return;
-    const int j = lists[d + g];
-    double acc = gather_dot(rows, cval, s, colptr[j] + lane, colptr[j + 1], 64);
+    const int4 c = lists[d + g];
+    double acc = gather_dot(rows, cval, s, nullptr, 0, c.y + lane, c.z, 64);
     acc = wave_sum(acc);
-    if (lane == 0) y[j] = acc;
+    if (lane == 0) y[c.x] = acc;
   } else {
     const int g = (bid - nlong - gm) * 32 + (tid >> 3);
     const int sub = tid & 7;
     double acc = 0.0;
     int j = -1;
     if (g < nshort) {
-      j = lists[g];
-      acc = gather_dot(rows, cval, s, colptr[j] + sub, colptr[j + 1], 8);
+      const int4 c = lists[g];
+      j = c.x;
+      acc = gather_dot(rows, cval, s, nullptr, 0, c.y + sub, c.z, 8);
     }
     acc += __shfl_xor(acc, 4, 8);
     acc += __shfl_xor(acc, 2, 8);
@@ -399,9 +410,11 @@ inline unsigned nb256(int64_t x) { return (unsigned)((x + 255) / 256); }
 GramPlan make_sparse_plan(const nys_sparse_s* S) {
   GramPlan pl;
   pl.sparse = S;
-  pl.grid = (int)std::max<int64_t>(1, (S->n + 3) / 4);   // row-pass workgroups (q partials)
+  // row-pass workgroups (q partials): one per CU, fewer for small n
+  pl.grid = (int)std::max<int64_t>(
+      1, std::min<int64_t>(std::max(S->num_cu, 1), (S->n + kCsrT / 64 - 1) / (kCsrT / 64)));
   pl.ldy = (int)((S->d + 63) / 64 * 64);
-  pl.rows_per_wg = 4;
+  pl.rows_per_wg = kCsrT / 64;
   return pl;
 }
 
@@ -413,18 +426,18 @@ nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& pl, int mod
   double* s = S->s.as<double>();
   if (ev0 != nullptr) NYS_TRY_HIP(hipEventRecord(ev0, st));
   if (S->n > 0)
-    hipLaunchKernelGGL(k_csr_pass, dim3(pl.grid), dim3(256), 0, st, S->rowptr, S->colidx, S->val,
-                       S->n, mode, p, aux, auxout, s, qpart, done, note, note_seq);
+    hipLaunchKernelGGL(k_csr_pass, dim3(pl.grid), dim3(kCsrT), 0, st, S->rowptr, S->colidx,
+                       S->val, S->n, S->d, mode, p, aux, auxout, s, qpart, done, note, note_seq);
   else {
     NYS_TRY_HIP(hipMemsetAsync(qpart, 0, sizeof(double), st));
     if (note != nullptr)
       NYS_TRY(launch_note(reinterpret_cast<const PcgDev*>(done), note, note_seq, st));
   }
-  const int* lists = S->bins.as<int>();
+  const int4* lists = S->bins.as<int4>();
   const int64_t gcsc = (int64_t)S->nlong + (S->nmed + 3) / 4 + (S->nshort + 31) / 32;
   if (gcsc > 0)
-    hipLaunchKernelGGL(k_csc_pass, dim3((unsigned)gcsc), dim3(256), 0, st, S->colptr(), S->rows(),
-                       S->cvals(), lists, S->d, S->nshort, S->nmed, S->nlong, s, ypart, done);
+    hipLaunchKernelGGL(k_csc_pass, dim3((unsigned)gcsc), dim3(256), 0, st, S->rows(), S->cvals(),
+                       lists, S->d, S->nshort, S->nmed, S->nlong, s, ypart, done);
   if (ev1 != nullptr) NYS_TRY_HIP(hipEventRecord(ev1, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
@@ -462,12 +475,15 @@ nys_status sparse_sketch(const nys_sparse_s* S, const double* D, double c, const
 namespace nys {
 // device bytes nys_sparse_create holds at once (CSC copy, s vector, column
 // bins, and the transient per-block column counts)
+// the three column lists (d triples each) and their lengths
+size_t sparse_bins_bytes(int64_t d) { return sizeof(int4) * (size_t)(3 * d + 1); }
+
 size_t sparse_handle_bytes(int64_t n, int64_t d, int64_t nnz) {
   const int64_t rpb = std::max<int64_t>(1, (n + kTBlocks - 1) / kTBlocks);
   const int64_t nblk = std::max<int64_t>(1, (n + rpb - 1) / rpb);
   return (sizeof(int) * (size_t)(d + 1 + 2 * nnz) + 256) +
          sizeof(double) * (size_t)std::max<int64_t>(n, 1) +
-         sizeof(int) * ((size_t)nblk * d + 1) + sizeof(int) * (size_t)(3 * d + 3) + 4 * 256;
+         sizeof(int) * ((size_t)nblk * d + 1) + sparse_bins_bytes(d) + 4 * 256;
 }
 }  // namespace nys
 
@@ -498,6 +514,7 @@ nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, con
   S->d = d;
   S->nnz = nnz;
   S->device = ctx->device;
+  S->num_cu = ctx->num_cu;
   S->rowptr = rowptr;
   S->colidx = colidx;
   S->val = val;
@@ -541,10 +558,10 @@ nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, con
     if (hipGetLastError() != hipSuccess) s = NYS_ERR_HIP;
   }
   // column bins for the A^T pass: three lists of d slots and their lengths
-  if (s == NYS_OK) s = S->bins.reserve(sizeof(int) * (size_t)(3 * d + 3));
+  if (s == NYS_OK) s = S->bins.reserve(sparse_bins_bytes(d));
   if (s == NYS_OK) {
-    int* lists = S->bins.as<int>();
-    int* counts = lists + 3 * d;
+    int4* lists = S->bins.as<int4>();
+    int* counts = reinterpret_cast<int*>(lists + 3 * d);
     int hc[3] = {0, 0, 0};
     if (hipMemsetAsync(counts, 0, sizeof(int) * 3, st) != hipSuccess) s = NYS_ERR_HIP;
     if (s == NYS_OK) {
