@@ -327,7 +327,7 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
   ws->ypart = ctx->ypart.as<double>();
   ws->qpart = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ypart.ptr) + yb);
   const size_t nv = align_up(sizeof(double) * d);
-  const size_t cb = align_up(sizeof(double) * 1024 * kDotSlicesMax);
+  const size_t cb = align_up(sizeof(double) * kCvecDoubles);
   const size_t vb = 3 * nv + cb + align_up(sizeof(double) * kWyRing);
   NYS_TRY(ctx->vecs.reserve(vb));
   char* v = static_cast<char*>(ctx->vecs.ptr);
@@ -632,9 +632,13 @@ nys_status pcg_run(nys_ctx ctx, const nys_dense& A, const double* D, double c, d
       // earlier solve's queued iteration can never be taken for this one
       const int seq = ctx->poll_seq = (ctx->poll_seq % 1000000000) + 1;
       seqs[k % 4] = seq;
+      // large d: c, g = s o c and sum s c^2 reduced once (k_c_reduce) rather
+      // than from the slices by every workgroup of the update
+      double* gvec = ws.cvec + (size_t)1024 * kDotSlicesMax;
+      if (pre) NYS_TRY(launch_c_reduce(ws.cvec, d, r, lam, lam_s, rho, gvec, ws.st, st));
       NYS_TRY(launch_precond_update(U, u32, d, r, lam, lam_s, rho, ws.cvec, ws.w, ws.p, ws.wy, k,
                                     ws.wwpart, ws.nred, ws.pppart, ws.st, 0, st, nullptr, seq,
-                                    pre));
+                                    pre, pre ? gvec : nullptr));
       return NYS_OK;
     };
     int it = 0, consumed = 0;
@@ -938,7 +942,7 @@ nys_status nys_workspace_query(nys_ctx ctx, const nys_dense* A, int r_max, int c
   total += 2 * part + align_up(sizeof(double) * d);
   // PCG vectors and scalars, H_rho x, the argument-check flag
   const size_t nv = align_up(sizeof(double) * d);
-  total += 3 * nv + align_up(sizeof(double) * 1024 * kDotSlicesMax) +
+  total += 3 * nv + align_up(sizeof(double) * kCvecDoubles) +
            align_up(sizeof(double) * kWyRing);
   total += align_up(sizeof(PcgDev)) + 4 * align_up(sizeof(double) * (size_t)nblk(d, kRedBlock)) +
            align_up(sizeof(double) * (size_t)nblk(d, kVecBlock));

@@ -433,6 +433,9 @@ constexpr int kRedBlock = 16;    // columns per workgroup of the partial reducti
 // (all 256 lanes busy) when there are few partial rows to add
 inline int red_block(int G) { return G <= 16 ? 256 : kRedBlock; }
 constexpr int kDotSlicesMax = 64; // d-slices of the U^T w partial sums (buffer size)
+// the U^T w partials (kDotSlicesMax slices of 1024) and, after them, the
+// reduced g = s o c and sum s c^2 of the large-d path (1025 doubles)
+constexpr size_t kCvecDoubles = (size_t)1024 * (kDotSlicesMax + 2);
 // slices for dimension d: 8, or one per 4096 entries up to 64 for large d
 inline int dot_slices(int64_t d) {
   const int64_t s = (d + 4095) / 4096;
@@ -496,6 +499,11 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
                                  double lam_s, double rho, const double* cvec, const double* w,
                                  double* p, double* wy, int k, const double* wwpart, int nww,
                                  double* pppart, const PcgDev* st, int mode, hipStream_t stream,
-                                 PcgDev* host_slot = nullptr, int seq = 0, bool pre = false);
+                                 PcgDev* host_slot = nullptr, int seq = 0, bool pre = false,
+                                 const double* gpre = nullptr);
+// large d: g_i = s_i c_i (c summed from its slices) and sum_i s_i c_i^2 into
+// gout[0, r) and gout[1024], once per iteration, for launch_precond_update
+nys_status launch_c_reduce(const double* cvec, int64_t d, int r, const double* lam, double lam_s,
+                           double rho, double* gout, const PcgDev* st, hipStream_t stream);
 
 }  // namespace nys

@@ -356,9 +356,10 @@ __global__ __launch_bounds__(256) void k_precond_update(
     double rho, const double* __restrict__ cvec, const double* __restrict__ w,
     double* __restrict__ p, double* __restrict__ wy, int k, const double* __restrict__ wwpart,
     int nww, double* __restrict__ pppart, const PcgDev* __restrict__ st, int mode,
-    PcgDev* __restrict__ host_slot, int seq, int nsl, int pre) {
+    PcgDev* __restrict__ host_slot, int seq, int nsl, int pre, const double* __restrict__ gpre) {
   // host_slot (pinned host memory, may be NULL): receives the state at the end
-  // of the iteration, read by the host once the kernel has completed
+  // of the iteration, read by the host once the kernel has completed.
+  // gpre (may be NULL): g and sum s c^2 already reduced by k_c_reduce
   constexpr int VJ = kVecBlock;        // entries of y per workgroup
   constexpr int VS = 256 / VJ;         // slices of the rank index
   __shared__ double g[1024];
@@ -399,17 +400,21 @@ __global__ __launch_bounds__(256) void k_precond_update(
     }
   }
   double sc = 0.0;
-  for (int i = tid; i < r; i += 256) {
-    const double ci = slice_sum(cvec + i, nsl);   // slices in a fixed order
-    const double s = (lam_s + rho) / (lam[i] + rho) - 1.0;
-    g[i] = s * ci;
-    sc += s * ci * ci;
+  if (gpre != nullptr) {
+    for (int i = tid; i < r; i += 256) g[i] = gpre[i];
+  } else {
+    for (int i = tid; i < r; i += 256) {
+      const double ci = slice_sum(cvec + i, nsl);   // slices in a fixed order
+      const double s = (lam_s + rho) / (lam[i] + rho) - 1.0;
+      g[i] = s * ci;
+      sc += s * ci * ci;
+    }
   }
   double wy_new = 0.0;
   if (mode != 2) {
     const double ww = (pre && mode == 0) ? st->wwn : pre_sum(wwpart, nww, wv, sh4);
     __syncthreads();
-    wy_new = ww + block_sum_value(sc, sh4);
+    wy_new = ww + (gpre != nullptr ? gpre[1024] : block_sum_value(sc, sh4));
   } else {
     __syncthreads();
   }
@@ -475,6 +480,35 @@ __global__ __launch_bounds__(256) void k_precond_update(
         *host_slot = h;
       }
     }
+  }
+}
+
+// Large d: c_i from its slice partials (in slice order), g_i = s_i c_i into
+// gout[i] and sum_i s_i c_i^2 (wavefront sums, then the 16 in order) into
+// gout[1024]; one workgroup per iteration instead of the slice sums being
+// repeated by each of the d / 32 workgroups of k_precond_update.
+__global__ __launch_bounds__(1024) void k_c_reduce(const double* __restrict__ cvec, int nsl,
+                                                   int r, const double* __restrict__ lam,
+                                                   double lam_s, double rho,
+                                                   double* __restrict__ gout,
+                                                   const PcgDev* __restrict__ st) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  const int i = threadIdx.x;
+  double v = 0.0;
+  if (i < r) {
+    const double ci = slice_sum(cvec + i, nsl);
+    const double s = (lam_s + rho) / (lam[i] + rho) - 1.0;
+    gout[i] = s * ci;
+    v = s * ci * ci;
+  }
+  v = wave_sum(v);
+  if ((i & 63) == 0) sh[i >> 6] = v;
+  __syncthreads();
+  if (i == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += sh[w];
+    gout[1024] = t;
   }
 }
 
@@ -686,11 +720,19 @@ nys_status launch_precond_dot(const void* U, bool u32, int64_t d, int r, const d
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
+nys_status launch_c_reduce(const double* cvec, int64_t d, int r, const double* lam, double lam_s,
+                           double rho, double* gout, const PcgDev* st, hipStream_t stream) {
+  if (r < 0 || r > 1024) return NYS_ERR_INVALID;
+  hipLaunchKernelGGL(k_c_reduce, dim3(1), dim3(1024), 0, stream, cvec, dot_slices(d), r, lam, lam_s,
+                     rho, gout, st);
+  return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
 nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, const double* lam,
                                  double lam_s, double rho, const double* cvec, const double* w,
                                  double* p, double* wy, int k, const double* wwpart, int nww,
                                  double* pppart, const PcgDev* st, int mode, hipStream_t stream,
-                                 PcgDev* host_slot, int seq, bool pre) {
+                                 PcgDev* host_slot, int seq, bool pre, const double* gpre) {
   if (r > 1024) return NYS_ERR_INVALID;
   const int grid = nblk(d, kVecBlock);
   const int nsl = dot_slices(d);
@@ -702,7 +744,8 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
   const bool wide = r > 8 * vs && r <= 32 * vs;
   auto go = [&](auto kern, const auto* u) {
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, stream, u, d, r, lam, lam_s, rho, cvec, w,
-                       p, wy, k, wwpart, nww, pppart, st, mode, host_slot, seq, nsl, pre ? 1 : 0);
+                       p, wy, k, wwpart, nww, pppart, st, mode, host_slot, seq, nsl, pre ? 1 : 0,
+                       gpre);
   };
   if (u32) {
     const float* u = static_cast<const float*>(U);
