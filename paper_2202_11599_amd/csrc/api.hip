@@ -802,6 +802,11 @@ nys_status nys_ctx_destroy(nys_ctx ctx) {
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->pcg_ev) (void)hipEventDestroy(e);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (int k = 0; k < nys_ctx_s::kSideStreams; ++k) {
+    if (ctx->side_stream[k]) (void)hipStreamDestroy(ctx->side_stream[k]);
+    if (ctx->side_join[k]) (void)hipEventDestroy(ctx->side_join[k]);
+  }
+  if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
   delete ctx;
   return NYS_OK;
 }

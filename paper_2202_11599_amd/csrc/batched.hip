@@ -506,19 +506,56 @@ nys_status launch_bg_t(const Bucket& b, const BInst* insts, int mode, int vecsel
   return NYS_ERR_INVALID;
 }
 
-nys_status bgram(const Batch& B, int mode, int vecsel, int skip, hipStream_t st) {
-  for (const Bucket& b : B.buckets) {
-    if (b.ntiles == 0) continue;
-    if (b.f64)
-      NYS_TRY(launch_bg_t<double>(b, B.insts, mode, vecsel, skip, st));
-    else
-      NYS_TRY(launch_bg_t<float>(b, B.insts, mode, vecsel, skip, st));
+// Side streams and events of the context (created on first use, default
+// priority, non-blocking)
+nys_status side_init(nys_ctx ctx) {
+  for (int k = 0; k < nys_ctx_s::kSideStreams; ++k) {
+    if (ctx->side_stream[k] == nullptr)
+      NYS_TRY_HIP(hipStreamCreateWithFlags(&ctx->side_stream[k], hipStreamNonBlocking));
+    if (ctx->side_join[k] == nullptr)
+      NYS_TRY_HIP(hipEventCreateWithFlags(&ctx->side_join[k], hipEventDisableTiming));
+  }
+  if (ctx->side_fork == nullptr)
+    NYS_TRY_HIP(hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming));
+  return NYS_OK;
+}
+
+// The matvec pair of every bucket with tiles.  With side (the context, its
+// side streams initialised) the buckets are dealt round-robin over st and the
+// side streams, forked from st and joined back to it with events: their
+// kernels touch disjoint instances, so one bucket's tail overlaps the next
+// bucket's work, and everything after the call stays ordered on st (also
+// under graph capture, where the events become graph edges).
+nys_status bgram(const Batch& B, int mode, int vecsel, int skip, hipStream_t st,
+                 nys_ctx side = nullptr) {
+  std::vector<const Bucket*> bs;
+  for (const Bucket& b : B.buckets)
+    if (b.ntiles > 0) bs.push_back(&b);
+  auto launch = [&](const Bucket& b, hipStream_t s) {
+    return b.f64 ? launch_bg_t<double>(b, B.insts, mode, vecsel, skip, s)
+                 : launch_bg_t<float>(b, B.insts, mode, vecsel, skip, s);
+  };
+  if (side == nullptr || bs.size() <= 1) {
+    for (const Bucket* b : bs) NYS_TRY(launch(*b, st));
+    return NYS_OK;
+  }
+  const int ns = (int)std::min<size_t>(bs.size(), 1 + nys_ctx_s::kSideStreams);
+  NYS_TRY_HIP(hipEventRecord(side->side_fork, st));
+  for (int k = 1; k < ns; ++k)
+    NYS_TRY_HIP(hipStreamWaitEvent(side->side_stream[k - 1], side->side_fork, 0));
+  for (size_t i = 0; i < bs.size(); ++i) {
+    const int k = (int)(i % ns);
+    NYS_TRY(launch(*bs[i], k == 0 ? st : side->side_stream[k - 1]));
+  }
+  for (int k = 1; k < ns; ++k) {
+    NYS_TRY_HIP(hipEventRecord(side->side_join[k - 1], side->side_stream[k - 1]));
+    NYS_TRY_HIP(hipStreamWaitEvent(st, side->side_join[k - 1], 0));
   }
   return NYS_OK;
 }
 
-nys_status pcg_iteration(const Batch& B, hipStream_t st) {
-  NYS_TRY(bgram(B, kModeHess, 1, 1, st));
+nys_status pcg_iteration(nys_ctx ctx, const Batch& B, hipStream_t st) {
+  NYS_TRY(bgram(B, kModeHess, 1, 1, st, ctx));
   hipLaunchKernelGGL(k_breduce, dim3(B.n64), dim3(1024), 0, st, B.insts, B.it64, 0);
   hipLaunchKernelGGL(k_bdot, dim3(B.ndot), dim3(256), 0, st, B.insts, B.itdot, 0);
   hipLaunchKernelGGL(k_bupdate, dim3(B.n256), dim3(256), 0, st, B.insts, B.it256, 0);
@@ -526,12 +563,12 @@ nys_status pcg_iteration(const Batch& B, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
 
-nys_status bpcg_init(const Batch& B, hipStream_t st, bool carry) {
+nys_status bpcg_init(nys_ctx ctx, const Batch& B, hipStream_t st, bool carry) {
   hipLaunchKernelGGL(k_breset, dim3((B.count + 255) / 256), dim3(256), 0, st, B.insts, B.count);
   if (carry) {
     hipLaunchKernelGGL(k_breduce, dim3(B.n64), dim3(1024), 0, st, B.insts, B.it64, 4);
   } else {
-    NYS_TRY(bgram(B, kModeHess, 0, 0, st));
+    NYS_TRY(bgram(B, kModeHess, 0, 0, st, ctx));
     hipLaunchKernelGGL(k_breduce, dim3(B.n64), dim3(1024), 0, st, B.insts, B.it64, 1);
   }
   hipLaunchKernelGGL(k_bdot, dim3(B.ndot), dim3(256), 0, st, B.insts, B.itdot, 1);
@@ -840,7 +877,7 @@ nys_status batch_graph(nys_ctx ctx, Batch* B) {
   hipGraph_t g = nullptr;
   NYS_TRY_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
   nys_status s = NYS_OK;
-  for (int i = 0; i < kGraphIters && s == NYS_OK; ++i) s = pcg_iteration(*B, ctx->cap_stream);
+  for (int i = 0; i < kGraphIters && s == NYS_OK; ++i) s = pcg_iteration(ctx, *B, ctx->cap_stream);
   hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
   if (s != NYS_OK) return s;
   NYS_TRY_HIP(e);
@@ -858,7 +895,8 @@ nys_status batch_graph(nys_ctx ctx, Batch* B) {
 nys_status batch_pcg(nys_ctx ctx, Batch* B, int max_iter, std::vector<PcgDev>* states, bool carry,
                      bool check) {
   hipStream_t st = ctx->stream;
-  NYS_TRY(bpcg_init(*B, st, carry));
+  NYS_TRY(side_init(ctx));
+  NYS_TRY(bpcg_init(ctx, *B, st, carry));
   NYS_TRY(batch_graph(ctx, B));
   int done_iters = 0;
   for (;;) {
@@ -884,7 +922,7 @@ nys_status batch_pcg(nys_ctx ctx, Batch* B, int max_iter, std::vector<PcgDev>* s
       e1 = ctx->prof_ev[ctx->prof_used + 1];
       NYS_TRY_HIP(hipEventRecord(e0, st));
     }
-    NYS_TRY(bgram(*B, kModeHess, 0, 0, st));
+    NYS_TRY(bgram(*B, kModeHess, 0, 0, st, ctx));
     if (e1 != nullptr) {
       NYS_TRY_HIP(hipEventRecord(e1, st));
       ctx->prof_used += 2;

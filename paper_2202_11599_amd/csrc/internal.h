@@ -319,6 +319,13 @@ struct nys_ctx_s {
   std::map<std::string, nys::GramPlan> plans;   // autotuned launch shapes per matrix shape
   std::map<std::string, std::vector<int>> bplans;  // autotuned batched shapes per batch
   hipStream_t cap_stream = nullptr;              // graph-capture stream (batched path)
+  // batched path: streams on which the matvec pairs of the row-width buckets
+  // after the first run concurrently (forked from and joined back to the
+  // calling stream with these events)
+  static constexpr int kSideStreams = 3;
+  hipStream_t side_stream[kSideStreams] = {};
+  hipEvent_t side_fork = nullptr;
+  hipEvent_t side_join[kSideStreams] = {};
   bool prof_on = false;          // time matvec-pair launches with events
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used = 0;
