@@ -664,8 +664,18 @@ nys_status batch_build(nys_ctx ctx, int count, const nys_problem* P, const nys_a
     const int vn = A.dtype == NYS_F64 ? 2 : 4;
     const int esize = vn == 2 ? 8 : 4;
     const int aligned = ((uintptr_t)A.data % 16 == 0) && ((A.ld * esize) % 16 == 0);
-    int cls = 128 * vn;
-    while (cls < A.d) cls *= 2;
+    // classes at the column counts the launch shapes cover exactly (128 vn
+    // times 1, 1.5, 2, 3, 4, 6, ...), so that an instance leaves at most a
+    // third of a bucket's lanes idle
+    int cls = 128 * vn, lo = cls;
+    while (cls < A.d) {
+      if (cls == lo) {
+        cls = lo * 3 / 2;
+      } else {
+        lo *= 2;
+        cls = lo;
+      }
+    }
     groups[{(A.dtype == NYS_F64 ? 2 : 0) | aligned, cls}].push_back(q);
   }
   size_t tiles_total = 0;
