@@ -716,6 +716,25 @@ __device__ __forceinline__ void blk_rotate(double2 ra, double2 rb, double& x00, 
   }
 }
 
+// The same with no test: a rotation (1, 0) leaves finite entries unchanged
+// bit for bit (c x - s y = x and s x + c y = y with c = 1, s = 0), so the
+// cross steps apply every rotation without diverging on which ones are idle.
+__device__ __forceinline__ void blk_rotate_all(double2 ra, double2 rb, double& x00, double& x01,
+                                               double& x10, double& x11) {
+  {
+    const double c = ra.x, s = ra.y;
+    const double y00 = c * x00 - s * x10, y01 = c * x01 - s * x11;
+    const double y10 = s * x00 + c * x10, y11 = s * x01 + c * x11;
+    x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+  }
+  {
+    const double c = rb.x, s = rb.y;
+    const double y00 = c * x00 - s * x01, y01 = s * x00 + c * x01;
+    const double y10 = c * x10 - s * x11, y11 = s * x10 + c * x11;
+    x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+  }
+}
+
 __device__ __forceinline__ int rr16(int x, int st) { return x == 0 ? 0 : ((x - 1 + st) % 15) + 1; }
 
 // Positions p < q of rotation k (0..15) at step st of a visit.  INTRA steps:
@@ -763,6 +782,20 @@ __device__ __forceinline__ void upd_block(double (&S)[kJP][kJP + 1], const doubl
   }
 }
 
+// upd_block for a cross step's off-diagonal block (ka < kb), every rotation
+// applied (see blk_rotate_all)
+__device__ __forceinline__ void upd_block_cross(double (&S)[kJP][kJP + 1], const double2* C,
+                                                int st, int ka, int kb) {
+  const double2 ra = C[ka], rb = C[kb];
+  int p, q, p2, q2;
+  step_pair<false>(ka, st, &p, &q);
+  step_pair<false>(kb, st, &p2, &q2);
+  double x00 = S[p][p2], x01 = S[p][q2], x10 = S[q][p2], x11 = S[q][q2];
+  blk_rotate_all(ra, rb, x00, x01, x10, x11);
+  S[p][p2] = x00; S[p][q2] = x01; S[q][p2] = x10; S[q][q2] = x11;
+  S[p2][p] = x00; S[q2][p] = x01; S[p2][q] = x10; S[q2][q] = x11;
+}
+
 // Q <- Q J over the 16 rotations of the step: two (row, rotation) pairs per thread
 template <bool INTRA>
 __device__ __forceinline__ void upd_q(double (&Q)[kJP][kJP + 1], const double2* C, int st,
@@ -801,16 +834,18 @@ __device__ __forceinline__ void upd_q_cross(double (&Q)[kJP][kJP + 1], const dou
     step_pair<false>(k, st, &pp[h], &qq[h]);
     r[h] = (e < kJP * kJB) ? C[k] : make_double2(1.0, 0.0);
   }
+  // every rotation applied (see blk_rotate_all); only the pairs past the 512
+  // of the step are left out
 #pragma unroll
   for (int h = 0; h < kJQN; ++h) {
-    if (r[h].y != 0.0) {
+    if (t + kJQT * h < kJP * kJB) {
       qp[h] = Q[row[h]][pp[h]];
       qv[h] = Q[row[h]][qq[h]];
     }
   }
 #pragma unroll
   for (int h = 0; h < kJQN; ++h) {
-    if (r[h].y != 0.0) {
+    if (t + kJQT * h < kJP * kJB) {
       Q[row[h]][pp[h]] = r[h].x * qp[h] - r[h].y * qv[h];
       Q[row[h]][qq[h]] = r[h].y * qp[h] + r[h].x * qv[h];
     }
@@ -1110,21 +1145,19 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
       const int p2 = kb, q2 = kJB + ((kb + st) & (kJB - 1));
       double x00 = S[p][p2], x01 = S[p][q2], x10 = S[q][p2], x11 = S[q][q2];
       const double2 rk = C[k], ra = C[ka], rb = C[kb];
-      // the diagonal block of rotation k, from the registers
+      // the diagonal block of rotation k, from the registers; every rotation
+      // applied (see blk_rotate_all), the rotated pair's entry set to 0
       double d00 = app, d01 = apq, d10 = apq, d11 = aqq;
-      if (rk.y != 0.0) {
-        const int qk = kJB + ((k + st) & (kJB - 1));
-        blk_rotate(rk, rk, d00, d01, d10, d11);
-        S[k][k] = d00;
-        S[qk][qk] = d11;
-        S[k][qk] = 0.0;
-        S[qk][k] = 0.0;
-      }
-      if (ra.y != 0.0 || rb.y != 0.0) {
-        blk_rotate(ra, rb, x00, x01, x10, x11);
-        S[p][p2] = x00; S[p][q2] = x01; S[q][p2] = x10; S[q][q2] = x11;
-        S[p2][p] = x00; S[q2][p] = x01; S[p2][q] = x10; S[q2][q] = x11;
-      }
+      const int qk = kJB + ((k + st) & (kJB - 1));
+      blk_rotate_all(rk, rk, d00, d01, d10, d11);
+      const double dz = (rk.y != 0.0) ? 0.0 : apq;
+      S[k][k] = d00;
+      S[qk][qk] = d11;
+      S[k][qk] = dz;
+      S[qk][k] = dz;
+      blk_rotate_all(ra, rb, x00, x01, x10, x11);
+      S[p][p2] = x00; S[p][q2] = x01; S[q][p2] = x10; S[q][q2] = x11;
+      S[p2][p] = x00; S[q2][p] = x01; S[p2][q] = x10; S[q2][q] = x11;
       const double nx11 = __shfl(d11, k1, 64);
       if (st + 1 < kJB) {
         app = d00;
@@ -1135,7 +1168,7 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
     } else if (tid >= 64) {
       // wavefronts 1-3: the other blocks, then Q (wavefront 0 carries the
       // rotation lanes' dependent chain alone)
-      if (oblk) upd_block<false>(S, C, st, oka, okb);
+      if (oblk) upd_block_cross(S, C, st, oka, okb);
       upd_q_cross(Q, C, st, tid - 64);
     }
     __syncthreads();
