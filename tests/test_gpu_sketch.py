@@ -254,3 +254,23 @@ def test_sketch_fp64_large_rank_blocked_cholesky(N, ctx, r):
     # U = B V Sigma^-1 is orthonormal to rounding: ~1e-12 per entry at r = 700
     assert np.linalg.norm(U.T @ U - np.eye(r)) < 1e-11 * r
     F.close()
+
+
+@pytest.mark.parametrize("r", [1, 15, 16, 17, 31, 32, 33, 64, 65, 96, 255, 256])
+def test_sketch_fp64_ranks_at_block_edges(N, ctx, r):
+    # ranks at the edges of the Cholesky blocks (32 rows: register diagonal
+    # block, MFMA trailing tiles of 16) and of the eigensolver blocks (16,
+    # pair blocks of 32, padding to an even block count), FP64 end to end
+    n, d = 1200, 300
+    A64 = synth.decay_matrix(n, d, 0.6, seed=r)
+    om = synth.omega_raw(d, r, seed=r + 1)
+    F = N.nys_sketch(ctx, A64.to(DEV), om.to(DEV), prec=N.NYS_F64)
+    H, U, lam, inf = hhat(F, ctx)
+    f = ny.rand_nys_appx(A64.numpy(), None, 0.0, om.numpy().T)
+    e = rel(H, f.dense())
+    print(f"[sketch fp64 r={r}] rel(Hhat)={e:.3e} nu={inf['nu']:.3e}/{f.nu:.3e}", flush=True)
+    assert e < 1e-10
+    assert inf["nu"] == f.nu
+    assert np.allclose(lam, f.lam, rtol=1e-9, atol=1e-12 * f.lam[0])
+    assert np.linalg.norm(U.T @ U - np.eye(r)) < 1e-10
+    F.close()

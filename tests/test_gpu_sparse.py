@@ -166,3 +166,25 @@ def test_sparse_large_d_pcg(N, ctx):
     assert e < 1e-7
     F.close()
     S.close()
+
+
+@pytest.mark.parametrize("n,d", [(20000, 30000), (5000, 16384), (777, 16385)])
+def test_sparse_pair_persistent_rows_and_head(N, ctx, n, d):
+    # the row pass runs persistent workgroups (several rows per wavefront at
+    # n = 20000) with p[0, 16384) staged in LDS and the rest gathered from
+    # memory; d = 16384 / 16385 put the last column exactly at / past the
+    # staged head
+    import scipy.sparse as sps
+    rp, c, v32 = synth.sparse_text_like(n, d, 0.003, seed=d % 1000)
+    S = N.SparseMatrix(ctx, rp.to(DEV), c.to(DEV), v32.to(DEV), (n, d))
+    A = sps.csr_matrix((v32.double().numpy(), c.numpy(), rp.numpy()), shape=(n, d))
+    r = np.random.default_rng(2)
+    p = r.standard_normal(d)
+    D = r.random(n) + 0.1
+    v = N.nys_hessian_apply(ctx, S, torch.tensor(p, device=DEV), rho=0.7,
+                            D=torch.tensor(D, device=DEV))
+    ref = A.T @ (D * (A @ p)) + 0.7 * p
+    e = np.linalg.norm(v.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"[sparse pair persistent] {n}x{d} nnz {S.nnz} rel err {e:.2e}", flush=True)
+    assert e < 1e-12
+    S.close()
