@@ -1075,10 +1075,13 @@ __global__ __launch_bounds__(kJT) void k_jacobi_round(const double* __restrict__
                                                       const double* __restrict__ gnorm,
                                                       double tol) {
   if (jacobi_skip(counters, sweep)) return;
-  __shared__ double S[kJP][kJP + 1];
-  __shared__ double Q[kJP][kJP + 1];
+  // S and Q live in the first two T tiles of F: those are dead once the
+  // pair block is formed (and never used in round 0), which keeps the launch
+  // at 47 KB of LDS (three workgroups per CU at large r)
   __shared__ double2 cs[2][kJB];
   __shared__ PairForm F;
+  double (&S)[kJP][kJP + 1] = F.T[0];
+  double (&Q)[kJP][kJP + 1] = F.T[1];
   const int tid = threadIdx.x;
   const int nb = R / kJB;
   const int np = nb / 2;
