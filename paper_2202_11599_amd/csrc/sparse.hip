@@ -95,16 +95,31 @@ __global__ __launch_bounds__(256) void k_tr_count(const int* __restrict__ rowptr
 }
 
 // colptr[j] (exclusive) and, in place, cnt[b * d + j] <- start of block b's
-// entries of column j.  One workgroup; threads own contiguous column ranges.
-__global__ __launch_bounds__(1024) void k_tr_scan(int* __restrict__ cnt, int64_t d, int nblk,
-                                                  int* __restrict__ colptr) {
+// entries of column j, in three passes over the counts:
+//   k_tr_colsum:  per column j (one thread, coalesced over j), cnt[b * d + j]
+//                 <- the entries of blocks before b, colptr[j] <- the total;
+//   k_tr_colscan: exclusive scan of colptr[0, d) in place, colptr[d] = nnz
+//                 (one workgroup; threads own contiguous column ranges);
+//   k_tr_addbase: cnt[b * d + j] += colptr[j].
+__global__ __launch_bounds__(256) void k_tr_colsum(int* __restrict__ cnt, int64_t d, int nblk,
+                                                   int* __restrict__ colptr) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= d) return;
+  int s = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int c = cnt[(int64_t)b * d + j];
+    cnt[(int64_t)b * d + j] = s;
+    s += c;
+  }
+  colptr[j] = s;
+}
+__global__ __launch_bounds__(1024) void k_tr_colscan(int* __restrict__ colptr, int64_t d) {
   __shared__ long long part[1024];
   const int64_t per = (d + 1023) / 1024;
   const int64_t j0 = std::min<int64_t>(d, threadIdx.x * per);
   const int64_t j1 = std::min<int64_t>(d, j0 + per);
   long long s = 0;
-  for (int64_t j = j0; j < j1; ++j)
-    for (int b = 0; b < nblk; ++b) s += cnt[(int64_t)b * d + j];
+  for (int64_t j = j0; j < j1; ++j) s += colptr[j];
   part[threadIdx.x] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -114,19 +129,22 @@ __global__ __launch_bounds__(1024) void k_tr_scan(int* __restrict__ cnt, int64_t
       part[i] = acc;
       acc += v;
     }
+    colptr[d] = (int)acc;
   }
   __syncthreads();
   long long acc = part[threadIdx.x];
   for (int64_t j = j0; j < j1; ++j) {
+    const int c = colptr[j];
     colptr[j] = (int)acc;
-    for (int b = 0; b < nblk; ++b) {
-      const int c = cnt[(int64_t)b * d + j];
-      cnt[(int64_t)b * d + j] = (int)acc;
-      acc += c;
-    }
+    acc += c;
   }
-  if (j1 == d && j0 < j1) colptr[d] = (int)acc;
-  if (d == 0 && threadIdx.x == 0) colptr[0] = 0;
+}
+__global__ __launch_bounds__(256) void k_tr_addbase(int* __restrict__ cnt, int64_t d, int nblk,
+                                                    const int* __restrict__ colptr) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= d) return;
+  const int base = colptr[j];
+  for (int b = 0; b < nblk; ++b) cnt[(int64_t)b * d + j] += base;
 }
 
 // Block b places its rows in order: each lane takes distinct columns of one
@@ -550,7 +568,10 @@ nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, con
     s = check();
   }
   if (s == NYS_OK) {
-    hipLaunchKernelGGL(k_tr_scan, dim3(1), dim3(1024), 0, st, cnt.as<int>(), d, nblk,
+    hipLaunchKernelGGL(k_tr_colsum, dim3(nb256(d)), dim3(256), 0, st, cnt.as<int>(), d, nblk,
+                       S->colptr());
+    hipLaunchKernelGGL(k_tr_colscan, dim3(1), dim3(1024), 0, st, S->colptr(), d);
+    hipLaunchKernelGGL(k_tr_addbase, dim3(nb256(d)), dim3(256), 0, st, cnt.as<int>(), d, nblk,
                        S->colptr());
     if (n > 0 && nnz > 0)
       hipLaunchKernelGGL(k_tr_fill, dim3(nblk), dim3(64), 0, st, rowptr, colidx, val, n, d, rpb,
