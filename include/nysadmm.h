@@ -357,7 +357,9 @@ nys_status admm_step(nys_ctx ctx, const nys_problem* P, const nys_admm_opts* O, 
  * or take opts->factor), then iterate until max_iter or a stopping rule.
  * count > 1 with every problem least squares: the problems are solved
  * together in lockstep (batched path): one persistent matvec launch per row-
- * width bucket covers all of them, the PCG iterations run as a captured
+ * width bucket covers all of them (the buckets run concurrently on streams of
+ * the context that are forked from and joined back to its stream, so all
+ * work stays ordered on that stream), the PCG iterations run as a captured
  * hipGraph, converged instances drop out (per-instance masks).  KKT checks
  * are made at the end only in that mode.  Otherwise the problems are solved
  * one after another.  Arrays have length count. */
