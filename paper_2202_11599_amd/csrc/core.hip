@@ -879,25 +879,22 @@ __device__ __forceinline__ void other_block(int e, int* ka, int* kb) {
   }
 }
 
-// o[a][b] = sum_l X(l, ii + 16a) Y(l, jj + 16b) over l in order (the two
-// 32 x 32 operands in LDS; X read as X[l][i] when XT, else X[i][l]): each
-// thread owns a 2 x 2 block of outputs, four LDS reads per four FMAs
-static_assert(kJP == 32 && kJT == 256, "tile_mm: 16 x 16 threads, 2 x 2 outputs each");
+// The 16 x 16 tile (ti, tj) of X Y (X^T Y when XT) for 32 x 32 operands in
+// LDS on the FP64 matrix cores: lane (fk, fi) supplies X(16 ti + fi, k0 + fk)
+// and Y(k0 + fk, 16 tj + fi) and holds rows 16 ti + fk + 4 v of column
+// 16 tj + fi of the product in acc[v].  Wavefront w takes tile (w >> 1, w & 1).
+static_assert(kJP == 32 && kJT == 256, "tile_mfma: four wavefronts, one 16 x 16 tile each");
 template <bool XT>
-__device__ __forceinline__ void tile_mm(const double (&X)[kJP][kJP + 1],
-                                        const double (&Y)[kJP][kJP + 1], int ii, int jj,
-                                        double (&o)[2][2]) {
-  o[0][0] = o[0][1] = o[1][0] = o[1][1] = 0.0;
-#pragma unroll 8
-  for (int l = 0; l < kJP; ++l) {
-    const double a0 = XT ? X[l][ii] : X[ii][l];
-    const double a1 = XT ? X[l][ii + 16] : X[ii + 16][l];
-    const double b0 = Y[l][jj], b1 = Y[l][jj + 16];
-    o[0][0] = fma(a0, b0, o[0][0]);
-    o[0][1] = fma(a0, b1, o[0][1]);
-    o[1][0] = fma(a1, b0, o[1][0]);
-    o[1][1] = fma(a1, b1, o[1][1]);
+__device__ __forceinline__ d4 tile_mfma(const double (&X)[kJP][kJP + 1],
+                                        const double (&Y)[kJP][kJP + 1], int ti, int tj, int fi,
+                                        int fk) {
+  d4 acc = (d4)0.0;
+#pragma unroll
+  for (int k0 = 0; k0 < kJP; k0 += 4) {
+    const double a = XT ? X[k0 + fk][16 * ti + fi] : X[16 * ti + fi][k0 + fk];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Y[k0 + fk][16 * tj + fi], acc, 0, 0, 0);
   }
+  return acc;
 }
 
 // Update workgroup v of round t: v < np^2 forms tile (P, Q) of
@@ -910,8 +907,8 @@ __device__ __forceinline__ void jacobi_update(const double* __restrict__ Hin,
   const int tid = threadIdx.x;
   const int nb = R / kJB;
   const int np = nb / 2;
-  const int ii = tid >> 4, jj = tid & 15;
-  double o[2][2];
+  const int lane = tid & 63, wv = tid >> 6;
+  const int ti = wv >> 1, tj = wv & 1, fi = lane & 15, fk = lane >> 4;
   if (v < np * np) {
     const int P = v / np, Qi = v % np;
     int pa, pb, qa, qb;
@@ -927,25 +924,21 @@ __device__ __forceinline__ void jacobi_update(const double* __restrict__ Hin,
       W[i][j] = QQ[e];
     }
     __syncthreads();
-    tile_mm<false>(T, W, ii, jj, o);   // X = T Q_Q
+    d4 o = tile_mfma<false>(T, W, ti, tj, fi, fk);   // X = T Q_Q
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) T[ii + 16 * a][jj + 16 * b] = o[a][b];
+    for (int q = 0; q < 4; ++q) T[16 * ti + fk + 4 * q][16 * tj + fi] = o[q];
 #pragma unroll
     for (int h = 0; h < kJE; ++h) {
       const int e = tid + h * kJT;
       W[e / kJP][e % kJP] = QP[e];
     }
     __syncthreads();
-    tile_mm<true>(W, T, ii, jj, o);    // Q_P^T X
+    o = tile_mfma<true>(W, T, ti, tj, fi, fk);        // Q_P^T X
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        Hout[(int64_t)pair_index(pa, pb, ii + 16 * a) * R + pair_index(qa, qb, jj + 16 * b)] =
-            o[a][b];
+    for (int q = 0; q < 4; ++q)
+      Hout[(int64_t)pair_index(pa, pb, 16 * ti + fk + 4 * q) * R +
+           pair_index(qa, qb, 16 * tj + fi)] = o[q];
   } else {
     const int w = v - np * np;
     const int P = w % np, rc = w / np;
@@ -960,12 +953,10 @@ __device__ __forceinline__ void jacobi_update(const double* __restrict__ Hin,
       W[i][j] = QP[e];
     }
     __syncthreads();
-    tile_mm<false>(T, W, ii, jj, o);
+    const d4 o = tile_mfma<false>(T, W, ti, tj, fi, fk);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        V[(int64_t)(rc * kJP + ii + 16 * a) * R + pair_index(pa, pb, jj + 16 * b)] = o[a][b];
+    for (int q = 0; q < 4; ++q)
+      V[(int64_t)(rc * kJP + 16 * ti + fk + 4 * q) * R + pair_index(pa, pb, 16 * tj + fi)] = o[q];
   }
 }
 
