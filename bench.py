@@ -700,8 +700,9 @@ def copy_reference(torch):
 def bench_sparse(args, N, synth, torch):
     """Sparse lasso shaped like E2006.train (16087 x 150348, 0.8% nonzero):
     bag-of-words rows with Zipf column popularity, unit-norm rows; gamma =
-    0.01 ||A^T b||_inf, rho = 1e-3, rank 50 (FP64 sketch), PCG tol 1e-6; a step
-    = factor built + `admm_iters` iterations from a cold start."""
+    0.01 ||A^T b||_inf, rho = 1e-3, rank 50 (FP64 sketch products and core,
+    the preconditioner applying an FP32 copy of U), PCG tol 1e-6; a step =
+    factor built + `admm_iters` iterations from a cold start."""
     n, d, dens, r, rho, its = 16087, 150348, 0.008, 50, 1e-3, args.admm_iters
     rp, col, val, b, gamma, _ = synth.sparse_lasso(n, d, dens, seed=0, device="cuda")
     torch.cuda.synchronize()
@@ -720,10 +721,10 @@ def bench_sparse(args, N, synth, torch):
         t1 = time.perf_counter()
         for _ in range(k):
             ts = time.perf_counter()
-            F = N.nys_sketch(ctx, S, omega, prec=N.NYS_F64)
+            F = N.nys_sketch(ctx, S, omega, prec=N.NYS_F32)
             torch.cuda.synchronize()
             sk += time.perf_counter() - ts
-            o = N.admm_opts(rho, r, omega, sketch_prec=N.NYS_F64, max_iter=its,
+            o = N.admm_opts(rho, r, omega, sketch_prec=N.NYS_F32, max_iter=its,
                             pcg=N.pcg_opts(tol=1e-6, max_iter=2000), factor=F,
                             true_res_every=args.true_res_every)
             st = N.State(d, "cuda")
@@ -744,6 +745,7 @@ def bench_sparse(args, N, synth, torch):
     out = base_record(tot / wall, args.steps, args.warmup, wall, "f32", {
         "workload": f"sparse-lasso-E2006-shape-{n}x{d}-nnz{nnz}-rank{r}-{its}iters",
         "n": n, "d": d, "nnz": nnz, "rho": rho, "gamma": gamma, "rank": r, "pcg_tol": 1e-6,
+        "preconditioner_U": "fp32 copy of the FP64 factor",
         "admm_iters_per_step": its, "true_res_every": args.true_res_every})
     # CSR pass: rowptr, colidx, val, p, s; CSC pass: colptr, rows, values, s, y
     alg = 16.0 * nnz + 4.0 * (n + 1) + 4.0 * (d + 1) + 16.0 * n + 16.0 * d

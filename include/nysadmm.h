@@ -76,8 +76,9 @@ typedef struct nys_sparse_s* nys_sparse;
 /* Dense row-major matrix: element (i, j) at data + i*ld + j.
  * dtype NYS_CSR describes a sparse matrix instead: data is a nys_sparse
  * handle from nys_sparse_create, n and d its shape, ld = d; every entry point
- * that takes an A accepts it (the sketch then runs in FP64, sketch_prec
- * NYS_F64; the batched path takes dense instances only). */
+ * that takes an A accepts it (the sketch products then run in FP64; sketch_prec
+ * is NYS_F64 or NYS_F32, see nys_sketch; the batched path takes dense
+ * instances only). */
 typedef struct {
   int64_t n, d, ld;
   nys_dtype dtype;   /* NYS_F32, NYS_F64, or NYS_CSR */
@@ -157,7 +158,8 @@ nys_status nys_ctx_profile_pcg(nys_ctx ctx, long* solves, double* total_ms);
  *   Y_nu = Y + nu Omega, C = chol(Omega^T Y_nu) (upper), B = Y_nu C^-1,
  *   [U, Sigma] = svd(B), Lambda = max(0, Sigma^2 - nu).
  * eps(x) is the FP64 spacing of x (2^(floor(log2 x) - 52)) when
- * sketch_prec == NYS_F64 and the FP32 spacing (exponent - 23) otherwise.
+ * sketch_prec == NYS_F64 or A is sparse, and the FP32 spacing (exponent - 23)
+ * otherwise.
  * If the Cholesky fails, nu is multiplied by 10 and the step repeated, at most
  * 3 times, then NYS_ERR_NOT_SPD.
  *
@@ -167,6 +169,12 @@ nys_status nys_ctx_profile_pcg(nys_ctx ctx, long* solves, double* total_ms);
  *              any A dtype), NYS_F32 (A FP32, FP32 MFMA, FP32 accumulate) or
  *              NYS_BF16 (A FP32 rounded to BF16 on load, BF16 MFMA, FP32
  *              accumulate).  The core (shift, Cholesky, SVD) is always FP64.
+ *              For a sparse A (NYS_CSR) the products are FP64 sparse passes
+ *              at either NYS_F64 or NYS_F32; NYS_F32 there keeps, beside the
+ *              FP64 U, an FP32 copy of U that the preconditioner applies
+ *              (half the bytes per application; PCG itself stays FP64), and
+ *              NYS_BF16 is NYS_ERR_INVALID.  The factor's sketch_prec and
+ *              kind (dense, sparse, symmetric) are fixed by its first call.
  *  F           in/out.  *F == NULL creates a factor of rank r.  *F != NULL
  *              appends r new columns to the existing sketch (the block step of
  *              Algorithm AdaptiveRandNysAppx: only the new block is

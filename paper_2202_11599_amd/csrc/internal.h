@@ -373,6 +373,7 @@ struct nys_factor_s {
   std::vector<double> lam_host;
   bool use_u32 = false;
   bool sym = false;          // factor of an explicit symmetric H = K + c I (kernel SVM)
+  bool sparse = false;       // factor of a CSR A: FP64 products at any prec (NYS_F32 keeps U32)
   // non-owning, set only while a rebuild runs: the previous factor's U (d x r
   // FP64), whose projection starts the eigensolver near its answer
   const double* basis_hint = nullptr;

@@ -797,7 +797,7 @@ nys_status nys_core(nys_ctx ctx, nys_factor F, double test_mu, int* above) {
   // base core matrix Omega^T Y (FP64 form; also for an explicit symmetric
   // matrix) or the stored T^T D T + c Omega^T Omega
   const double* base;
-  if (F->prec == NYS_F64 || F->sym) {
+  if (F->prec == NYS_F64 || F->sym || F->sparse) {
     NYS_TRY(gemm64(st, r, r, (int)d, Om, false, d, 1, Y, false, 1, d, w.G, r, 1, 1.0, 0.0,
                    w.split, w.split_elems));
     base = w.G;
@@ -1029,7 +1029,7 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
     const int cap = std::min<int64_t>(std::max(r1, 2 * F->cap), d - 1);
     NYS_TRY(grow(F->Omega, sizeof(double) * d * r0, sizeof(double) * d * cap, st));
     NYS_TRY(grow(F->Y, sizeof(double) * d * r0, sizeof(double) * d * cap, st));
-    if (F->prec != NYS_F64) {
+    if (F->prec != NYS_F64 && !F->sparse) {
       const int64_t ldt = (n + 7) / 8 * 8;
       NYS_TRY(grow(F->T, sizeof(float) * ldt * r0, sizeof(float) * ldt * cap, st));
       // Mbase is cap x cap, row-major with ld = cap: re-pitch on growth
@@ -1153,7 +1153,7 @@ nys_status sketch_and_core(nys_ctx ctx, const nys_dense& A, const double* D, dou
                            const double* omega, int m, nys_factor F, double test_mu = -1.0,
                            int* above = nullptr) {
   NYS_TRY(sketch_block(ctx, A, D, c, omega, m, F));
-  if (F->prec != NYS_F64 && !F->sym && F->cap != F->r) {
+  if (F->prec != NYS_F64 && !F->sym && !F->sparse && F->cap != F->r) {
     // compact Mbase (cap pitch) into core order (r pitch) in gemm_ws
     nys::DevBuf& Mb = F->Mbase;
     nys::DevBuf tmp;
@@ -1179,15 +1179,20 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
   NYS_TRY(validate_dense(A));
   if (!(c >= 0.0) || r < 1) return NYS_ERR_INVALID;
   if (prec != NYS_F64 && prec != NYS_F32 && prec != NYS_BF16) return NYS_ERR_INVALID;
-  if (prec != NYS_F64 && A->dtype != NYS_F32) return NYS_ERR_INVALID;
+  // FP32 / BF16 products need FP32 A; a CSR A takes NYS_F32 to mean FP64
+  // products with an FP32 copy of U for the preconditioner
+  const bool csr = (A->dtype == NYS_CSR);
+  if (prec != NYS_F64 && A->dtype != NYS_F32 && !(csr && prec == NYS_F32))
+    return NYS_ERR_INVALID;
   if (A->d > (int64_t)1 << 30 || A->n > ((int64_t)1 << 31) - 1) return NYS_ERR_INVALID;
   const int r_old = (*F != nullptr) ? (*F)->r : 0;
   if (r_old + r >= A->d || r_old + r > 1024) return NYS_ERR_INVALID;
-  if (*F != nullptr && ((*F)->d != A->d || (*F)->prec != prec || (*F)->sym != sym))
+  if (*F != nullptr &&
+      ((*F)->d != A->d || (*F)->prec != prec || (*F)->sym != sym || (*F)->sparse != csr))
     return NYS_ERR_INVALID;
   if (sym && (D != nullptr || A->n != A->d || prec == NYS_BF16 || A->dtype == NYS_CSR))
     return NYS_ERR_INVALID;
-  if (A->dtype == NYS_CSR && prec != NYS_F64) return NYS_ERR_INVALID;
+
   NYS_TRY_HIP(hipSetDevice(ctx->device));
   nys::CtxScope ctx_scope(ctx);
   nys_factor f = *F;
@@ -1199,7 +1204,8 @@ nys_status sketch_round(nys_ctx ctx, const nys_dense* A, const double* D, double
     f->device = ctx->device;
     f->prec = prec;
     f->sym = sym;
-    f->mantissa_bits = (prec == NYS_F64) ? 52 : 23;
+    f->sparse = csr;
+    f->mantissa_bits = (prec == NYS_F64 || csr) ? 52 : 23;
     created = true;
   }
   f->basis_hint = (basis_hint != nullptr && r_old == 0) ? basis_hint : nullptr;

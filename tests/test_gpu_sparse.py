@@ -3,8 +3,10 @@ oracle run on the same matrix densified, through the C ABI.
 
 Parity contract: the matvec pair A^T (D (A p)) + (c + rho) p at 1e-12
 relative (rows of 24..45 entries, empty columns, a column present in every
-row); the FP64 sketch's H-hat at 1e-10 with nu equal; lasso and logistic
-NysADMM iterates within 1e-8 of the oracle's after the same iterations;
+row); the FP64 sketch's H-hat at 1e-10 with nu equal (the NYS_F32 factor
+of a sparse A: the same U, Lambda, nu, and P^-1 w at 1e-13 against the
+oracle's with U rounded to FP32); lasso and logistic NysADMM iterates within
+1e-8 of the oracle's after the same iterations (lasso also with the FP32 U);
 malformed CSR input is rejected with NYS_ERR_INVALID before any slot is
 written; two handles of the same matrix give bit-for-bit equal results.
 """
@@ -74,8 +76,25 @@ def test_sparse_sketch_matches_oracle(N, ctx, r):
     e = np.linalg.norm((U * lam) @ U.T - f.dense()) / np.linalg.norm(f.dense())
     print(f"[sparse sketch] r={r} rel(Hhat) {e:.2e} nu {F.info()['nu']:.3e}/{f.nu:.3e}", flush=True)
     assert e < 1e-10 and F.info()["nu"] == f.nu
-    with pytest.raises(N.NysError):      # the sparse sketch is FP64 only
-        N.nys_sketch(ctx, S, om.to(DEV), prec=N.NYS_F32)
+    # NYS_F32 on a sparse A: the same FP64 products and core (U, Lambda and nu
+    # bit-for-bit those of the FP64 factor), and the preconditioner applies
+    # the FP32 copy of U: P^-1 w equals the oracle's P^-1 with U rounded to
+    # FP32 (FP64 arithmetic on those values)
+    F32 = N.nys_sketch(ctx, S, om.to(DEV), prec=N.NYS_F32)
+    assert torch.equal(F32.U(ctx), F.U(ctx))
+    assert F32.info()["lam"] == F.info()["lam"] and F32.info()["nu"] == F.info()["nu"]
+    w = np.random.default_rng(r).standard_normal(d)
+    y = N.nys_precond_apply(ctx, F32, 0.5, torch.tensor(w, device=DEV)).cpu().numpy()
+    U32 = U.astype(np.float32).astype(np.float64)
+    ref32 = ny.precond_inverse_apply(U32, lam, 0.5, w)
+    ref64 = ny.precond_inverse_apply(U, lam, 0.5, w)
+    e32 = np.linalg.norm(y - ref32) / np.linalg.norm(ref32)
+    e64 = np.linalg.norm(y - ref64) / np.linalg.norm(ref64)
+    print(f"[sparse sketch] r={r} FP32-U P^-1 w rel err {e32:.2e} (vs FP64 U {e64:.2e})", flush=True)
+    assert e32 < 1e-13 and e64 < 1e-5
+    with pytest.raises(N.NysError):      # BF16 rounds A, which a sparse A does not take
+        N.nys_sketch(ctx, S, om.to(DEV), prec=N.NYS_BF16)
+    F32.close()
     F.close()
     S.close()
 
@@ -113,6 +132,15 @@ def test_sparse_lasso_and_logistic_match_oracle(N, ctx):
     el = np.linalg.norm(zl - oral.z) / np.linalg.norm(oral.z)
     print(f"[sparse logistic] rel z diff {el:.2e} nnz(z) {(zl != 0).sum()}", flush=True)
     assert el < 1e-8
+    # lasso again with the FP32 copy of U in the preconditioner: PCG solves to
+    # the same tolerance, so the iterates stay within 1e-8 of the oracle's
+    st = N.State(d, DEV)
+    o = N.admm_opts(rho, r, om.to(DEV), pcg=N.pcg_opts(tol=1e-10), max_iter=its,
+                    sketch_prec=N.NYS_F32)
+    info = N.admm_solve(ctx, [N.problem(S, b.to(DEV), gamma)], [o], [st])[0]
+    e32 = np.linalg.norm(st.z.cpu().numpy() - ora.z) / np.linalg.norm(ora.z)
+    print(f"[sparse lasso FP32 U] rel z diff {e32:.2e} pcg {info.pcg_iters}", flush=True)
+    assert info.iters == its and e32 < 1e-8
     S.close()
 
 
