@@ -61,8 +61,9 @@ __device__ __forceinline__ f8 load8(const float* p, int valid, bool vec) {
   return r;
 }
 
-// T(:, col0 + c) = A Omega_lp(:, c), c < ncols.  A workgroup of NW
-// wavefronts (blockDim = 64 NW) covers 16 RB NW rows; wavefront w owns RB
+// T(:, col0 + c) = A Omega_lp(:, c), c < ncols, for rows row0 <= i < n (a
+// launch may cover a range of rows).  A workgroup of NW wavefronts
+// (blockDim = 64 NW) covers 16 RB NW rows from row0; wavefront w owns RB
 // consecutive 16-row blocks (RB = 2 for at most 5 column blocks, so that a K
 // step holds enough MFMA work, else 1) and all NB column blocks (16 NB
 // columns from 16 NB blockIdx.y).  The Omega tile (16 NB x 32 per K step) goes
@@ -72,27 +73,34 @@ __device__ __forceinline__ f8 load8(const float* p, int valid, bool vec) {
 // run (one barrier per step).  Omega_lp is (rows = columns of Omega) x ldo
 // with zero padding up to ldo (a multiple of 32) and up to 16 NB rows.
 constexpr int kSkMaxChunks = 4;   // 16-byte Omega chunks staged per thread
-constexpr int kSk1MaxW = 13;      // wavefronts per first-pass workgroup, at most
+constexpr int kSk1MaxW = 13;      // wavefronts per workgroup of a single first-pass launch, at most
 constexpr int sk1_row_blocks(int NB) { return NB <= 5 ? 2 : 1; }
-// wavefronts per first-pass workgroup, at most: the two-block form and the
-// widest column tiles need more than 128 registers per lane, so at most 8 or
-// 12 wavefronts (3 per SIMD resident)
+// wavefronts per first-pass workgroup, at most: 16 (four per SIMD, at most
+// 128 registers per lane) up to 13 column blocks, 12 for the widest tiles
+// (more registers: three per SIMD); the two-block form launches at most 8
 constexpr int sk1_max_waves(int NB) {
-  return sk1_row_blocks(NB) == 2 ? 8 : (NB >= 14 ? 12 : kSk1MaxW);
+  return sk1_row_blocks(NB) == 2 ? 8 : (NB >= 14 ? 12 : 16);
+}
+// wavefronts per first-pass workgroup, at least: the Omega tile is staged
+// in kSkMaxChunks 16-byte chunks per thread
+constexpr int sk1_min_waves(int NB, bool bf) {
+  return (16 * NB * (bf ? 4 : 8) + 64 * kSkMaxChunks - 1) / (64 * kSkMaxChunks) > 4
+             ? (16 * NB * (bf ? 4 : 8) + 64 * kSkMaxChunks - 1) / (64 * kSkMaxChunks)
+             : 4;
 }
 constexpr int sk2_col_blocks(int) { return 2; }
 template <bool BF, int NB>
 __global__ __launch_bounds__(64 * sk1_max_waves(NB)) void k_sk1(const float* __restrict__ A, int64_t n, int d,
                                               int64_t ld, int vec, const void* __restrict__ Olp,
                                               int ldo, float* __restrict__ T, int64_t ldt,
-                                              int col0, int ncols) {
+                                              int col0, int ncols, int64_t row0) {
   constexpr int NP = 16 * NB;
   constexpr int RB = sk1_row_blocks(NB);
   constexpr int TILE = NP * kOPad * (BF ? 2 : 4);
   __shared__ __attribute__((aligned(32))) char smem[2 * TILE];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
   const int q = lane >> 4, m = lane & 15;
-  const int64_t m0 = ((int64_t)blockIdx.x * (nthr >> 6) + wv) * 16 * RB;
+  const int64_t m0 = row0 + ((int64_t)blockIdx.x * (nthr >> 6) + wv) * 16 * RB;
   const int n0 = blockIdx.y * NP;
   f4 acc[RB][NB];
 #pragma unroll
@@ -932,18 +940,32 @@ nys_status grow(nys::DevBuf& b, size_t old_bytes, size_t new_bytes, hipStream_t 
     default: X(16); break;      \
   }
 
+// Rows [row0, row1) of T, workgroups of NW wavefronts.
 template <bool BF>
-nys_status launch_sk1(int NB, int NW, const nys_dense& A, int vec, const void* Olp, int ldo,
-                      float* T, int64_t ldt, int col0, int ncols, int npass, hipStream_t st) {
+nys_status launch_sk1_rows(int NB, int NW, const nys_dense& A, int vec, const void* Olp, int ldo,
+                           float* T, int64_t ldt, int col0, int ncols, int npass, int64_t row0,
+                           int64_t row1, hipStream_t st) {
+  if (row1 <= row0) return NYS_OK;
   const int rows = 16 * NW * sk1_row_blocks(NB);
-  dim3 grid((unsigned)((A.n + rows - 1) / rows), npass);
+  dim3 grid((unsigned)((row1 - row0 + rows - 1) / rows), npass);
   const float* a = static_cast<const float*>(A.data);
 #define NYS_SK1(N)                                                                              \
-  hipLaunchKernelGGL((k_sk1<BF, N>), grid, dim3(64 * NW), 0, st, a, A.n, (int)A.d, A.ld, vec,  \
-                     Olp, ldo, T, ldt, col0, ncols)
+  hipLaunchKernelGGL((k_sk1<BF, N>), grid, dim3(64 * NW), 0, st, a, row1, (int)A.d, A.ld, vec, \
+                     Olp, ldo, T, ldt, col0, ncols, row0)
   NYS_NB_SWITCH(NB, NYS_SK1)
 #undef NYS_SK1
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
+}
+
+// T = A Omega_lp over all rows: the first launch takes rows [0, rows1) with NW
+// wavefronts per workgroup, a second one the rest with NW2.
+template <bool BF>
+nys_status launch_sk1(int NB, int NW, int64_t rows1, int NW2, const nys_dense& A, int vec,
+                      const void* Olp, int ldo, float* T, int64_t ldt, int col0, int ncols,
+                      int npass, hipStream_t st) {
+  const int64_t r1 = std::min<int64_t>(rows1, A.n);
+  NYS_TRY(launch_sk1_rows<BF>(NB, NW, A, vec, Olp, ldo, T, ldt, col0, ncols, npass, 0, r1, st));
+  return launch_sk1_rows<BF>(NB, NW2, A, vec, Olp, ldo, T, ldt, col0, ncols, npass, r1, A.n, st);
 }
 
 template <bool BF>
@@ -963,7 +985,8 @@ nys_status launch_sk2(int NB, const nys_dense& A, const double* D, const float* 
 
 // Launch shape and temporaries of the FP32/BF16-MFMA sketch of m columns.
 struct Sk32Shape {
-  int ldo, NB, NP, npass, nrows_pad, ldy, S, NW;
+  int ldo, NB, NP, npass, nrows_pad, ldy, S, NW, NW2;
+  int64_t rows1;   // rows of the first-pass launch with NW wavefronts; NW2 takes the rest
   int64_t ldt, slice;
   size_t olp_b, yp_b;
 };
@@ -975,9 +998,8 @@ int sk1_waves(int64_t n, int NB, bool bf, int num_cu) {
   const int64_t nblk = (n + 16 * rb - 1) / (16 * rb);
   const size_t lds = 2 * (size_t)16 * NB * kOPad * (bf ? 2 : 4);
   const int by_lds = std::max<int>(1, (int)((160 * 1024) / lds));
-  const int nch = 16 * NB * (bf ? 4 : 8);   // 16-byte chunks of an Omega tile
-  const int lo = std::max(4, (nch + 64 * kSkMaxChunks - 1) / (64 * kSkMaxChunks));
-  const int hi = rb == 2 ? 8 : (NB >= 14 ? 12 : kSk1MaxW);   // sk1_max_waves
+  const int lo = sk1_min_waves(NB, bf);
+  const int hi = rb == 2 ? 8 : (NB >= 14 ? 12 : kSk1MaxW);
   const int waves_cu = (rb == 2 || NB >= 14) ? 12 : 16;       // 3 or 4 resident per SIMD
   int best = hi;
   double best_eff = -1.0;
@@ -994,6 +1016,45 @@ int sk1_waves(int64_t n, int NB, bool bf, int num_cu) {
   }
   return best;
 }
+
+// Launch plan of the first pass (T = A Omega), from measured rates on
+// 100000 x 4000:
+//  * FP32, one 16-row block per wavefront (more than 5 column blocks): the
+//    matrix cores bound it, so every SIMD should hold the same number of
+//    wavefronts until the rows run out.  Full rounds of 16-wavefront
+//    workgroups (one per CU, four per SIMD), then the remaining blocks in
+//    one more launch spread over at most one workgroup per CU (at most three
+//    wavefronts per SIMD).  One launch leaves 13-wavefront workgroups with
+//    four wavefronts on one SIMD and three on the others, or a second round
+//    of 16-wavefront workgroups on half of the CUs: 1.81 ms against 1.65 ms
+//    at 208 columns, 1.16 against 1.08 at 112.
+//  * BF16, one block per wavefront: bound by the latency of the A loads;
+//    seven-wavefront workgroups (two per CU) measured fastest (0.53 ms against
+//    0.56 at 208 columns, 0.41 against 0.47 at 112).
+//  * two blocks per wavefront (at most 5 column blocks): one launch with the
+//    workgroup size of sk1_waves.
+void sk1_plan(int64_t n, int NB, bool bf, int num_cu, int* nw1, int64_t* rows1, int* nw2) {
+  const int rb = sk1_row_blocks(NB);
+  *rows1 = n;
+  *nw1 = *nw2 = sk1_waves(n, NB, bf, num_cu);
+  if (rb != 1) return;
+  const int lo = sk1_min_waves(NB, bf);
+  if (bf) {
+    *nw1 = *nw2 = std::max(lo, 7);
+    return;
+  }
+  const int full = sk1_max_waves(NB) == 16 ? 16 : 12;   // four (three) per SIMD
+  const int64_t nblk = (n + 15) / 16;
+  const int64_t per_round = (int64_t)full * num_cu;
+  const int64_t k_full = nblk / per_round;
+  if (k_full == 0) return;
+  const int64_t rem = nblk - k_full * per_round;
+  *nw1 = full;
+  *nw2 = full;
+  if (rem == 0) return;
+  *rows1 = k_full * per_round * 16;
+  *nw2 = (int)std::max<int64_t>(lo, (rem + num_cu - 1) / num_cu);
+}
 Sk32Shape sk32_shape(int64_t n, int64_t d, int m, int num_cu, bool bf) {
   Sk32Shape s;
   s.ldo = (int)((d + 31) / 32 * 32);
@@ -1003,7 +1064,7 @@ Sk32Shape sk32_shape(int64_t n, int64_t d, int m, int num_cu, bool bf) {
   s.nrows_pad = s.npass * s.NP;
   s.ldt = (n + 7) / 8 * 8;
   s.ldy = (int)((d + 3) / 4 * 4);
-  s.NW = sk1_waves(n, s.NB, bf, num_cu);
+  sk1_plan(n, s.NB, bf, num_cu, &s.NW, &s.rows1, &s.NW2);
   // split-K over rows of A for the second pass: one resident workgroup per CU
   // (the accumulators of 32 columns x 16 NB per wavefront), S slices so that
   // the j tiles x slices fill the device once
@@ -1073,7 +1134,7 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
                        st, Om, (int)d, m, Olp, ldo, nrows_pad);
     const int vec = (((uintptr_t)A.data % 16) == 0 && (A.ld % 4) == 0) ? 1 : 0;
     float* T = F->T.as<float>();
-    NYS_TRY(launch_sk1<false>(NB, sh.NW, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+    NYS_TRY(launch_sk1<false>(NB, sh.NW, sh.rows1, sh.NW2, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
     hipLaunchKernelGGL(k_sym_y, dim3(blocks((int64_t)m * d)), dim3(256), 0, st, T + ldt * r0, ldt,
                        (int)d, m, Om, c, Y + d * r0);
   } else if (F->prec == NYS_F64) {
@@ -1106,9 +1167,9 @@ nys_status sketch_block(nys_ctx ctx, const nys_dense& A, const double* D, double
     const int vec = (((uintptr_t)A.data % 16) == 0 && (A.ld % 4) == 0) ? 1 : 0;
     float* T = F->T.as<float>();
     if (bf)
-      NYS_TRY(launch_sk1<true>(NB, sh.NW, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+      NYS_TRY(launch_sk1<true>(NB, sh.NW, sh.rows1, sh.NW2, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
     else
-      NYS_TRY(launch_sk1<false>(NB, sh.NW, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
+      NYS_TRY(launch_sk1<false>(NB, sh.NW, sh.rows1, sh.NW2, A, vec, Olp, ldo, T, ldt, r0, m, npass, st));
     for (int p = 0; p < npass; ++p) {
       const int cols = std::min(NP, m - p * NP);
       if (bf)

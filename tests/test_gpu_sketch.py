@@ -85,7 +85,11 @@ def test_sketch_fp64_rank_deficient_exact(N, ctx):
     F.close()
 
 
-@pytest.mark.parametrize("n,d,r", [(20000, 1000, 100), (5003, 517, 37), (30000, 2000, 200)])
+# the last three run the first pass as full rounds of 16-wavefront workgroups
+# plus a launch for the remaining rows (4125, 4376 and 8193 row blocks of 16:
+# 29, 280 and 1 block left, the last one holding 5 rows)
+@pytest.mark.parametrize("n,d,r", [(20000, 1000, 100), (5003, 517, 37), (30000, 2000, 200),
+                                   (66000, 257, 100), (70001, 300, 200), (131077, 257, 200)])
 def test_sketch_fp32_parity(N, ctx, n, d, r):
     print(f"[sketch fp32] n={n} d={d} r={r}", flush=True)
     A64 = synth.decay_matrix(n, d, 0.8, seed=n % 97)
