@@ -73,6 +73,9 @@ __device__ __forceinline__ f8 load8(const float* p, int valid, bool vec) {
 // run (one barrier per step).  Omega_lp is (rows = columns of Omega) x ldo
 // with zero padding up to ldo (a multiple of 32) and up to 16 NB rows.
 constexpr int kSkMaxChunks = 4;   // 16-byte Omega chunks staged per thread
+// column blocks from which the sketch passes read the next block's LDS operand
+// during the current block's products (with fewer, measured slower)
+constexpr int kSkPipeNB = 6;
 constexpr int kSk1MaxW = 13;      // wavefronts per workgroup of a single first-pass launch, at most
 constexpr int sk1_row_blocks(int NB) { return NB <= 5 ? 2 : 1; }
 // wavefronts per first-pass workgroup, at most: 16 (four per SIMD, at most
@@ -174,26 +177,54 @@ __global__ __launch_bounds__(64 * sk1_max_waves(NB)) void k_sk1(const float* __r
       load_a(k0 + kBK);
     }
     const char* buf = smem + cur * TILE;
+    // the Omega operand of column block nb + 1 is read from LDS while block
+    // nb's products run; from kSkPipeNB column blocks on, group barriers keep
+    // the scheduler from sinking each read to its products (DS reads = 0x100,
+    // MFMA = 0x8)
     if constexpr (BF) {
-      const __bf16* Os = reinterpret_cast<const __bf16*>(buf);
+      const __bf16* Os = reinterpret_cast<const __bf16*>(buf) + m * kOPad + 8 * q;
+      bf16x8 bv = *reinterpret_cast<const bf16x8*>(Os);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Os + (nb * 16 + m) * kOPad + 8 * q);
+        bf16x8 bn = bv;
+        if (nb + 1 < NB) bn = *reinterpret_cast<const bf16x8*>(Os + (nb + 1) * 16 * kOPad);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
           acc[rb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[rb], bv, acc[rb][nb], 0, 0, 0);
+        bv = bn;
+      }
+      if constexpr (NB >= kSkPipeNB) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+        for (int nb = 0; nb + 1 < NB; ++nb) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, RB, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, RB, 0);
       }
     } else {
-      const float* Os = reinterpret_cast<const float*>(buf);
+      const float* Os = reinterpret_cast<const float*>(buf) + m * kOPad + 8 * q;
+      f8 bv = *reinterpret_cast<const f8*>(Os);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const f8 bv = *reinterpret_cast<const f8*>(Os + (nb * 16 + m) * kOPad + 8 * q);
+        f8 bn = bv;
+        if (nb + 1 < NB) bn = *reinterpret_cast<const f8*>(Os + (nb + 1) * 16 * kOPad);
 #pragma unroll
         for (int s = 0; s < 8; ++s)
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb)
             acc[rb][nb] =
                 __builtin_amdgcn_mfma_f32_16x16x4f32(af[rb][s], bv[s], acc[rb][nb], 0, 0, 0);
+        bv = bn;
+      }
+      if constexpr (NB >= kSkPipeNB) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+        for (int nb = 0; nb + 1 < NB; ++nb) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 8 * RB, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 8 * RB, 0);
       }
     }
     if (more) store_omega(smem + (cur ^ 1) * TILE);
@@ -333,27 +364,60 @@ __global__ __launch_bounds__(64 * kSk2W) void k_sk2(const float* __restrict__ A,
       for (int jb = 0; jb < JB; ++jb) b[jb] = to_bf16(a[jb]);
       const __bf16* hi = reinterpret_cast<const __bf16*>(buf);
       const __bf16* lo = hi + NP * kTPad;
+      // block nb + 1's operands are read while block nb's products run
+      const int off0 = m * kTPad + 8 * q;
+      bf16x8 th = *reinterpret_cast<const bf16x8*>(hi + off0);
+      bf16x8 tl = *reinterpret_cast<const bf16x8*>(lo + off0);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int off = (nb * 16 + m) * kTPad + 8 * q;
-        const bf16x8 th = *reinterpret_cast<const bf16x8*>(hi + off);
-        const bf16x8 tl = *reinterpret_cast<const bf16x8*>(lo + off);
+        bf16x8 nh = th, nl = tl;
+        if (nb + 1 < NB) {
+          nh = *reinterpret_cast<const bf16x8*>(hi + off0 + (nb + 1) * 16 * kTPad);
+          nl = *reinterpret_cast<const bf16x8*>(lo + off0 + (nb + 1) * 16 * kTPad);
+        }
 #pragma unroll
         for (int jb = 0; jb < JB; ++jb) {
           acc[jb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[jb], th, acc[jb][nb], 0, 0, 0);
           acc[jb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[jb], tl, acc[jb][nb], 0, 0, 0);
         }
+        th = nh;
+        tl = nl;
+      }
+      if constexpr (NB >= kSkPipeNB) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+        for (int nb = 0; nb + 1 < NB; ++nb) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 2 * JB, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 2 * JB, 0);
       }
     } else {
-      const float* Ts = reinterpret_cast<const float*>(buf);
+      // the (D o T) operand of block nb + 1 is read from LDS while block nb's
+      // products run (two wavefronts per SIMD hide little latency otherwise)
+      const float* Ts = reinterpret_cast<const float*>(buf) + m * kTPad + 8 * q;
+      f8 bv = *reinterpret_cast<const f8*>(Ts);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const f8 bv = *reinterpret_cast<const f8*>(Ts + (nb * 16 + m) * kTPad + 8 * q);
+        f8 bn = bv;
+        if (nb + 1 < NB) bn = *reinterpret_cast<const f8*>(Ts + (nb + 1) * 16 * kTPad);
 #pragma unroll
         for (int s = 0; s < 8; ++s)
 #pragma unroll
           for (int jb = 0; jb < JB; ++jb)
             acc[jb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jb][s], bv[s], acc[jb][nb], 0, 0, 0);
+        bv = bn;
+      }
+      // keep that order from kSkPipeNB column blocks on: the scheduler
+      // otherwise sinks each read to its products (DS reads = 0x100, MFMA = 0x8)
+      if constexpr (NB >= kSkPipeNB) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+        for (int nb = 0; nb + 1 < NB; ++nb) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 8 * JB, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 8 * JB, 0);
       }
     }
     if (more) store_t(smem + (cur ^ 1) * TILE);
