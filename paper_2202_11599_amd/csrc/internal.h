@@ -341,17 +341,24 @@ struct nys_sparse_s {
   const int* rowptr = nullptr;   // caller's CSR arrays
   const int* colidx = nullptr;
   const float* val = nullptr;
-  nys::DevBuf csc;               // colptr (d + 1 ints), rows (nnz ints), values (nnz floats)
+  // CSC copy: colptr (d + 1 ints), then (at a 16-byte boundary) the row
+  // indices and values, cap slots each; nnzc = colptr[d] entries are used
+  // (nnz plus one zero entry per empty column), the rest is zero
+  nys::DevBuf csc;
+  int64_t cap = 0, nnzc = 0;
+  int64_t row_off() const { return (d + 1 + 3) / 4 * 4; }
   int* colptr() const { return csc.as<int>(); }
-  int* rows() const { return csc.as<int>() + (d + 1); }
-  float* cvals() const { return reinterpret_cast<float*>(csc.as<int>() + (d + 1) + nnz); }
+  int* rows() const { return csc.as<int>() + row_off(); }
+  float* cvals() const { return reinterpret_cast<float*>(csc.as<int>() + row_off() + cap); }
   nys::DevBuf s;                 // the n-vector s = f(A p) between the two passes
-  // columns binned by length for the A^T pass: short ones (<= kShortCol
-  // entries) by groups of 8 lanes, medium ones by a wavefront, long ones
-  // (> kLongCol) by a workgroup; bins holds the three lists of (column,
-  // begin, end) triples back to back (d slots each), then their lengths
-  nys::DevBuf bins;
-  int nshort = 0, nmed = 0, nlong = 0;
+  // column-pass work split: cgrid workgroups of 16 wavefronts; part holds
+  // wstart (16 cgrid + 1 ints: first entry of each wavefront's range, the
+  // last = nnzc) and wbase (16 cgrid + 1 ints: columns starting before that
+  // entry, minus one)
+  nys::DevBuf part;
+  int cgrid = 0;
+  const int* wstart() const { return part.as<int>(); }
+  const int* wbase() const { return part.as<int>() + 16 * (int64_t)cgrid + 1; }
   int num_cu = 256;              // CUs of the device (row-pass grid)
 };
 

@@ -1,12 +1,15 @@
 // Sparse A (CSR) for the NysADMM hot path: the matvec pair A^T (D (A p)) as
 // two streaming passes, a row pass over the CSR arrays (t = A p and the mode
 // epilogue s = f(t)) and a column pass over a CSC copy (y = A^T s), and the
-// sketch A^T (D (A Omega)) as two sparse-times-dense products.  One wavefront
-// per row (column); every sum is FP64 in a fixed order, so results are
-// bitwise reproducible.  The CSC copy is built once by a deterministic
-// counting transpose: rows are split into blocks, each block's column counts
-// are prefix-summed across blocks, and each block places its entries row by
-// row (within a row the columns are distinct, so no two lanes share a slot).
+// sketch A^T (D (A Omega)) as two sparse-times-dense products.  Every sum is
+// FP64 in a fixed order, so results are bitwise reproducible.  The CSC copy
+// is built once by a deterministic counting transpose: rows are split into
+// blocks, each block's column counts are prefix-summed across blocks, and
+// each block places its entries row by row (within a row the columns are
+// distinct, so no two lanes share a slot).  In the copy every column holds at
+// least one entry (an empty column holds the entry (row 0, value 0)), and the
+// row index of each column's first entry carries bit 31, so that a pass over
+// the entries in storage order finds column j as the j-th flagged entry.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -22,48 +25,7 @@ using gram::sigm;
 using gram::wave_sum;
 
 constexpr int kTBlocks = 64;   // row blocks of the transpose
-constexpr int kShortCol = 32;  // columns with at most this many entries: 8 lanes each
-constexpr int kLongCol = 2048; // columns with more: a 256-thread workgroup each
-
-// Column j goes to list 0 (short), 1 (medium) or 2 (long), each list in
-// increasing column order (so a pass over a list reads the CSC arrays in
-// storage order) as the triple (j, colptr[j], colptr[j + 1]), so that the
-// column pass finds a column's range with one load; counts[3] are the list
-// lengths.  One workgroup: thread t counts its contiguous range of columns
-// per class, the counts are prefix-summed, and each thread places its range
-// in order.
-__device__ __forceinline__ int col_class(const int* __restrict__ colptr, int64_t j) {
-  const int len = colptr[j + 1] - colptr[j];
-  return len <= kShortCol ? 0 : (len <= kLongCol ? 1 : 2);
-}
-__global__ __launch_bounds__(1024) void k_bin_cols(const int* __restrict__ colptr, int64_t d,
-                                                   int4* __restrict__ lists,
-                                                   int* __restrict__ counts) {
-  __shared__ int part[3][1024];
-  const int t = threadIdx.x;
-  const int64_t per = (d + 1023) / 1024;
-  const int64_t j0 = std::min<int64_t>(d, t * per), j1 = std::min<int64_t>(d, j0 + per);
-  int c[3] = {0, 0, 0};
-  for (int64_t j = j0; j < j1; ++j) ++c[col_class(colptr, j)];
-#pragma unroll
-  for (int b = 0; b < 3; ++b) part[b][t] = c[b];
-  __syncthreads();
-  if (t < 3) {
-    int acc = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const int v = part[t][i];
-      part[t][i] = acc;
-      acc += v;
-    }
-    counts[t] = acc;
-  }
-  __syncthreads();
-  int pos[3] = {part[0][t], part[1][t], part[2][t]};
-  for (int64_t j = j0; j < j1; ++j) {
-    const int b = col_class(colptr, j);
-    lists[(int64_t)b * d + pos[b]++] = make_int4((int)j, colptr[j], colptr[j + 1], 0);
-  }
-}
+constexpr int kColFlag = (int)0x80000000u;   // first entry of a column in the CSC copy
 
 // *bad = 1 unless rowptr is non-decreasing (its ends were checked on the host)
 __global__ __launch_bounds__(256) void k_tr_check_rows(const int* __restrict__ rowptr, int64_t n,
@@ -111,7 +73,7 @@ __global__ __launch_bounds__(256) void k_tr_colsum(int* __restrict__ cnt, int64_
     cnt[(int64_t)b * d + j] = s;
     s += c;
   }
-  colptr[j] = s;
+  colptr[j] = s > 0 ? s : 1;   // an empty column keeps one slot for its zero entry
 }
 __global__ __launch_bounds__(1024) void k_tr_colscan(int* __restrict__ colptr, int64_t d) {
   __shared__ long long part[1024];
@@ -147,6 +109,23 @@ __global__ __launch_bounds__(256) void k_tr_addbase(int* __restrict__ cnt, int64
   for (int b = 0; b < nblk; ++b) cnt[(int64_t)b * d + j] += base;
 }
 
+// After the fill: flag each column's first entry; an empty column (the last
+// block's slot counter still at the column start) gets the entry (row 0,
+// value 0) in its one slot.
+__global__ __launch_bounds__(256) void k_tr_pad(const int* __restrict__ cnt, int64_t d, int nblk,
+                                                const int* __restrict__ colptr,
+                                                int* __restrict__ rows, float* __restrict__ cval) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= d) return;
+  const int pos = colptr[j];
+  if (cnt[(int64_t)(nblk - 1) * d + j] == pos) {
+    rows[pos] = kColFlag;
+    cval[pos] = 0.0f;
+  } else {
+    rows[pos] |= kColFlag;
+  }
+}
+
 // Block b places its rows in order: each lane takes distinct columns of one
 // row, so the slot counters cnt[b * d + col] are bumped without conflicts.
 __global__ __launch_bounds__(64) void k_tr_fill(const int* __restrict__ rowptr,
@@ -171,30 +150,21 @@ __global__ __launch_bounds__(64) void k_tr_fill(const int* __restrict__ rowptr,
   }
 }
 
-// sum over k = k0, k0 + step, ... (below k1) of v[k] x[idx[k]]: four terms
-// in flight per lane (their index and value loads issued together, then the
-// four gathers), four running sums combined in a fixed order, then the
-// remaining terms one at a time.  x[i] is read from xl (LDS) for i < head.
-// (Eight or more terms in flight per lane measured slower at the E2006.train
-// shape: the extra registers cost more occupancy than the longer batches
-// save.)
-__device__ __forceinline__ double gather_dot(const int* __restrict__ idx,
-                                             const float* __restrict__ v,
-                                             const double* __restrict__ x, const double* xl,
-                                             int head, int64_t k0, int64_t k1, int step) {
-  auto X = [&](int i) { return i < head ? xl[i] : x[i]; };
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int64_t k = k0;
-  for (; k + 3 * step < k1; k += 4 * step) {
-    const int i0 = idx[k], i1 = idx[k + step], i2 = idx[k + 2 * step], i3 = idx[k + 3 * step];
-    const float v0 = v[k], v1 = v[k + step], v2 = v[k + 2 * step], v3 = v[k + 3 * step];
-    a0 = fma((double)v0, X(i0), a0);
-    a1 = fma((double)v1, X(i1), a1);
-    a2 = fma((double)v2, X(i2), a2);
-    a3 = fma((double)v3, X(i3), a3);
+// Stage x[0, h) (h <= 16 * 1024) into LDS by a 1024-thread workgroup with
+// all sixteen loads of a thread in flight before the stores.
+__device__ __forceinline__ void stage16(double* xl, const double* __restrict__ x, int h, int tid) {
+  if (h <= 0) return;
+  double t[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int i = tid + u * 1024;
+    t[u] = x[i < h ? i : h - 1];
   }
-  for (; k < k1; k += step) a0 = fma((double)v[k], X(idx[k]), a0);
-  return (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int i = tid + u * 1024;
+    if (i < h) xl[i] = t[u];
+  }
 }
 
 // Row pass: t_i = A_i p (one wavefront per row), s_i = f_mode(t_i) into s,
@@ -202,10 +172,17 @@ __device__ __forceinline__ double gather_dot(const int* __restrict__ idx,
 // of 1024 threads (one per CU): the first kCsrHead entries of p are staged in
 // LDS, where the gathers of the popular (low-index) columns of bag-of-words
 // data land, and wavefront w of workgroup g takes rows g * 16 + w, then
-// every 16 * gridDim.x rows on; its q terms are added in row order, the 16
+// every 16 * gridDim.x rows on.  The next row's bounds are loaded before the
+// current row's entries; a row is read in batches of 64 * kCsrCh entries
+// (lane l takes entries k0 + c * 64 + l), every index and value load of a
+// batch unconditional (a lane past the row end re-reads its last entry with
+// value 0) so that all are in flight at once, then the LDS reads and, for
+// columns past the head only, the global gathers.  Each lane adds its
+// products in entry order; q terms are added in row order, the 16
 // wavefronts' sums in wavefront order.
 constexpr int kCsrT = 1024;
 constexpr int kCsrHead = 16384;
+constexpr int kCsrCh = 10;   // entries per lane per batch (rows up to 640 in one batch)
 __global__ __launch_bounds__(kCsrT) void k_csr_pass(const int* __restrict__ rowptr,
                                                     const int* __restrict__ col,
                                                     const float* __restrict__ val, int64_t n,
@@ -222,15 +199,48 @@ __global__ __launch_bounds__(kCsrT) void k_csr_pass(const int* __restrict__ rowp
   __shared__ double pl[kCsrHead];
   __shared__ double qs[kCsrT / 64];
   const int head = (mode == kModeTOnly) ? 0 : (int)(d < kCsrHead ? d : kCsrHead);
-  for (int i = threadIdx.x; i < head; i += kCsrT) pl[i] = p[i];
+  stage16(pl, p, head, threadIdx.x);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double q = 0.0;
   const int64_t stride = (int64_t)gridDim.x * (kCsrT / 64);
-  for (int64_t i = (int64_t)blockIdx.x * (kCsrT / 64) + wv; i < n; i += stride) {
+  int64_t i = (int64_t)blockIdx.x * (kCsrT / 64) + wv;
+  int rb = 0, re = 0;
+  if (i < n && mode != kModeTOnly) {
+    rb = rowptr[i];
+    re = rowptr[i + 1];
+  }
+  for (; i < n; i += stride) {
+    int nb = 0, ne = 0;
+    if (i + stride < n && mode != kModeTOnly) {
+      nb = rowptr[i + stride];
+      ne = rowptr[i + stride + 1];
+    }
     double acc = 0.0;
-    if (mode != kModeTOnly) acc = gather_dot(col, val, p, pl, head, rowptr[i] + lane,
-                                             rowptr[i + 1], 64);
+    for (int k0 = rb; k0 < re; k0 += 64 * kCsrCh) {
+      int jj[kCsrCh];
+      float vv[kCsrCh];
+#pragma unroll
+      for (int c = 0; c < kCsrCh; ++c) {
+        const int k = k0 + c * 64 + lane;
+        const int kk = k < re ? k : re - 1;
+        jj[c] = col[kk];
+        const float w = val[kk];
+        vv[c] = k < re ? w : 0.0f;
+      }
+      double lv[kCsrCh], gv[kCsrCh];
+#pragma unroll
+      for (int c = 0; c < kCsrCh; ++c) {
+        lv[c] = pl[jj[c] < head ? jj[c] : 0];
+        gv[c] = 0.0;
+        if (jj[c] >= head) gv[c] = p[jj[c]];
+      }
+#pragma unroll
+      for (int c = 0; c < kCsrCh; ++c)
+        acc = fma((double)vv[c], (jj[c] < head ? lv[c] : 0.0) + gv[c], acc);
+    }
+    rb = nb;
+    re = ne;
     const double t = wave_sum(acc);
     if (lane == 0) {
       double si = 0.0, qi = 0.0;
@@ -267,51 +277,164 @@ __global__ __launch_bounds__(kCsrT) void k_csr_pass(const int* __restrict__ rowp
   }
 }
 
-// Column pass: y_j = sum over column j of A_ij s_i, one launch for the three
-// column lists (triples (j, begin, end)): workgroups [0, nlong) take one long
-// column each (256 threads), the next ceil(nmed / 4) one medium column per
-// wavefront, the rest 32 short columns each (8 lanes per column).  Long
-// columns come first so that the longest work is dispatched first.  Fixed
-// summation order per column.
-__global__ __launch_bounds__(256) void k_csc_pass(const int* __restrict__ rows,
-                                                  const float* __restrict__ cval,
-                                                  const int4* __restrict__ lists, int64_t d,
-                                                  int nshort, int nmed, int nlong,
-                                                  const double* __restrict__ s,
-                                                  double* __restrict__ y,
-                                                  const int* __restrict__ done) {
+// DPP helpers of the column pass (FP64 as two 32-bit halves)
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffull), CTRL, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, RM, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// One step of a segmented inclusive scan over the 64 lanes: (v, fs) of the
+// partner the DPP control selects (row_shr 1/2/4/8 within rows of 16, then
+// row_bcast 15 and 31; (0, no flag) where there is none) is added in front
+// unless a segment starts at or before this lane within the window.
+template <int CTRL, int RM>
+__device__ __forceinline__ void seg_step(double& v, int& fs) {
+  const double pv = dpp_f64<CTRL, RM>(v);
+  const int pf = __builtin_amdgcn_update_dpp(0, fs, CTRL, RM, 0xf, false);
+  if (!fs) {
+    v = pv + v;
+    fs = pf;
+  }
+}
+
+// Column pass: y_j = sum over column j of A_ij s_i over the CSC copy in
+// storage order, with s staged in LDS (its first kCscHead entries).
+// Workgroup g (1024 threads, one per CU) owns the entries [B_g, B_{g+1}), a
+// column-aligned range chosen at handle creation so that the largest range
+// is as small as possible; its wavefront w owns the w-th sixteenth of it
+// (wstart[16 g + w] to wstart[16 g + w + 1]), whatever the column
+// boundaries, and wbase[16 g + w] is the number of columns starting before
+// its first entry, minus one.  A wavefront reads 256 entries per round, four
+// consecutive ones per lane (16-byte loads from the entry index rounded down
+// to a multiple of 4; entries outside its range count as zero), sums them in
+// order split at column starts, then combines the lanes by one segmented
+// scan: a column that ends inside the wavefront's range is written by the
+// lane holding its last entry's successor (or at the range end), its sum
+// taken in entry order.  The partial sums of the columns that cross
+// wavefront boundaries (the part before a wavefront's first column start,
+// the part from its last one) are combined in wavefront order by one thread
+// after a barrier.
+constexpr int kCscHead = 16384;
+constexpr int kCscPad = 512;   // entries past the end of the CSC arrays (16-byte loads overrun)
+__global__ __launch_bounds__(1024) void k_csc_pass(const int* __restrict__ rows,
+                                                   const float* __restrict__ cval,
+                                                   const int* __restrict__ wstart,
+                                                   const int* __restrict__ wbase, int64_t n,
+                                                   const double* __restrict__ s,
+                                                   double* __restrict__ y,
+                                                   const int* __restrict__ done) {
   if (done != nullptr && *done) return;
-  const int bid = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-  const int gm = (nmed + 3) / 4;
-  if (bid < nlong) {
-    __shared__ double red[4];
-    const int4 c = lists[2 * d + bid];
-    double acc = gather_dot(rows, cval, s, nullptr, 0, c.y + tid, c.z, 256);
-    acc = wave_sum(acc);
-    if (lane == 0) red[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) y[c.x] = ((red[0] + red[1]) + red[2]) + red[3];
-  } else if (bid < nlong + gm) {
-    const int g = (bid - nlong) * 4 + (tid >> 6);
-    if (g >= nmed) return;
-    const int4 c = lists[d + g];
-    double acc = gather_dot(rows, cval, s, nullptr, 0, c.y + lane, c.z, 64);
-    acc = wave_sum(acc);
-    if (lane == 0) y[c.x] = acc;
-  } else {
-    const int g = (bid - nlong - gm) * 32 + (tid >> 3);
-    const int sub = tid & 7;
-    double acc = 0.0;
-    int j = -1;
-    if (g < nshort) {
-      const int4 c = lists[g];
-      j = c.x;
-      acc = gather_dot(rows, cval, s, nullptr, 0, c.y + sub, c.z, 8);
+  __shared__ double sl[kCscHead];
+  __shared__ double hd[16], tl[16];
+  __shared__ int hf[16], tord[16], topen[16];
+  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int hs = (int)(n < kCscHead ? n : kCscHead);
+  const bool all_lds = n <= kCscHead;
+  stage16(sl, s, hs, tid);
+  __syncthreads();
+  const int r0 = wstart[g * 16 + w], r1 = wstart[g * 16 + w + 1];
+  const int wend = wstart[g * 16 + 16];
+  const int base = wbase[g * 16 + w];
+  double carry = 0.0;   // partial of the column open at the end of the last round
+  int cnt = 0;          // column starts seen so far by the wavefront
+  double head = 0.0;    // partial before the wavefront's first column start
+  for (int a = r0 & ~3; a < r1; a += 256) {
+    const int e0 = a + 4 * lane;
+    const int4 rr = *reinterpret_cast<const int4*>(rows + e0);
+    const float4 cc = *reinterpret_cast<const float4*>(cval + e0);
+    const int rw[4] = {rr.x, rr.y, rr.z, rr.w};
+    const float cv[4] = {cc.x, cc.y, cc.z, cc.w};
+    double x[4];
+    int fl = 0;   // bit j: entry e0 + j starts a column
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool valid = e0 + j >= r0 && e0 + j < r1;
+      const int row = valid ? (rw[j] & ~kColFlag) : 0;
+      double sv;
+      if (all_lds) {
+        sv = sl[row < hs ? row : 0];
+      } else {
+        const double lv = sl[row < kCscHead ? row : 0];
+        const double gv = s[row < kCscHead ? 0 : row];
+        sv = row < kCscHead ? lv : gv;
+      }
+      x[j] = (valid && row < n) ? (double)cv[j] * sv : 0.0;
+      if (valid && (rw[j] & kColFlag)) fl |= 1 << j;
     }
-    acc += __shfl_xor(acc, 4, 8);
-    acc += __shfl_xor(acc, 2, 8);
-    acc += __shfl_xor(acc, 1, 8);
-    if (j >= 0 && sub == 0) y[j] = acc;
+    const int nf = __popc(fl);
+    const unsigned long long fm = __ballot(fl != 0);
+    // column starts in the lanes below (exclusive prefix over the wavefront)
+    int pre = nf;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(pre, off, 64);
+      if (lane >= off) pre += o;
+    }
+    const int fb = cnt + pre - nf;
+    // in-lane pass: columns that start and end inside the lane are written
+    double hsum = 0.0, run = 0.0;
+    int seen = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (fl & (1 << j)) {
+        if (seen == 0) hsum = run;
+        else y[base + fb + seen] = run;
+        run = 0.0;
+        ++seen;
+      }
+      run += x[j];
+    }
+    if (!fl) hsum = run;
+    double v = fl ? run : hsum;   // from the lane's last column start, or the whole lane
+    int fs = fl ? 1 : 0;
+    seg_step<0x111, 0xf>(v, fs);
+    seg_step<0x112, 0xf>(v, fs);
+    seg_step<0x114, 0xf>(v, fs);
+    seg_step<0x118, 0xf>(v, fs);
+    seg_step<0x142, 0xa>(v, fs);
+    seg_step<0x143, 0xc>(v, fs);
+    // the column that ends just before this lane's first column start
+    const double vprev = dpp_f64<0x138, 0xf>(v);   // wave_shr:1
+    const int fsprev = __builtin_amdgcn_update_dpp(0, fs, 0x138, 0xf, 0xf, false);
+    const double prev_total = (fsprev ? vprev : carry + vprev) + hsum;
+    if (fl && fb > 0) y[base + fb] = prev_total;
+    if (cnt == 0 && fm != 0ull) head = readlane_f64(prev_total, __ffsll((long long)fm) - 1);
+    const double v63 = readlane_f64(v, 63);
+    carry = fm ? v63 : carry + v63;
+    cnt = __shfl(fb + nf, 63, 64);
+  }
+  if (lane == 0) {
+    hf[w] = cnt > 0;
+    hd[w] = cnt > 0 ? head : carry;
+    tl[w] = carry;
+    tord[w] = base + cnt;
+    topen[w] = cnt > 0 && r1 < wend;
+    if (cnt > 0 && r1 >= wend && r1 > r0) y[base + cnt] = carry;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    bool open = false;
+    double acc = 0.0;
+    int ord = -1;
+    for (int v = 0; v < 16; ++v) {
+      if (!hf[v]) {
+        acc += hd[v];
+        continue;
+      }
+      if (open) y[ord] = acc + hd[v];
+      open = topen[v] != 0;
+      acc = tl[v];
+      ord = tord[v];
+    }
+    if (open) y[ord] = acc;
   }
 }
 
@@ -362,7 +485,7 @@ __device__ __forceinline__ void spmm_acc(const int* __restrict__ idx, const floa
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       vv[u] = v[k + u];
-      const double* b = B + (int64_t)idx[k + u] * m;
+      const double* b = B + (int64_t)(idx[k + u] & ~kColFlag) * m;
 #pragma unroll
       for (int h = 0; h < NH; ++h) bv[u][h] = b[cc[h]];
     }
@@ -373,7 +496,7 @@ __device__ __forceinline__ void spmm_acc(const int* __restrict__ idx, const floa
   }
   for (; k < k1; ++k) {
     const double vv = v[k];
-    const double* b = B + (int64_t)idx[k] * m;
+    const double* b = B + (int64_t)(idx[k] & ~kColFlag) * m;
 #pragma unroll
     for (int h = 0; h < NH; ++h) a[0][h] = fma(vv, ok[h] ? b[cc[h]] : 0.0, a[0][h]);
   }
@@ -451,11 +574,8 @@ nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& pl, int mod
     if (note != nullptr)
       NYS_TRY(launch_note(reinterpret_cast<const PcgDev*>(done), note, note_seq, st));
   }
-  const int4* lists = S->bins.as<int4>();
-  const int64_t gcsc = (int64_t)S->nlong + (S->nmed + 3) / 4 + (S->nshort + 31) / 32;
-  if (gcsc > 0)
-    hipLaunchKernelGGL(k_csc_pass, dim3((unsigned)gcsc), dim3(256), 0, st, S->rows(), S->cvals(),
-                       lists, S->d, S->nshort, S->nmed, S->nlong, s, ypart, done);
+  hipLaunchKernelGGL(k_csc_pass, dim3((unsigned)S->cgrid), dim3(1024), 0, st, S->rows(),
+                     S->cvals(), S->wstart(), S->wbase(), S->n, s, ypart, done);
   if (ev1 != nullptr) NYS_TRY_HIP(hipEventRecord(ev1, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
@@ -491,17 +611,64 @@ nys_status sparse_sketch(const nys_sparse_s* S, const double* D, double c, const
 }  // namespace nys
 
 namespace nys {
-// device bytes nys_sparse_create holds at once (CSC copy, s vector, column
-// bins, and the transient per-block column counts)
-// the three column lists (d triples each) and their lengths
-size_t sparse_bins_bytes(int64_t d) { return sizeof(int4) * (size_t)(3 * d + 1); }
+// CSC slots (rows and values each): every entry, one per empty column, and
+// the overrun of the column pass's 16-byte loads; a multiple of 4
+static int64_t sparse_csc_cap(int64_t d, int64_t nnz) { return (nnz + d + kCscPad + 3) / 4 * 4; }
 
+// device bytes nys_sparse_create holds at once (CSC copy, s vector, the
+// column-pass split, and the transient per-block column counts)
 size_t sparse_handle_bytes(int64_t n, int64_t d, int64_t nnz) {
   const int64_t rpb = std::max<int64_t>(1, (n + kTBlocks - 1) / kTBlocks);
   const int64_t nblk = std::max<int64_t>(1, (n + rpb - 1) / rpb);
-  return (sizeof(int) * (size_t)(d + 1 + 2 * nnz) + 256) +
+  const int64_t roff = (d + 1 + 3) / 4 * 4;
+  return (sizeof(int) * (size_t)(roff + 2 * sparse_csc_cap(d, nnz)) + 256) +
          sizeof(double) * (size_t)std::max<int64_t>(n, 1) +
-         sizeof(int) * ((size_t)nblk * d + 1) + sparse_bins_bytes(d) + 4 * 256;
+         sizeof(int) * ((size_t)nblk * d + 1) + sizeof(int) * (2 * (16 * 1024 + 1)) + 4 * 256;
+}
+
+// Column-aligned split of the nnzc CSC entries into at most G ranges with
+// the largest range as small as possible (binary search on the capacity T;
+// for a given T, ranges are cut greedily at the last column start within
+// T); then each range into 16 wavefront ranges of equal size.  cp is the
+// CSC colptr (d + 1 entries, strictly increasing: no column is empty).
+static void sparse_split(const std::vector<int>& cp, int G, std::vector<int>& wstart,
+                         std::vector<int>& wbase) {
+  const int64_t d = (int64_t)cp.size() - 1;
+  const int64_t nnzc = cp[d];
+  auto cut = [&](int64_t T, std::vector<int64_t>* out) {
+    int64_t b = 0;
+    int parts = 0;
+    while (b < nnzc) {
+      if (parts == G) return false;
+      const auto it = std::upper_bound(cp.begin(), cp.end(), (int64_t)std::min<int64_t>(b + T, nnzc));
+      const int64_t nb = *(it - 1);
+      if (nb <= b) return false;   // a column longer than T
+      if (out != nullptr) out->push_back(nb);
+      b = nb;
+      ++parts;
+    }
+    return true;
+  };
+  int64_t longest = 0;
+  for (int64_t j = 0; j < d; ++j) longest = std::max<int64_t>(longest, cp[j + 1] - cp[j]);
+  int64_t lo = std::max<int64_t>(longest, (nnzc + G - 1) / G), hi = std::max<int64_t>(nnzc, 1);
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (cut(mid, nullptr)) hi = mid;
+    else lo = mid + 1;
+  }
+  std::vector<int64_t> B{0};
+  cut(lo, &B);
+  while ((int)B.size() < G + 1) B.push_back(nnzc);
+  wstart.assign((size_t)16 * G + 1, 0);
+  wbase.assign((size_t)16 * G + 1, 0);
+  for (int g = 0; g < G; ++g) {
+    const int64_t L = B[g + 1] - B[g];
+    for (int w = 0; w < 16; ++w) wstart[(size_t)16 * g + w] = (int)(B[g] + L * w / 16);
+  }
+  wstart[(size_t)16 * G] = (int)nnzc;
+  for (size_t i = 0; i < wstart.size(); ++i)
+    wbase[i] = (int)(std::lower_bound(cp.begin(), cp.begin() + d, wstart[i]) - cp.begin()) - 1;
 }
 }  // namespace nys
 
@@ -512,8 +679,8 @@ extern "C" {
 nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, const int* rowptr,
                              const int* colidx, const float* val, nys_sparse* out) {
   if (ctx == nullptr || out == nullptr || n < 0 || d < 1 || nnz < 0 ||
-      nnz > ((int64_t)1 << 31) - 1 || n > ((int64_t)1 << 31) - 2 ||
-      d > ((int64_t)1 << 31) - 2 || rowptr == nullptr ||
+      n > ((int64_t)1 << 31) - 2 || d > ((int64_t)1 << 31) - 2 ||
+      sparse_csc_cap(d, nnz) > ((int64_t)1 << 31) - 1 || rowptr == nullptr ||
       (nnz > 0 && (colidx == nullptr || val == nullptr)))
     return NYS_ERR_INVALID;
   *out = nullptr;
@@ -536,7 +703,12 @@ nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, con
   S->rowptr = rowptr;
   S->colidx = colidx;
   S->val = val;
-  nys_status s = S->csc.reserve(sizeof(int) * (size_t)(d + 1 + 2 * nnz) + 256);
+  S->cap = sparse_csc_cap(d, nnz);
+  nys_status s = S->csc.reserve(sizeof(int) * (size_t)(S->row_off() + 2 * S->cap) + 256);
+  // row indices and values start zeroed (the slots past colptr[d] stay so)
+  if (s == NYS_OK && hipMemsetAsync(S->rows(), 0, sizeof(int) * (size_t)(2 * S->cap), st) !=
+                         hipSuccess)
+    s = NYS_ERR_HIP;
   if (s == NYS_OK) s = S->s.reserve(sizeof(double) * (size_t)std::max<int64_t>(n, 1));
   nys::DevBuf cnt;
   const int64_t rpb = std::max<int64_t>(1, (n + kTBlocks - 1) / kTBlocks);
@@ -576,31 +748,37 @@ nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, con
     if (n > 0 && nnz > 0)
       hipLaunchKernelGGL(k_tr_fill, dim3(nblk), dim3(64), 0, st, rowptr, colidx, val, n, d, rpb,
                          cnt.as<int>(), S->rows(), S->cvals());
+    hipLaunchKernelGGL(k_tr_pad, dim3(nb256(d)), dim3(256), 0, st, cnt.as<int>(), d, nblk,
+                       S->colptr(), S->rows(), S->cvals());
     if (hipGetLastError() != hipSuccess) s = NYS_ERR_HIP;
   }
-  // column bins for the A^T pass: three lists of d slots and their lengths
-  if (s == NYS_OK) s = S->bins.reserve(sparse_bins_bytes(d));
+  // the column pass's split, from the CSC colptr on the host
   if (s == NYS_OK) {
-    int4* lists = S->bins.as<int4>();
-    int* counts = reinterpret_cast<int*>(lists + 3 * d);
-    int hc[3] = {0, 0, 0};
-    if (hipMemsetAsync(counts, 0, sizeof(int) * 3, st) != hipSuccess) s = NYS_ERR_HIP;
+    std::vector<int> cp((size_t)d + 1);
+    if (hipMemcpyAsync(cp.data(), S->colptr(), sizeof(int) * (size_t)(d + 1),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      s = NYS_ERR_HIP;
     if (s == NYS_OK) {
-      hipLaunchKernelGGL(k_bin_cols, dim3(1), dim3(1024), 0, st, S->colptr(), d, lists, counts);
-      if (hipGetLastError() != hipSuccess ||
-          hipMemcpyAsync(hc, counts, sizeof(int) * 3, hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
+      S->nnzc = cp[(size_t)d];
+      S->cgrid = std::max(1, S->num_cu);
+      std::vector<int> ws, wb;
+      sparse_split(cp, S->cgrid, ws, wb);
+      s = S->part.reserve(sizeof(int) * (ws.size() + wb.size()));
+      if (s == NYS_OK &&
+          (hipMemcpyAsync(S->part.as<int>(), ws.data(), sizeof(int) * ws.size(),
+                          hipMemcpyHostToDevice, st) != hipSuccess ||
+           hipMemcpyAsync(S->part.as<int>() + ws.size(), wb.data(), sizeof(int) * wb.size(),
+                          hipMemcpyHostToDevice, st) != hipSuccess ||
+           hipStreamSynchronize(st) != hipSuccess))
         s = NYS_ERR_HIP;
     }
-    S->nshort = hc[0];
-    S->nmed = hc[1];
-    S->nlong = hc[2];
   }
   cnt.release();
   if (s != NYS_OK) {
     S->csc.release();
     S->s.release();
-    S->bins.release();
+    S->part.release();
     delete S;
     return s;
   }
@@ -613,7 +791,7 @@ nys_status nys_sparse_destroy(nys_sparse S) {
   (void)hipSetDevice(S->device);
   S->csc.release();
   S->s.release();
-  S->bins.release();
+  S->part.release();
   delete S;
   return NYS_OK;
 }

@@ -216,3 +216,33 @@ def test_sparse_pair_persistent_rows_and_head(N, ctx, n, d):
     print(f"[sparse pair persistent] {n}x{d} nnz {S.nnz} rel err {e:.2e}", flush=True)
     assert e < 1e-12
     S.close()
+
+
+@pytest.mark.parametrize("n,d,dens,seed", [(1, 9, 0.5, 1), (7, 300, 0.01, 2), (3000, 50, 0.5, 3),
+                                           (20000, 40, 0.3, 4), (17000, 2000, 0.02, 5)])
+def test_sparse_pair_elementwise_edges(N, ctx, n, d, dens, seed):
+    # element by element against the FP64 product: a single row, mostly empty
+    # columns (each kept as one zero entry in the CSC copy), columns longer
+    # than a wavefront's share of the entries (their partial sums combined
+    # across wavefronts), fewer entries than workgroups, and n above the
+    # LDS-staged part of s
+    import scipy.sparse as sps
+    r = np.random.default_rng(seed)
+    M = sps.random(n, d, density=dens, format="csr", random_state=seed, dtype=np.float64)
+    M.data = (np.abs(r.standard_normal(M.nnz)) + 0.1).astype(np.float32).astype(np.float64)
+    M.sort_indices()
+    rp = torch.tensor(M.indptr, dtype=torch.int32)
+    c = torch.tensor(M.indices, dtype=torch.int32)
+    v32 = torch.tensor(M.data, dtype=torch.float32)
+    S = N.SparseMatrix(ctx, rp.to(DEV), c.to(DEV), v32.to(DEV), (n, d))
+    p = r.standard_normal(d)
+    D = r.random(n) + 0.1
+    v = N.nys_hessian_apply(ctx, S, torch.tensor(p, device=DEV), rho=0.4,
+                            D=torch.tensor(D, device=DEV)).cpu().numpy()
+    ref = M.T @ (D * (M @ p)) + 0.4 * p
+    scale = abs(M).T @ (D * (abs(M) @ np.abs(p))) + 0.4 * np.abs(p)
+    err = np.abs(v - ref)
+    print(f"[sparse pair edges] {n}x{d} nnz {M.nnz} max err/scale {np.max(err / scale):.2e}",
+          flush=True)
+    assert np.all(err <= 1e-13 * scale + 1e-300)
+    S.close()
