@@ -312,9 +312,9 @@ __device__ __forceinline__ void seg_step(double& v, int& fs) {
 // is as small as possible; its wavefront w owns the w-th sixteenth of it
 // (wstart[16 g + w] to wstart[16 g + w + 1]), whatever the column
 // boundaries, and wbase[16 g + w] is the number of columns starting before
-// its first entry, minus one.  A wavefront reads 256 entries per round, four
-// consecutive ones per lane (16-byte loads from the entry index rounded down
-// to a multiple of 4; entries outside its range count as zero), sums them in
+// its first entry, minus one.  A wavefront reads 64 EPL entries per round,
+// EPL consecutive ones per lane (16-byte loads from the entry index rounded
+// down to a multiple of 4; entries outside its range count as zero), sums them in
 // order split at column starts, then combines the lanes by one segmented
 // scan: a column that ends inside the wavefront's range is written by the
 // lane holding its last entry's successor (or at the range end), its sum
@@ -323,7 +323,9 @@ __device__ __forceinline__ void seg_step(double& v, int& fs) {
 // the part from its last one) are combined in wavefront order by one thread
 // after a barrier.
 constexpr int kCscHead = 16384;
-constexpr int kCscPad = 512;   // entries past the end of the CSC arrays (16-byte loads overrun)
+constexpr int kCscEpl = 8;      // consecutive entries per lane per round
+constexpr int kCscPad = 1024;   // entries past the end of the CSC arrays (a round's loads overrun)
+template <int EPL>
 __global__ __launch_bounds__(1024) void k_csc_pass(const int* __restrict__ rows,
                                                    const float* __restrict__ cval,
                                                    const int* __restrict__ wstart,
@@ -346,16 +348,21 @@ __global__ __launch_bounds__(1024) void k_csc_pass(const int* __restrict__ rows,
   double carry = 0.0;   // partial of the column open at the end of the last round
   int cnt = 0;          // column starts seen so far by the wavefront
   double head = 0.0;    // partial before the wavefront's first column start
-  for (int a = r0 & ~3; a < r1; a += 256) {
-    const int e0 = a + 4 * lane;
-    const int4 rr = *reinterpret_cast<const int4*>(rows + e0);
-    const float4 cc = *reinterpret_cast<const float4*>(cval + e0);
-    const int rw[4] = {rr.x, rr.y, rr.z, rr.w};
-    const float cv[4] = {cc.x, cc.y, cc.z, cc.w};
-    double x[4];
+  for (int a = r0 & ~3; a < r1; a += 64 * EPL) {
+    const int e0 = a + EPL * lane;
+    int rw[EPL];
+    float cv[EPL];
+#pragma unroll
+    for (int h = 0; h < EPL / 4; ++h) {
+      const int4 rr = *reinterpret_cast<const int4*>(rows + e0 + 4 * h);
+      const float4 cc = *reinterpret_cast<const float4*>(cval + e0 + 4 * h);
+      rw[4 * h] = rr.x; rw[4 * h + 1] = rr.y; rw[4 * h + 2] = rr.z; rw[4 * h + 3] = rr.w;
+      cv[4 * h] = cc.x; cv[4 * h + 1] = cc.y; cv[4 * h + 2] = cc.z; cv[4 * h + 3] = cc.w;
+    }
+    double x[EPL];
     int fl = 0;   // bit j: entry e0 + j starts a column
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < EPL; ++j) {
       const bool valid = e0 + j >= r0 && e0 + j < r1;
       const int row = valid ? (rw[j] & ~kColFlag) : 0;
       double sv;
@@ -383,7 +390,7 @@ __global__ __launch_bounds__(1024) void k_csc_pass(const int* __restrict__ rows,
     double hsum = 0.0, run = 0.0;
     int seen = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < EPL; ++j) {
       if (fl & (1 << j)) {
         if (seen == 0) hsum = run;
         else y[base + fb + seen] = run;
@@ -574,7 +581,7 @@ nys_status launch_sparse_pair(const nys_sparse_s* S, const GramPlan& pl, int mod
     if (note != nullptr)
       NYS_TRY(launch_note(reinterpret_cast<const PcgDev*>(done), note, note_seq, st));
   }
-  hipLaunchKernelGGL(k_csc_pass, dim3((unsigned)S->cgrid), dim3(1024), 0, st, S->rows(),
+  hipLaunchKernelGGL(k_csc_pass<kCscEpl>, dim3((unsigned)S->cgrid), dim3(1024), 0, st, S->rows(),
                      S->cvals(), S->wstart(), S->wbase(), S->n, s, ypart, done);
   if (ev1 != nullptr) NYS_TRY_HIP(hipEventRecord(ev1, st));
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
