@@ -18,6 +18,8 @@ via low-rank approximation", ICML 2022) by eye:
   mlp       the warm-start network (not in the paper), FP64 forward/backward/Adam
   svm       the kernel SVM dual (eq. 8) by NysADMM: RBF kernel, projection onto
             {0 <= z <= C, b^T z = 0}, duality gap
+  rng       the Gaussian entries of the test matrix of Algorithm RandNysAppx
+            when the library draws them: Philox4x32-10 and Box-Muller
 
 Parity status of every function is stated in its module header.
 """
