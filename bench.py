@@ -937,8 +937,11 @@ def main():
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     print(f"[bench] generated {args.n}x{args.d} in {gen_s:.1f} s", file=sys.stderr, flush=True)
-    A, b, omega = p.A, p.b.contiguous(), p.omega.contiguous()
+    A, b = p.A, p.b.contiguous()
     ctx = N.Context()
+    # the adaptive sketch's d x 800 Gaussian test matrix, drawn by the library
+    # on the device (Philox4x32-10 + Box-Muller, seed 1)
+    omega = N.gaussian_omega(ctx, args.d, 800, seed=1)
     prob = N.problem(A, b, p.gamma)
     if args.copy_reference:
         copy_reference(torch)
@@ -991,6 +994,7 @@ def main():
             "n": args.n, "d": args.d, "rho": p.rho, "gamma": p.gamma, "pcg_tol": p.pcg_tol,
             "admm_iters_per_step": args.admm_iters, "ada_tol": 2.0,
             "rank_final": plain["ranks"][-1], "true_res_every": tre,
+            "test_matrix": "nys_gaussian seed 1 (device Philox4x32-10, Box-Muller)",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -31,10 +31,10 @@
  *    a negative weight gives NYS_ERR_INVALID, a NaN or infinite one
  *    NYS_ERR_NONFINITE.  A NaN or infinity in A, b or rhs surfaces as
  *    NYS_ERR_NONFINITE from the first residual or sketch norm it reaches.
- *  - The Gaussian test-matrix entries `omega` are drawn by the caller (the
- *    library draws no random numbers): FP64, column-major d x r (column k at
- *    omega + k*d).  The library orthonormalises them (thin QR, as in
- *    Algorithm RandNysAppx).
+ *  - The Gaussian test-matrix entries `omega` are passed in by the caller:
+ *    FP64, column-major d x r (column k at omega + k*d).  They may come from
+ *    any generator; nys_gaussian draws them on the device from a seed.  The
+ *    library orthonormalises them (thin QR, as in Algorithm RandNysAppx).
  *  - All work is ordered on the HIP stream given to nys_ctx_create.  Calls
  *    that return scalars (info structs, factor info) synchronise that stream.
  *    A context is not thread-safe; use one per stream.
@@ -151,6 +151,21 @@ nys_status nys_ctx_profile_pcg_enable(nys_ctx ctx, int on);
 nys_status nys_ctx_profile_pcg(nys_ctx ctx, long* solves, double* total_ms);
 
 /* ------------------------------------------------------------------ sketch */
+
+/* Standard Gaussian entries for the test matrix of Algorithm RandNysAppx,
+ * drawn on the device: out[i] = sample offset + i of the stream of `seed`,
+ * i < count (FP64, device pointer, caller-owned).  The stream is
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) with Box-Muller:
+ * sample e comes from the Philox call with counter (q mod 2^32, q div 2^32,
+ * 0, 0), q = e div 4, and key (seed mod 2^32, seed div 2^32); the call's
+ * words (w0, w1) give samples 4q, 4q + 1 as sqrt(-2 ln u1) (cos, sin)(2 pi u2)
+ * with u = (w + 1/2) 2^-32, and (w2, w3) give samples 4q + 2, 4q + 3.  So a
+ * d x r test matrix is count = d * r from offset 0, and the block of columns
+ * [k, k + m) of it is count = d * m from offset d * k.  Stream-ordered on the
+ * context's stream (no synchronisation).  count < 0, out == NULL with
+ * count > 0, or offset + count past 2^64: NYS_ERR_INVALID; count == 0 does
+ * nothing. */
+nys_status nys_gaussian(nys_ctx ctx, uint64_t seed, uint64_t offset, int64_t count, double* out);
 
 /* Randomized Nystrom approximation of H = A^T diag(D) A + c I
  * (Algorithm RandNysAppx; eq. NysAppx; Section 2.2):

@@ -35,7 +35,7 @@ EXPORTS = [
     "nys_ws_train_step", "nys_ws_destroy", "nys_kernel_rbf", "nys_sketch_sym", "pcg_solve_sym",
     "svm_solve", "nys_sparse_create", "nys_sparse_destroy", "nys_hessian_apply_noalloc",
     "nys_workspace_query", "nys_ctx_set_workspace", "nys_ctx_workspace_peak",
-    "nys_ws_set_precision",
+    "nys_ws_set_precision", "nys_gaussian",
 ]
 
 
@@ -155,6 +155,7 @@ def lib():
         "svm_solve": (i32, [vp, P(SvmProblem), P(SvmOpts), P(AdmmState), P(SvmInfo)]),
         "nys_sparse_create": (i32, [vp, i64, i64, i64, vp, vp, vp, P(vp)]),
         "nys_sparse_destroy": (i32, [vp]),
+        "nys_gaussian": (i32, [vp, C.c_uint64, C.c_uint64, i64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -359,6 +360,25 @@ class Factor:
             self.close()
         except Exception:
             pass
+
+
+def nys_gaussian(ctx: Context, seed: int, count: int, offset: int = 0,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Samples offset .. offset + count - 1 of the device Gaussian stream of
+    `seed` (FP64, on the context's device, ordered on its stream)."""
+    if out is None:
+        out = torch.empty(count, dtype=torch.float64, device=f"cuda:{ctx.device}")
+    elif out.dtype != torch.float64 or not out.is_contiguous() or out.numel() < count:
+        raise ValueError("out: contiguous FP64 tensor with at least count entries")
+    _check(lib().nys_gaussian(ctx.h, int(seed) & (2**64 - 1), int(offset), int(count),
+                              _ptr(out) if count > 0 else None), "nys_gaussian")
+    return out
+
+
+def gaussian_omega(ctx: Context, d: int, s: int, seed: int) -> torch.Tensor:
+    """A d x s Gaussian test matrix drawn on the device, column-major (torch
+    shape (s, d): row k of the tensor is column k of Omega)."""
+    return nys_gaussian(ctx, seed, d * s).view(s, d)
 
 
 def nys_factor_import(ctx: Context, U_rows: torch.Tensor, lam: Sequence[float], nu: float = 0.0) -> Factor:
