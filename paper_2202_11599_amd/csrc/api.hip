@@ -338,7 +338,7 @@ nys_status pcg_workspace(nys_ctx ctx, const GramPlan& pl, int64_t d, int max_ite
   ws->w2 = reinterpret_cast<double*>(v + 2 * nv + cb + align_up(sizeof(double) * kWyRing));
   ws->rj = red_block(pl.ny());
   ws->nred = nblk(d, ws->rj);
-  ws->nvec = nblk(d, kVecBlock);
+  ws->nvec = nblk(d, vec_block(d));
   const size_t sb = align_up(sizeof(PcgDev)) + 4 * align_up(sizeof(double) * ws->nred) +
                     align_up(sizeof(double) * ws->nvec);
   NYS_TRY(ctx->small.reserve(sb));
@@ -950,7 +950,7 @@ nys_status nys_workspace_query(nys_ctx ctx, const nys_dense* A, int r_max, int c
   total += 3 * nv + align_up(sizeof(double) * kCvecDoubles) +
            align_up(sizeof(double) * kWyRing);
   total += align_up(sizeof(PcgDev)) + 4 * align_up(sizeof(double) * (size_t)nblk(d, kRedBlock)) +
-           align_up(sizeof(double) * (size_t)nblk(d, kVecBlock));
+           align_up(sizeof(double) * (size_t)nblk(d, vec_block(d)));
   total += nv + 256;
   // ADMM vectors
   total += admm_ws_bytes(n, d);

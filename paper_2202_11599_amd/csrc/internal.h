@@ -442,6 +442,7 @@ inline const nys_sparse_s* as_sparse(const nys_dense& A) {
 
 // ---- vec.hip
 constexpr int kVecBlock = 32;    // entries of y per workgroup of the preconditioner update
+constexpr int kVecBlockWide = 256;   // the same for d > kPreReduceDim
 constexpr int kRedBlock = 16;    // columns per workgroup of the partial reduction
 // columns per workgroup of the partial reduction for G partial rows: 16
 // columns x 16 slices of the partials for large G, one column per thread
@@ -460,6 +461,9 @@ inline int dot_slices(int64_t d) {
 // iteration by a one-workgroup kernel instead of by every workgroup of the
 // vector kernels (whose partial counts grow with d).
 constexpr int64_t kPreReduceDim = 32768;
+// entries of y per workgroup of the preconditioner update at dimension d
+// (also the count of its p^T p partials: nblk(d, vec_block(d)))
+inline int vec_block(int64_t d) { return d > kPreReduceDim ? kVecBlockWide : kVecBlock; }
 inline int nblk(int64_t d, int b) { return (int)((d + b - 1) / b); }
 
 // v = sum_g ypart[g] + rho_eff * p ; then per `op`:

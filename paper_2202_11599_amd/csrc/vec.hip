@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void k_precond_dot(
 // mode 0: p = y + beta p (beta = (w^T y)/wy[k]), wy[k+1] = w^T y
 // mode 1: p = y, wy[0] = w^T y
 // mode 2: p (output) = y, standalone apply
-template <typename UT, int NU>
+template <typename UT, int NU, int VJ>
 __global__ __launch_bounds__(256) void k_precond_update(
     const UT* __restrict__ U, int64_t d, int r, const double* __restrict__ lam, double lam_s,
     double rho, const double* __restrict__ cvec, const double* __restrict__ w,
@@ -360,8 +360,8 @@ __global__ __launch_bounds__(256) void k_precond_update(
   // host_slot (pinned host memory, may be NULL): receives the state at the end
   // of the iteration, read by the host once the kernel has completed.
   // gpre (may be NULL): g and sum s c^2 already reduced by k_c_reduce
-  constexpr int VJ = kVecBlock;        // entries of y per workgroup
-  constexpr int VS = 256 / VJ;         // slices of the rank index
+  // VJ entries of y per workgroup, VS slices of the rank index
+  constexpr int VS = 256 / VJ;
   __shared__ double g[1024];
   __shared__ double ys[VS][VJ];
   __shared__ double sh4[4];
@@ -734,13 +734,14 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
                                  double* pppart, const PcgDev* st, int mode, hipStream_t stream,
                                  PcgDev* host_slot, int seq, bool pre, const double* gpre) {
   if (r > 1024) return NYS_ERR_INVALID;
-  const int grid = nblk(d, kVecBlock);
+  const int vj = vec_block(d);
+  const int grid = nblk(d, vj);
   const int nsl = dot_slices(d);
   // eight rank terms per lane in flight up to rank 64 (every term in one
   // group); sixteen up to rank 256, where the pass is latency bound and the
   // lane's terms fit two groups; eight above, where U streams from HBM and
   // the clamped tail of a wider group only adds loads
-  const int vs = 256 / kVecBlock;
+  const int vs = 256 / vj;
   const bool wide = r > 8 * vs && r <= 32 * vs;
   auto go = [&](auto kern, const auto* u) {
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, stream, u, d, r, lam, lam_s, rho, cvec, w,
@@ -749,10 +750,22 @@ nys_status launch_precond_update(const void* U, bool u32, int64_t d, int r, cons
   };
   if (u32) {
     const float* u = static_cast<const float*>(U);
-    if (wide) go(k_precond_update<float, 16>, u); else go(k_precond_update<float, 8>, u);
+    if (vj == kVecBlock) {
+      if (wide) go(k_precond_update<float, 16, kVecBlock>, u);
+      else go(k_precond_update<float, 8, kVecBlock>, u);
+    } else {
+      if (wide) go(k_precond_update<float, 16, kVecBlockWide>, u);
+      else go(k_precond_update<float, 8, kVecBlockWide>, u);
+    }
   } else {
     const double* u = static_cast<const double*>(U);
-    if (wide) go(k_precond_update<double, 16>, u); else go(k_precond_update<double, 8>, u);
+    if (vj == kVecBlock) {
+      if (wide) go(k_precond_update<double, 16, kVecBlock>, u);
+      else go(k_precond_update<double, 8, kVecBlock>, u);
+    } else {
+      if (wide) go(k_precond_update<double, 16, kVecBlockWide>, u);
+      else go(k_precond_update<double, 8, kVecBlockWide>, u);
+    }
   }
   return hipGetLastError() == hipSuccess ? NYS_OK : NYS_ERR_HIP;
 }
