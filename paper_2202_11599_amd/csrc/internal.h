@@ -454,7 +454,10 @@ constexpr int kDotSlicesMax = 64; // d-slices of the U^T w partial sums (buffer 
 constexpr size_t kCvecDoubles = (size_t)1024 * (kDotSlicesMax + 2);
 // slices for dimension d: 8, or one per 4096 entries up to 64 for large d
 inline int dot_slices(int64_t d) {
-  const int64_t s = (d + 4095) / 4096;
+  // slices of 4096 entries; 8192 above 32768, where one workgroup sums the
+  // slices once per iteration (measured at d = 150348, rank 50: 2048, 4096,
+  // 8192 and 16384 entries per slice gave 468, 482, 489 and 462 solves/s)
+  const int64_t s = d > 32768 ? (d + 8191) / 8192 : (d + 4095) / 4096;
   return (int)(s < 8 ? 8 : (s > kDotSlicesMax ? kDotSlicesMax : s));
 }
 // Above this dimension the PCG scalars (p^T v, ||w||^2) are summed once per
