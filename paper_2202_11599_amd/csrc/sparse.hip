@@ -174,15 +174,17 @@ __device__ __forceinline__ void stage16(double* xl, const double* __restrict__ x
 // data land, and wavefront w of workgroup g takes rows g * 16 + w, then
 // every 16 * gridDim.x rows on.  The next row's bounds are loaded before the
 // current row's entries; a row is read in batches of 64 * kCsrCh entries
-// (lane l takes entries k0 + c * 64 + l), every index and value load of a
-// batch unconditional (a lane past the row end re-reads its last entry with
-// value 0) so that all are in flight at once, then the LDS reads and, for
-// columns past the head only, the global gathers.  Each lane adds its
+// (lane l takes entries k0 + c * 64 + l) through buffer resources bounded to
+// the row (a lane past the row end reads index 0 and value 0), every index
+// and value load of a batch issued before its gathers, then the LDS reads
+// and, for columns past the head only, the global gathers.  Each lane adds its
 // products in entry order; q terms are added in row order, the 16
 // wavefronts' sums in wavefront order.
 constexpr int kCsrT = 1024;
 constexpr int kCsrHead = 16384;
 constexpr int kCsrCh = 10;   // entries per lane per batch (rows up to 640 in one batch)
+// word 3 of a raw buffer resource (32-bit elements, no swizzle) on gfx950
+constexpr int kBufferWord3 = 0x00020000;
 __global__ __launch_bounds__(kCsrT) void k_csr_pass(const int* __restrict__ rowptr,
                                                     const int* __restrict__ col,
                                                     const float* __restrict__ val, int64_t n,
@@ -217,16 +219,23 @@ __global__ __launch_bounds__(kCsrT) void k_csr_pass(const int* __restrict__ rowp
       ne = rowptr[i + stride + 1];
     }
     double acc = 0.0;
-    for (int k0 = rb; k0 < re; k0 += 64 * kCsrCh) {
+    // the row's index and value arrays as buffer resources of exactly its
+    // length: a lane past the row end reads 0 (index 0, value 0), so the
+    // loads need no clamp and take their offsets from the instruction
+    const int rbu = __builtin_amdgcn_readfirstlane(rb);
+    const int len = __builtin_amdgcn_readfirstlane(re) - rbu;
+    const __amdgpu_buffer_rsrc_t rcol = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(col + rbu), (short)0, len * 4, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rval = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(val + rbu), (short)0, len * 4, kBufferWord3);
+    for (int k0 = 0; k0 < len; k0 += 64 * kCsrCh) {
       int jj[kCsrCh];
       float vv[kCsrCh];
 #pragma unroll
       for (int c = 0; c < kCsrCh; ++c) {
-        const int k = k0 + c * 64 + lane;
-        const int kk = k < re ? k : re - 1;
-        jj[c] = col[kk];
-        const float w = val[kk];
-        vv[c] = k < re ? w : 0.0f;
+        const int off = (k0 + c * 64 + lane) * 4;
+        jj[c] = __builtin_amdgcn_raw_buffer_load_b32(rcol, off, 0, 0);
+        vv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rval, off, 0, 0));
       }
       double lv[kCsrCh], gv[kCsrCh];
 #pragma unroll
