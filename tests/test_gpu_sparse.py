@@ -246,3 +246,30 @@ def test_sparse_pair_elementwise_edges(N, ctx, n, d, dens, seed):
           flush=True)
     assert np.all(err <= 1e-13 * scale + 1e-300)
     S.close()
+
+
+def test_sparse_pair_no_rows_and_one_column(N, ctx):
+    # n = 0: every column of the CSC copy is its zero entry and s is empty, so
+    # the pair is rho p exactly; d = 1 with every row in the one column: one
+    # workgroup owns all entries, split over its sixteen wavefronts
+    d = 5
+    rp = torch.zeros(1, dtype=torch.int32)
+    S = N.SparseMatrix(ctx, rp.to(DEV), torch.zeros(0, dtype=torch.int32, device=DEV),
+                       torch.zeros(0, dtype=torch.float32, device=DEV), (0, d))
+    p = torch.arange(1, d + 1, dtype=torch.float64, device=DEV)
+    v = N.nys_hessian_apply(ctx, S, p, rho=0.5)
+    assert torch.equal(v, 0.5 * p)
+    S.close()
+    n = 5000
+    r = np.random.default_rng(3)
+    vals = (np.abs(r.standard_normal(n)) + 0.1).astype(np.float32)
+    rp = torch.arange(n + 1, dtype=torch.int32)
+    S = N.SparseMatrix(ctx, rp.to(DEV), torch.zeros(n, dtype=torch.int32, device=DEV),
+                       torch.tensor(vals, device=DEV), (n, 1))
+    D = r.random(n) + 0.1
+    v = N.nys_hessian_apply(ctx, S, torch.tensor([0.7], dtype=torch.float64, device=DEV), rho=0.0,
+                            D=torch.tensor(D, device=DEV)).item()
+    a = vals.astype(np.float64)
+    ref = float(np.sum(a * D * a) * 0.7)
+    assert abs(v - ref) <= 1e-13 * abs(ref)
+    S.close()
