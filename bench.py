@@ -280,6 +280,15 @@ def cpu_baseline(A, b, omega, p, admm_iters, cpu_iters):
     r = ad.admm_lasso(A64, b64, p.gamma, p.rho, factor=f, iters=cpu_iters, pcg_tol=p.pcg_tol)
     t_iter = (time.perf_counter() - t0) / cpu_iters
     step = t_sketch + admm_iters * t_iter
+    # the oracle's matvec pair A^T (A p) on the FP64 A (two passes over it):
+    # its memory rate beside the GPU's
+    pv = np.random.default_rng(0).standard_normal((A64.shape[1], 1))
+    ny.hessian_apply(A64, None, 0.0, pv)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        ny.hessian_apply(A64, None, 0.0, pv)
+    t_pair = (time.perf_counter() - t0) / 3
+    pair_bytes = 2.0 * A64.shape[0] * A64.shape[1] * 8
     # the same oracle iteration on one thread (the sketch is not repeated)
     t1 = None
     try:
@@ -293,6 +302,8 @@ def cpu_baseline(A, b, omega, p, admm_iters, cpu_iters):
     return {
         "value": admm_iters / step, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
         "host": host_description(),
+        "gemv_pair": {"ms": round(1e3 * t_pair, 2), "gbs": round(pair_bytes / t_pair / 1e9, 1),
+                      "note": "oracle A^T (A p) on the FP64 A, 2 n d 8 bytes per pair"},
         "single_thread": None if t1 is None else {
             "solves_per_s_excl_sketch": round(1.0 / t1, 4), "seconds_per_iteration": round(t1, 3),
             "note": "one NysADMM iteration of the oracle with BLAS limited to one thread"},
