@@ -397,7 +397,10 @@ nys_status admm_solve(nys_ctx ctx, int count, const nys_problem* P, const nys_ad
  * duplicates); they stay owned by the caller and must outlive the handle.
  * The library builds a column-major copy (CSC, rows ascending within a
  * column) for the A^T pass; every product is an FP64 product of the stored
- * FP32 value, every sum FP64 in a fixed order.  nnz < 2^31. */
+ * FP32 value, every sum FP64 in a fixed order.  Limits: nnz + d + 1024 <
+ * 2^31 and at most 2^29 entries per row; otherwise (and for a decreasing
+ * rowptr, rowptr[0] != 0, rowptr[n] != nnz or a column index outside
+ * [0, d)) NYS_ERR_INVALID before any entry is placed. */
 nys_status nys_sparse_create(nys_ctx ctx, int64_t n, int64_t d, int64_t nnz, const int* rowptr,
                              const int* colidx, const float* val, nys_sparse* out);
 nys_status nys_sparse_destroy(nys_sparse S);

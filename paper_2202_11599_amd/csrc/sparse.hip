@@ -28,10 +28,13 @@ constexpr int kTBlocks = 64;   // row blocks of the transpose
 constexpr int kColFlag = (int)0x80000000u;   // first entry of a column in the CSC copy
 
 // *bad = 1 unless rowptr is non-decreasing (its ends were checked on the host)
+// and every row holds at most kMaxRowLen entries (the row pass addresses a
+// row through a buffer resource of 4-byte elements with a 32-bit byte size)
+constexpr int kMaxRowLen = 1 << 29;
 __global__ __launch_bounds__(256) void k_tr_check_rows(const int* __restrict__ rowptr, int64_t n,
                                                        int* __restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n && rowptr[i + 1] < rowptr[i]) *bad = 1;
+  if (i < n && (rowptr[i + 1] < rowptr[i] || rowptr[i + 1] - rowptr[i] > kMaxRowLen)) *bad = 1;
 }
 
 // cnt[b * d + j] = entries of column j in row block b; *bad = 1 on a column
